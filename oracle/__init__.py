@@ -1,0 +1,245 @@
+"""ORACLE -- test infrastructure, not part of the library.
+
+A plain FP64 CPU statement of Q4C real-space grid integration (paper Sec. III A,
+Eq. 29/31), of its spinor assembly (Eq. 16a with the Eq. 8b kinetic balance at
+V_A -> 0) and of the density / adjoint contraction (Eq. 39, Eq. 4).  Only the
+tests, the smoke check and the benchmark's CPU-baseline leg may import it; the
+library never does.  Shares no code with the HIP path: the C part
+(q4c_oracle.c) is compiled with gcc, and the spinor algebra below is written
+out from the Pauli matrices.
+
+Layout convention (shared as a *format* with the library, not as code): the
+result for an atom pair (A, B), A <= B, is five nA x nB row-major blocks
+(V, Ws, Wso_x, Wso_y, Wso_z), rows = functions of A in shell order and
+m = -l..l, columns = functions of B.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "q4c_oracle.c")
+_lib = None
+
+SIGMA = (
+    np.array([[0, 1], [1, 0]], dtype=np.complex128),
+    np.array([[0, -1j], [1j, 0]], dtype=np.complex128),
+    np.array([[1, 0], [0, -1]], dtype=np.complex128),
+)
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (no GPU toolchain involved)."""
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        tmp = _SO + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-ffp-contract=off", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+class _Basis(ctypes.Structure):
+    _fields_ = [("n_atoms", ctypes.c_int32), ("R", ctypes.POINTER(ctypes.c_double)),
+                ("atom_shell_off", ctypes.POINTER(ctypes.c_int32)), ("shell_l", ctypes.POINTER(ctypes.c_int32)),
+                ("shell_rcut", ctypes.POINTER(ctypes.c_double)), ("shell_nint", ctypes.POINTER(ctypes.c_int32)),
+                ("shell_coef_off", ctypes.POINTER(ctypes.c_int64)), ("coef", ctypes.POINTER(ctypes.c_double))]
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_SO)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int32)
+        bp = ctypes.POINTER(_Basis)
+        lib.orc_solid_harmonic.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                           ctypes.c_double, dp, dp]
+        lib.orc_radial.argtypes = [dp, ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp]
+        lib.orc_n_functions.argtypes = [bp]
+        lib.orc_tabulate.argtypes = [bp, ctypes.c_int64, dp, dp, dp, dp, dp]
+        lib.orc_pair_blocks.argtypes = [bp, ctypes.c_int64, dp, dp, dp, dp, dp, ctypes.c_double, ctypes.c_int,
+                                        ip, ip, ctypes.c_int, dp, dp]
+        lib.orc_density_points.argtypes = [bp, ctypes.c_int64, dp, dp, dp, dp, ctypes.c_double, ctypes.c_int,
+                                           ip, ip, dp, ctypes.c_int, dp, dp]
+        _lib = lib
+    return _lib
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+class _BasisHandle:
+    """Keeps the arrays referenced by the C struct alive."""
+
+    def __init__(self, wl):
+        self.R = _c(wl.R, np.float64).reshape(-1)
+        self.aso = _c(wl.atom_shell_off, np.int32)
+        self.sl = _c(wl.shell_l, np.int32)
+        self.sr = _c(wl.shell_rcut, np.float64)
+        self.sn = _c(wl.shell_nint, np.int32)
+        self.so = _c(wl.shell_coef_off, np.int64)
+        self.coef = _c(wl.coef, np.float64)
+        self.s = _Basis(int(wl.n_atoms), _dp(self.R), _ip(self.aso), _ip(self.sl), _dp(self.sr), _ip(self.sn),
+                        self.so.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dp(self.coef))
+
+    @property
+    def ptr(self):
+        return ctypes.byref(self.s)
+
+
+def solid_harmonic(l: int, m: int, x: float, y: float, z: float):
+    """(S, grad S) with S = s^l Y_lm (App. B real harmonics)."""
+    lib = _load()
+    S = ctypes.c_double()
+    g = np.zeros(3)
+    lib.orc_solid_harmonic(l, m, x, y, z, ctypes.byref(S), _dp(g))
+    return S.value, g
+
+
+def radial(table: np.ndarray, rcut: float, s: float):
+    lib = _load()
+    t = _c(table, np.float64).reshape(-1)
+    v = ctypes.c_double()
+    d = ctypes.c_double()
+    lib.orc_radial(_dp(t), int(t.size // 4), float(rcut), float(s), ctypes.byref(v), ctypes.byref(d))
+    return v.value, d.value
+
+
+def tabulate(wl, x, y, z):
+    """phi [npts, nfn] and grad phi [npts, nfn, 3] of every function (brute force)."""
+    lib = _load()
+    h = _BasisHandle(wl)
+    x, y, z = _c(x, np.float64), _c(y, np.float64), _c(z, np.float64)
+    nfn = lib.orc_n_functions(h.ptr)
+    phi = np.zeros((x.size, nfn))
+    grad = np.zeros((x.size, nfn, 3))
+    lib.orc_tabulate(h.ptr, x.size, _dp(x), _dp(y), _dp(z), _dp(phi), _dp(grad))
+    return phi, grad
+
+
+def pair_blocks(wl, pairs: np.ndarray, v: Optional[np.ndarray] = None, screened: bool = True,
+                with_abs: bool = False):
+    """Five real parts (V, Ws, Wso_x, Wso_y, Wso_z) per requested atom pair.
+
+    Returns a list of float64[5, nA, nB] (and the matching sum-|term| scales if
+    with_abs)."""
+    lib = _load()
+    h = _BasisHandle(wl)
+    pairs = _c(pairs, np.int32).reshape(-1, 2)
+    pa, pb = _c(pairs[:, 0], np.int32), _c(pairs[:, 1], np.int32)
+    nfn = wl.atom_nfn()
+    sizes = [5 * int(nfn[a]) * int(nfn[b]) for a, b in pairs]
+    out = np.zeros(int(sum(sizes)))
+    absout = np.zeros_like(out) if with_abs else None
+    vv = _c(wl.v if v is None else v, np.float64)
+    x, y, z, w = (_c(t, np.float64) for t in (wl.x, wl.y, wl.z, wl.w))
+    lib.orc_pair_blocks(h.ptr, x.size, _dp(x), _dp(y), _dp(z), _dp(w), _dp(vv), float(wl.c_light),
+                        int(pairs.shape[0]), _ip(pa), _ip(pb), 1 if screened else 0, _dp(out),
+                        _dp(absout) if with_abs else None)
+    res, ares, o = [], [], 0
+    for (a, b), s in zip(pairs, sizes):
+        res.append(out[o:o + s].reshape(5, int(nfn[a]), int(nfn[b])))
+        if with_abs:
+            ares.append(absout[o:o + s].reshape(5, int(nfn[a]), int(nfn[b])))
+        o += s
+    return (res, ares) if with_abs else res
+
+
+def density(wl, pairs: np.ndarray, coef_blocks: Sequence[np.ndarray], idx: Optional[np.ndarray] = None,
+            weight_mode: int = 0, with_parts: bool = False):
+    """Density / adjoint at grid points `idx` (default all) from per-pair
+    coefficient blocks float64[5, nA, nB] (V, Ws, x, y, z; each stored element
+    counts once)."""
+    lib = _load()
+    h = _BasisHandle(wl)
+    pairs = _c(pairs, np.int32).reshape(-1, 2)
+    pa, pb = _c(pairs[:, 0], np.int32), _c(pairs[:, 1], np.int32)
+    coef = _c(np.concatenate([np.asarray(c, dtype=np.float64).reshape(-1) for c in coef_blocks]), np.float64)
+    if idx is None:
+        idx = np.arange(wl.n_points)
+    x, y, z, w = (_c(t[idx], np.float64) for t in (wl.x, wl.y, wl.z, wl.w))
+    out = np.zeros(x.size)
+    parts = np.zeros((x.size, 3)) if with_parts else None
+    lib.orc_density_points(h.ptr, x.size, _dp(x), _dp(y), _dp(z), _dp(w), float(wl.c_light),
+                           int(pairs.shape[0]), _ip(pa), _ip(pb), _dp(coef), int(weight_mode), _dp(out),
+                           _dp(parts) if with_parts else None)
+    return (out, parts) if with_parts else out
+
+
+# ---------------------------------------------------------------------------
+# Spinor algebra (Eq. 16a with K = sigma.p / 2c; Pauli identity)
+# ---------------------------------------------------------------------------
+
+def spinor_W(parts: np.ndarray) -> np.ndarray:
+    """W_sp = Ws (x) I2 + i sum_m Wso_m (x) sigma_m for one pair block.
+
+    parts: float64[5, nA, nB].  Returns complex128[2 nA, 2 nB] with rows
+    (spin, function) spin-major: [[uu, ud], [du, dd]]."""
+    Ws, Wx, Wy, Wz = parts[1], parts[2], parts[3], parts[4]
+    nA, nB = Ws.shape
+    out = np.zeros((2 * nA, 2 * nB), dtype=np.complex128)
+    for s in range(2):
+        for t in range(2):
+            blk = Ws * (1.0 if s == t else 0.0) + 0j
+            for m, Wm in enumerate((Wx, Wy, Wz)):
+                blk = blk + 1j * Wm * SIGMA[m][s, t]
+            out[s * nA:(s + 1) * nA, t * nB:(t + 1) * nB] = blk
+    return out
+
+
+def spinor_V(parts: np.ndarray) -> np.ndarray:
+    """V_sp = V (x) I2, same layout as spinor_W."""
+    V = parts[0]
+    nA, nB = V.shape
+    out = np.zeros((2 * nA, 2 * nB), dtype=np.complex128)
+    out[:nA, :nB] = V
+    out[nA:, nB:] = V
+    return out
+
+
+def coef_from_spinor_density(pairs: np.ndarray, D_blocks: Sequence[np.ndarray]) -> List[np.ndarray]:
+    """Coefficients on the stored elements such that the density / adjoint of
+    L = Re Tr(D H), H = V_sp + W_sp, is a sum over stored elements.
+
+    Re tr2(D_ji H_ij) = (V_ij + Ws_ij) d_ij - sum_m Wso_m,ij e^m_ij with
+    d_ij = Re tr2 D_ji and e^m_ij = Im tr2(D_ji sigma_m).  Off-diagonal pair
+    blocks are stored once for (i,j) and stand for (j,i) too; both terms are
+    equal for Hermitian D, so their coefficient is doubled.  D_blocks[p] is the
+    (2 nA) x (2 nB) block D_AB; D_ji (j on B, i on A) = conj(D_AB)^T entries."""
+    out = []
+    for (a, b), D in zip(pairs, D_blocks):
+        nA, nB = D.shape[0] // 2, D.shape[1] // 2
+        # D_ji as a 2x2 spin matrix for each (i, j): (D_ji)_{s t} = D[(s, j), (t, i)] = conj(D_AB[(t,i),(s,j)])
+        Dab = D.reshape(2, nA, 2, nB)  # [t, i, s, j]
+        Dji = np.conj(Dab).transpose(1, 3, 2, 0)  # [i, j, s, t]
+        d = np.real(Dji[:, :, 0, 0] + Dji[:, :, 1, 1])
+        e = [np.imag(np.einsum("ijst,ts->ij", Dji, SIGMA[m])) for m in range(3)]
+        f = 1.0 if a == b else 2.0
+        out.append(np.stack([f * d, f * d, -f * e[0], -f * e[1], -f * e[2]]))
+    return out
+
+
+def loss_re_tr(pairs: np.ndarray, D_blocks: Sequence[np.ndarray], parts_blocks: Sequence[np.ndarray]) -> float:
+    """Re Tr(D H) for the full Hermitian matrices rebuilt from the A <= B blocks."""
+    tot = 0.0
+    for (a, b), D, P in zip(pairs, D_blocks, parts_blocks):
+        H = spinor_V(P) + spinor_W(P)
+        # Tr over this block and its mirror: sum_{IJ} D_JI H_IJ, with D_JI = conj(D_IJ) for the stored block
+        t = np.sum(np.conj(D) * H)  # = sum_IJ conj(D_IJ) H_IJ = sum_IJ D_JI H_IJ
+        tot += np.real(t) * (1.0 if a == b else 2.0)
+    return float(tot)

@@ -1,0 +1,374 @@
+/*
+ * ORACLE -- test infrastructure, not part of the library.
+ *
+ * A plain, slow FP64 CPU implementation of what Q4C real-space grid
+ * integration computes.  Only the tests, the smoke check and the CPU-baseline
+ * leg of the benchmark may load it.  It shares no code with the HIP library.
+ *
+ * What it computes (paper, Sec. III A, Eq. 29 and Eq. 31; Eq. 39 for the
+ * density):
+ *
+ *   V_ij      = sum_g w_g v_g phi_i(r_g) phi_j(r_g)
+ *   Ws_ij     = c' sum_g w_g v_g grad phi_i . grad phi_j
+ *   Wso_m,ij  = c' sum_g w_g v_g (grad phi_i x grad phi_j)_m ,  c' = 1/(4 c^2)
+ *
+ * W = (sigma.p) v (sigma.p) / 4c^2 is the small-small block <chi^S|V|chi^S>
+ * (Eq. 16a) with the kinetic-balance operator of Eq. 8b taken with V_A -> 0,
+ * K = sigma.p / 2c.  For real phi and p = -i grad, the Pauli identity
+ * (sigma.a)(sigma.b) = a.b + i sigma.(a x b) splits it into the scalar part
+ * Ws and the three spin-orbit parts Wso_m.
+ *
+ * The sums run over the whole grid (no batching): batching in the paper
+ * (Eq. 31) only regroups the same terms.  Sums are compensated (Neumaier).
+ *
+ * Basis functions (Eq. 12a): phi(r) = R(s)/s^l * S_lm(r - R_A), where
+ * S_lm = s^l Y_lm is the real solid harmonic with the real Y_lm of App. B
+ * (Condon-Shortley convention as written there), and the radial part
+ * Rt(s) = R(s)/s^l is given as a piecewise cubic on knots
+ * r_j = rcut (j/nint)^2, coefficients (c0..c3) per interval in t in [0,1).
+ * phi = 0 for s >= rcut.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+  int32_t n_atoms;
+  const double *R;              /* [3*n_atoms] */
+  const int32_t *atom_shell_off; /* [n_atoms+1] */
+  const int32_t *shell_l;        /* [n_shells] */
+  const double *shell_rcut;      /* [n_shells] */
+  const int32_t *shell_nint;     /* [n_shells] */
+  const int64_t *shell_coef_off; /* [n_shells] */
+  const double *coef;            /* 4 doubles per interval */
+} orc_basis;
+
+/* ------------------------------------------------------------------ */
+/* Real spherical harmonics, App. B                                    */
+/* ------------------------------------------------------------------ */
+
+static double fact(int n) {
+  double r = 1.0;
+  for (int i = 2; i <= n; ++i) r *= i;
+  return r;
+}
+
+static double binom(int n, int k) { return fact(n) / (fact(k) * fact(n - k)); }
+
+static double ipow(double x, int n) {
+  double r = 1.0;
+  for (int i = 0; i < n; ++i) r *= x;
+  return r;
+}
+
+/* Coefficients a[j] (j = 0..l-m) of the m-th derivative of the Legendre
+ * polynomial P_l(t) = 2^-l sum_k (-1)^k C(l,k) C(2l-2k,l) t^(l-2k). */
+static void legendre_deriv(int l, int m, double *a) {
+  for (int j = 0; j <= l; ++j) a[j] = 0.0;
+  for (int k = 0; 2 * k <= l; ++k) {
+    int p = l - 2 * k;
+    if (p < m) continue;
+    double c = ipow(0.5, l) * ((k & 1) ? -1.0 : 1.0) * binom(l, k) * binom(2 * l - 2 * k, l);
+    a[p - m] += c * fact(p) / fact(p - m);
+  }
+}
+
+/*
+ * S = s^l Y_lm(theta, phi) at (x, y, z) relative to the centre, and its
+ * Cartesian gradient.
+ *
+ * App. B: P_l^m(cos t) = sin^m(t) d^m/d(cos t)^m P_l(cos t) (no (-1)^m inside),
+ *   Y_l^m = (-1)^m sqrt2 K cos(m phi) P_l^m      (m > 0)
+ *         = K P_l^0                               (m = 0)
+ *         = (-1)^m sqrt2 K sin(|m| phi) P_l^|m|   (m < 0)
+ *   K = sqrt((2l+1)(l-|m|)! / (4 pi (l+|m|)!)).
+ * With s^m sin^m(t) cos(m phi) = Re (x+iy)^m, s^m sin^m(t) sin(m phi) = Im (x+iy)^m
+ * and s^(l-m) P_l^(m)(z/s) = sum_j a_j z^j (s^2)^((l-m-j)/2), S is a polynomial.
+ */
+void orc_solid_harmonic(int l, int m, double x, double y, double z, double *S, double *g) {
+  int am = m < 0 ? -m : m;
+  double K = sqrt((2.0 * l + 1.0) * fact(l - am) / (4.0 * M_PI * fact(l + am)));
+  double pref = (m == 0) ? K : ((am & 1) ? -1.0 : 1.0) * sqrt(2.0) * K;
+  /* (x+iy)^am and (x+iy)^(am-1) */
+  double cr = 1.0, ci = 0.0, pr = 0.0, pi_ = 0.0;
+  for (int k = 0; k < am; ++k) {
+    pr = cr;
+    pi_ = ci;
+    double nr = cr * x - ci * y, ni = cr * y + ci * x;
+    cr = nr;
+    ci = ni;
+  }
+  double A, Ax, Ay;
+  if (m >= 0) {
+    A = cr;
+    Ax = am * pr;
+    Ay = -am * pi_;
+  } else {
+    A = ci;
+    Ax = am * pi_;
+    Ay = am * pr;
+  }
+  if (am == 0) {
+    Ax = 0.0;
+    Ay = 0.0;
+  }
+  double a[8];
+  legendre_deriv(l, am, a);
+  double rho = x * x + y * y + z * z;
+  double Q = 0.0, Qx = 0.0, Qy = 0.0, Qz = 0.0;
+  for (int j = 0; j <= l - am; ++j) {
+    if (a[j] == 0.0) continue;
+    int e = (l - am - j) / 2;
+    double zj = ipow(z, j), re = ipow(rho, e);
+    Q += a[j] * zj * re;
+    if (e >= 1) {
+      double re1 = ipow(rho, e - 1);
+      Qx += a[j] * zj * e * re1 * 2.0 * x;
+      Qy += a[j] * zj * e * re1 * 2.0 * y;
+      Qz += a[j] * zj * e * re1 * 2.0 * z;
+    }
+    if (j >= 1) Qz += a[j] * j * ipow(z, j - 1) * re;
+  }
+  *S = pref * A * Q;
+  g[0] = pref * (Ax * Q + A * Qx);
+  g[1] = pref * (Ay * Q + A * Qy);
+  g[2] = pref * (A * Qz);
+}
+
+/* ------------------------------------------------------------------ */
+/* Radial table                                                        */
+/* ------------------------------------------------------------------ */
+
+void orc_radial(const double *tab, int nint, double rcut, double s, double *val, double *der) {
+  if (!(s < rcut)) {
+    *val = 0.0;
+    *der = 0.0;
+    return;
+  }
+  int j = (int)floor(nint * sqrt(s / rcut));
+  if (j > nint - 1) j = nint - 1;
+  if (j < 0) j = 0;
+  double rj = rcut * ((double)j / nint) * ((double)j / nint);
+  double rj1 = rcut * ((double)(j + 1) / nint) * ((double)(j + 1) / nint);
+  double h = rj1 - rj;
+  double t = (s - rj) / h;
+  const double *c = tab + 4 * (int64_t)j;
+  *val = c[0] + c[1] * t + c[2] * t * t + c[3] * t * t * t;
+  *der = (c[1] + 2.0 * c[2] * t + 3.0 * c[3] * t * t) / h;
+}
+
+/* number of functions on atom a */
+static int atom_nfn(const orc_basis *b, int a) {
+  int n = 0;
+  for (int s = b->atom_shell_off[a]; s < b->atom_shell_off[a + 1]; ++s) n += 2 * b->shell_l[s] + 1;
+  return n;
+}
+
+static double atom_rcut(const orc_basis *b, int a) {
+  double r = 0.0;
+  for (int s = b->atom_shell_off[a]; s < b->atom_shell_off[a + 1]; ++s)
+    if (b->shell_rcut[s] > r) r = b->shell_rcut[s];
+  return r;
+}
+
+/*
+ * Values and gradients of every function of atom a at point (px,py,pz).
+ * phi = Rt(s) S_lm(d), grad phi = Rt'(s) (d/s) S_lm + Rt(s) grad S_lm, d = p - R_a.
+ * At s = 0 the first gradient term is 0 (Rt'(s) d/s -> 0 for a smooth radial).
+ */
+static void atom_functions(const orc_basis *b, int a, double px, double py, double pz, double *phi,
+                           double *grad) {
+  double dx = px - b->R[3 * a], dy = py - b->R[3 * a + 1], dz = pz - b->R[3 * a + 2];
+  double s = sqrt(dx * dx + dy * dy + dz * dz);
+  int f = 0;
+  for (int sh = b->atom_shell_off[a]; sh < b->atom_shell_off[a + 1]; ++sh) {
+    int l = b->shell_l[sh];
+    double Rt, dRt;
+    orc_radial(b->coef + b->shell_coef_off[sh], b->shell_nint[sh], b->shell_rcut[sh], s, &Rt, &dRt);
+    double u[3] = {0.0, 0.0, 0.0};
+    if (s > 0.0) {
+      u[0] = dRt * dx / s;
+      u[1] = dRt * dy / s;
+      u[2] = dRt * dz / s;
+    }
+    for (int m = -l; m <= l; ++m, ++f) {
+      double S, gS[3];
+      orc_solid_harmonic(l, m, dx, dy, dz, &S, gS);
+      phi[f] = Rt * S;
+      for (int c = 0; c < 3; ++c) grad[3 * f + c] = u[c] * S + Rt * gS[c];
+    }
+  }
+}
+
+int orc_n_functions(const orc_basis *b) {
+  int n = 0;
+  for (int a = 0; a < b->n_atoms; ++a) n += atom_nfn(b, a);
+  return n;
+}
+
+/* phi[g*nfn + i], grad[(g*nfn + i)*3 + c] for all functions at all points. */
+void orc_tabulate(const orc_basis *b, int64_t npts, const double *x, const double *y, const double *z,
+                  double *phi, double *grad) {
+  int nfn = orc_n_functions(b);
+  for (int64_t g = 0; g < npts; ++g) {
+    int f0 = 0;
+    for (int a = 0; a < b->n_atoms; ++a) {
+      atom_functions(b, a, x[g], y[g], z[g], phi + g * nfn + f0, grad + (g * nfn + f0) * 3);
+      f0 += atom_nfn(b, a);
+    }
+  }
+}
+
+/* ------------------------------------------------------------------ */
+/* Compensated summation                                               */
+/* ------------------------------------------------------------------ */
+
+static inline void neu_add(double *s, double *c, double x) {
+  double t = *s + x;
+  if (fabs(*s) >= fabs(x))
+    *c += (*s - t) + x;
+  else
+    *c += (x - t) + *s;
+  *s = t;
+}
+
+/*
+ * Pair blocks of the five real parts for the listed atom pairs.
+ * out for pair p: 5 consecutive nA x nB row-major blocks (V, Ws, Wso_x,
+ * Wso_y, Wso_z), rows = functions of A, columns = functions of B.  Blocks of
+ * successive pairs follow each other.
+ * screened != 0 skips points outside the support of A or of B (exact zeros);
+ * screened == 0 evaluates every point (brute force).
+ * absout (optional, same layout) receives sum |term| of each element: the
+ * scale used by relative error bars.
+ */
+int orc_pair_blocks(const orc_basis *b, int64_t npts, const double *x, const double *y, const double *z,
+                    const double *w, const double *v, double c_light, int npairs, const int32_t *pa,
+                    const int32_t *pb, int screened, double *out, double *absout) {
+  const double cp = 1.0 / (4.0 * c_light * c_light);
+  int64_t off = 0;
+  for (int p = 0; p < npairs; ++p) {
+    int A = pa[p], B = pb[p];
+    int nA = atom_nfn(b, A), nB = atom_nfn(b, B);
+    double rA = atom_rcut(b, A), rB = atom_rcut(b, B);
+    int64_t blk = (int64_t)nA * nB;
+    double *sum = (double *)calloc(5 * blk, sizeof(double));
+    double *cmp = (double *)calloc(5 * blk, sizeof(double));
+    double *abs_ = (double *)calloc(5 * blk, sizeof(double));
+    double *fa = (double *)malloc(sizeof(double) * nA * 4);
+    double *fb = (double *)malloc(sizeof(double) * nB * 4);
+    double *ga = fa + nA, *gb = fb + nB;
+    for (int64_t g = 0; g < npts; ++g) {
+      if (screened) {
+        double ax = x[g] - b->R[3 * A], ay = y[g] - b->R[3 * A + 1], az = z[g] - b->R[3 * A + 2];
+        double bx = x[g] - b->R[3 * B], by = y[g] - b->R[3 * B + 1], bz = z[g] - b->R[3 * B + 2];
+        if (!(ax * ax + ay * ay + az * az < rA * rA)) continue;
+        if (!(bx * bx + by * by + bz * bz < rB * rB)) continue;
+      }
+      double om = w[g] * v[g];
+      atom_functions(b, A, x[g], y[g], z[g], fa, ga);
+      atom_functions(b, B, x[g], y[g], z[g], fb, gb);
+      for (int i = 0; i < nA; ++i) {
+        const double *gi = ga + 3 * i;
+        for (int j = 0; j < nB; ++j) {
+          const double *gj = gb + 3 * j;
+          int64_t e = (int64_t)i * nB + j;
+          double t[5];
+          t[0] = om * fa[i] * fb[j];
+          t[1] = om * (gi[0] * gj[0] + gi[1] * gj[1] + gi[2] * gj[2]);
+          t[2] = om * (gi[1] * gj[2] - gi[2] * gj[1]);
+          t[3] = om * (gi[2] * gj[0] - gi[0] * gj[2]);
+          t[4] = om * (gi[0] * gj[1] - gi[1] * gj[0]);
+          for (int q = 0; q < 5; ++q) {
+            neu_add(sum + q * blk + e, cmp + q * blk + e, t[q]);
+            abs_[q * blk + e] += fabs(t[q]);
+          }
+        }
+      }
+    }
+    for (int q = 0; q < 5; ++q) {
+      double sc = (q == 0) ? 1.0 : cp;
+      for (int64_t e = 0; e < blk; ++e) {
+        out[off + q * blk + e] = (sum[q * blk + e] + cmp[q * blk + e]) * sc;
+        if (absout) absout[off + q * blk + e] = abs_[q * blk + e] * sc;
+      }
+    }
+    off += 5 * blk;
+    free(sum);
+    free(cmp);
+    free(abs_);
+    free(fa);
+    free(fb);
+  }
+  return 0;
+}
+
+/*
+ * Density / adjoint at the listed points (Eq. 39 with the coefficient
+ * matrices given on the same pair blocks as the integrals):
+ *
+ *   nL_g  = sum_pairs sum_ij C^V_ij phi_i phi_j
+ *   nSs_g = c' sum_pairs sum_ij C^Ws_ij grad phi_i . grad phi_j
+ *   nSo_g = c' sum_pairs sum_m sum_ij C^m_ij (grad phi_i x grad phi_j)_m
+ *
+ * coef: per pair 5 blocks nA x nB in the order V, Ws, x, y, z (same layout as
+ * orc_pair_blocks output).  Each stored element counts once.
+ * out[g] = (weight_mode ? w_g : 1) * (nL + nSs + nSo); parts (optional)
+ * receives [g*3 + 0..2] = nL, nSs, nSo (unweighted).
+ */
+int orc_density_points(const orc_basis *b, int64_t npts, const double *x, const double *y, const double *z,
+                       const double *w, double c_light, int npairs, const int32_t *pa, const int32_t *pb,
+                       const double *coef, int weight_mode, double *out, double *parts) {
+  const double cp = 1.0 / (4.0 * c_light * c_light);
+  int na = b->n_atoms;
+  int64_t *poff = (int64_t *)malloc(sizeof(int64_t) * (npairs + 1));
+  poff[0] = 0;
+  for (int p = 0; p < npairs; ++p) poff[p + 1] = poff[p] + 5 * (int64_t)atom_nfn(b, pa[p]) * atom_nfn(b, pb[p]);
+  int maxfn = 0;
+  for (int a = 0; a < na; ++a)
+    if (atom_nfn(b, a) > maxfn) maxfn = atom_nfn(b, a);
+  double *fa = (double *)malloc(sizeof(double) * maxfn * 4);
+  double *fb = (double *)malloc(sizeof(double) * maxfn * 4);
+  for (int64_t g = 0; g < npts; ++g) {
+    double sL = 0, cL = 0, sS = 0, cS = 0, sO = 0, cO = 0;
+    for (int p = 0; p < npairs; ++p) {
+      int A = pa[p], B = pb[p];
+      double rA = atom_rcut(b, A), rB = atom_rcut(b, B);
+      double ax = x[g] - b->R[3 * A], ay = y[g] - b->R[3 * A + 1], az = z[g] - b->R[3 * A + 2];
+      double bx = x[g] - b->R[3 * B], by = y[g] - b->R[3 * B + 1], bz = z[g] - b->R[3 * B + 2];
+      if (!(ax * ax + ay * ay + az * az < rA * rA)) continue;
+      if (!(bx * bx + by * by + bz * bz < rB * rB)) continue;
+      int nA = atom_nfn(b, A), nB = atom_nfn(b, B);
+      int64_t blk = (int64_t)nA * nB;
+      double *ga = fa + nA, *gb = fb + nB;
+      atom_functions(b, A, x[g], y[g], z[g], fa, ga);
+      atom_functions(b, B, x[g], y[g], z[g], fb, gb);
+      const double *C = coef + poff[p];
+      for (int i = 0; i < nA; ++i) {
+        const double *gi = ga + 3 * i;
+        for (int j = 0; j < nB; ++j) {
+          const double *gj = gb + 3 * j;
+          int64_t e = (int64_t)i * nB + j;
+          neu_add(&sL, &cL, C[e] * fa[i] * fb[j]);
+          neu_add(&sS, &cS, C[blk + e] * (gi[0] * gj[0] + gi[1] * gj[1] + gi[2] * gj[2]));
+          neu_add(&sO, &cO, C[2 * blk + e] * (gi[1] * gj[2] - gi[2] * gj[1]));
+          neu_add(&sO, &cO, C[3 * blk + e] * (gi[2] * gj[0] - gi[0] * gj[2]));
+          neu_add(&sO, &cO, C[4 * blk + e] * (gi[0] * gj[1] - gi[1] * gj[0]));
+        }
+      }
+    }
+    double nL = sL + cL, nS = cp * (sS + cS), nO = cp * (sO + cO);
+    double f = weight_mode ? w[g] : 1.0;
+    out[g] = f * (nL + nS + nO);
+    if (parts) {
+      parts[3 * g] = nL;
+      parts[3 * g + 1] = nS;
+      parts[3 * g + 2] = nO;
+    }
+  }
+  free(poff);
+  free(fa);
+  free(fb);
+  return 0;
+}

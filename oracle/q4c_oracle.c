@@ -240,8 +240,10 @@ static inline void neu_add(double *s, double *c, double x) {
  * successive pairs follow each other.
  * screened != 0 skips points outside the support of A or of B (exact zeros);
  * screened == 0 evaluates every point (brute force).
- * absout (optional, same layout) receives sum |term| of each element: the
- * scale used by relative error bars.
+ * absout (optional, same layout) receives the error scale of each element:
+ * sum_g |w_g v_g| times the sum of the absolute values of the products that
+ * enter the term (|phi_i phi_j|, sum_a |d_a phi_i d_a phi_j|, and
+ * |d_b phi_i d_c phi_j| + |d_c phi_i d_b phi_j| for the spin-orbit parts).
  */
 int orc_pair_blocks(const orc_basis *b, int64_t npts, const double *x, const double *y, const double *z,
                     const double *w, const double *v, double c_light, int npairs, const int32_t *pa,
@@ -280,9 +282,16 @@ int orc_pair_blocks(const orc_basis *b, int64_t npts, const double *x, const dou
           t[2] = om * (gi[1] * gj[2] - gi[2] * gj[1]);
           t[3] = om * (gi[2] * gj[0] - gi[0] * gj[2]);
           t[4] = om * (gi[0] * gj[1] - gi[1] * gj[0]);
+          /* error scale: sum of |w v| times the absolute value of every product entering the term */
+          double ao = fabs(om), a[5];
+          a[0] = fabs(t[0]);
+          a[1] = ao * (fabs(gi[0] * gj[0]) + fabs(gi[1] * gj[1]) + fabs(gi[2] * gj[2]));
+          a[2] = ao * (fabs(gi[1] * gj[2]) + fabs(gi[2] * gj[1]));
+          a[3] = ao * (fabs(gi[2] * gj[0]) + fabs(gi[0] * gj[2]));
+          a[4] = ao * (fabs(gi[0] * gj[1]) + fabs(gi[1] * gj[0]));
           for (int q = 0; q < 5; ++q) {
             neu_add(sum + q * blk + e, cmp + q * blk + e, t[q]);
-            abs_[q * blk + e] += fabs(t[q]);
+            abs_[q * blk + e] += a[q];
           }
         }
       }

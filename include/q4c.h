@@ -1,0 +1,215 @@
+/*
+ * q4c.h -- C ABI of libq4c, MI355X (gfx950) real-space grid integration of
+ * quasi-four-component (Q4C) Hamiltonian matrix elements over numeric
+ * atom-centred orbitals (NAOs).
+ *
+ * Problem statement (paper Sec. III A): overlapping atom-centred integration
+ * grids with partition weights w(r), scalar NAOs
+ *     phi_i(r) = Rt_i(s) S_lm(r - R_A),  s = |r - R_A|            (Eq. 12a)
+ * (S_lm = s^l Y_lm, real Y_lm of App. B), the potential v on the grid, and the
+ * matrix elements integrated as weighted grid sums over batches of points
+ *     F_ij = sum_B sum_{r in B} w(r) phi_i(r) F phi_j(r)           (Eq. 29, 31)
+ * with F = v for the large-large block V and F = (sigma.p) v (sigma.p)/4c^2
+ * for the small-small block W (Eq. 16a with the kinetic balance of Eq. 8b at
+ * V_A -> 0).  For real phi the Pauli identity splits W into a scalar part and
+ * three spin-orbit parts:
+ *     V_ij      = sum_g w_g v_g phi_i phi_j
+ *     Ws_ij     = c' sum_g w_g v_g grad phi_i . grad phi_j
+ *     Wso_m,ij  = c' sum_g w_g v_g (grad phi_i x grad phi_j)_m,   c' = 1/(4c^2)
+ * and the 2x2-spinor blocks are V (x) I2 and Ws (x) I2 + i sum_m Wso_m (x) sigma_m.
+ *
+ * Conventions
+ *  - Units: bohr, hartree.  All floating point arguments are IEEE binary64.
+ *  - Functions are numbered atom-major, then shell order, then m = -l..l.
+ *  - Sparse atom-pair store: the pairs (A, B), A <= B, with
+ *    |R_A - R_B| < rcut_A + rcut_B (rcut_A = largest shell cutoff of A), in
+ *    (A, B) order.  Pair p owns nA x nB row-major doubles at pair_off[p]
+ *    (rows = functions of A).  Diagonal pairs (A, A) hold the full block.
+ *    A real part is store_len doubles; a store of all five parts is
+ *    5 * store_len doubles, part-major: V, Ws, Wso_x, Wso_y, Wso_z.
+ *  - Spinor blocks: pair p owns a (2 nA) x (2 nB) row-major complex128 block
+ *    at complex offset 4 * pair_off[p]; rows (spin, function of A) spin-major,
+ *    i.e. [[uu, ud], [du, dd]] sub-blocks.
+ *  - Host pointers are read during the call only; nothing is retained.
+ *  - Device pointers ("_dev") must be device memory of the plan's device.
+ *  - Calls taking a stream are asynchronous on that stream (NULL = default
+ *    stream).  Calls on one plan use the plan's scratch buffers and must not
+ *    overlap in time (serialise them on one stream).
+ *  - Every call returns Q4C_OK (0) or a negative status; no C++ exception or
+ *    abort crosses the ABI.  q4c_last_error() gives a message for the last
+ *    failure on the calling thread.
+ */
+#ifndef Q4C_H
+#define Q4C_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  Q4C_OK = 0,
+  Q4C_EINVAL = -1,       /* invalid argument (NULL, negative size, bad layout) */
+  Q4C_ENOMEM = -2,       /* host or device allocation failed */
+  Q4C_EHIP = -3,         /* HIP runtime error (message via q4c_last_error) */
+  Q4C_ENOTIMPL = -4,     /* option not implemented */
+  Q4C_EUNSUPPORTED = -5, /* unsupported input, e.g. l > 3 */
+  Q4C_ESIZE = -6,        /* output buffer too small */
+  Q4C_ENONFINITE = -7,   /* non-finite input detected (Q4C_CHECK_FINITE) */
+  Q4C_ENODEV = -8        /* plan has no device data (host-only plan or no GPU) */
+};
+
+/* precision of the per-batch contractions */
+enum {
+  Q4C_PREC_F64 = 0,      /* FP64 MFMA, FP64 accumulation */
+  Q4C_PREC_SPLIT_F32 = 1 /* FP32 MFMA on hi+lo split operands, FP32 per-batch
+                            accumulation, FP64 batch-to-global sums; the V part
+                            stays on FP64 MFMA (see q4c_integrate_H) */
+};
+
+/* flags of q4c_integrate_H */
+enum {
+  Q4C_ACCUMULATE = 1u,     /* add into the store instead of overwriting it */
+  Q4C_ASSEMBLE_W = 2u,     /* also write the W spinor blocks */
+  Q4C_ASSEMBLE_V = 4u,     /* also write the V spinor blocks (V (x) I2) */
+  Q4C_CHECK_FINITE = 8u    /* reject a potential with NaN/Inf (synchronises) */
+};
+
+/* plan option flags */
+enum {
+  Q4C_PLAN_HOST_ONLY = 1   /* build host structures only (no device upload) */
+};
+
+typedef struct q4c_plan q4c_plan;
+
+/* Basis set: per-atom shells with piecewise-cubic radial tables.
+ * Shell s: angular momentum shell_l[s] in 0..3, cutoff shell_rcut[s] > 0,
+ * nint = shell_nint[s] >= 1 intervals on knots r_j = rcut (j / nint)^2,
+ * coefficients coef[shell_coef_off[s] + 4 j + k], k = 0..3, such that for
+ * r_j <= s < r_{j+1} and t = (s - r_j) / (r_{j+1} - r_j):
+ *     Rt(s) = c0 + c1 t + c2 t^2 + c3 t^3,   Rt(s) = 0 for s >= rcut.
+ * Rt is the radial function divided by s^l (paper Eq. 12a: P(r)/r = Rt s^l),
+ * so phi = Rt(s) s^l Y_lm.  Shells may share coefficient ranges. */
+typedef struct {
+  int32_t n_atoms;
+  const double *R;               /* [3 n_atoms] positions, xyz interleaved */
+  const int32_t *atom_shell_off; /* [n_atoms + 1], non-decreasing, from 0 */
+  int32_t n_shells;
+  const int32_t *shell_l;        /* [n_shells] */
+  const double *shell_rcut;      /* [n_shells] */
+  const int32_t *shell_nint;     /* [n_shells] */
+  const int64_t *shell_coef_off; /* [n_shells] offsets into coef (doubles) */
+  int64_t n_coef;                /* length of coef */
+  const double *coef;
+} q4c_basis;
+
+/* Integration grid in the caller's point order ("user order"). */
+typedef struct {
+  int64_t n_points;
+  const double *x, *y, *z;  /* [n_points] bohr */
+  const double *w;          /* [n_points] quadrature x partition weight, finite */
+} q4c_grid;
+
+typedef struct {
+  double c_light;           /* speed of light in a.u.; <= 0 selects 137.035999084 */
+  int32_t p_max;            /* max points per batch; <= 0 selects 300 */
+  int32_t flags;            /* Q4C_PLAN_* */
+  int64_t staging_bytes;    /* per-plan staging budget; <= 0 selects 8 GiB */
+} q4c_opts;
+
+typedef struct {
+  int32_t n_atoms, n_fn;
+  int64_t n_points;        /* input points */
+  int64_t n_active;        /* points inside at least one basis support */
+  int64_t n_batches;
+  int64_t n_pairs;
+  int64_t store_len;       /* doubles per real part */
+  int64_t fn_entries;      /* sum over batches of relevant functions */
+  int64_t max_batch_points, max_batch_fn;
+  int64_t n_work;          /* contraction work items (batch, tile, tile) */
+  int64_t n_passes;        /* staging passes per call */
+  int64_t device_bytes;    /* device memory owned by the plan */
+  double flops_alg;        /* sum_B 10 P_B n_B^2, the algorithmic flop count of one H build */
+} q4c_info;
+
+/* Build a plan: batching (recursive median bisection of the active points to
+ * at most p_max points), per-batch relevant functions, the pair store layout,
+ * scatter maps and device buffers.  Paper Sec. III A: batches B_v (Eq. 31)
+ * and the reduced index set nnz(B_v).  Inputs are copied.  Returns
+ * Q4C_EUNSUPPORTED for l > 3 and Q4C_EINVAL for malformed descriptors. */
+int q4c_plan_create(const q4c_basis *basis, const q4c_grid *grid, const q4c_opts *opts, q4c_plan **out);
+
+/* Free a plan and its device memory; NULL is a no-op.  Synchronises the device. */
+void q4c_plan_destroy(q4c_plan *plan);
+
+int q4c_plan_info(const q4c_plan *plan, q4c_info *info);
+
+/* Pair list: pair_atoms[2p], pair_atoms[2p+1] = (A, B); pair_off[n_pairs + 1]
+ * offsets (doubles) into one real part.  Host buffers of the sizes in q4c_info. */
+int q4c_plan_pairs(const q4c_plan *plan, int32_t *pair_atoms, int64_t *pair_off);
+
+/* Batches: batch b holds points point_index[pt_off[b] .. pt_off[b+1]) (user
+ * indices) and functions fn_index[fn_off[b] .. fn_off[b+1]) (global indices,
+ * ascending).  Sizes: n_batches + 1, n_active, n_batches + 1, fn_entries.
+ * Any pointer may be NULL to skip it. */
+int q4c_plan_batches(const q4c_plan *plan, int64_t *pt_off, int64_t *point_index, int64_t *fn_off,
+                     int32_t *fn_index);
+
+/* Number of doubles nao_tabulate writes for batches [b0, b1). */
+int q4c_tabulate_size(const q4c_plan *plan, int64_t b0, int64_t b1, int32_t deriv, int64_t *n_doubles);
+
+/* nao_tabulate: values (deriv = 0) or values and gradients (deriv = 1) of the
+ * relevant functions of batches [b0, b1) at their points (Eq. 12a, App. B).
+ * Output (device, FP64): batch after batch; batch b is a [ncomp][P_b][n_b]
+ * array (ncomp = 1 or 4: phi, d/dx, d/dy, d/dz), points in the batch order of
+ * q4c_plan_batches, functions in the order of fn_index.  out_len (doubles)
+ * must be at least q4c_tabulate_size(); else Q4C_ESIZE. */
+int nao_tabulate(const q4c_plan *plan, int64_t b0, int64_t b1, int32_t deriv, double *out_dev, int64_t out_len,
+                 void *stream);
+
+/* q4c_integrate_H: the five real parts of the atom-pair store from the
+ * potential v (device, [n_points], user order, hartree):
+ * store_dev[0..5 store_len) = V, Ws, Wso_x, Wso_y, Wso_z with c' applied.
+ * Q4C_PREC_F64 runs the per-batch contractions on FP64 MFMA; Q4C_PREC_SPLIT_F32
+ * runs the four W parts on FP32 MFMA with hi+lo split operands and FP32
+ * accumulation within a batch, and V on FP64 MFMA (its elements reach
+ * ~1e2 Ha, where FP32 accumulation cannot hold 1e-8 Ha).  Batch partial sums
+ * are added to the store in FP64 in a fixed order, so repeated calls are
+ * bitwise identical.  With Q4C_ASSEMBLE_W / _V the spinor blocks are written
+ * to spin_w_dev / spin_v_dev (complex128, 4 store_len elements each). */
+int q4c_integrate_H(const q4c_plan *plan, const double *v_dev, int32_t precision, uint32_t flags,
+                    double *store_dev, double *spin_w_dev, double *spin_v_dev, void *stream);
+
+/* density_on_grid: for coefficients C on the stored elements (device,
+ * 5 store_len doubles, same layout as the store, c' NOT included),
+ *   n_g = sum_{stored ij} [ C^V_ij phi_i phi_j + c' C^Ws_ij grad phi_i . grad phi_j
+ *                            + c' sum_m C^m_ij (grad phi_i x grad phi_j)_m ]
+ * (paper Eq. 39 on the scalar basis).  out_dev[g] (device, [n_points], user
+ * order) = n_g (weight_mode 0) or w_g n_g (weight_mode 1).  With weight_mode 1
+ * and C = dL/d(store), out is dL/dv: the exact adjoint of q4c_integrate_H.
+ * terms selects Q4C_TERM_* (bit set). */
+enum { Q4C_TERM_LL = 1u, Q4C_TERM_SS = 2u, Q4C_TERM_SO = 4u, Q4C_TERM_ALL = 7u };
+int density_on_grid(const q4c_plan *plan, const double *coef_dev, uint32_t terms, int32_t weight_mode,
+                    double *out_dev, void *stream);
+
+/* Coefficients on the stored elements from a Hermitian spinor density matrix
+ * D given as spinor blocks (device complex128, 4 store_len, spinor layout)
+ * such that density_on_grid yields Re Tr(D H) derivatives (Eq. 21/39):
+ * C^V = C^Ws = f Re tr2 D_ji, C^m = -f Im tr2(D_ji sigma_m), f = 2 on
+ * off-diagonal pairs (each stored block stands for its mirror), 1 on diagonal
+ * pairs.  coef_out_dev: 5 store_len doubles. */
+int q4c_coef_from_spinor(const q4c_plan *plan, const double *spin_d_dev, double *coef_out_dev, void *stream);
+
+/* Block until the plan's queued work is done; reports asynchronous HIP errors. */
+int q4c_plan_sync(const q4c_plan *plan, void *stream);
+
+const char *q4c_status_string(int status);
+const char *q4c_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* Q4C_H */

@@ -1,0 +1,267 @@
+"""Python binding of libq4c (Q4C real-space Hamiltonian integration on MI355X).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  PyTorch supplies device memory and the current stream.  The names
+follow the C ABI in include/q4c.h: ``nao_tabulate``, ``q4c_integrate_H``,
+``density_on_grid`` (plus plan helpers).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libq4c.so")
+
+Q4C_OK = 0
+Q4C_EINVAL, Q4C_ENOMEM, Q4C_EHIP, Q4C_ENOTIMPL, Q4C_EUNSUPPORTED, Q4C_ESIZE, Q4C_ENONFINITE, Q4C_ENODEV = \
+    -1, -2, -3, -4, -5, -6, -7, -8
+PREC_F64, PREC_SPLIT_F32 = 0, 1
+ACCUMULATE, ASSEMBLE_W, ASSEMBLE_V, CHECK_FINITE = 1, 2, 4, 8
+PLAN_HOST_ONLY = 1
+TERM_LL, TERM_SS, TERM_SO, TERM_ALL = 1, 2, 4, 7
+PART_NAMES = ("V", "Ws", "Wso_x", "Wso_y", "Wso_z")
+
+
+class Q4CError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("q4c status %d (%s): %s" % (status, _status_string(status), msg))
+        self.status = status
+
+
+_lib = None
+
+
+def _status_string(s):
+    try:
+        return _load().q4c_status_string(s).decode()
+    except Exception:  # pragma: no cover
+        return "?"
+
+
+class _Basis(ctypes.Structure):
+    _fields_ = [("n_atoms", ctypes.c_int32), ("R", ctypes.c_void_p), ("atom_shell_off", ctypes.c_void_p),
+                ("n_shells", ctypes.c_int32), ("shell_l", ctypes.c_void_p), ("shell_rcut", ctypes.c_void_p),
+                ("shell_nint", ctypes.c_void_p), ("shell_coef_off", ctypes.c_void_p), ("n_coef", ctypes.c_int64),
+                ("coef", ctypes.c_void_p)]
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("n_points", ctypes.c_int64), ("x", ctypes.c_void_p), ("y", ctypes.c_void_p),
+                ("z", ctypes.c_void_p), ("w", ctypes.c_void_p)]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("c_light", ctypes.c_double), ("p_max", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("staging_bytes", ctypes.c_int64)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("n_atoms", ctypes.c_int32), ("n_fn", ctypes.c_int32), ("n_points", ctypes.c_int64),
+                ("n_active", ctypes.c_int64), ("n_batches", ctypes.c_int64), ("n_pairs", ctypes.c_int64),
+                ("store_len", ctypes.c_int64), ("fn_entries", ctypes.c_int64), ("max_batch_points", ctypes.c_int64),
+                ("max_batch_fn", ctypes.c_int64), ("n_work", ctypes.c_int64), ("n_passes", ctypes.c_int64),
+                ("device_bytes", ctypes.c_int64), ("flops_alg", ctypes.c_double)]
+
+
+EXPORTS = ("q4c_plan_create", "q4c_plan_destroy", "q4c_plan_info", "q4c_plan_pairs", "q4c_plan_batches",
+           "q4c_tabulate_size", "nao_tabulate", "q4c_integrate_H", "density_on_grid", "q4c_coef_from_spinor",
+           "q4c_plan_sync", "q4c_status_string", "q4c_last_error")
+
+
+def _load():
+    """Load libq4c.so.  There is no fallback: a missing library is an error."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libq4c.so not built (run __graft_entry__.build() or "
+                              "python paper_2608_00773_amd/build.py): %s" % LIB_PATH)
+        lib = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+        lib.q4c_plan_create.argtypes = [ctypes.POINTER(_Basis), ctypes.POINTER(_Grid), ctypes.POINTER(_Opts),
+                                        ctypes.POINTER(vp)]
+        lib.q4c_plan_destroy.argtypes = [vp]
+        lib.q4c_plan_destroy.restype = None
+        lib.q4c_plan_info.argtypes = [vp, ctypes.POINTER(_Info)]
+        lib.q4c_plan_pairs.argtypes = [vp, vp, vp]
+        lib.q4c_plan_batches.argtypes = [vp, vp, vp, vp, vp]
+        lib.q4c_tabulate_size.argtypes = [vp, i64, i64, i32, ctypes.POINTER(i64)]
+        lib.nao_tabulate.argtypes = [vp, i64, i64, i32, vp, i64, vp]
+        lib.q4c_integrate_H.argtypes = [vp, vp, i32, u32, vp, vp, vp, vp]
+        lib.density_on_grid.argtypes = [vp, vp, u32, i32, vp, vp]
+        lib.q4c_coef_from_spinor.argtypes = [vp, vp, vp, vp]
+        lib.q4c_plan_sync.argtypes = [vp, vp]
+        lib.q4c_status_string.argtypes = [ctypes.c_int]
+        lib.q4c_status_string.restype = ctypes.c_char_p
+        lib.q4c_last_error.argtypes = []
+        lib.q4c_last_error.restype = ctypes.c_char_p
+        for name in EXPORTS:
+            if name not in ("q4c_plan_destroy", "q4c_status_string", "q4c_last_error"):
+                getattr(lib, name).restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _check(rc: int):
+    if rc != Q4C_OK:
+        raise Q4CError(rc, _load().q4c_last_error().decode())
+
+
+def _np(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+def _stream_handle():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_ptr(t, dtype_name="float64", min_numel=0, name="tensor"):
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if str(t.dtype) != "torch." + dtype_name:
+        raise TypeError("%s must be %s, got %s" % (name, dtype_name, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if t.numel() < min_numel:
+        raise ValueError("%s has %d elements, needs %d" % (name, t.numel(), min_numel))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """An integration plan for one system and grid (q4c_plan_create)."""
+
+    def __init__(self, wl, p_max: Optional[int] = None, c_light: Optional[float] = None, host_only: bool = False,
+                 staging_bytes: int = 0):
+        lib = _load()
+        self._keep = dict(
+            R=_np(wl.R, np.float64).reshape(-1), aso=_np(wl.atom_shell_off, np.int32), sl=_np(wl.shell_l, np.int32),
+            sr=_np(wl.shell_rcut, np.float64), sn=_np(wl.shell_nint, np.int32),
+            so=_np(wl.shell_coef_off, np.int64), coef=_np(wl.coef, np.float64), x=_np(wl.x, np.float64),
+            y=_np(wl.y, np.float64), z=_np(wl.z, np.float64), w=_np(wl.w, np.float64))
+        k = self._keep
+        b = _Basis(int(k["aso"].size - 1), k["R"].ctypes.data, k["aso"].ctypes.data, int(k["sl"].size),
+                   k["sl"].ctypes.data, k["sr"].ctypes.data, k["sn"].ctypes.data, k["so"].ctypes.data,
+                   int(k["coef"].size), k["coef"].ctypes.data)
+        g = _Grid(int(k["x"].size), k["x"].ctypes.data, k["y"].ctypes.data, k["z"].ctypes.data, k["w"].ctypes.data)
+        if p_max is None:
+            p_max = int(getattr(wl, "meta", {}).get("p_max", 300))
+        o = _Opts(float(c_light if c_light is not None else getattr(wl, "c_light", 0.0)), int(p_max),
+                  PLAN_HOST_ONLY if host_only else 0, int(staging_bytes))
+        h = ctypes.c_void_p()
+        _check(lib.q4c_plan_create(ctypes.byref(b), ctypes.byref(g), ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self._keep = None
+        self.info = self._info()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _load().q4c_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _info(self):
+        inf = _Info()
+        _check(_load().q4c_plan_info(self._h, ctypes.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in _Info._fields_}
+
+    def pairs(self):
+        n = self.info["n_pairs"]
+        pa = np.zeros(2 * max(n, 1), dtype=np.int32)
+        po = np.zeros(n + 1, dtype=np.int64)
+        _check(_load().q4c_plan_pairs(self._h, pa.ctypes.data, po.ctypes.data))
+        return pa[:2 * n].reshape(n, 2), po
+
+    def batches(self):
+        nb, na, fe = self.info["n_batches"], self.info["n_active"], self.info["fn_entries"]
+        pt_off = np.zeros(nb + 1, dtype=np.int64)
+        pidx = np.zeros(max(na, 1), dtype=np.int64)
+        fn_off = np.zeros(nb + 1, dtype=np.int64)
+        fidx = np.zeros(max(fe, 1), dtype=np.int32)
+        _check(_load().q4c_plan_batches(self._h, pt_off.ctypes.data, pidx.ctypes.data, fn_off.ctypes.data,
+                                        fidx.ctypes.data))
+        return pt_off, pidx[:na], fn_off, fidx[:fe]
+
+    def tabulate_size(self, b0: int, b1: int, deriv: int = 1) -> int:
+        n = ctypes.c_int64()
+        _check(_load().q4c_tabulate_size(self._h, int(b0), int(b1), int(deriv), ctypes.byref(n)))
+        return int(n.value)
+
+    def sync(self):
+        _check(_load().q4c_plan_sync(self._h, _stream_handle()))
+
+
+# ---------------------------------------------------------------------------
+# C-ABI calls on torch device tensors
+# ---------------------------------------------------------------------------
+
+def nao_tabulate(plan: Plan, b0: int, b1: int, deriv: int, out):
+    """Write the batch panels of batches [b0, b1) into `out` (float64 CUDA tensor)."""
+    need = plan.tabulate_size(b0, b1, deriv)
+    _check(_load().nao_tabulate(plan.handle, int(b0), int(b1), int(deriv), _dev_ptr(out, name="out"),
+                                int(out.numel()), _stream_handle()))
+    return need
+
+
+def q4c_integrate_H(plan: Plan, v, precision: int = PREC_F64, flags: int = 0, store=None, spin_w=None,
+                    spin_v=None):
+    """Integrate the five real parts into `store` ([5, store_len] float64)."""
+    L = plan.info["store_len"]
+    _check(_load().q4c_integrate_H(
+        plan.handle, _dev_ptr(v, min_numel=plan.info["n_points"], name="v"), int(precision), int(flags),
+        _dev_ptr(store, min_numel=5 * L, name="store"),
+        _dev_ptr(spin_w, min_numel=8 * L, name="spin_w") if spin_w is not None else None,
+        _dev_ptr(spin_v, min_numel=8 * L, name="spin_v") if spin_v is not None else None, _stream_handle()))
+    return store
+
+
+def density_on_grid(plan: Plan, coef, terms: int = TERM_ALL, weight_mode: int = 0, out=None):
+    L = plan.info["store_len"]
+    _check(_load().density_on_grid(plan.handle, _dev_ptr(coef, min_numel=5 * L, name="coef"), int(terms),
+                                   int(weight_mode), _dev_ptr(out, min_numel=plan.info["n_points"], name="out"),
+                                   _stream_handle()))
+    return out
+
+
+def q4c_coef_from_spinor(plan: Plan, spin_d, out):
+    L = plan.info["store_len"]
+    _check(_load().q4c_coef_from_spinor(plan.handle, _dev_ptr(spin_d, min_numel=8 * L, name="spin_d"),
+                                        _dev_ptr(out, min_numel=5 * L, name="out"), _stream_handle()))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Convenience: allocation through torch
+# ---------------------------------------------------------------------------
+
+def new_store(plan: Plan, device="cuda"):
+    import torch
+    return torch.empty((5, plan.info["store_len"]), dtype=torch.float64, device=device)
+
+
+def new_spinor(plan: Plan, device="cuda"):
+    import torch
+    return torch.empty((4 * plan.info["store_len"], 2), dtype=torch.float64, device=device)
+
+
+def integrate(plan: Plan, v, precision: int = PREC_F64, assemble: bool = False):
+    """Allocate outputs and run q4c_integrate_H; returns (store, spin_w or None)."""
+    store = new_store(plan, v.device)
+    spin_w = new_spinor(plan, v.device) if assemble else None
+    q4c_integrate_H(plan, v, precision, ASSEMBLE_W if assemble else 0, store, spin_w)
+    return store, spin_w

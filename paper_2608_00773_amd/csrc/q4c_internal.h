@@ -1,0 +1,143 @@
+// Internal declarations shared by the host plan builder and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "q4c.h"
+
+namespace q4c {
+
+// Contraction tile edge (functions) and points per staged K chunk.
+constexpr int kTile = 64;
+constexpr int kChunk = 16;
+
+// Work item of the contraction / adjoint kernels: one (batch, row tile, column tile)
+// with ti <= tj over the batch's local function list.
+struct WorkItem {
+  int32_t batch;
+  int16_t ti, tj;
+};
+
+// Everything a kernel needs about the plan, as raw device pointers.
+struct DevPlan {
+  // basis
+  const double *R;             // [3 n_atoms]
+  const int32_t *fn_atom;      // [n_fn]
+  const int32_t *fn_shlm;      // [n_fn] shell * 16 + (l*l + l + m)
+  const double *shell_rcut;    // [n_shells]
+  const int32_t *shell_nint;   // [n_shells]
+  const int64_t *shell_coef_off;
+  const double *coef;
+  // grid, batch order
+  const double *px, *py, *pz, *pw;  // [n_active]
+  const int32_t *perm;              // [n_active] user index
+  const int32_t *batch_pt_off;      // [n_batches + 1]
+  const int32_t *batch_fn_off;      // [n_batches + 1]
+  const int32_t *loc_fn;            // [fn_entries] global function
+  const int32_t *loc_slot;          // [fn_entries] slot (relevant atom) within the batch
+  const int32_t *batch_slot_off;    // [n_batches + 1]
+  const int32_t *slot_fnoff;        // [n_slots] local function offset of the slot
+  const int32_t *slot_nfn;          // [n_slots]
+  const int64_t *slot_row_off;      // [n_slots] staging offset of the slot's block row (pass relative)
+  const int64_t *work_part_off;     // [n_work] adjoint partial offset (pass relative)
+  const int64_t *pair_off;          // [n_pairs + 1]
+  const int32_t *pair_na, *pair_nb; // [n_pairs]
+  const int32_t *pair_a, *pair_b;   // [n_pairs]
+  const int64_t *batch_work_off;    // [n_batches + 1] first work item of each batch
+  const int64_t *tab_off;           // [n_batches + 1] prefix of P_b n_b (nao_tabulate layout)
+  int64_t store_len;
+  int64_t n_active;
+  int64_t n_points;
+  double cprime;  // 1 / (4 c^2)
+};
+
+struct Pass {
+  int64_t b0, b1;        // batch range
+  int64_t w0, w1;        // work range
+  int64_t r0, r1;        // reduction-entry range
+  int64_t z0, z1;        // zero-block range (non-pair slot combinations)
+  int64_t staging_len;   // doubles
+  int64_t partial_len;   // doubles (adjoint partials, stored after the staging)
+};
+
+}  // namespace q4c
+
+struct q4c_plan {
+  // ---- host copies of the inputs
+  int32_t n_atoms = 0, n_shells = 0, n_fn = 0;
+  std::vector<double> R;
+  std::vector<int32_t> atom_shell_off, shell_l, shell_nint;
+  std::vector<double> shell_rcut;
+  std::vector<int64_t> shell_coef_off;
+  std::vector<double> coef;
+  std::vector<int32_t> atom_fn_off;  // [n_atoms + 1]
+  std::vector<double> atom_rcut;     // [n_atoms]
+  std::vector<int32_t> fn_atom, fn_shlm;
+  double c_light = 137.035999084;
+  int32_t p_max = 300;
+  int32_t flags = 0;
+  int64_t staging_budget = 0;
+
+  // ---- grid / batches
+  int64_t n_points = 0, n_active = 0, n_batches = 0;
+  std::vector<int32_t> perm;  // batch-ordered active point -> user index
+  std::vector<double> px, py, pz, pw;
+  std::vector<int32_t> batch_pt_off, batch_fn_off, loc_fn, loc_slot;
+  std::vector<int32_t> batch_slot_off, slot_atom, slot_fnoff, slot_nfn;
+  std::vector<int64_t> slot_row_off;
+
+  // ---- pairs
+  int64_t n_pairs = 0, store_len = 0;
+  std::vector<int32_t> pair_a, pair_b, pair_na, pair_nb;
+  std::vector<int64_t> pair_off;
+  std::vector<int64_t> atom_pair_start;  // [n_atoms + 1] pairs with first atom A
+
+  // ---- work, passes, reductions
+  std::vector<q4c::WorkItem> work;
+  std::vector<int64_t> work_part_off;
+  std::vector<q4c::Pass> passes;
+  std::vector<int32_t> red_pair;
+  std::vector<uint8_t> red_first;
+  std::vector<int64_t> red_inc_off;  // [n_red + 1]
+  std::vector<int64_t> inc_src;      // staging offsets (pass relative)
+  std::vector<int32_t> untouched_pairs;
+  std::vector<int64_t> zero_off, zero_len;  // staged blocks of slot combinations that are not stored pairs
+  std::vector<int64_t> batch_work_off, tab_off;
+  int64_t max_scratch = 0;
+  int64_t max_batch_points = 0, max_batch_fn = 0, fn_entries = 0;
+  double flops_alg = 0.0;
+
+  // ---- device
+  bool on_device = false;
+  int device = -1;
+  int64_t device_bytes = 0;
+  std::vector<void *> allocations;
+  q4c::DevPlan dp{};
+  q4c::WorkItem *d_work = nullptr;
+  int32_t *d_red_pair = nullptr;
+  uint8_t *d_red_first = nullptr;
+  int64_t *d_red_inc_off = nullptr;
+  int64_t *d_inc_src = nullptr;
+  int32_t *d_untouched = nullptr;
+  int64_t *d_zero_off = nullptr, *d_zero_len = nullptr;
+  double *d_staging = nullptr;
+  int32_t *d_flag = nullptr;
+};
+
+namespace q4c {
+void set_error(const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+
+// kernel launchers (q4c_kernels.hip)
+int launch_tabulate(const q4c_plan *p, int64_t b0, int64_t b1, int deriv, double *out, hipStream_t s);
+int launch_integrate(const q4c_plan *p, const double *v, int precision, uint32_t flags, double *store,
+                     double *spin_w, double *spin_v, hipStream_t s);
+int launch_density(const q4c_plan *p, const double *coef, uint32_t terms, int weight_mode, double *out,
+                   hipStream_t s);
+int launch_coef_from_spinor(const q4c_plan *p, const double *spin_d, double *coef_out, hipStream_t s);
+int launch_check_finite(const q4c_plan *p, const double *v, hipStream_t s, bool *finite);
+}  // namespace q4c

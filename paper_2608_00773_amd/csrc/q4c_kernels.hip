@@ -1,0 +1,725 @@
+// HIP kernels of libq4c for CDNA4 (gfx950).
+//
+//  k_tabulate        nao_tabulate: phi and grad phi of a batch's relevant
+//                    functions at its points (Eq. 12a, App. B).
+//  k_contract<prec>  per (batch, tile ti, tile tj) work item: tabulates the
+//                    row and column functions of the tile chunk by chunk of
+//                    16 points into LDS (values and gradients never touch
+//                    HBM) and accumulates the five weighted products
+//                        V  = Phi^T diag(w v) Phi
+//                        Gs = sum_a dPhi_a^T diag(w v) dPhi_a
+//                        Gm = dPhi_b^T diag(w v) dPhi_c - dPhi_c^T diag(w v) dPhi_b
+//                    on MFMA (Eq. 29 restricted to the batch, Eq. 31).
+//                    Only tiles ti <= tj run; the lower atom-block triangle
+//                    follows from (anti)symmetry.  Results go to a staging
+//                    buffer laid out per (batch, atom pair).
+//  k_reduce          deterministic batch-to-global sum: every stored atom
+//                    pair adds its staged blocks in batch order (FP64).
+//  k_spinor          2x2-spinor assembly of the W and V blocks.
+//  k_broadcast,
+//  k_density_tiles,
+//  k_density_points  density_on_grid: the transpose of the three steps above
+//                    (Eq. 39): coefficients are broadcast to the staged
+//                    layout, each tile contracts a_g^T C b_g at its points on
+//                    MFMA, and every point sums its tiles in a fixed order.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "q4c_internal.h"
+
+namespace q4c {
+namespace {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+constexpr int T = kTile;
+constexpr int KC = kChunk;
+constexpr int LDP = T + 1;  // padded LDS row (doubles): conflict-free column writes
+constexpr int NT = 256;     // threads per contraction workgroup (4 waves)
+
+// ---------------------------------------------------------------------------
+// Basis functions
+// ---------------------------------------------------------------------------
+
+// Real solid harmonics S_lm = s^l Y_lm (App. B convention, Condon-Shortley
+// phase as written there: Y_1,1 = -sqrt(3/4pi) x/s) and their gradients,
+// l <= 3, indexed by lm = l^2 + l + m.
+__device__ __forceinline__ void solid_harmonic(int lm, double x, double y, double z, double &S, double &gx,
+                                               double &gy, double &gz) {
+  constexpr double C00 = 0.28209479177387814, C1 = 0.4886025119029199, C2a = 1.0925484305920792,
+                   C20 = 0.31539156525252005, C22 = 0.5462742152960396, C33 = 0.5900435899266435,
+                   C32b = 2.8906114426405543, C31 = 0.4570457994644657, C30 = 0.3731763325901154,
+                   C32a = 1.4453057213202771;
+  switch (lm) {
+    case 0: S = C00; gx = gy = gz = 0.0; break;
+    case 1: S = -C1 * y; gx = 0.0; gy = -C1; gz = 0.0; break;
+    case 2: S = C1 * z; gx = 0.0; gy = 0.0; gz = C1; break;
+    case 3: S = -C1 * x; gx = -C1; gy = 0.0; gz = 0.0; break;
+    case 4: S = C2a * x * y; gx = C2a * y; gy = C2a * x; gz = 0.0; break;
+    case 5: S = -C2a * y * z; gx = 0.0; gy = -C2a * z; gz = -C2a * y; break;
+    case 6: S = C20 * (2.0 * z * z - x * x - y * y); gx = -2.0 * C20 * x; gy = -2.0 * C20 * y; gz = 4.0 * C20 * z; break;
+    case 7: S = -C2a * x * z; gx = -C2a * z; gy = 0.0; gz = -C2a * x; break;
+    case 8: S = C22 * (x * x - y * y); gx = 2.0 * C22 * x; gy = -2.0 * C22 * y; gz = 0.0; break;
+    case 9: S = -C33 * y * (3.0 * x * x - y * y); gx = -6.0 * C33 * x * y; gy = -3.0 * C33 * (x * x - y * y); gz = 0.0; break;
+    case 10: S = C32b * x * y * z; gx = C32b * y * z; gy = C32b * x * z; gz = C32b * x * y; break;
+    case 11: {
+      double q = 4.0 * z * z - x * x - y * y;
+      S = -C31 * y * q; gx = 2.0 * C31 * x * y; gy = -C31 * (q - 2.0 * y * y); gz = -8.0 * C31 * y * z;
+    } break;
+    case 12: S = C30 * z * (2.0 * z * z - 3.0 * x * x - 3.0 * y * y); gx = -6.0 * C30 * x * z; gy = -6.0 * C30 * y * z;
+      gz = C30 * (6.0 * z * z - 3.0 * x * x - 3.0 * y * y); break;
+    case 13: {
+      double q = 4.0 * z * z - x * x - y * y;
+      S = -C31 * x * q; gx = -C31 * (q - 2.0 * x * x); gy = 2.0 * C31 * x * y; gz = -8.0 * C31 * x * z;
+    } break;
+    case 14: S = C32a * z * (x * x - y * y); gx = 2.0 * C32a * x * z; gy = -2.0 * C32a * y * z; gz = C32a * (x * x - y * y); break;
+    default: S = -C33 * x * (x * x - 3.0 * y * y); gx = -3.0 * C33 * (x * x - y * y); gy = 6.0 * C33 * x * y; gz = 0.0; break;
+  }
+}
+
+// phi and grad phi of global function fn at point (px, py, pz):
+// phi = Rt(s) S_lm(d), grad phi = Rt'(s) (d / s) S_lm + Rt(s) grad S_lm, d = p - R_A.
+__device__ __forceinline__ void tab_one(const DevPlan &d, int fn, double px, double py, double pz, double &f,
+                                        double &fx, double &fy, double &fz) {
+  const int a = d.fn_atom[fn];
+  const int shlm = d.fn_shlm[fn];
+  const int sh = shlm >> 4;
+  const double dx = px - d.R[3 * a], dy = py - d.R[3 * a + 1], dz = pz - d.R[3 * a + 2];
+  const double s2 = dx * dx + dy * dy + dz * dz;
+  const double rc = d.shell_rcut[sh];
+  const double s = sqrt(s2);
+  if (!(s < rc)) {
+    f = fx = fy = fz = 0.0;
+    return;
+  }
+  const int n = d.shell_nint[sh];
+  int j = (int)((double)n * sqrt(s / rc));
+  j = j > n - 1 ? n - 1 : j;
+  const double fj = (double)j, inv_n2 = 1.0 / ((double)n * (double)n);
+  const double rj = rc * fj * fj * inv_n2;
+  const double h = rc * (2.0 * fj + 1.0) * inv_n2;
+  const double t = (s - rj) / h;
+  const dbl4 c = *reinterpret_cast<const dbl4 *>(d.coef + d.shell_coef_off[sh] + 4 * (int64_t)j);
+  const double R = ((c[3] * t + c[2]) * t + c[1]) * t + c[0];
+  const double dR = ((3.0 * c[3] * t + 2.0 * c[2]) * t + c[1]) / h;
+  double S, gx, gy, gz;
+  solid_harmonic(shlm & 15, dx, dy, dz, S, gx, gy, gz);
+  const double q = s > 0.0 ? dR / s : 0.0;
+  f = R * S;
+  fx = q * dx * S + R * gx;
+  fy = q * dy * S + R * gy;
+  fz = q * dz * S + R * gz;
+}
+
+// ---------------------------------------------------------------------------
+// nao_tabulate
+// ---------------------------------------------------------------------------
+
+__global__ void k_tabulate(DevPlan d, int64_t b0, int deriv, double *out) {
+  const int64_t b = b0 + blockIdx.x;
+  const int g0 = d.batch_pt_off[b], P = d.batch_pt_off[b + 1] - g0;
+  const int f0 = d.batch_fn_off[b], n = d.batch_fn_off[b + 1] - f0;
+  double *o = out + (deriv ? 4 : 1) * (d.tab_off[b] - d.tab_off[b0]);
+  const int64_t plane = (int64_t)P * n;
+  for (int64_t it = threadIdx.x; it < plane; it += blockDim.x) {
+    const int g = (int)(it / n), i = (int)(it - (int64_t)g * n);
+    double f, fx, fy, fz;
+    tab_one(d, d.loc_fn[f0 + i], d.px[g0 + g], d.py[g0 + g], d.pz[g0 + g], f, fx, fy, fz);
+    o[it] = f;
+    if (deriv) {
+      o[plane + it] = fx;
+      o[2 * plane + it] = fy;
+      o[3 * plane + it] = fz;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Contraction
+// ---------------------------------------------------------------------------
+
+// Shared staging of one 16-point chunk: [comp][point][function] with padded rows.
+struct ChunkLDS {
+  double a[4 * KC * LDP];  // row functions
+  double b[4 * KC * LDP];  // column functions (weighted by w v in the forward)
+};
+
+// Tabulate the chunk's row (and unless diagonal, column) functions.  With
+// `om` the column side is multiplied by the point weights om[pt].
+__device__ __forceinline__ void fill_chunk(const DevPlan &d, ChunkLDS &L, const int *s_fn, int g0, int P, int k0,
+                                           bool diag, const double *om) {
+  const int nside = diag ? 1 : 2;
+  for (int it = threadIdx.x; it < nside * T * KC; it += NT) {
+    const int side = it / (T * KC);
+    const int rem = it - side * (T * KC);
+    const int fl = rem / KC, pt = rem - fl * KC;
+    const int fn = s_fn[side * T + fl];
+    const int g = k0 + pt;
+    double f = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
+    if (fn >= 0 && g < P) tab_one(d, fn, d.px[g0 + g], d.py[g0 + g], d.pz[g0 + g], f, fx, fy, fz);
+    double *dst = side ? L.b : L.a;
+    if (side && om) {
+      const double w = om[pt];
+      f *= w; fx *= w; fy *= w; fz *= w;
+    }
+    dst[(0 * KC + pt) * LDP + fl] = f;
+    dst[(1 * KC + pt) * LDP + fl] = fx;
+    dst[(2 * KC + pt) * LDP + fl] = fy;
+    dst[(3 * KC + pt) * LDP + fl] = fz;
+  }
+  if (diag) {
+    __syncthreads();
+    for (int it = threadIdx.x; it < 4 * KC * T; it += NT) {
+      const int q = it / (KC * T);
+      const int rem = it - q * (KC * T);
+      const int pt = rem / T, fl = rem - pt * T;
+      const double w = om ? om[pt] : 1.0;
+      L.b[(q * KC + pt) * LDP + fl] = L.a[(q * KC + pt) * LDP + fl] * w;
+    }
+  }
+}
+
+__device__ __forceinline__ dbl4 mfma64(double a, double b, dbl4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ flt4 mfma32(float a, float b, flt4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Staging address of element (li, lj) of a batch (local function indices) for
+// part q, given the slot data of li (row) and lj (column).
+struct SlotInfo {
+  int slot, fnoff, nfn;
+  int64_t row_off;
+};
+
+__device__ __forceinline__ SlotInfo slot_of(const DevPlan &d, int fbase, int sbase, int lf) {
+  SlotInfo s;
+  s.slot = d.loc_slot[fbase + lf];
+  s.fnoff = d.slot_fnoff[sbase + s.slot];
+  s.nfn = d.slot_nfn[sbase + s.slot];
+  s.row_off = d.slot_row_off[sbase + s.slot];
+  return s;
+}
+
+// The five parts: 0 V, 1 Ws, 2 Wso_x, 3 Wso_y, 4 Wso_z.  Mirror sign under
+// (i, j) -> (j, i): + for V, Ws; - for the spin-orbit parts.
+__device__ __forceinline__ double mirror_sign(int q) { return q >= 2 ? -1.0 : 1.0; }
+
+// Write one accumulated tile element to the staged (batch, atom pair) block.
+template <int Q0, int Q1>
+__device__ __forceinline__ void stage_store(double *staging, const SlotInfo &si, const SlotInfo &sj, int li, int lj,
+                                            bool diag, const double *v) {
+  if (si.slot > sj.slot) return;  // lower atom-block triangle (diagonal tiles only)
+  const int64_t blk = si.row_off + 5 * (int64_t)si.nfn * (sj.fnoff - si.fnoff);
+  const int64_t pq = (int64_t)si.nfn * sj.nfn;
+  const int64_t e = (int64_t)(li - si.fnoff) * sj.nfn + (lj - sj.fnoff);
+#pragma unroll
+  for (int q = Q0; q < Q1; ++q) staging[blk + q * pq + e] = v[q - Q0];
+  if (!diag && si.slot == sj.slot) {
+    // same atom block split over two tiles: the mirrored element lives in
+    // tile (tj, ti), which is not computed
+    const int64_t em = (int64_t)(lj - si.fnoff) * sj.nfn + (li - sj.fnoff);
+#pragma unroll
+    for (int q = Q0; q < Q1; ++q) staging[blk + q * pq + em] = mirror_sign(q) * v[q - Q0];
+  }
+}
+
+// MFMA 16x16x4 lane layouts (lane l, l16 = l % 16, lk = l / 16):
+//   A[i][k]: lane i + 16 k;  B[k][j]: lane j + 16 k;
+//   D (f64_16x16x4): register r of lane l holds D[lk + 4 r][l16];
+//   D (f32_16x16x4): register r of lane l holds D[4 lk + r][l16].
+__device__ __forceinline__ int d_row_f64(int lk, int r) { return lk + 4 * r; }
+__device__ __forceinline__ int d_row_f32(int lk, int r) { return 4 * lk + r; }
+//
+// Precision modes of the forward contraction.
+enum { MODE_F64 = 0, MODE_SPLIT = 1 };
+
+template <int MODE>
+__global__ __launch_bounds__(NT, 2) void k_contract(DevPlan d, const WorkItem *work, int64_t w0, const double *v,
+                                                    double *staging) {
+  __shared__ ChunkLDS L;
+  __shared__ int s_fn[2 * T];
+  __shared__ double s_om[KC];
+  const WorkItem it = work[w0 + blockIdx.x];
+  const int b = it.batch;
+  const int g0 = d.batch_pt_off[b], P = d.batch_pt_off[b + 1] - g0;
+  const int f0 = d.batch_fn_off[b], n = d.batch_fn_off[b + 1] - f0;
+  const int sbase = d.batch_slot_off[b];
+  const int r0 = it.ti * T, c0 = it.tj * T;
+  const bool diag = it.ti == it.tj;
+  const int tid = threadIdx.x;
+  if (tid < 2 * T) {
+    const int lf = (tid < T ? r0 : c0) + (tid & (T - 1));
+    s_fn[tid] = lf < n ? d.loc_fn[f0 + lf] : -1;
+  }
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;  // wave sub-tile origin within the tile
+  const int li16 = lane & 15, lk = lane >> 4;
+
+  dbl4 acc[2][2][5];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int q = 0; q < 5; ++q) acc[x][y][q] = dbl4{0.0, 0.0, 0.0, 0.0};
+  // split mode: FP32 accumulators of the four W parts
+  flt4 accf[2][2][4];
+  if (MODE == MODE_SPLIT) {
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) accf[x][y][q] = flt4{0.f, 0.f, 0.f, 0.f};
+  }
+
+  for (int k0 = 0; k0 < P; k0 += KC) {
+    __syncthreads();  // previous chunk fully consumed; s_fn visible on the first pass
+    if (tid < KC) {
+      const int g = k0 + tid;
+      s_om[tid] = g < P ? d.pw[g0 + g] * v[d.perm[g0 + g]] : 0.0;
+    }
+    __syncthreads();
+    fill_chunk(d, L, s_fn, g0, P, k0, diag, s_om);
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < KC / 4; ++ks) {
+      const int pt = ks * 4 + lk;
+      double a[2][4], bb[2][4];
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a[x][q] = L.a[(q * KC + pt) * LDP + wr + x * 16 + li16];
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bb[y][q] = L.b[(q * KC + pt) * LDP + wc + y * 16 + li16];
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+          acc[x][y][0] = mfma64(a[x][0], bb[y][0], acc[x][y][0]);
+          if (MODE == MODE_F64) {
+            acc[x][y][1] = mfma64(a[x][1], bb[y][1], acc[x][y][1]);
+            acc[x][y][1] = mfma64(a[x][2], bb[y][2], acc[x][y][1]);
+            acc[x][y][1] = mfma64(a[x][3], bb[y][3], acc[x][y][1]);
+            acc[x][y][2] = mfma64(a[x][2], bb[y][3], acc[x][y][2]);
+            acc[x][y][2] = mfma64(-a[x][3], bb[y][2], acc[x][y][2]);
+            acc[x][y][3] = mfma64(a[x][3], bb[y][1], acc[x][y][3]);
+            acc[x][y][3] = mfma64(-a[x][1], bb[y][3], acc[x][y][3]);
+            acc[x][y][4] = mfma64(a[x][1], bb[y][2], acc[x][y][4]);
+            acc[x][y][4] = mfma64(-a[x][2], bb[y][1], acc[x][y][4]);
+          } else {
+            // hi + lo split: x = hi + lo with hi = fl(x), lo = fl(x - hi);
+            // x y ~ hi_x hi_y + hi_x lo_y + lo_x hi_y (lo_x lo_y dropped)
+            float ah[4], al[4], bh[4], bl[4];
+#pragma unroll
+            for (int q = 1; q < 4; ++q) {
+              ah[q] = (float)a[x][q];
+              al[q] = (float)(a[x][q] - (double)ah[q]);
+              bh[q] = (float)bb[y][q];
+              bl[q] = (float)(bb[y][q] - (double)bh[q]);
+            }
+#define SPLIT3(ACC, AI, BI, SG)                                  \
+  ACC = mfma32(SG ah[AI], bh[BI], ACC);                          \
+  ACC = mfma32(SG ah[AI], bl[BI], ACC);                          \
+  ACC = mfma32(SG al[AI], bh[BI], ACC);
+            SPLIT3(accf[x][y][0], 1, 1, +)
+            SPLIT3(accf[x][y][0], 2, 2, +)
+            SPLIT3(accf[x][y][0], 3, 3, +)
+            SPLIT3(accf[x][y][1], 2, 3, +)
+            SPLIT3(accf[x][y][1], 3, 2, -)
+            SPLIT3(accf[x][y][2], 3, 1, +)
+            SPLIT3(accf[x][y][2], 1, 3, -)
+            SPLIT3(accf[x][y][3], 1, 2, +)
+            SPLIT3(accf[x][y][3], 2, 1, -)
+#undef SPLIT3
+          }
+        }
+    }
+  }
+
+  // write the tile to the staged atom-pair blocks
+  const double cp = d.cprime;
+#pragma unroll
+  for (int y = 0; y < 2; ++y) {
+    const int lj = c0 + wc + y * 16 + li16;
+    if (lj >= n) continue;
+    const SlotInfo sj = slot_of(d, f0, sbase, lj);
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int li = r0 + wr + x * 16 + d_row_f64(lk, r);
+        if (li < n) {
+          const SlotInfo si = slot_of(d, f0, sbase, li);
+          if (MODE == MODE_F64) {
+            double vals[5];
+            vals[0] = acc[x][y][0][r];
+#pragma unroll
+            for (int q = 1; q < 5; ++q) vals[q] = cp * acc[x][y][q][r];
+            stage_store<0, 5>(staging, si, sj, li, lj, diag, vals);
+          } else {
+            double v0 = acc[x][y][0][r];
+            stage_store<0, 1>(staging, si, sj, li, lj, diag, &v0);
+          }
+        }
+        if (MODE == MODE_SPLIT) {
+          const int lf = r0 + wr + x * 16 + d_row_f32(lk, r);
+          if (lf < n) {
+            const SlotInfo sf = slot_of(d, f0, sbase, lf);
+            double vals[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) vals[q] = cp * (double)accf[x][y][q][r];
+            stage_store<1, 5>(staging, sf, sj, lf, lj, diag, vals);
+          }
+        }
+      }
+  }
+}
+
+// Batch-to-global sum for one pass: reduction entry r adds the staged blocks
+// of pair red_pair[r] in batch order.
+__global__ void k_reduce(DevPlan d, int64_t r0, const int32_t *red_pair, const uint8_t *red_first,
+                         const int64_t *red_inc_off, const int64_t *inc_src, const double *staging, double *store,
+                         int accumulate) {
+  const int64_t r = r0 + blockIdx.x;
+  const int p = red_pair[r];
+  const int64_t blk = (int64_t)d.pair_na[p] * d.pair_nb[p];
+  const int64_t k0 = red_inc_off[r], k1 = red_inc_off[r + 1];
+  const bool add = accumulate || !red_first[r];
+  const int64_t po = d.pair_off[p];
+  for (int64_t e = threadIdx.x; e < 5 * blk; e += blockDim.x) {
+    double s = 0.0;
+    for (int64_t k = k0; k < k1; ++k) s += staging[inc_src[k] + e];
+    const int q = (int)(e / blk);
+    double *dst = store + q * d.store_len + po + (e - q * blk);
+    *dst = add ? *dst + s : s;
+  }
+}
+
+// Pairs no batch touches are zero unless accumulating.
+__global__ void k_zero_pairs(DevPlan d, const int32_t *pairs, double *store) {
+  const int p = pairs[blockIdx.x];
+  const int64_t blk = (int64_t)d.pair_na[p] * d.pair_nb[p];
+  for (int64_t e = threadIdx.x; e < 5 * blk; e += blockDim.x) {
+    const int q = (int)(e / blk);
+    store[q * d.store_len + d.pair_off[p] + (e - q * blk)] = 0.0;
+  }
+}
+
+// W_sp = Ws (x) I2 + i sum_m Wso_m (x) sigma_m and V_sp = V (x) I2, per pair a
+// (2 nA) x (2 nB) complex block, spin-major rows and columns.
+__global__ void k_spinor(DevPlan d, const double *store, double *spin_w, double *spin_v) {
+  const int p = blockIdx.x;
+  const int na = d.pair_na[p], nb = d.pair_nb[p];
+  const int64_t blk = (int64_t)na * nb;
+  const int64_t po = d.pair_off[p];
+  const int64_t L = d.store_len;
+  const int64_t cb = 8 * po;           // doubles: complex offset 4 po
+  const int64_t rs = 2 * (int64_t)nb;  // complex row stride
+  for (int64_t e = threadIdx.x; e < blk; e += blockDim.x) {
+    const int i = (int)(e / nb), j = (int)(e - (int64_t)i * nb);
+    const int64_t uu = 2 * ((int64_t)i * rs + j), ud = 2 * ((int64_t)i * rs + nb + j);
+    const int64_t du = 2 * ((int64_t)(na + i) * rs + j), dd = 2 * ((int64_t)(na + i) * rs + nb + j);
+    if (spin_w) {
+      const double ws = store[L + po + e], wx = store[2 * L + po + e], wy = store[3 * L + po + e],
+                   wz = store[4 * L + po + e];
+      double *o = spin_w + cb;
+      o[uu] = ws; o[uu + 1] = wz;
+      o[ud] = wy; o[ud + 1] = wx;
+      o[du] = -wy; o[du + 1] = wx;
+      o[dd] = ws; o[dd + 1] = -wz;
+    }
+    if (spin_v) {
+      const double vv = store[po + e];
+      double *o = spin_v + cb;
+      o[uu] = vv; o[uu + 1] = 0.0;
+      o[ud] = 0.0; o[ud + 1] = 0.0;
+      o[du] = 0.0; o[du + 1] = 0.0;
+      o[dd] = vv; o[dd + 1] = 0.0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint / density
+// ---------------------------------------------------------------------------
+
+// Copy the coefficient blocks of every stored pair to each of its staged
+// (batch, pair) blocks: the transpose of k_reduce.
+__global__ void k_broadcast(DevPlan d, int64_t r0, const int32_t *red_pair, const int64_t *red_inc_off,
+                            const int64_t *inc_src, const double *coef, double *staging) {
+  const int64_t r = r0 + blockIdx.x;
+  const int p = red_pair[r];
+  const int64_t blk = (int64_t)d.pair_na[p] * d.pair_nb[p];
+  const int64_t k0 = red_inc_off[r], k1 = red_inc_off[r + 1];
+  const int64_t po = d.pair_off[p];
+  for (int64_t e = threadIdx.x; e < 5 * blk; e += blockDim.x) {
+    const int q = (int)(e / blk);
+    const double c = coef[q * d.store_len + po + (e - q * blk)];
+    for (int64_t k = k0; k < k1; ++k) staging[inc_src[k] + e] = c;
+  }
+}
+
+// Effective coefficient of tile element (li, lj), part q (c' applied to W parts).
+// Staged blocks of slot combinations that are not stored pairs hold zeros.
+__device__ __forceinline__ double coef_elem(const DevPlan &d, const double *staging, int f0, int sbase, int n, int li,
+                                            int lj, int q, bool diag) {
+  if (li >= n || lj >= n) return 0.0;
+  const SlotInfo si = slot_of(d, f0, sbase, li), sj = slot_of(d, f0, sbase, lj);
+  if (si.slot > sj.slot) return 0.0;
+  const int64_t blk = si.row_off + 5 * (int64_t)si.nfn * (sj.fnoff - si.fnoff);
+  const int64_t pq = (int64_t)si.nfn * sj.nfn;
+  double c = staging[blk + q * pq + (int64_t)(li - si.fnoff) * sj.nfn + (lj - sj.fnoff)];
+  if (!diag && si.slot == sj.slot)
+    c += mirror_sign(q) * staging[blk + q * pq + (int64_t)(lj - si.fnoff) * sj.nfn + (li - sj.fnoff)];
+  return q == 0 ? c : d.cprime * c;
+}
+
+// One work item: partial[g] = sum over the tile of a_g^T C b_g for all selected terms.
+__global__ __launch_bounds__(NT, 2) void k_density_tiles(DevPlan d, uint32_t terms, const WorkItem *work, int64_t w0,
+                                                         const double *staging, double *partial) {
+  __shared__ ChunkLDS L;
+  __shared__ int s_fn[2 * T];
+  __shared__ double s_red[4][KC];
+  const int64_t wi = w0 + blockIdx.x;
+  const WorkItem it = work[wi];
+  const int b = it.batch;
+  const int g0 = d.batch_pt_off[b], P = d.batch_pt_off[b + 1] - g0;
+  const int f0 = d.batch_fn_off[b], n = d.batch_fn_off[b + 1] - f0;
+  const int sbase = d.batch_slot_off[b];
+  const int r0 = it.ti * T, c0 = it.tj * T;
+  const bool diag = it.ti == it.tj;
+  const int tid = threadIdx.x;
+  if (tid < 2 * T) {
+    const int lf = (tid < T ? r0 : c0) + (tid & (T - 1));
+    s_fn[tid] = lf < n ? d.loc_fn[f0 + lf] : -1;
+  }
+  const int lane = tid & 63, wave = tid >> 6;
+  const int l16 = lane & 15, lk = lane >> 4;
+  // coefficient slice of this wave: rows i = r0 + 4 ks + lk (ks = 0..15), column j = c0 + 16 wave + l16
+  double creg[5][T / 4];
+  const int lj = c0 + wave * 16 + l16;
+#pragma unroll
+  for (int q = 0; q < 5; ++q)
+#pragma unroll
+    for (int ks = 0; ks < T / 4; ++ks)
+      creg[q][ks] = coef_elem(d, staging, f0, sbase, n, r0 + ks * 4 + lk, lj, q, diag);
+  const bool tLL = terms & Q4C_TERM_LL, tSS = terms & Q4C_TERM_SS, tSO = terms & Q4C_TERM_SO;
+  double *out = partial + d.work_part_off[wi];
+
+  for (int k0 = 0; k0 < P; k0 += KC) {
+    __syncthreads();
+    fill_chunk(d, L, s_fn, g0, P, k0, diag, nullptr);
+    __syncthreads();
+    double accp[4] = {0.0, 0.0, 0.0, 0.0};
+    // combos (row comp, coef part, column comp, sign)
+#define COMBO(YQ, CQ, ZQ, SG)                                                                 \
+  {                                                                                           \
+    dbl4 u = dbl4{0.0, 0.0, 0.0, 0.0};                                                        \
+    _Pragma("unroll") for (int ks = 0; ks < T / 4; ++ks) {                                    \
+      const double av = L.a[(YQ * KC + l16) * LDP + ks * 4 + lk];                             \
+      u = mfma64(av, creg[CQ][ks], u);                                                        \
+    }                                                                                         \
+    _Pragma("unroll") for (int r = 0; r < 4; ++r) accp[r] +=                                  \
+        SG u[r] * L.b[(ZQ * KC + d_row_f64(lk, r)) * LDP + wave * 16 + l16];                  \
+  }
+    if (tLL) COMBO(0, 0, 0, +)
+    if (tSS) {
+      COMBO(1, 1, 1, +)
+      COMBO(2, 1, 2, +)
+      COMBO(3, 1, 3, +)
+    }
+    if (tSO) {
+      COMBO(2, 2, 3, +)
+      COMBO(3, 2, 2, -)
+      COMBO(3, 3, 1, +)
+      COMBO(1, 3, 3, -)
+      COMBO(1, 4, 2, +)
+      COMBO(2, 4, 1, -)
+    }
+#undef COMBO
+    // sum over the 16 columns held by lanes with equal lk
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+#pragma unroll
+      for (int off = 1; off < 16; off <<= 1) accp[r] += __shfl_xor(accp[r], off);
+    }
+    if (l16 == 0) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) s_red[wave][d_row_f64(lk, r)] = accp[r];
+    }
+    __syncthreads();
+    if (tid < KC && k0 + tid < P) out[k0 + tid] = ((s_red[0][tid] + s_red[1][tid]) + s_red[2][tid]) + s_red[3][tid];
+  }
+}
+
+// Point sums: out[perm[g]] = (w_g if weighted) * sum over the batch's work items (in order).
+__global__ void k_density_points(DevPlan d, int64_t b0, const double *partial, int weight_mode, double *out) {
+  const int64_t b = b0 + blockIdx.x;
+  const int g0 = d.batch_pt_off[b], P = d.batch_pt_off[b + 1] - g0;
+  const int64_t wa = d.batch_work_off[b], wb = d.batch_work_off[b + 1];
+  for (int g = threadIdx.x; g < P; g += blockDim.x) {
+    double s = 0.0;
+    for (int64_t w = wa; w < wb; ++w) s += partial[d.work_part_off[w] + g];
+    out[d.perm[g0 + g]] = weight_mode ? d.pw[g0 + g] * s : s;
+  }
+}
+
+__global__ void k_fill(double *p, int64_t n, double v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_zero_blocks(const int64_t *off, const int64_t *len, int64_t z0, double *staging) {
+  const int64_t z = z0 + blockIdx.x;
+  double *p = staging + off[z];
+  for (int64_t i = threadIdx.x; i < len[z]; i += blockDim.x) p[i] = 0.0;
+}
+
+// Coefficients from spinor blocks D_AB (see q4c_coef_from_spinor).
+__global__ void k_coef_from_spinor(DevPlan d, const double *spin, double *coef) {
+  const int p = blockIdx.x;
+  const int na = d.pair_na[p], nb = d.pair_nb[p];
+  const int64_t blk = (int64_t)na * nb;
+  const int64_t po = d.pair_off[p];
+  const int64_t L = d.store_len;
+  const int64_t rs = 2 * (int64_t)nb;
+  const double f = d.pair_a[p] == d.pair_b[p] ? 1.0 : 2.0;
+  const double *D = spin + 8 * po;
+  for (int64_t e = threadIdx.x; e < blk; e += blockDim.x) {
+    const int i = (int)(e / nb), j = (int)(e - (int64_t)i * nb);
+    const double *uu = D + 2 * ((int64_t)i * rs + j), *ud = D + 2 * ((int64_t)i * rs + nb + j);
+    const double *du = D + 2 * ((int64_t)(na + i) * rs + j), *dd = D + 2 * ((int64_t)(na + i) * rs + nb + j);
+    const double dsum = f * (uu[0] + dd[0]);
+    coef[po + e] = dsum;
+    coef[L + po + e] = dsum;
+    coef[2 * L + po + e] = f * (ud[1] + du[1]);
+    coef[3 * L + po + e] = f * (ud[0] - du[0]);
+    coef[4 * L + po + e] = f * (uu[1] - dd[1]);
+  }
+}
+
+__global__ void k_check_finite(const double *v, int64_t n, int32_t *flag) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    if (!isfinite(v[i])) flag[0] = 1;
+}
+
+}  // namespace
+
+static int check_launch(const char *what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, what);
+  return Q4C_OK;
+}
+
+int launch_tabulate(const q4c_plan *p, int64_t b0, int64_t b1, int deriv, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_tabulate, dim3((unsigned)(b1 - b0)), dim3(256), 0, s, p->dp, b0, deriv, out);
+  return check_launch("k_tabulate");
+}
+
+int launch_integrate(const q4c_plan *p, const double *v, int precision, uint32_t flags, double *store,
+                     double *spin_w, double *spin_v, hipStream_t s) {
+  const int accumulate = (flags & Q4C_ACCUMULATE) ? 1 : 0;
+  for (const Pass &ps : p->passes) {
+    const int64_t nw = ps.w1 - ps.w0;
+    if (nw > 0) {
+      if (precision == Q4C_PREC_F64)
+        hipLaunchKernelGGL(k_contract<MODE_F64>, dim3((unsigned)nw), dim3(NT), 0, s, p->dp, p->d_work, ps.w0, v,
+                           p->d_staging);
+      else
+        hipLaunchKernelGGL(k_contract<MODE_SPLIT>, dim3((unsigned)nw), dim3(NT), 0, s, p->dp, p->d_work, ps.w0, v,
+                           p->d_staging);
+      int rc = check_launch("k_contract");
+      if (rc != Q4C_OK) return rc;
+    }
+    const int64_t nr = ps.r1 - ps.r0;
+    if (nr > 0) {
+      hipLaunchKernelGGL(k_reduce, dim3((unsigned)nr), dim3(256), 0, s, p->dp, ps.r0, p->d_red_pair, p->d_red_first,
+                         p->d_red_inc_off, p->d_inc_src, p->d_staging, store, accumulate);
+      int rc = check_launch("k_reduce");
+      if (rc != Q4C_OK) return rc;
+    }
+  }
+  if (!accumulate && !p->untouched_pairs.empty()) {
+    hipLaunchKernelGGL(k_zero_pairs, dim3((unsigned)p->untouched_pairs.size()), dim3(256), 0, s, p->dp,
+                       p->d_untouched, store);
+    int rc = check_launch("k_zero_pairs");
+    if (rc != Q4C_OK) return rc;
+  }
+  if ((flags & (Q4C_ASSEMBLE_W | Q4C_ASSEMBLE_V)) && p->n_pairs > 0) {
+    hipLaunchKernelGGL(k_spinor, dim3((unsigned)p->n_pairs), dim3(256), 0, s, p->dp, store,
+                       (flags & Q4C_ASSEMBLE_W) ? spin_w : nullptr, (flags & Q4C_ASSEMBLE_V) ? spin_v : nullptr);
+    int rc = check_launch("k_spinor");
+    if (rc != Q4C_OK) return rc;
+  }
+  return Q4C_OK;
+}
+
+int launch_density(const q4c_plan *p, const double *coef, uint32_t terms, int weight_mode, double *out,
+                   hipStream_t s) {
+  int rc;
+  if (p->n_points > 0) {
+    unsigned nb = (unsigned)std::min<int64_t>((p->n_points + 255) / 256, 65535);
+    hipLaunchKernelGGL(k_fill, dim3(nb), dim3(256), 0, s, out, p->n_points, 0.0);
+    if ((rc = check_launch("k_fill")) != Q4C_OK) return rc;
+  }
+  for (const Pass &ps : p->passes) {
+    const int64_t nr = ps.r1 - ps.r0, nw = ps.w1 - ps.w0, nbt = ps.b1 - ps.b0, nz = ps.z1 - ps.z0;
+    if (nz > 0) {
+      hipLaunchKernelGGL(k_zero_blocks, dim3((unsigned)nz), dim3(256), 0, s, p->d_zero_off, p->d_zero_len, ps.z0,
+                         p->d_staging);
+      if ((rc = check_launch("k_zero_blocks")) != Q4C_OK) return rc;
+    }
+    if (nr > 0) {
+      hipLaunchKernelGGL(k_broadcast, dim3((unsigned)nr), dim3(256), 0, s, p->dp, ps.r0, p->d_red_pair,
+                         p->d_red_inc_off, p->d_inc_src, coef, p->d_staging);
+      if ((rc = check_launch("k_broadcast")) != Q4C_OK) return rc;
+    }
+    // partials go after the staged coefficients of this pass
+    double *partial = p->d_staging + ps.staging_len;
+    if (nw > 0) {
+      hipLaunchKernelGGL(k_density_tiles, dim3((unsigned)nw), dim3(NT), 0, s, p->dp, terms, p->d_work, ps.w0,
+                         p->d_staging, partial);
+      if ((rc = check_launch("k_density_tiles")) != Q4C_OK) return rc;
+    }
+    if (nbt > 0) {
+      hipLaunchKernelGGL(k_density_points, dim3((unsigned)nbt), dim3(256), 0, s, p->dp, ps.b0, partial, weight_mode,
+                         out);
+      if ((rc = check_launch("k_density_points")) != Q4C_OK) return rc;
+    }
+  }
+  return Q4C_OK;
+}
+
+int launch_coef_from_spinor(const q4c_plan *p, const double *spin_d, double *coef_out, hipStream_t s) {
+  if (p->n_pairs == 0) return Q4C_OK;
+  hipLaunchKernelGGL(k_coef_from_spinor, dim3((unsigned)p->n_pairs), dim3(256), 0, s, p->dp, spin_d, coef_out);
+  return check_launch("k_coef_from_spinor");
+}
+
+int launch_check_finite(const q4c_plan *p, const double *v, hipStream_t s, bool *finite) {
+  hipError_t e = hipMemsetAsync(p->d_flag, 0, sizeof(int32_t), s);
+  if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
+  if (p->n_points > 0) {
+    unsigned nb = (unsigned)std::min<int64_t>((p->n_points + 255) / 256, 65535);
+    hipLaunchKernelGGL(k_check_finite, dim3(nb), dim3(256), 0, s, v, p->n_points, p->d_flag);
+    int rc = check_launch("k_check_finite");
+    if (rc != Q4C_OK) return rc;
+  }
+  int32_t h = 0;
+  e = hipMemcpyAsync(&h, p->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  *finite = (h == 0);
+  return Q4C_OK;
+}
+
+}  // namespace q4c

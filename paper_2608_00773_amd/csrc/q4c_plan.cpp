@@ -1,0 +1,735 @@
+// Host side of libq4c: argument validation, the integration plan (batching,
+// basis-relevance lists, atom-pair store layout, staging passes), device
+// upload and the C ABI entry points.
+//
+// Paper Sec. III A: the grid is split into batches B_v of nearby points
+// (Eq. 31) and only the functions non-zero on a batch, nnz(B_v), enter its
+// partial integrals.  Here the batches come from recursive median bisection
+// of the active points (points inside at least one basis support), the
+// relevant set is taken per atom (all functions of an atom with a point of
+// the batch inside its cutoff; with equal shell cutoffs this is the exact
+// set), and the per-batch dense partial matrices are summed into a sparse
+// atom-pair block store instead of per-task dense matrices.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "q4c_internal.h"
+
+namespace {
+thread_local std::string g_last_error;
+
+struct CellList {
+  double lo[3]{}, h = 1.0;
+  int n[3]{1, 1, 1};
+  std::vector<int32_t> head, next;
+  void build(int na, const double *R, double cell) {
+    h = cell > 1e-6 ? cell : 1.0;
+    double hi[3] = {-1e300, -1e300, -1e300};
+    for (int d = 0; d < 3; ++d) lo[d] = 1e300;
+    for (int a = 0; a < na; ++a)
+      for (int d = 0; d < 3; ++d) {
+        lo[d] = std::min(lo[d], R[3 * a + d]);
+        hi[d] = std::max(hi[d], R[3 * a + d]);
+      }
+    if (na == 0)
+      for (int d = 0; d < 3; ++d) lo[d] = hi[d] = 0.0;
+    for (int d = 0; d < 3; ++d) n[d] = std::max(1, (int)std::floor((hi[d] - lo[d]) / h) + 1);
+    head.assign((size_t)n[0] * n[1] * n[2], -1);
+    next.assign(std::max(na, 1), -1);
+    for (int a = na - 1; a >= 0; --a) {
+      int ix[3];
+      for (int d = 0; d < 3; ++d) ix[d] = std::min(n[d] - 1, std::max(0, (int)((R[3 * a + d] - lo[d]) / h)));
+      size_t id = ((size_t)ix[2] * n[1] + ix[1]) * n[0] + ix[0];
+      next[a] = head[id];
+      head[id] = a;
+    }
+  }
+  // visit atoms in cells overlapping the box [bl, bh]
+  template <class F>
+  void visit_box(const double *bl, const double *bh, F &&f) const {
+    int a0[3], a1[3];
+    for (int d = 0; d < 3; ++d) {
+      a0[d] = std::max(0, (int)std::floor((bl[d] - lo[d]) / h));
+      a1[d] = std::min(n[d] - 1, (int)std::floor((bh[d] - lo[d]) / h));
+      if (a0[d] > a1[d]) return;
+    }
+    for (int iz = a0[2]; iz <= a1[2]; ++iz)
+      for (int iy = a0[1]; iy <= a1[1]; ++iy)
+        for (int ix = a0[0]; ix <= a1[0]; ++ix)
+          for (int a = head[((size_t)iz * n[1] + iy) * n[0] + ix]; a >= 0; a = next[a]) f(a);
+  }
+};
+
+int fail(int code, const std::string &msg) {
+  g_last_error = msg;
+  return code;
+}
+
+bool finite_all(const double *p, int64_t n) {
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+// Recursive median bisection along the axis of largest extent until a batch
+// holds at most pmax points.  Ties are broken by index, so the result does not
+// depend on the nth_element implementation.
+void bisect(std::vector<int32_t> &idx, int64_t lo, int64_t hi, int pmax, const double *const xyz[3],
+            std::vector<int64_t> &ends) {
+  struct Seg {
+    int64_t lo, hi;
+  };
+  std::vector<Seg> stack{{lo, hi}};
+  std::vector<Seg> leaves;
+  // depth-first, left before right: push right first
+  while (!stack.empty()) {
+    Seg s = stack.back();
+    stack.pop_back();
+    int64_t n = s.hi - s.lo;
+    if (n <= pmax) {
+      leaves.push_back(s);
+      continue;
+    }
+    double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
+    for (int64_t i = s.lo; i < s.hi; ++i)
+      for (int d = 0; d < 3; ++d) {
+        double c = xyz[d][idx[i]];
+        mn[d] = std::min(mn[d], c);
+        mx[d] = std::max(mx[d], c);
+      }
+    int ax = 0;
+    for (int d = 1; d < 3; ++d)
+      if (mx[d] - mn[d] > mx[ax] - mn[ax]) ax = d;
+    const double *c = xyz[ax];
+    int64_t mid = s.lo + n / 2;
+    std::nth_element(idx.begin() + s.lo, idx.begin() + mid, idx.begin() + s.hi,
+                     [c](int32_t a, int32_t b) { return c[a] < c[b] || (c[a] == c[b] && a < b); });
+    stack.push_back({mid, s.hi});
+    stack.push_back({s.lo, mid});
+  }
+  for (auto &s : leaves) ends.push_back(s.hi);
+}
+
+template <class T>
+int upload(q4c_plan *p, const std::vector<T> &h, T **d) {
+  size_t bytes = std::max<size_t>(h.size() * sizeof(T), 16);
+  void *ptr = nullptr;
+  hipError_t e = hipMalloc(&ptr, bytes);
+  if (e != hipSuccess) return q4c::hip_fail(e, "hipMalloc");
+  p->allocations.push_back(ptr);
+  p->device_bytes += (int64_t)bytes;
+  if (!h.empty()) {
+    e = hipMemcpy(ptr, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return q4c::hip_fail(e, "hipMemcpy");
+  }
+  *d = (T *)ptr;
+  return Q4C_OK;
+}
+
+int device_alloc(q4c_plan *p, size_t bytes, void **d) {
+  void *ptr = nullptr;
+  hipError_t e = hipMalloc(&ptr, std::max<size_t>(bytes, 16));
+  if (e != hipSuccess) return q4c::hip_fail(e, "hipMalloc");
+  p->allocations.push_back(ptr);
+  p->device_bytes += (int64_t)bytes;
+  *d = ptr;
+  return Q4C_OK;
+}
+
+void free_device(q4c_plan *p) {
+  if (!p->allocations.empty()) {
+    if (p->device >= 0) (void)hipSetDevice(p->device);
+    (void)hipDeviceSynchronize();
+    for (void *ptr : p->allocations) (void)hipFree(ptr);
+    p->allocations.clear();
+  }
+}
+
+int validate(const q4c_basis *b, const q4c_grid *g) {
+  if (!b || !g) return fail(Q4C_EINVAL, "basis and grid descriptors are required");
+  if (b->n_atoms < 0 || b->n_shells < 0 || b->n_coef < 0 || g->n_points < 0)
+    return fail(Q4C_EINVAL, "negative size");
+  if (g->n_points >= (int64_t)INT32_MAX) return fail(Q4C_EINVAL, "more than 2^31-1 grid points");
+  if (b->n_atoms > 0 && (!b->R || !b->atom_shell_off)) return fail(Q4C_EINVAL, "NULL atom arrays");
+  if (b->n_shells > 0 && (!b->shell_l || !b->shell_rcut || !b->shell_nint || !b->shell_coef_off || !b->coef))
+    return fail(Q4C_EINVAL, "NULL shell arrays");
+  if (g->n_points > 0 && (!g->x || !g->y || !g->z || !g->w)) return fail(Q4C_EINVAL, "NULL grid arrays");
+  if (b->n_atoms > 0) {
+    if (b->atom_shell_off[0] != 0 || b->atom_shell_off[b->n_atoms] != b->n_shells)
+      return fail(Q4C_EINVAL, "atom_shell_off must run from 0 to n_shells");
+    for (int a = 0; a < b->n_atoms; ++a)
+      if (b->atom_shell_off[a + 1] < b->atom_shell_off[a]) return fail(Q4C_EINVAL, "atom_shell_off decreasing");
+    if (!finite_all(b->R, 3 * (int64_t)b->n_atoms)) return fail(Q4C_EINVAL, "non-finite atom position");
+  } else if (b->n_shells != 0) {
+    return fail(Q4C_EINVAL, "shells without atoms");
+  }
+  for (int s = 0; s < b->n_shells; ++s) {
+    if (b->shell_l[s] < 0) return fail(Q4C_EINVAL, "negative angular momentum");
+    if (b->shell_l[s] > 3) return fail(Q4C_EUNSUPPORTED, "angular momentum above 3 (f) is not supported");
+    if (!(b->shell_rcut[s] > 0.0) || !std::isfinite(b->shell_rcut[s])) return fail(Q4C_EINVAL, "bad shell cutoff");
+    if (b->shell_nint[s] < 1) return fail(Q4C_EINVAL, "shell_nint must be >= 1");
+    if (b->shell_coef_off[s] < 0 || b->shell_coef_off[s] + 4 * (int64_t)b->shell_nint[s] > b->n_coef)
+      return fail(Q4C_EINVAL, "radial table outside coef");
+    if (b->shell_coef_off[s] % 4 != 0) return fail(Q4C_EINVAL, "shell_coef_off must be a multiple of 4");
+  }
+  if (b->n_coef > 0 && !finite_all(b->coef, b->n_coef)) return fail(Q4C_EINVAL, "non-finite radial coefficient");
+  if (g->n_points > 0) {
+    if (!finite_all(g->x, g->n_points) || !finite_all(g->y, g->n_points) || !finite_all(g->z, g->n_points) ||
+        !finite_all(g->w, g->n_points))
+      return fail(Q4C_EINVAL, "non-finite grid coordinate or weight");
+  }
+  return Q4C_OK;
+}
+
+int build_host(q4c_plan *p, const q4c_basis *b, const q4c_grid *g) {
+  const int na = b->n_atoms;
+  p->n_atoms = na;
+  p->n_shells = b->n_shells;
+  p->R.assign(b->R, b->R + 3 * (size_t)na);
+  p->atom_shell_off.assign(b->atom_shell_off, b->atom_shell_off + na + 1);
+  if (na == 0) p->atom_shell_off.assign(1, 0);
+  p->shell_l.assign(b->shell_l, b->shell_l + b->n_shells);
+  p->shell_rcut.assign(b->shell_rcut, b->shell_rcut + b->n_shells);
+  p->shell_nint.assign(b->shell_nint, b->shell_nint + b->n_shells);
+  p->shell_coef_off.assign(b->shell_coef_off, b->shell_coef_off + b->n_shells);
+  p->coef.assign(b->coef, b->coef + b->n_coef);
+
+  // functions and per-atom data
+  p->atom_fn_off.assign(na + 1, 0);
+  p->atom_rcut.assign(na, 0.0);
+  for (int a = 0; a < na; ++a) {
+    int nf = 0;
+    for (int s = p->atom_shell_off[a]; s < p->atom_shell_off[a + 1]; ++s) {
+      nf += 2 * p->shell_l[s] + 1;
+      p->atom_rcut[a] = std::max(p->atom_rcut[a], p->shell_rcut[s]);
+      for (int m = -p->shell_l[s]; m <= p->shell_l[s]; ++m) {
+        p->fn_atom.push_back(a);
+        p->fn_shlm.push_back(s * 16 + p->shell_l[s] * p->shell_l[s] + p->shell_l[s] + m);
+      }
+    }
+    p->atom_fn_off[a + 1] = p->atom_fn_off[a] + nf;
+  }
+  p->n_fn = p->atom_fn_off[na];
+  double rmax = 0.0;
+  for (double r : p->atom_rcut) rmax = std::max(rmax, r);
+
+  // active points
+  CellList cl;
+  cl.build(na, p->R.data(), rmax);
+  p->n_points = g->n_points;
+  std::vector<int32_t> active;
+  active.reserve(g->n_points);
+  for (int64_t i = 0; i < g->n_points; ++i) {
+    double q[3] = {g->x[i], g->y[i], g->z[i]};
+    double bl[3] = {q[0] - rmax, q[1] - rmax, q[2] - rmax}, bh[3] = {q[0] + rmax, q[1] + rmax, q[2] + rmax};
+    bool hit = false;
+    cl.visit_box(bl, bh, [&](int a) {
+      if (hit) return;
+      double dx = q[0] - p->R[3 * a], dy = q[1] - p->R[3 * a + 1], dz = q[2] - p->R[3 * a + 2];
+      if (dx * dx + dy * dy + dz * dz < p->atom_rcut[a] * p->atom_rcut[a]) hit = true;
+    });
+    if (hit) active.push_back((int32_t)i);
+  }
+  p->n_active = (int64_t)active.size();
+
+  // batching
+  const double *xyz[3] = {g->x, g->y, g->z};
+  std::vector<int64_t> ends;
+  if (!active.empty()) bisect(active, 0, (int64_t)active.size(), p->p_max, xyz, ends);
+  p->n_batches = (int64_t)ends.size();
+  p->perm = active;
+  p->px.resize(p->n_active);
+  p->py.resize(p->n_active);
+  p->pz.resize(p->n_active);
+  p->pw.resize(p->n_active);
+  for (int64_t i = 0; i < p->n_active; ++i) {
+    p->px[i] = g->x[active[i]];
+    p->py[i] = g->y[active[i]];
+    p->pz[i] = g->z[active[i]];
+    p->pw[i] = g->w[active[i]];
+  }
+  p->batch_pt_off.assign(1, 0);
+  for (int64_t e : ends) p->batch_pt_off.push_back((int32_t)e);
+
+  // pairs A <= B within rcut_A + rcut_B
+  CellList cl2;
+  cl2.build(na, p->R.data(), 2.0 * rmax);
+  p->atom_pair_start.assign(na + 1, 0);
+  for (int a = 0; a < na; ++a) {
+    std::vector<int32_t> nb;
+    double q[3] = {p->R[3 * a], p->R[3 * a + 1], p->R[3 * a + 2]};
+    double r2 = p->atom_rcut[a] + rmax;
+    double bl[3] = {q[0] - r2, q[1] - r2, q[2] - r2}, bh[3] = {q[0] + r2, q[1] + r2, q[2] + r2};
+    cl2.visit_box(bl, bh, [&](int c) {
+      if (c < a) return;
+      double dx = q[0] - p->R[3 * c], dy = q[1] - p->R[3 * c + 1], dz = q[2] - p->R[3 * c + 2];
+      double rc = p->atom_rcut[a] + p->atom_rcut[c];
+      if (dx * dx + dy * dy + dz * dz < rc * rc) nb.push_back(c);
+    });
+    std::sort(nb.begin(), nb.end());
+    for (int c : nb) {
+      p->pair_a.push_back(a);
+      p->pair_b.push_back(c);
+    }
+    p->atom_pair_start[a + 1] = (int64_t)p->pair_a.size();
+  }
+  p->n_pairs = (int64_t)p->pair_a.size();
+  p->pair_off.assign(p->n_pairs + 1, 0);
+  p->pair_na.resize(p->n_pairs);
+  p->pair_nb.resize(p->n_pairs);
+  for (int64_t q = 0; q < p->n_pairs; ++q) {
+    int a = p->pair_a[q], c = p->pair_b[q];
+    p->pair_na[q] = p->atom_fn_off[a + 1] - p->atom_fn_off[a];
+    p->pair_nb[q] = p->atom_fn_off[c + 1] - p->atom_fn_off[c];
+    p->pair_off[q + 1] = p->pair_off[q] + (int64_t)p->pair_na[q] * p->pair_nb[q];
+  }
+  p->store_len = p->pair_off[p->n_pairs];
+  auto pair_index = [&](int a, int c) -> int64_t {
+    auto beg = p->pair_b.begin() + p->atom_pair_start[a], end = p->pair_b.begin() + p->atom_pair_start[a + 1];
+    auto it = std::lower_bound(beg, end, c);
+    if (it == end || *it != c) return -1;
+    return it - p->pair_b.begin();
+  };
+
+  // per-batch relevant atoms (slots), local functions, staging layout, work, passes
+  p->batch_fn_off.assign(1, 0);
+  p->batch_slot_off.assign(1, 0);
+  const int T = q4c::kTile;
+  int64_t staging = 0, partial = 0;
+  q4c::Pass cur{0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  std::vector<std::pair<int32_t, int64_t>> pass_inc;  // (pair, staging offset) for the current pass
+  std::vector<uint8_t> pair_seen(p->n_pairs, 0);
+  const int64_t budget_doubles = std::max<int64_t>(p->staging_budget / 8, 1);
+  auto close_pass = [&](int64_t b_end) {
+    cur.b1 = b_end;
+    cur.w1 = (int64_t)p->work.size();
+    cur.staging_len = staging;
+    cur.partial_len = partial;
+    std::stable_sort(pass_inc.begin(), pass_inc.end(),
+                     [](const std::pair<int32_t, int64_t> &x, const std::pair<int32_t, int64_t> &y) {
+                       return x.first < y.first;
+                     });
+    cur.r0 = (int64_t)p->red_pair.size();
+    for (size_t i = 0; i < pass_inc.size(); ++i) {
+      if (i == 0 || pass_inc[i].first != pass_inc[i - 1].first) {
+        p->red_pair.push_back(pass_inc[i].first);
+        p->red_first.push_back(pair_seen[pass_inc[i].first] ? 0 : 1);
+        pair_seen[pass_inc[i].first] = 1;
+        p->red_inc_off.push_back((int64_t)p->inc_src.size());
+      }
+      p->inc_src.push_back(pass_inc[i].second);
+    }
+    cur.r1 = (int64_t)p->red_pair.size();
+    cur.z1 = (int64_t)p->zero_off.size();
+    p->passes.push_back(cur);
+    p->max_scratch = std::max(p->max_scratch, staging + partial);
+    pass_inc.clear();
+    staging = 0;
+    partial = 0;
+    int64_t nz = (int64_t)p->zero_off.size();
+    cur = q4c::Pass{b_end, b_end, (int64_t)p->work.size(), (int64_t)p->work.size(), 0, 0, nz, nz, 0, 0};
+  };
+
+  std::vector<int32_t> rel;
+  for (int64_t bt = 0; bt < p->n_batches; ++bt) {
+    int64_t g0 = p->batch_pt_off[bt], g1 = p->batch_pt_off[bt + 1];
+    double bl[3] = {1e300, 1e300, 1e300}, bh[3] = {-1e300, -1e300, -1e300};
+    for (int64_t i = g0; i < g1; ++i) {
+      double q[3] = {p->px[i], p->py[i], p->pz[i]};
+      for (int d = 0; d < 3; ++d) {
+        bl[d] = std::min(bl[d], q[d]);
+        bh[d] = std::max(bh[d], q[d]);
+      }
+    }
+    double el[3] = {bl[0] - rmax, bl[1] - rmax, bl[2] - rmax}, eh[3] = {bh[0] + rmax, bh[1] + rmax, bh[2] + rmax};
+    rel.clear();
+    cl.visit_box(el, eh, [&](int a) {
+      double rc = p->atom_rcut[a], rc2 = rc * rc;
+      // distance from the atom to the batch box
+      double dmin2 = 0.0, dmax2 = 0.0;
+      for (int d = 0; d < 3; ++d) {
+        double c = p->R[3 * a + d];
+        double lo = bl[d] - c, hi = bh[d] - c;
+        double dn = (lo > 0) ? lo : ((hi < 0) ? -hi : 0.0);
+        double df = std::max(std::fabs(lo), std::fabs(hi));
+        dmin2 += dn * dn;
+        dmax2 += df * df;
+      }
+      if (!(dmin2 < rc2)) return;
+      bool hit = dmax2 < rc2;
+      for (int64_t i = g0; i < g1 && !hit; ++i) {
+        double dx = p->px[i] - p->R[3 * a], dy = p->py[i] - p->R[3 * a + 1], dz = p->pz[i] - p->R[3 * a + 2];
+        if (dx * dx + dy * dy + dz * dz < rc2) hit = true;
+      }
+      if (hit) rel.push_back(a);
+    });
+    std::sort(rel.begin(), rel.end());
+    int nb_fn = 0;
+    for (int a : rel) nb_fn += p->atom_fn_off[a + 1] - p->atom_fn_off[a];
+    // staging size of this batch: upper atom-block triangle, five parts
+    int64_t bstage = 0;
+    {
+      int off = 0;
+      for (int a : rel) {
+        int nf = p->atom_fn_off[a + 1] - p->atom_fn_off[a];
+        bstage += 5 * (int64_t)nf * (nb_fn - off);
+        off += nf;
+      }
+    }
+    int nt = (nb_fn + T - 1) / T;
+    int64_t bpart = (int64_t)(nt * (nt + 1) / 2) * (g1 - g0);
+    if (bt > cur.b0 && (staging + bstage > budget_doubles)) close_pass(bt);
+    // slots
+    int off = 0;
+    int32_t slot0 = (int32_t)p->slot_atom.size();
+    for (size_t si = 0; si < rel.size(); ++si) {
+      int a = rel[si];
+      int nf = p->atom_fn_off[a + 1] - p->atom_fn_off[a];
+      p->slot_atom.push_back(a);
+      p->slot_fnoff.push_back(off);
+      p->slot_nfn.push_back(nf);
+      p->slot_row_off.push_back(staging);
+      for (int f = 0; f < nf; ++f) {
+        p->loc_fn.push_back(p->atom_fn_off[a] + f);
+        p->loc_slot.push_back((int32_t)si);
+      }
+      // incidences of this row: (a, c) for slots c >= a that form a stored pair
+      int64_t col_off = 0;
+      for (size_t sj = si; sj < rel.size(); ++sj) {
+        int c = rel[sj];
+        int nfc = p->atom_fn_off[c + 1] - p->atom_fn_off[c];
+        int64_t q = pair_index(a, c);
+        if (q >= 0) {
+          pass_inc.push_back({(int32_t)q, staging + 5 * (int64_t)nf * col_off});
+        } else {
+          p->zero_off.push_back(staging + 5 * (int64_t)nf * col_off);
+          p->zero_len.push_back(5 * (int64_t)nf * nfc);
+        }
+        col_off += nfc;
+      }
+      staging += 5 * (int64_t)nf * (nb_fn - off);
+      off += nf;
+    }
+    (void)slot0;
+    p->batch_slot_off.push_back((int32_t)p->slot_atom.size());
+    p->batch_fn_off.push_back((int32_t)p->loc_fn.size());
+    for (int ti = 0; ti < nt; ++ti)
+      for (int tj = ti; tj < nt; ++tj) {
+        p->work.push_back(q4c::WorkItem{(int32_t)bt, (int16_t)ti, (int16_t)tj});
+        p->work_part_off.push_back(partial);
+        partial += (g1 - g0);
+      }
+    (void)bpart;
+    p->max_batch_points = std::max<int64_t>(p->max_batch_points, g1 - g0);
+    p->max_batch_fn = std::max<int64_t>(p->max_batch_fn, nb_fn);
+    p->flops_alg += 10.0 * (double)(g1 - g0) * (double)nb_fn * (double)nb_fn;
+  }
+  close_pass(p->n_batches);
+  p->red_inc_off.push_back((int64_t)p->inc_src.size());
+  p->batch_work_off.assign(p->n_batches + 1, 0);
+  for (auto &w : p->work) p->batch_work_off[w.batch + 1]++;
+  for (int64_t b = 0; b < p->n_batches; ++b) p->batch_work_off[b + 1] += p->batch_work_off[b];
+  p->tab_off.assign(p->n_batches + 1, 0);
+  for (int64_t b = 0; b < p->n_batches; ++b)
+    p->tab_off[b + 1] = p->tab_off[b] + (int64_t)(p->batch_pt_off[b + 1] - p->batch_pt_off[b]) *
+                                            (p->batch_fn_off[b + 1] - p->batch_fn_off[b]);
+  p->fn_entries = (int64_t)p->loc_fn.size();
+  for (int64_t q = 0; q < p->n_pairs; ++q)
+    if (!pair_seen[q]) p->untouched_pairs.push_back((int32_t)q);
+  if (p->fn_entries >= (int64_t)INT32_MAX) return fail(Q4C_EINVAL, "too many batch-function entries");
+  return Q4C_OK;
+}
+
+int build_device(q4c_plan *p) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return q4c::hip_fail(e, "hipGetDevice");
+  p->device = dev;
+  q4c::DevPlan &d = p->dp;
+  int rc = Q4C_OK;
+#define UP(vec, ptr)                                           \
+  do {                                                         \
+    rc = upload(p, vec, &ptr);                                 \
+    if (rc != Q4C_OK) return rc;                               \
+  } while (0)
+  double *R, *rcut, *coef, *px, *py, *pz, *pw;
+  int32_t *fn_atom, *fn_shlm, *nint, *perm, *bpo, *bfo, *lfn, *lsl, *bso, *sfo, *snf, *pna, *pnb, *pa, *pb;
+  int64_t *coff, *sro, *wpo, *poff, *bwo, *toff;
+  UP(p->R, R);
+  UP(p->fn_atom, fn_atom);
+  UP(p->fn_shlm, fn_shlm);
+  UP(p->shell_rcut, rcut);
+  UP(p->shell_nint, nint);
+  UP(p->shell_coef_off, coff);
+  UP(p->coef, coef);
+  UP(p->px, px);
+  UP(p->py, py);
+  UP(p->pz, pz);
+  UP(p->pw, pw);
+  UP(p->perm, perm);
+  UP(p->batch_pt_off, bpo);
+  UP(p->batch_fn_off, bfo);
+  UP(p->loc_fn, lfn);
+  UP(p->loc_slot, lsl);
+  UP(p->batch_slot_off, bso);
+  UP(p->slot_fnoff, sfo);
+  UP(p->slot_nfn, snf);
+  UP(p->slot_row_off, sro);
+  UP(p->work_part_off, wpo);
+  UP(p->pair_off, poff);
+  UP(p->pair_na, pna);
+  UP(p->pair_nb, pnb);
+  UP(p->pair_a, pa);
+  UP(p->pair_b, pb);
+  UP(p->batch_work_off, bwo);
+  UP(p->tab_off, toff);
+  UP(p->zero_off, p->d_zero_off);
+  UP(p->zero_len, p->d_zero_len);
+  UP(p->work, p->d_work);
+  UP(p->red_pair, p->d_red_pair);
+  UP(p->red_first, p->d_red_first);
+  UP(p->red_inc_off, p->d_red_inc_off);
+  UP(p->inc_src, p->d_inc_src);
+  UP(p->untouched_pairs, p->d_untouched);
+#undef UP
+  rc = device_alloc(p, (size_t)p->max_scratch * sizeof(double), (void **)&p->d_staging);
+  if (rc != Q4C_OK) return rc;
+  rc = device_alloc(p, 64, (void **)&p->d_flag);
+  if (rc != Q4C_OK) return rc;
+  d.R = R;
+  d.fn_atom = fn_atom;
+  d.fn_shlm = fn_shlm;
+  d.shell_rcut = rcut;
+  d.shell_nint = nint;
+  d.shell_coef_off = coff;
+  d.coef = coef;
+  d.px = px;
+  d.py = py;
+  d.pz = pz;
+  d.pw = pw;
+  d.perm = perm;
+  d.batch_pt_off = bpo;
+  d.batch_fn_off = bfo;
+  d.loc_fn = lfn;
+  d.loc_slot = lsl;
+  d.batch_slot_off = bso;
+  d.slot_fnoff = sfo;
+  d.slot_nfn = snf;
+  d.slot_row_off = sro;
+  d.work_part_off = wpo;
+  d.pair_off = poff;
+  d.pair_na = pna;
+  d.pair_nb = pnb;
+  d.pair_a = pa;
+  d.pair_b = pb;
+  d.batch_work_off = bwo;
+  d.tab_off = toff;
+  d.store_len = p->store_len;
+  d.n_active = p->n_active;
+  d.n_points = p->n_points;
+  d.cprime = 1.0 / (4.0 * p->c_light * p->c_light);
+  p->on_device = true;
+  return Q4C_OK;
+}
+
+int check_plan_dev(const q4c_plan *p) {
+  if (!p) return fail(Q4C_EINVAL, "NULL plan");
+  if (!p->on_device) return fail(Q4C_ENODEV, "plan has no device data");
+  hipError_t e = hipSetDevice(p->device);
+  if (e != hipSuccess) return q4c::hip_fail(e, "hipSetDevice");
+  return Q4C_OK;
+}
+
+}  // namespace
+
+namespace q4c {
+void set_error(const std::string &msg) { g_last_error = msg; }
+int hip_fail(hipError_t e, const char *what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return Q4C_EHIP;
+}
+}  // namespace q4c
+
+extern "C" {
+
+int q4c_plan_create(const q4c_basis *basis, const q4c_grid *grid, const q4c_opts *opts, q4c_plan **out) {
+  if (!out) return fail(Q4C_EINVAL, "NULL output handle");
+  *out = nullptr;
+  int rc = validate(basis, grid);
+  if (rc != Q4C_OK) return rc;
+  q4c_plan *p = nullptr;
+  try {
+    p = new q4c_plan();
+    if (opts) {
+      if (opts->c_light > 0.0) p->c_light = opts->c_light;
+      if (opts->p_max > 0) p->p_max = opts->p_max;
+      p->flags = opts->flags;
+      p->staging_budget = opts->staging_bytes;
+    }
+    if (p->p_max < 1) p->p_max = 300;
+    if (p->staging_budget <= 0) p->staging_budget = (int64_t)8 << 30;
+    rc = build_host(p, basis, grid);
+    if (rc == Q4C_OK && !(p->flags & Q4C_PLAN_HOST_ONLY)) rc = build_device(p);
+  } catch (const std::bad_alloc &) {
+    rc = fail(Q4C_ENOMEM, "host allocation failed");
+  } catch (const std::exception &ex) {
+    rc = fail(Q4C_EINVAL, ex.what());
+  }
+  if (rc != Q4C_OK) {
+    if (p) {
+      free_device(p);
+      delete p;
+    }
+    return rc;
+  }
+  *out = p;
+  return Q4C_OK;
+}
+
+void q4c_plan_destroy(q4c_plan *plan) {
+  if (!plan) return;
+  free_device(plan);
+  delete plan;
+}
+
+int q4c_plan_info(const q4c_plan *p, q4c_info *info) {
+  if (!p || !info) return fail(Q4C_EINVAL, "NULL argument");
+  info->n_atoms = p->n_atoms;
+  info->n_fn = p->n_fn;
+  info->n_points = p->n_points;
+  info->n_active = p->n_active;
+  info->n_batches = p->n_batches;
+  info->n_pairs = p->n_pairs;
+  info->store_len = p->store_len;
+  info->fn_entries = p->fn_entries;
+  info->max_batch_points = p->max_batch_points;
+  info->max_batch_fn = p->max_batch_fn;
+  info->n_work = (int64_t)p->work.size();
+  info->n_passes = (int64_t)p->passes.size();
+  info->device_bytes = p->device_bytes;
+  info->flops_alg = p->flops_alg;
+  return Q4C_OK;
+}
+
+int q4c_plan_pairs(const q4c_plan *p, int32_t *pair_atoms, int64_t *pair_off) {
+  if (!p) return fail(Q4C_EINVAL, "NULL plan");
+  if (pair_atoms)
+    for (int64_t q = 0; q < p->n_pairs; ++q) {
+      pair_atoms[2 * q] = p->pair_a[q];
+      pair_atoms[2 * q + 1] = p->pair_b[q];
+    }
+  if (pair_off) std::copy(p->pair_off.begin(), p->pair_off.end(), pair_off);
+  return Q4C_OK;
+}
+
+int q4c_plan_batches(const q4c_plan *p, int64_t *pt_off, int64_t *point_index, int64_t *fn_off, int32_t *fn_index) {
+  if (!p) return fail(Q4C_EINVAL, "NULL plan");
+  if (pt_off)
+    for (int64_t b = 0; b <= p->n_batches; ++b) pt_off[b] = p->batch_pt_off[b];
+  if (point_index)
+    for (int64_t i = 0; i < p->n_active; ++i) point_index[i] = p->perm[i];
+  if (fn_off)
+    for (int64_t b = 0; b <= p->n_batches; ++b) fn_off[b] = p->batch_fn_off[b];
+  if (fn_index) std::copy(p->loc_fn.begin(), p->loc_fn.end(), fn_index);
+  return Q4C_OK;
+}
+
+int q4c_tabulate_size(const q4c_plan *p, int64_t b0, int64_t b1, int32_t deriv, int64_t *n) {
+  if (!p || !n) return fail(Q4C_EINVAL, "NULL argument");
+  if (b0 < 0 || b1 < b0 || b1 > p->n_batches) return fail(Q4C_EINVAL, "batch range outside the plan");
+  if (deriv != 0 && deriv != 1) return fail(Q4C_EINVAL, "deriv must be 0 or 1");
+  int64_t tot = 0;
+  for (int64_t b = b0; b < b1; ++b)
+    tot += (int64_t)(p->batch_pt_off[b + 1] - p->batch_pt_off[b]) * (p->batch_fn_off[b + 1] - p->batch_fn_off[b]);
+  *n = tot * (deriv ? 4 : 1);
+  return Q4C_OK;
+}
+
+int nao_tabulate(const q4c_plan *p, int64_t b0, int64_t b1, int32_t deriv, double *out_dev, int64_t out_len,
+                 void *stream) {
+  int64_t need = 0;
+  int rc = q4c_tabulate_size(p, b0, b1, deriv, &need);
+  if (rc != Q4C_OK) return rc;
+  if (out_len < need) return fail(Q4C_ESIZE, "output buffer too small for nao_tabulate");
+  if (need > 0 && !out_dev) return fail(Q4C_EINVAL, "NULL output");
+  rc = check_plan_dev(p);
+  if (rc != Q4C_OK) return rc;
+  if (need == 0) return Q4C_OK;
+  return q4c::launch_tabulate(p, b0, b1, deriv, out_dev, (hipStream_t)stream);
+}
+
+int q4c_integrate_H(const q4c_plan *p, const double *v_dev, int32_t precision, uint32_t flags, double *store_dev,
+                    double *spin_w_dev, double *spin_v_dev, void *stream) {
+  if (!p) return fail(Q4C_EINVAL, "NULL plan");
+  if (precision != Q4C_PREC_F64 && precision != Q4C_PREC_SPLIT_F32) return fail(Q4C_EINVAL, "unknown precision");
+  if (flags & ~(uint32_t)(Q4C_ACCUMULATE | Q4C_ASSEMBLE_W | Q4C_ASSEMBLE_V | Q4C_CHECK_FINITE))
+    return fail(Q4C_EINVAL, "unknown flag");
+  if (p->n_points > 0 && !v_dev) return fail(Q4C_EINVAL, "NULL potential");
+  if (p->store_len > 0 && !store_dev) return fail(Q4C_EINVAL, "NULL store");
+  if ((flags & Q4C_ASSEMBLE_W) && p->store_len > 0 && !spin_w_dev) return fail(Q4C_EINVAL, "NULL W spinor output");
+  if ((flags & Q4C_ASSEMBLE_V) && p->store_len > 0 && !spin_v_dev) return fail(Q4C_EINVAL, "NULL V spinor output");
+  int rc = check_plan_dev(p);
+  if (rc != Q4C_OK) return rc;
+  if (flags & Q4C_CHECK_FINITE) {
+    bool ok = true;
+    rc = q4c::launch_check_finite(p, v_dev, (hipStream_t)stream, &ok);
+    if (rc != Q4C_OK) return rc;
+    if (!ok) return fail(Q4C_ENONFINITE, "potential contains NaN or Inf");
+  }
+  return q4c::launch_integrate(p, v_dev, precision, flags, store_dev, spin_w_dev, spin_v_dev, (hipStream_t)stream);
+}
+
+int density_on_grid(const q4c_plan *p, const double *coef_dev, uint32_t terms, int32_t weight_mode, double *out_dev,
+                    void *stream) {
+  if (!p) return fail(Q4C_EINVAL, "NULL plan");
+  if (terms == 0 || (terms & ~(uint32_t)Q4C_TERM_ALL)) return fail(Q4C_EINVAL, "bad term selection");
+  if (weight_mode != 0 && weight_mode != 1) return fail(Q4C_EINVAL, "weight_mode must be 0 or 1");
+  if (p->store_len > 0 && !coef_dev) return fail(Q4C_EINVAL, "NULL coefficients");
+  if (p->n_points > 0 && !out_dev) return fail(Q4C_EINVAL, "NULL output");
+  int rc = check_plan_dev(p);
+  if (rc != Q4C_OK) return rc;
+  return q4c::launch_density(p, coef_dev, terms, weight_mode, out_dev, (hipStream_t)stream);
+}
+
+int q4c_coef_from_spinor(const q4c_plan *p, const double *spin_d_dev, double *coef_out_dev, void *stream) {
+  if (!p) return fail(Q4C_EINVAL, "NULL plan");
+  if (p->store_len > 0 && (!spin_d_dev || !coef_out_dev)) return fail(Q4C_EINVAL, "NULL buffer");
+  int rc = check_plan_dev(p);
+  if (rc != Q4C_OK) return rc;
+  return q4c::launch_coef_from_spinor(p, spin_d_dev, coef_out_dev, (hipStream_t)stream);
+}
+
+int q4c_plan_sync(const q4c_plan *p, void *stream) {
+  int rc = check_plan_dev(p);
+  if (rc != Q4C_OK) return rc;
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return q4c::hip_fail(e, "hipStreamSynchronize");
+  e = hipGetLastError();
+  if (e != hipSuccess) return q4c::hip_fail(e, "asynchronous kernel error");
+  return Q4C_OK;
+}
+
+const char *q4c_status_string(int s) {
+  switch (s) {
+    case Q4C_OK: return "ok";
+    case Q4C_EINVAL: return "invalid argument";
+    case Q4C_ENOMEM: return "out of memory";
+    case Q4C_EHIP: return "HIP runtime error";
+    case Q4C_ENOTIMPL: return "not implemented";
+    case Q4C_EUNSUPPORTED: return "unsupported input";
+    case Q4C_ESIZE: return "buffer too small";
+    case Q4C_ENONFINITE: return "non-finite input";
+    case Q4C_ENODEV: return "no device data";
+    default: return "unknown status";
+  }
+}
+
+const char *q4c_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,62 @@
+"""Shared test helpers: layout conversion and comparison against the oracle.
+
+Nothing here computes the method's arithmetic; it only rearranges arrays
+between the library's store layout and the oracle's per-pair blocks."""
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def gpu_available():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+def store_to_blocks(store: np.ndarray, pairs: np.ndarray, pair_off: np.ndarray, nfn: np.ndarray):
+    """[5, store_len] -> list of [5, nA, nB] blocks."""
+    out = []
+    for p, (a, b) in enumerate(pairs):
+        na, nb = int(nfn[a]), int(nfn[b])
+        out.append(store[:, pair_off[p]:pair_off[p + 1]].reshape(5, na, nb))
+    return out
+
+
+def blocks_to_store(blocks, pair_off: np.ndarray) -> np.ndarray:
+    L = int(pair_off[-1])
+    st = np.zeros((5, L))
+    for p, blk in enumerate(blocks):
+        st[:, pair_off[p]:pair_off[p + 1]] = np.asarray(blk).reshape(5, -1)
+    return st
+
+
+def spinor_to_blocks(spin: np.ndarray, pairs, pair_off, nfn):
+    """[4 store_len, 2] float64 (re, im) -> list of complex [2nA, 2nB]."""
+    c = spin[:, 0] + 1j * spin[:, 1]
+    out = []
+    for p, (a, b) in enumerate(pairs):
+        na, nb = int(nfn[a]), int(nfn[b])
+        out.append(c[4 * pair_off[p]:4 * pair_off[p + 1]].reshape(2 * na, 2 * nb))
+    return out
+
+
+def spinor_from_blocks(blocks, pair_off) -> np.ndarray:
+    L = int(pair_off[-1])
+    out = np.zeros((4 * L, 2))
+    for p, blk in enumerate(blocks):
+        c = np.asarray(blk).reshape(-1)
+        out[4 * pair_off[p]:4 * pair_off[p + 1], 0] = c.real
+        out[4 * pair_off[p]:4 * pair_off[p + 1], 1] = c.imag
+    return out
+
+
+def rel_to_scale(got, ref, scale, floor=0.0):
+    """max |got - ref| / (scale + floor) elementwise."""
+    return float(np.max(np.abs(got - ref) / (scale + floor))) if np.size(got) else 0.0

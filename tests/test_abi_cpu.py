@@ -1,0 +1,159 @@
+"""C-ABI checks that need no GPU: every function declared in include/q4c.h is
+exported by libq4c.so, argument validation returns the documented status
+codes, and the host-side plan (batching, relevance lists, pair layout) is
+correct.  No kernel is launched."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workload as W
+from helpers import ROOT
+
+HEADER = os.path.join(ROOT, "include", "q4c.h")
+
+
+def _lib():
+    import paper_2608_00773_amd as q
+    return q, q._load()
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?(?:int|void|char)\s*\*?\s*([A-Za-z_0-9]+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_three_calls():
+    names = declared_functions()
+    for n in ("nao_tabulate", "q4c_integrate_H", "density_on_grid", "q4c_plan_create", "q4c_plan_destroy"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    q, lib = _lib()
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+    assert set(declared_functions()) == set(q.EXPORTS)
+
+
+def test_status_strings():
+    q, lib = _lib()
+    for s in range(0, -9, -1):
+        assert lib.q4c_status_string(s).decode() != "unknown status"
+
+
+def _host_plan(q, wl, **kw):
+    return q.Plan(wl, host_only=True, **kw)
+
+
+def test_host_only_plan_and_nodev_errors():
+    q, lib = _lib()
+    wl = W.config_small(nrad=10, nang=26)
+    p = _host_plan(q, wl)
+    assert p.info["n_atoms"] == 3 and p.info["n_fn"] == 42
+    assert p.info["device_bytes"] == 0
+    rc = lib.q4c_integrate_H(p.handle, ctypes.c_void_p(1), 0, 0, ctypes.c_void_p(1), None, None, None)
+    assert rc == q.Q4C_ENODEV
+    rc = lib.density_on_grid(p.handle, ctypes.c_void_p(1), 7, 0, ctypes.c_void_p(1), None)
+    assert rc == q.Q4C_ENODEV
+
+
+def test_argument_validation():
+    q, lib = _lib()
+    wl = W.config_small(nrad=10, nang=26)
+    p = _host_plan(q, wl)
+    # bad precision / flags / terms / weight mode are rejected before any device work
+    assert lib.q4c_integrate_H(p.handle, ctypes.c_void_p(1), 7, 0, ctypes.c_void_p(1), None, None, None) == q.Q4C_EINVAL
+    assert lib.q4c_integrate_H(p.handle, ctypes.c_void_p(1), 0, 1 << 10, ctypes.c_void_p(1), None, None,
+                               None) == q.Q4C_EINVAL
+    assert lib.q4c_integrate_H(p.handle, None, 0, 0, ctypes.c_void_p(1), None, None, None) == q.Q4C_EINVAL
+    assert lib.q4c_integrate_H(p.handle, ctypes.c_void_p(1), 0, q.ASSEMBLE_W, ctypes.c_void_p(1), None, None,
+                               None) == q.Q4C_EINVAL
+    assert lib.density_on_grid(p.handle, ctypes.c_void_p(1), 0, 0, ctypes.c_void_p(1), None) == q.Q4C_EINVAL
+    assert lib.density_on_grid(p.handle, ctypes.c_void_p(1), 7, 2, ctypes.c_void_p(1), None) == q.Q4C_EINVAL
+    assert lib.q4c_integrate_H(None, ctypes.c_void_p(1), 0, 0, ctypes.c_void_p(1), None, None, None) == q.Q4C_EINVAL
+    n = ctypes.c_int64()
+    assert lib.q4c_tabulate_size(p.handle, 0, p.info["n_batches"] + 1, 1, ctypes.byref(n)) == q.Q4C_EINVAL
+    assert lib.q4c_tabulate_size(p.handle, 0, 1, 2, ctypes.byref(n)) == q.Q4C_EINVAL
+    assert lib.nao_tabulate(p.handle, 0, 1, 1, ctypes.c_void_p(1), 0, None) == q.Q4C_ESIZE
+
+
+def test_unsupported_l_and_malformed_basis():
+    q, lib = _lib()
+    wl = W.config_small(nrad=10, nang=26)
+    bad = W.Workload(**{**wl.__dict__})
+    bad.shell_l = wl.shell_l.copy()
+    bad.shell_l[0] = 4
+    with pytest.raises(q.Q4CError) as e:
+        _host_plan(q, bad)
+    assert e.value.status == q.Q4C_EUNSUPPORTED
+    bad2 = W.Workload(**{**wl.__dict__})
+    bad2.atom_shell_off = wl.atom_shell_off.copy()
+    bad2.atom_shell_off[1] = wl.atom_shell_off[2] + 1
+    with pytest.raises(q.Q4CError) as e:
+        _host_plan(q, bad2)
+    assert e.value.status == q.Q4C_EINVAL
+    bad3 = W.Workload(**{**wl.__dict__})
+    bad3.w = wl.w.copy()
+    bad3.w[5] = np.nan
+    with pytest.raises(q.Q4CError) as e:
+        _host_plan(q, bad3)
+    assert e.value.status == q.Q4C_EINVAL
+    bad4 = W.Workload(**{**wl.__dict__})
+    bad4.shell_coef_off = wl.shell_coef_off.copy()
+    bad4.shell_coef_off[-1] = wl.coef.size
+    with pytest.raises(q.Q4CError) as e:
+        _host_plan(q, bad4)
+    assert e.value.status == q.Q4C_EINVAL
+
+
+def test_empty_grid_and_no_active_points():
+    q, lib = _lib()
+    wl = W.config_small(nrad=10, nang=26)
+    empty = wl.subset_points(np.arange(0))
+    p = _host_plan(q, empty)
+    assert p.info["n_batches"] == 0 and p.info["n_active"] == 0 and p.info["flops_alg"] == 0.0
+    assert p.info["n_pairs"] == 6
+    far = wl.translated([0.0, 0.0, 0.0])
+    far.x = far.x + 1e4
+    p2 = _host_plan(q, far)
+    assert p2.info["n_active"] == 0 and p2.info["n_batches"] == 0
+
+
+def test_batching_properties():
+    q, lib = _lib()
+    wl = W.config_cluster(n_atoms=30, nrad=12, nang=26, box_ang=10.0)
+    for pmax in (1, 7, 64, 300):
+        p = _host_plan(q, wl, p_max=pmax)
+        pt_off, pidx, fn_off, fidx = p.batches()
+        sizes = np.diff(pt_off)
+        assert sizes.max() <= pmax and sizes.min() >= 1
+        if p.info["n_active"] > pmax:
+            assert sizes.min() >= pmax // 2  # median bisection
+        assert len(np.unique(pidx)) == len(pidx)
+        # relevance: atom-level exact set
+        rc = wl.atom_rcut()
+        aoff = np.concatenate([[0], np.cumsum(wl.atom_nfn())])
+        for b in np.random.default_rng(0).choice(p.info["n_batches"], size=min(20, p.info["n_batches"]),
+                                                 replace=False):
+            pts = pidx[pt_off[b]:pt_off[b + 1]]
+            d = np.sqrt(np.sum((np.stack([wl.x[pts], wl.y[pts], wl.z[pts]], 1)[:, None, :] - wl.R[None]) ** 2, -1))
+            atoms = np.nonzero(np.any(d < rc[None], axis=0))[0]
+            want = np.concatenate([np.arange(aoff[a], aoff[a + 1]) for a in atoms])
+            assert np.array_equal(fidx[fn_off[b]:fn_off[b + 1]], want)
+        # F_alg = sum_B 10 P_B n_B^2
+        assert p.info["flops_alg"] == pytest.approx(float(np.sum(10.0 * sizes * np.diff(fn_off) ** 2)), rel=1e-12)
+
+
+def test_staging_passes_split_by_budget():
+    q, lib = _lib()
+    wl = W.config_cluster(n_atoms=30, nrad=12, nang=26, box_ang=10.0)
+    p1 = _host_plan(q, wl)
+    p2 = _host_plan(q, wl, staging_bytes=1 << 20)
+    assert p1.info["n_passes"] == 1
+    assert p2.info["n_passes"] > 1
+    assert p1.info["n_work"] == p2.info["n_work"]

@@ -1,0 +1,273 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Bars (FP64 path): per element |GPU - oracle| <= 1e-12 * A_ij with
+A_ij = sum_g |term_g| (the oracle's own scale of the element).  Split-FP32
+path: |GPU - oracle| <= 1e-8 Ha per element and part.  Integer work (batches,
+pairs) is compared bit for bit."""
+import numpy as np
+import pytest
+
+import oracle
+import workload as W
+from helpers import gpu_available, spinor_to_blocks, store_to_blocks
+
+pytestmark = pytest.mark.gpu
+
+FP64_REL = 1e-12
+SPLIT_ABS = 1e-8
+
+
+def _torch():
+    import torch
+    return torch
+
+
+@pytest.fixture(scope="module")
+def q():
+    if not gpu_available():
+        pytest.skip("no GPU")
+    import paper_2608_00773_amd as q4c
+    return q4c
+
+
+def _run(q, wl, precision=0, assemble=True, p_max=None, staging_bytes=0):
+    torch = _torch()
+    plan = q.Plan(wl, p_max=p_max, staging_bytes=staging_bytes)
+    v = torch.from_numpy(wl.v).cuda()
+    store = q.new_store(plan)
+    spin_w = q.new_spinor(plan)
+    spin_v = q.new_spinor(plan)
+    flags = (q.ASSEMBLE_W | q.ASSEMBLE_V) if assemble else 0
+    q.q4c_integrate_H(plan, v, precision, flags, store, spin_w, spin_v)
+    torch.cuda.synchronize()
+    return plan, store.cpu().numpy(), spin_w.cpu().numpy(), spin_v.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def small(q):
+    wl = W.config_small()
+    pairs = W.atom_pairs(wl)
+    ref, scale = oracle.pair_blocks(wl, pairs, with_abs=True)
+    return wl, pairs, ref, scale
+
+
+def _compare_f64(got_blocks, ref, scale, tol=FP64_REL):
+    worst = 0.0
+    for g, r, s in zip(got_blocks, ref, scale):
+        # elements whose terms are all exact zeros must come out exactly zero
+        err = np.abs(g - r)
+        ok_zero = np.all(err[s == 0] == 0)
+        assert ok_zero
+        nz = s > 0
+        if np.any(nz):
+            worst = max(worst, float(np.max(err[nz] / s[nz])))
+    assert worst <= tol, worst
+    return worst
+
+
+def test_plan_pairs_and_batches_bitexact(q, small):
+    wl, pairs, _, _ = small
+    plan = q.Plan(wl)
+    p, _ = plan.pairs()
+    assert np.array_equal(p, pairs)
+    pt_off, pidx, fn_off, fidx = plan.batches()
+    # every active point exactly once; inactive points have no function in range
+    assert len(np.unique(pidx)) == len(pidx) == plan.info["n_active"]
+    rc = wl.atom_rcut()
+    d = np.sqrt((wl.x[:, None] - wl.R[None, :, 0]) ** 2 + (wl.y[:, None] - wl.R[None, :, 1]) ** 2 +
+                (wl.z[:, None] - wl.R[None, :, 2]) ** 2)
+    active = np.nonzero(np.any(d < rc[None, :], axis=1))[0]
+    assert np.array_equal(np.sort(pidx), active)
+    # relevant functions of each batch = all functions of atoms with a point of the batch inside the cutoff
+    aoff = np.concatenate([[0], np.cumsum(wl.atom_nfn())])
+    for b in range(plan.info["n_batches"]):
+        pts = pidx[pt_off[b]:pt_off[b + 1]]
+        atoms = np.nonzero(np.any(d[pts] < rc[None, :], axis=0))[0]
+        want = np.concatenate([np.arange(aoff[a], aoff[a + 1]) for a in atoms])
+        assert np.array_equal(fidx[fn_off[b]:fn_off[b + 1]], want)
+        assert pt_off[b + 1] - pt_off[b] <= 128
+
+
+def test_nao_tabulate_matches_oracle(q, small):
+    torch = _torch()
+    wl = small[0]
+    plan = q.Plan(wl)
+    nb = plan.info["n_batches"]
+    n = plan.tabulate_size(0, nb, 1)
+    out = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+    q.nao_tabulate(plan, 0, nb, 1, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    pt_off, pidx, fn_off, fidx = plan.batches()
+    phi, grad = oracle.tabulate(wl, wl.x[pidx], wl.y[pidx], wl.z[pidx])
+    o = 0
+    worst = 0.0
+    for b in range(nb):
+        P = pt_off[b + 1] - pt_off[b]
+        fns = fidx[fn_off[b]:fn_off[b + 1]]
+        nf = len(fns)
+        blk = got[o:o + 4 * P * nf].reshape(4, P, nf)
+        o += 4 * P * nf
+        rows = slice(pt_off[b], pt_off[b + 1])
+        ref = np.concatenate([phi[rows][:, fns][None], np.moveaxis(grad[rows][:, fns, :], 2, 0)], axis=0)
+        sc = np.max(np.abs(ref)) + 1e-300
+        worst = max(worst, float(np.max(np.abs(blk - ref))) / sc)
+    assert o == n
+    assert worst < 1e-13, worst
+
+
+def test_tabulate_values_only_and_size_errors(q, small):
+    torch = _torch()
+    wl = small[0]
+    plan = q.Plan(wl)
+    n1 = plan.tabulate_size(3, 7, 0)
+    n4 = plan.tabulate_size(3, 7, 1)
+    assert n4 == 4 * n1
+    full = torch.zeros(n4, dtype=torch.float64, device="cuda")
+    q.nao_tabulate(plan, 3, 7, 1, full)
+    vals = torch.zeros(n1, dtype=torch.float64, device="cuda")
+    q.nao_tabulate(plan, 3, 7, 0, vals)
+    torch.cuda.synchronize()
+    # values-only output equals the phi planes of the full output
+    f = full.cpu().numpy()
+    pt_off, _, fn_off, _ = plan.batches()
+    o4 = o1 = 0
+    for b in range(3, 7):
+        m = (pt_off[b + 1] - pt_off[b]) * (fn_off[b + 1] - fn_off[b])
+        assert np.array_equal(vals.cpu().numpy()[o1:o1 + m], f[o4:o4 + m])
+        o1 += m
+        o4 += 4 * m
+    small_buf = torch.zeros(n1 - 1, dtype=torch.float64, device="cuda")
+    with pytest.raises(q.Q4CError) as e:
+        q.nao_tabulate(plan, 3, 7, 0, small_buf)
+    assert e.value.status == q.Q4C_ESIZE
+
+
+def test_integrate_f64_small(q, small):
+    wl, pairs, ref, scale = small
+    plan, store, spin_w, spin_v = _run(q, wl)
+    _, po = plan.pairs()
+    got = store_to_blocks(store, pairs, po, wl.atom_nfn())
+    _compare_f64(got, ref, scale)
+
+
+def test_spinor_assembly_small(q, small):
+    wl, pairs, ref, scale = small
+    plan, store, spin_w, spin_v = _run(q, wl)
+    _, po = plan.pairs()
+    nfn = wl.atom_nfn()
+    got_parts = store_to_blocks(store, pairs, po, nfn)
+    gw = spinor_to_blocks(spin_w, pairs, po, nfn)
+    gv = spinor_to_blocks(spin_v, pairs, po, nfn)
+    for p in range(len(pairs)):
+        # assembly is exact given the parts
+        assert np.array_equal(gw[p], oracle.spinor_W(got_parts[p]))
+        assert np.array_equal(gv[p], oracle.spinor_V(got_parts[p]))
+        # and matches the oracle's spinor blocks within the parity bar
+        wref = oracle.spinor_W(ref[p])
+        sc = oracle.spinor_W(scale[p]).real + np.abs(oracle.spinor_W(scale[p]).imag) + 1e-300
+        assert np.max(np.abs(gw[p] - wref) / sc) < 1e-11
+
+
+def test_integrate_repeatable_bitwise(q, small):
+    torch = _torch()
+    wl = small[0]
+    plan = q.Plan(wl)
+    v = torch.from_numpy(wl.v).cuda()
+    a = q.new_store(plan)
+    b = q.new_store(plan)
+    q.q4c_integrate_H(plan, v, 0, 0, a)
+    q.q4c_integrate_H(plan, v, 0, 0, b)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_integrate_accumulate(q, small):
+    torch = _torch()
+    wl = small[0]
+    plan = q.Plan(wl)
+    v = torch.from_numpy(wl.v).cuda()
+    a = q.new_store(plan)
+    q.q4c_integrate_H(plan, v, 0, 0, a)
+    b = a.clone()
+    q.q4c_integrate_H(plan, v, 0, q.ACCUMULATE, b)
+    torch.cuda.synchronize()
+    assert torch.allclose(b, 2 * a, rtol=1e-14, atol=0)
+
+
+def test_integrate_split_small(q, small):
+    wl, pairs, ref, scale = small
+    plan, store, _, _ = _run(q, wl, precision=1)
+    _, po = plan.pairs()
+    got = store_to_blocks(store, pairs, po, wl.atom_nfn())
+    err = [np.max(np.abs(g[k] - r[k])) for g, r in zip(got, ref) for k in range(5)]
+    assert max(err) <= SPLIT_ABS, max(err)
+    # V stays on FP64 MFMA: FP64 bar
+    worst = 0.0
+    for g, r, s in zip(got, ref, scale):
+        nz = s[0] > 0
+        worst = max(worst, float(np.max(np.abs(g[0][nz] - r[0][nz]) / s[0][nz])))
+    assert worst <= FP64_REL
+
+
+def test_density_matches_oracle(q, small):
+    torch = _torch()
+    wl, pairs, _, _ = small
+    plan = q.Plan(wl)
+    _, po = plan.pairs()
+    nfn = wl.atom_nfn()
+    rng = np.random.default_rng(77)
+    coef_blocks = [rng.standard_normal((5, nfn[a], nfn[b])) for a, b in pairs]
+    from helpers import blocks_to_store
+    coef = torch.from_numpy(blocks_to_store(coef_blocks, po)).cuda()
+    for mode in (0, 1):
+        out = torch.full((wl.n_points,), float("nan"), dtype=torch.float64, device="cuda")
+        q.density_on_grid(plan, coef, q.TERM_ALL, mode, out)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        ref = oracle.density(wl, pairs, coef_blocks, weight_mode=mode)
+        sc = np.max(np.abs(ref))
+        assert np.max(np.abs(got - ref)) <= 1e-12 * sc, np.max(np.abs(got - ref)) / sc
+
+
+def test_density_terms_and_dot_product(q, small):
+    """Adjoint identity through the library alone: <density(C, weighted), dv> = <C, H(dv)>."""
+    torch = _torch()
+    wl, pairs, _, _ = small
+    plan = q.Plan(wl)
+    L = plan.info["store_len"]
+    rng = np.random.default_rng(78)
+    coef = torch.from_numpy(rng.standard_normal((5, L))).cuda()
+    dv = torch.from_numpy(rng.standard_normal(wl.n_points)).cuda()
+    grad = torch.zeros(wl.n_points, dtype=torch.float64, device="cuda")
+    q.density_on_grid(plan, coef, q.TERM_ALL, 1, grad)
+    H = q.new_store(plan)
+    q.q4c_integrate_H(plan, dv, 0, 0, H)
+    torch.cuda.synchronize()
+    lhs = float(torch.dot(grad, dv))
+    rhs = float(torch.sum(coef * H))
+    scale = float(torch.sum(torch.abs(coef * H)))
+    assert abs(lhs - rhs) <= 1e-12 * scale
+    # term selection adds up
+    parts = []
+    for t in (q.TERM_LL, q.TERM_SS, q.TERM_SO):
+        o = torch.zeros_like(grad)
+        q.density_on_grid(plan, coef, t, 1, o)
+        parts.append(o)
+    torch.cuda.synchronize()
+    assert torch.allclose(parts[0] + parts[1] + parts[2], grad, rtol=1e-12, atol=1e-12 * float(grad.abs().max()))
+
+
+def test_coef_from_spinor_matches_oracle(q, small):
+    torch = _torch()
+    wl, pairs, _, _ = small
+    plan = q.Plan(wl)
+    _, po = plan.pairs()
+    D = W.spinor_density(wl, pairs, 5001)
+    from helpers import blocks_to_store, spinor_from_blocks
+    spin = torch.from_numpy(spinor_from_blocks(D, po)).cuda()
+    out = q.new_store(plan)
+    q.q4c_coef_from_spinor(plan, spin, out)
+    torch.cuda.synchronize()
+    ref = blocks_to_store(oracle.coef_from_spinor_density(pairs, D), po)
+    assert np.max(np.abs(out.cpu().numpy() - ref)) <= 1e-15 * np.max(np.abs(ref))

@@ -1,0 +1,196 @@
+#!/usr/bin/env python3
+"""Benchmark of Q4C real-space Hamiltonian integration on one MI355X.
+
+Workload: the seeded 120-atom cluster (20% Pb, 30% I, 50% H/C/N in a 20
+angstrom cube; 26 NAOs per heavy atom, 5 per light atom, l <= 3; 60 x 302
+points per atom = 2,174,400 points; batches of at most 300 points; model
+potential plus smooth noise).  Inputs are resident in HBM before timing.
+
+One step = the whole hot path once: q4c_integrate_H (tabulation, weighting,
+the five contractions, batch-to-global sums, W spinor assembly) followed by
+density_on_grid (the adjoint dL/dv for a seeded upstream gradient).
+
+Prints one JSON line.  `value` is active grid points per second of the step.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "H-integration grid points/s & MFMA util: split-FP32 vs FP64 at ≤1e-8 Ha"
+PEAK_F64 = 78.6e12    # MI355X dense FP64 MFMA, flop/s
+PEAK_F32 = 157.3e12   # MI355X dense FP32 MFMA, flop/s
+PREC = {"f64": 0, "split": 1, "f32": 2}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", choices=sorted(PREC), default="f64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=float, default=0.02, help="fraction of grid points for the oracle timing")
+    ap.add_argument("--n-atoms", type=int, default=120)
+    return ap.parse_args()
+
+
+def contraction_peak(prec: str) -> float:
+    """Peak of the contraction kernel for its operand types: 1 of the 10 P n^2
+    algorithmic flops (V) runs on FP64 MFMA in every mode; the other 9 (W parts)
+    run on FP64 MFMA (f64) or FP32 MFMA (split, f32)."""
+    if prec == "f64":
+        return PEAK_F64
+    return 10.0 / (1.0 / PEAK_F64 + 9.0 / PEAK_F32)
+
+
+def cpu_baseline(wl, frac: float, seed: int = 6002):
+    """Time the oracle on a seeded sample of grid points (all atom pairs)."""
+    import numpy as np
+    import oracle
+    import workload as W
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(wl.n_points, size=max(1, int(frac * wl.n_points)), replace=False))
+    sub = wl.subset_points(idx)
+    pairs = W.atom_pairs(wl)
+    rc = wl.atom_rcut()
+    d2 = ((sub.x[:, None] - wl.R[None, :, 0]) ** 2 + (sub.y[:, None] - wl.R[None, :, 1]) ** 2 +
+          (sub.z[:, None] - wl.R[None, :, 2]) ** 2)
+    n_act = int(np.sum(np.any(d2 < rc[None, :] ** 2, axis=1)))
+    oracle.build()
+    t0 = time.perf_counter()
+    oracle.pair_blocks(sub, pairs)
+    dt = time.perf_counter() - t0
+    return {"value": n_act / dt, "unit": "points/s", "cores": 1, "kind": "oracle",
+            "sample": "%d of %d grid points (%d active, seed %d), all %d atom pairs, %.1f s" %
+                      (idx.size, wl.n_points, n_act, seed, len(pairs), dt)}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py measures one GPU only; this build has no multi-GPU path (requested --gpus %d)" % a.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import paper_2608_00773_amd as q
+    import workload as W
+
+    t0 = time.perf_counter()
+    wl = W.config_cluster(n_atoms=a.n_atoms)
+    t_gen = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    plan = q.Plan(wl)
+    t_plan = time.perf_counter() - t0
+    info = plan.info
+    L = info["store_len"]
+    dev = torch.device("cuda:0")
+    v = torch.from_numpy(wl.v).to(dev)
+    store = q.new_store(plan, dev)
+    spin = q.new_spinor(plan, dev)
+    rng = np.random.default_rng(5002)
+    gbar = torch.from_numpy(rng.standard_normal((5, L))).to(dev)
+    grad = torch.empty(wl.n_points, dtype=torch.float64, device=dev)
+    prec = PREC[a.precision]
+
+    def step(p):
+        q.q4c_integrate_H(plan, v, p, q.ASSEMBLE_W, store, spin)
+        q.density_on_grid(plan, gbar, q.TERM_ALL, 1, grad)
+
+    def timed(fn, k):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(k):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    for _ in range(a.warmup):
+        step(prec)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms_step = timed(lambda: step(prec), a.steps)
+    wall = time.perf_counter() - t0
+    print("[bench] %d steps of %.3f ms" % (a.steps, ms_step), file=sys.stderr, flush=True)
+
+    # per-kernel times of the same step, HIP events on the launch stream
+    plan.profile(True)
+    for _ in range(a.steps):
+        step(prec)
+    tim = plan.timers()
+    plan.profile(False)
+    n_contract = max(tim["contract"][1], 1)
+    t_contract = tim["contract"][0] / n_contract * 1e-3  # s per launch
+    launches_per_step = tim["contract"][1] / a.steps
+    flops_launch = info["flops_alg"] / launches_per_step
+    achieved = flops_launch / t_contract
+    peak = contraction_peak(a.precision)
+
+    # forward-only throughput and error of each precision against the FP64 path
+    fwd = {}
+    outs = {}
+    for name, p in PREC.items():
+        st = q.new_store(plan, dev)
+        fwd[name] = timed(lambda: q.q4c_integrate_H(plan, v, p, q.ASSEMBLE_W, st, spin), max(3, a.steps // 4))
+        outs[name] = st
+    err = {n: [float(torch.max(torch.abs(outs[n][k] - outs["f64"][k]))) for k in range(5)] for n in outs}
+    ms_adj = timed(lambda: q.density_on_grid(plan, gbar, q.TERM_ALL, 1, grad), max(3, a.steps // 4))
+
+    n_act = info["n_active"]
+    res = {
+        "metric": METRIC,
+        "value": n_act / (ms_step * 1e-3),
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f64": "f64", "split": "f32-hi/lo+f64", "f32": "f32+f64"}[a.precision],
+        "data": "synthetic",
+        "config": {
+            "workload": "random cluster, %d atoms (Pb/I/H,C,N), %d NAOs, %d points (%d active), %d batches <= 300 pts" %
+                        (wl.n_atoms, info["n_fn"], info["n_points"], n_act, info["n_batches"]),
+            "precision": a.precision,
+            "step": "q4c_integrate_H (all parts + W spinor) + density_on_grid (adjoint, all terms)",
+            "flops_alg_per_H": info["flops_alg"],
+        },
+        "roofline": {
+            "kernel": "k_contract",
+            "bound": "mfma",
+            "achieved": achieved / 1e12,
+            "peak": peak / 1e12,
+            "unit": "TFLOP/s",
+            "frac": achieved / peak,
+            "traffic": None,
+            "avg_launch_ms": t_contract * 1e3,
+            "launches_per_step": launches_per_step,
+        },
+        "kernels_ms_per_step": {k: v_[0] / a.steps for k, v_ in tim.items() if v_[1]},
+        "forward_ms": fwd,
+        "forward_points_per_s": {k: n_act / (t * 1e-3) for k, t in fwd.items()},
+        "adjoint_ms": ms_adj,
+        "max_abs_diff_vs_f64_Ha": {k: dict(zip(q.PART_NAMES, e)) for k, e in err.items() if k != "f64"},
+        "plan_s": t_plan,
+        "workload_gen_s": t_gen,
+        "wall_timed_s": wall,
+    }
+    if not a.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(wl, a.cpu_sample)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -64,9 +64,12 @@ enum {
 /* precision of the per-batch contractions */
 enum {
   Q4C_PREC_F64 = 0,      /* FP64 MFMA, FP64 accumulation */
-  Q4C_PREC_SPLIT_F32 = 1 /* FP32 MFMA on hi+lo split operands, FP32 per-batch
-                            accumulation, FP64 batch-to-global sums; the V part
-                            stays on FP64 MFMA (see q4c_integrate_H) */
+  Q4C_PREC_SPLIT_F32 = 1, /* FP32 MFMA on hi+lo split operands (three products),
+                             FP32 per-batch accumulation, FP64 batch-to-global
+                             sums; the V part stays on FP64 MFMA */
+  Q4C_PREC_F32 = 2        /* as Q4C_PREC_SPLIT_F32 with single FP32 operands
+                             (one product): the W parts' error is dominated by
+                             the FP32 accumulation either way */
 };
 
 /* flags of q4c_integrate_H */
@@ -201,6 +204,25 @@ int density_on_grid(const q4c_plan *plan, const double *coef_dev, uint32_t terms
  * off-diagonal pairs (each stored block stands for its mirror), 1 on diagonal
  * pairs.  coef_out_dev: 5 store_len doubles. */
 int q4c_coef_from_spinor(const q4c_plan *plan, const double *spin_d_dev, double *coef_out_dev, void *stream);
+
+/* Per-kernel timing.  While profiling is enabled on a plan, every kernel the
+ * plan launches is bracketed by HIP events on the launch stream.
+ * q4c_plan_timers waits for those events, returns per-kernel-kind totals
+ * (milliseconds, launch counts; arrays of Q4C_NTIMERS) since the last query,
+ * and resets them.  Meant for measurement, not for code under graph capture. */
+enum {
+  Q4C_TIMER_TABULATE = 0,
+  Q4C_TIMER_CONTRACT = 1,
+  Q4C_TIMER_REDUCE = 2,
+  Q4C_TIMER_SPINOR = 3,
+  Q4C_TIMER_BROADCAST = 4,
+  Q4C_TIMER_DENSITY_TILES = 5,
+  Q4C_TIMER_DENSITY_POINTS = 6,
+  Q4C_TIMER_OTHER = 7,
+  Q4C_NTIMERS = 8
+};
+int q4c_plan_profile(q4c_plan *plan, int enable);
+int q4c_plan_timers(q4c_plan *plan, double *ms, int64_t *launches);
 
 /* Block until the plan's queued work is done; reports asynchronous HIP errors. */
 int q4c_plan_sync(const q4c_plan *plan, void *stream);

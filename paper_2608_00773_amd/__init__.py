@@ -19,7 +19,8 @@ LIB_PATH = os.path.join(_PKG, "libq4c.so")
 Q4C_OK = 0
 Q4C_EINVAL, Q4C_ENOMEM, Q4C_EHIP, Q4C_ENOTIMPL, Q4C_EUNSUPPORTED, Q4C_ESIZE, Q4C_ENONFINITE, Q4C_ENODEV = \
     -1, -2, -3, -4, -5, -6, -7, -8
-PREC_F64, PREC_SPLIT_F32 = 0, 1
+PREC_F64, PREC_SPLIT_F32, PREC_F32 = 0, 1, 2
+TIMER_NAMES = ("tabulate", "contract", "reduce", "spinor", "broadcast", "density_tiles", "density_points", "other")
 ACCUMULATE, ASSEMBLE_W, ASSEMBLE_V, CHECK_FINITE = 1, 2, 4, 8
 PLAN_HOST_ONLY = 1
 TERM_LL, TERM_SS, TERM_SO, TERM_ALL = 1, 2, 4, 7
@@ -69,7 +70,7 @@ class _Info(ctypes.Structure):
 
 EXPORTS = ("q4c_plan_create", "q4c_plan_destroy", "q4c_plan_info", "q4c_plan_pairs", "q4c_plan_batches",
            "q4c_tabulate_size", "nao_tabulate", "q4c_integrate_H", "density_on_grid", "q4c_coef_from_spinor",
-           "q4c_plan_sync", "q4c_status_string", "q4c_last_error")
+           "q4c_plan_sync", "q4c_plan_profile", "q4c_plan_timers", "q4c_status_string", "q4c_last_error")
 
 
 def _load():
@@ -94,6 +95,8 @@ def _load():
         lib.density_on_grid.argtypes = [vp, vp, u32, i32, vp, vp]
         lib.q4c_coef_from_spinor.argtypes = [vp, vp, vp, vp]
         lib.q4c_plan_sync.argtypes = [vp, vp]
+        lib.q4c_plan_profile.argtypes = [vp, ctypes.c_int]
+        lib.q4c_plan_timers.argtypes = [vp, vp, vp]
         lib.q4c_status_string.argtypes = [ctypes.c_int]
         lib.q4c_status_string.restype = ctypes.c_char_p
         lib.q4c_last_error.argtypes = []
@@ -201,6 +204,17 @@ class Plan:
         n = ctypes.c_int64()
         _check(_load().q4c_tabulate_size(self._h, int(b0), int(b1), int(deriv), ctypes.byref(n)))
         return int(n.value)
+
+    def profile(self, enable: bool = True):
+        """Bracket every kernel launch of this plan with HIP events (q4c_plan_profile)."""
+        _check(_load().q4c_plan_profile(self._h, 1 if enable else 0))
+
+    def timers(self):
+        """{kernel kind: (total ms, launches)} since the last call (q4c_plan_timers)."""
+        ms = np.zeros(len(TIMER_NAMES))
+        n = np.zeros(len(TIMER_NAMES), dtype=np.int64)
+        _check(_load().q4c_plan_timers(self._h, ms.ctypes.data, n.ctypes.data))
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(TIMER_NAMES)}
 
     def sync(self):
         _check(_load().q4c_plan_sync(self._h, _stream_handle()))

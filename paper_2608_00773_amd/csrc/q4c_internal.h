@@ -126,6 +126,11 @@ struct q4c_plan {
   int64_t *d_zero_off = nullptr, *d_zero_len = nullptr;
   double *d_staging = nullptr;
   int32_t *d_flag = nullptr;
+
+  // ---- profiling (mutable: calls take a const plan)
+  mutable bool profiling = false;
+  mutable std::vector<hipEvent_t> ev_pool;                // free events
+  mutable std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_live;  // (timer, start/stop)
 };
 
 namespace q4c {
@@ -140,4 +145,14 @@ int launch_density(const q4c_plan *p, const double *coef, uint32_t terms, int we
                    hipStream_t s);
 int launch_coef_from_spinor(const q4c_plan *p, const double *spin_d, double *coef_out, hipStream_t s);
 int launch_check_finite(const q4c_plan *p, const double *v, hipStream_t s, bool *finite);
+
+// Brackets one launch with events when the plan is profiling.
+struct TimedLaunch {
+  const q4c_plan *p;
+  int timer;
+  hipStream_t s;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  TimedLaunch(const q4c_plan *p_, int timer_, hipStream_t s_);
+  ~TimedLaunch();
+};
 }  // namespace q4c

@@ -236,7 +236,7 @@ __device__ __forceinline__ int d_row_f64(int lk, int r) { return lk + 4 * r; }
 __device__ __forceinline__ int d_row_f32(int lk, int r) { return 4 * lk + r; }
 //
 // Precision modes of the forward contraction.
-enum { MODE_F64 = 0, MODE_SPLIT = 1 };
+enum { MODE_F64 = 0, MODE_SPLIT = 1, MODE_F32 = 2 };
 
 template <int MODE>
 __global__ __launch_bounds__(NT, 2) void k_contract(DevPlan d, const WorkItem *work, int64_t w0, const double *v,
@@ -269,7 +269,7 @@ __global__ __launch_bounds__(NT, 2) void k_contract(DevPlan d, const WorkItem *w
       for (int q = 0; q < 5; ++q) acc[x][y][q] = dbl4{0.0, 0.0, 0.0, 0.0};
   // split mode: FP32 accumulators of the four W parts
   flt4 accf[2][2][4];
-  if (MODE == MODE_SPLIT) {
+  if (MODE != MODE_F64) {
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -314,6 +314,22 @@ __global__ __launch_bounds__(NT, 2) void k_contract(DevPlan d, const WorkItem *w
             acc[x][y][3] = mfma64(-a[x][1], bb[y][3], acc[x][y][3]);
             acc[x][y][4] = mfma64(a[x][1], bb[y][2], acc[x][y][4]);
             acc[x][y][4] = mfma64(-a[x][2], bb[y][1], acc[x][y][4]);
+          } else if (MODE == MODE_F32) {
+            float af[4], bf[4];
+#pragma unroll
+            for (int q = 1; q < 4; ++q) {
+              af[q] = (float)a[x][q];
+              bf[q] = (float)bb[y][q];
+            }
+            accf[x][y][0] = mfma32(af[1], bf[1], accf[x][y][0]);
+            accf[x][y][0] = mfma32(af[2], bf[2], accf[x][y][0]);
+            accf[x][y][0] = mfma32(af[3], bf[3], accf[x][y][0]);
+            accf[x][y][1] = mfma32(af[2], bf[3], accf[x][y][1]);
+            accf[x][y][1] = mfma32(-af[3], bf[2], accf[x][y][1]);
+            accf[x][y][2] = mfma32(af[3], bf[1], accf[x][y][2]);
+            accf[x][y][2] = mfma32(-af[1], bf[3], accf[x][y][2]);
+            accf[x][y][3] = mfma32(af[1], bf[2], accf[x][y][3]);
+            accf[x][y][3] = mfma32(-af[2], bf[1], accf[x][y][3]);
           } else {
             // hi + lo split: x = hi + lo with hi = fl(x), lo = fl(x - hi);
             // x y ~ hi_x hi_y + hi_x lo_y + lo_x hi_y (lo_x lo_y dropped)
@@ -369,7 +385,7 @@ __global__ __launch_bounds__(NT, 2) void k_contract(DevPlan d, const WorkItem *w
             stage_store<0, 1>(staging, si, sj, li, lj, diag, &v0);
           }
         }
-        if (MODE == MODE_SPLIT) {
+        if (MODE != MODE_F64) {
           const int lf = r0 + wr + x * 16 + d_row_f32(lk, r);
           if (lf < n) {
             const SlotInfo sf = slot_of(d, f0, sbase, lf);
@@ -620,7 +636,10 @@ static int check_launch(const char *what) {
 }
 
 int launch_tabulate(const q4c_plan *p, int64_t b0, int64_t b1, int deriv, double *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_tabulate, dim3((unsigned)(b1 - b0)), dim3(256), 0, s, p->dp, b0, deriv, out);
+  {
+    TimedLaunch tl_(p, Q4C_TIMER_TABULATE, s);
+    hipLaunchKernelGGL(k_tabulate, dim3((unsigned)(b1 - b0)), dim3(256), 0, s, p->dp, b0, deriv, out);
+  }
   return check_launch("k_tabulate");
 }
 
@@ -630,32 +649,47 @@ int launch_integrate(const q4c_plan *p, const double *v, int precision, uint32_t
   for (const Pass &ps : p->passes) {
     const int64_t nw = ps.w1 - ps.w0;
     if (nw > 0) {
-      if (precision == Q4C_PREC_F64)
-        hipLaunchKernelGGL(k_contract<MODE_F64>, dim3((unsigned)nw), dim3(NT), 0, s, p->dp, p->d_work, ps.w0, v,
-                           p->d_staging);
-      else
-        hipLaunchKernelGGL(k_contract<MODE_SPLIT>, dim3((unsigned)nw), dim3(NT), 0, s, p->dp, p->d_work, ps.w0, v,
-                           p->d_staging);
+      {
+        TimedLaunch tl_(p, Q4C_TIMER_CONTRACT, s);
+        if (precision == Q4C_PREC_F64)
+          hipLaunchKernelGGL(k_contract<MODE_F64>, dim3((unsigned)nw), dim3(NT), 0, s, p->dp, p->d_work, ps.w0, v,
+                             p->d_staging);
+        else if (precision == Q4C_PREC_F32)
+          hipLaunchKernelGGL(k_contract<MODE_F32>, dim3((unsigned)nw), dim3(NT), 0, s, p->dp, p->d_work, ps.w0, v,
+                             p->d_staging);
+        else
+          hipLaunchKernelGGL(k_contract<MODE_SPLIT>, dim3((unsigned)nw), dim3(NT), 0, s, p->dp, p->d_work, ps.w0, v,
+                             p->d_staging);
+      }
       int rc = check_launch("k_contract");
       if (rc != Q4C_OK) return rc;
     }
     const int64_t nr = ps.r1 - ps.r0;
     if (nr > 0) {
-      hipLaunchKernelGGL(k_reduce, dim3((unsigned)nr), dim3(256), 0, s, p->dp, ps.r0, p->d_red_pair, p->d_red_first,
-                         p->d_red_inc_off, p->d_inc_src, p->d_staging, store, accumulate);
+      {
+        TimedLaunch tl_(p, Q4C_TIMER_REDUCE, s);
+        hipLaunchKernelGGL(k_reduce, dim3((unsigned)nr), dim3(256), 0, s, p->dp, ps.r0, p->d_red_pair, p->d_red_first,
+                           p->d_red_inc_off, p->d_inc_src, p->d_staging, store, accumulate);
+      }
       int rc = check_launch("k_reduce");
       if (rc != Q4C_OK) return rc;
     }
   }
   if (!accumulate && !p->untouched_pairs.empty()) {
-    hipLaunchKernelGGL(k_zero_pairs, dim3((unsigned)p->untouched_pairs.size()), dim3(256), 0, s, p->dp,
-                       p->d_untouched, store);
+    {
+      TimedLaunch tl_(p, Q4C_TIMER_OTHER, s);
+      hipLaunchKernelGGL(k_zero_pairs, dim3((unsigned)p->untouched_pairs.size()), dim3(256), 0, s, p->dp,
+                         p->d_untouched, store);
+    }
     int rc = check_launch("k_zero_pairs");
     if (rc != Q4C_OK) return rc;
   }
   if ((flags & (Q4C_ASSEMBLE_W | Q4C_ASSEMBLE_V)) && p->n_pairs > 0) {
-    hipLaunchKernelGGL(k_spinor, dim3((unsigned)p->n_pairs), dim3(256), 0, s, p->dp, store,
-                       (flags & Q4C_ASSEMBLE_W) ? spin_w : nullptr, (flags & Q4C_ASSEMBLE_V) ? spin_v : nullptr);
+    {
+      TimedLaunch tl_(p, Q4C_TIMER_SPINOR, s);
+      hipLaunchKernelGGL(k_spinor, dim3((unsigned)p->n_pairs), dim3(256), 0, s, p->dp, store,
+                         (flags & Q4C_ASSEMBLE_W) ? spin_w : nullptr, (flags & Q4C_ASSEMBLE_V) ? spin_v : nullptr);
+    }
     int rc = check_launch("k_spinor");
     if (rc != Q4C_OK) return rc;
   }
@@ -667,31 +701,46 @@ int launch_density(const q4c_plan *p, const double *coef, uint32_t terms, int we
   int rc;
   if (p->n_points > 0) {
     unsigned nb = (unsigned)std::min<int64_t>((p->n_points + 255) / 256, 65535);
-    hipLaunchKernelGGL(k_fill, dim3(nb), dim3(256), 0, s, out, p->n_points, 0.0);
+    {
+      TimedLaunch tl_(p, Q4C_TIMER_OTHER, s);
+      hipLaunchKernelGGL(k_fill, dim3(nb), dim3(256), 0, s, out, p->n_points, 0.0);
+    }
     if ((rc = check_launch("k_fill")) != Q4C_OK) return rc;
   }
   for (const Pass &ps : p->passes) {
     const int64_t nr = ps.r1 - ps.r0, nw = ps.w1 - ps.w0, nbt = ps.b1 - ps.b0, nz = ps.z1 - ps.z0;
     if (nz > 0) {
-      hipLaunchKernelGGL(k_zero_blocks, dim3((unsigned)nz), dim3(256), 0, s, p->d_zero_off, p->d_zero_len, ps.z0,
-                         p->d_staging);
+      {
+        TimedLaunch tl_(p, Q4C_TIMER_OTHER, s);
+        hipLaunchKernelGGL(k_zero_blocks, dim3((unsigned)nz), dim3(256), 0, s, p->d_zero_off, p->d_zero_len, ps.z0,
+                           p->d_staging);
+      }
       if ((rc = check_launch("k_zero_blocks")) != Q4C_OK) return rc;
     }
     if (nr > 0) {
-      hipLaunchKernelGGL(k_broadcast, dim3((unsigned)nr), dim3(256), 0, s, p->dp, ps.r0, p->d_red_pair,
-                         p->d_red_inc_off, p->d_inc_src, coef, p->d_staging);
+      {
+        TimedLaunch tl_(p, Q4C_TIMER_BROADCAST, s);
+        hipLaunchKernelGGL(k_broadcast, dim3((unsigned)nr), dim3(256), 0, s, p->dp, ps.r0, p->d_red_pair,
+                           p->d_red_inc_off, p->d_inc_src, coef, p->d_staging);
+      }
       if ((rc = check_launch("k_broadcast")) != Q4C_OK) return rc;
     }
     // partials go after the staged coefficients of this pass
     double *partial = p->d_staging + ps.staging_len;
     if (nw > 0) {
-      hipLaunchKernelGGL(k_density_tiles, dim3((unsigned)nw), dim3(NT), 0, s, p->dp, terms, p->d_work, ps.w0,
-                         p->d_staging, partial);
+      {
+        TimedLaunch tl_(p, Q4C_TIMER_DENSITY_TILES, s);
+        hipLaunchKernelGGL(k_density_tiles, dim3((unsigned)nw), dim3(NT), 0, s, p->dp, terms, p->d_work, ps.w0,
+                           p->d_staging, partial);
+      }
       if ((rc = check_launch("k_density_tiles")) != Q4C_OK) return rc;
     }
     if (nbt > 0) {
-      hipLaunchKernelGGL(k_density_points, dim3((unsigned)nbt), dim3(256), 0, s, p->dp, ps.b0, partial, weight_mode,
-                         out);
+      {
+        TimedLaunch tl_(p, Q4C_TIMER_DENSITY_POINTS, s);
+        hipLaunchKernelGGL(k_density_points, dim3((unsigned)nbt), dim3(256), 0, s, p->dp, ps.b0, partial, weight_mode,
+                           out);
+      }
       if ((rc = check_launch("k_density_points")) != Q4C_OK) return rc;
     }
   }
@@ -700,7 +749,10 @@ int launch_density(const q4c_plan *p, const double *coef, uint32_t terms, int we
 
 int launch_coef_from_spinor(const q4c_plan *p, const double *spin_d, double *coef_out, hipStream_t s) {
   if (p->n_pairs == 0) return Q4C_OK;
-  hipLaunchKernelGGL(k_coef_from_spinor, dim3((unsigned)p->n_pairs), dim3(256), 0, s, p->dp, spin_d, coef_out);
+  {
+    TimedLaunch tl_(p, Q4C_TIMER_OTHER, s);
+    hipLaunchKernelGGL(k_coef_from_spinor, dim3((unsigned)p->n_pairs), dim3(256), 0, s, p->dp, spin_d, coef_out);
+  }
   return check_launch("k_coef_from_spinor");
 }
 

@@ -143,6 +143,17 @@ int device_alloc(q4c_plan *p, size_t bytes, void **d) {
 }
 
 void free_device(q4c_plan *p) {
+  if (p->device >= 0 && (!p->ev_pool.empty() || !p->ev_live.empty())) {
+    (void)hipSetDevice(p->device);
+    (void)hipDeviceSynchronize();
+    for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
+    for (auto &x : p->ev_live) {
+      (void)hipEventDestroy(x.second.first);
+      (void)hipEventDestroy(x.second.second);
+    }
+    p->ev_pool.clear();
+    p->ev_live.clear();
+  }
   if (!p->allocations.empty()) {
     if (p->device >= 0) (void)hipSetDevice(p->device);
     (void)hipDeviceSynchronize();
@@ -549,6 +560,30 @@ int check_plan_dev(const q4c_plan *p) {
 }  // namespace
 
 namespace q4c {
+static hipEvent_t take_event(const q4c_plan *p) {
+  if (!p->ev_pool.empty()) {
+    hipEvent_t e = p->ev_pool.back();
+    p->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+TimedLaunch::TimedLaunch(const q4c_plan *p_, int timer_, hipStream_t s_) : p(p_), timer(timer_), s(s_) {
+  if (!p->profiling) return;
+  e0 = take_event(p);
+  e1 = take_event(p);
+  if (e0 && e1) (void)hipEventRecord(e0, s);
+}
+
+TimedLaunch::~TimedLaunch() {
+  if (!e0 || !e1) return;
+  (void)hipEventRecord(e1, s);
+  p->ev_live.push_back({timer, {e0, e1}});
+}
+
 void set_error(const std::string &msg) { g_last_error = msg; }
 int hip_fail(hipError_t e, const char *what) {
   g_last_error = std::string(what) + ": " + hipGetErrorString(e);
@@ -667,7 +702,8 @@ int nao_tabulate(const q4c_plan *p, int64_t b0, int64_t b1, int32_t deriv, doubl
 int q4c_integrate_H(const q4c_plan *p, const double *v_dev, int32_t precision, uint32_t flags, double *store_dev,
                     double *spin_w_dev, double *spin_v_dev, void *stream) {
   if (!p) return fail(Q4C_EINVAL, "NULL plan");
-  if (precision != Q4C_PREC_F64 && precision != Q4C_PREC_SPLIT_F32) return fail(Q4C_EINVAL, "unknown precision");
+  if (precision != Q4C_PREC_F64 && precision != Q4C_PREC_SPLIT_F32 && precision != Q4C_PREC_F32)
+    return fail(Q4C_EINVAL, "unknown precision");
   if (flags & ~(uint32_t)(Q4C_ACCUMULATE | Q4C_ASSEMBLE_W | Q4C_ASSEMBLE_V | Q4C_CHECK_FINITE))
     return fail(Q4C_EINVAL, "unknown flag");
   if (p->n_points > 0 && !v_dev) return fail(Q4C_EINVAL, "NULL potential");
@@ -713,6 +749,38 @@ int q4c_plan_sync(const q4c_plan *p, void *stream) {
   e = hipGetLastError();
   if (e != hipSuccess) return q4c::hip_fail(e, "asynchronous kernel error");
   return Q4C_OK;
+}
+
+int q4c_plan_profile(q4c_plan *p, int enable) {
+  if (!p) return fail(Q4C_EINVAL, "NULL plan");
+  if (!p->on_device) return fail(Q4C_ENODEV, "plan has no device data");
+  p->profiling = enable != 0;
+  return Q4C_OK;
+}
+
+int q4c_plan_timers(q4c_plan *p, double *ms, int64_t *launches) {
+  if (!p || !ms || !launches) return fail(Q4C_EINVAL, "NULL argument");
+  for (int k = 0; k < Q4C_NTIMERS; ++k) {
+    ms[k] = 0.0;
+    launches[k] = 0;
+  }
+  if (!p->on_device) return Q4C_OK;
+  (void)hipSetDevice(p->device);
+  int rc = Q4C_OK;
+  for (auto &x : p->ev_live) {
+    float t = 0.0f;
+    hipError_t e = hipEventSynchronize(x.second.second);
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, x.second.first, x.second.second);
+    if (e != hipSuccess && rc == Q4C_OK) rc = q4c::hip_fail(e, "hipEventElapsedTime");
+    if (x.first >= 0 && x.first < Q4C_NTIMERS) {
+      ms[x.first] += t;
+      launches[x.first] += 1;
+    }
+    p->ev_pool.push_back(x.second.first);
+    p->ev_pool.push_back(x.second.second);
+  }
+  p->ev_live.clear();
+  return rc;
 }
 
 const char *q4c_status_string(int s) {

@@ -140,10 +140,16 @@ void orc_solid_harmonic(int l, int m, double x, double y, double z, double *S, d
 /* Radial table                                                        */
 /* ------------------------------------------------------------------ */
 
-void orc_radial(const double *tab, int nint, double rcut, double s, double *val, double *der) {
+/* Rt(s) and Rt'(s); with cval/cder non-NULL also the evaluation scales
+ * sum_k |c_k t^k| and sum_k k |c_k t^(k-1)| / h (the size of the terms the
+ * cubic is summed from, which bounds its rounding error). */
+static void radial_eval(const double *tab, int nint, double rcut, double s, double *val, double *der, double *cval,
+                        double *cder) {
   if (!(s < rcut)) {
     *val = 0.0;
     *der = 0.0;
+    if (cval) *cval = 0.0;
+    if (cder) *cder = 0.0;
     return;
   }
   int j = (int)floor(nint * sqrt(s / rcut));
@@ -156,6 +162,12 @@ void orc_radial(const double *tab, int nint, double rcut, double s, double *val,
   const double *c = tab + 4 * (int64_t)j;
   *val = c[0] + c[1] * t + c[2] * t * t + c[3] * t * t * t;
   *der = (c[1] + 2.0 * c[2] * t + 3.0 * c[3] * t * t) / h;
+  if (cval) *cval = fabs(c[0]) + fabs(c[1] * t) + fabs(c[2] * t * t) + fabs(c[3] * t * t * t);
+  if (cder) *cder = (fabs(c[1]) + fabs(2.0 * c[2] * t) + fabs(3.0 * c[3] * t * t)) / h;
+}
+
+void orc_radial(const double *tab, int nint, double rcut, double s, double *val, double *der) {
+  radial_eval(tab, nint, rcut, s, val, der, NULL, NULL);
 }
 
 /* number of functions on atom a */
@@ -177,28 +189,40 @@ static double atom_rcut(const orc_basis *b, int a) {
  * phi = Rt(s) S_lm(d), grad phi = Rt'(s) (d/s) S_lm + Rt(s) grad S_lm, d = p - R_a.
  * At s = 0 the first gradient term is 0 (Rt'(s) d/s -> 0 for a smooth radial).
  */
-static void atom_functions(const orc_basis *b, int a, double px, double py, double pz, double *phi,
-                           double *grad) {
+static void atom_functions_c(const orc_basis *b, int a, double px, double py, double pz, double *phi,
+                             double *grad, double *aphi, double *agrad) {
   double dx = px - b->R[3 * a], dy = py - b->R[3 * a + 1], dz = pz - b->R[3 * a + 2];
   double s = sqrt(dx * dx + dy * dy + dz * dz);
   int f = 0;
   for (int sh = b->atom_shell_off[a]; sh < b->atom_shell_off[a + 1]; ++sh) {
     int l = b->shell_l[sh];
-    double Rt, dRt;
-    orc_radial(b->coef + b->shell_coef_off[sh], b->shell_nint[sh], b->shell_rcut[sh], s, &Rt, &dRt);
-    double u[3] = {0.0, 0.0, 0.0};
+    double Rt, dRt, cR, cdR;
+    radial_eval(b->coef + b->shell_coef_off[sh], b->shell_nint[sh], b->shell_rcut[sh], s, &Rt, &dRt, &cR, &cdR);
+    double u[3] = {0.0, 0.0, 0.0}, au[3] = {0.0, 0.0, 0.0};
     if (s > 0.0) {
       u[0] = dRt * dx / s;
       u[1] = dRt * dy / s;
       u[2] = dRt * dz / s;
+      au[0] = cdR * fabs(dx) / s;
+      au[1] = cdR * fabs(dy) / s;
+      au[2] = cdR * fabs(dz) / s;
     }
     for (int m = -l; m <= l; ++m, ++f) {
       double S, gS[3];
       orc_solid_harmonic(l, m, dx, dy, dz, &S, gS);
       phi[f] = Rt * S;
       for (int c = 0; c < 3; ++c) grad[3 * f + c] = u[c] * S + Rt * gS[c];
+      if (aphi) {
+        aphi[f] = cR * fabs(S);
+        for (int c = 0; c < 3; ++c) agrad[3 * f + c] = au[c] * fabs(S) + cR * fabs(gS[c]);
+      }
     }
   }
+}
+
+static void atom_functions(const orc_basis *b, int a, double px, double py, double pz, double *phi,
+                           double *grad) {
+  atom_functions_c(b, a, px, py, pz, phi, grad, NULL, NULL);
 }
 
 int orc_n_functions(const orc_basis *b) {
@@ -241,9 +265,13 @@ static inline void neu_add(double *s, double *c, double x) {
  * screened != 0 skips points outside the support of A or of B (exact zeros);
  * screened == 0 evaluates every point (brute force).
  * absout (optional, same layout) receives the error scale of each element:
- * sum_g |w_g v_g| times the sum of the absolute values of the products that
- * enter the term (|phi_i phi_j|, sum_a |d_a phi_i d_a phi_j|, and
- * |d_b phi_i d_c phi_j| + |d_c phi_i d_b phi_j| for the spin-orbit parts).
+ * sum_g |w_g v_g| times the sum of the magnitudes of the products that enter
+ * the term (|phi_i||phi_j|, sum_a |d_a phi_i||d_a phi_j|, and
+ * |d_b phi_i||d_c phi_j| + |d_c phi_i||d_b phi_j| for the spin-orbit parts),
+ * where each magnitude is that of the terms the function value is computed
+ * from: the radial cubic contributes sum_k |c_k t^k| (resp. its derivative
+ * analogue) instead of |Rt|, so tail values that arise from cancellation in
+ * the table carry their rounding scale.
  */
 int orc_pair_blocks(const orc_basis *b, int64_t npts, const double *x, const double *y, const double *z,
                     const double *w, const double *v, double c_light, int npairs, const int32_t *pa,
@@ -258,9 +286,11 @@ int orc_pair_blocks(const orc_basis *b, int64_t npts, const double *x, const dou
     double *sum = (double *)calloc(5 * blk, sizeof(double));
     double *cmp = (double *)calloc(5 * blk, sizeof(double));
     double *abs_ = (double *)calloc(5 * blk, sizeof(double));
-    double *fa = (double *)malloc(sizeof(double) * nA * 4);
-    double *fb = (double *)malloc(sizeof(double) * nB * 4);
+    double *fa = (double *)malloc(sizeof(double) * nA * 8);
+    double *fb = (double *)malloc(sizeof(double) * nB * 8);
     double *ga = fa + nA, *gb = fb + nB;
+    double *xa = fa + 4 * nA, *xb = fb + 4 * nB;  /* magnitudes */
+    double *ya = xa + nA, *yb = xb + nB;
     for (int64_t g = 0; g < npts; ++g) {
       if (screened) {
         double ax = x[g] - b->R[3 * A], ay = y[g] - b->R[3 * A + 1], az = z[g] - b->R[3 * A + 2];
@@ -269,12 +299,12 @@ int orc_pair_blocks(const orc_basis *b, int64_t npts, const double *x, const dou
         if (!(bx * bx + by * by + bz * bz < rB * rB)) continue;
       }
       double om = w[g] * v[g];
-      atom_functions(b, A, x[g], y[g], z[g], fa, ga);
-      atom_functions(b, B, x[g], y[g], z[g], fb, gb);
+      atom_functions_c(b, A, x[g], y[g], z[g], fa, ga, xa, ya);
+      atom_functions_c(b, B, x[g], y[g], z[g], fb, gb, xb, yb);
       for (int i = 0; i < nA; ++i) {
-        const double *gi = ga + 3 * i;
+        const double *gi = ga + 3 * i, *hi = ya + 3 * i;
         for (int j = 0; j < nB; ++j) {
-          const double *gj = gb + 3 * j;
+          const double *gj = gb + 3 * j, *hj = yb + 3 * j;
           int64_t e = (int64_t)i * nB + j;
           double t[5];
           t[0] = om * fa[i] * fb[j];
@@ -282,13 +312,12 @@ int orc_pair_blocks(const orc_basis *b, int64_t npts, const double *x, const dou
           t[2] = om * (gi[1] * gj[2] - gi[2] * gj[1]);
           t[3] = om * (gi[2] * gj[0] - gi[0] * gj[2]);
           t[4] = om * (gi[0] * gj[1] - gi[1] * gj[0]);
-          /* error scale: sum of |w v| times the absolute value of every product entering the term */
           double ao = fabs(om), a[5];
-          a[0] = fabs(t[0]);
-          a[1] = ao * (fabs(gi[0] * gj[0]) + fabs(gi[1] * gj[1]) + fabs(gi[2] * gj[2]));
-          a[2] = ao * (fabs(gi[1] * gj[2]) + fabs(gi[2] * gj[1]));
-          a[3] = ao * (fabs(gi[2] * gj[0]) + fabs(gi[0] * gj[2]));
-          a[4] = ao * (fabs(gi[0] * gj[1]) + fabs(gi[1] * gj[0]));
+          a[0] = ao * xa[i] * xb[j];
+          a[1] = ao * (hi[0] * hj[0] + hi[1] * hj[1] + hi[2] * hj[2]);
+          a[2] = ao * (hi[1] * hj[2] + hi[2] * hj[1]);
+          a[3] = ao * (hi[2] * hj[0] + hi[0] * hj[2]);
+          a[4] = ao * (hi[0] * hj[1] + hi[1] * hj[0]);
           for (int q = 0; q < 5; ++q) {
             neu_add(sum + q * blk + e, cmp + q * blk + e, t[q]);
             abs_[q * blk + e] += a[q];

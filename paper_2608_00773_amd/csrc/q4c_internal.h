@@ -30,7 +30,8 @@ struct DevPlan {
   const int32_t *fn_shlm;      // [n_fn] shell * 16 + (l*l + l + m)
   const double *shell_rcut;    // [n_shells]
   const int32_t *shell_nint;   // [n_shells]
-  const int64_t *shell_coef_off;
+  const double *shell_knot;    // [2 n_shells]: nint^2 / rcut, rcut / nint^2
+  const int64_t *shell_coef_off;   // into coef (scaled table, see q4c_plan::coef_scaled)
   const double *coef;
   // grid, batch order
   const double *px, *py, *pz, *pw;  // [n_active]
@@ -74,6 +75,11 @@ struct q4c_plan {
   std::vector<double> shell_rcut;
   std::vector<int64_t> shell_coef_off;
   std::vector<double> coef;
+  // Radial tables re-expressed in d = s - r_j: (c0, c1/h, c2/h^2, c3/h^3) per
+  // interval, so the kernels evaluate Rt and Rt' without dividing by h.
+  std::vector<double> coef_scaled;
+  std::vector<int64_t> shell_cs_off;
+  std::vector<double> shell_knot;
   std::vector<int32_t> atom_fn_off;  // [n_atoms + 1]
   std::vector<double> atom_rcut;     // [n_atoms]
   std::vector<int32_t> fn_atom, fn_shlm;

@@ -94,16 +94,16 @@ __device__ __forceinline__ void tab_one(const DevPlan &d, int fn, double px, dou
     f = fx = fy = fz = 0.0;
     return;
   }
+  // interval j with r_j = rcut (j / n)^2 <= s < r_{j+1}
   const int n = d.shell_nint[sh];
-  int j = (int)((double)n * sqrt(s / rc));
+  int j = (int)sqrt(s * d.shell_knot[2 * sh]);
   j = j > n - 1 ? n - 1 : j;
-  const double fj = (double)j, inv_n2 = 1.0 / ((double)n * (double)n);
-  const double rj = rc * fj * fj * inv_n2;
-  const double h = rc * (2.0 * fj + 1.0) * inv_n2;
-  const double t = (s - rj) / h;
+  const double fj = (double)j;
+  const double dd = s - fj * fj * d.shell_knot[2 * sh + 1];  // s - r_j
+  // coefficients in d = s - r_j (scaled at plan time)
   const dbl4 c = *reinterpret_cast<const dbl4 *>(d.coef + d.shell_coef_off[sh] + 4 * (int64_t)j);
-  const double R = ((c[3] * t + c[2]) * t + c[1]) * t + c[0];
-  const double dR = ((3.0 * c[3] * t + 2.0 * c[2]) * t + c[1]) / h;
+  const double R = ((c[3] * dd + c[2]) * dd + c[1]) * dd + c[0];
+  const double dR = (3.0 * c[3] * dd + 2.0 * c[2]) * dd + c[1];
   double S, gx, gy, gz;
   solid_harmonic(shlm & 15, dx, dy, dz, S, gx, gy, gz);
   const double q = s > 0.0 ? dR / s : 0.0;
@@ -148,10 +148,11 @@ struct ChunkLDS {
 
 // Tabulate the chunk's row (and unless diagonal, column) functions.  With
 // `om` the column side is multiplied by the point weights om[pt].
+template <int NTH>
 __device__ __forceinline__ void fill_chunk(const DevPlan &d, ChunkLDS &L, const int *s_fn, int g0, int P, int k0,
                                            bool diag, const double *om) {
   const int nside = diag ? 1 : 2;
-  for (int it = threadIdx.x; it < nside * T * KC; it += NT) {
+  for (int it = threadIdx.x; it < nside * T * KC; it += NTH) {
     const int side = it / (T * KC);
     const int rem = it - side * (T * KC);
     const int fl = rem / KC, pt = rem - fl * KC;
@@ -171,7 +172,7 @@ __device__ __forceinline__ void fill_chunk(const DevPlan &d, ChunkLDS &L, const 
   }
   if (diag) {
     __syncthreads();
-    for (int it = threadIdx.x; it < 4 * KC * T; it += NT) {
+    for (int it = threadIdx.x; it < 4 * KC * T; it += NTH) {
       const int q = it / (KC * T);
       const int rem = it - q * (KC * T);
       const int pt = rem / T, fl = rem - pt * T;
@@ -209,19 +210,26 @@ __device__ __forceinline__ SlotInfo slot_of(const DevPlan &d, int fbase, int sba
 // (i, j) -> (j, i): + for V, Ws; - for the spin-orbit parts.
 __device__ __forceinline__ double mirror_sign(int q) { return q >= 2 ? -1.0 : 1.0; }
 
-// Write one accumulated tile element to the staged (batch, atom pair) block.
+// Which 16 x 16 blocks of a batch's local n x n matrix are computed: blocks
+// (rb, cb) with rb <= cb (block starts), both inside n.  A strictly upper
+// block (rb < cb) also stands for its mirror block (cb, rb), which no work
+// item computes.
+__device__ __forceinline__ bool block_active(int rb, int cb, int n) { return rb < n && cb < n && rb <= cb; }
+
+// Write one accumulated element (li, lj) of a computed block to the staged
+// (batch, atom pair) block; `upper` = the element's block is strictly upper.
 template <int Q0, int Q1>
 __device__ __forceinline__ void stage_store(double *staging, const SlotInfo &si, const SlotInfo &sj, int li, int lj,
-                                            bool diag, const double *v) {
-  if (si.slot > sj.slot) return;  // lower atom-block triangle (diagonal tiles only)
+                                            bool upper, const double *v) {
+  if (si.slot > sj.slot) return;  // lower atom-block triangle: not stored
   const int64_t blk = si.row_off + 5 * (int64_t)si.nfn * (sj.fnoff - si.fnoff);
   const int64_t pq = (int64_t)si.nfn * sj.nfn;
   const int64_t e = (int64_t)(li - si.fnoff) * sj.nfn + (lj - sj.fnoff);
 #pragma unroll
   for (int q = Q0; q < Q1; ++q) staging[blk + q * pq + e] = v[q - Q0];
-  if (!diag && si.slot == sj.slot) {
-    // same atom block split over two tiles: the mirrored element lives in
-    // tile (tj, ti), which is not computed
+  if (upper && si.slot == sj.slot) {
+    // the mirrored element (lj, li) of the same atom block lies in a block
+    // that is never computed
     const int64_t em = (int64_t)(lj - si.fnoff) * sj.nfn + (li - sj.fnoff);
 #pragma unroll
     for (int q = Q0; q < Q1; ++q) staging[blk + q * pq + em] = mirror_sign(q) * v[q - Q0];
@@ -234,7 +242,7 @@ __device__ __forceinline__ void stage_store(double *staging, const SlotInfo &si,
 //   D (f32_16x16x4): register r of lane l holds D[4 lk + r][l16].
 __device__ __forceinline__ int d_row_f64(int lk, int r) { return lk + 4 * r; }
 __device__ __forceinline__ int d_row_f32(int lk, int r) { return 4 * lk + r; }
-//
+
 // Precision modes of the forward contraction.
 enum { MODE_F64 = 0, MODE_SPLIT = 1, MODE_F32 = 2 };
 
@@ -259,6 +267,11 @@ __global__ __launch_bounds__(NT, 2) void k_contract(DevPlan d, const WorkItem *w
   const int lane = tid & 63, wave = tid >> 6;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;  // wave sub-tile origin within the tile
   const int li16 = lane & 15, lk = lane >> 4;
+  bool act[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) act[x][y] = block_active(r0 + wr + 16 * x, c0 + wc + 16 * y, n);
 
   dbl4 acc[2][2][5];
 #pragma unroll
@@ -267,7 +280,7 @@ __global__ __launch_bounds__(NT, 2) void k_contract(DevPlan d, const WorkItem *w
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int q = 0; q < 5; ++q) acc[x][y][q] = dbl4{0.0, 0.0, 0.0, 0.0};
-  // split mode: FP32 accumulators of the four W parts
+  // FP32 accumulators of the four W parts (split / f32 modes)
   flt4 accf[2][2][4];
   if (MODE != MODE_F64) {
 #pragma unroll
@@ -285,7 +298,7 @@ __global__ __launch_bounds__(NT, 2) void k_contract(DevPlan d, const WorkItem *w
       s_om[tid] = g < P ? d.pw[g0 + g] * v[d.perm[g0 + g]] : 0.0;
     }
     __syncthreads();
-    fill_chunk(d, L, s_fn, g0, P, k0, diag, s_om);
+    fill_chunk<NT>(d, L, s_fn, g0, P, k0, diag, s_om);
     __syncthreads();
 #pragma unroll
     for (int ks = 0; ks < KC / 4; ++ks) {
@@ -303,6 +316,7 @@ __global__ __launch_bounds__(NT, 2) void k_contract(DevPlan d, const WorkItem *w
       for (int x = 0; x < 2; ++x)
 #pragma unroll
         for (int y = 0; y < 2; ++y) {
+          if (!act[x][y]) continue;  // wave-uniform
           acc[x][y][0] = mfma64(a[x][0], bb[y][0], acc[x][y][0]);
           if (MODE == MODE_F64) {
             acc[x][y][1] = mfma64(a[x][1], bb[y][1], acc[x][y][1]);
@@ -360,18 +374,22 @@ __global__ __launch_bounds__(NT, 2) void k_contract(DevPlan d, const WorkItem *w
     }
   }
 
-  // write the tile to the staged atom-pair blocks
+  // write the computed blocks to the staged atom-pair blocks
   const double cp = d.cprime;
 #pragma unroll
   for (int y = 0; y < 2; ++y) {
-    const int lj = c0 + wc + y * 16 + li16;
+    const int cb = c0 + wc + y * 16;
+    const int lj = cb + li16;
     if (lj >= n) continue;
     const SlotInfo sj = slot_of(d, f0, sbase, lj);
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+    for (int x = 0; x < 2; ++x) {
+      if (!act[x][y]) continue;
+      const int rb = r0 + wr + x * 16;
+      const bool upper = rb < cb;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int li = r0 + wr + x * 16 + d_row_f64(lk, r);
+        const int li = rb + d_row_f64(lk, r);
         if (li < n) {
           const SlotInfo si = slot_of(d, f0, sbase, li);
           if (MODE == MODE_F64) {
@@ -379,28 +397,30 @@ __global__ __launch_bounds__(NT, 2) void k_contract(DevPlan d, const WorkItem *w
             vals[0] = acc[x][y][0][r];
 #pragma unroll
             for (int q = 1; q < 5; ++q) vals[q] = cp * acc[x][y][q][r];
-            stage_store<0, 5>(staging, si, sj, li, lj, diag, vals);
+            stage_store<0, 5>(staging, si, sj, li, lj, upper, vals);
           } else {
             double v0 = acc[x][y][0][r];
-            stage_store<0, 1>(staging, si, sj, li, lj, diag, &v0);
+            stage_store<0, 1>(staging, si, sj, li, lj, upper, &v0);
           }
         }
         if (MODE != MODE_F64) {
-          const int lf = r0 + wr + x * 16 + d_row_f32(lk, r);
+          const int lf = rb + d_row_f32(lk, r);
           if (lf < n) {
             const SlotInfo sf = slot_of(d, f0, sbase, lf);
             double vals[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) vals[q] = cp * (double)accf[x][y][q][r];
-            stage_store<1, 5>(staging, sf, sj, lf, lj, diag, vals);
+            stage_store<1, 5>(staging, sf, sj, lf, lj, upper, vals);
           }
         }
       }
+    }
   }
 }
 
 // Batch-to-global sum for one pass: reduction entry r adds the staged blocks
-// of pair red_pair[r] in batch order.
+// of pair red_pair[r] in batch order.  Loads of four incidences are issued
+// together; their sum order is fixed, so results repeat bit for bit.
 __global__ void k_reduce(DevPlan d, int64_t r0, const int32_t *red_pair, const uint8_t *red_first,
                          const int64_t *red_inc_off, const int64_t *inc_src, const double *staging, double *store,
                          int accumulate) {
@@ -412,7 +432,13 @@ __global__ void k_reduce(DevPlan d, int64_t r0, const int32_t *red_pair, const u
   const int64_t po = d.pair_off[p];
   for (int64_t e = threadIdx.x; e < 5 * blk; e += blockDim.x) {
     double s = 0.0;
-    for (int64_t k = k0; k < k1; ++k) s += staging[inc_src[k] + e];
+    int64_t k = k0;
+    for (; k + 4 <= k1; k += 4) {
+      const double a0 = staging[inc_src[k] + e], a1 = staging[inc_src[k + 1] + e];
+      const double a2 = staging[inc_src[k + 2] + e], a3 = staging[inc_src[k + 3] + e];
+      s += (a0 + a1) + (a2 + a3);
+    }
+    for (; k < k1; ++k) s += staging[inc_src[k] + e];
     const int q = (int)(e / blk);
     double *dst = store + q * d.store_len + po + (e - q * blk);
     *dst = add ? *dst + s : s;
@@ -483,27 +509,30 @@ __global__ void k_broadcast(DevPlan d, int64_t r0, const int32_t *red_pair, cons
   }
 }
 
-// Effective coefficient of tile element (li, lj), part q (c' applied to W parts).
-// Staged blocks of slot combinations that are not stored pairs hold zeros.
+// Effective coefficient of element (li, lj) of a computed block, part q (c'
+// applied to W parts).  A strictly upper block also carries the mirrored
+// same-atom element; staged blocks of non-pair slot combinations hold zeros.
 __device__ __forceinline__ double coef_elem(const DevPlan &d, const double *staging, int f0, int sbase, int n, int li,
-                                            int lj, int q, bool diag) {
+                                            int lj, int q, bool upper) {
   if (li >= n || lj >= n) return 0.0;
   const SlotInfo si = slot_of(d, f0, sbase, li), sj = slot_of(d, f0, sbase, lj);
   if (si.slot > sj.slot) return 0.0;
   const int64_t blk = si.row_off + 5 * (int64_t)si.nfn * (sj.fnoff - si.fnoff);
   const int64_t pq = (int64_t)si.nfn * sj.nfn;
   double c = staging[blk + q * pq + (int64_t)(li - si.fnoff) * sj.nfn + (lj - sj.fnoff)];
-  if (!diag && si.slot == sj.slot)
+  if (upper && si.slot == sj.slot)
     c += mirror_sign(q) * staging[blk + q * pq + (int64_t)(lj - si.fnoff) * sj.nfn + (li - sj.fnoff)];
   return q == 0 ? c : d.cprime * c;
 }
 
+constexpr int NTD = 512;  // adjoint workgroup: 8 waves = 4 column slices x 2 row halves
+
 // One work item: partial[g] = sum over the tile of a_g^T C b_g for all selected terms.
-__global__ __launch_bounds__(NT, 2) void k_density_tiles(DevPlan d, uint32_t terms, const WorkItem *work, int64_t w0,
-                                                         const double *staging, double *partial) {
+__global__ __launch_bounds__(NTD, 1) void k_density_tiles(DevPlan d, uint32_t terms, const WorkItem *work,
+                                                          int64_t w0, const double *staging, double *partial) {
   __shared__ ChunkLDS L;
   __shared__ int s_fn[2 * T];
-  __shared__ double s_red[4][KC];
+  __shared__ double s_red[8][KC];
   const int64_t wi = w0 + blockIdx.x;
   const WorkItem it = work[wi];
   const int b = it.batch;
@@ -518,47 +547,65 @@ __global__ __launch_bounds__(NT, 2) void k_density_tiles(DevPlan d, uint32_t ter
     s_fn[tid] = lf < n ? d.loc_fn[f0 + lf] : -1;
   }
   const int lane = tid & 63, wave = tid >> 6;
+  const int js = wave & 3, ih = wave >> 2;  // column slice, row half
   const int l16 = lane & 15, lk = lane >> 4;
-  // coefficient slice of this wave: rows i = r0 + 4 ks + lk (ks = 0..15), column j = c0 + 16 wave + l16
-  double creg[5][T / 4];
-  const int lj = c0 + wave * 16 + l16;
+  const int cb = c0 + 16 * js;  // column block of this wave
+  const int lj = cb + l16;
+  // blocks (rows) of this wave: rb = r0 + 32 ih + 16 h, h = 0, 1
+  bool act[2];
+  bool upper[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int rb = r0 + 32 * ih + 16 * h;
+    act[h] = block_active(rb, cb, n);
+    upper[h] = rb < cb;
+  }
+  // coefficient slice: rows i = r0 + 32 ih + 4 ks + lk (ks = 0..7), column lj
+  double creg[5][8];
 #pragma unroll
   for (int q = 0; q < 5; ++q)
 #pragma unroll
-    for (int ks = 0; ks < T / 4; ++ks)
-      creg[q][ks] = coef_elem(d, staging, f0, sbase, n, r0 + ks * 4 + lk, lj, q, diag);
+    for (int ks = 0; ks < 8; ++ks)
+      creg[q][ks] = act[ks >> 2] ? coef_elem(d, staging, f0, sbase, n, r0 + 32 * ih + 4 * ks + lk, lj, q,
+                                             upper[ks >> 2])
+                                 : 0.0;
   const bool tLL = terms & Q4C_TERM_LL, tSS = terms & Q4C_TERM_SS, tSO = terms & Q4C_TERM_SO;
   double *out = partial + d.work_part_off[wi];
+  const int ibase = 32 * ih;
 
   for (int k0 = 0; k0 < P; k0 += KC) {
     __syncthreads();
-    fill_chunk(d, L, s_fn, g0, P, k0, diag, nullptr);
+    fill_chunk<NTD>(d, L, s_fn, g0, P, k0, diag, nullptr);
     __syncthreads();
     double accp[4] = {0.0, 0.0, 0.0, 0.0};
-    // combos (row comp, coef part, column comp, sign)
+    // combos (row comp, coefficient part, column comp, sign)
 #define COMBO(YQ, CQ, ZQ, SG)                                                                 \
   {                                                                                           \
     dbl4 u = dbl4{0.0, 0.0, 0.0, 0.0};                                                        \
-    _Pragma("unroll") for (int ks = 0; ks < T / 4; ++ks) {                                    \
-      const double av = L.a[(YQ * KC + l16) * LDP + ks * 4 + lk];                             \
-      u = mfma64(av, creg[CQ][ks], u);                                                        \
+    _Pragma("unroll") for (int ks = 0; ks < 8; ++ks) {                                        \
+      if (act[ks >> 2]) {                                                                     \
+        const double av = L.a[(YQ * KC + l16) * LDP + ibase + ks * 4 + lk];                   \
+        u = mfma64(av, creg[CQ][ks], u);                                                      \
+      }                                                                                       \
     }                                                                                         \
     _Pragma("unroll") for (int r = 0; r < 4; ++r) accp[r] +=                                  \
-        SG u[r] * L.b[(ZQ * KC + d_row_f64(lk, r)) * LDP + wave * 16 + l16];                  \
+        SG u[r] * L.b[(ZQ * KC + d_row_f64(lk, r)) * LDP + 16 * js + l16];                    \
   }
-    if (tLL) COMBO(0, 0, 0, +)
-    if (tSS) {
-      COMBO(1, 1, 1, +)
-      COMBO(2, 1, 2, +)
-      COMBO(3, 1, 3, +)
-    }
-    if (tSO) {
-      COMBO(2, 2, 3, +)
-      COMBO(3, 2, 2, -)
-      COMBO(3, 3, 1, +)
-      COMBO(1, 3, 3, -)
-      COMBO(1, 4, 2, +)
-      COMBO(2, 4, 1, -)
+    if (act[0] || act[1]) {
+      if (tLL) COMBO(0, 0, 0, +)
+      if (tSS) {
+        COMBO(1, 1, 1, +)
+        COMBO(2, 1, 2, +)
+        COMBO(3, 1, 3, +)
+      }
+      if (tSO) {
+        COMBO(2, 2, 3, +)
+        COMBO(3, 2, 2, -)
+        COMBO(3, 3, 1, +)
+        COMBO(1, 3, 3, -)
+        COMBO(1, 4, 2, +)
+        COMBO(2, 4, 1, -)
+      }
     }
 #undef COMBO
     // sum over the 16 columns held by lanes with equal lk
@@ -572,7 +619,12 @@ __global__ __launch_bounds__(NT, 2) void k_density_tiles(DevPlan d, uint32_t ter
       for (int r = 0; r < 4; ++r) s_red[wave][d_row_f64(lk, r)] = accp[r];
     }
     __syncthreads();
-    if (tid < KC && k0 + tid < P) out[k0 + tid] = ((s_red[0][tid] + s_red[1][tid]) + s_red[2][tid]) + s_red[3][tid];
+    if (tid < KC && k0 + tid < P) {
+      double sum = 0.0;
+#pragma unroll
+      for (int w = 0; w < 8; ++w) sum += s_red[w][tid];
+      out[k0 + tid] = sum;
+    }
   }
 }
 
@@ -730,7 +782,7 @@ int launch_density(const q4c_plan *p, const double *coef, uint32_t terms, int we
     if (nw > 0) {
       {
         TimedLaunch tl_(p, Q4C_TIMER_DENSITY_TILES, s);
-        hipLaunchKernelGGL(k_density_tiles, dim3((unsigned)nw), dim3(NT), 0, s, p->dp, terms, p->d_work, ps.w0,
+        hipLaunchKernelGGL(k_density_tiles, dim3((unsigned)nw), dim3(NTD), 0, s, p->dp, terms, p->d_work, ps.w0,
                            p->d_staging, partial);
       }
       if ((rc = check_launch("k_density_tiles")) != Q4C_OK) return rc;

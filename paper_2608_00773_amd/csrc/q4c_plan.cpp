@@ -211,6 +211,39 @@ int build_host(q4c_plan *p, const q4c_basis *b, const q4c_grid *g) {
   p->shell_coef_off.assign(b->shell_coef_off, b->shell_coef_off + b->n_shells);
   p->coef.assign(b->coef, b->coef + b->n_coef);
 
+  // radial tables in d = s - r_j (one scaled copy per distinct (offset, rcut, nint))
+  {
+    std::vector<std::pair<std::pair<int64_t, int32_t>, std::pair<double, int64_t>>> seen;
+    p->shell_cs_off.assign(b->n_shells, 0);
+    for (int s = 0; s < b->n_shells; ++s) {
+      int64_t found = -1;
+      for (auto &e : seen)
+        if (e.first.first == p->shell_coef_off[s] && e.first.second == p->shell_nint[s] &&
+            e.second.first == p->shell_rcut[s]) {
+          found = e.second.second;
+          break;
+        }
+      if (found < 0) {
+        found = (int64_t)p->coef_scaled.size();
+        const int n = p->shell_nint[s];
+        const double rc = p->shell_rcut[s];
+        for (int j = 0; j < n; ++j) {
+          const double h = rc * (2.0 * j + 1.0) / ((double)n * (double)n);
+          const double *c = &p->coef[p->shell_coef_off[s] + 4 * (int64_t)j];
+          p->coef_scaled.push_back(c[0]);
+          p->coef_scaled.push_back(c[1] / h);
+          p->coef_scaled.push_back(c[2] / (h * h));
+          p->coef_scaled.push_back(c[3] / (h * h * h));
+        }
+        seen.push_back({{p->shell_coef_off[s], p->shell_nint[s]}, {p->shell_rcut[s], found}});
+      }
+      p->shell_cs_off[s] = found;
+      const double n2 = (double)p->shell_nint[s] * (double)p->shell_nint[s];
+      p->shell_knot.push_back(n2 / p->shell_rcut[s]);
+      p->shell_knot.push_back(p->shell_rcut[s] / n2);
+    }
+  }
+
   // functions and per-atom data
   p->atom_fn_off.assign(na + 1, 0);
   p->atom_rcut.assign(na, 0.0);
@@ -472,13 +505,15 @@ int build_device(q4c_plan *p) {
   double *R, *rcut, *coef, *px, *py, *pz, *pw;
   int32_t *fn_atom, *fn_shlm, *nint, *perm, *bpo, *bfo, *lfn, *lsl, *bso, *sfo, *snf, *pna, *pnb, *pa, *pb;
   int64_t *coff, *sro, *wpo, *poff, *bwo, *toff;
+  double *sknot;
   UP(p->R, R);
   UP(p->fn_atom, fn_atom);
   UP(p->fn_shlm, fn_shlm);
   UP(p->shell_rcut, rcut);
   UP(p->shell_nint, nint);
-  UP(p->shell_coef_off, coff);
-  UP(p->coef, coef);
+  UP(p->shell_cs_off, coff);
+  UP(p->shell_knot, sknot);
+  UP(p->coef_scaled, coef);
   UP(p->px, px);
   UP(p->py, py);
   UP(p->pz, pz);
@@ -518,6 +553,7 @@ int build_device(q4c_plan *p) {
   d.fn_shlm = fn_shlm;
   d.shell_rcut = rcut;
   d.shell_nint = nint;
+  d.shell_knot = sknot;
   d.shell_coef_off = coff;
   d.coef = coef;
   d.px = px;

@@ -52,16 +52,19 @@ def small(q):
 
 
 def _compare_f64(got_blocks, ref, scale, tol=FP64_REL):
-    worst = 0.0
-    for g, r, s in zip(got_blocks, ref, scale):
+    worst, where = 0.0, None
+    for p, (g, r, s) in enumerate(zip(got_blocks, ref, scale)):
         # elements whose terms are all exact zeros must come out exactly zero
         err = np.abs(g - r)
         ok_zero = np.all(err[s == 0] == 0)
         assert ok_zero
         nz = s > 0
         if np.any(nz):
-            worst = max(worst, float(np.max(err[nz] / s[nz])))
-    assert worst <= tol, worst
+            rel = np.where(nz, err / np.where(nz, s, 1.0), 0.0)
+            k = np.unravel_index(np.argmax(rel), rel.shape)
+            if rel[k] > worst:
+                worst, where = float(rel[k]), (p, k, float(g[k]), float(r[k]), float(s[k]), float(np.max(s[k[0]])))
+    assert worst <= tol, (worst, where)
     return worst
 
 
@@ -271,3 +274,68 @@ def test_coef_from_spinor_matches_oracle(q, small):
     torch.cuda.synchronize()
     ref = blocks_to_store(oracle.coef_from_spinor_density(pairs, D), po)
     assert np.max(np.abs(out.cpu().numpy() - ref)) <= 1e-15 * np.max(np.abs(ref))
+
+
+# ---------------------------------------------------------------------------
+# Multi-tile case: 24 atoms in a 9 angstrom cube, 119..372 functions per batch
+# (up to 6 x 6 tiles of 64), so off-diagonal tiles and atom blocks split over
+# tiles are exercised; also run with small batches and a tiny staging budget
+# (many passes).
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def medium(q):
+    wl = W.config_cluster(n_atoms=24, nrad=24, nang=50, box_ang=9.0, k=7)
+    pairs = W.atom_pairs(wl)
+    ref, scale = oracle.pair_blocks(wl, pairs, with_abs=True)
+    return wl, pairs, ref, scale
+
+
+@pytest.mark.parametrize("p_max,staging", [(300, 0), (64, 1 << 20)])
+def test_integrate_f64_multitile(q, medium, p_max, staging):
+    wl, pairs, ref, scale = medium
+    plan, store, spin_w, _ = _run(q, wl, p_max=p_max, staging_bytes=staging)
+    if staging:
+        assert plan.info["n_passes"] > 1
+    assert plan.info["max_batch_fn"] > 2 * 64
+    _, po = plan.pairs()
+    nfn = wl.atom_nfn()
+    got = store_to_blocks(store, pairs, po, nfn)
+    _compare_f64(got, ref, scale)
+    gw = spinor_to_blocks(spin_w, pairs, po, nfn)
+    for p in range(len(pairs)):
+        assert np.array_equal(gw[p], oracle.spinor_W(got[p]))
+
+
+@pytest.mark.xfail(reason="FP32 accumulation within a batch leaves ~2e-8 Ha on the largest W elements of this "
+                          "dense case; FP64 routing of the large-term chunks is not built yet", strict=False)
+def test_integrate_split_multitile(q, medium):
+    wl, pairs, ref, scale = medium
+    for prec in (1, 2):
+        plan, store, _, _ = _run(q, wl, precision=prec, assemble=False)
+        _, po = plan.pairs()
+        got = store_to_blocks(store, pairs, po, wl.atom_nfn())
+        err = max(float(np.max(np.abs(g[k] - r[k]))) for g, r in zip(got, ref) for k in range(1, 5))
+        assert err <= SPLIT_ABS, (prec, err)
+        _compare_f64([g[:1] for g in got], [r[:1] for r in ref], [s[:1] for s in scale])
+
+
+def test_density_multitile(q, medium):
+    torch = _torch()
+    wl, pairs, _, _ = medium
+    nfn = wl.atom_nfn()
+    rng = np.random.default_rng(79)
+    coef_blocks = [rng.standard_normal((5, nfn[a], nfn[b])) for a, b in pairs]
+    idx = np.sort(rng.choice(wl.n_points, size=1500, replace=False))
+    ref = oracle.density(wl, pairs, coef_blocks, idx=idx, weight_mode=1)
+    from helpers import blocks_to_store
+    for p_max, staging in ((300, 0), (64, 1 << 20)):
+        plan = q.Plan(wl, p_max=p_max, staging_bytes=staging)
+        _, po = plan.pairs()
+        coef = torch.from_numpy(blocks_to_store(coef_blocks, po)).cuda()
+        out = torch.full((wl.n_points,), float("nan"), dtype=torch.float64, device="cuda")
+        q.density_on_grid(plan, coef, q.TERM_ALL, 1, out)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        assert np.all(np.isfinite(got))
+        assert np.max(np.abs(got[idx] - ref)) <= 1e-12 * np.max(np.abs(ref)), (p_max, staging)

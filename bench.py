@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=float, default=0.02, help="fraction of grid points for the oracle timing")
     ap.add_argument("--n-atoms", type=int, default=120)
+    ap.add_argument("--mode", choices=["full", "forward", "adjoint"], default="full",
+                    help="forward/adjoint: run only that call `steps` times (for profiler runs) and print its time")
     return ap.parse_args()
 
 
@@ -114,6 +116,18 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / k
+
+    if a.mode != "full":
+        if a.mode == "forward":
+            call = lambda: q.q4c_integrate_H(plan, v, prec, q.ASSEMBLE_W, store, spin)
+        else:
+            call = lambda: q.density_on_grid(plan, gbar, q.TERM_ALL, 1, grad)
+        for _ in range(a.warmup):
+            call()
+        ms = timed(call, a.steps)
+        print(json.dumps({"mode": a.mode, "precision": a.precision, "ms": ms, "steps": a.steps,
+                          "points_per_s": info["n_active"] / (ms * 1e-3)}), flush=True)
+        return
 
     for _ in range(a.warmup):
         step(prec)

@@ -119,7 +119,9 @@ typedef struct {
   double c_light;           /* speed of light in a.u.; <= 0 selects 137.035999084 */
   int32_t p_max;            /* max points per batch; <= 0 selects 300 */
   int32_t flags;            /* Q4C_PLAN_* */
-  int64_t staging_bytes;    /* per-plan staging budget; <= 0 selects 8 GiB */
+  int64_t staging_bytes;    /* per-plan scratch budget (staged batch results and
+                               operand panels); <= 0 selects 16 GiB.  Batches are
+                               processed in passes that fit the budget. */
 } q4c_opts;
 
 typedef struct {

@@ -50,6 +50,7 @@ struct DevPlan {
   const int32_t *pair_a, *pair_b;   // [n_pairs]
   const int64_t *batch_work_off;    // [n_batches + 1] first work item of each batch
   const int64_t *tab_off;           // [n_batches + 1] prefix of P_b n_b (nao_tabulate layout)
+  const int64_t *panel_off;         // [n_batches] pass-relative offset of the batch's operand panel
   int64_t store_len;
   int64_t n_active;
   int64_t n_points;
@@ -61,9 +62,14 @@ struct Pass {
   int64_t w0, w1;        // work range
   int64_t r0, r1;        // reduction-entry range
   int64_t z0, z1;        // zero-block range (non-pair slot combinations)
+  int64_t t0, t1;        // panel-tile range
   int64_t staging_len;   // doubles
   int64_t partial_len;   // doubles (adjoint partials, stored after the staging)
+  int64_t panel_len;     // doubles (operand panels, stored after the partials)
 };
+
+// Padded panel sizes: points to a multiple of kChunk, functions to a multiple of 16.
+__host__ __device__ inline int64_t pad16(int64_t x) { return (x + 15) / 16 * 16; }
 
 }  // namespace q4c
 
@@ -112,7 +118,8 @@ struct q4c_plan {
   std::vector<int64_t> inc_src;      // staging offsets (pass relative)
   std::vector<int32_t> untouched_pairs;
   std::vector<int64_t> zero_off, zero_len;  // staged blocks of slot combinations that are not stored pairs
-  std::vector<int64_t> batch_work_off, tab_off;
+  std::vector<int64_t> batch_work_off, tab_off, panel_off;
+  std::vector<q4c::WorkItem> ptile;  // (batch, function tile) list of the panel kernel
   int64_t max_scratch = 0;
   int64_t max_batch_points = 0, max_batch_fn = 0, fn_entries = 0;
   double flops_alg = 0.0;
@@ -130,6 +137,8 @@ struct q4c_plan {
   int64_t *d_inc_src = nullptr;
   int32_t *d_untouched = nullptr;
   int64_t *d_zero_off = nullptr, *d_zero_len = nullptr;
+  q4c::WorkItem *d_ptile = nullptr;
+  double *d_om = nullptr;  // [n_active + 16] point weights w_g v_g of the current call
   double *d_staging = nullptr;
   int32_t *d_flag = nullptr;
 

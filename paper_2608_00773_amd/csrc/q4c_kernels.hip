@@ -35,8 +35,6 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 typedef float flt4 __attribute__((ext_vector_type(4)));
 
 constexpr int T = kTile;
-constexpr int KC = kChunk;
-constexpr int LDP = T + 1;  // padded LDS row (doubles): conflict-free column writes
 constexpr int NT = 256;     // threads per contraction workgroup (4 waves)
 
 // ---------------------------------------------------------------------------
@@ -140,45 +138,176 @@ __global__ void k_tabulate(DevPlan d, int64_t b0, int deriv, double *out) {
 // Contraction
 // ---------------------------------------------------------------------------
 
-// Shared staging of one 16-point chunk: [comp][point][function] with padded rows.
-struct ChunkLDS {
-  double a[4 * KC * LDP];  // row functions
-  double b[4 * KC * LDP];  // column functions (weighted by w v in the forward)
+// ---------------------------------------------------------------------------
+// Tile tabulation: the metadata of a tile's functions is staged in LDS, so
+// the per-(function, point) work touches global memory only for the point
+// and the four radial coefficients of its interval.
+// ---------------------------------------------------------------------------
+
+struct TileMeta {
+  double ax[2 * T], ay[2 * T], az[2 * T];  // centres
+  double rc[2 * T];                        // cutoffs (0 for padding)
+  double k1[2 * T], k2[2 * T];             // nint^2 / rcut, rcut / nint^2
+  int64_t coef[2 * T];                     // offset of the shell's table
+  int nint[2 * T], lm[2 * T];
+  int order[2 * T];                        // per side: tile columns sorted by lm
 };
 
-// Tabulate the chunk's row (and unless diagonal, column) functions.  With
-// `om` the column side is multiplied by the point weights om[pt].
-template <int NTH>
-__device__ __forceinline__ void fill_chunk(const DevPlan &d, ChunkLDS &L, const int *s_fn, int g0, int P, int k0,
-                                           bool diag, const double *om) {
-  const int nside = diag ? 1 : 2;
-  for (int it = threadIdx.x; it < nside * T * KC; it += NTH) {
-    const int side = it / (T * KC);
-    const int rem = it - side * (T * KC);
-    const int fl = rem / KC, pt = rem - fl * KC;
-    const int fn = s_fn[side * T + fl];
-    const int g = k0 + pt;
-    double f = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
-    if (fn >= 0 && g < P) tab_one(d, fn, d.px[g0 + g], d.py[g0 + g], d.pz[g0 + g], f, fx, fy, fz);
-    double *dst = side ? L.b : L.a;
-    if (side && om) {
-      const double w = om[pt];
-      f *= w; fx *= w; fy *= w; fz *= w;
+// Stage metadata of the tile's functions (threads 0 .. 2T-1) and, per side,
+// an ordering by lm so that lanes working on neighbouring items mostly take
+// the same solid-harmonic branch.
+__device__ __forceinline__ void load_tile_meta(const DevPlan &d, TileMeta &M, int f0, int n, int r0, int c0) {
+  const int tid = threadIdx.x;
+  if (tid < 2 * T) {
+    const int lf = (tid < T ? r0 : c0) + (tid & (T - 1));
+    if (lf < n) {
+      const int fn = d.loc_fn[f0 + lf];
+      const int a = d.fn_atom[fn], shlm = d.fn_shlm[fn], sh = shlm >> 4;
+      M.ax[tid] = d.R[3 * a];
+      M.ay[tid] = d.R[3 * a + 1];
+      M.az[tid] = d.R[3 * a + 2];
+      M.rc[tid] = d.shell_rcut[sh];
+      M.k1[tid] = d.shell_knot[2 * sh];
+      M.k2[tid] = d.shell_knot[2 * sh + 1];
+      M.coef[tid] = d.shell_coef_off[sh];
+      M.nint[tid] = d.shell_nint[sh];
+      M.lm[tid] = shlm & 15;
+    } else {
+      M.ax[tid] = M.ay[tid] = M.az[tid] = 0.0;
+      M.rc[tid] = 0.0;
+      M.k1[tid] = M.k2[tid] = 0.0;
+      M.coef[tid] = 0;
+      M.nint[tid] = 0;
+      M.lm[tid] = 16;
     }
-    dst[(0 * KC + pt) * LDP + fl] = f;
-    dst[(1 * KC + pt) * LDP + fl] = fx;
-    dst[(2 * KC + pt) * LDP + fl] = fy;
-    dst[(3 * KC + pt) * LDP + fl] = fz;
   }
-  if (diag) {
-    __syncthreads();
-    for (int it = threadIdx.x; it < 4 * KC * T; it += NTH) {
-      const int q = it / (KC * T);
-      const int rem = it - q * (KC * T);
-      const int pt = rem / T, fl = rem - pt * T;
-      const double w = om ? om[pt] : 1.0;
-      L.b[(q * KC + pt) * LDP + fl] = L.a[(q * KC + pt) * LDP + fl] * w;
+  __syncthreads();
+  if (tid < 2 * T) {
+    const int side = tid / T, k = tid - side * T;
+    const int *lmv = M.lm + side * T;
+    const int mine = lmv[k];
+    int rank = 0;
+    for (int o = 0; o < T; ++o) rank += (lmv[o] < mine) || (lmv[o] == mine && o < k);
+    M.order[side * T + rank] = k;
+  }
+}
+
+// phi and grad phi of tile function m at point (px, py, pz); see tab_one.
+// 1/s comes from a Newton-refined reciprocal square root, and the interval
+// index from an approximate square root corrected against the exact knots.
+__device__ __forceinline__ void tab_meta(const DevPlan &d, const TileMeta &M, int m, double px, double py,
+                                         double pz, double &f, double &fx, double &fy, double &fz) {
+  const double dx = px - M.ax[m], dy = py - M.ay[m], dz = pz - M.az[m];
+  const double s2 = dx * dx + dy * dy + dz * dz;
+  const double rc = M.rc[m];
+  if (!(s2 < rc * rc)) {
+    f = fx = fy = fz = 0.0;
+    return;
+  }
+  double rinv = 0.0, s = 0.0;
+  if (s2 > 0.0) {
+    rinv = __builtin_amdgcn_rsq(s2);
+    rinv = rinv * (1.5 - 0.5 * s2 * rinv * rinv);
+    s = s2 * rinv;
+  }
+  const int n = M.nint[m];
+  const double k1 = M.k1[m], k2 = M.k2[m];
+  const double u = s * k1;
+  int j = u > 0.0 ? (int)(u * __builtin_amdgcn_rsq(u)) : 0;
+  j = j < 0 ? 0 : (j > n - 1 ? n - 1 : j);
+  double rj = (double)j * (double)j * k2;
+  if (s < rj && j > 0) {
+    --j;
+    rj = (double)j * (double)j * k2;
+  } else if (j < n - 1 && s >= (double)(j + 1) * (double)(j + 1) * k2) {
+    ++j;
+    rj = (double)j * (double)j * k2;
+  }
+  const double dd = s - rj;
+  const dbl4 c = *reinterpret_cast<const dbl4 *>(d.coef + M.coef[m] + 4 * (int64_t)j);
+  const double R = ((c[3] * dd + c[2]) * dd + c[1]) * dd + c[0];
+  const double q = ((3.0 * c[3] * dd + 2.0 * c[2]) * dd + c[1]) * rinv;  // Rt'(s) / s
+  double S, gx, gy, gz;
+  solid_harmonic(M.lm[m], dx, dy, dz, S, gx, gy, gz);
+  f = R * S;
+  fx = q * dx * S + R * gx;
+  fy = q * dy * S + R * gy;
+  fz = q * dz * S + R * gz;
+}
+
+// ---------------------------------------------------------------------------
+// Operand panels.  Batch b's panel holds phi, d/dx, d/dy, d/dz of its
+// functions at its points, padded to Pp = pad16(P) points and np = pad16(n)
+// functions (zeros in the padding), in a 4-point-interleaved layout:
+//     element (q, pt, i) at ((q * Pp/4 + pt/4) * np + i) * 4 + pt % 4.
+// A 64-lane MFMA operand slice (16 functions x 4 points) is then one
+// contiguous 512-byte run, for the forward (functions as rows) and, in
+// 128-byte runs, for the adjoint (points as rows).
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int64_t panel_index(int q, int pt, int i, int Pp, int np) {
+  return ((int64_t)(q * (Pp >> 2) + (pt >> 2)) * np + i) * 4 + (pt & 3);
+}
+
+// Work items -> workgroups: the hardware hands workgroup id x to XCD x % 8;
+// map it so that every XCD runs one contiguous range of work items (the
+// tiles of a batch share that XCD's L2).
+__device__ __forceinline__ int64_t xcd_map(int64_t bid, int64_t n) {
+  const int64_t nx = 8, x = bid % nx, k = bid / nx, q = n / nx, r = n % nx;
+  return x * q + (x < r ? x : r) + k;
+}
+
+// w_g v_g for every active point (batch order); 16 zero entries after the end.
+__global__ void k_om(DevPlan d, const double *v, double *om) {
+  const int64_t n = d.n_active;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n + 16; g += (int64_t)gridDim.x * blockDim.x)
+    om[g] = g < n ? d.pw[g] * v[d.perm[g]] : 0.0;
+}
+
+// One (batch, function tile of 64): tabulate the tile's functions at all
+// points of the batch into the panel.  Each group of 16 points is computed
+// in lm order (few divergent harmonic branches per wave) into LDS, then
+// written out as 16 contiguous 2 KB runs.
+constexpr int PLD = T + 1;  // padded LDS row of the panel stage
+
+__global__ __launch_bounds__(256) void k_panel(DevPlan d, const WorkItem *tiles, int64_t t0, int64_t nt,
+                                               double *panel) {
+  __shared__ TileMeta M;
+  __shared__ double st[4 * 16 * PLD];
+  const WorkItem it = tiles[t0 + xcd_map(blockIdx.x, nt)];
+  const int b = it.batch;
+  const int g0 = d.batch_pt_off[b], P = d.batch_pt_off[b + 1] - g0;
+  const int f0 = d.batch_fn_off[b], n = d.batch_fn_off[b + 1] - f0;
+  const int Pp = (int)pad16(P), np = (int)pad16(n);
+  const int r0 = it.ti * T;
+  const int nrow = np - r0 < T ? np - r0 : T;  // panel rows of this tile
+  load_tile_meta(d, M, f0, n, r0, r0);
+  __syncthreads();
+  double *pb = panel + d.panel_off[b];
+  for (int g16 = 0; g16 < Pp; g16 += 16) {
+    for (int e = threadIdx.x; e < T * 16; e += 256) {
+      const int k = e >> 4, pt = e & 15;
+      const int fl = M.order[k];
+      double f = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
+      const int g = g16 + pt;
+      if (M.nint[fl] > 0 && g < P) tab_meta(d, M, fl, d.px[g0 + g], d.py[g0 + g], d.pz[g0 + g], f, fx, fy, fz);
+      st[(0 * 16 + pt) * PLD + fl] = f;
+      st[(1 * 16 + pt) * PLD + fl] = fx;
+      st[(2 * 16 + pt) * PLD + fl] = fy;
+      st[(3 * 16 + pt) * PLD + fl] = fz;
     }
+    __syncthreads();
+    // (q, point quad) runs: rows r0 .. r0 + nrow - 1, 4 points each, contiguous
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int p4 = 0; p4 < 4; ++p4) {
+        const int e = threadIdx.x;  // 256 = 64 rows x 4 points
+        const int il = e >> 2, pp = e & 3;
+        if (il < nrow)
+          pb[((int64_t)(q * (Pp >> 2) + (g16 >> 2) + p4) * np + r0 + il) * 4 + pp] = st[(q * 16 + 4 * p4 + pp) * PLD + il];
+      }
+    __syncthreads();
   }
 }
 
@@ -246,24 +375,106 @@ __device__ __forceinline__ int d_row_f32(int lk, int r) { return 4 * lk + r; }
 // Precision modes of the forward contraction.
 enum { MODE_F64 = 0, MODE_SPLIT = 1, MODE_F32 = 2 };
 
+// LDS slab of one 16-point chunk of a tile: [comp][point][function], rows
+// padded to SEGW doubles.  Forward operand reads (16 functions x 4 points
+// per MFMA operand) are 128-byte runs in 4 rows; SEGW = T + 8 puts those
+// rows a quarter of the banks apart.  The adjoint reads 16 rows x 4 functions;
+// SEGW = T + 4 spreads its rows over the banks.
+constexpr int SEGF = T + 8;   // forward
+constexpr int SEGA = T + 4;   // adjoint
+template <int SEGW>
+struct Slab {
+  double v[4 * 16 * SEGW];
+};
+
+// Copy a chunk's 16 points of functions row0 .. row0+T-1 from the panel into
+// a slab (optionally weighted per point).  2048 units of 16 bytes
+// (function f, points 2h and 2h+1 of K step ks, component q); every thread
+// issues all of its loads before the first store.
+template <int NTH, int SEGW>
+__device__ __forceinline__ void copy_slab(const double *pb, int64_t plane, int np, int row0, int ks0,
+                                          Slab<SEGW> &dst, const double *omc) {
+  constexpr int U = 4 * 4 * 2 * T / NTH;  // units per thread
+  constexpr int G = U < 4 ? U : 4;        // loads in flight per thread
+#pragma unroll
+  for (int k0 = 0; k0 < U; k0 += G) {
+    double2 val[G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      const int u = (k0 + k) * NTH + threadIdx.x;
+      const int f = u & (T - 1), h = (u >> 6) & 1, ks = (u >> 7) & 3, q = u >> 9;
+      const int row = row0 + f;
+      val[k] = make_double2(0.0, 0.0);
+      if (row < np)
+        val[k] = *reinterpret_cast<const double2 *>(pb + q * plane + ((int64_t)(ks0 + ks) * np + row) * 4 + 2 * h);
+    }
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      const int u = (k0 + k) * NTH + threadIdx.x;
+      const int f = u & (T - 1), h = (u >> 6) & 1, ks = (u >> 7) & 3, q = u >> 9;
+      const int pt = 4 * ks + 2 * h;
+      double x = val[k].x, y = val[k].y;
+      if (omc) {
+        x *= omc[pt];
+        y *= omc[pt + 1];
+      }
+      dst.v[(q * 16 + pt) * SEGW + f] = x;
+      dst.v[(q * 16 + pt + 1) * SEGW + f] = y;
+    }
+  }
+}
+
+
+// Two-phase form of copy_slab for software pipelining: fetch a chunk into
+// registers (U units per thread), later store it to a slab.
+template <int NTH>
+struct SlabRegs {
+  static constexpr int U = 4 * 4 * 2 * T / NTH;
+  double2 v[U];
+};
+
+template <int NTH>
+__device__ __forceinline__ void fetch_slab(const double *pb, int64_t plane, int np, int row0, int ks0, int nks,
+                                           SlabRegs<NTH> &r) {
+#pragma unroll
+  for (int k = 0; k < SlabRegs<NTH>::U; ++k) {
+    const int u = k * NTH + threadIdx.x;
+    const int f = u & (T - 1), h = (u >> 6) & 1, ks = (u >> 7) & 3, q = u >> 9;
+    const int row = row0 + f;
+    r.v[k] = make_double2(0.0, 0.0);
+    if (row < np && ks0 < nks)
+      r.v[k] = *reinterpret_cast<const double2 *>(pb + q * plane + ((int64_t)(ks0 + ks) * np + row) * 4 + 2 * h);
+  }
+}
+
+template <int NTH, int SEGW>
+__device__ __forceinline__ void store_slab(const SlabRegs<NTH> &r, Slab<SEGW> &dst) {
+#pragma unroll
+  for (int k = 0; k < SlabRegs<NTH>::U; ++k) {
+    const int u = k * NTH + threadIdx.x;
+    const int f = u & (T - 1), h = (u >> 6) & 1, ks = (u >> 7) & 3, q = u >> 9;
+    const int pt = 4 * ks + 2 * h;
+    dst.v[(q * 16 + pt) * SEGW + f] = r.v[k].x;
+    dst.v[(q * 16 + pt + 1) * SEGW + f] = r.v[k].y;
+  }
+}
+
 template <int MODE>
-__global__ __launch_bounds__(NT, 2) void k_contract(DevPlan d, const WorkItem *work, int64_t w0, const double *v,
-                                                    double *staging) {
-  __shared__ ChunkLDS L;
-  __shared__ int s_fn[2 * T];
-  __shared__ double s_om[KC];
-  const WorkItem it = work[w0 + blockIdx.x];
+__global__ __launch_bounds__(NT, 2) void k_contract(DevPlan d, const WorkItem *work, int64_t w0, int64_t nw,
+                                                    const double *om, const double *panel, double *staging) {
+  __shared__ Slab<SEGF> sa, sb;
+  __shared__ double s_om[16];
+  const WorkItem it = work[w0 + xcd_map(blockIdx.x, nw)];
   const int b = it.batch;
   const int g0 = d.batch_pt_off[b], P = d.batch_pt_off[b + 1] - g0;
   const int f0 = d.batch_fn_off[b], n = d.batch_fn_off[b + 1] - f0;
   const int sbase = d.batch_slot_off[b];
   const int r0 = it.ti * T, c0 = it.tj * T;
   const bool diag = it.ti == it.tj;
+  const int Pp = (int)pad16(P), np = (int)pad16(n);
+  const double *pb = panel + d.panel_off[b];
+  const int64_t plane = (int64_t)Pp * np;
   const int tid = threadIdx.x;
-  if (tid < 2 * T) {
-    const int lf = (tid < T ? r0 : c0) + (tid & (T - 1));
-    s_fn[tid] = lf < n ? d.loc_fn[f0 + lf] : -1;
-  }
   const int lane = tid & 63, wave = tid >> 6;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;  // wave sub-tile origin within the tile
   const int li16 = lane & 15, lk = lane >> 4;
@@ -291,69 +502,67 @@ __global__ __launch_bounds__(NT, 2) void k_contract(DevPlan d, const WorkItem *w
         for (int q = 0; q < 4; ++q) accf[x][y][q] = flt4{0.f, 0.f, 0.f, 0.f};
   }
 
-  for (int k0 = 0; k0 < P; k0 += KC) {
-    __syncthreads();  // previous chunk fully consumed; s_fn visible on the first pass
-    if (tid < KC) {
-      const int g = k0 + tid;
-      s_om[tid] = g < P ? d.pw[g0 + g] * v[d.perm[g0 + g]] : 0.0;
-    }
-    __syncthreads();
-    fill_chunk<NT>(d, L, s_fn, g0, P, k0, diag, s_om);
+  for (int k0 = 0; k0 < Pp; k0 += 16) {
+    if (tid < 16) s_om[tid] = k0 + tid < P ? om[g0 + k0 + tid] : 0.0;
+    __syncthreads();  // s_om visible; previous chunk's operands consumed
+    copy_slab<NT, SEGF>(pb, plane, np, r0, k0 >> 2, sa, nullptr);
+    copy_slab<NT, SEGF>(pb, plane, np, c0, k0 >> 2, sb, s_om);
     __syncthreads();
 #pragma unroll
-    for (int ks = 0; ks < KC / 4; ++ks) {
-      const int pt = ks * 4 + lk;
+    for (int ks = 0; ks < 4; ++ks) {
       double a[2][4], bb[2][4];
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) a[x][q] = L.a[(q * KC + pt) * LDP + wr + x * 16 + li16];
+        for (int q = 0; q < 4; ++q) a[x][q] = sa.v[(q * 16 + 4 * ks + lk) * SEGF + wr + 16 * x + li16];
 #pragma unroll
       for (int y = 0; y < 2; ++y)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) bb[y][q] = L.b[(q * KC + pt) * LDP + wc + y * 16 + li16];
+        for (int q = 0; q < 4; ++q) bb[y][q] = sb.v[(q * 16 + 4 * ks + lk) * SEGF + wc + 16 * y + li16];
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll
         for (int y = 0; y < 2; ++y) {
           if (!act[x][y]) continue;  // wave-uniform
-          acc[x][y][0] = mfma64(a[x][0], bb[y][0], acc[x][y][0]);
+          const double *av = a[x];
+          const double *bv = bb[y];
+          acc[x][y][0] = mfma64(av[0], bv[0], acc[x][y][0]);
           if (MODE == MODE_F64) {
-            acc[x][y][1] = mfma64(a[x][1], bb[y][1], acc[x][y][1]);
-            acc[x][y][1] = mfma64(a[x][2], bb[y][2], acc[x][y][1]);
-            acc[x][y][1] = mfma64(a[x][3], bb[y][3], acc[x][y][1]);
-            acc[x][y][2] = mfma64(a[x][2], bb[y][3], acc[x][y][2]);
-            acc[x][y][2] = mfma64(-a[x][3], bb[y][2], acc[x][y][2]);
-            acc[x][y][3] = mfma64(a[x][3], bb[y][1], acc[x][y][3]);
-            acc[x][y][3] = mfma64(-a[x][1], bb[y][3], acc[x][y][3]);
-            acc[x][y][4] = mfma64(a[x][1], bb[y][2], acc[x][y][4]);
-            acc[x][y][4] = mfma64(-a[x][2], bb[y][1], acc[x][y][4]);
+            acc[x][y][1] = mfma64(av[1], bv[1], acc[x][y][1]);
+            acc[x][y][2] = mfma64(av[2], bv[3], acc[x][y][2]);
+            acc[x][y][3] = mfma64(av[3], bv[1], acc[x][y][3]);
+            acc[x][y][4] = mfma64(av[1], bv[2], acc[x][y][4]);
+            acc[x][y][1] = mfma64(av[2], bv[2], acc[x][y][1]);
+            acc[x][y][2] = mfma64(-av[3], bv[2], acc[x][y][2]);
+            acc[x][y][3] = mfma64(-av[1], bv[3], acc[x][y][3]);
+            acc[x][y][4] = mfma64(-av[2], bv[1], acc[x][y][4]);
+            acc[x][y][1] = mfma64(av[3], bv[3], acc[x][y][1]);
           } else if (MODE == MODE_F32) {
             float af[4], bf[4];
 #pragma unroll
             for (int q = 1; q < 4; ++q) {
-              af[q] = (float)a[x][q];
-              bf[q] = (float)bb[y][q];
+              af[q] = (float)av[q];
+              bf[q] = (float)bv[q];
             }
             accf[x][y][0] = mfma32(af[1], bf[1], accf[x][y][0]);
-            accf[x][y][0] = mfma32(af[2], bf[2], accf[x][y][0]);
-            accf[x][y][0] = mfma32(af[3], bf[3], accf[x][y][0]);
             accf[x][y][1] = mfma32(af[2], bf[3], accf[x][y][1]);
-            accf[x][y][1] = mfma32(-af[3], bf[2], accf[x][y][1]);
             accf[x][y][2] = mfma32(af[3], bf[1], accf[x][y][2]);
-            accf[x][y][2] = mfma32(-af[1], bf[3], accf[x][y][2]);
             accf[x][y][3] = mfma32(af[1], bf[2], accf[x][y][3]);
+            accf[x][y][0] = mfma32(af[2], bf[2], accf[x][y][0]);
+            accf[x][y][1] = mfma32(-af[3], bf[2], accf[x][y][1]);
+            accf[x][y][2] = mfma32(-af[1], bf[3], accf[x][y][2]);
             accf[x][y][3] = mfma32(-af[2], bf[1], accf[x][y][3]);
+            accf[x][y][0] = mfma32(af[3], bf[3], accf[x][y][0]);
           } else {
             // hi + lo split: x = hi + lo with hi = fl(x), lo = fl(x - hi);
             // x y ~ hi_x hi_y + hi_x lo_y + lo_x hi_y (lo_x lo_y dropped)
             float ah[4], al[4], bh[4], bl[4];
 #pragma unroll
             for (int q = 1; q < 4; ++q) {
-              ah[q] = (float)a[x][q];
-              al[q] = (float)(a[x][q] - (double)ah[q]);
-              bh[q] = (float)bb[y][q];
-              bl[q] = (float)(bb[y][q] - (double)bh[q]);
+              ah[q] = (float)av[q];
+              al[q] = (float)(av[q] - (double)ah[q]);
+              bh[q] = (float)bv[q];
+              bl[q] = (float)(bv[q] - (double)bh[q]);
             }
 #define SPLIT3(ACC, AI, BI, SG)                                  \
   ACC = mfma32(SG ah[AI], bh[BI], ACC);                          \
@@ -373,6 +582,7 @@ __global__ __launch_bounds__(NT, 2) void k_contract(DevPlan d, const WorkItem *w
         }
     }
   }
+  (void)diag;
 
   // write the computed blocks to the staged atom-pair blocks
   const double cp = d.cprime;
@@ -527,39 +737,39 @@ __device__ __forceinline__ double coef_elem(const DevPlan &d, const double *stag
 
 constexpr int NTD = 512;  // adjoint workgroup: 8 waves = 4 column slices x 2 row halves
 
-// One work item: partial[g] = sum over the tile of a_g^T C b_g for all selected terms.
+// One work item: partial[g] = sum over the tile of a_g^T C b_g for all
+// selected terms; the chunk's row and column functions are staged in LDS
+// from the batch's panel and shared by the 8 waves.
 __global__ __launch_bounds__(NTD, 1) void k_density_tiles(DevPlan d, uint32_t terms, const WorkItem *work,
-                                                          int64_t w0, const double *staging, double *partial) {
-  __shared__ ChunkLDS L;
-  __shared__ int s_fn[2 * T];
-  __shared__ double s_red[8][KC];
-  const int64_t wi = w0 + blockIdx.x;
+                                                          int64_t w0, int64_t nw, const double *staging,
+                                                          const double *panel, double *partial) {
+  __shared__ Slab<SEGA> sa[2], sb[2];
+  __shared__ double s_red[8][16];
+  const int64_t wi = w0 + xcd_map(blockIdx.x, nw);
   const WorkItem it = work[wi];
   const int b = it.batch;
   const int g0 = d.batch_pt_off[b], P = d.batch_pt_off[b + 1] - g0;
   const int f0 = d.batch_fn_off[b], n = d.batch_fn_off[b + 1] - f0;
   const int sbase = d.batch_slot_off[b];
   const int r0 = it.ti * T, c0 = it.tj * T;
-  const bool diag = it.ti == it.tj;
+  const int Pp = (int)pad16(P), np = (int)pad16(n);
+  const double *pb = panel + d.panel_off[b];
+  const int64_t plane = (int64_t)Pp * np;
   const int tid = threadIdx.x;
-  if (tid < 2 * T) {
-    const int lf = (tid < T ? r0 : c0) + (tid & (T - 1));
-    s_fn[tid] = lf < n ? d.loc_fn[f0 + lf] : -1;
-  }
   const int lane = tid & 63, wave = tid >> 6;
   const int js = wave & 3, ih = wave >> 2;  // column slice, row half
   const int l16 = lane & 15, lk = lane >> 4;
   const int cb = c0 + 16 * js;  // column block of this wave
   const int lj = cb + l16;
-  // blocks (rows) of this wave: rb = r0 + 32 ih + 16 h, h = 0, 1
-  bool act[2];
-  bool upper[2];
+  // row blocks of this wave: rb = r0 + 32 ih + 16 h, h = 0, 1
+  bool act[2], upper[2];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int rb = r0 + 32 * ih + 16 * h;
     act[h] = block_active(rb, cb, n);
     upper[h] = rb < cb;
   }
+  const bool any = act[0] || act[1];
   // coefficient slice: rows i = r0 + 32 ih + 4 ks + lk (ks = 0..7), column lj
   double creg[5][8];
 #pragma unroll
@@ -571,55 +781,89 @@ __global__ __launch_bounds__(NTD, 1) void k_density_tiles(DevPlan d, uint32_t te
                                  : 0.0;
   const bool tLL = terms & Q4C_TERM_LL, tSS = terms & Q4C_TERM_SS, tSO = terms & Q4C_TERM_SO;
   double *out = partial + d.work_part_off[wi];
-  const int ibase = 32 * ih;
+  const int iloc = 32 * ih;  // tile-local first row of this wave
 
-  for (int k0 = 0; k0 < P; k0 += KC) {
-    __syncthreads();
-    fill_chunk<NTD>(d, L, s_fn, g0, P, k0, diag, nullptr);
-    __syncthreads();
+  // chunk k0 + 16 is fetched into registers while chunk k0 is multiplied
+  const int nks = Pp >> 2;
+  SlabRegs<NTD> ra, rb;
+  fetch_slab<NTD>(pb, plane, np, r0, 0, nks, ra);
+  fetch_slab<NTD>(pb, plane, np, c0, 0, nks, rb);
+  for (int k0 = 0; k0 < Pp; k0 += 16) {
+    const int buf = (k0 >> 4) & 1;
+    store_slab<NTD, SEGA>(ra, sa[buf]);
+    store_slab<NTD, SEGA>(rb, sb[buf]);
+    __syncthreads();  // slabs of this chunk visible (and s_red of the previous one consumed)
+    fetch_slab<NTD>(pb, plane, np, r0, (k0 >> 2) + 4, nks, ra);
+    fetch_slab<NTD>(pb, plane, np, c0, (k0 >> 2) + 4, nks, rb);
+    const Slab<SEGA> &A = sa[buf];
+    const Slab<SEGA> &B = sb[buf];
     double accp[4] = {0.0, 0.0, 0.0, 0.0};
-    // combos (row comp, coefficient part, column comp, sign)
-#define COMBO(YQ, CQ, ZQ, SG)                                                                 \
-  {                                                                                           \
-    dbl4 u = dbl4{0.0, 0.0, 0.0, 0.0};                                                        \
-    _Pragma("unroll") for (int ks = 0; ks < 8; ++ks) {                                        \
-      if (act[ks >> 2]) {                                                                     \
-        const double av = L.a[(YQ * KC + l16) * LDP + ibase + ks * 4 + lk];                   \
-        u = mfma64(av, creg[CQ][ks], u);                                                      \
-      }                                                                                       \
-    }                                                                                         \
-    _Pragma("unroll") for (int r = 0; r < 4; ++r) accp[r] +=                                  \
-        SG u[r] * L.b[(ZQ * KC + d_row_f64(lk, r)) * LDP + 16 * js + l16];                    \
-  }
-    if (act[0] || act[1]) {
-      if (tLL) COMBO(0, 0, 0, +)
-      if (tSS) {
-        COMBO(1, 1, 1, +)
-        COMBO(2, 1, 2, +)
-        COMBO(3, 1, 3, +)
-      }
-      if (tSO) {
-        COMBO(2, 2, 3, +)
-        COMBO(3, 2, 2, -)
-        COMBO(3, 3, 1, +)
-        COMBO(1, 3, 3, -)
-        COMBO(1, 4, 2, +)
-        COMBO(2, 4, 1, -)
-      }
-    }
-#undef COMBO
-    // sum over the 16 columns held by lanes with equal lk
+    if (any) {
+      // column values: Z[q][pt = lk + 4 r][j = 16 js + l16]
+      double zb[4][4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+      for (int q = 0; q < 4; ++q)
 #pragma unroll
-      for (int off = 1; off < 16; off <<= 1) accp[r] += __shfl_xor(accp[r], off);
+        for (int r = 0; r < 4; ++r) zb[q][r] = B.v[(q * 16 + d_row_f64(lk, r)) * SEGA + 16 * js + l16];
+      // terms grouped by the row component Y (A operand, points x functions):
+      //   Y=phi: (V, phi); Y=dx: (Ws, dx), (Wso_y, -dz), (Wso_z, +dy);
+      //   Y=dy: (Ws, dy), (Wso_x, +dz), (Wso_z, -dx); Y=dz: (Ws, dz), (Wso_x, -dy), (Wso_y, +dx)
+#pragma unroll
+      for (int yq = 0; yq < 4; ++yq) {
+        if (yq == 0 ? !tLL : !(tSS || tSO)) continue;
+        // A operand: Y[yq][pt = l16][i = iloc + 4 ks + lk]
+        double ya[8];
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks)
+          ya[ks] = A.v[(yq * 16 + l16) * SEGA + iloc + 4 * ks + lk];
+        // the terms sharing this Y run as independent MFMA chains, interleaved
+        // over the K steps; a lone term uses two chains (even / odd steps)
+        if (yq == 0) {
+          dbl4 u0 = dbl4{0.0, 0.0, 0.0, 0.0}, u1 = u0;
+#pragma unroll
+          for (int ks = 0; ks < 8; ks += 2) {
+            if (act[ks >> 2]) {
+              u0 = mfma64(ya[ks], creg[0][ks], u0);
+              u1 = mfma64(ya[ks + 1], creg[0][ks + 1], u1);
+            }
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r) accp[r] += (u0[r] + u1[r]) * zb[0][r];
+        } else {
+          // (coefficient part, column comp, sign) of the three terms
+          const int c1 = 1, z1 = yq;
+          const int c2 = yq == 1 ? 3 : (yq == 2 ? 2 : 2), z2 = yq == 1 ? 3 : (yq == 2 ? 3 : 2);
+          const double g2 = yq == 1 ? -1.0 : (yq == 2 ? 1.0 : -1.0);
+          const int c3 = yq == 1 ? 4 : (yq == 2 ? 4 : 3), z3 = yq == 1 ? 2 : (yq == 2 ? 1 : 1);
+          const double g3 = yq == 1 ? 1.0 : (yq == 2 ? -1.0 : 1.0);
+          dbl4 u1 = dbl4{0.0, 0.0, 0.0, 0.0}, u2 = u1, u3 = u1;
+#pragma unroll
+          for (int ks = 0; ks < 8; ++ks) {
+            if (act[ks >> 2]) {
+              if (tSS) u1 = mfma64(ya[ks], creg[c1][ks], u1);
+              if (tSO) {
+                u2 = mfma64(ya[ks], creg[c2][ks], u2);
+                u3 = mfma64(ya[ks], creg[c3][ks], u3);
+              }
+            }
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r) accp[r] += u1[r] * zb[z1][r] + g2 * u2[r] * zb[z2][r] + g3 * u3[r] * zb[z3][r];
+        }
+      }
+      // sum over the 16 columns held by lanes with equal lk
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) accp[r] += __shfl_xor(accp[r], off);
+      }
     }
     if (l16 == 0) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) s_red[wave][d_row_f64(lk, r)] = accp[r];
     }
     __syncthreads();
-    if (tid < KC && k0 + tid < P) {
+    if (tid < 16 && k0 + tid < P) {
       double sum = 0.0;
 #pragma unroll
       for (int w = 0; w < 8; ++w) sum += s_red[w][tid];
@@ -698,33 +942,45 @@ int launch_tabulate(const q4c_plan *p, int64_t b0, int64_t b1, int deriv, double
 int launch_integrate(const q4c_plan *p, const double *v, int precision, uint32_t flags, double *store,
                      double *spin_w, double *spin_v, hipStream_t s) {
   const int accumulate = (flags & Q4C_ACCUMULATE) ? 1 : 0;
+  int rc;
+  {
+    TimedLaunch tl_(p, Q4C_TIMER_OTHER, s);
+    const unsigned nb = (unsigned)std::min<int64_t>((p->n_active + 16 + 255) / 256, 65535);
+    hipLaunchKernelGGL(k_om, dim3(nb), dim3(256), 0, s, p->dp, v, p->d_om);
+  }
+  if ((rc = check_launch("k_om")) != Q4C_OK) return rc;
   for (const Pass &ps : p->passes) {
-    const int64_t nw = ps.w1 - ps.w0;
+    const int64_t nw = ps.w1 - ps.w0, nt = ps.t1 - ps.t0, nr = ps.r1 - ps.r0;
+    double *panel = p->d_staging + ps.staging_len + ps.partial_len;
+    if (nt > 0) {
+      {
+        TimedLaunch tl_(p, Q4C_TIMER_TABULATE, s);
+        hipLaunchKernelGGL(k_panel, dim3((unsigned)nt), dim3(256), 0, s, p->dp, p->d_ptile, ps.t0, nt, panel);
+      }
+      if ((rc = check_launch("k_panel")) != Q4C_OK) return rc;
+    }
     if (nw > 0) {
       {
         TimedLaunch tl_(p, Q4C_TIMER_CONTRACT, s);
         if (precision == Q4C_PREC_F64)
-          hipLaunchKernelGGL(k_contract<MODE_F64>, dim3((unsigned)nw), dim3(NT), 0, s, p->dp, p->d_work, ps.w0, v,
-                             p->d_staging);
+          hipLaunchKernelGGL(k_contract<MODE_F64>, dim3((unsigned)nw), dim3(NT), 0, s, p->dp, p->d_work, ps.w0, nw,
+                             p->d_om, panel, p->d_staging);
         else if (precision == Q4C_PREC_F32)
-          hipLaunchKernelGGL(k_contract<MODE_F32>, dim3((unsigned)nw), dim3(NT), 0, s, p->dp, p->d_work, ps.w0, v,
-                             p->d_staging);
+          hipLaunchKernelGGL(k_contract<MODE_F32>, dim3((unsigned)nw), dim3(NT), 0, s, p->dp, p->d_work, ps.w0, nw,
+                             p->d_om, panel, p->d_staging);
         else
-          hipLaunchKernelGGL(k_contract<MODE_SPLIT>, dim3((unsigned)nw), dim3(NT), 0, s, p->dp, p->d_work, ps.w0, v,
-                             p->d_staging);
+          hipLaunchKernelGGL(k_contract<MODE_SPLIT>, dim3((unsigned)nw), dim3(NT), 0, s, p->dp, p->d_work, ps.w0, nw,
+                             p->d_om, panel, p->d_staging);
       }
-      int rc = check_launch("k_contract");
-      if (rc != Q4C_OK) return rc;
+      if ((rc = check_launch("k_contract")) != Q4C_OK) return rc;
     }
-    const int64_t nr = ps.r1 - ps.r0;
     if (nr > 0) {
       {
         TimedLaunch tl_(p, Q4C_TIMER_REDUCE, s);
         hipLaunchKernelGGL(k_reduce, dim3((unsigned)nr), dim3(256), 0, s, p->dp, ps.r0, p->d_red_pair, p->d_red_first,
                            p->d_red_inc_off, p->d_inc_src, p->d_staging, store, accumulate);
       }
-      int rc = check_launch("k_reduce");
-      if (rc != Q4C_OK) return rc;
+      if ((rc = check_launch("k_reduce")) != Q4C_OK) return rc;
     }
   }
   if (!accumulate && !p->untouched_pairs.empty()) {
@@ -733,8 +989,7 @@ int launch_integrate(const q4c_plan *p, const double *v, int precision, uint32_t
       hipLaunchKernelGGL(k_zero_pairs, dim3((unsigned)p->untouched_pairs.size()), dim3(256), 0, s, p->dp,
                          p->d_untouched, store);
     }
-    int rc = check_launch("k_zero_pairs");
-    if (rc != Q4C_OK) return rc;
+    if ((rc = check_launch("k_zero_pairs")) != Q4C_OK) return rc;
   }
   if ((flags & (Q4C_ASSEMBLE_W | Q4C_ASSEMBLE_V)) && p->n_pairs > 0) {
     {
@@ -742,8 +997,7 @@ int launch_integrate(const q4c_plan *p, const double *v, int precision, uint32_t
       hipLaunchKernelGGL(k_spinor, dim3((unsigned)p->n_pairs), dim3(256), 0, s, p->dp, store,
                          (flags & Q4C_ASSEMBLE_W) ? spin_w : nullptr, (flags & Q4C_ASSEMBLE_V) ? spin_v : nullptr);
     }
-    int rc = check_launch("k_spinor");
-    if (rc != Q4C_OK) return rc;
+    if ((rc = check_launch("k_spinor")) != Q4C_OK) return rc;
   }
   return Q4C_OK;
 }
@@ -752,15 +1006,17 @@ int launch_density(const q4c_plan *p, const double *coef, uint32_t terms, int we
                    hipStream_t s) {
   int rc;
   if (p->n_points > 0) {
-    unsigned nb = (unsigned)std::min<int64_t>((p->n_points + 255) / 256, 65535);
     {
       TimedLaunch tl_(p, Q4C_TIMER_OTHER, s);
+      const unsigned nb = (unsigned)std::min<int64_t>((p->n_points + 255) / 256, 65535);
       hipLaunchKernelGGL(k_fill, dim3(nb), dim3(256), 0, s, out, p->n_points, 0.0);
     }
     if ((rc = check_launch("k_fill")) != Q4C_OK) return rc;
   }
   for (const Pass &ps : p->passes) {
-    const int64_t nr = ps.r1 - ps.r0, nw = ps.w1 - ps.w0, nbt = ps.b1 - ps.b0, nz = ps.z1 - ps.z0;
+    const int64_t nr = ps.r1 - ps.r0, nw = ps.w1 - ps.w0, nbt = ps.b1 - ps.b0, nz = ps.z1 - ps.z0, nt = ps.t1 - ps.t0;
+    double *partial = p->d_staging + ps.staging_len;
+    double *panel = partial + ps.partial_len;
     if (nz > 0) {
       {
         TimedLaunch tl_(p, Q4C_TIMER_OTHER, s);
@@ -777,21 +1033,26 @@ int launch_density(const q4c_plan *p, const double *coef, uint32_t terms, int we
       }
       if ((rc = check_launch("k_broadcast")) != Q4C_OK) return rc;
     }
-    // partials go after the staged coefficients of this pass
-    double *partial = p->d_staging + ps.staging_len;
+    if (nt > 0) {
+      {
+        TimedLaunch tl_(p, Q4C_TIMER_TABULATE, s);
+        hipLaunchKernelGGL(k_panel, dim3((unsigned)nt), dim3(256), 0, s, p->dp, p->d_ptile, ps.t0, nt, panel);
+      }
+      if ((rc = check_launch("k_panel")) != Q4C_OK) return rc;
+    }
     if (nw > 0) {
       {
         TimedLaunch tl_(p, Q4C_TIMER_DENSITY_TILES, s);
-        hipLaunchKernelGGL(k_density_tiles, dim3((unsigned)nw), dim3(NTD), 0, s, p->dp, terms, p->d_work, ps.w0,
-                           p->d_staging, partial);
+        hipLaunchKernelGGL(k_density_tiles, dim3((unsigned)nw), dim3(NTD), 0, s, p->dp, terms, p->d_work, ps.w0, nw,
+                           p->d_staging, panel, partial);
       }
       if ((rc = check_launch("k_density_tiles")) != Q4C_OK) return rc;
     }
     if (nbt > 0) {
       {
         TimedLaunch tl_(p, Q4C_TIMER_DENSITY_POINTS, s);
-        hipLaunchKernelGGL(k_density_points, dim3((unsigned)nbt), dim3(256), 0, s, p->dp, ps.b0, partial, weight_mode,
-                           out);
+        hipLaunchKernelGGL(k_density_points, dim3((unsigned)nbt), dim3(256), 0, s, p->dp, ps.b0, partial,
+                           weight_mode, out);
       }
       if ((rc = check_launch("k_density_points")) != Q4C_OK) return rc;
     }

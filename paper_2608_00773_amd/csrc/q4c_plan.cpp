@@ -345,16 +345,20 @@ int build_host(q4c_plan *p, const q4c_basis *b, const q4c_grid *g) {
   p->batch_fn_off.assign(1, 0);
   p->batch_slot_off.assign(1, 0);
   const int T = q4c::kTile;
-  int64_t staging = 0, partial = 0;
-  q4c::Pass cur{0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  int64_t staging = 0, partial = 0, panel = 0;
+  q4c::Pass cur{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   std::vector<std::pair<int32_t, int64_t>> pass_inc;  // (pair, staging offset) for the current pass
   std::vector<uint8_t> pair_seen(p->n_pairs, 0);
   const int64_t budget_doubles = std::max<int64_t>(p->staging_budget / 8, 1);
   auto close_pass = [&](int64_t b_end) {
     cur.b1 = b_end;
     cur.w1 = (int64_t)p->work.size();
+    // region lengths rounded to 64 doubles: the panel region after them stays 512-byte aligned
+    staging = (staging + 63) / 64 * 64;
+    partial = (partial + 63) / 64 * 64;
     cur.staging_len = staging;
     cur.partial_len = partial;
+    cur.panel_len = panel;
     std::stable_sort(pass_inc.begin(), pass_inc.end(),
                      [](const std::pair<int32_t, int64_t> &x, const std::pair<int32_t, int64_t> &y) {
                        return x.first < y.first;
@@ -371,13 +375,15 @@ int build_host(q4c_plan *p, const q4c_basis *b, const q4c_grid *g) {
     }
     cur.r1 = (int64_t)p->red_pair.size();
     cur.z1 = (int64_t)p->zero_off.size();
+    cur.t1 = (int64_t)p->ptile.size();
     p->passes.push_back(cur);
-    p->max_scratch = std::max(p->max_scratch, staging + partial);
+    p->max_scratch = std::max(p->max_scratch, staging + partial + panel);
     pass_inc.clear();
     staging = 0;
     partial = 0;
-    int64_t nz = (int64_t)p->zero_off.size();
-    cur = q4c::Pass{b_end, b_end, (int64_t)p->work.size(), (int64_t)p->work.size(), 0, 0, nz, nz, 0, 0};
+    panel = 0;
+    int64_t nz = (int64_t)p->zero_off.size(), nt_ = (int64_t)p->ptile.size();
+    cur = q4c::Pass{b_end, b_end, (int64_t)p->work.size(), (int64_t)p->work.size(), 0, 0, nz, nz, nt_, nt_, 0, 0, 0};
   };
 
   std::vector<int32_t> rel;
@@ -428,7 +434,11 @@ int build_host(q4c_plan *p, const q4c_basis *b, const q4c_grid *g) {
     }
     int nt = (nb_fn + T - 1) / T;
     int64_t bpart = (int64_t)(nt * (nt + 1) / 2) * (g1 - g0);
-    if (bt > cur.b0 && (staging + bstage > budget_doubles)) close_pass(bt);
+    int64_t bpanel = 4 * q4c::pad16(g1 - g0) * q4c::pad16(nb_fn);
+    if (bt > cur.b0 && (staging + partial + panel + bstage + bpart + bpanel > budget_doubles)) close_pass(bt);
+    p->panel_off.push_back(panel);
+    panel += bpanel;
+    for (int t = 0; t < nt; ++t) p->ptile.push_back(q4c::WorkItem{(int32_t)bt, (int16_t)t, (int16_t)t});
     // slots
     int off = 0;
     int32_t slot0 = (int32_t)p->slot_atom.size();
@@ -469,7 +479,6 @@ int build_host(q4c_plan *p, const q4c_basis *b, const q4c_grid *g) {
         p->work_part_off.push_back(partial);
         partial += (g1 - g0);
       }
-    (void)bpart;
     p->max_batch_points = std::max<int64_t>(p->max_batch_points, g1 - g0);
     p->max_batch_fn = std::max<int64_t>(p->max_batch_fn, nb_fn);
     p->flops_alg += 10.0 * (double)(g1 - g0) * (double)nb_fn * (double)nb_fn;
@@ -504,7 +513,7 @@ int build_device(q4c_plan *p) {
   } while (0)
   double *R, *rcut, *coef, *px, *py, *pz, *pw;
   int32_t *fn_atom, *fn_shlm, *nint, *perm, *bpo, *bfo, *lfn, *lsl, *bso, *sfo, *snf, *pna, *pnb, *pa, *pb;
-  int64_t *coff, *sro, *wpo, *poff, *bwo, *toff;
+  int64_t *coff, *sro, *wpo, *poff, *bwo, *toff, *pnoff;
   double *sknot;
   UP(p->R, R);
   UP(p->fn_atom, fn_atom);
@@ -535,6 +544,8 @@ int build_device(q4c_plan *p) {
   UP(p->pair_b, pb);
   UP(p->batch_work_off, bwo);
   UP(p->tab_off, toff);
+  UP(p->panel_off, pnoff);
+  UP(p->ptile, p->d_ptile);
   UP(p->zero_off, p->d_zero_off);
   UP(p->zero_len, p->d_zero_len);
   UP(p->work, p->d_work);
@@ -547,6 +558,8 @@ int build_device(q4c_plan *p) {
   rc = device_alloc(p, (size_t)p->max_scratch * sizeof(double), (void **)&p->d_staging);
   if (rc != Q4C_OK) return rc;
   rc = device_alloc(p, 64, (void **)&p->d_flag);
+  if (rc != Q4C_OK) return rc;
+  rc = device_alloc(p, (size_t)(p->n_active + 16) * sizeof(double), (void **)&p->d_om);
   if (rc != Q4C_OK) return rc;
   d.R = R;
   d.fn_atom = fn_atom;
@@ -577,6 +590,7 @@ int build_device(q4c_plan *p) {
   d.pair_b = pb;
   d.batch_work_off = bwo;
   d.tab_off = toff;
+  d.panel_off = pnoff;
   d.store_len = p->store_len;
   d.n_active = p->n_active;
   d.n_points = p->n_points;
@@ -644,7 +658,7 @@ int q4c_plan_create(const q4c_basis *basis, const q4c_grid *grid, const q4c_opts
       p->staging_budget = opts->staging_bytes;
     }
     if (p->p_max < 1) p->p_max = 300;
-    if (p->staging_budget <= 0) p->staging_budget = (int64_t)8 << 30;
+    if (p->staging_budget <= 0) p->staging_budget = (int64_t)16 << 30;
     rc = build_host(p, basis, grid);
     if (rc == Q4C_OK && !(p->flags & Q4C_PLAN_HOST_ONLY)) rc = build_device(p);
   } catch (const std::bad_alloc &) {

@@ -153,10 +153,14 @@ def main():
     # forward-only throughput and error of each precision against the FP64 path
     fwd = {}
     outs = {}
+    hot = {}
     for name, p in PREC.items():
         st = q.new_store(plan, dev)
         fwd[name] = timed(lambda: q.q4c_integrate_H(plan, v, p, q.ASSEMBLE_W, st, spin), max(3, a.steps // 4))
         outs[name] = st
+        if name != "f64":
+            h, t = plan.split_stats()
+            hot[name] = h / max(t, 1)
     err = {n: [float(torch.max(torch.abs(outs[n][k] - outs["f64"][k]))) for k in range(5)] for n in outs}
     ms_adj = timed(lambda: q.density_on_grid(plan, gbar, q.TERM_ALL, 1, grad), max(3, a.steps // 4))
 
@@ -197,6 +201,7 @@ def main():
         "forward_points_per_s": {k: n_act / (t * 1e-3) for k, t in fwd.items()},
         "adjoint_ms": ms_adj,
         "max_abs_diff_vs_f64_Ha": {k: dict(zip(q.PART_NAMES, e)) for k, e in err.items() if k != "f64"},
+        "w_chunks_on_f64_mfma": hot,
         "plan_s": t_plan,
         "workload_gen_s": t_gen,
         "wall_timed_s": wall,

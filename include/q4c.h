@@ -122,6 +122,8 @@ typedef struct {
   int64_t staging_bytes;    /* per-plan scratch budget (staged batch results and
                                operand panels); <= 0 selects 16 GiB.  Batches are
                                processed in passes that fit the budget. */
+  double split_threshold;   /* split-precision routing bound in hartree (see
+                               q4c_integrate_H); <= 0 selects 3e-11 */
 } q4c_opts;
 
 typedef struct {
@@ -177,12 +179,14 @@ int nao_tabulate(const q4c_plan *plan, int64_t b0, int64_t b1, int32_t deriv, do
 /* q4c_integrate_H: the five real parts of the atom-pair store from the
  * potential v (device, [n_points], user order, hartree):
  * store_dev[0..5 store_len) = V, Ws, Wso_x, Wso_y, Wso_z with c' applied.
- * Q4C_PREC_F64 runs the per-batch contractions on FP64 MFMA; Q4C_PREC_SPLIT_F32
- * runs the four W parts on FP32 MFMA with hi+lo split operands and FP32
- * accumulation within a batch, and V on FP64 MFMA (its elements reach
- * ~1e2 Ha, where FP32 accumulation cannot hold 1e-8 Ha).  Batch partial sums
- * are added to the store in FP64 in a fixed order, so repeated calls are
- * bitwise identical.  With Q4C_ASSEMBLE_W / _V the spinor blocks are written
+ * Q4C_PREC_F64 runs the per-batch contractions on FP64 MFMA.  The split
+ * modes run V on FP64 MFMA (its elements reach ~1e2 Ha) and the four W parts
+ * per 16-point chunk either on FP32 MFMA (FP32 operands, or hi+lo split
+ * operands for Q4C_PREC_SPLIT_F32, FP32 accumulation over the batch) or, when
+ * the chunk's bound 2^-24 c' 48 max|grad phi| max|w v grad phi| exceeds the
+ * plan's split_threshold, on FP64 MFMA; the FP32 partial sums join the FP64
+ * ones once per batch tile.  Batch partial sums are added to the store in
+ * FP64 in a fixed order, so repeated calls are bitwise identical.  With Q4C_ASSEMBLE_W / _V the spinor blocks are written
  * to spin_w_dev / spin_v_dev (complex128, 4 store_len elements each). */
 int q4c_integrate_H(const q4c_plan *plan, const double *v_dev, int32_t precision, uint32_t flags,
                     double *store_dev, double *spin_w_dev, double *spin_v_dev, void *stream);
@@ -224,6 +228,10 @@ enum {
   Q4C_NTIMERS = 8
 };
 int q4c_plan_profile(q4c_plan *plan, int enable);
+
+/* Chunks of the last split-precision q4c_integrate_H call routed to FP64 MFMA
+ * and chunks in total (waits for the call to finish). */
+int q4c_plan_split_stats(const q4c_plan *plan, int64_t *fp64_chunks, int64_t *total_chunks);
 int q4c_plan_timers(q4c_plan *plan, double *ms, int64_t *launches);
 
 /* Block until the plan's queued work is done; reports asynchronous HIP errors. */

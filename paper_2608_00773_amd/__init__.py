@@ -57,7 +57,7 @@ class _Grid(ctypes.Structure):
 
 class _Opts(ctypes.Structure):
     _fields_ = [("c_light", ctypes.c_double), ("p_max", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("staging_bytes", ctypes.c_int64)]
+                ("staging_bytes", ctypes.c_int64), ("split_threshold", ctypes.c_double)]
 
 
 class _Info(ctypes.Structure):
@@ -70,7 +70,8 @@ class _Info(ctypes.Structure):
 
 EXPORTS = ("q4c_plan_create", "q4c_plan_destroy", "q4c_plan_info", "q4c_plan_pairs", "q4c_plan_batches",
            "q4c_tabulate_size", "nao_tabulate", "q4c_integrate_H", "density_on_grid", "q4c_coef_from_spinor",
-           "q4c_plan_sync", "q4c_plan_profile", "q4c_plan_timers", "q4c_status_string", "q4c_last_error")
+           "q4c_plan_sync", "q4c_plan_profile", "q4c_plan_timers", "q4c_plan_split_stats", "q4c_status_string",
+           "q4c_last_error")
 
 
 def _load():
@@ -97,6 +98,7 @@ def _load():
         lib.q4c_plan_sync.argtypes = [vp, vp]
         lib.q4c_plan_profile.argtypes = [vp, ctypes.c_int]
         lib.q4c_plan_timers.argtypes = [vp, vp, vp]
+        lib.q4c_plan_split_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
         lib.q4c_status_string.argtypes = [ctypes.c_int]
         lib.q4c_status_string.restype = ctypes.c_char_p
         lib.q4c_last_error.argtypes = []
@@ -141,7 +143,7 @@ class Plan:
     """An integration plan for one system and grid (q4c_plan_create)."""
 
     def __init__(self, wl, p_max: Optional[int] = None, c_light: Optional[float] = None, host_only: bool = False,
-                 staging_bytes: int = 0):
+                 staging_bytes: int = 0, split_threshold: float = 0.0):
         lib = _load()
         self._keep = dict(
             R=_np(wl.R, np.float64).reshape(-1), aso=_np(wl.atom_shell_off, np.int32), sl=_np(wl.shell_l, np.int32),
@@ -156,7 +158,7 @@ class Plan:
         if p_max is None:
             p_max = int(getattr(wl, "meta", {}).get("p_max", 300))
         o = _Opts(float(c_light if c_light is not None else getattr(wl, "c_light", 0.0)), int(p_max),
-                  PLAN_HOST_ONLY if host_only else 0, int(staging_bytes))
+                  PLAN_HOST_ONLY if host_only else 0, int(staging_bytes), float(split_threshold))
         h = ctypes.c_void_p()
         _check(lib.q4c_plan_create(ctypes.byref(b), ctypes.byref(g), ctypes.byref(o), ctypes.byref(h)))
         self._h = h
@@ -215,6 +217,12 @@ class Plan:
         n = np.zeros(len(TIMER_NAMES), dtype=np.int64)
         _check(_load().q4c_plan_timers(self._h, ms.ctypes.data, n.ctypes.data))
         return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(TIMER_NAMES)}
+
+    def split_stats(self):
+        """(FP64-routed chunks, total chunks) of the last split-precision call."""
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        _check(_load().q4c_plan_split_stats(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return int(a.value), int(b.value)
 
     def sync(self):
         _check(_load().q4c_plan_sync(self._h, _stream_handle()))

@@ -93,6 +93,7 @@ struct q4c_plan {
   int32_t p_max = 300;
   int32_t flags = 0;
   int64_t staging_budget = 0;
+  double split_tau = 3e-11;
 
   // ---- grid / batches
   int64_t n_points = 0, n_active = 0, n_batches = 0;
@@ -139,6 +140,7 @@ struct q4c_plan {
   int64_t *d_zero_off = nullptr, *d_zero_len = nullptr;
   q4c::WorkItem *d_ptile = nullptr;
   double *d_om = nullptr;  // [n_active + 16] point weights w_g v_g of the current call
+  unsigned long long *d_chunks = nullptr;  // [64][2]: FP64-routed and total chunks of the last split call
   double *d_staging = nullptr;
   int32_t *d_flag = nullptr;
 

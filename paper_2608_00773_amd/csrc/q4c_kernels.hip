@@ -258,7 +258,8 @@ __device__ __forceinline__ int64_t xcd_map(int64_t bid, int64_t n) {
 }
 
 // w_g v_g for every active point (batch order); 16 zero entries after the end.
-__global__ void k_om(DevPlan d, const double *v, double *om) {
+__global__ void k_om(DevPlan d, const double *v, double *om, unsigned long long *chunks) {
+  if (blockIdx.x == 0 && threadIdx.x < 128) chunks[threadIdx.x] = 0;
   const int64_t n = d.n_active;
   for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n + 16; g += (int64_t)gridDim.x * blockDim.x)
     om[g] = g < n ? d.pw[g] * v[d.perm[g]] : 0.0;
@@ -391,11 +392,12 @@ struct Slab {
 // a slab (optionally weighted per point).  2048 units of 16 bytes
 // (function f, points 2h and 2h+1 of K step ks, component q); every thread
 // issues all of its loads before the first store.
-template <int NTH, int SEGW>
-__device__ __forceinline__ void copy_slab(const double *pb, int64_t plane, int np, int row0, int ks0,
-                                          Slab<SEGW> &dst, const double *omc) {
+template <int NTH, int SEGW, bool TRACK = false>
+__device__ __forceinline__ double copy_slab(const double *pb, int64_t plane, int np, int row0, int ks0,
+                                            Slab<SEGW> &dst, const double *omc) {
   constexpr int U = 4 * 4 * 2 * T / NTH;  // units per thread
   constexpr int G = U < 4 ? U : 4;        // loads in flight per thread
+  double gmax = 0.0;                      // largest |gradient component| stored (TRACK)
 #pragma unroll
   for (int k0 = 0; k0 < U; k0 += G) {
     double2 val[G];
@@ -418,12 +420,13 @@ __device__ __forceinline__ void copy_slab(const double *pb, int64_t plane, int n
         x *= omc[pt];
         y *= omc[pt + 1];
       }
+      if (TRACK && q > 0) gmax = fmax(gmax, fmax(fabs(x), fabs(y)));
       dst.v[(q * 16 + pt) * SEGW + f] = x;
       dst.v[(q * 16 + pt + 1) * SEGW + f] = y;
     }
   }
+  return gmax;
 }
-
 
 // Two-phase form of copy_slab for software pipelining: fetch a chunk into
 // registers (U units per thread), later store it to a slab.
@@ -459,11 +462,21 @@ __device__ __forceinline__ void store_slab(const SlabRegs<NTH> &r, Slab<SEGW> &d
   }
 }
 
+// Split modes: a chunk's W contribution is bounded by c' 48 A B with A the
+// largest |grad phi| of the tile's rows and B the largest |w v grad phi| of
+// its columns over the chunk's 16 points (16 points x 3 products per term);
+// with FP32 rounding 2^-24 that bounds the FP32 error of the chunk.
+constexpr double kU32 = 5.9604644775390625e-08;
+
 template <int MODE>
-__global__ __launch_bounds__(NT, 2) void k_contract(DevPlan d, const WorkItem *work, int64_t w0, int64_t nw,
-                                                    const double *om, const double *panel, double *staging) {
+__global__ __launch_bounds__(NT, MODE == 0 ? 2 : 1) void k_contract(DevPlan d, const WorkItem *work, int64_t w0,
+                                                                    int64_t nw, const double *om,
+                                                                    const double *panel, double *staging,
+                                                                    double tau, unsigned long long *chunks) {
+  constexpr bool SPLIT = MODE != 0;
   __shared__ Slab<SEGF> sa, sb;
   __shared__ double s_om[16];
+  __shared__ double s_gm[2][NT / 64];
   const WorkItem it = work[w0 + xcd_map(blockIdx.x, nw)];
   const int b = it.batch;
   const int g0 = d.batch_pt_off[b], P = d.batch_pt_off[b + 1] - g0;
@@ -502,12 +515,37 @@ __global__ __launch_bounds__(NT, 2) void k_contract(DevPlan d, const WorkItem *w
         for (int q = 0; q < 4; ++q) accf[x][y][q] = flt4{0.f, 0.f, 0.f, 0.f};
   }
 
+  const double cp = d.cprime;
+  unsigned long long n_hot = 0, n_all = 0;
   for (int k0 = 0; k0 < Pp; k0 += 16) {
     if (tid < 16) s_om[tid] = k0 + tid < P ? om[g0 + k0 + tid] : 0.0;
     __syncthreads();  // s_om visible; previous chunk's operands consumed
-    copy_slab<NT, SEGF>(pb, plane, np, r0, k0 >> 2, sa, nullptr);
-    copy_slab<NT, SEGF>(pb, plane, np, c0, k0 >> 2, sb, s_om);
+    double ma = copy_slab<NT, SEGF, SPLIT>(pb, plane, np, r0, k0 >> 2, sa, nullptr);
+    double mb = copy_slab<NT, SEGF, SPLIT>(pb, plane, np, c0, k0 >> 2, sb, s_om);
+    if (SPLIT) {
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        ma = fmax(ma, __shfl_xor(ma, off));
+        mb = fmax(mb, __shfl_xor(mb, off));
+      }
+      if (lane == 0) {
+        s_gm[0][wave] = ma;
+        s_gm[1][wave] = mb;
+      }
+    }
     __syncthreads();
+    bool hot = true;  // W parts of this chunk on FP64 MFMA
+    if (SPLIT) {
+      double A = 0.0, B = 0.0;
+#pragma unroll
+      for (int w = 0; w < NT / 64; ++w) {
+        A = fmax(A, s_gm[0][w]);
+        B = fmax(B, s_gm[1][w]);
+      }
+      hot = kU32 * cp * 48.0 * A * B > tau;
+      n_hot += hot ? 1 : 0;
+      n_all += 1;
+    }
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
       double a[2][4], bb[2][4];
@@ -527,7 +565,7 @@ __global__ __launch_bounds__(NT, 2) void k_contract(DevPlan d, const WorkItem *w
           const double *av = a[x];
           const double *bv = bb[y];
           acc[x][y][0] = mfma64(av[0], bv[0], acc[x][y][0]);
-          if (MODE == MODE_F64) {
+          if (hot) {
             acc[x][y][1] = mfma64(av[1], bv[1], acc[x][y][1]);
             acc[x][y][2] = mfma64(av[2], bv[3], acc[x][y][2]);
             acc[x][y][3] = mfma64(av[3], bv[1], acc[x][y][3]);
@@ -553,7 +591,7 @@ __global__ __launch_bounds__(NT, 2) void k_contract(DevPlan d, const WorkItem *w
             accf[x][y][2] = mfma32(-af[1], bf[3], accf[x][y][2]);
             accf[x][y][3] = mfma32(-af[2], bf[1], accf[x][y][3]);
             accf[x][y][0] = mfma32(af[3], bf[3], accf[x][y][0]);
-          } else {
+          } else if (MODE == MODE_SPLIT) {
             // hi + lo split: x = hi + lo with hi = fl(x), lo = fl(x - hi);
             // x y ~ hi_x hi_y + hi_x lo_y + lo_x hi_y (lo_x lo_y dropped)
             float ah[4], al[4], bh[4], bl[4];
@@ -582,10 +620,30 @@ __global__ __launch_bounds__(NT, 2) void k_contract(DevPlan d, const WorkItem *w
         }
     }
   }
-  (void)diag;
+  if (SPLIT) {
+    // FP32 partials (register r of lane (l16, lk) holds X[4 lk + r][l16]) join
+    // the FP64 accumulators as X = sum_r S_r X_r, S_r[i][k] = [i == 4 k + r],
+    // X_r[k][j] = X[4 k + r][j]: four rank-4 FP64 MFMAs per block and part.
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        if (!act[x][y]) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const double sel = li16 == 4 * lk + r ? 1.0 : 0.0;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[x][y][q + 1] = mfma64(sel, (double)accf[x][y][q][r], acc[x][y][q + 1]);
+        }
+      }
+    if (tid == 0) {
+      const int slot = (int)(blockIdx.x & 63);
+      atomicAdd(&chunks[2 * slot], n_hot);
+      atomicAdd(&chunks[2 * slot + 1], n_all);
+    }
+  }
 
   // write the computed blocks to the staged atom-pair blocks
-  const double cp = d.cprime;
 #pragma unroll
   for (int y = 0; y < 2; ++y) {
     const int cb = c0 + wc + y * 16;
@@ -602,26 +660,11 @@ __global__ __launch_bounds__(NT, 2) void k_contract(DevPlan d, const WorkItem *w
         const int li = rb + d_row_f64(lk, r);
         if (li < n) {
           const SlotInfo si = slot_of(d, f0, sbase, li);
-          if (MODE == MODE_F64) {
-            double vals[5];
-            vals[0] = acc[x][y][0][r];
+          double vals[5];
+          vals[0] = acc[x][y][0][r];
 #pragma unroll
-            for (int q = 1; q < 5; ++q) vals[q] = cp * acc[x][y][q][r];
-            stage_store<0, 5>(staging, si, sj, li, lj, upper, vals);
-          } else {
-            double v0 = acc[x][y][0][r];
-            stage_store<0, 1>(staging, si, sj, li, lj, upper, &v0);
-          }
-        }
-        if (MODE != MODE_F64) {
-          const int lf = rb + d_row_f32(lk, r);
-          if (lf < n) {
-            const SlotInfo sf = slot_of(d, f0, sbase, lf);
-            double vals[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) vals[q] = cp * (double)accf[x][y][q][r];
-            stage_store<1, 5>(staging, sf, sj, lf, lj, upper, vals);
-          }
+          for (int q = 1; q < 5; ++q) vals[q] = cp * acc[x][y][q][r];
+          stage_store<0, 5>(staging, si, sj, li, lj, upper, vals);
         }
       }
     }
@@ -946,7 +989,7 @@ int launch_integrate(const q4c_plan *p, const double *v, int precision, uint32_t
   {
     TimedLaunch tl_(p, Q4C_TIMER_OTHER, s);
     const unsigned nb = (unsigned)std::min<int64_t>((p->n_active + 16 + 255) / 256, 65535);
-    hipLaunchKernelGGL(k_om, dim3(nb), dim3(256), 0, s, p->dp, v, p->d_om);
+    hipLaunchKernelGGL(k_om, dim3(nb), dim3(256), 0, s, p->dp, v, p->d_om, p->d_chunks);
   }
   if ((rc = check_launch("k_om")) != Q4C_OK) return rc;
   for (const Pass &ps : p->passes) {
@@ -964,13 +1007,13 @@ int launch_integrate(const q4c_plan *p, const double *v, int precision, uint32_t
         TimedLaunch tl_(p, Q4C_TIMER_CONTRACT, s);
         if (precision == Q4C_PREC_F64)
           hipLaunchKernelGGL(k_contract<MODE_F64>, dim3((unsigned)nw), dim3(NT), 0, s, p->dp, p->d_work, ps.w0, nw,
-                             p->d_om, panel, p->d_staging);
+                             p->d_om, panel, p->d_staging, p->split_tau, p->d_chunks);
         else if (precision == Q4C_PREC_F32)
           hipLaunchKernelGGL(k_contract<MODE_F32>, dim3((unsigned)nw), dim3(NT), 0, s, p->dp, p->d_work, ps.w0, nw,
-                             p->d_om, panel, p->d_staging);
+                             p->d_om, panel, p->d_staging, p->split_tau, p->d_chunks);
         else
           hipLaunchKernelGGL(k_contract<MODE_SPLIT>, dim3((unsigned)nw), dim3(NT), 0, s, p->dp, p->d_work, ps.w0, nw,
-                             p->d_om, panel, p->d_staging);
+                             p->d_om, panel, p->d_staging, p->split_tau, p->d_chunks);
       }
       if ((rc = check_launch("k_contract")) != Q4C_OK) return rc;
     }

@@ -561,6 +561,9 @@ int build_device(q4c_plan *p) {
   if (rc != Q4C_OK) return rc;
   rc = device_alloc(p, (size_t)(p->n_active + 16) * sizeof(double), (void **)&p->d_om);
   if (rc != Q4C_OK) return rc;
+  rc = device_alloc(p, 128 * sizeof(unsigned long long), (void **)&p->d_chunks);
+  if (rc != Q4C_OK) return rc;
+  if (hipMemset(p->d_chunks, 0, 128 * sizeof(unsigned long long)) != hipSuccess) return fail(Q4C_EHIP, "hipMemset");
   d.R = R;
   d.fn_atom = fn_atom;
   d.fn_shlm = fn_shlm;
@@ -656,6 +659,7 @@ int q4c_plan_create(const q4c_basis *basis, const q4c_grid *grid, const q4c_opts
       if (opts->p_max > 0) p->p_max = opts->p_max;
       p->flags = opts->flags;
       p->staging_budget = opts->staging_bytes;
+      if (opts->split_threshold > 0.0) p->split_tau = opts->split_threshold;
     }
     if (p->p_max < 1) p->p_max = 300;
     if (p->staging_budget <= 0) p->staging_budget = (int64_t)16 << 30;
@@ -805,6 +809,24 @@ int q4c_plan_profile(q4c_plan *p, int enable) {
   if (!p) return fail(Q4C_EINVAL, "NULL plan");
   if (!p->on_device) return fail(Q4C_ENODEV, "plan has no device data");
   p->profiling = enable != 0;
+  return Q4C_OK;
+}
+
+int q4c_plan_split_stats(const q4c_plan *p, int64_t *fp64_chunks, int64_t *total_chunks) {
+  int rc = check_plan_dev(p);
+  if (rc != Q4C_OK) return rc;
+  if (!fp64_chunks || !total_chunks) return fail(Q4C_EINVAL, "NULL argument");
+  unsigned long long h[128];
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(h, p->d_chunks, sizeof(h), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return q4c::hip_fail(e, "hipMemcpy");
+  int64_t a = 0, t = 0;
+  for (int i = 0; i < 64; ++i) {
+    a += (int64_t)h[2 * i];
+    t += (int64_t)h[2 * i + 1];
+  }
+  *fp64_chunks = a;
+  *total_chunks = t;
   return Q4C_OK;
 }
 

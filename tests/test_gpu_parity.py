@@ -307,8 +307,6 @@ def test_integrate_f64_multitile(q, medium, p_max, staging):
         assert np.array_equal(gw[p], oracle.spinor_W(got[p]))
 
 
-@pytest.mark.xfail(reason="FP32 accumulation within a batch leaves ~2e-8 Ha on the largest W elements of this "
-                          "dense case; FP64 routing of the large-term chunks is not built yet", strict=False)
 def test_integrate_split_multitile(q, medium):
     wl, pairs, ref, scale = medium
     for prec in (1, 2):

@@ -29,6 +29,15 @@ PEAK_F64 = 78.6e12    # MI355X dense FP64 MFMA, flop/s
 PEAK_F32 = 157.3e12   # MI355X dense FP32 MFMA, flop/s
 PREC = {"f64": 0, "split": 1, "f32": 2}
 
+# HBM bytes per k_contract launch on the default cluster workload, from two
+# rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE), each scaled by what the same
+# counter reads for an elementwise copy of 1 GiB (read x1.9999, write x1.0000).
+# Keyed by the SHA-256 of the kernel source the counters were taken on: any
+# change to the kernels makes the figure stale, and it is then reported as null.
+TRAFFIC = {
+    ("38e02e0567d995788f404da2d5a93941dd20616daac8229ea623d4585b6739fe", "f64", 120): 6.907e9 + 4.282e9,
+}
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -37,10 +46,14 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", choices=sorted(PREC), default="f64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=float, default=0.02, help="fraction of grid points for the oracle timing")
+    ap.add_argument("--cpu-sample", type=float, default=0.05, help="fraction of grid points for the oracle timing")
     ap.add_argument("--n-atoms", type=int, default=120)
-    ap.add_argument("--mode", choices=["full", "forward", "adjoint"], default="full",
-                    help="forward/adjoint: run only that call `steps` times (for profiler runs) and print its time")
+    ap.add_argument("--mode", choices=["full", "step", "forward", "adjoint"], default="full",
+                    help="step/forward/adjoint: run only the whole step or that one call `steps` times "
+                         "(for profiler runs) and print its time")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="before the work, run one elementwise copy of this many MiB (read once, written once): "
+                         "the reference dispatch for scaling HBM byte counters")
     return ap.parse_args()
 
 
@@ -117,11 +130,21 @@ def main():
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / k
 
+    if a.calib_copy_mib:
+        n = a.calib_copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+
     if a.mode != "full":
         if a.mode == "forward":
             call = lambda: q.q4c_integrate_H(plan, v, prec, q.ASSEMBLE_W, store, spin)
-        else:
+        elif a.mode == "adjoint":
             call = lambda: q.density_on_grid(plan, gbar, q.TERM_ALL, 1, grad)
+        else:
+            call = lambda: step(prec)
         for _ in range(a.warmup):
             call()
         ms = timed(call, a.steps)
@@ -164,6 +187,11 @@ def main():
     err = {n: [float(torch.max(torch.abs(outs[n][k] - outs["f64"][k]))) for k in range(5)] for n in outs}
     ms_adj = timed(lambda: q.density_on_grid(plan, gbar, q.TERM_ALL, 1, grad), max(3, a.steps // 4))
 
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2608_00773_amd", "csrc", "q4c_kernels.hip"), "rb") as fh:
+        ksha = hashlib.sha256(fh.read()).hexdigest()
+    traffic = TRAFFIC.get((ksha, a.precision, a.n_atoms))
+
     n_act = info["n_active"]
     res = {
         "metric": METRIC,
@@ -192,7 +220,7 @@ def main():
             "peak": peak / 1e12,
             "unit": "TFLOP/s",
             "frac": achieved / peak,
-            "traffic": None,
+            "traffic": traffic,
             "avg_launch_ms": t_contract * 1e3,
             "launches_per_step": launches_per_step,
         },

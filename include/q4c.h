@@ -139,6 +139,7 @@ typedef struct {
   int64_t n_passes;        /* staging passes per call */
   int64_t device_bytes;    /* device memory owned by the plan */
   double flops_alg;        /* sum_B 10 P_B n_B^2, the algorithmic flop count of one H build */
+  int32_t n_systems;       /* independent systems (1 unless q4c_plan_create_batched) */
 } q4c_info;
 
 /* Build a plan: batching (recursive median bisection of the active points to
@@ -147,6 +148,24 @@ typedef struct {
  * and the reduced index set nnz(B_v).  Inputs are copied.  Returns
  * Q4C_EUNSUPPORTED for l > 3 and Q4C_EINVAL for malformed descriptors. */
 int q4c_plan_create(const q4c_basis *basis, const q4c_grid *grid, const q4c_opts *opts, q4c_plan **out);
+
+/* One plan over n_systems independent systems (e.g. many molecules): every
+ * call then runs all systems' batches in the same launches.  The union is
+ * system-major: atoms, functions, grid points (user order = the systems'
+ * points concatenated), pairs and store blocks of system 0, then system 1, ...
+ * Batches, relevant functions and pairs never mix systems, so each system's
+ * batches, pairs and results are exactly those of q4c_plan_create on that
+ * system alone (same batch contents, same summation order: bitwise equal).
+ * Systems passing the same coef pointer and n_coef share radial tables.
+ * Paper Sec. III A (Eq. 31): batches are independent work units. */
+int q4c_plan_create_batched(int32_t n_systems, const q4c_basis *bases, const q4c_grid *grids, const q4c_opts *opts,
+                            q4c_plan **out);
+
+/* Offsets of every system in the union ([n_systems + 1] each, NULL to skip):
+ * atoms, user-order grid points, batches, pairs and store elements (doubles
+ * per real part). */
+int q4c_plan_systems(const q4c_plan *plan, int64_t *atom_off, int64_t *point_off, int64_t *batch_off,
+                     int64_t *pair_off, int64_t *store_off);
 
 /* Free a plan and its device memory; NULL is a no-op.  Synchronises the device. */
 void q4c_plan_destroy(q4c_plan *plan);
@@ -233,6 +252,47 @@ int q4c_plan_profile(q4c_plan *plan, int enable);
  * and chunks in total (waits for the call to finish). */
 int q4c_plan_split_stats(const q4c_plan *plan, int64_t *fp64_chunks, int64_t *total_chunks);
 int q4c_plan_timers(q4c_plan *plan, double *ms, int64_t *launches);
+
+/* Launch shape of the two contraction kernels (k_contract of q4c_integrate_H,
+ * k_density_tiles of density_on_grid), per plan:
+ *   order      0: work items in batch order, consecutive items on one XCD;
+ *              1: largest items first (estimated cost), longest-first scheduling;
+ *   persistent 0: one workgroup per work item;
+ *              k > 0: k workgroups loop over the items, taking them from
+ *              ticket queues (one per XCD with stealing for order 0, one global
+ *              queue for order 1).
+ * Results do not depend on the launch shape (each item's arithmetic and the
+ * fixed-order sums are unchanged): bitwise equal outputs.  Setting a shape
+ * drops the plan's captured graphs. */
+enum { Q4C_KERNEL_CONTRACT = 0, Q4C_KERNEL_DENSITY = 1 };
+int q4c_plan_set_launch(q4c_plan *plan, int32_t kernel, int32_t order, int32_t persistent);
+int q4c_plan_get_launch(const q4c_plan *plan, int32_t kernel, int32_t *order, int32_t *persistent);
+
+/* Autotuner: times every candidate shape (order 0/1 x persistent 0, one and
+ * two chip-fills of workgroups) of the contraction kernel on this plan with
+ * q4c_integrate_H(v_dev, precision) into store_dev (5 store_len doubles,
+ * overwritten), and, when coef_dev / out_dev are given, of the adjoint kernel
+ * with density_on_grid(coef_dev, all terms, weight mode 1) into out_dev;
+ * median of reps timed calls after one warm-up, HIP events on `stream`.
+ * Keeps the fastest shape of each kernel on the plan and, if table is not
+ * NULL, writes up to table_len entries (kernel, order, persistent, ms);
+ * *n_entries = number of candidates timed.  Synchronises the stream.  Batch
+ * size is a plan-time choice (q4c_opts.p_max): tune it by building plans. */
+typedef struct {
+  int32_t kernel, order, persistent;
+  double ms;
+} q4c_tune_entry;
+int q4c_plan_autotune(q4c_plan *plan, const double *v_dev, int32_t precision, double *store_dev,
+                      const double *coef_dev, double *out_dev, int32_t reps, q4c_tune_entry *table,
+                      int32_t table_len, int32_t *n_entries, void *stream);
+
+/* HIP graphs: when enabled, each distinct q4c_integrate_H / density_on_grid
+ * call (same buffers, precision, flags or terms) is captured once into a HIP
+ * graph on the plan's own stream and replayed on the caller's stream on every
+ * later call: the whole launch sequence of a call is one graph launch.  Up to
+ * 16 graphs are kept per plan.  Disabled while profiling.  Buffers must stay
+ * allocated while graphs that use them may be replayed. */
+int q4c_plan_set_graphs(q4c_plan *plan, int enable);
 
 /* Block until the plan's queued work is done; reports asynchronous HIP errors. */
 int q4c_plan_sync(const q4c_plan *plan, void *stream);

@@ -65,13 +65,22 @@ class _Info(ctypes.Structure):
                 ("n_active", ctypes.c_int64), ("n_batches", ctypes.c_int64), ("n_pairs", ctypes.c_int64),
                 ("store_len", ctypes.c_int64), ("fn_entries", ctypes.c_int64), ("max_batch_points", ctypes.c_int64),
                 ("max_batch_fn", ctypes.c_int64), ("n_work", ctypes.c_int64), ("n_passes", ctypes.c_int64),
-                ("device_bytes", ctypes.c_int64), ("flops_alg", ctypes.c_double)]
+                ("device_bytes", ctypes.c_int64), ("flops_alg", ctypes.c_double), ("n_systems", ctypes.c_int32)]
+
+
+class _TuneEntry(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("order", ctypes.c_int32), ("persistent", ctypes.c_int32),
+                ("ms", ctypes.c_double)]
+
+
+KERNEL_CONTRACT, KERNEL_DENSITY = 0, 1
 
 
 EXPORTS = ("q4c_plan_create", "q4c_plan_destroy", "q4c_plan_info", "q4c_plan_pairs", "q4c_plan_batches",
            "q4c_tabulate_size", "nao_tabulate", "q4c_integrate_H", "density_on_grid", "q4c_coef_from_spinor",
            "q4c_plan_sync", "q4c_plan_profile", "q4c_plan_timers", "q4c_plan_split_stats", "q4c_status_string",
-           "q4c_last_error")
+           "q4c_last_error", "q4c_plan_create_batched", "q4c_plan_systems", "q4c_plan_set_launch",
+           "q4c_plan_get_launch", "q4c_plan_autotune", "q4c_plan_set_graphs")
 
 
 def _load():
@@ -99,6 +108,14 @@ def _load():
         lib.q4c_plan_profile.argtypes = [vp, ctypes.c_int]
         lib.q4c_plan_timers.argtypes = [vp, vp, vp]
         lib.q4c_plan_split_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+        lib.q4c_plan_create_batched.argtypes = [i32, ctypes.POINTER(_Basis), ctypes.POINTER(_Grid),
+                                                ctypes.POINTER(_Opts), ctypes.POINTER(vp)]
+        lib.q4c_plan_systems.argtypes = [vp, vp, vp, vp, vp, vp]
+        lib.q4c_plan_set_launch.argtypes = [vp, i32, i32, i32]
+        lib.q4c_plan_get_launch.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        lib.q4c_plan_autotune.argtypes = [vp, vp, i32, vp, vp, vp, i32, ctypes.POINTER(_TuneEntry), i32,
+                                          ctypes.POINTER(i32), vp]
+        lib.q4c_plan_set_graphs.argtypes = [vp, ctypes.c_int]
         lib.q4c_status_string.argtypes = [ctypes.c_int]
         lib.q4c_status_string.restype = ctypes.c_char_p
         lib.q4c_last_error.argtypes = []
@@ -139,30 +156,56 @@ def _dev_ptr(t, dtype_name="float64", min_numel=0, name="tensor"):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _descriptors(wl, keep):
+    k = dict(
+        R=_np(wl.R, np.float64).reshape(-1), aso=_np(wl.atom_shell_off, np.int32), sl=_np(wl.shell_l, np.int32),
+        sr=_np(wl.shell_rcut, np.float64), sn=_np(wl.shell_nint, np.int32),
+        so=_np(wl.shell_coef_off, np.int64), coef=_np(wl.coef, np.float64), x=_np(wl.x, np.float64),
+        y=_np(wl.y, np.float64), z=_np(wl.z, np.float64), w=_np(wl.w, np.float64))
+    keep.append(k)
+    b = _Basis(int(k["aso"].size - 1), k["R"].ctypes.data, k["aso"].ctypes.data, int(k["sl"].size),
+               k["sl"].ctypes.data, k["sr"].ctypes.data, k["sn"].ctypes.data, k["so"].ctypes.data,
+               int(k["coef"].size), k["coef"].ctypes.data)
+    g = _Grid(int(k["x"].size), k["x"].ctypes.data, k["y"].ctypes.data, k["z"].ctypes.data, k["w"].ctypes.data)
+    return b, g
+
+
 class Plan:
-    """An integration plan for one system and grid (q4c_plan_create)."""
+    """An integration plan (q4c_plan_create) for one system and grid, or, given
+    a list of systems, one plan over all of them (q4c_plan_create_batched):
+    the union is system-major and every call runs all systems at once."""
 
     def __init__(self, wl, p_max: Optional[int] = None, c_light: Optional[float] = None, host_only: bool = False,
                  staging_bytes: int = 0, split_threshold: float = 0.0):
         lib = _load()
-        self._keep = dict(
-            R=_np(wl.R, np.float64).reshape(-1), aso=_np(wl.atom_shell_off, np.int32), sl=_np(wl.shell_l, np.int32),
-            sr=_np(wl.shell_rcut, np.float64), sn=_np(wl.shell_nint, np.int32),
-            so=_np(wl.shell_coef_off, np.int64), coef=_np(wl.coef, np.float64), x=_np(wl.x, np.float64),
-            y=_np(wl.y, np.float64), z=_np(wl.z, np.float64), w=_np(wl.w, np.float64))
-        k = self._keep
-        b = _Basis(int(k["aso"].size - 1), k["R"].ctypes.data, k["aso"].ctypes.data, int(k["sl"].size),
-                   k["sl"].ctypes.data, k["sr"].ctypes.data, k["sn"].ctypes.data, k["so"].ctypes.data,
-                   int(k["coef"].size), k["coef"].ctypes.data)
-        g = _Grid(int(k["x"].size), k["x"].ctypes.data, k["y"].ctypes.data, k["z"].ctypes.data, k["w"].ctypes.data)
+        systems = list(wl) if isinstance(wl, (list, tuple)) else [wl]
+        first = systems[0]
+        keep = []
+        coef_cache = {}
+        descs = []
+        for w in systems:
+            # systems sharing one coefficient array pass the same pointer (shared tables)
+            key = id(w.coef)
+            b, g = _descriptors(w, keep)
+            if key in coef_cache:
+                b.coef, b.n_coef = coef_cache[key]
+            else:
+                coef_cache[key] = (b.coef, b.n_coef)
+            descs.append((b, g))
         if p_max is None:
-            p_max = int(getattr(wl, "meta", {}).get("p_max", 300))
-        o = _Opts(float(c_light if c_light is not None else getattr(wl, "c_light", 0.0)), int(p_max),
+            p_max = int(getattr(first, "meta", {}).get("p_max", 300))
+        o = _Opts(float(c_light if c_light is not None else getattr(first, "c_light", 0.0)), int(p_max),
                   PLAN_HOST_ONLY if host_only else 0, int(staging_bytes), float(split_threshold))
         h = ctypes.c_void_p()
-        _check(lib.q4c_plan_create(ctypes.byref(b), ctypes.byref(g), ctypes.byref(o), ctypes.byref(h)))
+        if isinstance(wl, (list, tuple)):
+            B = (_Basis * len(descs))(*[d[0] for d in descs])
+            G = (_Grid * len(descs))(*[d[1] for d in descs])
+            _check(lib.q4c_plan_create_batched(len(descs), B, G, ctypes.byref(o), ctypes.byref(h)))
+        else:
+            _check(lib.q4c_plan_create(ctypes.byref(descs[0][0]), ctypes.byref(descs[0][1]), ctypes.byref(o),
+                                       ctypes.byref(h)))
         self._h = h
-        self._keep = None
+        del keep
         self.info = self._info()
 
     @property
@@ -226,6 +269,39 @@ class Plan:
 
     def sync(self):
         _check(_load().q4c_plan_sync(self._h, _stream_handle()))
+
+    def systems(self):
+        """{atom, point, batch, pair, store}: [n_systems + 1] offsets of each system in the union."""
+        n = self.info["n_systems"] + 1
+        out = {k: np.zeros(n, dtype=np.int64) for k in ("atom", "point", "batch", "pair", "store")}
+        _check(_load().q4c_plan_systems(self._h, *[out[k].ctypes.data for k in ("atom", "point", "batch", "pair",
+                                                                                 "store")]))
+        return out
+
+    def set_launch(self, kernel: int, order: int, persistent: int):
+        _check(_load().q4c_plan_set_launch(self._h, int(kernel), int(order), int(persistent)))
+
+    def get_launch(self, kernel: int):
+        o, p = ctypes.c_int32(), ctypes.c_int32()
+        _check(_load().q4c_plan_get_launch(self._h, int(kernel), ctypes.byref(o), ctypes.byref(p)))
+        return int(o.value), int(p.value)
+
+    def set_graphs(self, enable: bool = True):
+        _check(_load().q4c_plan_set_graphs(self._h, 1 if enable else 0))
+
+    def autotune(self, v, store, precision: int = PREC_F64, coef=None, out=None, reps: int = 3):
+        """Time the candidate launch shapes (q4c_plan_autotune), keep the fastest;
+        returns [(kernel, order, persistent, ms), ...]."""
+        L = self.info["store_len"]
+        tab = (_TuneEntry * 32)()
+        n = ctypes.c_int32()
+        _check(_load().q4c_plan_autotune(
+            self._h, _dev_ptr(v, min_numel=self.info["n_points"], name="v"), int(precision),
+            _dev_ptr(store, min_numel=5 * L, name="store"),
+            _dev_ptr(coef, min_numel=5 * L, name="coef") if coef is not None else None,
+            _dev_ptr(out, min_numel=self.info["n_points"], name="out") if out is not None else None,
+            int(reps), tab, 32, ctypes.byref(n), _stream_handle()))
+        return [(e.kernel, e.order, e.persistent, e.ms) for e in tab[:min(n.value, 32)]]
 
 
 # ---------------------------------------------------------------------------

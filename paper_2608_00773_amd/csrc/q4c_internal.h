@@ -14,6 +14,8 @@ namespace q4c {
 // Contraction tile edge (functions) and points per staged K chunk.
 constexpr int kTile = 64;
 constexpr int kChunk = 16;
+constexpr int kTicketStride = 16;                  // one 64-byte line per ticket queue
+constexpr int kTicketsPerLaunch = 8 * kTicketStride; // 8 XCD queues
 
 // Work item of the contraction / adjoint kernels: one (batch, row tile, column tile)
 // with ti <= tj over the batch's local function list.
@@ -57,6 +59,14 @@ struct DevPlan {
   double cprime;  // 1 / (4 c^2)
 };
 
+// How the two contraction kernels are launched: work order (0: batch order,
+// 1: largest items first) and persistent workgroup count (0: one workgroup
+// per work item).
+struct LaunchCfg {
+  int32_t order = 0;
+  int32_t persistent = 0;
+};
+
 struct Pass {
   int64_t b0, b1;        // batch range
   int64_t w0, w1;        // work range
@@ -95,6 +105,11 @@ struct q4c_plan {
   int64_t staging_budget = 0;
   double split_tau = 3e-11;
 
+  // ---- independent systems (one unless built by q4c_plan_create_batched)
+  int32_t n_systems = 1;
+  std::vector<int32_t> atom_sys;  // [n_atoms]
+  std::vector<int64_t> sys_atom_off, sys_point_off, sys_batch_off, sys_pair_off;  // [n_systems + 1]
+
   // ---- grid / batches
   int64_t n_points = 0, n_active = 0, n_batches = 0;
   std::vector<int32_t> perm;  // batch-ordered active point -> user index
@@ -121,6 +136,7 @@ struct q4c_plan {
   std::vector<int64_t> zero_off, zero_len;  // staged blocks of slot combinations that are not stored pairs
   std::vector<int64_t> batch_work_off, tab_off, panel_off;
   std::vector<q4c::WorkItem> ptile;  // (batch, function tile) list of the panel kernel
+  std::vector<int32_t> work_order;   // per pass, pass-relative work indices by decreasing cost
   int64_t max_scratch = 0;
   int64_t max_batch_points = 0, max_batch_fn = 0, fn_entries = 0;
   double flops_alg = 0.0;
@@ -143,6 +159,23 @@ struct q4c_plan {
   unsigned long long *d_chunks = nullptr;  // [64][2]: FP64-routed and total chunks of the last split call
   double *d_staging = nullptr;
   int32_t *d_flag = nullptr;
+  int32_t *d_order = nullptr;      // per pass: work items sorted by cost (pass-relative indices)
+  unsigned *d_tickets = nullptr;   // [2][n_passes][kTicketsPerLaunch] persistent-launch queues
+  int n_cu = 256;                  // compute units of the plan's device
+
+  // ---- launch configuration (chosen by q4c_plan_autotune or set directly)
+  q4c::LaunchCfg cfg_contract{}, cfg_density{};
+  bool use_graphs = false;
+  mutable hipStream_t capture_stream = nullptr;
+  struct GraphEntry {
+    int kind;  // 0 integrate, 1 density
+    const void *in;
+    void *out0, *out1, *out2;
+    int64_t a, b, c;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+  };
+  mutable std::vector<GraphEntry> graphs;
 
   // ---- profiling (mutable: calls take a const plan)
   mutable bool profiling = false;

@@ -257,6 +257,44 @@ __device__ __forceinline__ int64_t xcd_map(int64_t bid, int64_t n) {
   return x * q + (x < r ? x : r) + k;
 }
 
+// Persistent launches: workgroups loop over work items drawn from ticket
+// counters (zeroed before the launch).  Without an order map the items are
+// split into 8 contiguous ranges, one queue per XCD (workgroup x runs on XCD
+// x % 8, so a batch's tiles stay on one L2); a workgroup whose queue is empty
+// takes items from the next XCD's queue.  With an order map (items sorted by
+// cost, largest first) there is one global queue.  Every counter only grows,
+// so every workgroup leaves the loop once all queues are drained.
+__device__ __forceinline__ int64_t next_item(unsigned *tickets, int64_t nw, bool global_queue, int64_t *s_pos) {
+  __syncthreads();  // every thread has read the previous position
+  if (threadIdx.x == 0) {
+    int64_t pos = nw;
+    if (global_queue) {
+      const int64_t t = atomicAdd(&tickets[0], 1u);
+      if (t < nw) pos = t;
+    } else {
+      const int x0 = (int)(blockIdx.x & 7);
+      for (int k = 0; k < 8 && pos == nw; ++k) {
+        const int x = (x0 + k) & 7;
+        const int64_t lo = nw * x / 8, hi = nw * (x + 1) / 8;
+        if (hi <= lo) continue;
+        if ((int64_t)__hip_atomic_load(&tickets[x * kTicketStride], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >=
+            hi - lo)
+          continue;
+        const int64_t t = atomicAdd(&tickets[x * kTicketStride], 1u);
+        if (lo + t < hi) pos = lo + t;
+      }
+    }
+    *s_pos = pos;
+  }
+  __syncthreads();
+  return *s_pos;
+}
+
+__global__ void k_zero_u32(unsigned *p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
 // w_g v_g for every active point (batch order); 16 zero entries after the end.
 __global__ void k_om(DevPlan d, const double *v, double *om, unsigned long long *chunks) {
   if (blockIdx.x == 0 && threadIdx.x < 128) chunks[threadIdx.x] = 0;
@@ -468,16 +506,25 @@ __device__ __forceinline__ void store_slab(const SlabRegs<NTH> &r, Slab<SEGW> &d
 // with FP32 rounding 2^-24 that bounds the FP32 error of the chunk.
 constexpr double kU32 = 5.9604644775390625e-08;
 
-template <int MODE>
-__global__ __launch_bounds__(NT, MODE == 0 ? 2 : 1) void k_contract(DevPlan d, const WorkItem *work, int64_t w0,
-                                                                    int64_t nw, const double *om,
-                                                                    const double *panel, double *staging,
-                                                                    double tau, unsigned long long *chunks) {
+// Work item positions 0..nw-1 of a pass map to work items w0 + order[w0 + pos]
+// (order != NULL: cost-sorted) or w0 + pos.  tickets == NULL: one workgroup
+// per position; otherwise a persistent loop (next_item).
+template <int MODE, bool PERSIST>
+__global__ __launch_bounds__(NT, MODE == 0 ? 2 : 1) void k_contract(DevPlan d, const WorkItem *work,
+                                                                    const int32_t *order, int64_t w0, int64_t nw,
+                                                                    const double *om, const double *panel,
+                                                                    double *staging, double tau,
+                                                                    unsigned long long *chunks, unsigned *tickets) {
   constexpr bool SPLIT = MODE != 0;
   __shared__ Slab<SEGF> sa, sb;
   __shared__ double s_om[16];
   __shared__ double s_gm[2][NT / 64];
-  const WorkItem it = work[w0 + xcd_map(blockIdx.x, nw)];
+  __shared__ int64_t s_pos;
+  unsigned long long n_hot = 0, n_all = 0;
+  int64_t pos = PERSIST ? next_item(tickets, nw, order != nullptr, &s_pos)
+                        : (order ? (int64_t)blockIdx.x : xcd_map(blockIdx.x, nw));
+  while (!PERSIST || pos < nw) {
+  const WorkItem it = work[w0 + (order ? order[w0 + pos] : pos)];
   const int b = it.batch;
   const int g0 = d.batch_pt_off[b], P = d.batch_pt_off[b + 1] - g0;
   const int f0 = d.batch_fn_off[b], n = d.batch_fn_off[b + 1] - f0;
@@ -516,7 +563,6 @@ __global__ __launch_bounds__(NT, MODE == 0 ? 2 : 1) void k_contract(DevPlan d, c
   }
 
   const double cp = d.cprime;
-  unsigned long long n_hot = 0, n_all = 0;
   for (int k0 = 0; k0 < Pp; k0 += 16) {
     if (tid < 16) s_om[tid] = k0 + tid < P ? om[g0 + k0 + tid] : 0.0;
     __syncthreads();  // s_om visible; previous chunk's operands consumed
@@ -636,11 +682,6 @@ __global__ __launch_bounds__(NT, MODE == 0 ? 2 : 1) void k_contract(DevPlan d, c
           for (int q = 0; q < 4; ++q) acc[x][y][q + 1] = mfma64(sel, (double)accf[x][y][q][r], acc[x][y][q + 1]);
         }
       }
-    if (tid == 0) {
-      const int slot = (int)(blockIdx.x & 63);
-      atomicAdd(&chunks[2 * slot], n_hot);
-      atomicAdd(&chunks[2 * slot + 1], n_all);
-    }
   }
 
   // write the computed blocks to the staged atom-pair blocks
@@ -668,6 +709,14 @@ __global__ __launch_bounds__(NT, MODE == 0 ? 2 : 1) void k_contract(DevPlan d, c
         }
       }
     }
+  }
+  if (!PERSIST) break;
+  pos = next_item(tickets, nw, order != nullptr, &s_pos);
+  }
+  if (SPLIT && threadIdx.x == 0) {
+    const int slot = (int)(blockIdx.x & 63);
+    atomicAdd(&chunks[2 * slot], n_hot);
+    atomicAdd(&chunks[2 * slot + 1], n_all);
   }
 }
 
@@ -783,12 +832,18 @@ constexpr int NTD = 512;  // adjoint workgroup: 8 waves = 4 column slices x 2 ro
 // One work item: partial[g] = sum over the tile of a_g^T C b_g for all
 // selected terms; the chunk's row and column functions are staged in LDS
 // from the batch's panel and shared by the 8 waves.
+template <bool PERSIST>
 __global__ __launch_bounds__(NTD, 1) void k_density_tiles(DevPlan d, uint32_t terms, const WorkItem *work,
-                                                          int64_t w0, int64_t nw, const double *staging,
-                                                          const double *panel, double *partial) {
+                                                          const int32_t *order, int64_t w0, int64_t nw,
+                                                          const double *staging, const double *panel,
+                                                          double *partial, unsigned *tickets) {
   __shared__ Slab<SEGA> sa[2], sb[2];
   __shared__ double s_red[8][16];
-  const int64_t wi = w0 + xcd_map(blockIdx.x, nw);
+  __shared__ int64_t s_pos;
+  int64_t pos = PERSIST ? next_item(tickets, nw, order != nullptr, &s_pos)
+                        : (order ? (int64_t)blockIdx.x : xcd_map(blockIdx.x, nw));
+  while (!PERSIST || pos < nw) {
+  const int64_t wi = w0 + (order ? order[w0 + pos] : pos);
   const WorkItem it = work[wi];
   const int b = it.batch;
   const int g0 = d.batch_pt_off[b], P = d.batch_pt_off[b + 1] - g0;
@@ -913,6 +968,9 @@ __global__ __launch_bounds__(NTD, 1) void k_density_tiles(DevPlan d, uint32_t te
       out[k0 + tid] = sum;
     }
   }
+  if (!PERSIST) break;
+  pos = next_item(tickets, nw, order != nullptr, &s_pos);
+  }
 }
 
 // Point sums: out[perm[g]] = (w_g if weighted) * sum over the batch's work items (in order).
@@ -992,8 +1050,18 @@ int launch_integrate(const q4c_plan *p, const double *v, int precision, uint32_t
     hipLaunchKernelGGL(k_om, dim3(nb), dim3(256), 0, s, p->dp, v, p->d_om, p->d_chunks);
   }
   if ((rc = check_launch("k_om")) != Q4C_OK) return rc;
-  for (const Pass &ps : p->passes) {
+  const LaunchCfg cfg = p->cfg_contract;
+  const int32_t *order = cfg.order ? p->d_order : nullptr;
+  if (cfg.persistent > 0) {
+    hipLaunchKernelGGL(k_zero_u32, dim3(8), dim3(256), 0, s, p->d_tickets,
+                       (int64_t)p->passes.size() * kTicketsPerLaunch);
+    if ((rc = check_launch("k_zero_u32")) != Q4C_OK) return rc;
+  }
+  for (size_t ip = 0; ip < p->passes.size(); ++ip) {
+    const Pass &ps = p->passes[ip];
     const int64_t nw = ps.w1 - ps.w0, nt = ps.t1 - ps.t0, nr = ps.r1 - ps.r0;
+    unsigned *tickets = cfg.persistent > 0 ? p->d_tickets + ip * kTicketsPerLaunch : nullptr;
+    const unsigned grid = (unsigned)(cfg.persistent > 0 ? std::min<int64_t>(cfg.persistent, nw) : nw);
     double *panel = p->d_staging + ps.staging_len + ps.partial_len;
     if (nt > 0) {
       {
@@ -1006,14 +1074,32 @@ int launch_integrate(const q4c_plan *p, const double *v, int precision, uint32_t
       {
         TimedLaunch tl_(p, Q4C_TIMER_CONTRACT, s);
         if (precision == Q4C_PREC_F64)
-          hipLaunchKernelGGL(k_contract<MODE_F64>, dim3((unsigned)nw), dim3(NT), 0, s, p->dp, p->d_work, ps.w0, nw,
-                             p->d_om, panel, p->d_staging, p->split_tau, p->d_chunks);
+          {
+          if (tickets)
+            hipLaunchKernelGGL((k_contract<MODE_F64, true>), dim3(grid), dim3(NT), 0, s, p->dp, p->d_work, order, ps.w0,
+                               nw, p->d_om, panel, p->d_staging, p->split_tau, p->d_chunks, tickets);
+          else
+            hipLaunchKernelGGL((k_contract<MODE_F64, false>), dim3(grid), dim3(NT), 0, s, p->dp, p->d_work, order, ps.w0,
+                               nw, p->d_om, panel, p->d_staging, p->split_tau, p->d_chunks, tickets);
+        }
         else if (precision == Q4C_PREC_F32)
-          hipLaunchKernelGGL(k_contract<MODE_F32>, dim3((unsigned)nw), dim3(NT), 0, s, p->dp, p->d_work, ps.w0, nw,
-                             p->d_om, panel, p->d_staging, p->split_tau, p->d_chunks);
+          {
+          if (tickets)
+            hipLaunchKernelGGL((k_contract<MODE_F32, true>), dim3(grid), dim3(NT), 0, s, p->dp, p->d_work, order, ps.w0,
+                               nw, p->d_om, panel, p->d_staging, p->split_tau, p->d_chunks, tickets);
+          else
+            hipLaunchKernelGGL((k_contract<MODE_F32, false>), dim3(grid), dim3(NT), 0, s, p->dp, p->d_work, order, ps.w0,
+                               nw, p->d_om, panel, p->d_staging, p->split_tau, p->d_chunks, tickets);
+        }
         else
-          hipLaunchKernelGGL(k_contract<MODE_SPLIT>, dim3((unsigned)nw), dim3(NT), 0, s, p->dp, p->d_work, ps.w0, nw,
-                             p->d_om, panel, p->d_staging, p->split_tau, p->d_chunks);
+          {
+          if (tickets)
+            hipLaunchKernelGGL((k_contract<MODE_SPLIT, true>), dim3(grid), dim3(NT), 0, s, p->dp, p->d_work, order, ps.w0,
+                               nw, p->d_om, panel, p->d_staging, p->split_tau, p->d_chunks, tickets);
+          else
+            hipLaunchKernelGGL((k_contract<MODE_SPLIT, false>), dim3(grid), dim3(NT), 0, s, p->dp, p->d_work, order, ps.w0,
+                               nw, p->d_om, panel, p->d_staging, p->split_tau, p->d_chunks, tickets);
+        }
       }
       if ((rc = check_launch("k_contract")) != Q4C_OK) return rc;
     }
@@ -1056,8 +1142,18 @@ int launch_density(const q4c_plan *p, const double *coef, uint32_t terms, int we
     }
     if ((rc = check_launch("k_fill")) != Q4C_OK) return rc;
   }
-  for (const Pass &ps : p->passes) {
+  const LaunchCfg cfg = p->cfg_density;
+  const int32_t *order = cfg.order ? p->d_order : nullptr;
+  unsigned *tick0 = p->d_tickets + p->passes.size() * kTicketsPerLaunch;
+  if (cfg.persistent > 0) {
+    hipLaunchKernelGGL(k_zero_u32, dim3(8), dim3(256), 0, s, tick0, (int64_t)p->passes.size() * kTicketsPerLaunch);
+    if ((rc = check_launch("k_zero_u32")) != Q4C_OK) return rc;
+  }
+  for (size_t ip = 0; ip < p->passes.size(); ++ip) {
+    const Pass &ps = p->passes[ip];
     const int64_t nr = ps.r1 - ps.r0, nw = ps.w1 - ps.w0, nbt = ps.b1 - ps.b0, nz = ps.z1 - ps.z0, nt = ps.t1 - ps.t0;
+    unsigned *tickets = cfg.persistent > 0 ? tick0 + ip * kTicketsPerLaunch : nullptr;
+    const unsigned grid = (unsigned)(cfg.persistent > 0 ? std::min<int64_t>(cfg.persistent, nw) : nw);
     double *partial = p->d_staging + ps.staging_len;
     double *panel = partial + ps.partial_len;
     if (nz > 0) {
@@ -1086,8 +1182,12 @@ int launch_density(const q4c_plan *p, const double *coef, uint32_t terms, int we
     if (nw > 0) {
       {
         TimedLaunch tl_(p, Q4C_TIMER_DENSITY_TILES, s);
-        hipLaunchKernelGGL(k_density_tiles, dim3((unsigned)nw), dim3(NTD), 0, s, p->dp, terms, p->d_work, ps.w0, nw,
-                           p->d_staging, panel, partial);
+        if (tickets)
+          hipLaunchKernelGGL(k_density_tiles<true>, dim3(grid), dim3(NTD), 0, s, p->dp, terms, p->d_work, order, ps.w0,
+                             nw, p->d_staging, panel, partial, tickets);
+        else
+          hipLaunchKernelGGL(k_density_tiles<false>, dim3(grid), dim3(NTD), 0, s, p->dp, terms, p->d_work, order,
+                             ps.w0, nw, p->d_staging, panel, partial, tickets);
       }
       if ((rc = check_launch("k_density_tiles")) != Q4C_OK) return rc;
     }

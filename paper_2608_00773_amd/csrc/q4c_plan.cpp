@@ -14,7 +14,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <new>
+#include <stdexcept>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -143,6 +145,17 @@ int device_alloc(q4c_plan *p, size_t bytes, void **d) {
 }
 
 void free_device(q4c_plan *p) {
+  if (!p->graphs.empty() || p->capture_stream) {
+    if (p->device >= 0) (void)hipSetDevice(p->device);
+    (void)hipDeviceSynchronize();
+    for (auto &g : p->graphs) {
+      (void)hipGraphExecDestroy(g.exec);
+      (void)hipGraphDestroy(g.graph);
+    }
+    p->graphs.clear();
+    if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
+    p->capture_stream = nullptr;
+  }
   if (p->device >= 0 && (!p->ev_pool.empty() || !p->ev_live.empty())) {
     (void)hipSetDevice(p->device);
     (void)hipDeviceSynchronize();
@@ -198,8 +211,19 @@ int validate(const q4c_basis *b, const q4c_grid *g) {
   return Q4C_OK;
 }
 
-int build_host(q4c_plan *p, const q4c_basis *b, const q4c_grid *g) {
+// sys_atom_off: [n_sys + 1] atom ranges of the independent systems (system-major);
+// pt_sys: system of every grid point (NULL: one system).  Points, batches,
+// relevant atoms and pairs never mix systems.
+int build_host(q4c_plan *p, const q4c_basis *b, const q4c_grid *g, const std::vector<int64_t> &sys_atom_off,
+               const int32_t *pt_sys) {
   const int na = b->n_atoms;
+  const int nsys = (int)sys_atom_off.size() - 1;
+  p->n_systems = nsys;
+  p->atom_sys.assign(na, 0);
+  for (int sy = 0; sy < nsys; ++sy)
+    for (int64_t a = sys_atom_off[sy]; a < sys_atom_off[sy + 1]; ++a) p->atom_sys[a] = sy;
+  p->sys_atom_off = sys_atom_off;
+  auto psys = [&](int64_t i) -> int32_t { return pt_sys ? pt_sys[i] : 0; };
   p->n_atoms = na;
   p->n_shells = b->n_shells;
   p->R.assign(b->R, b->R + 3 * (size_t)na);
@@ -273,8 +297,9 @@ int build_host(q4c_plan *p, const q4c_basis *b, const q4c_grid *g) {
     double q[3] = {g->x[i], g->y[i], g->z[i]};
     double bl[3] = {q[0] - rmax, q[1] - rmax, q[2] - rmax}, bh[3] = {q[0] + rmax, q[1] + rmax, q[2] + rmax};
     bool hit = false;
+    const int32_t sy = psys(i);
     cl.visit_box(bl, bh, [&](int a) {
-      if (hit) return;
+      if (hit || p->atom_sys[a] != sy) return;
       double dx = q[0] - p->R[3 * a], dy = q[1] - p->R[3 * a + 1], dz = q[2] - p->R[3 * a + 2];
       if (dx * dx + dy * dy + dz * dz < p->atom_rcut[a] * p->atom_rcut[a]) hit = true;
     });
@@ -285,7 +310,27 @@ int build_host(q4c_plan *p, const q4c_basis *b, const q4c_grid *g) {
   // batching
   const double *xyz[3] = {g->x, g->y, g->z};
   std::vector<int64_t> ends;
-  if (!active.empty()) bisect(active, 0, (int64_t)active.size(), p->p_max, xyz, ends);
+  // points arrive system-major (user order), so each system's active points
+  // are one contiguous range; each range is bisected on its own
+  p->sys_point_off.assign(nsys + 1, 0);
+  p->sys_batch_off.assign(nsys + 1, 0);
+  {
+    int64_t lo = 0;
+    for (int sy = 0; sy < nsys; ++sy) {
+      int64_t hi = lo;
+      while (hi < (int64_t)active.size() && psys(active[hi]) == sy) ++hi;
+      if (hi > lo) bisect(active, lo, hi, p->p_max, xyz, ends);
+      p->sys_batch_off[sy + 1] = (int64_t)ends.size();
+      lo = hi;
+    }
+    if (lo != (int64_t)active.size()) throw std::invalid_argument("grid points are not ordered by system");
+  }
+  if (pt_sys) {
+    for (int64_t i = 0; i < g->n_points; ++i) p->sys_point_off[pt_sys[i] + 1]++;
+    for (int sy = 0; sy < nsys; ++sy) p->sys_point_off[sy + 1] += p->sys_point_off[sy];
+  } else {
+    p->sys_point_off[1] = g->n_points;
+  }
   p->n_batches = (int64_t)ends.size();
   p->perm = active;
   p->px.resize(p->n_active);
@@ -311,7 +356,7 @@ int build_host(q4c_plan *p, const q4c_basis *b, const q4c_grid *g) {
     double r2 = p->atom_rcut[a] + rmax;
     double bl[3] = {q[0] - r2, q[1] - r2, q[2] - r2}, bh[3] = {q[0] + r2, q[1] + r2, q[2] + r2};
     cl2.visit_box(bl, bh, [&](int c) {
-      if (c < a) return;
+      if (c < a || p->atom_sys[c] != p->atom_sys[a]) return;
       double dx = q[0] - p->R[3 * c], dy = q[1] - p->R[3 * c + 1], dz = q[2] - p->R[3 * c + 2];
       double rc = p->atom_rcut[a] + p->atom_rcut[c];
       if (dx * dx + dy * dy + dz * dz < rc * rc) nb.push_back(c);
@@ -334,6 +379,8 @@ int build_host(q4c_plan *p, const q4c_basis *b, const q4c_grid *g) {
     p->pair_off[q + 1] = p->pair_off[q] + (int64_t)p->pair_na[q] * p->pair_nb[q];
   }
   p->store_len = p->pair_off[p->n_pairs];
+  p->sys_pair_off.assign(nsys + 1, 0);
+  for (int sy = 0; sy < nsys; ++sy) p->sys_pair_off[sy + 1] = p->atom_pair_start[sys_atom_off[sy + 1]];
   auto pair_index = [&](int a, int c) -> int64_t {
     auto beg = p->pair_b.begin() + p->atom_pair_start[a], end = p->pair_b.begin() + p->atom_pair_start[a + 1];
     auto it = std::lower_bound(beg, end, c);
@@ -399,7 +446,9 @@ int build_host(q4c_plan *p, const q4c_basis *b, const q4c_grid *g) {
     }
     double el[3] = {bl[0] - rmax, bl[1] - rmax, bl[2] - rmax}, eh[3] = {bh[0] + rmax, bh[1] + rmax, bh[2] + rmax};
     rel.clear();
+    const int32_t bsys = g1 > g0 ? psys(p->perm[g0]) : 0;
     cl.visit_box(el, eh, [&](int a) {
+      if (p->atom_sys[a] != bsys) return;
       double rc = p->atom_rcut[a], rc2 = rc * rc;
       // distance from the atom to the batch box
       double dmin2 = 0.0, dmax2 = 0.0;
@@ -493,6 +542,25 @@ int build_host(q4c_plan *p, const q4c_basis *b, const q4c_grid *g) {
     p->tab_off[b + 1] = p->tab_off[b] + (int64_t)(p->batch_pt_off[b + 1] - p->batch_pt_off[b]) *
                                             (p->batch_fn_off[b + 1] - p->batch_fn_off[b]);
   p->fn_entries = (int64_t)p->loc_fn.size();
+  // per pass: work items by decreasing estimated cost (padded points x active
+  // rows x active columns; a diagonal tile computes about half its blocks)
+  p->work_order.resize(p->work.size());
+  for (const q4c::Pass &ps : p->passes) {
+    std::vector<std::pair<double, int32_t>> c;
+    c.reserve(ps.w1 - ps.w0);
+    for (int64_t w = ps.w0; w < ps.w1; ++w) {
+      const q4c::WorkItem &it = p->work[w];
+      const int64_t P = p->batch_pt_off[it.batch + 1] - p->batch_pt_off[it.batch];
+      const int n = p->batch_fn_off[it.batch + 1] - p->batch_fn_off[it.batch];
+      const double rows = std::min(T, n - T * it.ti), cols = std::min(T, n - T * it.tj);
+      c.push_back({-(double)q4c::pad16(P) * rows * cols * (it.ti == it.tj ? 0.55 : 1.0), (int32_t)(w - ps.w0)});
+    }
+    std::stable_sort(c.begin(), c.end(),
+                     [](const std::pair<double, int32_t> &x, const std::pair<double, int32_t> &y) {
+                       return x.first < y.first;
+                     });
+    for (size_t i = 0; i < c.size(); ++i) p->work_order[ps.w0 + i] = c[i].second;
+  }
   for (int64_t q = 0; q < p->n_pairs; ++q)
     if (!pair_seen[q]) p->untouched_pairs.push_back((int32_t)q);
   if (p->fn_entries >= (int64_t)INT32_MAX) return fail(Q4C_EINVAL, "too many batch-function entries");
@@ -554,6 +622,7 @@ int build_device(q4c_plan *p) {
   UP(p->red_inc_off, p->d_red_inc_off);
   UP(p->inc_src, p->d_inc_src);
   UP(p->untouched_pairs, p->d_untouched);
+  UP(p->work_order, p->d_order);
 #undef UP
   rc = device_alloc(p, (size_t)p->max_scratch * sizeof(double), (void **)&p->d_staging);
   if (rc != Q4C_OK) return rc;
@@ -564,6 +633,14 @@ int build_device(q4c_plan *p) {
   rc = device_alloc(p, 128 * sizeof(unsigned long long), (void **)&p->d_chunks);
   if (rc != Q4C_OK) return rc;
   if (hipMemset(p->d_chunks, 0, 128 * sizeof(unsigned long long)) != hipSuccess) return fail(Q4C_EHIP, "hipMemset");
+  {
+    const size_t nt = 2 * std::max<size_t>(p->passes.size(), 1) * q4c::kTicketsPerLaunch;
+    rc = device_alloc(p, nt * sizeof(unsigned), (void **)&p->d_tickets);
+    if (rc != Q4C_OK) return rc;
+    if (hipMemset(p->d_tickets, 0, nt * sizeof(unsigned)) != hipSuccess) return fail(Q4C_EHIP, "hipMemset");
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0) p->n_cu = ncu;
+  }
   d.R = R;
   d.fn_atom = fn_atom;
   d.fn_shlm = fn_shlm;
@@ -646,12 +723,11 @@ int hip_fail(hipError_t e, const char *what) {
 
 extern "C" {
 
-int q4c_plan_create(const q4c_basis *basis, const q4c_grid *grid, const q4c_opts *opts, q4c_plan **out) {
-  if (!out) return fail(Q4C_EINVAL, "NULL output handle");
-  *out = nullptr;
-  int rc = validate(basis, grid);
-  if (rc != Q4C_OK) return rc;
+namespace {
+int create_plan(const q4c_basis *basis, const q4c_grid *grid, const q4c_opts *opts,
+                const std::vector<int64_t> &sys_atom_off, const int32_t *pt_sys, q4c_plan **out) {
   q4c_plan *p = nullptr;
+  int rc = Q4C_OK;
   try {
     p = new q4c_plan();
     if (opts) {
@@ -663,7 +739,7 @@ int q4c_plan_create(const q4c_basis *basis, const q4c_grid *grid, const q4c_opts
     }
     if (p->p_max < 1) p->p_max = 300;
     if (p->staging_budget <= 0) p->staging_budget = (int64_t)16 << 30;
-    rc = build_host(p, basis, grid);
+    rc = build_host(p, basis, grid, sys_atom_off, pt_sys);
     if (rc == Q4C_OK && !(p->flags & Q4C_PLAN_HOST_ONLY)) rc = build_device(p);
   } catch (const std::bad_alloc &) {
     rc = fail(Q4C_ENOMEM, "host allocation failed");
@@ -680,6 +756,99 @@ int q4c_plan_create(const q4c_basis *basis, const q4c_grid *grid, const q4c_opts
   *out = p;
   return Q4C_OK;
 }
+}  // namespace
+
+int q4c_plan_create(const q4c_basis *basis, const q4c_grid *grid, const q4c_opts *opts, q4c_plan **out) {
+  if (!out) return fail(Q4C_EINVAL, "NULL output handle");
+  *out = nullptr;
+  int rc = validate(basis, grid);
+  if (rc != Q4C_OK) return rc;
+  return create_plan(basis, grid, opts, std::vector<int64_t>{0, (int64_t)basis->n_atoms}, nullptr, out);
+}
+
+int q4c_plan_create_batched(int32_t n_systems, const q4c_basis *bases, const q4c_grid *grids, const q4c_opts *opts,
+                            q4c_plan **out) {
+  if (!out) return fail(Q4C_EINVAL, "NULL output handle");
+  *out = nullptr;
+  if (n_systems < 1 || !bases || !grids) return fail(Q4C_EINVAL, "need n_systems >= 1 basis and grid descriptors");
+  for (int sy = 0; sy < n_systems; ++sy) {
+    int rc = validate(&bases[sy], &grids[sy]);
+    if (rc != Q4C_OK) return rc;
+  }
+  try {
+    // union descriptors: atoms, shells and points system-major; radial tables
+    // shared between systems that pass the same coefficient array
+    std::vector<double> R, coef, rcut, x, y, z, w;
+    std::vector<int32_t> aso{0}, sl, sn, pt_sys;
+    std::vector<int64_t> sco, sys_atom_off{0};
+    std::vector<std::pair<std::pair<const double *, int64_t>, int64_t>> coef_seen;
+    int64_t np = 0;
+    for (int sy = 0; sy < n_systems; ++sy) np += grids[sy].n_points;
+    if (np >= (int64_t)INT32_MAX) return fail(Q4C_EINVAL, "more than 2^31-1 grid points in total");
+    for (int sy = 0; sy < n_systems; ++sy) {
+      const q4c_basis &b = bases[sy];
+      const q4c_grid &g = grids[sy];
+      int64_t cbase = -1;
+      for (auto &e : coef_seen)
+        if (e.first.first == b.coef && e.first.second == b.n_coef) cbase = e.second;
+      if (cbase < 0) {
+        cbase = (int64_t)coef.size();
+        if (b.n_coef > 0) coef.insert(coef.end(), b.coef, b.coef + b.n_coef);
+        coef_seen.push_back({{b.coef, b.n_coef}, cbase});
+      }
+      const int32_t s0 = (int32_t)sl.size();
+      R.insert(R.end(), b.R, b.R + 3 * (size_t)b.n_atoms);
+      for (int a = 0; a < b.n_atoms; ++a) aso.push_back(s0 + b.atom_shell_off[a + 1]);
+      for (int s = 0; s < b.n_shells; ++s) {
+        sl.push_back(b.shell_l[s]);
+        rcut.push_back(b.shell_rcut[s]);
+        sn.push_back(b.shell_nint[s]);
+        sco.push_back(cbase + b.shell_coef_off[s]);
+      }
+      sys_atom_off.push_back(sys_atom_off.back() + b.n_atoms);
+      if (g.n_points > 0) {
+        x.insert(x.end(), g.x, g.x + g.n_points);
+        y.insert(y.end(), g.y, g.y + g.n_points);
+        z.insert(z.end(), g.z, g.z + g.n_points);
+        w.insert(w.end(), g.w, g.w + g.n_points);
+        pt_sys.insert(pt_sys.end(), (size_t)g.n_points, sy);
+      }
+    }
+    q4c_basis ub{};
+    ub.n_atoms = (int32_t)(R.size() / 3);
+    ub.R = R.data();
+    ub.atom_shell_off = aso.data();
+    ub.n_shells = (int32_t)sl.size();
+    ub.shell_l = sl.data();
+    ub.shell_rcut = rcut.data();
+    ub.shell_nint = sn.data();
+    ub.shell_coef_off = sco.data();
+    ub.n_coef = (int64_t)coef.size();
+    ub.coef = coef.data();
+    q4c_grid ug{};
+    ug.n_points = np;
+    ug.x = x.data();
+    ug.y = y.data();
+    ug.z = z.data();
+    ug.w = w.data();
+    return create_plan(&ub, &ug, opts, sys_atom_off, pt_sys.data(), out);
+  } catch (const std::bad_alloc &) {
+    return fail(Q4C_ENOMEM, "host allocation failed");
+  }
+}
+
+int q4c_plan_systems(const q4c_plan *p, int64_t *atom_off, int64_t *point_off, int64_t *batch_off,
+                     int64_t *pair_off, int64_t *store_off) {
+  if (!p) return fail(Q4C_EINVAL, "NULL plan");
+  for (int sy = 0; sy <= p->n_systems; ++sy) {
+    if (atom_off) atom_off[sy] = p->sys_atom_off[sy];
+    if (point_off) point_off[sy] = p->sys_point_off[sy];
+    if (batch_off) batch_off[sy] = p->sys_batch_off[sy];
+    if (pair_off) pair_off[sy] = p->sys_pair_off[sy];
+    if (store_off) store_off[sy] = p->pair_off[p->sys_pair_off[sy]];
+  }
+  return Q4C_OK;
+}
 
 void q4c_plan_destroy(q4c_plan *plan) {
   if (!plan) return;
@@ -690,6 +859,7 @@ void q4c_plan_destroy(q4c_plan *plan) {
 int q4c_plan_info(const q4c_plan *p, q4c_info *info) {
   if (!p || !info) return fail(Q4C_EINVAL, "NULL argument");
   info->n_atoms = p->n_atoms;
+  info->n_systems = p->n_systems;
   info->n_fn = p->n_fn;
   info->n_points = p->n_points;
   info->n_active = p->n_active;
@@ -753,6 +923,65 @@ int nao_tabulate(const q4c_plan *p, int64_t b0, int64_t b1, int32_t deriv, doubl
   return q4c::launch_tabulate(p, b0, b1, deriv, out_dev, (hipStream_t)stream);
 }
 
+namespace {
+// Replays one captured HIP graph per distinct call (kind, buffers, options);
+// the first call of each captures the launch sequence on the plan's capture
+// stream.  Graphs never contain memset nodes: all clearing is done by kernels.
+int run_graph(const q4c_plan *p, int kind, const void *in, void *o0, void *o1, void *o2, int64_t a, int64_t b,
+              int64_t c, hipStream_t user, const std::function<int(hipStream_t)> &body) {
+  using GE = q4c_plan::GraphEntry;
+  const GE *hit = nullptr;
+  for (const GE &g : p->graphs)
+    if (g.kind == kind && g.in == in && g.out0 == o0 && g.out1 == o1 && g.out2 == o2 && g.a == a && g.b == b &&
+        g.c == c)
+      hit = &g;
+  if (!hit) {
+    hipError_t e;
+    if (!p->capture_stream) {
+      e = hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking);
+      if (e != hipSuccess) return q4c::hip_fail(e, "hipStreamCreateWithFlags");
+    }
+    e = hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return q4c::hip_fail(e, "hipStreamBeginCapture");
+    const int rc = body(p->capture_stream);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(p->capture_stream, &graph);
+    if (rc != Q4C_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    if (e != hipSuccess) return q4c::hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      return q4c::hip_fail(e, "hipGraphInstantiate");
+    }
+    if (p->graphs.size() >= 16) {  // bounded cache: drop the oldest once nothing runs
+      (void)hipDeviceSynchronize();
+      (void)hipGraphExecDestroy(p->graphs.front().exec);
+      (void)hipGraphDestroy(p->graphs.front().graph);
+      p->graphs.erase(p->graphs.begin());
+    }
+    p->graphs.push_back(GE{kind, in, o0, o1, o2, a, b, c, graph, exec});
+    hit = &p->graphs.back();
+  }
+  hipError_t e = hipGraphLaunch(hit->exec, user);
+  if (e != hipSuccess) return q4c::hip_fail(e, "hipGraphLaunch");
+  return Q4C_OK;
+}
+
+void drop_graphs(q4c_plan *p) {
+  if (p->graphs.empty()) return;
+  (void)hipDeviceSynchronize();
+  for (auto &g : p->graphs) {
+    (void)hipGraphExecDestroy(g.exec);
+    (void)hipGraphDestroy(g.graph);
+  }
+  p->graphs.clear();
+}
+}  // namespace
+
 int q4c_integrate_H(const q4c_plan *p, const double *v_dev, int32_t precision, uint32_t flags, double *store_dev,
                     double *spin_w_dev, double *spin_v_dev, void *stream) {
   if (!p) return fail(Q4C_EINVAL, "NULL plan");
@@ -772,6 +1001,13 @@ int q4c_integrate_H(const q4c_plan *p, const double *v_dev, int32_t precision, u
     if (rc != Q4C_OK) return rc;
     if (!ok) return fail(Q4C_ENONFINITE, "potential contains NaN or Inf");
   }
+  if (p->use_graphs && !p->profiling) {
+    const uint32_t f = flags & ~(uint32_t)Q4C_CHECK_FINITE;
+    return run_graph(p, 0, v_dev, store_dev, spin_w_dev, spin_v_dev, precision, f, 0, (hipStream_t)stream,
+                     [&](hipStream_t cs) {
+                       return q4c::launch_integrate(p, v_dev, precision, f, store_dev, spin_w_dev, spin_v_dev, cs);
+                     });
+  }
   return q4c::launch_integrate(p, v_dev, precision, flags, store_dev, spin_w_dev, spin_v_dev, (hipStream_t)stream);
 }
 
@@ -784,7 +1020,117 @@ int density_on_grid(const q4c_plan *p, const double *coef_dev, uint32_t terms, i
   if (p->n_points > 0 && !out_dev) return fail(Q4C_EINVAL, "NULL output");
   int rc = check_plan_dev(p);
   if (rc != Q4C_OK) return rc;
+  if (p->use_graphs && !p->profiling)
+    return run_graph(p, 1, coef_dev, out_dev, nullptr, nullptr, terms, weight_mode, 0, (hipStream_t)stream,
+                     [&](hipStream_t cs) { return q4c::launch_density(p, coef_dev, terms, weight_mode, out_dev, cs); });
   return q4c::launch_density(p, coef_dev, terms, weight_mode, out_dev, (hipStream_t)stream);
+}
+
+int q4c_plan_set_graphs(q4c_plan *p, int enable) {
+  int rc = check_plan_dev(p);
+  if (rc != Q4C_OK) return rc;
+  drop_graphs(p);
+  p->use_graphs = enable != 0;
+  return Q4C_OK;
+}
+
+int q4c_plan_set_launch(q4c_plan *p, int32_t kernel, int32_t order, int32_t persistent) {
+  int rc = check_plan_dev(p);
+  if (rc != Q4C_OK) return rc;
+  if (kernel != Q4C_KERNEL_CONTRACT && kernel != Q4C_KERNEL_DENSITY) return fail(Q4C_EINVAL, "unknown kernel");
+  if (order != 0 && order != 1) return fail(Q4C_EINVAL, "order must be 0 or 1");
+  if (persistent < 0 || persistent > 65535) return fail(Q4C_EINVAL, "persistent workgroups must be in 0..65535");
+  drop_graphs(p);
+  q4c::LaunchCfg &c = kernel == Q4C_KERNEL_CONTRACT ? p->cfg_contract : p->cfg_density;
+  c.order = order;
+  c.persistent = persistent;
+  return Q4C_OK;
+}
+
+int q4c_plan_get_launch(const q4c_plan *p, int32_t kernel, int32_t *order, int32_t *persistent) {
+  if (!p || !order || !persistent) return fail(Q4C_EINVAL, "NULL argument");
+  if (kernel != Q4C_KERNEL_CONTRACT && kernel != Q4C_KERNEL_DENSITY) return fail(Q4C_EINVAL, "unknown kernel");
+  const q4c::LaunchCfg &c = kernel == Q4C_KERNEL_CONTRACT ? p->cfg_contract : p->cfg_density;
+  *order = c.order;
+  *persistent = c.persistent;
+  return Q4C_OK;
+}
+
+int q4c_plan_autotune(q4c_plan *p, const double *v_dev, int32_t precision, double *store_dev, const double *coef_dev,
+                      double *out_dev, int32_t reps, q4c_tune_entry *table, int32_t table_len, int32_t *n_entries,
+                      void *stream) {
+  int rc = check_plan_dev(p);
+  if (rc != Q4C_OK) return rc;
+  if (precision != Q4C_PREC_F64 && precision != Q4C_PREC_SPLIT_F32 && precision != Q4C_PREC_F32)
+    return fail(Q4C_EINVAL, "unknown precision");
+  if ((p->n_points > 0 && !v_dev) || (p->store_len > 0 && !store_dev))
+    return fail(Q4C_EINVAL, "the potential and a store buffer are required");
+  if ((coef_dev == nullptr) != (out_dev == nullptr)) return fail(Q4C_EINVAL, "coef_dev and out_dev go together");
+  if (reps < 1) reps = 3;
+  const hipStream_t s = (hipStream_t)stream;
+  const bool prof = p->profiling, graphs = p->use_graphs;
+  p->profiling = false;
+  p->use_graphs = false;
+  drop_graphs(p);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return q4c::hip_fail(hipGetLastError(), "hipEventCreate");
+  int n_out = 0;
+  auto time_call = [&](const std::function<int()> &call, double *ms) -> int {
+    int r = call();  // warm-up
+    if (r != Q4C_OK) return r;
+    std::vector<double> t;
+    for (int i = 0; i < reps; ++i) {
+      hipError_t e = hipEventRecord(e0, s);
+      if (e != hipSuccess) return q4c::hip_fail(e, "hipEventRecord");
+      r = call();
+      if (r != Q4C_OK) return r;
+      e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float f = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&f, e0, e1);
+      if (e != hipSuccess) return q4c::hip_fail(e, "hipEvent timing");
+      t.push_back(f);
+    }
+    std::sort(t.begin(), t.end());
+    *ms = t[t.size() / 2];
+    return Q4C_OK;
+  };
+  for (int kernel = 0; kernel < 2 && rc == Q4C_OK; ++kernel) {
+    if (kernel == Q4C_KERNEL_DENSITY && !coef_dev) break;
+    // workgroups that fit on the chip at once: two per CU for the FP64
+    // contraction, one per CU for the split contraction and the adjoint
+    const int occ = (kernel == Q4C_KERNEL_CONTRACT && precision == Q4C_PREC_F64) ? 2 : 1;
+    const int cand_p[3] = {0, occ * p->n_cu, 2 * occ * p->n_cu};
+    q4c::LaunchCfg best{};
+    double best_ms = 1e300;
+    for (int order = 0; order < 2 && rc == Q4C_OK; ++order)
+      for (int ip = 0; ip < 3 && rc == Q4C_OK; ++ip) {
+        q4c::LaunchCfg &c = kernel == Q4C_KERNEL_CONTRACT ? p->cfg_contract : p->cfg_density;
+        c.order = order;
+        c.persistent = cand_p[ip];
+        double ms = 0.0;
+        if (kernel == Q4C_KERNEL_CONTRACT)
+          rc = time_call([&] { return q4c::launch_integrate(p, v_dev, precision, 0, store_dev, nullptr, nullptr, s); },
+                         &ms);
+        else
+          rc = time_call([&] { return q4c::launch_density(p, coef_dev, Q4C_TERM_ALL, 1, out_dev, s); }, &ms);
+        if (rc != Q4C_OK) break;
+        if (table && n_out < table_len) table[n_out] = q4c_tune_entry{kernel, order, cand_p[ip], ms};
+        ++n_out;
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = c;
+        }
+      }
+    (kernel == Q4C_KERNEL_CONTRACT ? p->cfg_contract : p->cfg_density) = best;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  p->profiling = prof;
+  p->use_graphs = graphs;
+  if (n_entries) *n_entries = n_out;
+  return rc;
 }
 
 int q4c_coef_from_spinor(const q4c_plan *p, const double *spin_d_dev, double *coef_out_dev, void *stream) {

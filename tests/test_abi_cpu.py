@@ -157,3 +157,55 @@ def test_staging_passes_split_by_budget():
     assert p1.info["n_passes"] == 1
     assert p2.info["n_passes"] > 1
     assert p1.info["n_work"] == p2.info["n_work"]
+
+
+def _small_molecules(n_mol=5, seed_sizes=(8, 14, 9, 11, 8)):
+    return W.config_molecules(n_mol=n_mol, sizes=list(seed_sizes[:n_mol]), nrad=12, nang=26)
+
+
+def test_batched_plan_reproduces_each_system():
+    """q4c_plan_create_batched: each system's batches (point sets, relevant
+    functions), pairs and store offsets are exactly those of its own plan,
+    shifted by the system offsets."""
+    q, lib = _lib()
+    wl = _small_molecules()
+    systems = W.split_molecules(wl)
+    pb = q.Plan(systems, host_only=True)
+    assert pb.info["n_systems"] == len(systems)
+    off = pb.systems()
+    pairs_b, po_b = pb.pairs()
+    pt_b, pidx_b, fo_b, fidx_b = pb.batches()
+    fn_off = 0
+    for s, ws in enumerate(systems):
+        p = q.Plan(ws, host_only=True)
+        assert off["atom"][s + 1] - off["atom"][s] == ws.n_atoms
+        assert off["point"][s + 1] - off["point"][s] == ws.n_points
+        pairs, po = p.pairs()
+        a0, a1 = off["pair"][s], off["pair"][s + 1]
+        assert np.array_equal(pairs_b[a0:a1] - off["atom"][s], pairs)
+        assert np.array_equal(po_b[a0:a1 + 1] - po_b[a0], po)
+        assert off["store"][s] == po_b[a0]
+        pt, pidx, fo, fidx = p.batches()
+        b0, b1 = off["batch"][s], off["batch"][s + 1]
+        assert b1 - b0 == p.info["n_batches"]
+        for b in range(b1 - b0):
+            got = pidx_b[pt_b[b0 + b]:pt_b[b0 + b + 1]] - off["point"][s]
+            assert np.array_equal(got, pidx[pt[b]:pt[b + 1]])
+            gotf = fidx_b[fo_b[b0 + b]:fo_b[b0 + b + 1]] - fn_off
+            assert np.array_equal(gotf, fidx[fo[b]:fo[b + 1]])
+        fn_off += ws.n_fn
+    # the systems' pairs never couple two systems
+    mol = wl.molecule
+    assert np.all(mol[pairs_b[:, 0]] == mol[pairs_b[:, 1]])
+
+
+def test_batched_plan_validation():
+    q, lib = _lib()
+    h = ctypes.c_void_p()
+    assert lib.q4c_plan_create_batched(0, None, None, None, ctypes.byref(h)) == q.Q4C_EINVAL
+    assert lib.q4c_plan_set_launch(None, 0, 0, 0) == q.Q4C_EINVAL
+    wl = _small_molecules(n_mol=2)
+    p = q.Plan(W.split_molecules(wl), host_only=True)
+    assert lib.q4c_plan_set_launch(p.handle, 0, 0, 0) == q.Q4C_ENODEV
+    assert lib.q4c_plan_set_graphs(p.handle, 1) == q.Q4C_ENODEV
+    assert lib.q4c_plan_autotune(p.handle, None, 0, None, None, None, 1, None, 0, None, None) == q.Q4C_ENODEV

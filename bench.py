@@ -46,11 +46,16 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", choices=sorted(PREC), default="f64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch shapes (one workgroup per work item) and eager launches")
     ap.add_argument("--cpu-sample", type=float, default=0.05, help="fraction of grid points for the oracle timing")
     ap.add_argument("--n-atoms", type=int, default=120)
     ap.add_argument("--mode", choices=["full", "step", "forward", "adjoint"], default="full",
                     help="step/forward/adjoint: run only the whole step or that one call `steps` times "
                          "(for profiler runs) and print its time")
+    ap.add_argument("--workload", choices=["cluster", "molecules"], default="cluster",
+                    help="molecules: 64 independent molecules (8..80 atoms), one batched plan (autotuned launch "
+                         "shapes, HIP graph replay) against 64 sequential per-molecule plans; prints its own line")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before the work, run one elementwise copy of this many MiB (read once, written once): "
                          "the reference dispatch for scaling HBM byte counters")
@@ -88,12 +93,131 @@ def cpu_baseline(wl, frac: float, seed: int = 6002):
                       (idx.size, wl.n_points, n_act, seed, len(pairs), dt)}
 
 
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def bench_molecules(a):
+    """64 independent molecules: one batched plan (all systems' batches in the
+    same launches, autotuned launch shapes, each call one HIP graph launch)
+    against 64 per-molecule plans called one after another."""
+    import numpy as np
+    import torch
+    import paper_2608_00773_amd as q
+    import workload as W
+
+    t0 = time.perf_counter()
+    wl = W.config_molecules()
+    systems = W.split_molecules(wl)
+    log("workload: %d molecules, %d atoms, %d points (%.1f s)" % (len(systems), wl.n_atoms, wl.n_points,
+                                                                    time.perf_counter() - t0))
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    pb = q.Plan(systems)
+    t_plan_b = time.perf_counter() - t0
+    log("batched plan: %s (%.1f s)" % (pb.info, t_plan_b))
+    t0 = time.perf_counter()
+    seq = [q.Plan(s, staging_bytes=2 << 30) for s in systems]
+    t_plan_s = time.perf_counter() - t0
+    log("64 sequential plans (%.1f s), scratch %.1f GiB in total" %
+        (t_plan_s, sum(p.info["scratch_bytes"] for p in seq) / 2 ** 30))
+    off = pb.systems()
+    v = torch.from_numpy(np.concatenate([s.v for s in systems])).to(dev)
+    rng = np.random.default_rng(5004)
+    L = pb.info["store_len"]
+    coef = torch.from_numpy(rng.standard_normal((5, L))).to(dev)
+    st_b, sp_b = q.new_store(pb, dev), q.new_spinor(pb, dev)
+    out_b = torch.empty(pb.info["n_points"], dtype=torch.float64, device=dev)
+    st_s, sp_s = q.new_store(pb, dev), q.new_spinor(pb, dev)
+    out_s = torch.empty_like(out_b)
+    sl = [(int(off["store"][i]), int(off["store"][i + 1]), int(off["point"][i]), int(off["point"][i + 1]))
+          for i in range(len(systems))]
+    # per-molecule views of one set of buffers (contiguous slices)
+    v_s = [v[g0:g1] for (_, _, g0, g1) in sl]
+    coef_s = [coef[:, s0:s1].contiguous() for (s0, s1, _, _) in sl]
+    st_m = [q.new_store(p, dev) for p in seq]
+    sp_m = [sp_s[4 * s0:4 * s1] for (s0, s1, _, _) in sl]
+    out_m = [out_s[g0:g1] for (_, _, g0, g1) in sl]
+
+    def timed(fn, k):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(k):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    def seq_fwd():
+        for i, p in enumerate(seq):
+            q.q4c_integrate_H(p, v_s[i], q.PREC_F64, q.ASSEMBLE_W, st_m[i], sp_m[i])
+
+    def seq_adj():
+        for i, p in enumerate(seq):
+            q.density_on_grid(p, coef_s[i], q.TERM_ALL, 1, out_m[i])
+
+    fwd_b = lambda: q.q4c_integrate_H(pb, v, q.PREC_F64, q.ASSEMBLE_W, st_b, sp_b)
+    adj_b = lambda: q.density_on_grid(pb, coef, q.TERM_ALL, 1, out_b)
+
+    k = max(1, a.steps // 4)
+    seq_fwd(); seq_adj()
+    r = {"seq_forward_ms": timed(seq_fwd, k), "seq_adjoint_ms": timed(seq_adj, k)}
+    log("sequential: %s" % r)
+    fwd_b(); adj_b()
+    r["batched_default_forward_ms"] = timed(fwd_b, k)
+    r["batched_default_adjoint_ms"] = timed(adj_b, k)
+    log("batched, default launch: %s" % r)
+    t0 = time.perf_counter()
+    table = pb.autotune(v, st_b, q.PREC_F64, coef, out_b, reps=3)
+    t_tune = time.perf_counter() - t0
+    log("autotune (%.1f s): %s" % (t_tune, table))
+    pb.set_graphs(True)
+    fwd_b(); adj_b()
+    r["batched_forward_ms"] = timed(fwd_b, k)
+    r["batched_adjoint_ms"] = timed(adj_b, k)
+    torch.cuda.synchronize()
+    same = all(torch.equal(st_b[:, s0:s1], st_m[i]) for i, (s0, s1, _, _) in enumerate(sl))
+    same = same and torch.equal(sp_b, sp_s) and torch.equal(out_b, out_s)
+    n_act = pb.info["n_active"]
+    res = {
+        "mode": "molecules",
+        "workload": "%d independent molecules of %d..%d atoms (%d atoms, %d NAOs), %d points (%d active), "
+                    "60 x 302 points per atom" % (len(systems), min(wl.meta["sizes"]), max(wl.meta["sizes"]),
+                                                  wl.n_atoms, pb.info["n_fn"], wl.n_points, n_act),
+        "unit": "active points/s",
+        "sequential_forward_points_per_s": n_act / (r["seq_forward_ms"] * 1e-3),
+        "batched_forward_points_per_s": n_act / (r["batched_forward_ms"] * 1e-3),
+        "forward_speedup": r["seq_forward_ms"] / r["batched_forward_ms"],
+        "sequential_step_points_per_s": n_act / ((r["seq_forward_ms"] + r["seq_adjoint_ms"]) * 1e-3),
+        "batched_step_points_per_s": n_act / ((r["batched_forward_ms"] + r["batched_adjoint_ms"]) * 1e-3),
+        "step_speedup": (r["seq_forward_ms"] + r["seq_adjoint_ms"]) / (r["batched_forward_ms"] +
+                                                                        r["batched_adjoint_ms"]),
+        "ms": r,
+        "flops_alg_batched": pb.info["flops_alg"],
+        "contract_tflops_alg_batched": pb.info["flops_alg"] / (r["batched_forward_ms"] * 1e-3) / 1e12,
+        "batched_launch": {"contract": pb.get_launch(q.KERNEL_CONTRACT), "density": pb.get_launch(q.KERNEL_DENSITY),
+                           "graphs": True},
+        "autotune_table": table,
+        "autotune_s": t_tune,
+        "bitwise_equal_to_sequential": bool(same),
+        "plan_s": {"batched": t_plan_b, "sequential": t_plan_s},
+        "scratch_gib": {"batched": pb.info["scratch_bytes"] / 2 ** 30,
+                        "sequential_total": sum(p.info["scratch_bytes"] for p in seq) / 2 ** 30},
+        "steps": k,
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
         print("bench.py measures one GPU only; this build has no multi-GPU path (requested --gpus %d)" % a.gpus,
               file=sys.stderr)
         sys.exit(2)
+    if a.workload == "molecules":
+        bench_molecules(a)
+        return
     import numpy as np
     import torch
     import paper_2608_00773_amd as q
@@ -119,6 +243,15 @@ def main():
     def step(p):
         q.q4c_integrate_H(plan, v, p, q.ASSEMBLE_W, store, spin)
         q.density_on_grid(plan, gbar, q.TERM_ALL, 1, grad)
+
+    tune = None
+    if not a.no_autotune:
+        # launch shapes of both contraction kernels picked on this plan (not timed);
+        # every later call is one HIP graph launch
+        t0 = time.perf_counter()
+        tune = plan.autotune(v, store, prec, gbar, grad, reps=3)
+        plan.set_graphs(True)
+        print("[bench] autotune %.1f s: %s" % (time.perf_counter() - t0, tune), file=sys.stderr, flush=True)
 
     def timed(fn, k):
         torch.cuda.synchronize()
@@ -179,7 +312,9 @@ def main():
     hot = {}
     for name, p in PREC.items():
         st = q.new_store(plan, dev)
-        fwd[name] = timed(lambda: q.q4c_integrate_H(plan, v, p, q.ASSEMBLE_W, st, spin), max(3, a.steps // 4))
+        call = lambda: q.q4c_integrate_H(plan, v, p, q.ASSEMBLE_W, st, spin)
+        call()  # untimed first call (captures its graph when graphs are on)
+        fwd[name] = timed(call, max(3, a.steps // 4))
         outs[name] = st
         if name != "f64":
             h, t = plan.split_stats()
@@ -224,6 +359,8 @@ def main():
             "avg_launch_ms": t_contract * 1e3,
             "launches_per_step": launches_per_step,
         },
+        "launch": {"contract": plan.get_launch(q.KERNEL_CONTRACT), "density": plan.get_launch(q.KERNEL_DENSITY),
+                   "graphs": tune is not None, "autotune_table": tune},
         "kernels_ms_per_step": {k: v_[0] / a.steps for k, v_ in tim.items() if v_[1]},
         "forward_ms": fwd,
         "forward_points_per_s": {k: n_act / (t * 1e-3) for k, t in fwd.items()},

@@ -140,6 +140,7 @@ typedef struct {
   int64_t device_bytes;    /* device memory owned by the plan */
   double flops_alg;        /* sum_B 10 P_B n_B^2, the algorithmic flop count of one H build */
   int32_t n_systems;       /* independent systems (1 unless q4c_plan_create_batched) */
+  int64_t scratch_bytes;   /* device scratch of the plan (largest pass: staging, partials, panels) */
 } q4c_info;
 
 /* Build a plan: batching (recursive median bisection of the active points to

@@ -65,7 +65,8 @@ class _Info(ctypes.Structure):
                 ("n_active", ctypes.c_int64), ("n_batches", ctypes.c_int64), ("n_pairs", ctypes.c_int64),
                 ("store_len", ctypes.c_int64), ("fn_entries", ctypes.c_int64), ("max_batch_points", ctypes.c_int64),
                 ("max_batch_fn", ctypes.c_int64), ("n_work", ctypes.c_int64), ("n_passes", ctypes.c_int64),
-                ("device_bytes", ctypes.c_int64), ("flops_alg", ctypes.c_double), ("n_systems", ctypes.c_int32)]
+                ("device_bytes", ctypes.c_int64), ("flops_alg", ctypes.c_double), ("n_systems", ctypes.c_int32),
+                ("scratch_bytes", ctypes.c_int64)]
 
 
 class _TuneEntry(ctypes.Structure):

@@ -721,8 +721,11 @@ __global__ __launch_bounds__(NT, MODE == 0 ? 2 : 1) void k_contract(DevPlan d, c
 }
 
 // Batch-to-global sum for one pass: reduction entry r adds the staged blocks
-// of pair red_pair[r] in batch order.  Loads of four incidences are issued
-// together; their sum order is fixed, so results repeat bit for bit.
+// of pair red_pair[r] in batch order, one after another onto the running
+// value (zero, or the stored value when a previous pass or ACCUMULATE left
+// one).  The sum is a single sequential chain in batch order, so results
+// repeat bit for bit and do not depend on how batches are split into passes.
+// Loads of four incidences are issued together.
 __global__ void k_reduce(DevPlan d, int64_t r0, const int32_t *red_pair, const uint8_t *red_first,
                          const int64_t *red_inc_off, const int64_t *inc_src, const double *staging, double *store,
                          int accumulate) {
@@ -733,17 +736,20 @@ __global__ void k_reduce(DevPlan d, int64_t r0, const int32_t *red_pair, const u
   const bool add = accumulate || !red_first[r];
   const int64_t po = d.pair_off[p];
   for (int64_t e = threadIdx.x; e < 5 * blk; e += blockDim.x) {
-    double s = 0.0;
+    const int q = (int)(e / blk);
+    double *dst = store + q * d.store_len + po + (e - q * blk);
+    double s = add ? *dst : 0.0;
     int64_t k = k0;
     for (; k + 4 <= k1; k += 4) {
       const double a0 = staging[inc_src[k] + e], a1 = staging[inc_src[k + 1] + e];
       const double a2 = staging[inc_src[k + 2] + e], a3 = staging[inc_src[k + 3] + e];
-      s += (a0 + a1) + (a2 + a3);
+      s += a0;
+      s += a1;
+      s += a2;
+      s += a3;
     }
     for (; k < k1; ++k) s += staging[inc_src[k] + e];
-    const int q = (int)(e / blk);
-    double *dst = store + q * d.store_len + po + (e - q * blk);
-    *dst = add ? *dst + s : s;
+    *dst = s;
   }
 }
 

@@ -860,6 +860,7 @@ int q4c_plan_info(const q4c_plan *p, q4c_info *info) {
   if (!p || !info) return fail(Q4C_EINVAL, "NULL argument");
   info->n_atoms = p->n_atoms;
   info->n_systems = p->n_systems;
+  info->scratch_bytes = p->max_scratch * (int64_t)sizeof(double);
   info->n_fn = p->n_fn;
   info->n_points = p->n_points;
   info->n_active = p->n_active;

@@ -1,0 +1,190 @@
+"""Full-size checks on the two perovskite-like slabs, in the default launch
+configuration of the library.
+
+* 1,000-atom slab (7,520 NAOs, 8,598,400 points): FP64 blocks against the
+  oracle on sampled atom pairs; split-FP32 within 1e-8 Ha on every stored
+  element (against the FP64 path) and on the sampled blocks (against the
+  oracle); the adjoint at sampled points; the adjoint dot-product identity.
+  Runs by default (about a minute, most of it input generation).
+* 3,383-atom (6x6)x2 slab (24,454 NAOs, 16,907,640 points): the same forward
+  checks, then, for the seeded sparse Hermitian spinor D within the pair
+  cutoff, dL/dv of L = Re Tr(D H(v)) against finite differences at 32 seeded
+  points with the split-FP32 forward, and against the oracle's density at
+  sampled points.  Takes several minutes: runs with Q4C_LARGE_TESTS=1.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workload as W
+from helpers import gpu_available, spinor_from_blocks
+
+pytestmark = pytest.mark.gpu
+LARGE = os.environ.get("Q4C_LARGE_TESTS") == "1"
+
+
+def _env(make):
+    if not gpu_available():
+        pytest.skip("no GPU")
+    import torch
+    import paper_2608_00773_amd as q
+    wl = make()
+    plan = q.Plan(wl)
+    print("plan:", plan.info, flush=True)
+    v = torch.from_numpy(wl.v).cuda()
+    store = q.new_store(plan)
+    q.q4c_integrate_H(plan, v, q.PREC_F64, 0, store)
+    torch.cuda.synchronize()
+    pairs, po = plan.pairs()
+    return dict(q=q, torch=torch, wl=wl, plan=plan, v=v, store=store, pairs=pairs, po=po)
+
+
+@pytest.fixture(scope="module")
+def slab():
+    return _env(W.config_slab)
+
+
+@pytest.fixture(scope="module")
+def pepi():
+    if not LARGE:
+        pytest.skip("3,383-atom slab takes several minutes: set Q4C_LARGE_TESTS=1")
+    return _env(W.config_pepi_3383)
+
+
+def _sample_pairs(wl, pairs, seed, k=8):
+    """A seeded mix of diagonal heavy, heavy-heavy, heavy-light and light-light pairs."""
+    rng = np.random.default_rng(seed)
+    heavy = wl.Z >= 21
+    a, b = pairs[:, 0], pairs[:, 1]
+    groups = [(a == b) & heavy[a], (a != b) & heavy[a] & heavy[b], (a != b) & (heavy[a] ^ heavy[b]),
+              (a != b) & ~heavy[a] & ~heavy[b]]
+    out = []
+    for g in groups:
+        idx = np.nonzero(g)[0]
+        if idx.size:
+            out.extend(rng.choice(idx, size=min(k // 4, idx.size), replace=False).tolist())
+    return np.array(sorted(set(out)))
+
+
+def _check_f64_blocks(env, seed):
+    wl, pairs, po = env["wl"], env["pairs"], env["po"]
+    st = env["store"].cpu().numpy()
+    sel = _sample_pairs(wl, pairs, seed)
+    ref, scale = oracle.pair_blocks(wl, pairs[sel], with_abs=True)
+    nfn = wl.atom_nfn()
+    worst = 0.0
+    for k, p in enumerate(sel):
+        a, b = pairs[p]
+        g = st[:, po[p]:po[p + 1]].reshape(5, nfn[a], nfn[b])
+        nz = scale[k] > 0
+        assert np.all(g[~nz] == ref[k][~nz])
+        worst = max(worst, float(np.max(np.abs(g - ref[k])[nz] / scale[k][nz])))
+    print("FP64 worst |d| / A_ij on %d sampled pairs: %.3g" % (len(sel), worst), flush=True)
+    assert worst <= 1e-12, worst
+    return sel, ref
+
+
+def _check_split(env, sel, ref):
+    q, torch, wl, plan, pairs, po = env["q"], env["torch"], env["wl"], env["plan"], env["pairs"], env["po"]
+    f64 = env["store"]
+    nfn = wl.atom_nfn()
+    for prec in (q.PREC_SPLIT_F32, q.PREC_F32):
+        st = q.new_store(plan)
+        q.q4c_integrate_H(plan, env["v"], prec, 0, st)
+        torch.cuda.synchronize()
+        hot, tot = plan.split_stats()
+        d_all = float(torch.max(torch.abs(st - f64)))
+        assert torch.equal(st[0], f64[0])
+        s = st.cpu().numpy()
+        err = 0.0
+        for k, p in enumerate(sel):
+            a, b = pairs[p]
+            err = max(err, float(np.max(np.abs(s[:, po[p]:po[p + 1]].reshape(5, nfn[a], nfn[b]) - ref[k]))))
+        print("precision %d: max |split - f64| over all %d elements %.3g Ha, vs oracle on samples %.3g Ha, "
+              "%d of %d chunks on FP64" % (prec, 5 * plan.info["store_len"], d_all, err, hot, tot), flush=True)
+        assert d_all <= 1e-8 and err <= 1e-8
+        del st
+
+
+def test_slab1000_f64_and_split(slab):
+    sel, ref = _check_f64_blocks(slab, 6003)
+    _check_split(slab, sel, ref)
+
+
+def test_slab1000_adjoint(slab):
+    q, torch, wl, plan, pairs, po = slab["q"], slab["torch"], slab["wl"], slab["plan"], slab["pairs"], slab["po"]
+    L = plan.info["store_len"]
+    rng = np.random.default_rng(6013)
+    coef = torch.from_numpy(rng.standard_normal((5, L))).cuda()
+    grad = torch.empty(wl.n_points, dtype=torch.float64, device="cuda")
+    q.density_on_grid(plan, coef, q.TERM_ALL, 1, grad)
+    # dot-product identity <dL/dv, dv> = <coef, H(dv)> (H linear in v)
+    dv = torch.from_numpy(rng.standard_normal(wl.n_points)).cuda()
+    st = q.new_store(plan)
+    q.q4c_integrate_H(plan, dv, q.PREC_F64, 0, st)
+    torch.cuda.synchronize()
+    lhs, rhs = float(torch.dot(grad, dv)), float(torch.sum(coef * st))
+    assert abs(lhs - rhs) <= 1e-11 * float(torch.sum(torch.abs(coef * st)))
+    # sampled points against the oracle (coefficients drawn again, host side)
+    c = coef.cpu().numpy()
+    nfn = wl.atom_nfn()
+    blocks = [c[:, po[p]:po[p + 1]].reshape(5, nfn[a], nfn[b]) for p, (a, b) in enumerate(pairs)]
+    idx = np.sort(rng.choice(wl.n_points, size=100, replace=False))
+    ref = oracle.density(wl, pairs, blocks, idx=idx, weight_mode=1)
+    got = grad.cpu().numpy()[idx]
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_pepi3383_f64_and_split(pepi):
+    sel, ref = _check_f64_blocks(pepi, 6005)
+    _check_split(pepi, sel, ref)
+
+
+def test_pepi3383_spinor_gradient_fd_32_points(pepi):
+    """L = Re Tr(D H(v)) for the seeded sparse Hermitian spinor D (12 angstrom
+    pair cutoff).  dL/dv = density_on_grid of D's coefficients (weight mode 1)
+    against central differences of L with the split-FP32 forward at 32 seeded
+    points, and against the oracle's density at sampled points."""
+    q, torch, wl, plan, pairs, po = pepi["q"], pepi["torch"], pepi["wl"], pepi["plan"], pepi["pairs"], pepi["po"]
+    from paper_2608_00773_amd.autograd import spinor_coefficients
+    D = W.spinor_density(wl, pairs, 5005)
+    print("spinor D on %d pairs" % len(D), flush=True)
+    spin = torch.from_numpy(spinor_from_blocks(D, po)).cuda()
+    coef = spinor_coefficients(plan, spin)
+    del spin
+    grad = torch.empty(wl.n_points, dtype=torch.float64, device="cuda")
+    q.density_on_grid(plan, coef, q.TERM_ALL, 1, grad)
+    torch.cuda.synchronize()
+    # oracle density at sampled points, from the oracle's own D -> coefficient map
+    rng = np.random.default_rng(6005)
+    idx = np.sort(rng.choice(wl.n_points, size=64, replace=False))
+    cblocks = oracle.coef_from_spinor_density(pairs, D)
+    del D
+    ref = oracle.density(wl, pairs, cblocks, idx=idx, weight_mode=1)
+    del cblocks
+    got = grad.cpu().numpy()[idx]
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+    # finite differences with the split-FP32 forward
+    _, pidx, _, _ = plan.batches()
+    pts = rng.choice(pidx, size=32, replace=False)
+    st = q.new_store(plan)
+    wv = wl.w
+    worst = 0.0
+    for n, g in enumerate(pts):
+        g = int(g)
+        h = 1e3 / max(wv[g], 1e-12)  # a large step: L is linear in v
+        vals = []
+        for sgn in (1.0, -1.0):
+            vv = pepi["v"].clone()
+            vv[g] += sgn * h
+            q.q4c_integrate_H(plan, vv, q.PREC_SPLIT_F32, 0, st)
+            vals.append(torch.sum(coef * st).item())
+        fd = (vals[0] - vals[1]) / (2 * h)
+        gg = grad[g].item()
+        bound = 1e-6 * abs(gg) + 1e-11 * float(torch.sum(torch.abs(coef * st)).item()) / (2 * h)
+        worst = max(worst, abs(fd - gg) / bound)
+        print("FD point %d/32 (g=%d): fd %.12g  adjoint %.12g" % (n + 1, g, fd, gg), flush=True)
+        assert abs(fd - gg) <= bound, (g, fd, gg)
+    print("worst |fd - adjoint| / bound: %.3g" % worst, flush=True)

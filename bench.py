@@ -53,7 +53,7 @@ def parse():
     ap.add_argument("--mode", choices=["full", "step", "forward", "adjoint"], default="full",
                     help="step/forward/adjoint: run only the whole step or that one call `steps` times "
                          "(for profiler runs) and print its time")
-    ap.add_argument("--workload", choices=["cluster", "molecules"], default="cluster",
+    ap.add_argument("--workload", choices=["cluster", "slab", "pepi", "molecules"], default="cluster",
                     help="molecules: 64 independent molecules (8..80 atoms), one batched plan (autotuned launch "
                          "shapes, HIP graph replay) against 64 sequential per-molecule plans; prints its own line")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -224,8 +224,15 @@ def main():
     import workload as W
 
     t0 = time.perf_counter()
-    wl = W.config_cluster(n_atoms=a.n_atoms)
+    if a.workload == "slab":
+        wl = W.config_slab()
+    elif a.workload == "pepi":
+        wl = W.config_pepi_3383()
+    else:
+        wl = W.config_cluster(n_atoms=a.n_atoms)
     t_gen = time.perf_counter() - t0
+    print("[bench] workload %s: %d atoms, %d points (%.1f s)" % (a.workload, wl.n_atoms, wl.n_points, t_gen),
+          file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     plan = q.Plan(wl)
     t_plan = time.perf_counter() - t0
@@ -325,7 +332,7 @@ def main():
     import hashlib
     with open(os.path.join(ROOT, "paper_2608_00773_amd", "csrc", "q4c_kernels.hip"), "rb") as fh:
         ksha = hashlib.sha256(fh.read()).hexdigest()
-    traffic = TRAFFIC.get((ksha, a.precision, a.n_atoms))
+    traffic = TRAFFIC.get((ksha, a.precision, a.n_atoms)) if a.workload == "cluster" else None
 
     n_act = info["n_active"]
     res = {
@@ -342,8 +349,10 @@ def main():
         "dtype": {"f64": "f64", "split": "f32-hi/lo+f64", "f32": "f32+f64"}[a.precision],
         "data": "synthetic",
         "config": {
-            "workload": "random cluster, %d atoms (Pb/I/H,C,N), %d NAOs, %d points (%d active), %d batches <= 300 pts" %
-                        (wl.n_atoms, info["n_fn"], info["n_points"], n_act, info["n_batches"]),
+            "workload": "%s, %d atoms, %d NAOs, %d points (%d active), %d batches <= 300 pts" %
+                        ({"cluster": "random cluster (Pb/I/H,C,N)", "slab": "perovskite-like slab",
+                          "pepi": "(6x6)x2 perovskite-like slab"}[a.workload],
+                         wl.n_atoms, info["n_fn"], info["n_points"], n_act, info["n_batches"]),
             "precision": a.precision,
             "step": "q4c_integrate_H (all parts + W spinor) + density_on_grid (adjoint, all terms)",
             "flops_alg_per_H": info["flops_alg"],
@@ -371,7 +380,7 @@ def main():
         "workload_gen_s": t_gen,
         "wall_timed_s": wall,
     }
-    if not a.no_cpu_baseline:
+    if not a.no_cpu_baseline and a.workload == "cluster":
         res["cpu_baseline"] = cpu_baseline(wl, a.cpu_sample)
     print(json.dumps(res), flush=True)
 

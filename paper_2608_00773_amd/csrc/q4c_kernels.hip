@@ -2,26 +2,30 @@
 //
 //  k_tabulate        nao_tabulate: phi and grad phi of a batch's relevant
 //                    functions at its points (Eq. 12a, App. B).
-//  k_contract<prec>  per (batch, tile ti, tile tj) work item: tabulates the
-//                    row and column functions of the tile chunk by chunk of
-//                    16 points into LDS (values and gradients never touch
-//                    HBM) and accumulates the five weighted products
+//  k_om              w_g v_g per active point (the weighting of Eq. 29).
+//  k_panel           per (batch, 64-function tile): phi and grad phi at all
+//                    batch points into the batch's operand panel (HBM).
+//  k_contract<prec>  per (batch, tile ti <= tj) work item: 16-point chunks of
+//                    the two tiles' panels are copied into LDS (the column
+//                    operand weighted by w v on the way) and the five
+//                    weighted products
 //                        V  = Phi^T diag(w v) Phi
 //                        Gs = sum_a dPhi_a^T diag(w v) dPhi_a
 //                        Gm = dPhi_b^T diag(w v) dPhi_c - dPhi_c^T diag(w v) dPhi_b
-//                    on MFMA (Eq. 29 restricted to the batch, Eq. 31).
-//                    Only tiles ti <= tj run; the lower atom-block triangle
-//                    follows from (anti)symmetry.  Results go to a staging
-//                    buffer laid out per (batch, atom pair).
+//                    accumulate on MFMA (Eq. 29 restricted to the batch,
+//                    Eq. 31).  The lower atom-block triangle follows from
+//                    (anti)symmetry.  Results go to a staging buffer laid
+//                    out per (batch, atom pair).
 //  k_reduce          deterministic batch-to-global sum: every stored atom
 //                    pair adds its staged blocks in batch order (FP64).
 //  k_spinor          2x2-spinor assembly of the W and V blocks.
 //  k_broadcast,
 //  k_density_tiles,
-//  k_density_points  density_on_grid: the transpose of the three steps above
+//  k_density_points  density_on_grid: the transpose of the steps above
 //                    (Eq. 39): coefficients are broadcast to the staged
-//                    layout, each tile contracts a_g^T C b_g at its points on
-//                    MFMA, and every point sums its tiles in a fixed order.
+//                    layout, each half work item contracts a_g^T C b_g at its
+//                    points on MFMA, and every point sums its partials in a
+//                    fixed order.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -417,10 +421,9 @@ enum { MODE_F64 = 0, MODE_SPLIT = 1, MODE_F32 = 2 };
 // LDS slab of one 16-point chunk of a tile: [comp][point][function], rows
 // padded to SEGW doubles.  Forward operand reads (16 functions x 4 points
 // per MFMA operand) are 128-byte runs in 4 rows; SEGW = T + 8 puts those
-// rows a quarter of the banks apart.  The adjoint reads 16 rows x 4 functions;
-// SEGW = T + 4 spreads its rows over the banks.
+// rows a quarter of the banks apart.  (The adjoint reads 16 rows x 4
+// functions and uses odd row strides instead; see k_density_tiles.)
 constexpr int SEGF = T + 8;   // forward
-constexpr int SEGA = T + 4;   // adjoint
 template <int SEGW>
 struct Slab {
   double v[4 * 16 * SEGW];
@@ -464,40 +467,6 @@ __device__ __forceinline__ double copy_slab(const double *pb, int64_t plane, int
     }
   }
   return gmax;
-}
-
-// Two-phase form of copy_slab for software pipelining: fetch a chunk into
-// registers (U units per thread), later store it to a slab.
-template <int NTH>
-struct SlabRegs {
-  static constexpr int U = 4 * 4 * 2 * T / NTH;
-  double2 v[U];
-};
-
-template <int NTH>
-__device__ __forceinline__ void fetch_slab(const double *pb, int64_t plane, int np, int row0, int ks0, int nks,
-                                           SlabRegs<NTH> &r) {
-#pragma unroll
-  for (int k = 0; k < SlabRegs<NTH>::U; ++k) {
-    const int u = k * NTH + threadIdx.x;
-    const int f = u & (T - 1), h = (u >> 6) & 1, ks = (u >> 7) & 3, q = u >> 9;
-    const int row = row0 + f;
-    r.v[k] = make_double2(0.0, 0.0);
-    if (row < np && ks0 < nks)
-      r.v[k] = *reinterpret_cast<const double2 *>(pb + q * plane + ((int64_t)(ks0 + ks) * np + row) * 4 + 2 * h);
-  }
-}
-
-template <int NTH, int SEGW>
-__device__ __forceinline__ void store_slab(const SlabRegs<NTH> &r, Slab<SEGW> &dst) {
-#pragma unroll
-  for (int k = 0; k < SlabRegs<NTH>::U; ++k) {
-    const int u = k * NTH + threadIdx.x;
-    const int f = u & (T - 1), h = (u >> 6) & 1, ks = (u >> 7) & 3, q = u >> 9;
-    const int pt = 4 * ks + 2 * h;
-    dst.v[(q * 16 + pt) * SEGW + f] = r.v[k].x;
-    dst.v[(q * 16 + pt + 1) * SEGW + f] = r.v[k].y;
-  }
 }
 
 // Split modes: a chunk's W contribution is bounded by c' 48 A B with A the
@@ -833,35 +802,73 @@ __device__ __forceinline__ double coef_elem(const DevPlan &d, const double *stag
   return q == 0 ? c : d.cprime * c;
 }
 
-constexpr int NTD = 512;  // adjoint workgroup: 8 waves = 4 column slices x 2 row halves
+constexpr int NTD = 256;       // adjoint workgroup: 4 waves = 2 column slices x 2 row halves of a half tile
+constexpr int SEGR = T + 1;     // adjoint row slab stride (odd: lanes reading 16 points hit distinct banks)
+constexpr int SEGC = T / 2 + 1; // adjoint column slab stride (half tile)
 
-// One work item: partial[g] = sum over the tile of a_g^T C b_g for all
-// selected terms; the chunk's row and column functions are staged in LDS
-// from the batch's panel and shared by the 8 waves.
+// Copy 16 points (K steps ks0 .. ks0+3) of functions f0 .. f0+W-1, all four
+// components, from a batch panel into an LDS slab dst[(q*16 + pt)*SEG + f].
+// Units of 16 bytes (function f, points 2h and 2h+1 of K step ks, component
+// q); every thread issues all of its loads before its first store.
+template <int NTH, int W, int SEG>
+__device__ __forceinline__ void copy_panel(const double *pb, int64_t plane, int np, int f0, int ks0, double *dst) {
+  constexpr int U = 4 * 4 * 2 * W / NTH;
+  constexpr int G = U < 4 ? U : 4;
+#pragma unroll
+  for (int k0 = 0; k0 < U; k0 += G) {
+    double2 val[G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      const int u = (k0 + k) * NTH + threadIdx.x;
+      const int f = u % W, h = (u / W) & 1, ks = (u / (2 * W)) & 3, q = u / (8 * W);
+      const int row = f0 + f;
+      val[k] = make_double2(0.0, 0.0);
+      if (row < np)
+        val[k] = *reinterpret_cast<const double2 *>(pb + q * plane + ((int64_t)(ks0 + ks) * np + row) * 4 + 2 * h);
+    }
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      const int u = (k0 + k) * NTH + threadIdx.x;
+      const int f = u % W, h = (u / W) & 1, ks = (u / (2 * W)) & 3, q = u / (8 * W);
+      const int pt = 4 * ks + 2 * h;
+      dst[(q * 16 + pt) * SEG + f] = val[k].x;
+      dst[(q * 16 + pt + 1) * SEG + f] = val[k].y;
+    }
+  }
+}
+
+// One half of a work item (positions 2 w + half): partial[g] = sum over the
+// tile's 64 rows and the half's 32 columns of a_g^T C b_g for all selected
+// terms.  The chunk's row functions (64) and column functions (32) are staged
+// in LDS and shared by the 4 waves; each wave owns 16 columns x 32 rows of C
+// in registers.  Two workgroups fit on a CU, so one computes while the other
+// stages its next chunk.
 template <bool PERSIST>
-__global__ __launch_bounds__(NTD, 1) void k_density_tiles(DevPlan d, uint32_t terms, const WorkItem *work,
+__global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t terms, const WorkItem *work,
                                                           const int32_t *order, int64_t w0, int64_t nw,
                                                           const double *staging, const double *panel,
                                                           double *partial, unsigned *tickets) {
-  __shared__ Slab<SEGA> sa[2], sb[2];
-  __shared__ double s_red[8][16];
+  __shared__ double sa[4 * 16 * SEGR], sb[4 * 16 * SEGC];
+  __shared__ double s_red[4][16];
   __shared__ int64_t s_pos;
-  int64_t pos = PERSIST ? next_item(tickets, nw, order != nullptr, &s_pos)
-                        : (order ? (int64_t)blockIdx.x : xcd_map(blockIdx.x, nw));
-  while (!PERSIST || pos < nw) {
-  const int64_t wi = w0 + (order ? order[w0 + pos] : pos);
+  const int64_t npos = 2 * nw;
+  int64_t pos = PERSIST ? next_item(tickets, npos, order != nullptr, &s_pos)
+                        : (order ? (int64_t)blockIdx.x : xcd_map(blockIdx.x, npos));
+  while (!PERSIST || pos < npos) {
+  const int half = (int)(pos & 1);
+  const int64_t wi = w0 + (order ? order[w0 + (pos >> 1)] : (pos >> 1));
   const WorkItem it = work[wi];
   const int b = it.batch;
   const int g0 = d.batch_pt_off[b], P = d.batch_pt_off[b + 1] - g0;
   const int f0 = d.batch_fn_off[b], n = d.batch_fn_off[b + 1] - f0;
   const int sbase = d.batch_slot_off[b];
-  const int r0 = it.ti * T, c0 = it.tj * T;
+  const int r0 = it.ti * T, c0 = it.tj * T + 32 * half;
   const int Pp = (int)pad16(P), np = (int)pad16(n);
   const double *pb = panel + d.panel_off[b];
   const int64_t plane = (int64_t)Pp * np;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int js = wave & 3, ih = wave >> 2;  // column slice, row half
+  const int js = wave & 1, ih = wave >> 1;  // column slice, row half
   const int l16 = lane & 15, lk = lane >> 4;
   const int cb = c0 + 16 * js;  // column block of this wave
   const int lj = cb + l16;
@@ -884,42 +891,37 @@ __global__ __launch_bounds__(NTD, 1) void k_density_tiles(DevPlan d, uint32_t te
                                              upper[ks >> 2])
                                  : 0.0;
   const bool tLL = terms & Q4C_TERM_LL, tSS = terms & Q4C_TERM_SS, tSO = terms & Q4C_TERM_SO;
-  double *out = partial + d.work_part_off[wi];
+  double *out = partial + 2 * d.work_part_off[wi] + half * P;
   const int iloc = 32 * ih;  // tile-local first row of this wave
+  const int jloc = 16 * js;  // half-local first column of this wave
 
-  // chunk k0 + 16 is fetched into registers while chunk k0 is multiplied
-  const int nks = Pp >> 2;
-  SlabRegs<NTD> ra, rb;
-  fetch_slab<NTD>(pb, plane, np, r0, 0, nks, ra);
-  fetch_slab<NTD>(pb, plane, np, c0, 0, nks, rb);
   for (int k0 = 0; k0 < Pp; k0 += 16) {
-    const int buf = (k0 >> 4) & 1;
-    store_slab<NTD, SEGA>(ra, sa[buf]);
-    store_slab<NTD, SEGA>(rb, sb[buf]);
-    __syncthreads();  // slabs of this chunk visible (and s_red of the previous one consumed)
-    fetch_slab<NTD>(pb, plane, np, r0, (k0 >> 2) + 4, nks, ra);
-    fetch_slab<NTD>(pb, plane, np, c0, (k0 >> 2) + 4, nks, rb);
-    const Slab<SEGA> &A = sa[buf];
-    const Slab<SEGA> &B = sb[buf];
-    double accp[4] = {0.0, 0.0, 0.0, 0.0};
+    __syncthreads();  // previous chunk's slabs and per-wave sums consumed
+    copy_panel<NTD, T, SEGR>(pb, plane, np, r0, k0 >> 2, sa);
+    copy_panel<NTD, T / 2, SEGC>(pb, plane, np, c0, k0 >> 2, sb);
+    __syncthreads();  // slabs visible
+    // X[j][pt] = sum over the selected terms of (C^T Y)[j][pt] Z[pt][j]: the
+    // MFMA takes the coefficients as its first operand, so register r of lane
+    // (l16, lk) holds column j = lk + 4 r (of the wave's 16) at point pt = l16
+    // and the product with Z is a lane-local multiply-add.
+    double xacc[4] = {0.0, 0.0, 0.0, 0.0};
     if (any) {
-      // column values: Z[q][pt = lk + 4 r][j = 16 js + l16]
-      double zb[4][4];
+      // column values: Z[q][pt = l16][j = jloc + lk + 4 r]
+      double zt[4][4];
 #pragma unroll
       for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) zb[q][r] = B.v[(q * 16 + d_row_f64(lk, r)) * SEGA + 16 * js + l16];
-      // terms grouped by the row component Y (A operand, points x functions):
+        for (int r = 0; r < 4; ++r) zt[q][r] = sb[(q * 16 + l16) * SEGC + jloc + d_row_f64(lk, r)];
+      // terms grouped by the row component Y (points x functions):
       //   Y=phi: (V, phi); Y=dx: (Ws, dx), (Wso_y, -dz), (Wso_z, +dy);
       //   Y=dy: (Ws, dy), (Wso_x, +dz), (Wso_z, -dx); Y=dz: (Ws, dz), (Wso_x, -dy), (Wso_y, +dx)
 #pragma unroll
       for (int yq = 0; yq < 4; ++yq) {
         if (yq == 0 ? !tLL : !(tSS || tSO)) continue;
-        // A operand: Y[yq][pt = l16][i = iloc + 4 ks + lk]
+        // second operand: Y[yq][pt = l16][i = iloc + 4 ks + lk]
         double ya[8];
 #pragma unroll
-        for (int ks = 0; ks < 8; ++ks)
-          ya[ks] = A.v[(yq * 16 + l16) * SEGA + iloc + 4 * ks + lk];
+        for (int ks = 0; ks < 8; ++ks) ya[ks] = sa[(yq * 16 + l16) * SEGR + iloc + 4 * ks + lk];
         // the terms sharing this Y run as independent MFMA chains, interleaved
         // over the K steps; a lone term uses two chains (even / odd steps)
         if (yq == 0) {
@@ -927,12 +929,12 @@ __global__ __launch_bounds__(NTD, 1) void k_density_tiles(DevPlan d, uint32_t te
 #pragma unroll
           for (int ks = 0; ks < 8; ks += 2) {
             if (act[ks >> 2]) {
-              u0 = mfma64(ya[ks], creg[0][ks], u0);
-              u1 = mfma64(ya[ks + 1], creg[0][ks + 1], u1);
+              u0 = mfma64(creg[0][ks], ya[ks], u0);
+              u1 = mfma64(creg[0][ks + 1], ya[ks + 1], u1);
             }
           }
 #pragma unroll
-          for (int r = 0; r < 4; ++r) accp[r] += (u0[r] + u1[r]) * zb[0][r];
+          for (int r = 0; r < 4; ++r) xacc[r] += (u0[r] + u1[r]) * zt[0][r];
         } else {
           // (coefficient part, column comp, sign) of the three terms
           const int c1 = 1, z1 = yq;
@@ -944,38 +946,28 @@ __global__ __launch_bounds__(NTD, 1) void k_density_tiles(DevPlan d, uint32_t te
 #pragma unroll
           for (int ks = 0; ks < 8; ++ks) {
             if (act[ks >> 2]) {
-              if (tSS) u1 = mfma64(ya[ks], creg[c1][ks], u1);
+              if (tSS) u1 = mfma64(creg[c1][ks], ya[ks], u1);
               if (tSO) {
-                u2 = mfma64(ya[ks], creg[c2][ks], u2);
-                u3 = mfma64(ya[ks], creg[c3][ks], u3);
+                u2 = mfma64(creg[c2][ks], ya[ks], u2);
+                u3 = mfma64(creg[c3][ks], ya[ks], u3);
               }
             }
           }
 #pragma unroll
-          for (int r = 0; r < 4; ++r) accp[r] += u1[r] * zb[z1][r] + g2 * u2[r] * zb[z2][r] + g3 * u3[r] * zb[z3][r];
+          for (int r = 0; r < 4; ++r) xacc[r] += u1[r] * zt[z1][r] + g2 * u2[r] * zt[z2][r] + g3 * u3[r] * zt[z3][r];
         }
       }
-      // sum over the 16 columns held by lanes with equal lk
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-#pragma unroll
-        for (int off = 1; off < 16; off <<= 1) accp[r] += __shfl_xor(accp[r], off);
-      }
     }
-    if (l16 == 0) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) s_red[wave][d_row_f64(lk, r)] = accp[r];
-    }
-    __syncthreads();
-    if (tid < 16 && k0 + tid < P) {
-      double sum = 0.0;
-#pragma unroll
-      for (int w = 0; w < 8; ++w) sum += s_red[w][tid];
-      out[k0 + tid] = sum;
-    }
+    // sum over the wave's 16 columns: the 4 registers, then the 4 lane rows
+    double sx = (xacc[0] + xacc[1]) + (xacc[2] + xacc[3]);
+    sx += __shfl_xor(sx, 16);
+    sx += __shfl_xor(sx, 32);
+    if (lane < 16) s_red[wave][l16] = sx;
+    __syncthreads();  // per-wave sums of this chunk
+    if (tid < 16 && k0 + tid < P) out[k0 + tid] = (s_red[0][tid] + s_red[1][tid]) + (s_red[2][tid] + s_red[3][tid]);
   }
   if (!PERSIST) break;
-  pos = next_item(tickets, nw, order != nullptr, &s_pos);
+  pos = next_item(tickets, npos, order != nullptr, &s_pos);
   }
 }
 
@@ -986,7 +978,11 @@ __global__ void k_density_points(DevPlan d, int64_t b0, const double *partial, i
   const int64_t wa = d.batch_work_off[b], wb = d.batch_work_off[b + 1];
   for (int g = threadIdx.x; g < P; g += blockDim.x) {
     double s = 0.0;
-    for (int64_t w = wa; w < wb; ++w) s += partial[d.work_part_off[w] + g];
+    for (int64_t w = wa; w < wb; ++w) {
+      const double *pw = partial + 2 * d.work_part_off[w];
+      s += pw[g];
+      s += pw[P + g];
+    }
     out[d.perm[g0 + g]] = weight_mode ? d.pw[g0 + g] * s : s;
   }
 }
@@ -1159,7 +1155,8 @@ int launch_density(const q4c_plan *p, const double *coef, uint32_t terms, int we
     const Pass &ps = p->passes[ip];
     const int64_t nr = ps.r1 - ps.r0, nw = ps.w1 - ps.w0, nbt = ps.b1 - ps.b0, nz = ps.z1 - ps.z0, nt = ps.t1 - ps.t0;
     unsigned *tickets = cfg.persistent > 0 ? tick0 + ip * kTicketsPerLaunch : nullptr;
-    const unsigned grid = (unsigned)(cfg.persistent > 0 ? std::min<int64_t>(cfg.persistent, nw) : nw);
+    // two workgroup positions (column halves) per work item
+    const unsigned grid = (unsigned)(cfg.persistent > 0 ? std::min<int64_t>(cfg.persistent, 2 * nw) : 2 * nw);
     double *partial = p->d_staging + ps.staging_len;
     double *panel = partial + ps.partial_len;
     if (nz > 0) {

@@ -482,7 +482,7 @@ int build_host(q4c_plan *p, const q4c_basis *b, const q4c_grid *g, const std::ve
       }
     }
     int nt = (nb_fn + T - 1) / T;
-    int64_t bpart = (int64_t)(nt * (nt + 1) / 2) * (g1 - g0);
+    int64_t bpart = 2 * (int64_t)(nt * (nt + 1) / 2) * (g1 - g0);  // two column halves per work item
     int64_t bpanel = 4 * q4c::pad16(g1 - g0) * q4c::pad16(nb_fn);
     if (bt > cur.b0 && (staging + partial + panel + bstage + bpart + bpanel > budget_doubles)) close_pass(bt);
     p->panel_off.push_back(panel);
@@ -525,8 +525,9 @@ int build_host(q4c_plan *p, const q4c_basis *b, const q4c_grid *g, const std::ve
     for (int ti = 0; ti < nt; ++ti)
       for (int tj = ti; tj < nt; ++tj) {
         p->work.push_back(q4c::WorkItem{(int32_t)bt, (int16_t)ti, (int16_t)tj});
-        p->work_part_off.push_back(partial);
-        partial += (g1 - g0);
+        // adjoint partials of this work item: two column halves of P doubles at 2 * work_part_off
+        p->work_part_off.push_back(partial / 2);
+        partial += 2 * (g1 - g0);
       }
     p->max_batch_points = std::max<int64_t>(p->max_batch_points, g1 - g0);
     p->max_batch_fn = std::max<int64_t>(p->max_batch_fn, nb_fn);
@@ -1100,8 +1101,8 @@ int q4c_plan_autotune(q4c_plan *p, const double *v_dev, int32_t precision, doubl
   for (int kernel = 0; kernel < 2 && rc == Q4C_OK; ++kernel) {
     if (kernel == Q4C_KERNEL_DENSITY && !coef_dev) break;
     // workgroups that fit on the chip at once: two per CU for the FP64
-    // contraction, one per CU for the split contraction and the adjoint
-    const int occ = (kernel == Q4C_KERNEL_CONTRACT && precision == Q4C_PREC_F64) ? 2 : 1;
+    // contraction and the adjoint, one per CU for the split contraction
+    const int occ = (kernel == Q4C_KERNEL_CONTRACT && precision != Q4C_PREC_F64) ? 1 : 2;
     const int cand_p[3] = {0, occ * p->n_cu, 2 * occ * p->n_cu};
     q4c::LaunchCfg best{};
     double best_ms = 1e300;

@@ -786,21 +786,6 @@ __global__ void k_broadcast(DevPlan d, int64_t r0, const int32_t *red_pair, cons
   }
 }
 
-// Effective coefficient of element (li, lj) of a computed block, part q (c'
-// applied to W parts).  A strictly upper block also carries the mirrored
-// same-atom element; staged blocks of non-pair slot combinations hold zeros.
-__device__ __forceinline__ double coef_elem(const DevPlan &d, const double *staging, int f0, int sbase, int n, int li,
-                                            int lj, int q, bool upper) {
-  if (li >= n || lj >= n) return 0.0;
-  const SlotInfo si = slot_of(d, f0, sbase, li), sj = slot_of(d, f0, sbase, lj);
-  if (si.slot > sj.slot) return 0.0;
-  const int64_t blk = si.row_off + 5 * (int64_t)si.nfn * (sj.fnoff - si.fnoff);
-  const int64_t pq = (int64_t)si.nfn * sj.nfn;
-  double c = staging[blk + q * pq + (int64_t)(li - si.fnoff) * sj.nfn + (lj - sj.fnoff)];
-  if (upper && si.slot == sj.slot)
-    c += mirror_sign(q) * staging[blk + q * pq + (int64_t)(lj - si.fnoff) * sj.nfn + (li - sj.fnoff)];
-  return q == 0 ? c : d.cprime * c;
-}
 
 constexpr int NTD = 256;       // adjoint workgroup: 4 waves = 2 column slices x 2 row halves of a half tile
 constexpr int SEGR = T + 1;     // adjoint row slab stride (odd: lanes reading 16 points hit distinct banks)
@@ -851,6 +836,9 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t te
   __shared__ double sa[4 * 16 * SEGR], sb[4 * 16 * SEGC];
   __shared__ double s_red[4][16];
   __shared__ int64_t s_pos;
+  // slot data of the tile's 64 rows and the half's 32 columns (slot -1: padding)
+  __shared__ int s_rslot[T], s_rfn[T], s_rnf[T], s_cslot[T / 2], s_cfn[T / 2], s_cnf[T / 2];
+  __shared__ int64_t s_rrow[T];
   const int64_t npos = 2 * nw;
   int64_t pos = PERSIST ? next_item(tickets, npos, order != nullptr, &s_pos)
                         : (order ? (int64_t)blockIdx.x : xcd_map(blockIdx.x, npos));
@@ -881,15 +869,53 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t te
     upper[h] = rb < cb;
   }
   const bool any = act[0] || act[1];
-  // coefficient slice: rows i = r0 + 32 ih + 4 ks + lk (ks = 0..7), column lj
+  if (tid < T + T / 2) {
+    const bool row = tid < T;
+    const int lf = row ? r0 + tid : c0 + tid - T;
+    SlotInfo si{-1, 0, 0, 0};
+    if (lf < n) si = slot_of(d, f0, sbase, lf);
+    if (row) {
+      s_rslot[tid] = si.slot;
+      s_rfn[tid] = si.fnoff;
+      s_rnf[tid] = si.nfn;
+      s_rrow[tid] = si.row_off;
+    } else {
+      s_cslot[tid - T] = si.slot;
+      s_cfn[tid - T] = si.fnoff;
+      s_cnf[tid - T] = si.nfn;
+    }
+  }
+  __syncthreads();  // slot tables visible
+  // coefficient slice: rows i = r0 + 32 ih + 4 ks + lk (ks = 0..7), column lj,
+  // from the staged (batch, atom pair) blocks: element (li, lj) of a block in
+  // the upper atom-block triangle, plus the mirrored element (lj, li) when
+  // the 16 x 16 block is strictly upper inside one atom block (no work item
+  // computes the mirrored block); c' on the W parts.  Slot combinations that
+  // are not stored pairs hold zeros (k_zero_blocks).  All loads of a thread
+  // are independent and issued together.
   double creg[5][8];
+  {
+    const int cl = 16 * js + l16;
+    const int cslot = s_cslot[cl], cfn = s_cfn[cl], cnf = s_cnf[cl];
 #pragma unroll
-  for (int q = 0; q < 5; ++q)
+    for (int ks = 0; ks < 8; ++ks) {
+      const int rl = 32 * ih + 4 * ks + lk;
+      const int li = r0 + rl;
+      const int rslot = s_rslot[rl], rfn = s_rfn[rl], rnf = s_rnf[rl];
+      const bool live = act[ks >> 2] && rslot >= 0 && cslot >= 0 && rslot <= cslot;
+      const bool mir = live && upper[ks >> 2] && rslot == cslot;
+      const int64_t blk = s_rrow[rl] + 5 * (int64_t)rnf * (cfn - rfn);
+      const int64_t pq = (int64_t)rnf * cnf;
+      const int64_t e = blk + (int64_t)(li - rfn) * cnf + (lj - cfn);
+      const int64_t em = blk + (int64_t)(lj - rfn) * cnf + (li - cfn);
 #pragma unroll
-    for (int ks = 0; ks < 8; ++ks)
-      creg[q][ks] = act[ks >> 2] ? coef_elem(d, staging, f0, sbase, n, r0 + 32 * ih + 4 * ks + lk, lj, q,
-                                             upper[ks >> 2])
-                                 : 0.0;
+      for (int q = 0; q < 5; ++q) {
+        double c = live ? staging[e + q * pq] : 0.0;
+        if (mir) c += mirror_sign(q) * staging[em + q * pq];
+        creg[q][ks] = q == 0 ? c : d.cprime * c;
+      }
+    }
+  }
   const bool tLL = terms & Q4C_TERM_LL, tSS = terms & Q4C_TERM_SS, tSO = terms & Q4C_TERM_SO;
   double *out = partial + 2 * d.work_part_off[wi] + half * P;
   const int iloc = 32 * ih;  // tile-local first row of this wave

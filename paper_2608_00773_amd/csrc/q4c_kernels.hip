@@ -418,55 +418,34 @@ __device__ __forceinline__ int d_row_f32(int lk, int r) { return 4 * lk + r; }
 // Precision modes of the forward contraction.
 enum { MODE_F64 = 0, MODE_SPLIT = 1, MODE_F32 = 2 };
 
-// LDS slab of one 16-point chunk of a tile: [comp][point][function], rows
-// padded to SEGW doubles.  Forward operand reads (16 functions x 4 points
-// per MFMA operand) are 128-byte runs in 4 rows; SEGW = T + 8 puts those
-// rows a quarter of the banks apart.  (The adjoint reads 16 rows x 4
-// functions and uses odd row strides instead; see k_density_tiles.)
-constexpr int SEGF = T + 8;   // forward
-template <int SEGW>
-struct Slab {
-  double v[4 * 16 * SEGW];
-};
+// LDS image of one 16-point chunk of a 64-function tile, in the panel's own
+// order: row (q, u) holds component q at points 2u and 2u+1 of the chunk,
+// the two points of function f as consecutive doubles, so element (q, pt, f)
+// sits at (q*8 + pt/2)*DROW + 2f + pt%2.  Each row is one 1 KB run of the
+// panel (64 functions x 16 bytes) and is filled by one wave-wide LDS DMA
+// load: no registers are involved, and all loads of a chunk are in flight at
+// once.
+constexpr int DROW = 2 * T;  // doubles per LDS row
+typedef __attribute__((address_space(3))) void lds_void;
 
-// Copy a chunk's 16 points of functions row0 .. row0+T-1 from the panel into
-// a slab (optionally weighted per point).  2048 units of 16 bytes
-// (function f, points 2h and 2h+1 of K step ks, component q); every thread
-// issues all of its loads before the first store.
-template <int NTH, int SEGW, bool TRACK = false>
-__device__ __forceinline__ double copy_slab(const double *pb, int64_t plane, int np, int row0, int ks0,
-                                            Slab<SEGW> &dst, const double *omc) {
-  constexpr int U = 4 * 4 * 2 * T / NTH;  // units per thread
-  constexpr int G = U < 4 ? U : 4;        // loads in flight per thread
-  double gmax = 0.0;                      // largest |gradient component| stored (TRACK)
+// Issue the LDS DMA loads of one chunk (K steps ks0 .. ks0+3) of functions
+// row0 .. row0+T-1 into dst (32 rows, spread over the waves).  Functions at
+// or beyond np are not loaded: their LDS entries are stale and lie in 16x16
+// blocks that are never multiplied (rows n .. np-1 are zero in the panel).
+// The caller waits for the loads (vmcnt) and synchronises the workgroup.
+template <int NTH>
+__device__ __forceinline__ void dma_chunk(const double *pb, int64_t plane, int np, int row0, int ks0, double *dst) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const bool ok = row0 + lane < np;
 #pragma unroll
-  for (int k0 = 0; k0 < U; k0 += G) {
-    double2 val[G];
-#pragma unroll
-    for (int k = 0; k < G; ++k) {
-      const int u = (k0 + k) * NTH + threadIdx.x;
-      const int f = u & (T - 1), h = (u >> 6) & 1, ks = (u >> 7) & 3, q = u >> 9;
-      const int row = row0 + f;
-      val[k] = make_double2(0.0, 0.0);
-      if (row < np)
-        val[k] = *reinterpret_cast<const double2 *>(pb + q * plane + ((int64_t)(ks0 + ks) * np + row) * 4 + 2 * h);
-    }
-#pragma unroll
-    for (int k = 0; k < G; ++k) {
-      const int u = (k0 + k) * NTH + threadIdx.x;
-      const int f = u & (T - 1), h = (u >> 6) & 1, ks = (u >> 7) & 3, q = u >> 9;
-      const int pt = 4 * ks + 2 * h;
-      double x = val[k].x, y = val[k].y;
-      if (omc) {
-        x *= omc[pt];
-        y *= omc[pt + 1];
-      }
-      if (TRACK && q > 0) gmax = fmax(gmax, fmax(fabs(x), fabs(y)));
-      dst.v[(q * 16 + pt) * SEGW + f] = x;
-      dst.v[(q * 16 + pt + 1) * SEGW + f] = y;
-    }
+  for (int k = 0; k < 32 / (NTH / 64); ++k) {
+    const int r = wave + k * (NTH / 64);
+    const int q = r >> 3, u = r & 7;
+    if (ok)
+      __builtin_amdgcn_global_load_lds(
+          (const void *)(pb + q * plane + ((int64_t)(ks0 + (u >> 1)) * np + row0 + lane) * 4 + 2 * (u & 1)),
+          (lds_void *)(dst + r * DROW), 16, 0, 0);
   }
-  return gmax;
 }
 
 // Split modes: a chunk's W contribution is bounded by c' 48 A B with A the
@@ -485,7 +464,7 @@ __global__ __launch_bounds__(NT, MODE == 0 ? 2 : 1) void k_contract(DevPlan d, c
                                                                     double *staging, double tau,
                                                                     unsigned long long *chunks, unsigned *tickets) {
   constexpr bool SPLIT = MODE != 0;
-  __shared__ Slab<SEGF> sa, sb;
+  __shared__ double sa[32 * DROW], sb[32 * DROW];
   __shared__ double s_om[16];
   __shared__ double s_gm[2][NT / 64];
   __shared__ int64_t s_pos;
@@ -533,11 +512,25 @@ __global__ __launch_bounds__(NT, MODE == 0 ? 2 : 1) void k_contract(DevPlan d, c
 
   const double cp = d.cprime;
   for (int k0 = 0; k0 < Pp; k0 += 16) {
+    __syncthreads();  // previous chunk's operands consumed
     if (tid < 16) s_om[tid] = k0 + tid < P ? om[g0 + k0 + tid] : 0.0;
-    __syncthreads();  // s_om visible; previous chunk's operands consumed
-    double ma = copy_slab<NT, SEGF, SPLIT>(pb, plane, np, r0, k0 >> 2, sa, nullptr);
-    double mb = copy_slab<NT, SEGF, SPLIT>(pb, plane, np, c0, k0 >> 2, sb, s_om);
+    dma_chunk<NT>(pb, plane, np, r0, k0 >> 2, sa);
+    dma_chunk<NT>(pb, plane, np, c0, k0 >> 2, sb);
+    __builtin_amdgcn_s_waitcnt(0);  // this thread's LDS DMA loads have landed
+    __syncthreads();                // the chunk and s_om are visible
+    bool hot = true;  // W parts of this chunk on FP64 MFMA
     if (SPLIT) {
+      // largest |gradient component| of the row tile and |w v gradient| of the
+      // column tile over the chunk (functions inside the panel)
+      double ma = 0.0, mb = 0.0;
+#pragma unroll
+      for (int k = 0; k < 3 * 16 * T / NT; ++k) {
+        const int e = tid + NT * k;
+        const int q = 1 + e / (16 * T), pt = (e / T) & 15, f = e & (T - 1);
+        const int idx = (q * 8 + (pt >> 1)) * DROW + 2 * f + (pt & 1);
+        if (r0 + f < np) ma = fmax(ma, fabs(sa[idx]));
+        if (c0 + f < np) mb = fmax(mb, fabs(sb[idx] * s_om[pt]));
+      }
 #pragma unroll
       for (int off = 1; off < 64; off <<= 1) {
         ma = fmax(ma, __shfl_xor(ma, off));
@@ -547,10 +540,7 @@ __global__ __launch_bounds__(NT, MODE == 0 ? 2 : 1) void k_contract(DevPlan d, c
         s_gm[0][wave] = ma;
         s_gm[1][wave] = mb;
       }
-    }
-    __syncthreads();
-    bool hot = true;  // W parts of this chunk on FP64 MFMA
-    if (SPLIT) {
+      __syncthreads();
       double A = 0.0, B = 0.0;
 #pragma unroll
       for (int w = 0; w < NT / 64; ++w) {
@@ -563,15 +553,19 @@ __global__ __launch_bounds__(NT, MODE == 0 ? 2 : 1) void k_contract(DevPlan d, c
     }
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
+      // K index lk of step ks is point 4 ks + lk of the chunk; the column
+      // operand takes its weight w v there (the weighting of Eq. 29)
+      const int rowk = 2 * ks + (lk >> 1), ck = lk & 1;
+      const double omk = s_om[4 * ks + lk];
       double a[2][4], bb[2][4];
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) a[x][q] = sa.v[(q * 16 + 4 * ks + lk) * SEGF + wr + 16 * x + li16];
+        for (int q = 0; q < 4; ++q) a[x][q] = sa[(q * 8 + rowk) * DROW + 2 * (wr + 16 * x + li16) + ck];
 #pragma unroll
       for (int y = 0; y < 2; ++y)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) bb[y][q] = sb.v[(q * 16 + 4 * ks + lk) * SEGF + wc + 16 * y + li16];
+        for (int q = 0; q < 4; ++q) bb[y][q] = sb[(q * 8 + rowk) * DROW + 2 * (wc + 16 * y + li16) + ck] * omk;
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll

@@ -428,19 +428,22 @@ enum { MODE_F64 = 0, MODE_SPLIT = 1, MODE_F32 = 2 };
 constexpr int DROW = 2 * T;  // doubles per LDS row
 typedef __attribute__((address_space(3))) void lds_void;
 
-// Issue the LDS DMA loads of one chunk (K steps ks0 .. ks0+3) of functions
-// row0 .. row0+T-1 into dst (32 rows, spread over the waves).  Functions at
+// Issue the LDS DMA loads of one chunk of CH points (panel K steps ks0 ..
+// ks0 + CH/4 - 1) of functions row0 .. row0+T-1 into dst (4 * CH/2 rows of
+// DROW doubles, spread over the waves; element (q, pt, f) of the chunk at
+// (q * CH/2 + pt/2) * DROW + 2f + pt%2).  Functions at
 // or beyond np are not loaded: their LDS entries are stale and lie in 16x16
 // blocks that are never multiplied (rows n .. np-1 are zero in the panel).
 // The caller waits for the loads (vmcnt) and synchronises the workgroup.
-template <int NTH>
+template <int NTH, int CH = 16>
 __device__ __forceinline__ void dma_chunk(const double *pb, int64_t plane, int np, int row0, int ks0, double *dst) {
+  constexpr int RPQ = CH / 2;  // rows (point pairs) per component
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const bool ok = row0 + lane < np;
 #pragma unroll
-  for (int k = 0; k < 32 / (NTH / 64); ++k) {
+  for (int k = 0; k < 4 * RPQ / (NTH / 64); ++k) {
     const int r = wave + k * (NTH / 64);
-    const int q = r >> 3, u = r & 7;
+    const int q = r / RPQ, u = r % RPQ;
     if (ok)
       __builtin_amdgcn_global_load_lds(
           (const void *)(pb + q * plane + ((int64_t)(ks0 + (u >> 1)) * np + row0 + lane) * 4 + 2 * (u & 1)),
@@ -484,13 +487,24 @@ __global__ __launch_bounds__(NT, MODE == 0 ? 2 : 1) void k_contract(DevPlan d, c
   const int64_t plane = (int64_t)Pp * np;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;  // wave sub-tile origin within the tile
+  // wave sub-tile origin within the tile: a 2 x 2 grid of 32 x 32 sub-tiles.
+  // A diagonal tile computes only the 10 blocks on or above its block
+  // diagonal: the lower-left wave would idle and the upper-right one carry 4
+  // blocks, so there the upper-right blocks (rows 0-15 and 16-31, columns
+  // 32-63) go one row each to waves 1 and 2 (at most 3 blocks per wave).
+  int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const bool split_ur = diag && (wave == 1 || wave == 2);
+  if (diag && wave == 2) {
+    wr = 16;
+    wc = 32;
+  }
   const int li16 = lane & 15, lk = lane >> 4;
   bool act[2][2];
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y) act[x][y] = block_active(r0 + wr + 16 * x, c0 + wc + 16 * y, n);
+    for (int y = 0; y < 2; ++y)
+      act[x][y] = block_active(r0 + wr + 16 * x, c0 + wc + 16 * y, n) && !(split_ur && x == 1);
 
   dbl4 acc[2][2][5];
 #pragma unroll
@@ -511,13 +525,42 @@ __global__ __launch_bounds__(NT, MODE == 0 ? 2 : 1) void k_contract(DevPlan d, c
   }
 
   const double cp = d.cprime;
-  for (int k0 = 0; k0 < Pp; k0 += 16) {
-    __syncthreads();  // previous chunk's operands consumed
-    if (tid < 16) s_om[tid] = k0 + tid < P ? om[g0 + k0 + tid] : 0.0;
-    dma_chunk<NT>(pb, plane, np, r0, k0 >> 2, sa);
-    dma_chunk<NT>(pb, plane, np, c0, k0 >> 2, sb);
-    __builtin_amdgcn_s_waitcnt(0);  // this thread's LDS DMA loads have landed
-    __syncthreads();                // the chunk and s_om are visible
+  // FP64: chunks of 8 points in two LDS buffers, the next chunk's DMA in
+  // flight while this one is multiplied (one barrier per chunk).  Split
+  // modes: chunks of 16 points, one buffer (the FP64 routing is decided per
+  // 16-point chunk).
+  constexpr int CH = SPLIT ? 16 : 8;
+  constexpr int RPQ = CH / 2;              // LDS rows per component
+  constexpr int BUFD = 4 * RPQ * DROW;     // doubles per chunk image
+  if (!SPLIT) {
+    dma_chunk<NT, CH>(pb, plane, np, r0, 0, sa);
+    dma_chunk<NT, CH>(pb, plane, np, c0, 0, sb);
+  }
+  for (int k0 = 0; k0 < Pp; k0 += CH) {
+    const int bo = SPLIT ? 0 : ((k0 / CH) & 1) * BUFD;  // this chunk's buffer
+    double omv[CH / 4];  // FP64 path: w v at points 4 ks + lk of this chunk
+    if (SPLIT) {
+      __syncthreads();  // previous chunk's operands consumed
+      if (tid < 16) s_om[tid] = k0 + tid < P ? om[g0 + k0 + tid] : 0.0;
+      dma_chunk<NT, CH>(pb, plane, np, r0, k0 >> 2, sa);
+      dma_chunk<NT, CH>(pb, plane, np, c0, k0 >> 2, sb);
+      __builtin_amdgcn_s_waitcnt(0);  // this thread's LDS DMA loads have landed
+      __syncthreads();                // the chunk and s_om are visible
+    } else {
+      __builtin_amdgcn_s_waitcnt(0);  // this thread's loads of this chunk have landed
+      __syncthreads();                // ... everyone's; the previous chunk is consumed
+#pragma unroll
+      for (int ks = 0; ks < CH / 4; ++ks) {
+        const int pt = k0 + 4 * ks + lk;
+        omv[ks] = pt < P ? om[g0 + pt] : 0.0;
+      }
+      if (k0 + CH < Pp) {
+        const int nbo = BUFD - bo;
+        dma_chunk<NT, CH>(pb, plane, np, r0, (k0 + CH) >> 2, sa + nbo);
+        dma_chunk<NT, CH>(pb, plane, np, c0, (k0 + CH) >> 2, sb + nbo);
+      }
+    }
+    const double *ca = sa + bo, *cb = sb + bo;
     bool hot = true;  // W parts of this chunk on FP64 MFMA
     if (SPLIT) {
       // largest |gradient component| of the row tile and |w v gradient| of the
@@ -527,9 +570,9 @@ __global__ __launch_bounds__(NT, MODE == 0 ? 2 : 1) void k_contract(DevPlan d, c
       for (int k = 0; k < 3 * 16 * T / NT; ++k) {
         const int e = tid + NT * k;
         const int q = 1 + e / (16 * T), pt = (e / T) & 15, f = e & (T - 1);
-        const int idx = (q * 8 + (pt >> 1)) * DROW + 2 * f + (pt & 1);
-        if (r0 + f < np) ma = fmax(ma, fabs(sa[idx]));
-        if (c0 + f < np) mb = fmax(mb, fabs(sb[idx] * s_om[pt]));
+        const int idx = (q * RPQ + (pt >> 1)) * DROW + 2 * f + (pt & 1);
+        if (r0 + f < np) ma = fmax(ma, fabs(ca[idx]));
+        if (c0 + f < np) mb = fmax(mb, fabs(cb[idx] * s_om[pt]));
       }
 #pragma unroll
       for (int off = 1; off < 64; off <<= 1) {
@@ -552,20 +595,20 @@ __global__ __launch_bounds__(NT, MODE == 0 ? 2 : 1) void k_contract(DevPlan d, c
       n_all += 1;
     }
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
+    for (int ks = 0; ks < CH / 4; ++ks) {
       // K index lk of step ks is point 4 ks + lk of the chunk; the column
       // operand takes its weight w v there (the weighting of Eq. 29)
       const int rowk = 2 * ks + (lk >> 1), ck = lk & 1;
-      const double omk = s_om[4 * ks + lk];
+      const double omk = SPLIT ? s_om[4 * ks + lk] : omv[ks];
       double a[2][4], bb[2][4];
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) a[x][q] = sa[(q * 8 + rowk) * DROW + 2 * (wr + 16 * x + li16) + ck];
+        for (int q = 0; q < 4; ++q) a[x][q] = ca[(q * RPQ + rowk) * DROW + 2 * (wr + 16 * x + li16) + ck];
 #pragma unroll
       for (int y = 0; y < 2; ++y)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) bb[y][q] = sb[(q * 8 + rowk) * DROW + 2 * (wc + 16 * y + li16) + ck] * omk;
+        for (int q = 0; q < 4; ++q) bb[y][q] = cb[(q * RPQ + rowk) * DROW + 2 * (wc + 16 * y + li16) + ck] * omk;
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll

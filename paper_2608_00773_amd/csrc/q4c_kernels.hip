@@ -434,12 +434,14 @@ typedef __attribute__((address_space(3))) void lds_void;
 // (q * CH/2 + pt/2) * DROW + 2f + pt%2).  Functions at
 // or beyond np are not loaded: their LDS entries are stale and lie in 16x16
 // blocks that are never multiplied (rows n .. np-1 are zero in the panel).
-// The caller waits for the loads (vmcnt) and synchronises the workgroup.
-template <int NTH, int CH = 16>
+// W < 64 loads only the first W functions (lanes W.. idle); RS is the row
+// stride in doubles (at least 2 W, a multiple of 2).  The caller waits for
+// the loads (vmcnt) and synchronises the workgroup.
+template <int NTH, int CH = 16, int W = T, int RS = DROW>
 __device__ __forceinline__ void dma_chunk(const double *pb, int64_t plane, int np, int row0, int ks0, double *dst) {
   constexpr int RPQ = CH / 2;  // rows (point pairs) per component
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const bool ok = row0 + lane < np;
+  const bool ok = lane < W && row0 + lane < np;
 #pragma unroll
   for (int k = 0; k < 4 * RPQ / (NTH / 64); ++k) {
     const int r = wave + k * (NTH / 64);
@@ -447,7 +449,7 @@ __device__ __forceinline__ void dma_chunk(const double *pb, int64_t plane, int n
     if (ok)
       __builtin_amdgcn_global_load_lds(
           (const void *)(pb + q * plane + ((int64_t)(ks0 + (u >> 1)) * np + row0 + lane) * 4 + 2 * (u & 1)),
-          (lds_void *)(dst + r * DROW), 16, 0, 0);
+          (lds_void *)(dst + r * RS), 16, 0, 0);
   }
 }
 
@@ -825,44 +827,17 @@ __global__ void k_broadcast(DevPlan d, int64_t r0, const int32_t *red_pair, cons
 
 
 constexpr int NTD = 256;       // adjoint workgroup: 4 waves = 2 column slices x 2 row halves of a half tile
-constexpr int SEGR = T + 1;     // adjoint row slab stride (odd: lanes reading 16 points hit distinct banks)
-constexpr int SEGC = T / 2 + 1; // adjoint column slab stride (half tile)
-
-// Copy 16 points (K steps ks0 .. ks0+3) of functions f0 .. f0+W-1, all four
-// components, from a batch panel into an LDS slab dst[(q*16 + pt)*SEG + f].
-// Units of 16 bytes (function f, points 2h and 2h+1 of K step ks, component
-// q); every thread issues all of its loads before its first store.
-template <int NTH, int W, int SEG>
-__device__ __forceinline__ void copy_panel(const double *pb, int64_t plane, int np, int f0, int ks0, double *dst) {
-  constexpr int U = 4 * 4 * 2 * W / NTH;
-  constexpr int G = U < 4 ? U : 4;
-#pragma unroll
-  for (int k0 = 0; k0 < U; k0 += G) {
-    double2 val[G];
-#pragma unroll
-    for (int k = 0; k < G; ++k) {
-      const int u = (k0 + k) * NTH + threadIdx.x;
-      const int f = u % W, h = (u / W) & 1, ks = (u / (2 * W)) & 3, q = u / (8 * W);
-      const int row = f0 + f;
-      val[k] = make_double2(0.0, 0.0);
-      if (row < np)
-        val[k] = *reinterpret_cast<const double2 *>(pb + q * plane + ((int64_t)(ks0 + ks) * np + row) * 4 + 2 * h);
-    }
-#pragma unroll
-    for (int k = 0; k < G; ++k) {
-      const int u = (k0 + k) * NTH + threadIdx.x;
-      const int f = u % W, h = (u / W) & 1, ks = (u / (2 * W)) & 3, q = u / (8 * W);
-      const int pt = 4 * ks + 2 * h;
-      dst[(q * 16 + pt) * SEG + f] = val[k].x;
-      dst[(q * 16 + pt + 1) * SEG + f] = val[k].y;
-    }
-  }
-}
+// adjoint LDS chunk images (layout of dma_chunk): row (q, u) of the 64 row
+// functions every RSA doubles, of the 32 column functions every RSB; both
+// are 2 mod 16, so 16 lanes reading 16 consecutive points of one function
+// hit distinct banks
+constexpr int RSA = 2 * T + 2;
+constexpr int RSB = T + 2;
 
 // One half of a work item (positions 2 w + half): partial[g] = sum over the
 // tile's 64 rows and the half's 32 columns of a_g^T C b_g for all selected
 // terms.  The chunk's row functions (64) and column functions (32) are staged
-// in LDS and shared by the 4 waves; each wave owns 16 columns x 32 rows of C
+// in LDS (loaded by DMA) and shared by the 4 waves; each wave owns 16 columns x 32 rows of C
 // in registers.  Two workgroups fit on a CU, so one computes while the other
 // stages its next chunk.
 template <bool PERSIST>
@@ -870,7 +845,7 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t te
                                                           const int32_t *order, int64_t w0, int64_t nw,
                                                           const double *staging, const double *panel,
                                                           double *partial, unsigned *tickets) {
-  __shared__ double sa[4 * 16 * SEGR], sb[4 * 16 * SEGC];
+  __shared__ double sa[32 * RSA], sb[32 * RSB];
   __shared__ double s_red[4][16];
   __shared__ int64_t s_pos;
   // slot data of the tile's 64 rows and the half's 32 columns (slot -1: padding)
@@ -897,12 +872,17 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t te
   const int l16 = lane & 15, lk = lane >> 4;
   const int cb = c0 + 16 * js;  // column block of this wave
   const int lj = cb + l16;
-  // row blocks of this wave: rb = r0 + 32 ih + 16 h, h = 0, 1
+  // row origin of this wave's two row blocks.  Column half 0 of a diagonal
+  // tile has 3 active blocks, (0,0), (0,1) and (1,1) in 16-blocks: block (1,1)
+  // moves from wave (ih 0, js 1) to the otherwise idle wave (ih 1, js 1), so
+  // no wave of that half carries two.
+  const bool dg0 = it.ti == it.tj && half == 0;
+  const int iloc = (dg0 && ih == 1 && js == 1) ? 16 : 32 * ih;
   bool act[2], upper[2];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    const int rb = r0 + 32 * ih + 16 * h;
-    act[h] = block_active(rb, cb, n);
+    const int rb = r0 + iloc + 16 * h;
+    act[h] = block_active(rb, cb, n) && !(dg0 && ih == 0 && js == 1 && h == 1);
     upper[h] = rb < cb;
   }
   const bool any = act[0] || act[1];
@@ -923,7 +903,7 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t te
     }
   }
   __syncthreads();  // slot tables visible
-  // coefficient slice: rows i = r0 + 32 ih + 4 ks + lk (ks = 0..7), column lj,
+  // coefficient slice: rows i = r0 + iloc + 4 ks + lk (ks = 0..7), column lj,
   // from the staged (batch, atom pair) blocks: element (li, lj) of a block in
   // the upper atom-block triangle, plus the mirrored element (lj, li) when
   // the 16 x 16 block is strictly upper inside one atom block (no work item
@@ -936,7 +916,7 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t te
     const int cslot = s_cslot[cl], cfn = s_cfn[cl], cnf = s_cnf[cl];
 #pragma unroll
     for (int ks = 0; ks < 8; ++ks) {
-      const int rl = 32 * ih + 4 * ks + lk;
+      const int rl = iloc + 4 * ks + lk;
       const int li = r0 + rl;
       const int rslot = s_rslot[rl], rfn = s_rfn[rl], rnf = s_rnf[rl];
       const bool live = act[ks >> 2] && rslot >= 0 && cslot >= 0 && rslot <= cslot;
@@ -955,14 +935,14 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t te
   }
   const bool tLL = terms & Q4C_TERM_LL, tSS = terms & Q4C_TERM_SS, tSO = terms & Q4C_TERM_SO;
   double *out = partial + 2 * d.work_part_off[wi] + half * P;
-  const int iloc = 32 * ih;  // tile-local first row of this wave
   const int jloc = 16 * js;  // half-local first column of this wave
 
   for (int k0 = 0; k0 < Pp; k0 += 16) {
-    __syncthreads();  // previous chunk's slabs and per-wave sums consumed
-    copy_panel<NTD, T, SEGR>(pb, plane, np, r0, k0 >> 2, sa);
-    copy_panel<NTD, T / 2, SEGC>(pb, plane, np, c0, k0 >> 2, sb);
-    __syncthreads();  // slabs visible
+    __syncthreads();  // previous chunk's images and per-wave sums consumed
+    dma_chunk<NTD, 16, T, RSA>(pb, plane, np, r0, k0 >> 2, sa);
+    dma_chunk<NTD, 16, T / 2, RSB>(pb, plane, np, c0, k0 >> 2, sb);
+    __builtin_amdgcn_s_waitcnt(0);  // this thread's LDS DMA loads have landed
+    __syncthreads();                // the chunk images are visible
     // X[j][pt] = sum over the selected terms of (C^T Y)[j][pt] Z[pt][j]: the
     // MFMA takes the coefficients as its first operand, so register r of lane
     // (l16, lk) holds column j = lk + 4 r (of the wave's 16) at point pt = l16
@@ -974,7 +954,8 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t te
 #pragma unroll
       for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) zt[q][r] = sb[(q * 16 + l16) * SEGC + jloc + d_row_f64(lk, r)];
+        for (int r = 0; r < 4; ++r)
+          zt[q][r] = sb[(q * 8 + (l16 >> 1)) * RSB + 2 * (jloc + d_row_f64(lk, r)) + (l16 & 1)];
       // terms grouped by the row component Y (points x functions):
       //   Y=phi: (V, phi); Y=dx: (Ws, dx), (Wso_y, -dz), (Wso_z, +dy);
       //   Y=dy: (Ws, dy), (Wso_x, +dz), (Wso_z, -dx); Y=dz: (Ws, dz), (Wso_x, -dy), (Wso_y, +dx)
@@ -984,7 +965,8 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t te
         // second operand: Y[yq][pt = l16][i = iloc + 4 ks + lk]
         double ya[8];
 #pragma unroll
-        for (int ks = 0; ks < 8; ++ks) ya[ks] = sa[(yq * 16 + l16) * SEGR + iloc + 4 * ks + lk];
+        for (int ks = 0; ks < 8; ++ks)
+          ya[ks] = sa[(yq * 8 + (l16 >> 1)) * RSA + 2 * (iloc + 4 * ks + lk) + (l16 & 1)];
         // the terms sharing this Y run as independent MFMA chains, interleaved
         // over the K steps; a lone term uses two chains (even / odd steps)
         if (yq == 0) {

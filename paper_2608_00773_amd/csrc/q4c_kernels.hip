@@ -734,30 +734,65 @@ __global__ __launch_bounds__(NT, MODE == 0 ? 2 : 1) void k_contract(DevPlan d, c
 // one).  The sum is a single sequential chain in batch order, so results
 // repeat bit for bit and do not depend on how batches are split into passes.
 // Loads of four incidences are issued together.
-__global__ void k_reduce(DevPlan d, int64_t r0, const int32_t *red_pair, const uint8_t *red_first,
-                         const int64_t *red_inc_off, const int64_t *inc_src, const double *staging, double *store,
-                         int accumulate) {
+__global__ __launch_bounds__(256) void k_reduce(DevPlan d, int64_t r0, const int32_t *red_pair,
+                                                const uint8_t *red_first, const int64_t *red_inc_off,
+                                                const int64_t *inc_src, const double *staging, double *store,
+                                                int accumulate) {
+  __shared__ int64_t s_src[256];
   const int64_t r = r0 + blockIdx.x;
   const int p = red_pair[r];
-  const int64_t blk = (int64_t)d.pair_na[p] * d.pair_nb[p];
+  const int blk = d.pair_na[p] * d.pair_nb[p];
   const int64_t k0 = red_inc_off[r], k1 = red_inc_off[r + 1];
   const bool add = accumulate || !red_first[r];
   const int64_t po = d.pair_off[p];
-  for (int64_t e = threadIdx.x; e < 5 * blk; e += blockDim.x) {
-    const int q = (int)(e / blk);
-    double *dst = store + q * d.store_len + po + (e - q * blk);
-    double s = add ? *dst : 0.0;
-    int64_t k = k0;
-    for (; k + 4 <= k1; k += 4) {
-      const double a0 = staging[inc_src[k] + e], a1 = staging[inc_src[k + 1] + e];
-      const double a2 = staging[inc_src[k + 2] + e], a3 = staging[inc_src[k + 3] + e];
-      s += a0;
-      s += a1;
-      s += a2;
-      s += a3;
+  const int m = 5 * blk;
+  // each thread owns elements e = tid, tid + 256, ... (at most 4 at a time in registers)
+  for (int e0 = 0; e0 < m; e0 += 4 * 256) {
+    double sum[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int e = e0 + j * 256 + threadIdx.x;
+      sum[j] = 0.0;
+      if (e < m && add) {
+        const int q = e / blk;
+        sum[j] = store[q * d.store_len + po + (e - q * blk)];
+      }
     }
-    for (; k < k1; ++k) s += staging[inc_src[k] + e];
-    *dst = s;
+    for (int64_t kb = k0; kb < k1; kb += 256) {
+      const int nk = (int)(k1 - kb < 256 ? k1 - kb : 256);
+      __syncthreads();  // previous offsets consumed
+      if (threadIdx.x < nk) s_src[threadIdx.x] = inc_src[kb + threadIdx.x];
+      __syncthreads();
+      int k = 0;
+      for (; k + 8 <= nk; k += 8) {
+        double a[4][8];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int e = e0 + j * 256 + threadIdx.x;
+#pragma unroll
+          for (int u = 0; u < 8; ++u) a[j][u] = e < m ? staging[s_src[k + u] + e] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int u = 0; u < 8; ++u) sum[j] += a[j][u];
+      }
+      for (; k < nk; ++k) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int e = e0 + j * 256 + threadIdx.x;
+          if (e < m) sum[j] += staging[s_src[k] + e];
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int e = e0 + j * 256 + threadIdx.x;
+      if (e < m) {
+        const int q = e / blk;
+        store[q * d.store_len + po + (e - q * blk)] = sum[j];
+      }
+    }
   }
 }
 
@@ -811,17 +846,34 @@ __global__ void k_spinor(DevPlan d, const double *store, double *spin_w, double 
 
 // Copy the coefficient blocks of every stored pair to each of its staged
 // (batch, pair) blocks: the transpose of k_reduce.
-__global__ void k_broadcast(DevPlan d, int64_t r0, const int32_t *red_pair, const int64_t *red_inc_off,
-                            const int64_t *inc_src, const double *coef, double *staging) {
+// Adjoint broadcast: every staged incidence of pair red_pair[r] gets the
+// pair's coefficient block.  Threads cover (incidence, element) pairs, so
+// small blocks keep every thread busy; the incidence offsets go through LDS.
+__global__ __launch_bounds__(256) void k_broadcast(DevPlan d, int64_t r0, const int32_t *red_pair,
+                                                   const int64_t *red_inc_off, const int64_t *inc_src,
+                                                   const double *coef, double *staging) {
+  __shared__ int64_t s_src[256];
   const int64_t r = r0 + blockIdx.x;
   const int p = red_pair[r];
-  const int64_t blk = (int64_t)d.pair_na[p] * d.pair_nb[p];
+  const int blk = d.pair_na[p] * d.pair_nb[p];
   const int64_t k0 = red_inc_off[r], k1 = red_inc_off[r + 1];
   const int64_t po = d.pair_off[p];
-  for (int64_t e = threadIdx.x; e < 5 * blk; e += blockDim.x) {
-    const int q = (int)(e / blk);
-    const double c = coef[q * d.store_len + po + (e - q * blk)];
-    for (int64_t k = k0; k < k1; ++k) staging[inc_src[k] + e] = c;
+  const int m = 5 * blk;
+  // elements per pass over the block and incidence groups sharing the 256 threads
+  const int span = m < 256 ? m : 256;
+  const int groups = 256 / span;
+  const int g = threadIdx.x / span, el = threadIdx.x - g * span;
+  for (int64_t kb = k0; kb < k1; kb += 256) {
+    const int nk = (int)(k1 - kb < 256 ? k1 - kb : 256);
+    __syncthreads();
+    if (threadIdx.x < nk) s_src[threadIdx.x] = inc_src[kb + threadIdx.x];
+    __syncthreads();
+    if (g >= groups) continue;
+    for (int e = el; e < m; e += span) {
+      const int q = e / blk;
+      const double c = coef[q * d.store_len + po + (e - q * blk)];
+      for (int k = g; k < nk; k += groups) staging[s_src[k] + e] = c;
+    }
   }
 }
 

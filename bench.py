@@ -35,7 +35,7 @@ PREC = {"f64": 0, "split": 1, "f32": 2}
 # Keyed by the SHA-256 of the kernel source the counters were taken on: any
 # change to the kernels makes the figure stale, and it is then reported as null.
 TRAFFIC = {
-    ("38e02e0567d995788f404da2d5a93941dd20616daac8229ea623d4585b6739fe", "f64", 120): 6.907e9 + 4.282e9,
+    ("c19ad13a15ae715720e4aac50f9b40d47e7c19eeba431f6f41cd292971300516", "f64", 120): 8.489e9 + 4.258e9,
 }
 
 
@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shapes (one workgroup per work item) and eager launches")
+    ap.add_argument("--no-graphs", action="store_true",
+                    help="autotune but launch eagerly (for per-dispatch counter collection)")
     ap.add_argument("--cpu-sample", type=float, default=0.05, help="fraction of grid points for the oracle timing")
     ap.add_argument("--n-atoms", type=int, default=120)
     ap.add_argument("--mode", choices=["full", "step", "forward", "adjoint"], default="full",
@@ -257,7 +259,7 @@ def main():
         # every later call is one HIP graph launch
         t0 = time.perf_counter()
         tune = plan.autotune(v, store, prec, gbar, grad, reps=3)
-        plan.set_graphs(True)
+        plan.set_graphs(not a.no_graphs)
         print("[bench] autotune %.1f s: %s" % (time.perf_counter() - t0, tune), file=sys.stderr, flush=True)
 
     def timed(fn, k):
@@ -369,7 +371,7 @@ def main():
             "launches_per_step": launches_per_step,
         },
         "launch": {"contract": plan.get_launch(q.KERNEL_CONTRACT), "density": plan.get_launch(q.KERNEL_DENSITY),
-                   "graphs": tune is not None, "autotune_table": tune},
+                   "graphs": tune is not None and not a.no_graphs, "autotune_table": tune},
         "kernels_ms_per_step": {k: v_[0] / a.steps for k, v_ in tim.items() if v_[1]},
         "forward_ms": fwd,
         "forward_points_per_s": {k: n_act / (t * 1e-3) for k, t in fwd.items()},

@@ -160,6 +160,7 @@ struct q4c_plan {
   double *d_staging = nullptr;
   int32_t *d_flag = nullptr;
   int32_t *d_order = nullptr;      // per pass: work items sorted by cost (pass-relative indices)
+  uint64_t *d_hotmask = nullptr;   // [n_work] split modes: 16-point chunks deferred to FP64
   unsigned *d_tickets = nullptr;   // [2][n_passes][kTicketsPerLaunch] persistent-launch queues
   int n_cu = 256;                  // compute units of the plan's device
 

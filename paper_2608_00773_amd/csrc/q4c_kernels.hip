@@ -308,7 +308,9 @@ __global__ void k_om(DevPlan d, const double *v, double *om, unsigned long long 
 }
 
 // One (batch, function tile of 64): tabulate the tile's functions at all
-// points of the batch into the panel.  Each group of 16 points is computed
+// points of the batch into the panel, and record for every point the largest
+// |gradient component| over the tile's functions (after the batch's panel, at
+// 4 Pp np + ti Pp + point): the split-precision routing bound reads it.  Each group of 16 points is computed
 // in lm order (few divergent harmonic branches per wave) into LDS, then
 // written out as 16 contiguous 2 KB runs.
 constexpr int PLD = T + 1;  // padded LDS row of the panel stage
@@ -317,6 +319,7 @@ __global__ __launch_bounds__(256) void k_panel(DevPlan d, const WorkItem *tiles,
                                                double *panel) {
   __shared__ TileMeta M;
   __shared__ double st[4 * 16 * PLD];
+  __shared__ double s_gx[4][16];
   const WorkItem it = tiles[t0 + xcd_map(blockIdx.x, nt)];
   const int b = it.batch;
   const int g0 = d.batch_pt_off[b], P = d.batch_pt_off[b + 1] - g0;
@@ -340,6 +343,19 @@ __global__ __launch_bounds__(256) void k_panel(DevPlan d, const WorkItem *tiles,
       st[(3 * 16 + pt) * PLD + fl] = fz;
     }
     __syncthreads();
+    {
+      // largest |d phi / d x_a| per point over the tile's functions: thread
+      // (pt, group of 4 functions), then the 4 groups of a wave, then the waves
+      const int pt = threadIdx.x & 15, fg = threadIdx.x >> 4;
+      double m = 0.0;
+#pragma unroll
+      for (int q = 1; q < 4; ++q)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) m = fmax(m, fabs(st[(q * 16 + pt) * PLD + 4 * fg + k]));
+      m = fmax(m, __shfl_xor(m, 16));
+      m = fmax(m, __shfl_xor(m, 32));
+      if ((threadIdx.x & 63) < 16) s_gx[threadIdx.x >> 6][pt] = m;
+    }
     // (q, point quad) runs: rows r0 .. r0 + nrow - 1, 4 points each, contiguous
 #pragma unroll
     for (int q = 0; q < 4; ++q)
@@ -350,7 +366,10 @@ __global__ __launch_bounds__(256) void k_panel(DevPlan d, const WorkItem *tiles,
         if (il < nrow)
           pb[((int64_t)(q * (Pp >> 2) + (g16 >> 2) + p4) * np + r0 + il) * 4 + pp] = st[(q * 16 + 4 * p4 + pp) * PLD + il];
       }
-    __syncthreads();
+    __syncthreads();  // s_gx written; st consumed
+    if (threadIdx.x < 16)
+      pb[(int64_t)4 * Pp * np + (int64_t)it.ti * Pp + g16 + threadIdx.x] =
+          fmax(fmax(s_gx[0][threadIdx.x], s_gx[1][threadIdx.x]), fmax(s_gx[2][threadIdx.x], s_gx[3][threadIdx.x]));
   }
 }
 
@@ -408,6 +427,23 @@ __device__ __forceinline__ void stage_store(double *staging, const SlotInfo &si,
   }
 }
 
+// As stage_store, adding to the staged element (and its mirror) instead.
+template <int Q0, int Q1>
+__device__ __forceinline__ void stage_add(double *staging, const SlotInfo &si, const SlotInfo &sj, int li, int lj,
+                                          bool upper, const double *v) {
+  if (si.slot > sj.slot) return;
+  const int64_t blk = si.row_off + 5 * (int64_t)si.nfn * (sj.fnoff - si.fnoff);
+  const int64_t pq = (int64_t)si.nfn * sj.nfn;
+  const int64_t e = (int64_t)(li - si.fnoff) * sj.nfn + (lj - sj.fnoff);
+#pragma unroll
+  for (int q = Q0; q < Q1; ++q) staging[blk + q * pq + e] += v[q - Q0];
+  if (upper && si.slot == sj.slot) {
+    const int64_t em = (int64_t)(lj - si.fnoff) * sj.nfn + (li - sj.fnoff);
+#pragma unroll
+    for (int q = Q0; q < Q1; ++q) staging[blk + q * pq + em] += mirror_sign(q) * v[q - Q0];
+  }
+}
+
 // MFMA 16x16x4 lane layouts (lane l, l16 = l % 16, lk = l / 16):
 //   A[i][k]: lane i + 16 k;  B[k][j]: lane j + 16 k;
 //   D (f64_16x16x4): register r of lane l holds D[lk + 4 r][l16];
@@ -415,8 +451,10 @@ __device__ __forceinline__ void stage_store(double *staging, const SlotInfo &si,
 __device__ __forceinline__ int d_row_f64(int lk, int r) { return lk + 4 * r; }
 __device__ __forceinline__ int d_row_f32(int lk, int r) { return 4 * lk + r; }
 
-// Precision modes of the forward contraction.
-enum { MODE_F64 = 0, MODE_SPLIT = 1, MODE_F32 = 2 };
+// Modes of the forward contraction: FP64; split (hi+lo FP32 operands) and
+// single FP32 operands for the W parts (V stays FP64), whose chunks with large
+// terms are deferred; MODE_HOT adds the deferred chunks' W parts in FP64.
+enum { MODE_F64 = 0, MODE_SPLIT = 1, MODE_F32 = 2, MODE_HOT = 3 };
 
 // LDS image of one 16-point chunk of a 64-function tile, in the panel's own
 // order: row (q, u) holds component q at points 2u and 2u+1 of the chunk,
@@ -462,22 +500,29 @@ constexpr double kU32 = 5.9604644775390625e-08;
 // Work item positions 0..nw-1 of a pass map to work items w0 + order[w0 + pos]
 // (order != NULL: cost-sorted) or w0 + pos.  tickets == NULL: one workgroup
 // per position; otherwise a persistent loop (next_item).
+//
+// Split modes (MODE_SPLIT, MODE_F32): V accumulates in FP64, the W parts in
+// FP32; a 16-point chunk whose W bound exceeds tau skips its W products here
+// and sets bit k0/16 of hotmask[w] (P <= 1024); MODE_HOT then runs those chunks'
+// W products in FP64 and adds them to the staged elements.
 template <int MODE, bool PERSIST>
-__global__ __launch_bounds__(NT, MODE == 0 ? 2 : 1) void k_contract(DevPlan d, const WorkItem *work,
-                                                                    const int32_t *order, int64_t w0, int64_t nw,
-                                                                    const double *om, const double *panel,
-                                                                    double *staging, double tau,
-                                                                    unsigned long long *chunks, unsigned *tickets) {
-  constexpr bool SPLIT = MODE != 0;
+__global__ __launch_bounds__(NT, 2) void k_contract(DevPlan d, const WorkItem *work, const int32_t *order,
+                                                    int64_t w0, int64_t nw, const double *om, const double *panel,
+                                                    double *staging, double tau, unsigned long long *chunks,
+                                                    unsigned *tickets, uint64_t *hotmask) {
+  constexpr bool SPLIT = MODE == MODE_SPLIT || MODE == MODE_F32;
+  constexpr bool HOTK = MODE == MODE_HOT;
   __shared__ double sa[32 * DROW], sb[32 * DROW];
   __shared__ double s_om[16];
-  __shared__ double s_gm[2][NT / 64];
   __shared__ int64_t s_pos;
   unsigned long long n_hot = 0, n_all = 0;
   int64_t pos = PERSIST ? next_item(tickets, nw, order != nullptr, &s_pos)
                         : (order ? (int64_t)blockIdx.x : xcd_map(blockIdx.x, nw));
   while (!PERSIST || pos < nw) {
-  const WorkItem it = work[w0 + (order ? order[w0 + pos] : pos)];
+  const int64_t wi = w0 + (order ? order[w0 + pos] : pos);
+  const WorkItem it = work[wi];
+  const uint64_t hmask_in = HOTK ? hotmask[wi] : 0;  // MODE_HOT: chunks to add
+  uint64_t hmask = 0;                               // split modes: deferred chunks
   const int b = it.batch;
   const int g0 = d.batch_pt_off[b], P = d.batch_pt_off[b + 1] - g0;
   const int f0 = d.batch_fn_off[b], n = d.batch_fn_off[b + 1] - f0;
@@ -515,9 +560,9 @@ __global__ __launch_bounds__(NT, MODE == 0 ? 2 : 1) void k_contract(DevPlan d, c
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int q = 0; q < 5; ++q) acc[x][y][q] = dbl4{0.0, 0.0, 0.0, 0.0};
-  // FP32 accumulators of the four W parts (split / f32 modes)
+  // FP32 accumulators of the four W parts (split modes)
   flt4 accf[2][2][4];
-  if (MODE != MODE_F64) {
+  if (SPLIT) {
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -527,21 +572,24 @@ __global__ __launch_bounds__(NT, MODE == 0 ? 2 : 1) void k_contract(DevPlan d, c
   }
 
   const double cp = d.cprime;
-  // FP64: chunks of 8 points in two LDS buffers, the next chunk's DMA in
-  // flight while this one is multiplied (one barrier per chunk).  Split
-  // modes: chunks of 16 points, one buffer (the FP64 routing is decided per
-  // 16-point chunk).
-  constexpr int CH = SPLIT ? 16 : 8;
+  // Chunks of 8 points in two LDS buffers, the next chunk's DMA in flight
+  // while this one is multiplied (one barrier per chunk); the split modes'
+  // FP64 routing is decided per 16 points.  MODE_HOT: 16-point chunks, one
+  // buffer, only the deferred ones.
+  constexpr int CH = HOTK ? 16 : 8;
+  constexpr bool DB = !HOTK;  // double-buffered chunk images
   constexpr int RPQ = CH / 2;              // LDS rows per component
   constexpr int BUFD = 4 * RPQ * DROW;     // doubles per chunk image
-  if (!SPLIT) {
+  bool hot = true;  // W parts of the current 16 points on FP64 MFMA
+  if (DB) {
     dma_chunk<NT, CH>(pb, plane, np, r0, 0, sa);
     dma_chunk<NT, CH>(pb, plane, np, c0, 0, sb);
   }
   for (int k0 = 0; k0 < Pp; k0 += CH) {
-    const int bo = SPLIT ? 0 : ((k0 / CH) & 1) * BUFD;  // this chunk's buffer
+    if (HOTK && !((hmask_in >> (k0 >> 4)) & 1)) continue;  // WG-uniform
+    const int bo = DB ? ((k0 / CH) & 1) * BUFD : 0;  // this chunk's buffer
     double omv[CH / 4];  // FP64 path: w v at points 4 ks + lk of this chunk
-    if (SPLIT) {
+    if (!DB) {
       __syncthreads();  // previous chunk's operands consumed
       if (tid < 16) s_om[tid] = k0 + tid < P ? om[g0 + k0 + tid] : 0.0;
       dma_chunk<NT, CH>(pb, plane, np, r0, k0 >> 2, sa);
@@ -563,45 +611,35 @@ __global__ __launch_bounds__(NT, MODE == 0 ? 2 : 1) void k_contract(DevPlan d, c
       }
     }
     const double *ca = sa + bo, *cb = sb + bo;
-    bool hot = true;  // W parts of this chunk on FP64 MFMA
-    if (SPLIT) {
-      // largest |gradient component| of the row tile and |w v gradient| of the
-      // column tile over the chunk (functions inside the panel)
-      double ma = 0.0, mb = 0.0;
-#pragma unroll
-      for (int k = 0; k < 3 * 16 * T / NT; ++k) {
-        const int e = tid + NT * k;
-        const int q = 1 + e / (16 * T), pt = (e / T) & 15, f = e & (T - 1);
-        const int idx = (q * RPQ + (pt >> 1)) * DROW + 2 * f + (pt & 1);
-        if (r0 + f < np) ma = fmax(ma, fabs(ca[idx]));
-        if (c0 + f < np) mb = fmax(mb, fabs(cb[idx] * s_om[pt]));
+    if (SPLIT && (k0 & 15) == 0) {
+      // bound of the 16 points k0 .. k0+15: A = largest |gradient component|
+      // of the row tile, B = largest |w v gradient component| of the column
+      // tile, from the panel's per-point maxima; every wave forms the same
+      // values, so the decision is uniform over the workgroup
+      const double *gmx = pb + 4 * plane;
+      double va = 0.0, vb = 0.0;
+      if (lane < 16) {
+        va = gmx[(int64_t)it.ti * Pp + k0 + lane];
+      } else if (lane < 32) {
+        const int pt = k0 + lane - 16;
+        vb = pt < P ? gmx[(int64_t)it.tj * Pp + pt] * fabs(om[g0 + pt]) : 0.0;
       }
 #pragma unroll
       for (int off = 1; off < 64; off <<= 1) {
-        ma = fmax(ma, __shfl_xor(ma, off));
-        mb = fmax(mb, __shfl_xor(mb, off));
+        va = fmax(va, __shfl_xor(va, off));
+        vb = fmax(vb, __shfl_xor(vb, off));
       }
-      if (lane == 0) {
-        s_gm[0][wave] = ma;
-        s_gm[1][wave] = mb;
-      }
-      __syncthreads();
-      double A = 0.0, B = 0.0;
-#pragma unroll
-      for (int w = 0; w < NT / 64; ++w) {
-        A = fmax(A, s_gm[0][w]);
-        B = fmax(B, s_gm[1][w]);
-      }
-      hot = kU32 * cp * 48.0 * A * B > tau;
+      hot = kU32 * cp * 48.0 * va * vb > tau;
       n_hot += hot ? 1 : 0;
       n_all += 1;
+      if (hot) hmask |= (uint64_t)1 << (k0 >> 4);
     }
 #pragma unroll
     for (int ks = 0; ks < CH / 4; ++ks) {
       // K index lk of step ks is point 4 ks + lk of the chunk; the column
       // operand takes its weight w v there (the weighting of Eq. 29)
       const int rowk = 2 * ks + (lk >> 1), ck = lk & 1;
-      const double omk = SPLIT ? s_om[4 * ks + lk] : omv[ks];
+      const double omk = DB ? omv[ks] : s_om[4 * ks + lk];
       double a[2][4], bb[2][4];
 #pragma unroll
       for (int x = 0; x < 2; ++x)
@@ -611,6 +649,21 @@ __global__ __launch_bounds__(NT, MODE == 0 ? 2 : 1) void k_contract(DevPlan d, c
       for (int y = 0; y < 2; ++y)
 #pragma unroll
         for (int q = 0; q < 4; ++q) bb[y][q] = cb[(q * RPQ + rowk) * DROW + 2 * (wc + 16 * y + li16) + ck] * omk;
+      // FP32 operands of the gradient components (split modes, chunks not deferred)
+      float a32[2][4], b32[2][4], a32l[2][4], b32l[2][4];
+      if (SPLIT && !hot) {
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int q = 1; q < 4; ++q) {
+            a32[x][q] = (float)a[x][q];
+            b32[x][q] = (float)bb[x][q];
+            if (MODE == MODE_SPLIT) {
+              a32l[x][q] = (float)(a[x][q] - (double)a32[x][q]);
+              b32l[x][q] = (float)(bb[x][q] - (double)b32[x][q]);
+            }
+          }
+      }
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -618,8 +671,8 @@ __global__ __launch_bounds__(NT, MODE == 0 ? 2 : 1) void k_contract(DevPlan d, c
           if (!act[x][y]) continue;  // wave-uniform
           const double *av = a[x];
           const double *bv = bb[y];
-          acc[x][y][0] = mfma64(av[0], bv[0], acc[x][y][0]);
-          if (hot) {
+          if (!HOTK) acc[x][y][0] = mfma64(av[0], bv[0], acc[x][y][0]);
+          if (MODE == MODE_F64 || HOTK) {
             acc[x][y][1] = mfma64(av[1], bv[1], acc[x][y][1]);
             acc[x][y][2] = mfma64(av[2], bv[3], acc[x][y][2]);
             acc[x][y][3] = mfma64(av[3], bv[1], acc[x][y][3]);
@@ -629,13 +682,10 @@ __global__ __launch_bounds__(NT, MODE == 0 ? 2 : 1) void k_contract(DevPlan d, c
             acc[x][y][3] = mfma64(-av[1], bv[3], acc[x][y][3]);
             acc[x][y][4] = mfma64(-av[2], bv[1], acc[x][y][4]);
             acc[x][y][1] = mfma64(av[3], bv[3], acc[x][y][1]);
+          } else if (hot) {
+            // deferred to MODE_HOT
           } else if (MODE == MODE_F32) {
-            float af[4], bf[4];
-#pragma unroll
-            for (int q = 1; q < 4; ++q) {
-              af[q] = (float)av[q];
-              bf[q] = (float)bv[q];
-            }
+            const float *af = a32[x], *bf = b32[y];
             accf[x][y][0] = mfma32(af[1], bf[1], accf[x][y][0]);
             accf[x][y][1] = mfma32(af[2], bf[3], accf[x][y][1]);
             accf[x][y][2] = mfma32(af[3], bf[1], accf[x][y][2]);
@@ -648,14 +698,7 @@ __global__ __launch_bounds__(NT, MODE == 0 ? 2 : 1) void k_contract(DevPlan d, c
           } else if (MODE == MODE_SPLIT) {
             // hi + lo split: x = hi + lo with hi = fl(x), lo = fl(x - hi);
             // x y ~ hi_x hi_y + hi_x lo_y + lo_x hi_y (lo_x lo_y dropped)
-            float ah[4], al[4], bh[4], bl[4];
-#pragma unroll
-            for (int q = 1; q < 4; ++q) {
-              ah[q] = (float)av[q];
-              al[q] = (float)(av[q] - (double)ah[q]);
-              bh[q] = (float)bv[q];
-              bl[q] = (float)(bv[q] - (double)bh[q]);
-            }
+            const float *ah = a32[x], *bh = b32[y], *al = a32l[x], *bl = b32l[y];
 #define SPLIT3(ACC, AI, BI, SG)                                  \
   ACC = mfma32(SG ah[AI], bh[BI], ACC);                          \
   ACC = mfma32(SG ah[AI], bl[BI], ACC);                          \
@@ -674,24 +717,6 @@ __global__ __launch_bounds__(NT, MODE == 0 ? 2 : 1) void k_contract(DevPlan d, c
         }
     }
   }
-  if (SPLIT) {
-    // FP32 partials (register r of lane (l16, lk) holds X[4 lk + r][l16]) join
-    // the FP64 accumulators as X = sum_r S_r X_r, S_r[i][k] = [i == 4 k + r],
-    // X_r[k][j] = X[4 k + r][j]: four rank-4 FP64 MFMAs per block and part.
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-      for (int y = 0; y < 2; ++y) {
-        if (!act[x][y]) continue;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const double sel = li16 == 4 * lk + r ? 1.0 : 0.0;
-#pragma unroll
-          for (int q = 0; q < 4; ++q) acc[x][y][q + 1] = mfma64(sel, (double)accf[x][y][q][r], acc[x][y][q + 1]);
-        }
-      }
-  }
-
   // write the computed blocks to the staged atom-pair blocks
 #pragma unroll
   for (int y = 0; y < 2; ++y) {
@@ -706,18 +731,36 @@ __global__ __launch_bounds__(NT, MODE == 0 ? 2 : 1) void k_contract(DevPlan d, c
       const bool upper = rb < cb;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
+        // V and, in FP64 modes, the W parts: FP64 MFMA rows lk + 4 r
         const int li = rb + d_row_f64(lk, r);
-        if (li < n) {
+        if (li < n && !(HOTK && hmask_in == 0)) {
           const SlotInfo si = slot_of(d, f0, sbase, li);
           double vals[5];
           vals[0] = acc[x][y][0][r];
 #pragma unroll
           for (int q = 1; q < 5; ++q) vals[q] = cp * acc[x][y][q][r];
-          stage_store<0, 5>(staging, si, sj, li, lj, upper, vals);
+          if (MODE == MODE_F64)
+            stage_store<0, 5>(staging, si, sj, li, lj, upper, vals);
+          else if (HOTK)
+            stage_add<1, 5>(staging, si, sj, li, lj, upper, vals + 1);
+          else
+            stage_store<0, 1>(staging, si, sj, li, lj, upper, vals);
+        }
+        if (SPLIT) {
+          // the W parts from the FP32 accumulators: FP32 MFMA rows 4 lk + r
+          const int lf = rb + d_row_f32(lk, r);
+          if (lf < n) {
+            const SlotInfo sf = slot_of(d, f0, sbase, lf);
+            double w[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) w[q] = cp * (double)accf[x][y][q][r];
+            stage_store<1, 5>(staging, sf, sj, lf, lj, upper, w);
+          }
         }
       }
     }
   }
+  if (SPLIT && threadIdx.x == 0) hotmask[wi] = hmask;
   if (!PERSIST) break;
   pos = next_item(tickets, nw, order != nullptr, &s_pos);
   }
@@ -1176,31 +1219,41 @@ int launch_integrate(const q4c_plan *p, const double *v, int precision, uint32_t
           {
           if (tickets)
             hipLaunchKernelGGL((k_contract<MODE_F64, true>), dim3(grid), dim3(NT), 0, s, p->dp, p->d_work, order, ps.w0,
-                               nw, p->d_om, panel, p->d_staging, p->split_tau, p->d_chunks, tickets);
+                               nw, p->d_om, panel, p->d_staging, p->split_tau, p->d_chunks, tickets, p->d_hotmask);
           else
             hipLaunchKernelGGL((k_contract<MODE_F64, false>), dim3(grid), dim3(NT), 0, s, p->dp, p->d_work, order, ps.w0,
-                               nw, p->d_om, panel, p->d_staging, p->split_tau, p->d_chunks, tickets);
+                               nw, p->d_om, panel, p->d_staging, p->split_tau, p->d_chunks, tickets, p->d_hotmask);
         }
         else if (precision == Q4C_PREC_F32)
           {
           if (tickets)
             hipLaunchKernelGGL((k_contract<MODE_F32, true>), dim3(grid), dim3(NT), 0, s, p->dp, p->d_work, order, ps.w0,
-                               nw, p->d_om, panel, p->d_staging, p->split_tau, p->d_chunks, tickets);
+                               nw, p->d_om, panel, p->d_staging, p->split_tau, p->d_chunks, tickets, p->d_hotmask);
           else
             hipLaunchKernelGGL((k_contract<MODE_F32, false>), dim3(grid), dim3(NT), 0, s, p->dp, p->d_work, order, ps.w0,
-                               nw, p->d_om, panel, p->d_staging, p->split_tau, p->d_chunks, tickets);
+                               nw, p->d_om, panel, p->d_staging, p->split_tau, p->d_chunks, tickets, p->d_hotmask);
         }
         else
           {
           if (tickets)
             hipLaunchKernelGGL((k_contract<MODE_SPLIT, true>), dim3(grid), dim3(NT), 0, s, p->dp, p->d_work, order, ps.w0,
-                               nw, p->d_om, panel, p->d_staging, p->split_tau, p->d_chunks, tickets);
+                               nw, p->d_om, panel, p->d_staging, p->split_tau, p->d_chunks, tickets, p->d_hotmask);
           else
             hipLaunchKernelGGL((k_contract<MODE_SPLIT, false>), dim3(grid), dim3(NT), 0, s, p->dp, p->d_work, order, ps.w0,
-                               nw, p->d_om, panel, p->d_staging, p->split_tau, p->d_chunks, tickets);
+                               nw, p->d_om, panel, p->d_staging, p->split_tau, p->d_chunks, tickets, p->d_hotmask);
         }
       }
       if ((rc = check_launch("k_contract")) != Q4C_OK) return rc;
+      if (precision != Q4C_PREC_F64) {
+        // the deferred chunks' W parts in FP64, one workgroup per work item
+        {
+          TimedLaunch tl_(p, Q4C_TIMER_CONTRACT, s);
+          hipLaunchKernelGGL((k_contract<MODE_HOT, false>), dim3((unsigned)nw), dim3(NT), 0, s, p->dp, p->d_work,
+                             nullptr, ps.w0, nw, p->d_om, panel, p->d_staging, p->split_tau, p->d_chunks, nullptr,
+                             p->d_hotmask);
+        }
+        if ((rc = check_launch("k_contract<hot>")) != Q4C_OK) return rc;
+      }
     }
     if (nr > 0) {
       {

@@ -483,7 +483,8 @@ int build_host(q4c_plan *p, const q4c_basis *b, const q4c_grid *g, const std::ve
     }
     int nt = (nb_fn + T - 1) / T;
     int64_t bpart = 2 * (int64_t)(nt * (nt + 1) / 2) * (g1 - g0);  // two column halves per work item
-    int64_t bpanel = 4 * q4c::pad16(g1 - g0) * q4c::pad16(nb_fn);
+    // panel (4 components) and, after it, the per-(tile, point) largest gradient magnitude
+    int64_t bpanel = 4 * q4c::pad16(g1 - g0) * q4c::pad16(nb_fn) + (int64_t)nt * q4c::pad16(g1 - g0);
     if (bt > cur.b0 && (staging + partial + panel + bstage + bpart + bpanel > budget_doubles)) close_pass(bt);
     p->panel_off.push_back(panel);
     panel += bpanel;
@@ -641,6 +642,8 @@ int build_device(q4c_plan *p) {
     if (hipMemset(p->d_tickets, 0, nt * sizeof(unsigned)) != hipSuccess) return fail(Q4C_EHIP, "hipMemset");
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0) p->n_cu = ncu;
+    rc = device_alloc(p, std::max<size_t>(p->work.size(), 1) * sizeof(uint64_t), (void **)&p->d_hotmask);
+    if (rc != Q4C_OK) return rc;
   }
   d.R = R;
   d.fn_atom = fn_atom;
@@ -997,6 +1000,8 @@ int q4c_integrate_H(const q4c_plan *p, const double *v_dev, int32_t precision, u
   if ((flags & Q4C_ASSEMBLE_V) && p->store_len > 0 && !spin_v_dev) return fail(Q4C_EINVAL, "NULL V spinor output");
   int rc = check_plan_dev(p);
   if (rc != Q4C_OK) return rc;
+  if (precision != Q4C_PREC_F64 && q4c::pad16(p->max_batch_points) > 64 * 16)
+    return fail(Q4C_EUNSUPPORTED, "split precisions need batches of at most 1024 points (p_max)");
   if (flags & Q4C_CHECK_FINITE) {
     bool ok = true;
     rc = q4c::launch_check_finite(p, v_dev, (hipStream_t)stream, &ok);

@@ -369,3 +369,47 @@ def test_staging_passes_do_not_change_results(q, medium):
     assert outs[0][0] == 1 and outs[1][0] > 3
     for x, y in zip(outs[0][1], outs[1][1]):
         assert torch.equal(x, y)
+
+
+def test_split_all_chunks_deferred_equals_f64(q, medium):
+    """With a vanishing routing bound every 16-point chunk's W products are
+    deferred to FP64 (added to zeros in the same MFMA order): the split and
+    FP32 stores then equal the FP64 store bit for bit.  A huge bound defers
+    none and keeps the 1e-8 Ha bar against the FP64 path only as an error
+    report (no chunk on FP64)."""
+    torch = _torch()
+    wl = medium[0]
+    v = torch.from_numpy(wl.v).cuda()
+    ref = q.new_store(q.Plan(wl))
+    q.q4c_integrate_H(q.Plan(wl), v, q.PREC_F64, 0, ref)
+    plan = q.Plan(wl, split_threshold=1e-300)
+    for prec in (q.PREC_SPLIT_F32, q.PREC_F32):
+        st = q.new_store(plan)
+        q.q4c_integrate_H(plan, v, prec, 0, st)
+        torch.cuda.synchronize()
+        hot, tot = plan.split_stats()
+        # chunks whose bound is exactly zero (every W product is zero) stay on FP32
+        assert tot > 0 and hot > 0.9 * tot
+        assert torch.equal(st, ref), prec
+    cold = q.Plan(wl, split_threshold=1e300)
+    st = q.new_store(cold)
+    q.q4c_integrate_H(cold, v, q.PREC_F32, 0, st)
+    torch.cuda.synchronize()
+    hot, tot = cold.split_stats()
+    assert hot == 0 and tot > 0
+    assert torch.equal(st[0], ref[0])
+    print("no chunk on FP64: max |W - W_f64| = %.3g Ha" % float(torch.max(torch.abs(st[1:] - ref[1:]))), flush=True)
+
+
+def test_split_rejects_batches_over_1024_points(q, small):
+    torch = _torch()
+    wl = small[0]
+    plan = q.Plan(wl, p_max=2048)
+    if plan.info["max_batch_points"] <= 1024:
+        pytest.skip("workload too small for a batch above 1024 points")
+    v = torch.from_numpy(wl.v).cuda()
+    st = q.new_store(plan)
+    with pytest.raises(q.Q4CError) as e:
+        q.q4c_integrate_H(plan, v, q.PREC_F32, 0, st)
+    assert e.value.status == q.Q4C_EUNSUPPORTED
+    q.q4c_integrate_H(plan, v, q.PREC_F64, 0, st)  # FP64 has no such limit

@@ -241,7 +241,7 @@ enum {
   Q4C_TIMER_CONTRACT = 1,
   Q4C_TIMER_REDUCE = 2,
   Q4C_TIMER_SPINOR = 3,
-  Q4C_TIMER_BROADCAST = 4,
+  Q4C_TIMER_BROADCAST = 4,   /* reserved (no kernel of this kind runs) */
   Q4C_TIMER_DENSITY_TILES = 5,
   Q4C_TIMER_DENSITY_POINTS = 6,
   Q4C_TIMER_OTHER = 7,

@@ -51,6 +51,10 @@ struct DevPlan {
   const int32_t *pair_na, *pair_nb; // [n_pairs]
   const int32_t *pair_a, *pair_b;   // [n_pairs]
   const int64_t *batch_work_off;    // [n_batches + 1] first work item of each batch
+  // per batch, for slot pairs si <= sj (upper triangle, row-major): the stored
+  // pair of the two atoms, or -1; batch b's table starts at batch_sp_off[b]
+  const int32_t *sp_pair;
+  const int64_t *batch_sp_off;      // [n_batches + 1]
   const int64_t *tab_off;           // [n_batches + 1] prefix of P_b n_b (nao_tabulate layout)
   const int64_t *panel_off;         // [n_batches] pass-relative offset of the batch's operand panel
   int64_t store_len;
@@ -71,7 +75,6 @@ struct Pass {
   int64_t b0, b1;        // batch range
   int64_t w0, w1;        // work range
   int64_t r0, r1;        // reduction-entry range
-  int64_t z0, z1;        // zero-block range (non-pair slot combinations)
   int64_t t0, t1;        // panel-tile range
   int64_t staging_len;   // doubles
   int64_t partial_len;   // doubles (adjoint partials, stored after the staging)
@@ -133,10 +136,11 @@ struct q4c_plan {
   std::vector<int64_t> red_inc_off;  // [n_red + 1]
   std::vector<int64_t> inc_src;      // staging offsets (pass relative)
   std::vector<int32_t> untouched_pairs;
-  std::vector<int64_t> zero_off, zero_len;  // staged blocks of slot combinations that are not stored pairs
   std::vector<int64_t> batch_work_off, tab_off, panel_off;
   std::vector<q4c::WorkItem> ptile;  // (batch, function tile) list of the panel kernel
   std::vector<int32_t> work_order;   // per pass, pass-relative work indices by decreasing cost
+  std::vector<int32_t> sp_pair;      // see DevPlan::sp_pair
+  std::vector<int64_t> batch_sp_off;
   int64_t max_scratch = 0;
   int64_t max_batch_points = 0, max_batch_fn = 0, fn_entries = 0;
   double flops_alg = 0.0;
@@ -153,7 +157,6 @@ struct q4c_plan {
   int64_t *d_red_inc_off = nullptr;
   int64_t *d_inc_src = nullptr;
   int32_t *d_untouched = nullptr;
-  int64_t *d_zero_off = nullptr, *d_zero_len = nullptr;
   q4c::WorkItem *d_ptile = nullptr;
   double *d_om = nullptr;  // [n_active + 16] point weights w_g v_g of the current call
   unsigned long long *d_chunks = nullptr;  // [64][2]: FP64-routed and total chunks of the last split call

@@ -19,13 +19,11 @@
 //  k_reduce          deterministic batch-to-global sum: every stored atom
 //                    pair adds its staged blocks in batch order (FP64).
 //  k_spinor          2x2-spinor assembly of the W and V blocks.
-//  k_broadcast,
 //  k_density_tiles,
 //  k_density_points  density_on_grid: the transpose of the steps above
-//                    (Eq. 39): coefficients are broadcast to the staged
-//                    layout, each half work item contracts a_g^T C b_g at its
-//                    points on MFMA, and every point sums its partials in a
-//                    fixed order.
+//                    (Eq. 39): each half work item reads its coefficients
+//                    from the store, contracts a_g^T C b_g at its points on
+//                    MFMA, and every point sums its partials in a fixed order.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -889,38 +887,6 @@ __global__ void k_spinor(DevPlan d, const double *store, double *spin_w, double 
 
 // Copy the coefficient blocks of every stored pair to each of its staged
 // (batch, pair) blocks: the transpose of k_reduce.
-// Adjoint broadcast: every staged incidence of pair red_pair[r] gets the
-// pair's coefficient block.  Threads cover (incidence, element) pairs, so
-// small blocks keep every thread busy; the incidence offsets go through LDS.
-__global__ __launch_bounds__(256) void k_broadcast(DevPlan d, int64_t r0, const int32_t *red_pair,
-                                                   const int64_t *red_inc_off, const int64_t *inc_src,
-                                                   const double *coef, double *staging) {
-  __shared__ int64_t s_src[256];
-  const int64_t r = r0 + blockIdx.x;
-  const int p = red_pair[r];
-  const int blk = d.pair_na[p] * d.pair_nb[p];
-  const int64_t k0 = red_inc_off[r], k1 = red_inc_off[r + 1];
-  const int64_t po = d.pair_off[p];
-  const int m = 5 * blk;
-  // elements per pass over the block and incidence groups sharing the 256 threads
-  const int span = m < 256 ? m : 256;
-  const int groups = 256 / span;
-  const int g = threadIdx.x / span, el = threadIdx.x - g * span;
-  for (int64_t kb = k0; kb < k1; kb += 256) {
-    const int nk = (int)(k1 - kb < 256 ? k1 - kb : 256);
-    __syncthreads();
-    if (threadIdx.x < nk) s_src[threadIdx.x] = inc_src[kb + threadIdx.x];
-    __syncthreads();
-    if (g >= groups) continue;
-    for (int e = el; e < m; e += span) {
-      const int q = e / blk;
-      const double c = coef[q * d.store_len + po + (e - q * blk)];
-      for (int k = g; k < nk; k += groups) staging[s_src[k] + e] = c;
-    }
-  }
-}
-
-
 constexpr int NTD = 256;       // adjoint workgroup: 4 waves = 2 column slices x 2 row halves of a half tile
 // adjoint LDS chunk images (layout of dma_chunk): row (q, u) of the 64 row
 // functions every RSA doubles, of the 32 column functions every RSB; both
@@ -938,14 +904,16 @@ constexpr int RSB = T + 2;
 template <bool PERSIST>
 __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t terms, const WorkItem *work,
                                                           const int32_t *order, int64_t w0, int64_t nw,
-                                                          const double *staging, const double *panel,
+                                                          const double *coef, const double *panel,
                                                           double *partial, unsigned *tickets) {
   __shared__ double sa[32 * RSA], sb[32 * RSB];
   __shared__ double s_red[4][16];
   __shared__ int64_t s_pos;
   // slot data of the tile's 64 rows and the half's 32 columns (slot -1: padding)
   __shared__ int s_rslot[T], s_rfn[T], s_rnf[T], s_cslot[T / 2], s_cfn[T / 2], s_cnf[T / 2];
-  __shared__ int64_t s_rrow[T];
+  // store offset of the pair block of (row slot, column slot) for the slots
+  // the tile spans (-1: lower atom-block triangle or not a stored pair)
+  __shared__ int64_t s_poff[T * T / 2];
   const int64_t npos = 2 * nw;
   int64_t pos = PERSIST ? next_item(tickets, npos, order != nullptr, &s_pos)
                         : (order ? (int64_t)blockIdx.x : xcd_map(blockIdx.x, npos));
@@ -990,7 +958,6 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t te
       s_rslot[tid] = si.slot;
       s_rfn[tid] = si.fnoff;
       s_rnf[tid] = si.nfn;
-      s_rrow[tid] = si.row_off;
     } else {
       s_cslot[tid - T] = si.slot;
       s_cfn[tid - T] = si.fnoff;
@@ -998,32 +965,53 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t te
     }
   }
   __syncthreads();  // slot tables visible
+  // slot ranges of the tile's rows and the half's columns (slots ascend with
+  // the functions; padding rows and columns carry slot -1)
+  const int rs0 = s_rslot[0], cs0 = s_cslot[0];
+  int rs1 = rs0, cs1 = cs0;
+  if (rs0 >= 0) rs1 = s_rslot[min(T, n - r0) - 1];
+  if (cs0 >= 0) cs1 = s_cslot[min(T / 2, n - c0) - 1];
+  const int nrs = rs0 >= 0 ? rs1 - rs0 + 1 : 0, ncs = cs0 >= 0 ? cs1 - cs0 + 1 : 0;
+  {
+    const int ns = d.batch_slot_off[b + 1] - sbase;
+    const int64_t spb = d.batch_sp_off[b];
+    for (int t = tid; t < nrs * ncs; t += NTD) {
+      const int si = rs0 + t / ncs, sj = cs0 + t % ncs;
+      int64_t po = -1;
+      if (si <= sj) {
+        // upper-triangle index of (si, sj)
+        const int q = d.sp_pair[spb + (int64_t)si * ns - (int64_t)si * (si - 1) / 2 + (sj - si)];
+        if (q >= 0) po = d.pair_off[q];
+      }
+      s_poff[t] = po;
+    }
+  }
+  __syncthreads();  // pair offsets visible
   // coefficient slice: rows i = r0 + iloc + 4 ks + lk (ks = 0..7), column lj,
-  // from the staged (batch, atom pair) blocks: element (li, lj) of a block in
-  // the upper atom-block triangle, plus the mirrored element (lj, li) when
-  // the 16 x 16 block is strictly upper inside one atom block (no work item
-  // computes the mirrored block); c' on the W parts.  Slot combinations that
-  // are not stored pairs hold zeros (k_zero_blocks).  All loads of a thread
-  // are independent and issued together.
+  // read from the coefficient store: element (li, lj) of the pair block of
+  // its two atoms (upper atom-block triangle only), plus the mirrored element
+  // (lj, li) when the 16 x 16 block is strictly upper inside one atom block
+  // (no work item computes the mirrored block); c' on the W parts.  All
+  // loads of a thread are independent and issued together.
   double creg[5][8];
   {
+    const int64_t L = d.store_len;
     const int cl = 16 * js + l16;
     const int cslot = s_cslot[cl], cfn = s_cfn[cl], cnf = s_cnf[cl];
 #pragma unroll
     for (int ks = 0; ks < 8; ++ks) {
       const int rl = iloc + 4 * ks + lk;
       const int li = r0 + rl;
-      const int rslot = s_rslot[rl], rfn = s_rfn[rl], rnf = s_rnf[rl];
-      const bool live = act[ks >> 2] && rslot >= 0 && cslot >= 0 && rslot <= cslot;
+      const int rslot = s_rslot[rl], rfn = s_rfn[rl];
+      const int64_t po = (act[ks >> 2] && rslot >= 0 && cslot >= 0) ? s_poff[(rslot - rs0) * ncs + (cslot - cs0)] : -1;
+      const bool live = po >= 0;
       const bool mir = live && upper[ks >> 2] && rslot == cslot;
-      const int64_t blk = s_rrow[rl] + 5 * (int64_t)rnf * (cfn - rfn);
-      const int64_t pq = (int64_t)rnf * cnf;
-      const int64_t e = blk + (int64_t)(li - rfn) * cnf + (lj - cfn);
-      const int64_t em = blk + (int64_t)(lj - rfn) * cnf + (li - cfn);
+      const int64_t e = po + (int64_t)(li - rfn) * cnf + (lj - cfn);
+      const int64_t em = po + (int64_t)(lj - rfn) * cnf + (li - cfn);
 #pragma unroll
       for (int q = 0; q < 5; ++q) {
-        double c = live ? staging[e + q * pq] : 0.0;
-        if (mir) c += mirror_sign(q) * staging[em + q * pq];
+        double c = live ? coef[q * L + e] : 0.0;
+        if (mir) c += mirror_sign(q) * coef[q * L + em];
         creg[q][ks] = q == 0 ? c : d.cprime * c;
       }
     }
@@ -1130,12 +1118,6 @@ __global__ void k_density_points(DevPlan d, int64_t b0, const double *partial, i
 __global__ void k_fill(double *p, int64_t n, double v) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = v;
-}
-
-__global__ void k_zero_blocks(const int64_t *off, const int64_t *len, int64_t z0, double *staging) {
-  const int64_t z = z0 + blockIdx.x;
-  double *p = staging + off[z];
-  for (int64_t i = threadIdx.x; i < len[z]; i += blockDim.x) p[i] = 0.0;
 }
 
 // Coefficients from spinor blocks D_AB (see q4c_coef_from_spinor).
@@ -1303,28 +1285,12 @@ int launch_density(const q4c_plan *p, const double *coef, uint32_t terms, int we
   }
   for (size_t ip = 0; ip < p->passes.size(); ++ip) {
     const Pass &ps = p->passes[ip];
-    const int64_t nr = ps.r1 - ps.r0, nw = ps.w1 - ps.w0, nbt = ps.b1 - ps.b0, nz = ps.z1 - ps.z0, nt = ps.t1 - ps.t0;
+    const int64_t nw = ps.w1 - ps.w0, nbt = ps.b1 - ps.b0, nt = ps.t1 - ps.t0;
     unsigned *tickets = cfg.persistent > 0 ? tick0 + ip * kTicketsPerLaunch : nullptr;
     // two workgroup positions (column halves) per work item
     const unsigned grid = (unsigned)(cfg.persistent > 0 ? std::min<int64_t>(cfg.persistent, 2 * nw) : 2 * nw);
     double *partial = p->d_staging + ps.staging_len;
     double *panel = partial + ps.partial_len;
-    if (nz > 0) {
-      {
-        TimedLaunch tl_(p, Q4C_TIMER_OTHER, s);
-        hipLaunchKernelGGL(k_zero_blocks, dim3((unsigned)nz), dim3(256), 0, s, p->d_zero_off, p->d_zero_len, ps.z0,
-                           p->d_staging);
-      }
-      if ((rc = check_launch("k_zero_blocks")) != Q4C_OK) return rc;
-    }
-    if (nr > 0) {
-      {
-        TimedLaunch tl_(p, Q4C_TIMER_BROADCAST, s);
-        hipLaunchKernelGGL(k_broadcast, dim3((unsigned)nr), dim3(256), 0, s, p->dp, ps.r0, p->d_red_pair,
-                           p->d_red_inc_off, p->d_inc_src, coef, p->d_staging);
-      }
-      if ((rc = check_launch("k_broadcast")) != Q4C_OK) return rc;
-    }
     if (nt > 0) {
       {
         TimedLaunch tl_(p, Q4C_TIMER_TABULATE, s);
@@ -1337,10 +1303,10 @@ int launch_density(const q4c_plan *p, const double *coef, uint32_t terms, int we
         TimedLaunch tl_(p, Q4C_TIMER_DENSITY_TILES, s);
         if (tickets)
           hipLaunchKernelGGL(k_density_tiles<true>, dim3(grid), dim3(NTD), 0, s, p->dp, terms, p->d_work, order, ps.w0,
-                             nw, p->d_staging, panel, partial, tickets);
+                             nw, coef, panel, partial, tickets);
         else
           hipLaunchKernelGGL(k_density_tiles<false>, dim3(grid), dim3(NTD), 0, s, p->dp, terms, p->d_work, order,
-                             ps.w0, nw, p->d_staging, panel, partial, tickets);
+                             ps.w0, nw, coef, panel, partial, tickets);
       }
       if ((rc = check_launch("k_density_tiles")) != Q4C_OK) return rc;
     }

@@ -391,9 +391,10 @@ int build_host(q4c_plan *p, const q4c_basis *b, const q4c_grid *g, const std::ve
   // per-batch relevant atoms (slots), local functions, staging layout, work, passes
   p->batch_fn_off.assign(1, 0);
   p->batch_slot_off.assign(1, 0);
+  p->batch_sp_off.assign(1, 0);
   const int T = q4c::kTile;
   int64_t staging = 0, partial = 0, panel = 0;
-  q4c::Pass cur{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  q4c::Pass cur{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   std::vector<std::pair<int32_t, int64_t>> pass_inc;  // (pair, staging offset) for the current pass
   std::vector<uint8_t> pair_seen(p->n_pairs, 0);
   const int64_t budget_doubles = std::max<int64_t>(p->staging_budget / 8, 1);
@@ -421,7 +422,6 @@ int build_host(q4c_plan *p, const q4c_basis *b, const q4c_grid *g, const std::ve
       p->inc_src.push_back(pass_inc[i].second);
     }
     cur.r1 = (int64_t)p->red_pair.size();
-    cur.z1 = (int64_t)p->zero_off.size();
     cur.t1 = (int64_t)p->ptile.size();
     p->passes.push_back(cur);
     p->max_scratch = std::max(p->max_scratch, staging + partial + panel);
@@ -429,8 +429,8 @@ int build_host(q4c_plan *p, const q4c_basis *b, const q4c_grid *g, const std::ve
     staging = 0;
     partial = 0;
     panel = 0;
-    int64_t nz = (int64_t)p->zero_off.size(), nt_ = (int64_t)p->ptile.size();
-    cur = q4c::Pass{b_end, b_end, (int64_t)p->work.size(), (int64_t)p->work.size(), 0, 0, nz, nz, nt_, nt_, 0, 0, 0};
+    int64_t nt_ = (int64_t)p->ptile.size();
+    cur = q4c::Pass{b_end, b_end, (int64_t)p->work.size(), (int64_t)p->work.size(), 0, 0, nt_, nt_, 0, 0, 0};
   };
 
   std::vector<int32_t> rel;
@@ -489,6 +489,13 @@ int build_host(q4c_plan *p, const q4c_basis *b, const q4c_grid *g, const std::ve
     p->panel_off.push_back(panel);
     panel += bpanel;
     for (int t = 0; t < nt; ++t) p->ptile.push_back(q4c::WorkItem{(int32_t)bt, (int16_t)t, (int16_t)t});
+    // slot-pair -> stored pair table (upper triangle)
+    {
+      const int ns = (int)rel.size();
+      for (int si = 0; si < ns; ++si)
+        for (int sj = si; sj < ns; ++sj) p->sp_pair.push_back((int32_t)pair_index(rel[si], rel[sj]));
+      p->batch_sp_off.push_back((int64_t)p->sp_pair.size());
+    }
     // slots
     int off = 0;
     int32_t slot0 = (int32_t)p->slot_atom.size();
@@ -509,12 +516,7 @@ int build_host(q4c_plan *p, const q4c_basis *b, const q4c_grid *g, const std::ve
         int c = rel[sj];
         int nfc = p->atom_fn_off[c + 1] - p->atom_fn_off[c];
         int64_t q = pair_index(a, c);
-        if (q >= 0) {
-          pass_inc.push_back({(int32_t)q, staging + 5 * (int64_t)nf * col_off});
-        } else {
-          p->zero_off.push_back(staging + 5 * (int64_t)nf * col_off);
-          p->zero_len.push_back(5 * (int64_t)nf * nfc);
-        }
+        if (q >= 0) pass_inc.push_back({(int32_t)q, staging + 5 * (int64_t)nf * col_off});
         col_off += nfc;
       }
       staging += 5 * (int64_t)nf * (nb_fn - off);
@@ -616,8 +618,6 @@ int build_device(q4c_plan *p) {
   UP(p->tab_off, toff);
   UP(p->panel_off, pnoff);
   UP(p->ptile, p->d_ptile);
-  UP(p->zero_off, p->d_zero_off);
-  UP(p->zero_len, p->d_zero_len);
   UP(p->work, p->d_work);
   UP(p->red_pair, p->d_red_pair);
   UP(p->red_first, p->d_red_first);
@@ -625,6 +625,14 @@ int build_device(q4c_plan *p) {
   UP(p->inc_src, p->d_inc_src);
   UP(p->untouched_pairs, p->d_untouched);
   UP(p->work_order, p->d_order);
+  {
+    int32_t *spp;
+    int64_t *spo;
+    UP(p->sp_pair, spp);
+    UP(p->batch_sp_off, spo);
+    p->dp.sp_pair = spp;
+    p->dp.batch_sp_off = spo;
+  }
 #undef UP
   rc = device_alloc(p, (size_t)p->max_scratch * sizeof(double), (void **)&p->d_staging);
   if (rc != Q4C_OK) return rc;

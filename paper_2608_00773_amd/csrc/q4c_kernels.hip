@@ -532,41 +532,58 @@ __global__ __launch_bounds__(NT, 2) void k_contract(DevPlan d, const WorkItem *w
   const int64_t plane = (int64_t)Pp * np;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  // wave sub-tile origin within the tile: a 2 x 2 grid of 32 x 32 sub-tiles.
-  // A diagonal tile computes only the 10 blocks on or above its block
-  // diagonal: the lower-left wave would idle and the upper-right one carry 4
-  // blocks, so there the upper-right blocks (rows 0-15 and 16-31, columns
-  // 32-63) go one row each to waves 1 and 2 (at most 3 blocks per wave).
-  int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-  const bool split_ur = diag && (wave == 1 || wave == 2);
-  if (diag && wave == 2) {
-    wr = 16;
-    wc = 32;
-  }
+  // The tile's active 16 x 16 blocks (inside n, on or above the diagonal),
+  // listed 2 x 2 square by square; wave w takes list entries
+  // [w nb / 4, (w+1) nb / 4): at most one block more than another wave, and
+  // a full tile gives every wave one 2 x 2 square.  Slot s of the wave holds
+  // block (brow[s], bcol[s]) (tile-local offsets) when act[s].
+  (void)diag;
   const int li16 = lane & 15, lk = lane >> 4;
-  bool act[2][2];
+  int nb = 0;
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int k = 0; k < 16; ++k) {
+    const int R = 2 * (k >> 3) + ((k >> 1) & 1), C = 2 * ((k >> 2) & 1) + (k & 1);
+    nb += block_active(r0 + 16 * R, c0 + 16 * C, n) ? 1 : 0;
+  }
+  const int kb0 = wave * nb / 4, kb1 = (wave + 1) * nb / 4;
+  int brow[4], bcol[4];
+  bool act[4];
 #pragma unroll
-    for (int y = 0; y < 2; ++y)
-      act[x][y] = block_active(r0 + wr + 16 * x, c0 + wc + 16 * y, n) && !(split_ur && x == 1);
+  for (int sl = 0; sl < 4; ++sl) {
+    brow[sl] = 0;
+    bcol[sl] = 0;
+    act[sl] = false;
+  }
+  {
+    int cnt = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int R = 2 * (k >> 3) + ((k >> 1) & 1), C = 2 * ((k >> 2) & 1) + (k & 1);
+      if (block_active(r0 + 16 * R, c0 + 16 * C, n)) {
+#pragma unroll
+        for (int sl = 0; sl < 4; ++sl)
+          if (cnt == kb0 + sl && cnt < kb1) {
+            brow[sl] = 16 * R;
+            bcol[sl] = 16 * C;
+            act[sl] = true;
+          }
+        ++cnt;
+      }
+    }
+  }
 
-  dbl4 acc[2][2][5];
+  dbl4 acc[4][5];
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int sl = 0; sl < 4; ++sl)
 #pragma unroll
-    for (int y = 0; y < 2; ++y)
-#pragma unroll
-      for (int q = 0; q < 5; ++q) acc[x][y][q] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int q = 0; q < 5; ++q) acc[sl][q] = dbl4{0.0, 0.0, 0.0, 0.0};
   // FP32 accumulators of the four W parts (split modes)
-  flt4 accf[2][2][4];
+  flt4 accf[4][4];
   if (SPLIT) {
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+    for (int sl = 0; sl < 4; ++sl)
 #pragma unroll
-      for (int y = 0; y < 2; ++y)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) accf[x][y][q] = flt4{0.f, 0.f, 0.f, 0.f};
+      for (int q = 0; q < 4; ++q) accf[sl][q] = flt4{0.f, 0.f, 0.f, 0.f};
   }
 
   const double cp = d.cprime;
@@ -638,122 +655,109 @@ __global__ __launch_bounds__(NT, 2) void k_contract(DevPlan d, const WorkItem *w
       // operand takes its weight w v there (the weighting of Eq. 29)
       const int rowk = 2 * ks + (lk >> 1), ck = lk & 1;
       const double omk = DB ? omv[ks] : s_om[4 * ks + lk];
-      double a[2][4], bb[2][4];
 #pragma unroll
-      for (int x = 0; x < 2; ++x)
+      for (int sl = 0; sl < 4; ++sl) {
+        if (!act[sl]) continue;  // wave-uniform
+        double av[4], bv[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) a[x][q] = ca[(q * RPQ + rowk) * DROW + 2 * (wr + 16 * x + li16) + ck];
-#pragma unroll
-      for (int y = 0; y < 2; ++y)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) bb[y][q] = cb[(q * RPQ + rowk) * DROW + 2 * (wc + 16 * y + li16) + ck] * omk;
-      // FP32 operands of the gradient components (split modes, chunks not deferred)
-      float a32[2][4], b32[2][4], a32l[2][4], b32l[2][4];
-      if (SPLIT && !hot) {
-#pragma unroll
-        for (int x = 0; x < 2; ++x)
+        for (int q = 0; q < 4; ++q) {
+          av[q] = ca[(q * RPQ + rowk) * DROW + 2 * (brow[sl] + li16) + ck];
+          bv[q] = cb[(q * RPQ + rowk) * DROW + 2 * (bcol[sl] + li16) + ck] * omk;
+        }
+        if (!HOTK) acc[sl][0] = mfma64(av[0], bv[0], acc[sl][0]);
+        if (MODE == MODE_F64 || HOTK) {
+          acc[sl][1] = mfma64(av[1], bv[1], acc[sl][1]);
+          acc[sl][2] = mfma64(av[2], bv[3], acc[sl][2]);
+          acc[sl][3] = mfma64(av[3], bv[1], acc[sl][3]);
+          acc[sl][4] = mfma64(av[1], bv[2], acc[sl][4]);
+          acc[sl][1] = mfma64(av[2], bv[2], acc[sl][1]);
+          acc[sl][2] = mfma64(-av[3], bv[2], acc[sl][2]);
+          acc[sl][3] = mfma64(-av[1], bv[3], acc[sl][3]);
+          acc[sl][4] = mfma64(-av[2], bv[1], acc[sl][4]);
+          acc[sl][1] = mfma64(av[3], bv[3], acc[sl][1]);
+        } else if (hot) {
+          // deferred to MODE_HOT
+        } else if (MODE == MODE_F32) {
+          float af[4], bf[4];
 #pragma unroll
           for (int q = 1; q < 4; ++q) {
-            a32[x][q] = (float)a[x][q];
-            b32[x][q] = (float)bb[x][q];
-            if (MODE == MODE_SPLIT) {
-              a32l[x][q] = (float)(a[x][q] - (double)a32[x][q]);
-              b32l[x][q] = (float)(bb[x][q] - (double)b32[x][q]);
-            }
+            af[q] = (float)av[q];
+            bf[q] = (float)bv[q];
           }
-      }
+          accf[sl][0] = mfma32(af[1], bf[1], accf[sl][0]);
+          accf[sl][1] = mfma32(af[2], bf[3], accf[sl][1]);
+          accf[sl][2] = mfma32(af[3], bf[1], accf[sl][2]);
+          accf[sl][3] = mfma32(af[1], bf[2], accf[sl][3]);
+          accf[sl][0] = mfma32(af[2], bf[2], accf[sl][0]);
+          accf[sl][1] = mfma32(-af[3], bf[2], accf[sl][1]);
+          accf[sl][2] = mfma32(-af[1], bf[3], accf[sl][2]);
+          accf[sl][3] = mfma32(-af[2], bf[1], accf[sl][3]);
+          accf[sl][0] = mfma32(af[3], bf[3], accf[sl][0]);
+        } else if (MODE == MODE_SPLIT) {
+          // hi + lo split: x = hi + lo with hi = fl(x), lo = fl(x - hi);
+          // x y ~ hi_x hi_y + hi_x lo_y + lo_x hi_y (lo_x lo_y dropped)
+          float ah[4], al[4], bh[4], bl[4];
 #pragma unroll
-      for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int y = 0; y < 2; ++y) {
-          if (!act[x][y]) continue;  // wave-uniform
-          const double *av = a[x];
-          const double *bv = bb[y];
-          if (!HOTK) acc[x][y][0] = mfma64(av[0], bv[0], acc[x][y][0]);
-          if (MODE == MODE_F64 || HOTK) {
-            acc[x][y][1] = mfma64(av[1], bv[1], acc[x][y][1]);
-            acc[x][y][2] = mfma64(av[2], bv[3], acc[x][y][2]);
-            acc[x][y][3] = mfma64(av[3], bv[1], acc[x][y][3]);
-            acc[x][y][4] = mfma64(av[1], bv[2], acc[x][y][4]);
-            acc[x][y][1] = mfma64(av[2], bv[2], acc[x][y][1]);
-            acc[x][y][2] = mfma64(-av[3], bv[2], acc[x][y][2]);
-            acc[x][y][3] = mfma64(-av[1], bv[3], acc[x][y][3]);
-            acc[x][y][4] = mfma64(-av[2], bv[1], acc[x][y][4]);
-            acc[x][y][1] = mfma64(av[3], bv[3], acc[x][y][1]);
-          } else if (hot) {
-            // deferred to MODE_HOT
-          } else if (MODE == MODE_F32) {
-            const float *af = a32[x], *bf = b32[y];
-            accf[x][y][0] = mfma32(af[1], bf[1], accf[x][y][0]);
-            accf[x][y][1] = mfma32(af[2], bf[3], accf[x][y][1]);
-            accf[x][y][2] = mfma32(af[3], bf[1], accf[x][y][2]);
-            accf[x][y][3] = mfma32(af[1], bf[2], accf[x][y][3]);
-            accf[x][y][0] = mfma32(af[2], bf[2], accf[x][y][0]);
-            accf[x][y][1] = mfma32(-af[3], bf[2], accf[x][y][1]);
-            accf[x][y][2] = mfma32(-af[1], bf[3], accf[x][y][2]);
-            accf[x][y][3] = mfma32(-af[2], bf[1], accf[x][y][3]);
-            accf[x][y][0] = mfma32(af[3], bf[3], accf[x][y][0]);
-          } else if (MODE == MODE_SPLIT) {
-            // hi + lo split: x = hi + lo with hi = fl(x), lo = fl(x - hi);
-            // x y ~ hi_x hi_y + hi_x lo_y + lo_x hi_y (lo_x lo_y dropped)
-            const float *ah = a32[x], *bh = b32[y], *al = a32l[x], *bl = b32l[y];
+          for (int q = 1; q < 4; ++q) {
+            ah[q] = (float)av[q];
+            al[q] = (float)(av[q] - (double)ah[q]);
+            bh[q] = (float)bv[q];
+            bl[q] = (float)(bv[q] - (double)bh[q]);
+          }
 #define SPLIT3(ACC, AI, BI, SG)                                  \
   ACC = mfma32(SG ah[AI], bh[BI], ACC);                          \
   ACC = mfma32(SG ah[AI], bl[BI], ACC);                          \
   ACC = mfma32(SG al[AI], bh[BI], ACC);
-            SPLIT3(accf[x][y][0], 1, 1, +)
-            SPLIT3(accf[x][y][0], 2, 2, +)
-            SPLIT3(accf[x][y][0], 3, 3, +)
-            SPLIT3(accf[x][y][1], 2, 3, +)
-            SPLIT3(accf[x][y][1], 3, 2, -)
-            SPLIT3(accf[x][y][2], 3, 1, +)
-            SPLIT3(accf[x][y][2], 1, 3, -)
-            SPLIT3(accf[x][y][3], 1, 2, +)
-            SPLIT3(accf[x][y][3], 2, 1, -)
+          SPLIT3(accf[sl][0], 1, 1, +)
+          SPLIT3(accf[sl][0], 2, 2, +)
+          SPLIT3(accf[sl][0], 3, 3, +)
+          SPLIT3(accf[sl][1], 2, 3, +)
+          SPLIT3(accf[sl][1], 3, 2, -)
+          SPLIT3(accf[sl][2], 3, 1, +)
+          SPLIT3(accf[sl][2], 1, 3, -)
+          SPLIT3(accf[sl][3], 1, 2, +)
+          SPLIT3(accf[sl][3], 2, 1, -)
 #undef SPLIT3
-          }
         }
+      }
     }
   }
   // write the computed blocks to the staged atom-pair blocks
 #pragma unroll
-  for (int y = 0; y < 2; ++y) {
-    const int cb = c0 + wc + y * 16;
+  for (int sl = 0; sl < 4; ++sl) {
+    if (!act[sl]) continue;
+    const int cb = c0 + bcol[sl];
     const int lj = cb + li16;
     if (lj >= n) continue;
     const SlotInfo sj = slot_of(d, f0, sbase, lj);
+    const int rb = r0 + brow[sl];
+    const bool upper = rb < cb;
 #pragma unroll
-    for (int x = 0; x < 2; ++x) {
-      if (!act[x][y]) continue;
-      const int rb = r0 + wr + x * 16;
-      const bool upper = rb < cb;
+    for (int r = 0; r < 4; ++r) {
+      // V and, in FP64 modes, the W parts: FP64 MFMA rows lk + 4 r
+      const int li = rb + d_row_f64(lk, r);
+      if (li < n && !(HOTK && hmask_in == 0)) {
+        const SlotInfo si = slot_of(d, f0, sbase, li);
+        double vals[5];
+        vals[0] = acc[sl][0][r];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        // V and, in FP64 modes, the W parts: FP64 MFMA rows lk + 4 r
-        const int li = rb + d_row_f64(lk, r);
-        if (li < n && !(HOTK && hmask_in == 0)) {
-          const SlotInfo si = slot_of(d, f0, sbase, li);
-          double vals[5];
-          vals[0] = acc[x][y][0][r];
+        for (int q = 1; q < 5; ++q) vals[q] = cp * acc[sl][q][r];
+        if (MODE == MODE_F64)
+          stage_store<0, 5>(staging, si, sj, li, lj, upper, vals);
+        else if (HOTK)
+          stage_add<1, 5>(staging, si, sj, li, lj, upper, vals + 1);
+        else
+          stage_store<0, 1>(staging, si, sj, li, lj, upper, vals);
+      }
+      if (SPLIT) {
+        // the W parts from the FP32 accumulators: FP32 MFMA rows 4 lk + r
+        const int lf = rb + d_row_f32(lk, r);
+        if (lf < n) {
+          const SlotInfo sf = slot_of(d, f0, sbase, lf);
+          double w[4];
 #pragma unroll
-          for (int q = 1; q < 5; ++q) vals[q] = cp * acc[x][y][q][r];
-          if (MODE == MODE_F64)
-            stage_store<0, 5>(staging, si, sj, li, lj, upper, vals);
-          else if (HOTK)
-            stage_add<1, 5>(staging, si, sj, li, lj, upper, vals + 1);
-          else
-            stage_store<0, 1>(staging, si, sj, li, lj, upper, vals);
-        }
-        if (SPLIT) {
-          // the W parts from the FP32 accumulators: FP32 MFMA rows 4 lk + r
-          const int lf = rb + d_row_f32(lk, r);
-          if (lf < n) {
-            const SlotInfo sf = slot_of(d, f0, sbase, lf);
-            double w[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) w[q] = cp * (double)accf[x][y][q][r];
-            stage_store<1, 5>(staging, sf, sj, lf, lj, upper, w);
-          }
+          for (int q = 0; q < 4; ++q) w[q] = cp * (double)accf[sl][q][r];
+          stage_store<1, 5>(staging, sf, sj, lf, lj, upper, w);
         }
       }
     }

@@ -911,7 +911,7 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t te
                                                           const double *coef, const double *panel,
                                                           double *partial, unsigned *tickets) {
   __shared__ double sa[32 * RSA], sb[32 * RSB];
-  __shared__ double s_red[4][16];
+  __shared__ double s_red[2][4][16];  // per-wave point sums, alternating chunks
   __shared__ int64_t s_pos;
   // slot data of the tile's 64 rows and the half's 32 columns (slot -1: padding)
   __shared__ int s_rslot[T], s_rfn[T], s_rnf[T], s_cslot[T / 2], s_cfn[T / 2], s_cnf[T / 2];
@@ -1025,7 +1025,11 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t te
   const int jloc = 16 * js;  // half-local first column of this wave
 
   for (int k0 = 0; k0 < Pp; k0 += 16) {
-    __syncthreads();  // previous chunk's images and per-wave sums consumed
+    const int rb2 = (k0 >> 4) & 1;
+    __syncthreads();  // previous chunk's images consumed, its per-wave sums visible
+    if (k0 > 0 && tid < 16 && k0 - 16 + tid < P)
+      out[k0 - 16 + tid] = (s_red[rb2 ^ 1][0][tid] + s_red[rb2 ^ 1][1][tid]) +
+                           (s_red[rb2 ^ 1][2][tid] + s_red[rb2 ^ 1][3][tid]);
     dma_chunk<NTD, 16, T, RSA>(pb, plane, np, r0, k0 >> 2, sa);
     dma_chunk<NTD, 16, T / 2, RSB>(pb, plane, np, c0, k0 >> 2, sb);
     __builtin_amdgcn_s_waitcnt(0);  // this thread's LDS DMA loads have landed
@@ -1094,9 +1098,13 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t te
     double sx = (xacc[0] + xacc[1]) + (xacc[2] + xacc[3]);
     sx += __shfl_xor(sx, 16);
     sx += __shfl_xor(sx, 32);
-    if (lane < 16) s_red[wave][l16] = sx;
-    __syncthreads();  // per-wave sums of this chunk
-    if (tid < 16 && k0 + tid < P) out[k0 + tid] = (s_red[0][tid] + s_red[1][tid]) + (s_red[2][tid] + s_red[3][tid]);
+    if (lane < 16) s_red[rb2][wave][l16] = sx;
+  }
+  __syncthreads();  // the last chunk's per-wave sums
+  {
+    const int k0 = Pp - 16, rb2 = (k0 >> 4) & 1;
+    if (tid < 16 && k0 + tid < P)
+      out[k0 + tid] = (s_red[rb2][0][tid] + s_red[rb2][1][tid]) + (s_red[rb2][2][tid] + s_red[rb2][3][tid]);
   }
   if (!PERSIST) break;
   pos = next_item(tickets, npos, order != nullptr, &s_pos);

@@ -27,6 +27,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "q4c_internal.h"
 
@@ -531,7 +532,8 @@ __global__ __launch_bounds__(NT, 2) void k_contract(DevPlan d, const WorkItem *w
   const double *pb = panel + d.panel_off[b];
   const int64_t plane = (int64_t)Pp * np;
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
+  // wave index as a scalar: conditions derived from it stay uniform
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   // The tile's active 16 x 16 blocks (inside n, on or above the diagonal),
   // listed 2 x 2 square by square; wave w takes list entries
   // [w nb / 4, (w+1) nb / 4): at most one block more than another wave, and
@@ -644,7 +646,8 @@ __global__ __launch_bounds__(NT, 2) void k_contract(DevPlan d, const WorkItem *w
         va = fmax(va, __shfl_xor(va, off));
         vb = fmax(vb, __shfl_xor(vb, off));
       }
-      hot = kU32 * cp * 48.0 * va * vb > tau;
+      // equal in every lane after the reductions; as a scalar the branches stay uniform
+      hot = __builtin_amdgcn_readfirstlane(kU32 * cp * 48.0 * va * vb > tau ? 1 : 0) != 0;
       n_hot += hot ? 1 : 0;
       n_all += 1;
       if (hot) hmask |= (uint64_t)1 << (k0 >> 4);
@@ -934,7 +937,8 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t te
   const double *pb = panel + d.panel_off[b];
   const int64_t plane = (int64_t)Pp * np;
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
+  // wave index as a scalar: conditions derived from it stay uniform
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int js = wave & 1, ih = wave >> 1;  // column slice, row half
   const int l16 = lane & 15, lk = lane >> 4;
   const int cb = c0 + 16 * js;  // column block of this wave
@@ -1047,6 +1051,55 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t te
 #pragma unroll
         for (int r = 0; r < 4; ++r)
           zt[q][r] = sb[(q * 8 + (l16 >> 1)) * RSB + 2 * (jloc + d_row_f64(lk, r)) + (l16 & 1)];
+      // All terms over the K steps [K0, K1) of active row blocks, as straight-line
+      // code: no branch between the MFMAs of a chain.  Terms grouped by the row
+      // component Y (points x functions):
+      //   Y=phi: (V, phi); Y=dx: (Ws, dx), (Wso_y, -dz), (Wso_z, +dy);
+      //   Y=dy: (Ws, dy), (Wso_x, +dz), (Wso_z, -dx); Y=dz: (Ws, dz), (Wso_x, -dy), (Wso_y, +dx)
+      auto all_terms = [&](auto k0c, auto k1c) {
+        constexpr int K0 = decltype(k0c)::value, K1 = decltype(k1c)::value;
+#pragma unroll
+        for (int yq = 0; yq < 4; ++yq) {
+          double ya[8];
+#pragma unroll
+          for (int ks = K0; ks < K1; ++ks)
+            ya[ks] = sa[(yq * 8 + (l16 >> 1)) * RSA + 2 * (iloc + 4 * ks + lk) + (l16 & 1)];
+          if (yq == 0) {
+            dbl4 u0 = dbl4{0.0, 0.0, 0.0, 0.0}, u1 = u0;
+#pragma unroll
+            for (int ks = K0; ks < K1; ks += 2) {
+              u0 = mfma64(creg[0][ks], ya[ks], u0);
+              u1 = mfma64(creg[0][ks + 1], ya[ks + 1], u1);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) xacc[r] += (u0[r] + u1[r]) * zt[0][r];
+          } else {
+            const int c2 = yq == 1 ? 3 : 2, z2 = yq == 1 ? 3 : (yq == 2 ? 3 : 2);
+            const double g2 = yq == 2 ? 1.0 : -1.0;
+            const int c3 = yq == 3 ? 3 : 4, z3 = yq == 1 ? 2 : 1;
+            const double g3 = yq == 2 ? -1.0 : 1.0;
+            dbl4 u1 = dbl4{0.0, 0.0, 0.0, 0.0}, u2 = u1, u3 = u1;
+#pragma unroll
+            for (int ks = K0; ks < K1; ++ks) {
+              u1 = mfma64(creg[1][ks], ya[ks], u1);
+              u2 = mfma64(creg[c2][ks], ya[ks], u2);
+              u3 = mfma64(creg[c3][ks], ya[ks], u3);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              xacc[r] += u1[r] * zt[yq][r] + g2 * u2[r] * zt[z2][r] + g3 * u3[r] * zt[z3][r];
+          }
+        }
+      };
+      if (terms == Q4C_TERM_ALL) {
+        if (act[0] && act[1])
+          all_terms(std::integral_constant<int, 0>{}, std::integral_constant<int, 8>{});
+        else if (act[0])
+          all_terms(std::integral_constant<int, 0>{}, std::integral_constant<int, 4>{});
+        else
+          all_terms(std::integral_constant<int, 4>{}, std::integral_constant<int, 8>{});
+      } else {
+      // selected terms (general path)
       // terms grouped by the row component Y (points x functions):
       //   Y=phi: (V, phi); Y=dx: (Ws, dx), (Wso_y, -dz), (Wso_z, +dy);
       //   Y=dy: (Ws, dy), (Wso_x, +dz), (Wso_z, -dx); Y=dz: (Ws, dz), (Wso_x, -dy), (Wso_y, +dx)
@@ -1092,6 +1145,7 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t te
 #pragma unroll
           for (int r = 0; r < 4; ++r) xacc[r] += u1[r] * zt[z1][r] + g2 * u2[r] * zt[z2][r] + g3 * u3[r] * zt[z3][r];
         }
+      }
       }
     }
     // sum over the wave's 16 columns: the 4 registers, then the 4 lane rows

@@ -598,7 +598,34 @@ __global__ __launch_bounds__(NT, 2) void k_contract(DevPlan d, const WorkItem *w
   constexpr int RPQ = CH / 2;              // LDS rows per component
   constexpr int BUFD = 4 * RPQ * DROW;     // doubles per chunk image
   bool hot = true;  // W parts of the current 16 points on FP64 MFMA
+  // Double-buffered path: the global loads a chunk needs besides its image
+  // (w v at its points; the split modes' bound inputs of its 16 points) are
+  // issued one chunk ahead, with the next image's DMA, so that nothing
+  // consumed between the barrier and the last MFMA of a chunk waits on
+  // loads still in flight.
+  double omn[CH / 4];  // w v at points 4 ks + lk of the next chunk
+  double ga = 0.0, gb = 0.0, gw = 0.0;  // bound inputs of the next 16 points
+  const double *gmx = pb + 4 * plane;  // per-point gradient maxima of the row tiles
+  auto load_om = [&](int k) {
+#pragma unroll
+    for (int ks = 0; ks < CH / 4; ++ks) {
+      const int pt = k + 4 * ks + lk;
+      omn[ks] = pt < P ? om[g0 + pt] : 0.0;
+    }
+  };
+  auto load_bound = [&](int k) {
+    // lanes 0..15: row tile maxima; lanes 16..31: column tile maxima and w v
+    ga = gb = gw = 0.0;
+    if (lane < 16) {
+      ga = gmx[(int64_t)it.ti * Pp + k + lane];
+    } else if (lane < 32 && k + lane - 16 < P) {
+      gb = gmx[(int64_t)it.tj * Pp + k + lane - 16];
+      gw = om[g0 + k + lane - 16];
+    }
+  };
   if (DB) {
+    load_om(0);
+    if (SPLIT) load_bound(0);
     dma_chunk<NT, CH>(pb, plane, np, r0, 0, sa);
     dma_chunk<NT, CH>(pb, plane, np, c0, 0, sb);
   }
@@ -606,6 +633,7 @@ __global__ __launch_bounds__(NT, 2) void k_contract(DevPlan d, const WorkItem *w
     if (HOTK && !((hmask_in >> (k0 >> 4)) & 1)) continue;  // WG-uniform
     const int bo = DB ? ((k0 / CH) & 1) * BUFD : 0;  // this chunk's buffer
     double omv[CH / 4];  // FP64 path: w v at points 4 ks + lk of this chunk
+    double va = 0.0, vb = 0.0;  // split modes: bound inputs of this lane
     if (!DB) {
       __syncthreads();  // previous chunk's operands consumed
       if (tid < 16) s_om[tid] = k0 + tid < P ? om[g0 + k0 + tid] : 0.0;
@@ -617,12 +645,15 @@ __global__ __launch_bounds__(NT, 2) void k_contract(DevPlan d, const WorkItem *w
       __builtin_amdgcn_s_waitcnt(0);  // this thread's loads of this chunk have landed
       __syncthreads();                // ... everyone's; the previous chunk is consumed
 #pragma unroll
-      for (int ks = 0; ks < CH / 4; ++ks) {
-        const int pt = k0 + 4 * ks + lk;
-        omv[ks] = pt < P ? om[g0 + pt] : 0.0;
+      for (int ks = 0; ks < CH / 4; ++ks) omv[ks] = omn[ks];
+      if (SPLIT && (k0 & 15) == 0) {
+        va = ga;
+        vb = gb * fabs(gw);
       }
       if (k0 + CH < Pp) {
         const int nbo = BUFD - bo;
+        load_om(k0 + CH);
+        if (SPLIT && ((k0 + CH) & 15) == 0) load_bound(k0 + CH);
         dma_chunk<NT, CH>(pb, plane, np, r0, (k0 + CH) >> 2, sa + nbo);
         dma_chunk<NT, CH>(pb, plane, np, c0, (k0 + CH) >> 2, sb + nbo);
       }
@@ -633,14 +664,6 @@ __global__ __launch_bounds__(NT, 2) void k_contract(DevPlan d, const WorkItem *w
       // of the row tile, B = largest |w v gradient component| of the column
       // tile, from the panel's per-point maxima; every wave forms the same
       // values, so the decision is uniform over the workgroup
-      const double *gmx = pb + 4 * plane;
-      double va = 0.0, vb = 0.0;
-      if (lane < 16) {
-        va = gmx[(int64_t)it.ti * Pp + k0 + lane];
-      } else if (lane < 32) {
-        const int pt = k0 + lane - 16;
-        vb = pt < P ? gmx[(int64_t)it.tj * Pp + pt] * fabs(om[g0 + pt]) : 0.0;
-      }
 #pragma unroll
       for (int off = 1; off < 64; off <<= 1) {
         va = fmax(va, __shfl_xor(va, off));

@@ -32,10 +32,13 @@ PREC = {"f64": 0, "split": 1, "f32": 2}
 # HBM bytes per k_contract launch on the default cluster workload, from two
 # rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE), each scaled by what the same
 # counter reads for an elementwise copy of 1 GiB (read x1.9999, write x1.0000).
-# Keyed by the SHA-256 of the kernel source the counters were taken on: any
-# change to the kernels makes the figure stale, and it is then reported as null.
+# Keyed by the SHA-256 of the kernel source the counters were taken on, the
+# precision, the atom count and the work order of the launch (batch order keeps
+# a batch's tiles on one L2, the cost-sorted queue does not): any change to the
+# kernels makes the figure stale, and it is then reported as null.
 TRAFFIC = {
-    ("c19ad13a15ae715720e4aac50f9b40d47e7c19eeba431f6f41cd292971300516", "f64", 120): 8.489e9 + 4.258e9,
+    ("1b64df8139b86ae9ff35be6f962f72eabe94ecd77ea0d49ebdd82d2f7918a86b", "f64", 120, 0): 11.039e9 + 3.981e9,
+    ("1b64df8139b86ae9ff35be6f962f72eabe94ecd77ea0d49ebdd82d2f7918a86b", "f64", 120, 1): 20.092e9 + 4.355e9,
 }
 
 
@@ -58,6 +61,9 @@ def parse():
     ap.add_argument("--workload", choices=["cluster", "slab", "pepi", "molecules"], default="cluster",
                     help="molecules: 64 independent molecules (8..80 atoms), one batched plan (autotuned launch "
                          "shapes, HIP graph replay) against 64 sequential per-molecule plans; prints its own line")
+    ap.add_argument("--contract-order", type=int, choices=[0, 1], default=None,
+                    help="after autotuning, keep the contraction's work order fixed (0: batch order, "
+                         "1: cost-sorted global queue) with the best persistent size timed for it")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before the work, run one elementwise copy of this many MiB (read once, written once): "
                          "the reference dispatch for scaling HBM byte counters")
@@ -259,6 +265,10 @@ def main():
         # every later call is one HIP graph launch
         t0 = time.perf_counter()
         tune = plan.autotune(v, store, prec, gbar, grad, reps=3)
+        if a.contract_order is not None:
+            rows = [t for t in tune if t[0] == q.KERNEL_CONTRACT and t[1] == a.contract_order]
+            best = min(rows, key=lambda t: t[3])
+            plan.set_launch(q.KERNEL_CONTRACT, best[1], best[2])
         plan.set_graphs(not a.no_graphs)
         print("[bench] autotune %.1f s: %s" % (time.perf_counter() - t0, tune), file=sys.stderr, flush=True)
 
@@ -334,7 +344,8 @@ def main():
     import hashlib
     with open(os.path.join(ROOT, "paper_2608_00773_amd", "csrc", "q4c_kernels.hip"), "rb") as fh:
         ksha = hashlib.sha256(fh.read()).hexdigest()
-    traffic = TRAFFIC.get((ksha, a.precision, a.n_atoms)) if a.workload == "cluster" else None
+    c_order = plan.get_launch(q.KERNEL_CONTRACT)[0]
+    traffic = TRAFFIC.get((ksha, a.precision, a.n_atoms, c_order)) if a.workload == "cluster" else None
 
     n_act = info["n_active"]
     res = {

@@ -1,7 +1,8 @@
 """ORACLE -- test infrastructure, not part of the library.
 
 A plain FP64 CPU statement of Q4C real-space grid integration (paper Sec. III A,
-Eq. 29/31), of its spinor assembly (Eq. 16a with the Eq. 8b kinetic balance at
+Eq. 29/31), of the paper's ket-dependent H and S integrand for one component
+(Sec. II, Eq. 19, symmetrised), of its spinor assembly (Eq. 16a with the Eq. 8b kinetic balance at
 V_A -> 0) and of the density / adjoint contraction (Eq. 39, Eq. 4).  Only the
 tests, the smoke check and the benchmark's CPU-baseline leg may import it; the
 library never does.  Shares no code with the HIP path: the C part
@@ -65,6 +66,8 @@ def _load():
         lib.orc_tabulate.argtypes = [bp, ctypes.c_int64, dp, dp, dp, dp, dp]
         lib.orc_pair_blocks.argtypes = [bp, ctypes.c_int64, dp, dp, dp, dp, dp, ctypes.c_double, ctypes.c_int,
                                         ip, ip, ctypes.c_int, dp, dp]
+        lib.orc_pair_blocks_hs.argtypes = [bp, ctypes.POINTER(ctypes.c_int64), dp, ctypes.c_int64, dp, dp, dp, dp,
+                                           dp, ctypes.c_int, ip, ip, ctypes.c_int, dp, dp]
         lib.orc_density_points.argtypes = [bp, ctypes.c_int64, dp, dp, dp, dp, ctypes.c_double, ctypes.c_int,
                                            ip, ip, dp, ctypes.c_int, dp, dp]
         _lib = lib
@@ -156,6 +159,39 @@ def pair_blocks(wl, pairs: np.ndarray, v: Optional[np.ndarray] = None, screened:
         res.append(out[o:o + s].reshape(5, int(nfn[a]), int(nfn[b])))
         if with_abs:
             ares.append(absout[o:o + s].reshape(5, int(nfn[a]), int(nfn[b])))
+        o += s
+    return (res, ares) if with_abs else res
+
+
+def pair_blocks_hs(wl, pairs: np.ndarray, v: Optional[np.ndarray] = None, screened: bool = True,
+                   with_abs: bool = False, u_coef: Optional[np.ndarray] = None,
+                   shell_u_off: Optional[np.ndarray] = None):
+    """H and S of one component per requested atom pair (Eq. 19 in the scalar
+    form of Eq. 29, symmetrised): H_ij = sum_g w phi_i phi_j (v + (u_i + u_j)/2),
+    S_ij = sum_g w phi_i phi_j, with the per-shell ket potential u = eps - V
+    tabulated like the radials (wl.u_coef at wl.shell_u_off, unless given).
+
+    Returns a list of float64[2, nA, nB] (and the error scales if with_abs)."""
+    lib = _load()
+    h = _BasisHandle(wl)
+    uc = _c(wl.u_coef if u_coef is None else u_coef, np.float64)
+    uo = _c(wl.shell_u_off if shell_u_off is None else shell_u_off, np.int64)
+    pairs = _c(pairs, np.int32).reshape(-1, 2)
+    pa, pb = _c(pairs[:, 0], np.int32), _c(pairs[:, 1], np.int32)
+    nfn = wl.atom_nfn()
+    sizes = [2 * int(nfn[a]) * int(nfn[b]) for a, b in pairs]
+    out = np.zeros(int(sum(sizes)))
+    absout = np.zeros_like(out) if with_abs else None
+    vv = _c(wl.v if v is None else v, np.float64)
+    x, y, z, w = (_c(t, np.float64) for t in (wl.x, wl.y, wl.z, wl.w))
+    lib.orc_pair_blocks_hs(h.ptr, uo.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dp(uc), x.size, _dp(x),
+                           _dp(y), _dp(z), _dp(w), _dp(vv), int(pairs.shape[0]), _ip(pa), _ip(pb),
+                           1 if screened else 0, _dp(out), _dp(absout) if with_abs else None)
+    res, ares, o = [], [], 0
+    for (a, b), s in zip(pairs, sizes):
+        res.append(out[o:o + s].reshape(2, int(nfn[a]), int(nfn[b])))
+        if with_abs:
+            ares.append(absout[o:o + s].reshape(2, int(nfn[a]), int(nfn[b])))
         o += s
     return (res, ares) if with_abs else res
 

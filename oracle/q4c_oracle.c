@@ -21,6 +21,19 @@
  * The sums run over the whole grid (no batching): batching in the paper
  * (Eq. 31) only regroups the same terms.  Sums are compensated (Neumaier).
  *
+ * The paper's own Q4C integrand (Sec. II, Eq. 19, evaluated on scalar
+ * functions as in Eq. 29) is also stated here, for one component X (large
+ * or small) whose scalar functions are given as a basis of their own:
+ *
+ *   F_ij = sum_g w_g phi_i (eps_j - V_j(|r_g - R_B(j)|) + v_g) phi_j
+ *   H_ij = (F_ij + F_ji) / 2
+ *        = sum_g w_g phi_i phi_j (v_g + (u_i + u_j) / 2),  u_k = eps_k - V_k
+ *   S_ij = sum_g w_g phi_i phi_j
+ *
+ * with u_k the per-shell "ket potential" given as a table like the radials.
+ * Small-component functions Q(r)/r Y_{l~m~} (Eq. 12b) are real: the i of
+ * Eq. 12b cancels between bra and ket.
+ *
  * Basis functions (Eq. 12a): phi(r) = R(s)/s^l * S_lm(r - R_A), where
  * S_lm = s^l Y_lm is the real solid harmonic with the real Y_lm of App. B
  * (Condon-Shortley convention as written there), and the radial part
@@ -333,6 +346,94 @@ int orc_pair_blocks(const orc_basis *b, int64_t npts, const double *x, const dou
       }
     }
     off += 5 * blk;
+    free(sum);
+    free(cmp);
+    free(abs_);
+    free(fa);
+    free(fb);
+  }
+  return 0;
+}
+
+/*
+ * H and S of one component for the listed atom pairs (the Q4C integrand,
+ * Eq. 19 in the scalar form of Eq. 29, symmetrised):
+ *
+ *   H_ij = sum_g w_g phi_i phi_j (v_g + (u_i(s_A) + u_j(s_B)) / 2)
+ *   S_ij = sum_g w_g phi_i phi_j
+ *
+ * u of shell sh is the piecewise cubic at u_coef + shell_u_off[sh] on the
+ * shell's own knots (same format as the radial tables).
+ * out for pair p: 2 consecutive nA x nB row-major blocks (H, S).
+ * absout (optional): error scales sum_g |w_g| |phi_i| |phi_j| (|v_g| +
+ * (|u_i| + |u_j|) / 2) for H and sum_g |w_g| |phi_i| |phi_j| for S, with the
+ * magnitudes of the terms the values are summed from (see orc_pair_blocks).
+ */
+static void atom_ket(const orc_basis *b, const int64_t *shell_u_off, const double *u_coef, int a, double px,
+                     double py, double pz, double *u, double *au) {
+  double dx = px - b->R[3 * a], dy = py - b->R[3 * a + 1], dz = pz - b->R[3 * a + 2];
+  double s = sqrt(dx * dx + dy * dy + dz * dz);
+  int f = 0;
+  for (int sh = b->atom_shell_off[a]; sh < b->atom_shell_off[a + 1]; ++sh) {
+    int l = b->shell_l[sh];
+    double val, der, cval, cder;
+    radial_eval(u_coef + shell_u_off[sh], b->shell_nint[sh], b->shell_rcut[sh], s, &val, &der, &cval, &cder);
+    for (int m = -l; m <= l; ++m, ++f) {
+      u[f] = val;
+      au[f] = cval;
+    }
+  }
+}
+
+int orc_pair_blocks_hs(const orc_basis *b, const int64_t *shell_u_off, const double *u_coef, int64_t npts,
+                       const double *x, const double *y, const double *z, const double *w, const double *v,
+                       int npairs, const int32_t *pa, const int32_t *pb, int screened, double *out,
+                       double *absout) {
+  int64_t off = 0;
+  for (int p = 0; p < npairs; ++p) {
+    int A = pa[p], B = pb[p];
+    int nA = atom_nfn(b, A), nB = atom_nfn(b, B);
+    double rA = atom_rcut(b, A), rB = atom_rcut(b, B);
+    int64_t blk = (int64_t)nA * nB;
+    double *sum = (double *)calloc(2 * blk, sizeof(double));
+    double *cmp = (double *)calloc(2 * blk, sizeof(double));
+    double *abs_ = (double *)calloc(2 * blk, sizeof(double));
+    /* per side: phi, gradient (unused), magnitudes, u, |u| terms */
+    double *fa = (double *)malloc(sizeof(double) * nA * 11);
+    double *fb = (double *)malloc(sizeof(double) * nB * 11);
+    double *ga = fa + nA, *gb = fb + nB;
+    double *xa = fa + 4 * nA, *xb = fb + 4 * nB;
+    double *ya = xa + nA, *yb = xb + nB;
+    double *ua = ya + 3 * nA, *ub = yb + 3 * nB;
+    double *va = ua + nA, *vb = ub + nB;
+    for (int64_t g = 0; g < npts; ++g) {
+      if (screened) {
+        double ax = x[g] - b->R[3 * A], ay = y[g] - b->R[3 * A + 1], az = z[g] - b->R[3 * A + 2];
+        double bx = x[g] - b->R[3 * B], by = y[g] - b->R[3 * B + 1], bz = z[g] - b->R[3 * B + 2];
+        if (!(ax * ax + ay * ay + az * az < rA * rA)) continue;
+        if (!(bx * bx + by * by + bz * bz < rB * rB)) continue;
+      }
+      atom_functions_c(b, A, x[g], y[g], z[g], fa, ga, xa, ya);
+      atom_functions_c(b, B, x[g], y[g], z[g], fb, gb, xb, yb);
+      atom_ket(b, shell_u_off, u_coef, A, x[g], y[g], z[g], ua, va);
+      atom_ket(b, shell_u_off, u_coef, B, x[g], y[g], z[g], ub, vb);
+      for (int i = 0; i < nA; ++i) {
+        for (int j = 0; j < nB; ++j) {
+          int64_t e = (int64_t)i * nB + j;
+          double wpp = w[g] * fa[i] * fb[j];
+          double aw = fabs(w[g]) * xa[i] * xb[j];
+          neu_add(sum + e, cmp + e, wpp * (v[g] + 0.5 * (ua[i] + ub[j])));
+          neu_add(sum + blk + e, cmp + blk + e, wpp);
+          abs_[e] += aw * (fabs(v[g]) + 0.5 * (va[i] + vb[j]));
+          abs_[blk + e] += aw;
+        }
+      }
+    }
+    for (int64_t e = 0; e < 2 * blk; ++e) {
+      out[off + e] = sum[e] + cmp[e];
+      if (absout) absout[off + e] = abs_[e];
+    }
+    off += 2 * blk;
     free(sum);
     free(cmp);
     free(abs_);

@@ -70,7 +70,7 @@ def test_solid_harmonics_match_scipy_app_b_convention():
     """Real Y_lm of App. B equal sqrt2 Re / Im of the complex (Condon-Shortley)
     harmonics of scipy: Y_l^m = sqrt2 Re Y_l^|m| (m>0), Y_l^0, sqrt2 Im Y_l^|m| (m<0)."""
     rng = np.random.default_rng(11)
-    for l in range(4):
+    for l in range(5):
         for m in range(-l, l + 1):
             for _ in range(6):
                 p = rng.standard_normal(3)
@@ -98,7 +98,7 @@ def test_solid_harmonics_explicit_low_order():
 def test_solid_harmonics_gradient_finite_difference():
     rng = np.random.default_rng(12)
     h = 1e-5
-    for l in range(4):
+    for l in range(5):
         for m in range(-l, l + 1):
             p = rng.standard_normal(3)
             _, g = oracle.solid_harmonic(l, m, *p)
@@ -109,9 +109,9 @@ def test_solid_harmonics_gradient_finite_difference():
 
 def test_solid_harmonics_orthonormal_on_product_grid():
     u, wu = W.product_sphere(10, 20)
-    Y = np.array([[oracle.solid_harmonic(l, m, *p)[0] for p in u] for l in range(4) for m in range(-l, l + 1)])
+    Y = np.array([[oracle.solid_harmonic(l, m, *p)[0] for p in u] for l in range(5) for m in range(-l, l + 1)])
     G = (Y * wu[None, :]) @ Y.T
-    assert np.max(np.abs(G - np.eye(16))) < 1e-13
+    assert np.max(np.abs(G - np.eye(25))) < 1e-13
 
 
 def test_radial_table_reproduces_analytic_function():

@@ -206,6 +206,11 @@ class Workload:
     c_light: float = C_LIGHT
     molecule: Optional[np.ndarray] = None  # int32[na] molecule id (batched workloads)
     meta: Dict = dataclasses.field(default_factory=dict)
+    # ket potential u_s(r) = eps_s - V_s(r) per shell (Q4C H integrand), tables
+    # in the radial format on the shell's own knots; None when not set
+    shell_u_off: Optional[np.ndarray] = None  # int64[ns] offsets (doubles) into u_coef
+    u_coef: Optional[np.ndarray] = None       # float64[...] 4 per interval
+    shell_eps: Optional[np.ndarray] = None    # float64[ns] eps_s (recipe record)
 
     @property
     def n_atoms(self) -> int:
@@ -634,6 +639,152 @@ def spinor_density(wl: Workload, pairs: np.ndarray, seed: int, scale: float = 0.
             rab = float(np.linalg.norm(wl.R[a] - wl.R[b]))
             blocks.append(scale * math.exp(-rab / decay_bohr) * X)
     return blocks
+
+
+# ----------------------------------------------------------------------------
+# Ket potentials and small-component bases (the paper's Q4C H integrand)
+# ----------------------------------------------------------------------------
+
+def hermite_table(fun, rcut: float, nint: int) -> np.ndarray:
+    """Cubic-Hermite coefficients of fun (returning value and r-derivative on an
+    array of radii) on knots r_j = rcut (j/nint)^2, in the radial-table format
+    (float64[nint, 4], t in [0,1) per interval).  Exact for cubics in r."""
+    j = np.arange(nint + 1, dtype=np.float64)
+    r = rcut * (j / nint) ** 2
+    f, d = fun(r)
+    h = r[1:] - r[:-1]
+    f0, f1 = f[:-1], f[1:]
+    d0, d1 = d[:-1] * h, d[1:] * h
+    out = np.empty((nint, 4))
+    out[:, 0] = f0
+    out[:, 1] = d0
+    out[:, 2] = 3.0 * (f1 - f0) - 2.0 * d0 - d1
+    out[:, 3] = 2.0 * (f0 - f1) + d0 + d1
+    return out
+
+
+def smeared_nucleus(r, Z: float, a_smear: float = 0.5):
+    """Z erf(r/a)/r (the negative of the smeared-nucleus model potential of one
+    atom) and its r-derivative; finite at r = 0 (series below r = 1e-4 a)."""
+    r = np.asarray(r, dtype=np.float64)
+    x = r / a_smear
+    small = x < 1e-4
+    xs = np.where(small, 1.0, x)
+    c = 2.0 / math.sqrt(math.pi)
+    from scipy.special import erf as _erf
+    val = np.where(small, Z * c / a_smear * (1.0 - x * x / 3.0),
+                   Z * _erf(xs) / (xs * a_smear))
+    der = np.where(small, -Z * c / a_smear * (2.0 * x / 3.0) / a_smear,
+                   Z * (c * np.exp(-xs * xs) / xs - _erf(xs) / (xs * xs)) / (a_smear * a_smear))
+    return val, der
+
+
+def _species_key(wl: Workload, a: int, k: int):
+    return (int(wl.Z[a]), k)
+
+
+def ket_tables(wl: Workload, shell_eps: np.ndarray, a_smear: float = 0.5) -> Workload:
+    """Attach u_s(r) = eps_s + Z_A erf(r/a)/r to every shell s of atom A: the ket
+    potential eps_s - V_s(r) of a free-atom-like shell whose defining potential is
+    the smeared-nucleus model potential of its own atom.  Shells with the same
+    (Z, eps, rcut, nint) share one table."""
+    shell_eps = np.asarray(shell_eps, dtype=np.float64)
+    tabs: Dict = {}
+    chunks: List[np.ndarray] = []
+    offs = np.zeros(wl.n_shells, dtype=np.int64)
+    off = 0
+    for a in range(wl.n_atoms):
+        for s in range(wl.atom_shell_off[a], wl.atom_shell_off[a + 1]):
+            key = (int(wl.Z[a]), float(shell_eps[s]), float(wl.shell_rcut[s]), int(wl.shell_nint[s]))
+            if key not in tabs:
+                eps, Z = key[1], key[0]
+                t = hermite_table(lambda r: (lambda v, d: (v + eps, d))(*smeared_nucleus(r, Z, a_smear)),
+                                  key[2], key[3])
+                tabs[key] = off
+                chunks.append(t.reshape(-1))
+                off += t.size
+            offs[s] = tabs[key]
+    return dataclasses.replace(wl, shell_u_off=offs, u_coef=np.ascontiguousarray(np.concatenate(chunks)),
+                               shell_eps=shell_eps.copy())
+
+
+def with_ket(wl: Workload, seed: int, eps_range=(-2.0, -0.05)) -> Workload:
+    """Seeded orbital energies eps per (species, shell index), uniform in eps_range
+    (Ha), and the matching ket-potential tables."""
+    eps = np.zeros(wl.n_shells)
+    cache: Dict = {}
+    for a in range(wl.n_atoms):
+        s0 = wl.atom_shell_off[a]
+        for k, s in enumerate(range(s0, wl.atom_shell_off[a + 1])):
+            key = _species_key(wl, a, k)
+            if key not in cache:
+                rng = np.random.default_rng(np.random.PCG64([seed, key[0], k]))
+                cache[key] = float(rng.uniform(*eps_range))
+            eps[s] = cache[key]
+    return ket_tables(wl, eps)
+
+
+def poly_ket_tables(wl: Workload, eps: Sequence[float], kq: Sequence[float]) -> Workload:
+    """u_s(r) = eps_s + kq_s r^2 per shell (a quadratic: the cubic table is exact).
+    For closed-form pins."""
+    chunks, offs, off = [], np.zeros(wl.n_shells, dtype=np.int64), 0
+    for s in range(wl.n_shells):
+        e, k = float(eps[s]), float(kq[s])
+        t = hermite_table(lambda r: (e + k * r * r, 2.0 * k * r), float(wl.shell_rcut[s]), int(wl.shell_nint[s]))
+        offs[s] = off
+        chunks.append(t.reshape(-1))
+        off += t.size
+    return dataclasses.replace(wl, shell_u_off=offs, u_coef=np.ascontiguousarray(np.concatenate(chunks)),
+                               shell_eps=np.asarray(eps, dtype=np.float64).copy())
+
+
+def small_component(wl: Workload, seed: int, alpha_range=(0.3, 30.0)) -> Workload:
+    """The small-component scalar basis of a large-component workload (Eq. 12b):
+    every large shell l gives small shells l~ = l + 1 (j = l + 1/2) and, for
+    l >= 1, l~ = l - 1 (j = l - 1/2).  Radials Q(r)/r are seeded normalised
+    3-Gaussian sums per (species, shell) on the parent shell's cutoff and knots;
+    each small shell takes its parent's eps, and its ket table is rebuilt from
+    its own atom's smeared-nucleus potential.  Same grid, atoms and v."""
+    rows = []  # (atom, l~, parent shell)
+    for a in range(wl.n_atoms):
+        for s in range(wl.atom_shell_off[a], wl.atom_shell_off[a + 1]):
+            l = int(wl.shell_l[s])
+            rows.append((a, l + 1, s))
+            if l >= 1:
+                rows.append((a, l - 1, s))
+    cache: Dict = {}
+    chunks: List[np.ndarray] = []
+    off = 0
+    aso = np.zeros(wl.n_atoms + 1, dtype=np.int32)
+    sl, sr, sn, so, sa, sc, eps = [], [], [], [], [], [], []
+    k_of_atom: Dict[int, int] = {}
+    for (a, lt, s) in rows:
+        k = k_of_atom.get(a, 0)
+        k_of_atom[a] = k + 1
+        key = (int(wl.Z[a]), k, float(wl.shell_rcut[s]), int(wl.shell_nint[s]))
+        if key not in cache:
+            rng = np.random.default_rng(np.random.PCG64([seed, key[0], k]))
+            lo, hi = np.log(alpha_range[0]), np.log(alpha_range[1])
+            alpha = np.sort(np.exp(rng.uniform(lo, hi, size=3)))
+            c = rng.uniform(0.2, 1.0, size=3)
+            c = c * gauss_norm(lt, alpha, c)
+            tab = spline_table(alpha, c, key[2], key[3])
+            cache[key] = (off, alpha, c)
+            chunks.append(tab.reshape(-1))
+            off += tab.size
+        o, alpha, c = cache[key]
+        sl.append(lt); sr.append(key[2]); sn.append(key[3]); so.append(o); sa.append(alpha); sc.append(c)
+        eps.append(float(wl.shell_eps[s]) if wl.shell_eps is not None else 0.0)
+        aso[a + 1] = len(sl)
+    for a in range(wl.n_atoms):
+        aso[a + 1] = max(aso[a + 1], aso[a])
+    ws = dataclasses.replace(
+        wl, name=wl.name + "-small", atom_shell_off=aso, shell_l=np.array(sl, dtype=np.int32),
+        shell_rcut=np.array(sr, dtype=np.float64), shell_nint=np.array(sn, dtype=np.int32),
+        shell_coef_off=np.array(so, dtype=np.int64), coef=np.ascontiguousarray(np.concatenate(chunks)),
+        shell_alpha=np.array(sa).reshape(-1, 3), shell_gcoef=np.array(sc).reshape(-1, 3),
+        shell_u_off=None, u_coef=None, shell_eps=None)
+    return ket_tables(ws, np.array(eps))
 
 
 def pin_workload(Z, R_bohr, shells_per_atom, nrad=300, ntheta=12, nphi=24, rcut=6.0 * ANGSTROM, nint=2048,

@@ -55,7 +55,7 @@ enum {
   Q4C_ENOMEM = -2,       /* host or device allocation failed */
   Q4C_EHIP = -3,         /* HIP runtime error (message via q4c_last_error) */
   Q4C_ENOTIMPL = -4,     /* option not implemented */
-  Q4C_EUNSUPPORTED = -5, /* unsupported input, e.g. l > 3 */
+  Q4C_EUNSUPPORTED = -5, /* unsupported input, e.g. l > 4 */
   Q4C_ESIZE = -6,        /* output buffer too small */
   Q4C_ENONFINITE = -7,   /* non-finite input detected (Q4C_CHECK_FINITE) */
   Q4C_ENODEV = -8        /* plan has no device data (host-only plan or no GPU) */
@@ -88,7 +88,7 @@ enum {
 typedef struct q4c_plan q4c_plan;
 
 /* Basis set: per-atom shells with piecewise-cubic radial tables.
- * Shell s: angular momentum shell_l[s] in 0..3, cutoff shell_rcut[s] > 0,
+ * Shell s: angular momentum shell_l[s] in 0..4, cutoff shell_rcut[s] > 0,
  * nint = shell_nint[s] >= 1 intervals on knots r_j = rcut (j / nint)^2,
  * coefficients coef[shell_coef_off[s] + 4 j + k], k = 0..3, such that for
  * r_j <= s < r_{j+1} and t = (s - r_j) / (r_{j+1} - r_j):
@@ -141,13 +141,14 @@ typedef struct {
   double flops_alg;        /* sum_B 10 P_B n_B^2, the algorithmic flop count of one H build */
   int32_t n_systems;       /* independent systems (1 unless q4c_plan_create_batched) */
   int64_t scratch_bytes;   /* device scratch of the plan (largest pass: staging, partials, panels) */
+  double flops_alg_hs;     /* sum_B 3 P_B n_B^2: the three contractions of one q4c_integrate_HS */
 } q4c_info;
 
 /* Build a plan: batching (recursive median bisection of the active points to
  * at most p_max points), per-batch relevant functions, the pair store layout,
  * scatter maps and device buffers.  Paper Sec. III A: batches B_v (Eq. 31)
  * and the reduced index set nnz(B_v).  Inputs are copied.  Returns
- * Q4C_EUNSUPPORTED for l > 3 and Q4C_EINVAL for malformed descriptors. */
+ * Q4C_EUNSUPPORTED for l > 4 and Q4C_EINVAL for malformed descriptors. */
 int q4c_plan_create(const q4c_basis *basis, const q4c_grid *grid, const q4c_opts *opts, q4c_plan **out);
 
 /* One plan over n_systems independent systems (e.g. many molecules): every
@@ -223,6 +224,34 @@ enum { Q4C_TERM_LL = 1u, Q4C_TERM_SS = 2u, Q4C_TERM_SO = 4u, Q4C_TERM_ALL = 7u }
 int density_on_grid(const q4c_plan *plan, const double *coef_dev, uint32_t terms, int32_t weight_mode,
                     double *out_dev, void *stream);
 
+/* The paper's own Q4C Hamiltonian integrand (Sec. II, Eq. 19), evaluated on
+ * the scalar functions of one component as in Eq. 29.  A plan built from the
+ * large-component basis (P(r)/r Y_lm, Eq. 12a) or from the small-component
+ * basis (Q(r)/r Y_{l~m~}, l~ = l +- 1, Eq. 12b; the i of Eq. 12b cancels
+ * between bra and ket) gives that component's H and S.
+ *
+ * q4c_plan_set_ket_potential: the ket potential u_s(r) = eps_s - V_s(r) of
+ * every shell s (eps_s, V_s: the orbital energy and defining radial
+ * potential of the spinor function the shell belongs to), as a piecewise
+ * cubic on the shell's own radial knots, in the radial-table format:
+ * u_coef[shell_u_off[s] + 4 j + k] (host arrays, n_shells offsets, n_u
+ * doubles; copied).  Replaces an earlier table.  Q4C_EINVAL for a table
+ * outside u_coef, an offset not a multiple of 4, or non-finite values. */
+int q4c_plan_set_ket_potential(q4c_plan *plan, const int64_t *shell_u_off, int64_t n_u, const double *u_coef);
+
+/* q4c_integrate_HS: for the potential v (device, [n_points], user order,
+ * hartree; V_eff of Eq. 19), the symmetrised ket-dependent Hamiltonian and
+ * the overlap of the plan's component on the atom-pair store layout:
+ *   H_ij = sum_g w_g phi_i phi_j (v_g + (u_i + u_j) / 2)
+ *        = (F_ij + F_ji) / 2,  F_ij = sum_g w_g phi_i (eps_j - V_j + v_g) phi_j
+ *   S_ij = sum_g w_g phi_i phi_j
+ * hs_dev (device): 2 store_len doubles, H then S, each part laid out like one
+ * part of the q4c_integrate_H store.  FP64 MFMA; batch sums added in a fixed
+ * order (bitwise repeatable).  flags: Q4C_ACCUMULATE adds to hs_dev,
+ * Q4C_CHECK_FINITE rejects a non-finite v (Q4C_ENONFINITE).  Q4C_EINVAL if no
+ * ket potential is set.  Runs eagerly (no graph capture). */
+int q4c_integrate_HS(const q4c_plan *plan, const double *v_dev, uint32_t flags, double *hs_dev, void *stream);
+
 /* Coefficients on the stored elements from a Hermitian spinor density matrix
  * D given as spinor blocks (device complex128, 4 store_len, spinor layout)
  * such that density_on_grid yields Re Tr(D H) derivatives (Eq. 21/39):
@@ -254,8 +283,9 @@ int q4c_plan_profile(q4c_plan *plan, int enable);
 int q4c_plan_split_stats(const q4c_plan *plan, int64_t *fp64_chunks, int64_t *total_chunks);
 int q4c_plan_timers(q4c_plan *plan, double *ms, int64_t *launches);
 
-/* Launch shape of the two contraction kernels (k_contract of q4c_integrate_H,
- * k_density_tiles of density_on_grid), per plan:
+/* Launch shape of the contraction kernels (k_contract of q4c_integrate_H,
+ * k_density_tiles of density_on_grid, k_contract_hs of q4c_integrate_HS), per
+ * plan (the autotuner covers the first two):
  *   order      0: work items in batch order, consecutive items on one XCD;
  *              1: largest items first (estimated cost), longest-first scheduling;
  *   persistent 0: one workgroup per work item;
@@ -265,7 +295,7 @@ int q4c_plan_timers(q4c_plan *plan, double *ms, int64_t *launches);
  * Results do not depend on the launch shape (each item's arithmetic and the
  * fixed-order sums are unchanged): bitwise equal outputs.  Setting a shape
  * drops the plan's captured graphs. */
-enum { Q4C_KERNEL_CONTRACT = 0, Q4C_KERNEL_DENSITY = 1 };
+enum { Q4C_KERNEL_CONTRACT = 0, Q4C_KERNEL_DENSITY = 1, Q4C_KERNEL_HS = 2 /* k_contract_hs, q4c_integrate_HS */ };
 int q4c_plan_set_launch(q4c_plan *plan, int32_t kernel, int32_t order, int32_t persistent);
 int q4c_plan_get_launch(const q4c_plan *plan, int32_t kernel, int32_t *order, int32_t *persistent);
 

@@ -66,7 +66,7 @@ class _Info(ctypes.Structure):
                 ("store_len", ctypes.c_int64), ("fn_entries", ctypes.c_int64), ("max_batch_points", ctypes.c_int64),
                 ("max_batch_fn", ctypes.c_int64), ("n_work", ctypes.c_int64), ("n_passes", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64), ("flops_alg", ctypes.c_double), ("n_systems", ctypes.c_int32),
-                ("scratch_bytes", ctypes.c_int64)]
+                ("scratch_bytes", ctypes.c_int64), ("flops_alg_hs", ctypes.c_double)]
 
 
 class _TuneEntry(ctypes.Structure):
@@ -74,14 +74,15 @@ class _TuneEntry(ctypes.Structure):
                 ("ms", ctypes.c_double)]
 
 
-KERNEL_CONTRACT, KERNEL_DENSITY = 0, 1
+KERNEL_CONTRACT, KERNEL_DENSITY, KERNEL_HS = 0, 1, 2
 
 
 EXPORTS = ("q4c_plan_create", "q4c_plan_destroy", "q4c_plan_info", "q4c_plan_pairs", "q4c_plan_batches",
            "q4c_tabulate_size", "nao_tabulate", "q4c_integrate_H", "density_on_grid", "q4c_coef_from_spinor",
            "q4c_plan_sync", "q4c_plan_profile", "q4c_plan_timers", "q4c_plan_split_stats", "q4c_status_string",
            "q4c_last_error", "q4c_plan_create_batched", "q4c_plan_systems", "q4c_plan_set_launch",
-           "q4c_plan_get_launch", "q4c_plan_autotune", "q4c_plan_set_graphs")
+           "q4c_plan_get_launch", "q4c_plan_autotune", "q4c_plan_set_graphs", "q4c_plan_set_ket_potential",
+           "q4c_integrate_HS")
 
 
 def _load():
@@ -117,6 +118,8 @@ def _load():
         lib.q4c_plan_autotune.argtypes = [vp, vp, i32, vp, vp, vp, i32, ctypes.POINTER(_TuneEntry), i32,
                                           ctypes.POINTER(i32), vp]
         lib.q4c_plan_set_graphs.argtypes = [vp, ctypes.c_int]
+        lib.q4c_plan_set_ket_potential.argtypes = [vp, vp, i64, vp]
+        lib.q4c_integrate_HS.argtypes = [vp, vp, u32, vp, vp]
         lib.q4c_status_string.argtypes = [ctypes.c_int]
         lib.q4c_status_string.restype = ctypes.c_char_p
         lib.q4c_last_error.argtypes = []
@@ -279,6 +282,22 @@ class Plan:
                                                                                  "store")]))
         return out
 
+    def set_ket_potential(self, wl):
+        """Ket-potential tables u = eps - V per shell (q4c_plan_set_ket_potential)
+        from a workload's shell_u_off / u_coef, or from a list of workloads in
+        the system order of a batched plan (their shells concatenated)."""
+        systems = list(wl) if isinstance(wl, (list, tuple)) else [wl]
+        offs, tabs, base = [], [], 0
+        for w in systems:
+            if w.u_coef is None or w.shell_u_off is None:
+                raise ValueError("workload has no ket-potential tables")
+            offs.append(np.asarray(w.shell_u_off, dtype=np.int64) + base)
+            tabs.append(np.asarray(w.u_coef, dtype=np.float64))
+            base += tabs[-1].size
+        off = np.ascontiguousarray(np.concatenate(offs))
+        tab = np.ascontiguousarray(np.concatenate(tabs))
+        _check(_load().q4c_plan_set_ket_potential(self._h, off.ctypes.data, int(tab.size), tab.ctypes.data))
+
     def set_launch(self, kernel: int, order: int, persistent: int):
         _check(_load().q4c_plan_set_launch(self._h, int(kernel), int(order), int(persistent)))
 
@@ -329,6 +348,14 @@ def q4c_integrate_H(plan: Plan, v, precision: int = PREC_F64, flags: int = 0, st
     return store
 
 
+def q4c_integrate_HS(plan: Plan, v, flags: int = 0, hs=None):
+    """H and S of the plan's component into `hs` ([2, store_len] float64)."""
+    L = plan.info["store_len"]
+    _check(_load().q4c_integrate_HS(plan.handle, _dev_ptr(v, min_numel=plan.info["n_points"], name="v"),
+                                    int(flags), _dev_ptr(hs, min_numel=2 * L, name="hs"), _stream_handle()))
+    return hs
+
+
 def density_on_grid(plan: Plan, coef, terms: int = TERM_ALL, weight_mode: int = 0, out=None):
     L = plan.info["store_len"]
     _check(_load().density_on_grid(plan.handle, _dev_ptr(coef, min_numel=5 * L, name="coef"), int(terms),
@@ -351,6 +378,11 @@ def q4c_coef_from_spinor(plan: Plan, spin_d, out):
 def new_store(plan: Plan, device="cuda"):
     import torch
     return torch.empty((5, plan.info["store_len"]), dtype=torch.float64, device=device)
+
+
+def new_hs(plan: Plan, device="cuda"):
+    import torch
+    return torch.empty((2, plan.info["store_len"]), dtype=torch.float64, device=device)
 
 
 def new_spinor(plan: Plan, device="cuda"):

@@ -29,12 +29,14 @@ struct DevPlan {
   // basis
   const double *R;             // [3 n_atoms]
   const int32_t *fn_atom;      // [n_fn]
-  const int32_t *fn_shlm;      // [n_fn] shell * 16 + (l*l + l + m)
+  const int32_t *fn_shlm;      // [n_fn] shell * 32 + (l*l + l + m), l <= 4
   const double *shell_rcut;    // [n_shells]
   const int32_t *shell_nint;   // [n_shells]
   const double *shell_knot;    // [2 n_shells]: nint^2 / rcut, rcut / nint^2
   const int64_t *shell_coef_off;   // into coef (scaled table, see q4c_plan::coef_scaled)
   const double *coef;
+  const int64_t *shell_u_off;  // into ucoef (ket potential, scaled like coef); null until set
+  const double *ucoef;
   // grid, batch order
   const double *px, *py, *pz, *pw;  // [n_active]
   const int32_t *perm;              // [n_active] user index
@@ -99,6 +101,10 @@ struct q4c_plan {
   std::vector<double> coef_scaled;
   std::vector<int64_t> shell_cs_off;
   std::vector<double> shell_knot;
+  // Ket potential u_s = eps_s - V_s per shell (H/S integrand), in the same
+  // scaled form; empty until q4c_plan_set_ket_potential.
+  std::vector<double> ucoef_scaled;
+  std::vector<int64_t> shell_us_off;
   std::vector<int32_t> atom_fn_off;  // [n_atoms + 1]
   std::vector<double> atom_rcut;     // [n_atoms]
   std::vector<int32_t> fn_atom, fn_shlm;
@@ -144,6 +150,7 @@ struct q4c_plan {
   int64_t max_scratch = 0;
   int64_t max_batch_points = 0, max_batch_fn = 0, fn_entries = 0;
   double flops_alg = 0.0;
+  double flops_alg_hs = 0.0;  // sum_B 3 P_B n_B^2: the three contractions of q4c_integrate_HS
 
   // ---- device
   bool on_device = false;
@@ -159,6 +166,8 @@ struct q4c_plan {
   int32_t *d_untouched = nullptr;
   q4c::WorkItem *d_ptile = nullptr;
   double *d_om = nullptr;  // [n_active + 16] point weights w_g v_g of the current call
+  double *d_ucoef = nullptr;         // ket-potential tables (q4c_plan_set_ket_potential)
+  int64_t *d_shell_us_off = nullptr;
   unsigned long long *d_chunks = nullptr;  // [64][2]: FP64-routed and total chunks of the last split call
   double *d_staging = nullptr;
   int32_t *d_flag = nullptr;
@@ -168,7 +177,7 @@ struct q4c_plan {
   int n_cu = 256;                  // compute units of the plan's device
 
   // ---- launch configuration (chosen by q4c_plan_autotune or set directly)
-  q4c::LaunchCfg cfg_contract{}, cfg_density{};
+  q4c::LaunchCfg cfg_contract{}, cfg_density{}, cfg_hs{};
   bool use_graphs = false;
   mutable hipStream_t capture_stream = nullptr;
   struct GraphEntry {
@@ -197,6 +206,7 @@ int launch_integrate(const q4c_plan *p, const double *v, int precision, uint32_t
                      double *spin_w, double *spin_v, hipStream_t s);
 int launch_density(const q4c_plan *p, const double *coef, uint32_t terms, int weight_mode, double *out,
                    hipStream_t s);
+int launch_integrate_hs(const q4c_plan *p, const double *v, uint32_t flags, double *hs, hipStream_t s);
 int launch_coef_from_spinor(const q4c_plan *p, const double *spin_d, double *coef_out, hipStream_t s);
 int launch_check_finite(const q4c_plan *p, const double *v, hipStream_t s, bool *finite);
 

@@ -46,13 +46,16 @@ constexpr int NT = 256;     // threads per contraction workgroup (4 waves)
 
 // Real solid harmonics S_lm = s^l Y_lm (App. B convention, Condon-Shortley
 // phase as written there: Y_1,1 = -sqrt(3/4pi) x/s) and their gradients,
-// l <= 3, indexed by lm = l^2 + l + m.
+// l <= 4, indexed by lm = l^2 + l + m.
 __device__ __forceinline__ void solid_harmonic(int lm, double x, double y, double z, double &S, double &gx,
                                                double &gy, double &gz) {
   constexpr double C00 = 0.28209479177387814, C1 = 0.4886025119029199, C2a = 1.0925484305920792,
                    C20 = 0.31539156525252005, C22 = 0.5462742152960396, C33 = 0.5900435899266435,
                    C32b = 2.8906114426405543, C31 = 0.4570457994644657, C30 = 0.3731763325901154,
                    C32a = 1.4453057213202771;
+  // l = 4: K_4^0 / 8 and sqrt2 K_4^|m| times the integer factors of the polynomials
+  constexpr double C40 = 0.10578554691520431, C41 = 0.6690465435572891, C42 = 0.47308734787878,
+                   C43 = 1.7701307697799304, C44 = 0.6258357354491761;
   switch (lm) {
     case 0: S = C00; gx = gy = gz = 0.0; break;
     case 1: S = -C1 * y; gx = 0.0; gy = -C1; gz = 0.0; break;
@@ -76,7 +79,39 @@ __device__ __forceinline__ void solid_harmonic(int lm, double x, double y, doubl
       S = -C31 * x * q; gx = -C31 * (q - 2.0 * x * x); gy = 2.0 * C31 * x * y; gz = -8.0 * C31 * x * z;
     } break;
     case 14: S = C32a * z * (x * x - y * y); gx = 2.0 * C32a * x * z; gy = -2.0 * C32a * y * z; gz = C32a * (x * x - y * y); break;
-    default: S = -C33 * x * (x * x - 3.0 * y * y); gx = -3.0 * C33 * (x * x - y * y); gy = 6.0 * C33 * x * y; gz = 0.0; break;
+    case 15: S = -C33 * x * (x * x - 3.0 * y * y); gx = -3.0 * C33 * (x * x - y * y); gy = 6.0 * C33 * x * y; gz = 0.0; break;
+    // l = 4 (the small-component partners of f shells), rho = x^2 + y^2 + z^2
+    case 16: S = 4.0 * C44 * (x * x * x * y - x * y * y * y); gx = 4.0 * C44 * (3.0 * x * x * y - y * y * y);
+      gy = 4.0 * C44 * (x * x * x - 3.0 * x * y * y); gz = 0.0; break;
+    case 17: S = -C43 * z * (3.0 * x * x * y - y * y * y); gx = -6.0 * C43 * x * y * z;
+      gy = -3.0 * C43 * z * (x * x - y * y); gz = -C43 * (3.0 * x * x * y - y * y * y); break;
+    case 18: {
+      const double t = 6.0 * z * z - x * x - y * y;  // 7 z^2 - rho
+      S = 2.0 * C42 * x * y * t; gx = 2.0 * C42 * y * (t - 2.0 * x * x); gy = 2.0 * C42 * x * (t - 2.0 * y * y);
+      gz = 24.0 * C42 * x * y * z;
+    } break;
+    case 19: {
+      const double q = 4.0 * z * z - 3.0 * x * x - 3.0 * y * y;  // 7 z^2 - 3 rho
+      S = -C41 * y * z * q; gx = 6.0 * C41 * x * y * z; gy = -C41 * z * (q - 6.0 * y * y); gz = -C41 * y * (q + 8.0 * z * z);
+    } break;
+    case 20: {
+      const double rho = x * x + y * y + z * z, z2 = z * z;
+      S = C40 * (35.0 * z2 * z2 - 30.0 * z2 * rho + 3.0 * rho * rho); gx = C40 * x * (12.0 * rho - 60.0 * z2);
+      gy = C40 * y * (12.0 * rho - 60.0 * z2); gz = C40 * z * (80.0 * z2 - 48.0 * rho);
+    } break;
+    case 21: {
+      const double q = 4.0 * z * z - 3.0 * x * x - 3.0 * y * y;
+      S = -C41 * x * z * q; gx = -C41 * z * (q - 6.0 * x * x); gy = 6.0 * C41 * x * y * z; gz = -C41 * x * (q + 8.0 * z * z);
+    } break;
+    case 22: {
+      const double t = 6.0 * z * z - x * x - y * y;
+      S = C42 * (x * x - y * y) * t; gx = 2.0 * C42 * x * (t - x * x + y * y); gy = -2.0 * C42 * y * (t + x * x - y * y);
+      gz = 12.0 * C42 * (x * x - y * y) * z;
+    } break;
+    case 23: S = -C43 * z * (x * x * x - 3.0 * x * y * y); gx = -3.0 * C43 * z * (x * x - y * y);
+      gy = 6.0 * C43 * x * y * z; gz = -C43 * (x * x * x - 3.0 * x * y * y); break;
+    default: S = C44 * (x * x * x * x - 6.0 * x * x * y * y + y * y * y * y); gx = 4.0 * C44 * (x * x * x - 3.0 * x * y * y);
+      gy = 4.0 * C44 * (y * y * y - 3.0 * x * x * y); gz = 0.0; break;
   }
 }
 
@@ -86,7 +121,7 @@ __device__ __forceinline__ void tab_one(const DevPlan &d, int fn, double px, dou
                                         double &fx, double &fy, double &fz) {
   const int a = d.fn_atom[fn];
   const int shlm = d.fn_shlm[fn];
-  const int sh = shlm >> 4;
+  const int sh = shlm >> 5;
   const double dx = px - d.R[3 * a], dy = py - d.R[3 * a + 1], dz = pz - d.R[3 * a + 2];
   const double s2 = dx * dx + dy * dy + dz * dz;
   const double rc = d.shell_rcut[sh];
@@ -106,7 +141,7 @@ __device__ __forceinline__ void tab_one(const DevPlan &d, int fn, double px, dou
   const double R = ((c[3] * dd + c[2]) * dd + c[1]) * dd + c[0];
   const double dR = (3.0 * c[3] * dd + 2.0 * c[2]) * dd + c[1];
   double S, gx, gy, gz;
-  solid_harmonic(shlm & 15, dx, dy, dz, S, gx, gy, gz);
+  solid_harmonic(shlm & 31, dx, dy, dz, S, gx, gy, gz);
   const double q = s > 0.0 ? dR / s : 0.0;
   f = R * S;
   fx = q * dx * S + R * gx;
@@ -152,6 +187,7 @@ struct TileMeta {
   double rc[2 * T];                        // cutoffs (0 for padding)
   double k1[2 * T], k2[2 * T];             // nint^2 / rcut, rcut / nint^2
   int64_t coef[2 * T];                     // offset of the shell's table
+  int64_t uoff[2 * T];                     // offset of the shell's ket-potential table (H/S panels)
   int nint[2 * T], lm[2 * T];
   int order[2 * T];                        // per side: tile columns sorted by lm
 };
@@ -165,7 +201,7 @@ __device__ __forceinline__ void load_tile_meta(const DevPlan &d, TileMeta &M, in
     const int lf = (tid < T ? r0 : c0) + (tid & (T - 1));
     if (lf < n) {
       const int fn = d.loc_fn[f0 + lf];
-      const int a = d.fn_atom[fn], shlm = d.fn_shlm[fn], sh = shlm >> 4;
+      const int a = d.fn_atom[fn], shlm = d.fn_shlm[fn], sh = shlm >> 5;
       M.ax[tid] = d.R[3 * a];
       M.ay[tid] = d.R[3 * a + 1];
       M.az[tid] = d.R[3 * a + 2];
@@ -173,15 +209,17 @@ __device__ __forceinline__ void load_tile_meta(const DevPlan &d, TileMeta &M, in
       M.k1[tid] = d.shell_knot[2 * sh];
       M.k2[tid] = d.shell_knot[2 * sh + 1];
       M.coef[tid] = d.shell_coef_off[sh];
+      M.uoff[tid] = d.shell_u_off ? d.shell_u_off[sh] : 0;
       M.nint[tid] = d.shell_nint[sh];
-      M.lm[tid] = shlm & 15;
+      M.lm[tid] = shlm & 31;
     } else {
       M.ax[tid] = M.ay[tid] = M.az[tid] = 0.0;
       M.rc[tid] = 0.0;
       M.k1[tid] = M.k2[tid] = 0.0;
       M.coef[tid] = 0;
+      M.uoff[tid] = 0;
       M.nint[tid] = 0;
-      M.lm[tid] = 16;
+      M.lm[tid] = 32;  // padding sorts last
     }
   }
   __syncthreads();
@@ -236,6 +274,48 @@ __device__ __forceinline__ void tab_meta(const DevPlan &d, const TileMeta &M, in
   fx = q * dx * S + R * gx;
   fy = q * dy * S + R * gy;
   fz = q * dz * S + R * gz;
+}
+
+// phi and psi = u phi / 2 of tile function m at (px, py, pz): the H/S panels.
+// u, the shell's ket potential, is a cubic on the radial table's own knots,
+// so it is evaluated on the same interval.
+__device__ __forceinline__ void tab_meta_hs(const DevPlan &d, const TileMeta &M, int m, double px, double py,
+                                            double pz, double &f, double &psi) {
+  const double dx = px - M.ax[m], dy = py - M.ay[m], dz = pz - M.az[m];
+  const double s2 = dx * dx + dy * dy + dz * dz;
+  const double rc = M.rc[m];
+  if (!(s2 < rc * rc)) {
+    f = psi = 0.0;
+    return;
+  }
+  double s = 0.0;
+  if (s2 > 0.0) {
+    double rinv = __builtin_amdgcn_rsq(s2);
+    rinv = rinv * (1.5 - 0.5 * s2 * rinv * rinv);
+    s = s2 * rinv;
+  }
+  const int n = M.nint[m];
+  const double k1 = M.k1[m], k2 = M.k2[m];
+  const double u = s * k1;
+  int j = u > 0.0 ? (int)(u * __builtin_amdgcn_rsq(u)) : 0;
+  j = j < 0 ? 0 : (j > n - 1 ? n - 1 : j);
+  double rj = (double)j * (double)j * k2;
+  if (s < rj && j > 0) {
+    --j;
+    rj = (double)j * (double)j * k2;
+  } else if (j < n - 1 && s >= (double)(j + 1) * (double)(j + 1) * k2) {
+    ++j;
+    rj = (double)j * (double)j * k2;
+  }
+  const double dd = s - rj;
+  const dbl4 c = *reinterpret_cast<const dbl4 *>(d.coef + M.coef[m] + 4 * (int64_t)j);
+  const dbl4 e = *reinterpret_cast<const dbl4 *>(d.ucoef + M.uoff[m] + 4 * (int64_t)j);
+  const double R = ((c[3] * dd + c[2]) * dd + c[1]) * dd + c[0];
+  const double U = ((e[3] * dd + e[2]) * dd + e[1]) * dd + e[0];
+  double S, gx, gy, gz;
+  solid_harmonic(M.lm[m], dx, dy, dz, S, gx, gy, gz);
+  f = R * S;
+  psi = 0.5 * U * f;
 }
 
 // ---------------------------------------------------------------------------
@@ -314,8 +394,10 @@ __global__ void k_om(DevPlan d, const double *v, double *om, unsigned long long 
 // written out as 16 contiguous 2 KB runs.
 constexpr int PLD = T + 1;  // padded LDS row of the panel stage
 
+template <bool HS>
 __global__ __launch_bounds__(256) void k_panel(DevPlan d, const WorkItem *tiles, int64_t t0, int64_t nt,
                                                double *panel) {
+  constexpr int NQ = HS ? 2 : 4;  // components: phi, psi (H/S) or phi and its gradient
   __shared__ TileMeta M;
   __shared__ double st[4 * 16 * PLD];
   __shared__ double s_gx[4][16];
@@ -335,14 +417,20 @@ __global__ __launch_bounds__(256) void k_panel(DevPlan d, const WorkItem *tiles,
       const int fl = M.order[k];
       double f = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
       const int g = g16 + pt;
-      if (M.nint[fl] > 0 && g < P) tab_meta(d, M, fl, d.px[g0 + g], d.py[g0 + g], d.pz[g0 + g], f, fx, fy, fz);
+      if (HS) {
+        if (M.nint[fl] > 0 && g < P) tab_meta_hs(d, M, fl, d.px[g0 + g], d.py[g0 + g], d.pz[g0 + g], f, fx);
+      } else {
+        if (M.nint[fl] > 0 && g < P) tab_meta(d, M, fl, d.px[g0 + g], d.py[g0 + g], d.pz[g0 + g], f, fx, fy, fz);
+      }
       st[(0 * 16 + pt) * PLD + fl] = f;
       st[(1 * 16 + pt) * PLD + fl] = fx;
-      st[(2 * 16 + pt) * PLD + fl] = fy;
-      st[(3 * 16 + pt) * PLD + fl] = fz;
+      if (!HS) {
+        st[(2 * 16 + pt) * PLD + fl] = fy;
+        st[(3 * 16 + pt) * PLD + fl] = fz;
+      }
     }
     __syncthreads();
-    {
+    if (!HS) {
       // largest |d phi / d x_a| per point over the tile's functions: thread
       // (pt, group of 4 functions), then the 4 groups of a wave, then the waves
       const int pt = threadIdx.x & 15, fg = threadIdx.x >> 4;
@@ -357,7 +445,7 @@ __global__ __launch_bounds__(256) void k_panel(DevPlan d, const WorkItem *tiles,
     }
     // (q, point quad) runs: rows r0 .. r0 + nrow - 1, 4 points each, contiguous
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < NQ; ++q)
 #pragma unroll
       for (int p4 = 0; p4 < 4; ++p4) {
         const int e = threadIdx.x;  // 256 = 64 rows x 4 points
@@ -366,7 +454,7 @@ __global__ __launch_bounds__(256) void k_panel(DevPlan d, const WorkItem *tiles,
           pb[((int64_t)(q * (Pp >> 2) + (g16 >> 2) + p4) * np + r0 + il) * 4 + pp] = st[(q * 16 + 4 * p4 + pp) * PLD + il];
       }
     __syncthreads();  // s_gx written; st consumed
-    if (threadIdx.x < 16)
+    if (!HS && threadIdx.x < 16)
       pb[(int64_t)4 * Pp * np + (int64_t)it.ti * Pp + g16 + threadIdx.x] =
           fmax(fmax(s_gx[0][threadIdx.x], s_gx[1][threadIdx.x]), fmax(s_gx[2][threadIdx.x], s_gx[3][threadIdx.x]));
   }
@@ -405,6 +493,44 @@ __device__ __forceinline__ double mirror_sign(int q) { return q >= 2 ? -1.0 : 1.
 // block (rb < cb) also stands for its mirror block (cb, rb), which no work
 // item computes.
 __device__ __forceinline__ bool block_active(int rb, int cb, int n) { return rb < n && cb < n && rb <= cb; }
+
+// The active 16 x 16 blocks of tile (r0, c0) (inside n, on or above the
+// diagonal), listed 2 x 2 square by square; wave w of four takes list entries
+// [w nb / 4, (w+1) nb / 4): at most one block more than another wave, and a
+// full tile gives every wave one 2 x 2 square.  Slot s of the wave holds block
+// (brow[s], bcol[s]) (tile-local offsets) when act[s]; the active slots are
+// 0 .. count-1, inactive ones point at block (0, 0).
+__device__ __forceinline__ void wave_blocks(int r0, int c0, int n, int wave, int (&brow)[4], int (&bcol)[4],
+                                            bool (&act)[4]) {
+  int nb = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int R = 2 * (k >> 3) + ((k >> 1) & 1), C = 2 * ((k >> 2) & 1) + (k & 1);
+    nb += block_active(r0 + 16 * R, c0 + 16 * C, n) ? 1 : 0;
+  }
+  const int kb0 = wave * nb / 4, kb1 = (wave + 1) * nb / 4;
+#pragma unroll
+  for (int sl = 0; sl < 4; ++sl) {
+    brow[sl] = 0;
+    bcol[sl] = 0;
+    act[sl] = false;
+  }
+  int cnt = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int R = 2 * (k >> 3) + ((k >> 1) & 1), C = 2 * ((k >> 2) & 1) + (k & 1);
+    if (block_active(r0 + 16 * R, c0 + 16 * C, n)) {
+#pragma unroll
+      for (int sl = 0; sl < 4; ++sl)
+        if (cnt == kb0 + sl && cnt < kb1) {
+          brow[sl] = 16 * R;
+          bcol[sl] = 16 * C;
+          act[sl] = true;
+        }
+      ++cnt;
+    }
+  }
+}
 
 // Write one accumulated element (li, lj) of a computed block to the staged
 // (batch, atom pair) block; `upper` = the element's block is strictly upper.
@@ -474,13 +600,13 @@ typedef __attribute__((address_space(3))) void lds_void;
 // W < 64 loads only the first W functions (lanes W.. idle); RS is the row
 // stride in doubles (at least 2 W, a multiple of 2).  The caller waits for
 // the loads (vmcnt) and synchronises the workgroup.
-template <int NTH, int CH = 16, int W = T, int RS = DROW>
+template <int NTH, int CH = 16, int W = T, int RS = DROW, int NQ = 4>
 __device__ __forceinline__ void dma_chunk(const double *pb, int64_t plane, int np, int row0, int ks0, double *dst) {
-  constexpr int RPQ = CH / 2;  // rows (point pairs) per component
+  constexpr int RPQ = CH / 2;  // rows (point pairs) per component; NQ components
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const bool ok = lane < W && row0 + lane < np;
 #pragma unroll
-  for (int k = 0; k < 4 * RPQ / (NTH / 64); ++k) {
+  for (int k = 0; k < NQ * RPQ / (NTH / 64); ++k) {
     const int r = wave + k * (NTH / 64);
     const int q = r / RPQ, u = r % RPQ;
     if (ok)
@@ -534,45 +660,11 @@ __global__ __launch_bounds__(NT, 2) void k_contract(DevPlan d, const WorkItem *w
   const int tid = threadIdx.x;
   // wave index as a scalar: conditions derived from it stay uniform
   const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  // The tile's active 16 x 16 blocks (inside n, on or above the diagonal),
-  // listed 2 x 2 square by square; wave w takes list entries
-  // [w nb / 4, (w+1) nb / 4): at most one block more than another wave, and
-  // a full tile gives every wave one 2 x 2 square.  Slot s of the wave holds
-  // block (brow[s], bcol[s]) (tile-local offsets) when act[s].
   (void)diag;
   const int li16 = lane & 15, lk = lane >> 4;
-  int nb = 0;
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const int R = 2 * (k >> 3) + ((k >> 1) & 1), C = 2 * ((k >> 2) & 1) + (k & 1);
-    nb += block_active(r0 + 16 * R, c0 + 16 * C, n) ? 1 : 0;
-  }
-  const int kb0 = wave * nb / 4, kb1 = (wave + 1) * nb / 4;
   int brow[4], bcol[4];
   bool act[4];
-#pragma unroll
-  for (int sl = 0; sl < 4; ++sl) {
-    brow[sl] = 0;
-    bcol[sl] = 0;
-    act[sl] = false;
-  }
-  {
-    int cnt = 0;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const int R = 2 * (k >> 3) + ((k >> 1) & 1), C = 2 * ((k >> 2) & 1) + (k & 1);
-      if (block_active(r0 + 16 * R, c0 + 16 * C, n)) {
-#pragma unroll
-        for (int sl = 0; sl < 4; ++sl)
-          if (cnt == kb0 + sl && cnt < kb1) {
-            brow[sl] = 16 * R;
-            bcol[sl] = 16 * C;
-            act[sl] = true;
-          }
-        ++cnt;
-      }
-    }
-  }
+  wave_blocks(r0, c0, n, wave, brow, bcol, act);
 
   dbl4 acc[4][5];
 #pragma unroll
@@ -799,6 +891,122 @@ __global__ __launch_bounds__(NT, 2) void k_contract(DevPlan d, const WorkItem *w
   }
 }
 
+// H and S of one component (the Q4C integrand of Eq. 19 in the scalar form
+// of Eq. 29, symmetrised), from panels of phi and psi = u phi / 2:
+//   H = Phi^T diag(w) (v Phi + Psi) + Psi^T diag(w) Phi,   S = Phi^T diag(w) Phi
+// i.e. per 16 x 16 block and K step of 4 points three FP64 MFMAs: the row
+// operands phi_i, psi_i against the column operands w v phi_j + w psi_j and
+// w phi_j (shared by the psi_i phi_j part of H and by S).  Same tiles, wave
+// slots and staging as the forward contraction; chunks of 16 points in two
+// LDS buffers (two components), the next chunk's DMA and weights in flight
+// while this one is multiplied.
+template <bool PERSIST>
+__global__ __launch_bounds__(NT, 2) void k_contract_hs(DevPlan d, const WorkItem *work, const int32_t *order,
+                                                       int64_t w0, int64_t nw, const double *om,
+                                                       const double *panel, double *staging, unsigned *tickets) {
+  constexpr int CH = 16, RPQ = CH / 2, NQ = 2;
+  constexpr int BUFD = NQ * RPQ * DROW;  // doubles per chunk image
+  __shared__ double sa[2 * BUFD], sb[2 * BUFD];
+  __shared__ int64_t s_pos;
+  int64_t pos = PERSIST ? next_item(tickets, nw, order != nullptr, &s_pos)
+                        : (order ? (int64_t)blockIdx.x : xcd_map(blockIdx.x, nw));
+  while (!PERSIST || pos < nw) {
+  const int64_t wi = w0 + (order ? order[w0 + pos] : pos);
+  const WorkItem it = work[wi];
+  const int b = it.batch;
+  const int g0 = d.batch_pt_off[b], P = d.batch_pt_off[b + 1] - g0;
+  const int f0 = d.batch_fn_off[b], n = d.batch_fn_off[b + 1] - f0;
+  const int sbase = d.batch_slot_off[b];
+  const int r0 = it.ti * T, c0 = it.tj * T;
+  const int Pp = (int)pad16(P), np = (int)pad16(n);
+  const double *pb = panel + d.panel_off[b];
+  const int64_t plane = (int64_t)Pp * np;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int li16 = lane & 15, lk = lane >> 4;
+  int brow[4], bcol[4];
+  bool act[4];
+  wave_blocks(r0, c0, n, wave, brow, bcol, act);
+  dbl4 acc[4][3];  // H (v phi + psi part), S, H (psi phi part)
+#pragma unroll
+  for (int sl = 0; sl < 4; ++sl)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) acc[sl][q] = dbl4{0.0, 0.0, 0.0, 0.0};
+  // weights at points 4 ks + lk of the next chunk: w v and w
+  double omn[CH / 4], wn[CH / 4];
+  auto load_w = [&](int k) {
+#pragma unroll
+    for (int ks = 0; ks < CH / 4; ++ks) {
+      const int pt = k + 4 * ks + lk;
+      omn[ks] = pt < P ? om[g0 + pt] : 0.0;
+      wn[ks] = pt < P ? d.pw[g0 + pt] : 0.0;
+    }
+  };
+  load_w(0);
+  dma_chunk<NT, CH, T, DROW, NQ>(pb, plane, np, r0, 0, sa);
+  dma_chunk<NT, CH, T, DROW, NQ>(pb, plane, np, c0, 0, sb);
+  for (int k0 = 0; k0 < Pp; k0 += CH) {
+    const int bo = ((k0 / CH) & 1) * BUFD;
+    double omv[CH / 4], wv[CH / 4];
+    __builtin_amdgcn_s_waitcnt(0);  // this thread's loads of this chunk have landed
+    __syncthreads();                // ... everyone's; the previous chunk is consumed
+#pragma unroll
+    for (int ks = 0; ks < CH / 4; ++ks) {
+      omv[ks] = omn[ks];
+      wv[ks] = wn[ks];
+    }
+    if (k0 + CH < Pp) {
+      const int nbo = BUFD - bo;
+      load_w(k0 + CH);
+      dma_chunk<NT, CH, T, DROW, NQ>(pb, plane, np, r0, (k0 + CH) >> 2, sa + nbo);
+      dma_chunk<NT, CH, T, DROW, NQ>(pb, plane, np, c0, (k0 + CH) >> 2, sb + nbo);
+    }
+    const double *ca = sa + bo, *cb = sb + bo;
+#pragma unroll
+    for (int ks = 0; ks < CH / 4; ++ks) {
+      const int rowk = 2 * ks + (lk >> 1), ck = lk & 1;
+#pragma unroll
+      for (int sl = 0; sl < 4; ++sl) {
+        if (!act[sl]) continue;  // wave-uniform
+        const double fi = ca[rowk * DROW + 2 * (brow[sl] + li16) + ck];
+        const double pi_ = ca[(RPQ + rowk) * DROW + 2 * (brow[sl] + li16) + ck];
+        const double fj = cb[rowk * DROW + 2 * (bcol[sl] + li16) + ck];
+        const double pj = cb[(RPQ + rowk) * DROW + 2 * (bcol[sl] + li16) + ck];
+        const double bw = wv[ks] * fj;                  // w phi_j
+        const double bh = omv[ks] * fj + wv[ks] * pj;   // w v phi_j + w psi_j
+        acc[sl][0] = mfma64(fi, bh, acc[sl][0]);
+        acc[sl][1] = mfma64(fi, bw, acc[sl][1]);
+        acc[sl][2] = mfma64(pi_, bw, acc[sl][2]);
+      }
+    }
+  }
+  // write the computed blocks (H, S) to the staged atom-pair blocks
+#pragma unroll
+  for (int sl = 0; sl < 4; ++sl) {
+    if (!act[sl]) continue;
+    const int cb = c0 + bcol[sl];
+    const int lj = cb + li16;
+    if (lj >= n) continue;
+    const SlotInfo sj = slot_of(d, f0, sbase, lj);
+    const int rb = r0 + brow[sl];
+    const bool upper = rb < cb;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int li = rb + d_row_f64(lk, r);
+      if (li < n) {
+        const SlotInfo si = slot_of(d, f0, sbase, li);
+        double vals[2];
+        vals[0] = acc[sl][0][r] + acc[sl][2][r];
+        vals[1] = acc[sl][1][r];
+        stage_store<0, 2>(staging, si, sj, li, lj, upper, vals);
+      }
+    }
+  }
+  if (!PERSIST) break;
+  pos = next_item(tickets, nw, order != nullptr, &s_pos);
+  }
+}
+
 // Batch-to-global sum for one pass: reduction entry r adds the staged blocks
 // of pair red_pair[r] in batch order, one after another onto the running
 // value (zero, or the stored value when a previous pass or ACCUMULATE left
@@ -808,7 +1016,7 @@ __global__ __launch_bounds__(NT, 2) void k_contract(DevPlan d, const WorkItem *w
 __global__ __launch_bounds__(256) void k_reduce(DevPlan d, int64_t r0, const int32_t *red_pair,
                                                 const uint8_t *red_first, const int64_t *red_inc_off,
                                                 const int64_t *inc_src, const double *staging, double *store,
-                                                int accumulate) {
+                                                int accumulate, int nq) {
   __shared__ int64_t s_src[256];
   const int64_t r = r0 + blockIdx.x;
   const int p = red_pair[r];
@@ -816,7 +1024,7 @@ __global__ __launch_bounds__(256) void k_reduce(DevPlan d, int64_t r0, const int
   const int64_t k0 = red_inc_off[r], k1 = red_inc_off[r + 1];
   const bool add = accumulate || !red_first[r];
   const int64_t po = d.pair_off[p];
-  const int m = 5 * blk;
+  const int m = nq * blk;  // parts 0 .. nq-1 of the staged blocks (the first nq of five)
   // each thread owns elements e = tid, tid + 256, ... (at most 4 at a time in registers)
   for (int e0 = 0; e0 < m; e0 += 4 * 256) {
     double sum[4];
@@ -868,10 +1076,10 @@ __global__ __launch_bounds__(256) void k_reduce(DevPlan d, int64_t r0, const int
 }
 
 // Pairs no batch touches are zero unless accumulating.
-__global__ void k_zero_pairs(DevPlan d, const int32_t *pairs, double *store) {
+__global__ void k_zero_pairs(DevPlan d, const int32_t *pairs, double *store, int nq) {
   const int p = pairs[blockIdx.x];
   const int64_t blk = (int64_t)d.pair_na[p] * d.pair_nb[p];
-  for (int64_t e = threadIdx.x; e < 5 * blk; e += blockDim.x) {
+  for (int64_t e = threadIdx.x; e < nq * blk; e += blockDim.x) {
     const int q = (int)(e / blk);
     store[q * d.store_len + d.pair_off[p] + (e - q * blk)] = 0.0;
   }
@@ -1279,7 +1487,7 @@ int launch_integrate(const q4c_plan *p, const double *v, int precision, uint32_t
     if (nt > 0) {
       {
         TimedLaunch tl_(p, Q4C_TIMER_TABULATE, s);
-        hipLaunchKernelGGL(k_panel, dim3((unsigned)nt), dim3(256), 0, s, p->dp, p->d_ptile, ps.t0, nt, panel);
+        hipLaunchKernelGGL(k_panel<false>, dim3((unsigned)nt), dim3(256), 0, s, p->dp, p->d_ptile, ps.t0, nt, panel);
       }
       if ((rc = check_launch("k_panel")) != Q4C_OK) return rc;
     }
@@ -1330,7 +1538,7 @@ int launch_integrate(const q4c_plan *p, const double *v, int precision, uint32_t
       {
         TimedLaunch tl_(p, Q4C_TIMER_REDUCE, s);
         hipLaunchKernelGGL(k_reduce, dim3((unsigned)nr), dim3(256), 0, s, p->dp, ps.r0, p->d_red_pair, p->d_red_first,
-                           p->d_red_inc_off, p->d_inc_src, p->d_staging, store, accumulate);
+                           p->d_red_inc_off, p->d_inc_src, p->d_staging, store, accumulate, 5);
       }
       if ((rc = check_launch("k_reduce")) != Q4C_OK) return rc;
     }
@@ -1339,7 +1547,7 @@ int launch_integrate(const q4c_plan *p, const double *v, int precision, uint32_t
     {
       TimedLaunch tl_(p, Q4C_TIMER_OTHER, s);
       hipLaunchKernelGGL(k_zero_pairs, dim3((unsigned)p->untouched_pairs.size()), dim3(256), 0, s, p->dp,
-                         p->d_untouched, store);
+                         p->d_untouched, store, 5);
     }
     if ((rc = check_launch("k_zero_pairs")) != Q4C_OK) return rc;
   }
@@ -1350,6 +1558,67 @@ int launch_integrate(const q4c_plan *p, const double *v, int precision, uint32_t
                          (flags & Q4C_ASSEMBLE_W) ? spin_w : nullptr, (flags & Q4C_ASSEMBLE_V) ? spin_v : nullptr);
     }
     if ((rc = check_launch("k_spinor")) != Q4C_OK) return rc;
+  }
+  return Q4C_OK;
+}
+
+int launch_integrate_hs(const q4c_plan *p, const double *v, uint32_t flags, double *hs, hipStream_t s) {
+  const int accumulate = (flags & Q4C_ACCUMULATE) ? 1 : 0;
+  int rc;
+  {
+    TimedLaunch tl_(p, Q4C_TIMER_OTHER, s);
+    const unsigned nb = (unsigned)std::min<int64_t>((p->n_active + 16 + 255) / 256, 65535);
+    hipLaunchKernelGGL(k_om, dim3(nb), dim3(256), 0, s, p->dp, v, p->d_om, p->d_chunks);
+  }
+  if ((rc = check_launch("k_om")) != Q4C_OK) return rc;
+  const LaunchCfg cfg = p->cfg_hs;
+  const int32_t *order = cfg.order ? p->d_order : nullptr;
+  if (cfg.persistent > 0) {
+    hipLaunchKernelGGL(k_zero_u32, dim3(8), dim3(256), 0, s, p->d_tickets,
+                       (int64_t)p->passes.size() * kTicketsPerLaunch);
+    if ((rc = check_launch("k_zero_u32")) != Q4C_OK) return rc;
+  }
+  for (size_t ip = 0; ip < p->passes.size(); ++ip) {
+    const Pass &ps = p->passes[ip];
+    const int64_t nw = ps.w1 - ps.w0, nt = ps.t1 - ps.t0, nr = ps.r1 - ps.r0;
+    unsigned *tickets = cfg.persistent > 0 ? p->d_tickets + ip * kTicketsPerLaunch : nullptr;
+    const unsigned grid = (unsigned)(cfg.persistent > 0 ? std::min<int64_t>(cfg.persistent, nw) : nw);
+    double *panel = p->d_staging + ps.staging_len + ps.partial_len;
+    if (nt > 0) {
+      {
+        TimedLaunch tl_(p, Q4C_TIMER_TABULATE, s);
+        hipLaunchKernelGGL(k_panel<true>, dim3((unsigned)nt), dim3(256), 0, s, p->dp, p->d_ptile, ps.t0, nt, panel);
+      }
+      if ((rc = check_launch("k_panel<hs>")) != Q4C_OK) return rc;
+    }
+    if (nw > 0) {
+      {
+        TimedLaunch tl_(p, Q4C_TIMER_CONTRACT, s);
+        if (tickets)
+          hipLaunchKernelGGL(k_contract_hs<true>, dim3(grid), dim3(NT), 0, s, p->dp, p->d_work, order, ps.w0, nw,
+                             p->d_om, panel, p->d_staging, tickets);
+        else
+          hipLaunchKernelGGL(k_contract_hs<false>, dim3(grid), dim3(NT), 0, s, p->dp, p->d_work, order, ps.w0, nw,
+                             p->d_om, panel, p->d_staging, tickets);
+      }
+      if ((rc = check_launch("k_contract_hs")) != Q4C_OK) return rc;
+    }
+    if (nr > 0) {
+      {
+        TimedLaunch tl_(p, Q4C_TIMER_REDUCE, s);
+        hipLaunchKernelGGL(k_reduce, dim3((unsigned)nr), dim3(256), 0, s, p->dp, ps.r0, p->d_red_pair, p->d_red_first,
+                           p->d_red_inc_off, p->d_inc_src, p->d_staging, hs, accumulate, 2);
+      }
+      if ((rc = check_launch("k_reduce")) != Q4C_OK) return rc;
+    }
+  }
+  if (!accumulate && !p->untouched_pairs.empty()) {
+    {
+      TimedLaunch tl_(p, Q4C_TIMER_OTHER, s);
+      hipLaunchKernelGGL(k_zero_pairs, dim3((unsigned)p->untouched_pairs.size()), dim3(256), 0, s, p->dp,
+                         p->d_untouched, hs, 2);
+    }
+    if ((rc = check_launch("k_zero_pairs")) != Q4C_OK) return rc;
   }
   return Q4C_OK;
 }
@@ -1383,7 +1652,7 @@ int launch_density(const q4c_plan *p, const double *coef, uint32_t terms, int we
     if (nt > 0) {
       {
         TimedLaunch tl_(p, Q4C_TIMER_TABULATE, s);
-        hipLaunchKernelGGL(k_panel, dim3((unsigned)nt), dim3(256), 0, s, p->dp, p->d_ptile, ps.t0, nt, panel);
+        hipLaunchKernelGGL(k_panel<false>, dim3((unsigned)nt), dim3(256), 0, s, p->dp, p->d_ptile, ps.t0, nt, panel);
       }
       if ((rc = check_launch("k_panel")) != Q4C_OK) return rc;
     }

@@ -195,7 +195,7 @@ int validate(const q4c_basis *b, const q4c_grid *g) {
   }
   for (int s = 0; s < b->n_shells; ++s) {
     if (b->shell_l[s] < 0) return fail(Q4C_EINVAL, "negative angular momentum");
-    if (b->shell_l[s] > 3) return fail(Q4C_EUNSUPPORTED, "angular momentum above 3 (f) is not supported");
+    if (b->shell_l[s] > 4) return fail(Q4C_EUNSUPPORTED, "angular momentum above 4 (g) is not supported");
     if (!(b->shell_rcut[s] > 0.0) || !std::isfinite(b->shell_rcut[s])) return fail(Q4C_EINVAL, "bad shell cutoff");
     if (b->shell_nint[s] < 1) return fail(Q4C_EINVAL, "shell_nint must be >= 1");
     if (b->shell_coef_off[s] < 0 || b->shell_coef_off[s] + 4 * (int64_t)b->shell_nint[s] > b->n_coef)
@@ -278,7 +278,7 @@ int build_host(q4c_plan *p, const q4c_basis *b, const q4c_grid *g, const std::ve
       p->atom_rcut[a] = std::max(p->atom_rcut[a], p->shell_rcut[s]);
       for (int m = -p->shell_l[s]; m <= p->shell_l[s]; ++m) {
         p->fn_atom.push_back(a);
-        p->fn_shlm.push_back(s * 16 + p->shell_l[s] * p->shell_l[s] + p->shell_l[s] + m);
+        p->fn_shlm.push_back(s * 32 + p->shell_l[s] * p->shell_l[s] + p->shell_l[s] + m);
       }
     }
     p->atom_fn_off[a + 1] = p->atom_fn_off[a] + nf;
@@ -535,6 +535,7 @@ int build_host(q4c_plan *p, const q4c_basis *b, const q4c_grid *g, const std::ve
     p->max_batch_points = std::max<int64_t>(p->max_batch_points, g1 - g0);
     p->max_batch_fn = std::max<int64_t>(p->max_batch_fn, nb_fn);
     p->flops_alg += 10.0 * (double)(g1 - g0) * (double)nb_fn * (double)nb_fn;
+    p->flops_alg_hs += 3.0 * (double)(g1 - g0) * (double)nb_fn * (double)nb_fn;
   }
   close_pass(p->n_batches);
   p->red_inc_off.push_back((int64_t)p->inc_src.size());
@@ -886,6 +887,7 @@ int q4c_plan_info(const q4c_plan *p, q4c_info *info) {
   info->n_passes = (int64_t)p->passes.size();
   info->device_bytes = p->device_bytes;
   info->flops_alg = p->flops_alg;
+  info->flops_alg_hs = p->flops_alg_hs;
   return Q4C_OK;
 }
 
@@ -1026,6 +1028,78 @@ int q4c_integrate_H(const q4c_plan *p, const double *v_dev, int32_t precision, u
   return q4c::launch_integrate(p, v_dev, precision, flags, store_dev, spin_w_dev, spin_v_dev, (hipStream_t)stream);
 }
 
+int q4c_plan_set_ket_potential(q4c_plan *p, const int64_t *shell_u_off, int64_t n_u, const double *u_coef) {
+  if (!p) return fail(Q4C_EINVAL, "NULL plan");
+  int rc = Q4C_OK;
+  if (n_u < 0) return fail(Q4C_EINVAL, "negative table length");
+  if (p->n_shells > 0 && (!shell_u_off || !u_coef)) return fail(Q4C_EINVAL, "NULL ket-potential table");
+  for (int s = 0; s < p->n_shells; ++s) {
+    if (shell_u_off[s] < 0 || shell_u_off[s] % 4 != 0 || shell_u_off[s] + 4 * (int64_t)p->shell_nint[s] > n_u)
+      return fail(Q4C_EINVAL, "ket-potential table outside u_coef (or offset not a multiple of 4)");
+  }
+  if (n_u > 0 && !finite_all(u_coef, n_u)) return fail(Q4C_EINVAL, "non-finite ket-potential coefficient");
+  // the same scaling as the radial tables: (c0, c1/h, c2/h^2, c3/h^3) per interval
+  std::vector<double> scaled;
+  std::vector<int64_t> off(p->n_shells, 0);
+  std::vector<std::pair<std::pair<int64_t, int32_t>, std::pair<double, int64_t>>> seen;
+  for (int s = 0; s < p->n_shells; ++s) {
+    int64_t found = -1;
+    for (auto &e : seen)
+      if (e.first.first == shell_u_off[s] && e.first.second == p->shell_nint[s] && e.second.first == p->shell_rcut[s]) {
+        found = e.second.second;
+        break;
+      }
+    if (found < 0) {
+      found = (int64_t)scaled.size();
+      const int n = p->shell_nint[s];
+      const double rc = p->shell_rcut[s];
+      for (int j = 0; j < n; ++j) {
+        const double h = rc * (2.0 * j + 1.0) / ((double)n * (double)n);
+        const double *c = u_coef + shell_u_off[s] + 4 * (int64_t)j;
+        scaled.push_back(c[0]);
+        scaled.push_back(c[1] / h);
+        scaled.push_back(c[2] / (h * h));
+        scaled.push_back(c[3] / (h * h * h));
+      }
+      seen.push_back({{shell_u_off[s], p->shell_nint[s]}, {p->shell_rcut[s], found}});
+    }
+    off[s] = found;
+  }
+  p->ucoef_scaled.swap(scaled);
+  p->shell_us_off.swap(off);
+  if (!p->on_device) return Q4C_OK;  // host-only plan: validated and kept
+  // new device copies; earlier ones stay allocated until the plan is destroyed
+  // (captured graphs may still hold their addresses)
+  if ((rc = check_plan_dev(p)) != Q4C_OK) return rc;
+  double *d_u = nullptr;
+  int64_t *d_off = nullptr;
+  if ((rc = upload(p, p->ucoef_scaled, &d_u)) != Q4C_OK) return rc;
+  if ((rc = upload(p, p->shell_us_off, &d_off)) != Q4C_OK) return rc;
+  p->d_ucoef = d_u;
+  p->d_shell_us_off = d_off;
+  p->dp.ucoef = d_u;
+  p->dp.shell_u_off = d_off;
+  drop_graphs(p);
+  return Q4C_OK;
+}
+
+int q4c_integrate_HS(const q4c_plan *p, const double *v_dev, uint32_t flags, double *hs_dev, void *stream) {
+  if (!p) return fail(Q4C_EINVAL, "NULL plan");
+  if (flags & ~(uint32_t)(Q4C_ACCUMULATE | Q4C_CHECK_FINITE)) return fail(Q4C_EINVAL, "unknown flag");
+  if (p->n_points > 0 && !v_dev) return fail(Q4C_EINVAL, "NULL potential");
+  if (p->store_len > 0 && !hs_dev) return fail(Q4C_EINVAL, "NULL H/S output");
+  int rc = check_plan_dev(p);
+  if (rc != Q4C_OK) return rc;
+  if (p->n_shells > 0 && !p->d_ucoef) return fail(Q4C_EINVAL, "no ket potential set (q4c_plan_set_ket_potential)");
+  if (flags & Q4C_CHECK_FINITE) {
+    bool ok = true;
+    rc = q4c::launch_check_finite(p, v_dev, (hipStream_t)stream, &ok);
+    if (rc != Q4C_OK) return rc;
+    if (!ok) return fail(Q4C_ENONFINITE, "potential contains NaN or Inf");
+  }
+  return q4c::launch_integrate_hs(p, v_dev, flags & ~(uint32_t)Q4C_CHECK_FINITE, hs_dev, (hipStream_t)stream);
+}
+
 int density_on_grid(const q4c_plan *p, const double *coef_dev, uint32_t terms, int32_t weight_mode, double *out_dev,
                     void *stream) {
   if (!p) return fail(Q4C_EINVAL, "NULL plan");
@@ -1052,11 +1126,14 @@ int q4c_plan_set_graphs(q4c_plan *p, int enable) {
 int q4c_plan_set_launch(q4c_plan *p, int32_t kernel, int32_t order, int32_t persistent) {
   int rc = check_plan_dev(p);
   if (rc != Q4C_OK) return rc;
-  if (kernel != Q4C_KERNEL_CONTRACT && kernel != Q4C_KERNEL_DENSITY) return fail(Q4C_EINVAL, "unknown kernel");
+  if (kernel != Q4C_KERNEL_CONTRACT && kernel != Q4C_KERNEL_DENSITY && kernel != Q4C_KERNEL_HS)
+    return fail(Q4C_EINVAL, "unknown kernel");
   if (order != 0 && order != 1) return fail(Q4C_EINVAL, "order must be 0 or 1");
   if (persistent < 0 || persistent > 65535) return fail(Q4C_EINVAL, "persistent workgroups must be in 0..65535");
   drop_graphs(p);
-  q4c::LaunchCfg &c = kernel == Q4C_KERNEL_CONTRACT ? p->cfg_contract : p->cfg_density;
+  q4c::LaunchCfg &c = kernel == Q4C_KERNEL_CONTRACT ? p->cfg_contract
+                      : kernel == Q4C_KERNEL_DENSITY ? p->cfg_density
+                                                     : p->cfg_hs;
   c.order = order;
   c.persistent = persistent;
   return Q4C_OK;
@@ -1064,8 +1141,11 @@ int q4c_plan_set_launch(q4c_plan *p, int32_t kernel, int32_t order, int32_t pers
 
 int q4c_plan_get_launch(const q4c_plan *p, int32_t kernel, int32_t *order, int32_t *persistent) {
   if (!p || !order || !persistent) return fail(Q4C_EINVAL, "NULL argument");
-  if (kernel != Q4C_KERNEL_CONTRACT && kernel != Q4C_KERNEL_DENSITY) return fail(Q4C_EINVAL, "unknown kernel");
-  const q4c::LaunchCfg &c = kernel == Q4C_KERNEL_CONTRACT ? p->cfg_contract : p->cfg_density;
+  if (kernel != Q4C_KERNEL_CONTRACT && kernel != Q4C_KERNEL_DENSITY && kernel != Q4C_KERNEL_HS)
+    return fail(Q4C_EINVAL, "unknown kernel");
+  const q4c::LaunchCfg &c = kernel == Q4C_KERNEL_CONTRACT ? p->cfg_contract
+                            : kernel == Q4C_KERNEL_DENSITY ? p->cfg_density
+                                                           : p->cfg_hs;
   *order = c.order;
   *persistent = c.persistent;
   return Q4C_OK;

@@ -87,7 +87,7 @@ def test_unsupported_l_and_malformed_basis():
     wl = W.config_small(nrad=10, nang=26)
     bad = W.Workload(**{**wl.__dict__})
     bad.shell_l = wl.shell_l.copy()
-    bad.shell_l[0] = 4
+    bad.shell_l[0] = 5
     with pytest.raises(q.Q4CError) as e:
         _host_plan(q, bad)
     assert e.value.status == q.Q4C_EUNSUPPORTED
@@ -209,3 +209,32 @@ def test_batched_plan_validation():
     assert lib.q4c_plan_set_launch(p.handle, 0, 0, 0) == q.Q4C_ENODEV
     assert lib.q4c_plan_set_graphs(p.handle, 1) == q.Q4C_ENODEV
     assert lib.q4c_plan_autotune(p.handle, None, 0, None, None, None, 1, None, 0, None, None) == q.Q4C_ENODEV
+
+
+def test_ket_potential_validation_and_hs_flop_count():
+    """q4c_plan_set_ket_potential checks its tables; q4c_integrate_HS needs a
+    device plan; flops_alg_hs = sum_B 3 P_B n_B^2 over the plan's batches."""
+    import dataclasses
+    q, lib = _lib()
+    wl = W.with_ket(W.config_small(nrad=10, nang=26), 7001)
+    p = _host_plan(q, wl)
+    p.set_ket_potential(wl)
+    for bad in (dataclasses.replace(wl, shell_u_off=wl.shell_u_off + 2),
+                dataclasses.replace(wl, shell_u_off=wl.shell_u_off + wl.u_coef.size)):
+        with pytest.raises(q.Q4CError) as e:
+            p.set_ket_potential(bad)
+        assert e.value.status == q.Q4C_EINVAL
+    nan = wl.u_coef.copy()
+    nan[5] = np.nan
+    with pytest.raises(q.Q4CError) as e:
+        p.set_ket_potential(dataclasses.replace(wl, u_coef=nan))
+    assert e.value.status == q.Q4C_EINVAL
+    assert lib.q4c_plan_set_ket_potential(p.handle, None, 0, None) == q.Q4C_EINVAL
+    rc = lib.q4c_integrate_HS(p.handle, ctypes.c_void_p(1), 0, ctypes.c_void_p(1), None)
+    assert rc == q.Q4C_ENODEV
+    assert lib.q4c_integrate_HS(p.handle, ctypes.c_void_p(1), 1 << 20, ctypes.c_void_p(1), None) == q.Q4C_EINVAL
+    pt_off, _, fn_off, _ = p.batches()
+    P = np.diff(pt_off).astype(np.float64)
+    nf = np.diff(fn_off).astype(np.float64)
+    assert p.info["flops_alg_hs"] == pytest.approx(float(np.sum(3.0 * P * nf * nf)), rel=1e-15)
+    assert p.info["flops_alg"] == pytest.approx(float(np.sum(10.0 * P * nf * nf)), rel=1e-15)

@@ -32,14 +32,31 @@ PREC = {"f64": 0, "split": 1, "f32": 2}
 # HBM bytes per k_contract launch on the default cluster workload, from two
 # rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE), each scaled by what the same
 # counter reads for an elementwise copy of 1 GiB (read x1.9999, write x1.0000).
-# Keyed by the SHA-256 of the kernel source the counters were taken on, the
-# precision, the atom count and the work order of the launch (batch order keeps
-# a batch's tiles on one L2, the cost-sorted queue does not): any change to the
-# kernels makes the figure stale, and it is then reported as null.
+# Keyed by the SHA-256 of the kernel sources the counters were taken on
+# (q4c_kernels.hip and q4c_device.h), the precision, the atom count and the
+# work order of the launch (batch order keeps a batch's tiles on one L2, the
+# cost-sorted queue does not): any change to those sources makes the figure
+# stale, and it is then reported as null.
 TRAFFIC = {
-    ("1b64df8139b86ae9ff35be6f962f72eabe94ecd77ea0d49ebdd82d2f7918a86b", "f64", 120, 0): 11.039e9 + 3.981e9,
-    ("1b64df8139b86ae9ff35be6f962f72eabe94ecd77ea0d49ebdd82d2f7918a86b", "f64", 120, 1): 20.092e9 + 4.355e9,
+    ("e6a1bc96d20c0bc4450f6897d092ebdc0a7ebbc55b3094c6189e33a90d380949", "f64", 120, 0): 11.117e9 + 3.974e9,
+    ("e6a1bc96d20c0bc4450f6897d092ebdc0a7ebbc55b3094c6189e33a90d380949", "f64", 120, 1): 19.788e9 + 4.381e9,
 }
+
+# The same for k_contract_hs (q4c_integrate_HS) per component and work order,
+# keyed by the SHA-256 of q4c_hs_kernels.hip and q4c_device.h.
+HS_TRAFFIC = {
+    ("b6e47b5a7ab3a0eee2d17982f078df9459625df7cb636b35ee354ffcc8b483c8", "large", 120, 0): 3.156e9 + 1.534e9,
+    ("b6e47b5a7ab3a0eee2d17982f078df9459625df7cb636b35ee354ffcc8b483c8", "small", 120, 0): 3.373e9 + 3.610e9,
+}
+
+
+def source_sha(*names):
+    import hashlib
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_2608_00773_amd", "csrc", n), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def parse():
@@ -55,15 +72,21 @@ def parse():
                     help="autotune but launch eagerly (for per-dispatch counter collection)")
     ap.add_argument("--cpu-sample", type=float, default=0.05, help="fraction of grid points for the oracle timing")
     ap.add_argument("--n-atoms", type=int, default=120)
-    ap.add_argument("--mode", choices=["full", "step", "forward", "adjoint"], default="full",
+    ap.add_argument("--mode", choices=["full", "step", "forward", "adjoint", "hs"], default="full",
                     help="step/forward/adjoint: run only the whole step or that one call `steps` times "
-                         "(for profiler runs) and print its time")
+                         "(for profiler runs) and print its time; hs: only the H/S leg")
     ap.add_argument("--workload", choices=["cluster", "slab", "pepi", "molecules"], default="cluster",
                     help="molecules: 64 independent molecules (8..80 atoms), one batched plan (autotuned launch "
                          "shapes, HIP graph replay) against 64 sequential per-molecule plans; prints its own line")
     ap.add_argument("--contract-order", type=int, choices=[0, 1], default=None,
                     help="after autotuning, keep the contraction's work order fixed (0: batch order, "
                          "1: cost-sorted global queue) with the best persistent size timed for it")
+    ap.add_argument("--no-hs", action="store_true",
+                    help="skip the H/S leg (the Q4C ket-dependent integrand of both components)")
+    ap.add_argument("--hs-component", choices=["both", "large", "small"], default="both",
+                    help="--mode hs: run one component only")
+    ap.add_argument("--hs-shape", default=None,
+                    help="--mode hs: fixed k_contract_hs launch shape 'order,persistent' instead of the best of three")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before the work, run one elementwise copy of this many MiB (read once, written once): "
                          "the reference dispatch for scaling HBM byte counters")
@@ -99,6 +122,83 @@ def cpu_baseline(wl, frac: float, seed: int = 6002):
     return {"value": n_act / dt, "unit": "points/s", "cores": 1, "kind": "oracle",
             "sample": "%d of %d grid points (%d active, seed %d), all %d atom pairs, %.1f s" %
                       (idx.size, wl.n_points, n_act, seed, len(pairs), dt)}
+
+
+def bench_hs(wl, timed, steps: int, cpu_frac: float, with_cpu: bool, components=("large", "small"),
+             shapes=((0, 0), (0, 1024), (1, 1024))):
+    """H and S of both components (q4c_integrate_HS: the Q4C integrand of Eq. 19
+    in the scalar form of Eq. 29) on the same grid and potential: the large
+    component is the workload's basis, the small component its l~ = l +- 1
+    partners (seeded radials); seeded ket potentials eps + Z erf(r/0.5)/r.
+    Per component: best of three launch shapes, time per call, and the
+    k_contract_hs roofline from HIP events (algorithmic 3 P n^2 flops per batch)."""
+    import numpy as np
+    import torch
+    import paper_2608_00773_amd as q
+    import workload as W
+    dev = torch.device("cuda:0")
+    hsha = source_sha("q4c_hs_kernels.hip", "q4c_device.h")
+    t0 = time.perf_counter()
+    wl_l = W.with_ket(wl, 7101)
+    wl_s = W.small_component(wl_l, 7102)
+    out = {"workload_gen_s": time.perf_counter() - t0}
+    for name, w in (("large", wl_l), ("small", wl_s)):
+        if name not in components:
+            continue
+        t0 = time.perf_counter()
+        plan = q.Plan(w)
+        plan.set_ket_potential(w)
+        t_plan = time.perf_counter() - t0
+        info = plan.info
+        v = torch.from_numpy(w.v).to(dev)
+        hs = q.new_hs(plan, dev)
+        call = lambda: q.q4c_integrate_HS(plan, v, 0, hs)
+        tune = []
+        for shape in shapes:
+            plan.set_launch(q.KERNEL_HS, *shape)
+            call()
+            tune.append((shape, timed(call, 3)))
+        best = min(tune, key=lambda t: t[1])[0]
+        plan.set_launch(q.KERNEL_HS, *best)
+        call()
+        ms = timed(call, steps)
+        plan.profile(True)
+        for _ in range(steps):
+            call()
+        tim = plan.timers()
+        plan.profile(False)
+        nc = max(tim["contract"][1], 1)
+        t_c = tim["contract"][0] / nc * 1e-3
+        per_call = tim["contract"][1] / steps
+        achieved = info["flops_alg_hs"] / per_call / t_c
+        out[name] = {
+            "n_fn": info["n_fn"], "max_batch_fn": info["max_batch_fn"], "store_len": info["store_len"],
+            "ms": ms, "points_per_s": info["n_active"] / (ms * 1e-3), "plan_s": t_plan,
+            "flops_alg": info["flops_alg_hs"],
+            "launch": {"order": best[0], "persistent": best[1], "tune_ms": [[list(s_), t] for s_, t in tune]},
+            "kernels_ms_per_call": {k: v_[0] / steps for k, v_ in tim.items() if v_[1]},
+            "roofline": {"kernel": "k_contract_hs", "bound": "mfma", "achieved": achieved / 1e12,
+                         "peak": PEAK_F64 / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_F64,
+                         "traffic": HS_TRAFFIC.get((hsha, name, int(wl.n_atoms), best[0])),
+                         "avg_launch_ms": t_c * 1e3, "launches_per_call": per_call},
+        }
+        log("H/S %s component: %d functions, %.3f ms per call, k_contract_hs %.1f%% of FP64 peak" %
+            (name, info["n_fn"], ms, 100 * achieved / PEAK_F64))
+        del hs, plan
+    if with_cpu:
+        import oracle
+        rng = np.random.default_rng(6102)
+        idx = np.sort(rng.choice(wl.n_points, size=max(1, int(cpu_frac * wl.n_points)), replace=False))
+        sub = wl_l.subset_points(idx)
+        pairs = W.atom_pairs(wl_l)
+        oracle.build()
+        t0 = time.perf_counter()
+        oracle.pair_blocks_hs(sub, pairs)
+        dt = time.perf_counter() - t0
+        out["cpu_oracle_large"] = {"value": idx.size / dt, "unit": "input points/s", "cores": 1, "kind": "oracle",
+                                   "sample": "%d of %d grid points (seed 6102), all %d atom pairs, %.1f s" %
+                                             (idx.size, wl.n_points, len(pairs), dt)}
+    return out
 
 
 def log(msg):
@@ -241,6 +341,30 @@ def main():
     t_gen = time.perf_counter() - t0
     print("[bench] workload %s: %d atoms, %d points (%.1f s)" % (a.workload, wl.n_atoms, wl.n_points, t_gen),
           file=sys.stderr, flush=True)
+    if a.mode == "hs":
+        def timed_hs(fn, k):
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(k):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / k
+        if a.calib_copy_mib:
+            n = a.calib_copy_mib * (1 << 20) // 8
+            src = torch.ones(n, dtype=torch.float64, device="cuda")
+            dst = torch.empty_like(src)
+            torch.mul(src, 1.0, out=dst)
+            torch.cuda.synchronize()
+            del src, dst
+        comps = ("large", "small") if a.hs_component == "both" else (a.hs_component,)
+        kw = {}
+        if a.hs_shape:
+            kw["shapes"] = (tuple(int(t) for t in a.hs_shape.split(",")),)
+        print(json.dumps({"mode": "hs", "hs": bench_hs(wl, timed_hs, a.steps, 0.0, False, comps, **kw)}),
+              flush=True)
+        return
     t0 = time.perf_counter()
     plan = q.Plan(wl)
     t_plan = time.perf_counter() - t0
@@ -341,9 +465,7 @@ def main():
     err = {n: [float(torch.max(torch.abs(outs[n][k] - outs["f64"][k]))) for k in range(5)] for n in outs}
     ms_adj = timed(lambda: q.density_on_grid(plan, gbar, q.TERM_ALL, 1, grad), max(3, a.steps // 4))
 
-    import hashlib
-    with open(os.path.join(ROOT, "paper_2608_00773_amd", "csrc", "q4c_kernels.hip"), "rb") as fh:
-        ksha = hashlib.sha256(fh.read()).hexdigest()
+    ksha = source_sha("q4c_kernels.hip", "q4c_device.h")
     c_order = plan.get_launch(q.KERNEL_CONTRACT)[0]
     traffic = TRAFFIC.get((ksha, a.precision, a.n_atoms, c_order)) if a.workload == "cluster" else None
 
@@ -393,6 +515,8 @@ def main():
         "workload_gen_s": t_gen,
         "wall_timed_s": wall,
     }
+    if not a.no_hs and a.workload == "cluster":
+        res["hs"] = bench_hs(wl, timed, a.steps, 0.2 * a.cpu_sample, not a.no_cpu_baseline)
     if not a.no_cpu_baseline and a.workload == "cluster":
         res["cpu_baseline"] = cpu_baseline(wl, a.cpu_sample)
     print(json.dumps(res), flush=True)

@@ -1,0 +1,145 @@
+// The contraction of q4c_integrate_HS: H and S of one component, the Q4C
+// integrand of Eq. 19 in the scalar form of Eq. 29, symmetrised.  The panel
+// tabulation, batch sums and launches around it are in q4c_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "q4c_internal.h"
+#include "q4c_device.h"
+
+namespace q4c {
+namespace {
+
+// H and S of one component (the Q4C integrand of Eq. 19 in the scalar form
+// of Eq. 29, symmetrised), from panels of phi and psi = u phi / 2:
+//   H = Phi^T diag(w) (v Phi + Psi) + Psi^T diag(w) Phi,   S = Phi^T diag(w) Phi
+// i.e. per 16 x 16 block and K step of 4 points three FP64 MFMAs: the row
+// operands phi_i, psi_i against the column operands w v phi_j + w psi_j and
+// w phi_j (shared by the psi_i phi_j part of H and by S).  Same tiles, wave
+// slots and staging as the forward contraction; chunks of 16 points in two
+// LDS buffers (two components), the next chunk's DMA and weights in flight
+// while this one is multiplied.
+template <bool PERSIST>
+__global__ __launch_bounds__(NT, 2) void k_contract_hs(DevPlan d, const WorkItem *work, const int32_t *order,
+                                                       int64_t w0, int64_t nw, const double *om,
+                                                       const double *panel, double *staging, unsigned *tickets) {
+  constexpr int CH = 16, RPQ = CH / 2, NQ = 2;
+  constexpr int BUFD = NQ * RPQ * DROW;  // doubles per chunk image
+  __shared__ double sa[2 * BUFD], sb[2 * BUFD];
+  __shared__ int64_t s_pos;
+  int64_t pos = PERSIST ? next_item(tickets, nw, order != nullptr, &s_pos)
+                        : (order ? (int64_t)blockIdx.x : xcd_map(blockIdx.x, nw));
+  while (!PERSIST || pos < nw) {
+  const int64_t wi = w0 + (order ? order[w0 + pos] : pos);
+  const WorkItem it = work[wi];
+  const int b = it.batch;
+  const int g0 = d.batch_pt_off[b], P = d.batch_pt_off[b + 1] - g0;
+  const int f0 = d.batch_fn_off[b], n = d.batch_fn_off[b + 1] - f0;
+  const int sbase = d.batch_slot_off[b];
+  const int r0 = it.ti * T, c0 = it.tj * T;
+  const int Pp = (int)pad16(P), np = (int)pad16(n);
+  const double *pb = panel + d.panel_off[b];
+  const int64_t plane = (int64_t)Pp * np;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int li16 = lane & 15, lk = lane >> 4;
+  int brow[4], bcol[4];
+  bool act[4];
+  wave_blocks(r0, c0, n, wave, brow, bcol, act);
+  dbl4 acc[4][3];  // H (v phi + psi part), S, H (psi phi part)
+#pragma unroll
+  for (int sl = 0; sl < 4; ++sl)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) acc[sl][q] = dbl4{0.0, 0.0, 0.0, 0.0};
+  // weights at points 4 ks + lk of the next chunk: w v and w
+  double omn[CH / 4], wn[CH / 4];
+  auto load_w = [&](int k) {
+#pragma unroll
+    for (int ks = 0; ks < CH / 4; ++ks) {
+      const int pt = k + 4 * ks + lk;
+      omn[ks] = pt < P ? om[g0 + pt] : 0.0;
+      wn[ks] = pt < P ? d.pw[g0 + pt] : 0.0;
+    }
+  };
+  load_w(0);
+  dma_chunk<NT, CH, T, DROW, NQ>(pb, plane, np, r0, 0, sa);
+  dma_chunk<NT, CH, T, DROW, NQ>(pb, plane, np, c0, 0, sb);
+  for (int k0 = 0; k0 < Pp; k0 += CH) {
+    const int bo = ((k0 / CH) & 1) * BUFD;
+    double omv[CH / 4], wv[CH / 4];
+    __builtin_amdgcn_s_waitcnt(0);  // this thread's loads of this chunk have landed
+    __syncthreads();                // ... everyone's; the previous chunk is consumed
+#pragma unroll
+    for (int ks = 0; ks < CH / 4; ++ks) {
+      omv[ks] = omn[ks];
+      wv[ks] = wn[ks];
+    }
+    if (k0 + CH < Pp) {
+      const int nbo = BUFD - bo;
+      load_w(k0 + CH);
+      dma_chunk<NT, CH, T, DROW, NQ>(pb, plane, np, r0, (k0 + CH) >> 2, sa + nbo);
+      dma_chunk<NT, CH, T, DROW, NQ>(pb, plane, np, c0, (k0 + CH) >> 2, sb + nbo);
+    }
+    const double *ca = sa + bo, *cb = sb + bo;
+#pragma unroll
+    for (int ks = 0; ks < CH / 4; ++ks) {
+      const int rowk = 2 * ks + (lk >> 1), ck = lk & 1;
+#pragma unroll
+      for (int sl = 0; sl < 4; ++sl) {
+        if (!act[sl]) continue;  // wave-uniform
+        const double fi = ca[rowk * DROW + 2 * (brow[sl] + li16) + ck];
+        const double pi_ = ca[(RPQ + rowk) * DROW + 2 * (brow[sl] + li16) + ck];
+        const double fj = cb[rowk * DROW + 2 * (bcol[sl] + li16) + ck];
+        const double pj = cb[(RPQ + rowk) * DROW + 2 * (bcol[sl] + li16) + ck];
+        const double bw = wv[ks] * fj;                  // w phi_j
+        const double bh = omv[ks] * fj + wv[ks] * pj;   // w v phi_j + w psi_j
+        acc[sl][0] = mfma64(fi, bh, acc[sl][0]);
+        acc[sl][1] = mfma64(fi, bw, acc[sl][1]);
+        acc[sl][2] = mfma64(pi_, bw, acc[sl][2]);
+      }
+    }
+  }
+  // write the computed blocks (H, S) to the staged atom-pair blocks
+#pragma unroll
+  for (int sl = 0; sl < 4; ++sl) {
+    if (!act[sl]) continue;
+    const int cb = c0 + bcol[sl];
+    const int lj = cb + li16;
+    if (lj >= n) continue;
+    const SlotInfo sj = slot_of(d, f0, sbase, lj);
+    const int rb = r0 + brow[sl];
+    const bool upper = rb < cb;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int li = rb + d_row_f64(lk, r);
+      if (li < n) {
+        const SlotInfo si = slot_of(d, f0, sbase, li);
+        double vals[2];
+        vals[0] = acc[sl][0][r] + acc[sl][2][r];
+        vals[1] = acc[sl][1][r];
+        stage_store<0, 2>(staging, si, sj, li, lj, upper, vals);
+      }
+    }
+  }
+  if (!PERSIST) break;
+  pos = next_item(tickets, nw, order != nullptr, &s_pos);
+  }
+}
+
+}  // namespace
+
+int launch_contract_hs(const q4c_plan *p, int64_t w0, int64_t nw, const int32_t *order, const double *panel,
+                       unsigned *tickets, unsigned grid, hipStream_t s) {
+  if (tickets)
+    hipLaunchKernelGGL(k_contract_hs<true>, dim3(grid), dim3(NT), 0, s, p->dp, p->d_work, order, w0, nw, p->d_om,
+                       panel, p->d_staging, tickets);
+  else
+    hipLaunchKernelGGL(k_contract_hs<false>, dim3(grid), dim3(NT), 0, s, p->dp, p->d_work, order, w0, nw, p->d_om,
+                       panel, p->d_staging, tickets);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "k_contract_hs");
+  return Q4C_OK;
+}
+
+}  // namespace q4c

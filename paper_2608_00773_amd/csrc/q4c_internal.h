@@ -207,6 +207,9 @@ int launch_integrate(const q4c_plan *p, const double *v, int precision, uint32_t
 int launch_density(const q4c_plan *p, const double *coef, uint32_t terms, int weight_mode, double *out,
                    hipStream_t s);
 int launch_integrate_hs(const q4c_plan *p, const double *v, uint32_t flags, double *hs, hipStream_t s);
+// k_contract_hs over work items [w0, w0 + nw) of a pass (q4c_hs_kernels.hip)
+int launch_contract_hs(const q4c_plan *p, int64_t w0, int64_t nw, const int32_t *order, const double *panel,
+                       unsigned *tickets, unsigned grid, hipStream_t s);
 int launch_coef_from_spinor(const q4c_plan *p, const double *spin_d, double *coef_out, hipStream_t s);
 int launch_check_finite(const q4c_plan *p, const double *v, hipStream_t s, bool *finite);
 

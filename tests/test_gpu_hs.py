@@ -194,3 +194,42 @@ def test_g_functions_tabulate_and_integrate_H(q, medium_sc):
     nfn = ws.atom_nfn()
     got = [st[:, po[p]:po[p + 1]].reshape(5, int(nfn[pairs[p, 0]]), int(nfn[pairs[p, 1]])) for p in sel]
     _compare(got, ref, sc)
+
+
+@pytest.mark.parametrize("component", ["large", "small"])
+def test_hs_fullsize_cluster_sampled_pairs(q, component):
+    """The 120-atom cluster (2,174,400 points; large component 1,860 functions,
+    small component 4,020 with g functions), in every launch shape the
+    benchmark chooses from: sampled pair blocks (heavy-heavy, heavy-light,
+    light-light, diagonal) against the oracle's whole-grid sums."""
+    import torch
+    wl = W.with_ket(W.config_cluster(), 7101)
+    if component == "small":
+        wl = W.small_component(wl, 7102)
+    plan = q.Plan(wl)
+    plan.set_ket_potential(wl)
+    v = torch.from_numpy(wl.v).cuda()
+    res = []
+    for shape in ((0, 0), (0, 1024), (1, 1024)):
+        plan.set_launch(q.KERNEL_HS, *shape)
+        hs = q.new_hs(plan)
+        q.q4c_integrate_HS(plan, v, 0, hs)
+        torch.cuda.synchronize()
+        res.append(hs.cpu().numpy())
+    assert all(np.array_equal(res[0], r) for r in res[1:])
+    pairs, po = plan.pairs()
+    heavy = wl.Z >= 21
+    a, b = pairs[:, 0], pairs[:, 1]
+    rng = np.random.default_rng(7041 if component == "large" else 7042)
+    sel = []
+    for g in ((a == b) & heavy[a], (a != b) & heavy[a] & heavy[b], (a != b) & (heavy[a] ^ heavy[b]),
+              (a != b) & ~heavy[a] & ~heavy[b]):
+        idx = np.nonzero(g)[0]
+        if idx.size:
+            sel.extend(rng.choice(idx, size=min(2, idx.size), replace=False).tolist())
+    sel = np.array(sorted(set(sel)))
+    print("%s component: %d functions, sampled pairs %s" % (component, wl.n_fn, sel.tolist()), flush=True)
+    ref, sc = oracle.pair_blocks_hs(wl, pairs[sel], with_abs=True)
+    nfn = wl.atom_nfn()
+    got = [res[0][:, po[p]:po[p + 1]].reshape(2, int(nfn[pairs[p, 0]]), int(nfn[pairs[p, 1]])) for p in sel]
+    _compare(got, ref, sc)

@@ -17,6 +17,7 @@ m = -l..l, columns = functions of B.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 from typing import List, Optional, Sequence
@@ -279,3 +280,132 @@ def loss_re_tr(pairs: np.ndarray, D_blocks: Sequence[np.ndarray], parts_blocks: 
         t = np.sum(np.conj(D) * H)  # = sum_IJ conj(D_IJ) H_IJ = sum_IJ D_JI H_IJ
         tot += np.real(t) * (1.0 if a == b else 2.0)
     return float(tot)
+
+
+# ---------------------------------------------------------------------------
+# Scalar -> spinor transformation (Sec. III A, Eq. 33; Eq. 10, 13, 14; App. A)
+# ---------------------------------------------------------------------------
+#
+# Spinor basis per large shell s (angular momentum l): kappa = -(l+1)
+# (j = l + 1/2) with m_j = -j..j, then, for l >= 1, kappa = l (j = l - 1/2);
+# 2 (2l+1) spinor functions per shell, m_j ascending.  Half-integers are
+# handled as twice their value (j2 = 2j, mj2 = 2 m_j).
+#
+# The small component of spinor (s, kappa, m_j) is the spin-angular function
+# Upsilon_{-kappa, m_j} (l~ = l + 1 for kappa < 0, l - 1 for kappa > 0) on the
+# small shell paired with (s, kappa); small shells follow the large shells in
+# the order l + 1, then l - 1 (as workload.small_component builds them).
+#
+# Complex harmonics: the Condon-Shortley ones that the coupling of App. A
+# assumes.  App. B's real harmonics already carry (-1)^m, so in their terms
+# Y~_l^m = (Y_l,|m| + i Y_l,-|m|)/sqrt2 for m > 0 and (-1)^m (Y_l,|m| -
+# i Y_l,-|m|)/sqrt2 for m < 0: Eq. 13 without its extra (-1)^m (applying both
+# factors would break (sigma.r) Upsilon_kappa = -Upsilon_-kappa).
+
+
+def complex_harmonic_coefs(l: int, m: int):
+    """Y~_l^m as a combination of App. B real harmonics: [(m', coefficient)]."""
+    if m == 0:
+        return [(0, 1.0 + 0j)]
+    s = 1.0 / math.sqrt(2.0)
+    if m > 0:
+        return [(m, s + 0j), (-m, 1j * s)]
+    sg = -1.0 if (m & 1) else 1.0
+    return [(-m, sg * s + 0j), (m, -1j * sg * s)]
+
+
+def cg_half(l: int, j2: int, mj2: int, spin: int) -> float:
+    """C_alpha (spin 0, m_s = +1/2) or C_beta (spin 1, m_s = -1/2) of Eq. 10 for
+    j = j2/2, m_j = mj2/2: with a = 2(j - l) = +-1,
+    C_alpha = a sqrt(l + a m_j + 1/2) / sqrt(2l + 1),
+    C_beta  = sqrt(l - a m_j + 1/2) / sqrt(2l + 1)."""
+    a = j2 - 2 * l
+    mj = 0.5 * mj2
+    if spin == 0:
+        return a * math.sqrt(max(l + a * mj + 0.5, 0.0)) / math.sqrt(2 * l + 1)
+    return math.sqrt(max(l - a * mj + 0.5, 0.0)) / math.sqrt(2 * l + 1)
+
+
+def spinor_labels(wl_large):
+    """Per atom: list of (large shell, l, kappa, mj2) in spinor order."""
+    out = []
+    for a in range(wl_large.n_atoms):
+        lab = []
+        for s in range(wl_large.atom_shell_off[a], wl_large.atom_shell_off[a + 1]):
+            l = int(wl_large.shell_l[s])
+            for kappa in ((-(l + 1), l) if l >= 1 else (-(l + 1),)):
+                j2 = 2 * abs(kappa) - 1
+                for mj2 in range(-j2, j2 + 1, 2):
+                    lab.append((s, l, kappa, mj2))
+        out.append(lab)
+    return out
+
+
+def _shell_fn_offsets(wl, a):
+    offs, f = [], 0
+    for s in range(wl.atom_shell_off[a], wl.atom_shell_off[a + 1]):
+        offs.append(f)
+        f += 2 * int(wl.shell_l[s]) + 1
+    return offs, f
+
+
+def spinor_G(wl_large, wl_small):
+    """Transformation matrices of Eq. 14 per atom: GL[a] complex[2, nL_a, NS_a]
+    and GS[a] complex[2, nS_a, NS_a] (spin, scalar function, spinor function),
+    NS_a = 2 nL_a.  G[sigma][t, mu] is the coefficient of scalar function t
+    with spin sigma in spinor function mu.  The i of the small component
+    (Eq. 12b) is left out: it cancels in every bra-ket of the same component."""
+    labels = spinor_labels(wl_large)
+    GL, GS = [], []
+    for a in range(wl_large.n_atoms):
+        offL, nL = _shell_fn_offsets(wl_large, a)
+        offS, nS = _shell_fn_offsets(wl_small, a)
+        lab = labels[a]
+        gl = np.zeros((2, nL, len(lab)), dtype=np.complex128)
+        gs = np.zeros((2, nS, len(lab)), dtype=np.complex128)
+        s0 = wl_large.atom_shell_off[a]
+        # small shell index (atom-local) paired with (large shell, kappa)
+        small_of, k = {}, 0
+        for s in range(s0, wl_large.atom_shell_off[a + 1]):
+            l = int(wl_large.shell_l[s])
+            small_of[(s, -(l + 1))] = k
+            k += 1
+            if l >= 1:
+                small_of[(s, l)] = k
+                k += 1
+        for mu, (s, l, kappa, mj2) in enumerate(lab):
+            j2 = 2 * abs(kappa) - 1
+            lt = l + 1 if kappa < 0 else l - 1
+            ks = small_of[(s, kappa)]
+            assert int(wl_small.shell_l[wl_small.atom_shell_off[a] + ks]) == lt
+            for spin in (0, 1):
+                ml2 = mj2 - (1 if spin == 0 else -1)  # 2 m_l = 2 m_j - 2 m_s
+                ml = ml2 // 2
+                if abs(ml) <= l:
+                    c = cg_half(l, j2, mj2, spin)
+                    for mp, z in complex_harmonic_coefs(l, ml):
+                        gl[spin, offL[s - s0] + mp + l, mu] += c * z
+                if abs(ml) <= lt:
+                    c = cg_half(lt, j2, mj2, spin)
+                    for mp, z in complex_harmonic_coefs(lt, ml):
+                        gs[spin, offS[ks] + mp + lt, mu] += c * z
+        GL.append(gl)
+        GS.append(gs)
+    return GL, GS
+
+
+def spinor_transform(pairs, blocks_large, blocks_small, GL, GS):
+    """H+ and S+ in the spinor basis for each atom pair (Eq. 33, summed over the
+    two components and the two spins):
+        X+_AB = sum_comp sum_sigma G_A[sigma]^H X^comp_AB G_B[sigma]
+    blocks_*: per pair float64[2, n_A, n_B] (H, S) of that component.
+    Returns a list of complex128[2, NS_A, NS_B] (H+, S+)."""
+    out = []
+    for p, (a, b) in enumerate(pairs):
+        res = np.zeros((2, GL[a].shape[2], GL[b].shape[2]), dtype=np.complex128)
+        for q in range(2):
+            for sp in range(2):
+                res[q] += GL[a][sp].conj().T @ blocks_large[p][q] @ GL[b][sp]
+                res[q] += GS[a][sp].conj().T @ blocks_small[p][q] @ GS[b][sp]
+        out.append(res)
+    return out

@@ -252,6 +252,31 @@ int q4c_plan_set_ket_potential(q4c_plan *plan, const int64_t *shell_u_off, int64
  * ket potential is set.  Runs eagerly (no graph capture). */
 int q4c_integrate_HS(const q4c_plan *plan, const double *v_dev, uint32_t flags, double *hs_dev, void *stream);
 
+/* q4c_spinor_transform: the scalar -> spinor transformation of H and S
+ * (paper Sec. III A, Eq. 33, with the matrices of Eq. 14 built from the
+ * Clebsch-Gordan coefficients of Eq. 10 / App. A and the complex harmonics
+ * of Eq. 13), summed over the two components and the two spins:
+ *   H+_AB = sum_c sum_s G^c_A[s]^H H^c_AB G^c_B[s],  S+ likewise.
+ * plan_large: plan over the large-component basis; plan_small: over its
+ * small-component partners on the same atoms and grid, listed per atom as
+ * two shells l + 1 and l - 1 (one for l = 0) right after one another for
+ * every large shell of l, in the large shells' order.  hs_large_dev,
+ * hs_small_dev: the q4c_integrate_HS outputs of the two plans (device).
+ * Spinor functions per atom: large shells in order; for each,
+ * kappa = -(l+1) (j = l + 1/2), then kappa = l (j = l - 1/2, l >= 1); m_j
+ * ascending; the small component of (kappa, m_j) lies on the shell of
+ * l~ = 2j - l.  Complex harmonics are the Condon-Shortley ones (in terms of
+ * the App. B real harmonics, which carry (-1)^m already, Eq. 13 without its
+ * own (-1)^m); the i of Eq. 12b cancels.
+ * h_dev, s_dev (device, complex128 as interleaved re, im): 4 store_len of
+ * the large plan each; pair block (2 n_A) x (2 n_B) row-major at complex
+ * offset 4 pair_off[p] (large plan's pairs).  Q4C_EINVAL if the small plan
+ * does not pair with the large one (atoms, atom pairs, shells).  The first
+ * call with a given small plan builds and uploads its tables on the large
+ * plan. */
+int q4c_spinor_transform(const q4c_plan *plan_large, const q4c_plan *plan_small, const double *hs_large_dev,
+                         const double *hs_small_dev, double *h_dev, double *s_dev, void *stream);
+
 /* Coefficients on the stored elements from a Hermitian spinor density matrix
  * D given as spinor blocks (device complex128, 4 store_len, spinor layout)
  * such that density_on_grid yields Re Tr(D H) derivatives (Eq. 21/39):

@@ -82,7 +82,7 @@ EXPORTS = ("q4c_plan_create", "q4c_plan_destroy", "q4c_plan_info", "q4c_plan_pai
            "q4c_plan_sync", "q4c_plan_profile", "q4c_plan_timers", "q4c_plan_split_stats", "q4c_status_string",
            "q4c_last_error", "q4c_plan_create_batched", "q4c_plan_systems", "q4c_plan_set_launch",
            "q4c_plan_get_launch", "q4c_plan_autotune", "q4c_plan_set_graphs", "q4c_plan_set_ket_potential",
-           "q4c_integrate_HS")
+           "q4c_integrate_HS", "q4c_spinor_transform")
 
 
 def _load():
@@ -120,6 +120,7 @@ def _load():
         lib.q4c_plan_set_graphs.argtypes = [vp, ctypes.c_int]
         lib.q4c_plan_set_ket_potential.argtypes = [vp, vp, i64, vp]
         lib.q4c_integrate_HS.argtypes = [vp, vp, u32, vp, vp]
+        lib.q4c_spinor_transform.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         lib.q4c_status_string.argtypes = [ctypes.c_int]
         lib.q4c_status_string.restype = ctypes.c_char_p
         lib.q4c_last_error.argtypes = []
@@ -354,6 +355,17 @@ def q4c_integrate_HS(plan: Plan, v, flags: int = 0, hs=None):
     _check(_load().q4c_integrate_HS(plan.handle, _dev_ptr(v, min_numel=plan.info["n_points"], name="v"),
                                     int(flags), _dev_ptr(hs, min_numel=2 * L, name="hs"), _stream_handle()))
     return hs
+
+
+def q4c_spinor_transform(plan_large: Plan, plan_small: Plan, hs_large, hs_small, h_out, s_out):
+    """H+ and S+ in the spinor basis into h_out, s_out ([4 store_len, 2] float64
+    each, complex as (re, im), store_len of the large plan)."""
+    L, Ls = plan_large.info["store_len"], plan_small.info["store_len"]
+    _check(_load().q4c_spinor_transform(
+        plan_large.handle, plan_small.handle, _dev_ptr(hs_large, min_numel=2 * L, name="hs_large"),
+        _dev_ptr(hs_small, min_numel=2 * Ls, name="hs_small"), _dev_ptr(h_out, min_numel=8 * L, name="h_out"),
+        _dev_ptr(s_out, min_numel=8 * L, name="s_out"), _stream_handle()))
+    return h_out, s_out
 
 
 def density_on_grid(plan: Plan, coef, terms: int = TERM_ALL, weight_mode: int = 0, out=None):

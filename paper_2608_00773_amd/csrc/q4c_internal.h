@@ -83,6 +83,19 @@ struct Pass {
   int64_t panel_len;     // doubles (operand panels, stored after the partials)
 };
 
+// Scalar -> spinor transformation (Eq. 33): coefficients of one spinor type
+// (l, kappa, m_j) on the scalar functions of its large shell (component 0)
+// and of its small partner shell (component 1), per spin (0: up, 1: down).
+struct SpinorType {
+  int32_t n[2][2];        // [component][spin]: number of entries (0..2)
+  int32_t m[2][2][2];     // function offset within the shell (m' + l)
+  double re[2][2][2], im[2][2][2];
+};
+// One spinor function: atom-local offsets of its large and small shells, type.
+struct SpinorFn {
+  int32_t offL, offS, type;
+};
+
 // Padded panel sizes: points to a multiple of kChunk, functions to a multiple of 16.
 __host__ __device__ inline int64_t pad16(int64_t x) { return (x + 15) / 16 * 16; }
 
@@ -176,6 +189,18 @@ struct q4c_plan {
   unsigned *d_tickets = nullptr;   // [2][n_passes][kTicketsPerLaunch] persistent-launch queues
   int n_cu = 256;                  // compute units of the plan's device
 
+  // ---- scalar -> spinor transformation tables, built for one small-component
+  // plan on first use (q4c_spinor_transform); mutable: calls take a const plan
+  mutable const q4c_plan *sp_small = nullptr;
+  mutable int64_t sp_small_fn = -1, sp_small_len = -1;
+  mutable q4c::SpinorType *d_sp_types = nullptr;
+  mutable q4c::SpinorFn *d_sp_fns = nullptr;
+  mutable int32_t *d_sp_off = nullptr;  // [n_atoms + 1] first spinor function of each atom
+  mutable int32_t *d_sp_nL = nullptr;   // [n_atoms] large-component functions per atom
+  mutable int32_t *d_sp_nS = nullptr;   // [n_atoms] small-component functions per atom
+  mutable int64_t *d_sp_poffS = nullptr;  // [n_pairs] block offsets in the small plan's store
+  mutable int64_t sp_store_len_S = 0;
+
   // ---- launch configuration (chosen by q4c_plan_autotune or set directly)
   q4c::LaunchCfg cfg_contract{}, cfg_density{}, cfg_hs{};
   bool use_graphs = false;
@@ -207,6 +232,9 @@ int launch_integrate(const q4c_plan *p, const double *v, int precision, uint32_t
 int launch_density(const q4c_plan *p, const double *coef, uint32_t terms, int weight_mode, double *out,
                    hipStream_t s);
 int launch_integrate_hs(const q4c_plan *p, const double *v, uint32_t flags, double *hs, hipStream_t s);
+// scalar -> spinor transformation of two H/S stores (q4c_spinor_kernels.hip)
+int launch_spinor_transform(const q4c_plan *pl, const double *hs_large, const double *hs_small, double *h_out,
+                            double *s_out, hipStream_t s);
 // k_contract_hs over work items [w0, w0 + nw) of a pass (q4c_hs_kernels.hip)
 int launch_contract_hs(const q4c_plan *p, int64_t w0, int64_t nw, const int32_t *order, const double *panel,
                        unsigned *tickets, unsigned grid, hipStream_t s);

@@ -11,6 +11,7 @@
 // set), and the per-batch dense partial matrices are summed into a sparse
 // atom-pair block store instead of per-task dense matrices.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -1081,6 +1082,149 @@ int q4c_plan_set_ket_potential(q4c_plan *p, const int64_t *shell_u_off, int64_t 
   p->dp.shell_u_off = d_off;
   drop_graphs(p);
   return Q4C_OK;
+}
+
+namespace {
+
+// C_alpha (spin 0, m_s = +1/2) or C_beta (spin 1) of Eq. 10 for j = j2/2,
+// m_j = mj2/2: a = 2(j - l); C_alpha = a sqrt((l + a m_j + 1/2)/(2l+1)),
+// C_beta = sqrt((l - a m_j + 1/2)/(2l+1)).
+double spinor_cg(int l, int j2, int mj2, int spin) {
+  const int a = j2 - 2 * l;
+  const double mj = 0.5 * mj2;
+  const double r = spin == 0 ? l + a * mj + 0.5 : l - a * mj + 0.5;
+  const double v = std::sqrt(std::max(r, 0.0) / (2.0 * l + 1.0));
+  return spin == 0 ? a * v : v;
+}
+
+// The Condon-Shortley complex harmonic Y~_l^m in terms of the real harmonics
+// of App. B (which carry (-1)^m themselves): m > 0: (Y_m + i Y_-m)/sqrt2;
+// m < 0: (-1)^m (Y_|m| - i Y_-|m|)/sqrt2; m = 0: Y_0.  Writes up to two
+// (m', re, im); returns their number.
+int complex_harmonic(int m, int *mp, double *re, double *im) {
+  const double h = 0.70710678118654752440;
+  if (m == 0) {
+    mp[0] = 0;
+    re[0] = 1.0;
+    im[0] = 0.0;
+    return 1;
+  }
+  if (m > 0) {
+    mp[0] = m, re[0] = h, im[0] = 0.0;
+    mp[1] = -m, re[1] = 0.0, im[1] = h;
+    return 2;
+  }
+  const double sg = (-m) & 1 ? -1.0 : 1.0;
+  mp[0] = -m, re[0] = sg * h, im[0] = 0.0;
+  mp[1] = m, re[1] = 0.0, im[1] = -sg * h;
+  return 2;
+}
+
+// The relation table of the scalar -> spinor transformation (the global form
+// of Algorithm 1: here every plan holds the whole system): spinor functions
+// per atom (large shells in order; kappa = -(l+1), then kappa = l for l >= 1;
+// m_j ascending), each tied to its large shell and to the small shell of the
+// same (shell, kappa), which the small plan must list right after one another
+// (l + 1, then l - 1).  Coefficient types are shared by all spinors of one
+// (l, kappa, m_j).
+int build_spinor_tables(const q4c_plan *pl, const q4c_plan *ps) {
+  if (ps->n_atoms != pl->n_atoms || ps->R != pl->R)
+    return fail(Q4C_EINVAL, "spinor transform: the two plans have different atoms");
+  if (ps->n_pairs != pl->n_pairs || ps->pair_a != pl->pair_a || ps->pair_b != pl->pair_b)
+    return fail(Q4C_EINVAL, "spinor transform: the two plans have different atom pairs");
+  std::vector<q4c::SpinorType> types;
+  std::vector<std::array<int, 3>> type_key;
+  std::vector<q4c::SpinorFn> fns;
+  std::vector<int32_t> sp_off(pl->n_atoms + 1, 0), nL(pl->n_atoms), nS(pl->n_atoms);
+  for (int a = 0; a < pl->n_atoms; ++a) {
+    sp_off[a] = (int32_t)fns.size();
+    int offL = 0, offS = 0, ks = ps->atom_shell_off[a];
+    for (int sh = pl->atom_shell_off[a]; sh < pl->atom_shell_off[a + 1]; ++sh) {
+      const int l = pl->shell_l[sh];
+      for (int kk = 0; kk < (l >= 1 ? 2 : 1); ++kk) {
+        const int kappa = kk == 0 ? -(l + 1) : l;
+        const int lt = kappa < 0 ? l + 1 : l - 1;
+        if (ks >= ps->atom_shell_off[a + 1] || ps->shell_l[ks] != lt)
+          return fail(Q4C_EINVAL, "spinor transform: the small plan's shells do not pair with the large plan's "
+                                  "(expected l+1, then l-1 after every large shell of l)");
+        const int j2 = 2 * (kappa < 0 ? -kappa : kappa) - 1;
+        for (int mj2 = -j2; mj2 <= j2; mj2 += 2) {
+          int t = -1;
+          for (size_t u = 0; u < type_key.size(); ++u)
+            if (type_key[u][0] == l && type_key[u][1] == kappa && type_key[u][2] == mj2) t = (int)u;
+          if (t < 0) {
+            q4c::SpinorType T{};
+            for (int c = 0; c < 2; ++c) {
+              const int lc = c == 0 ? l : lt;
+              for (int spin = 0; spin < 2; ++spin) {
+                const int ml2 = mj2 - (spin == 0 ? 1 : -1);
+                const int ml = ml2 / 2;
+                T.n[c][spin] = 0;
+                if (ml < -lc || ml > lc) continue;
+                const double cg = spinor_cg(lc, j2, mj2, spin);
+                int mp[2];
+                double re[2], im[2];
+                const int k = complex_harmonic(ml, mp, re, im);
+                for (int e = 0; e < k; ++e) {
+                  T.m[c][spin][e] = mp[e] + lc;
+                  T.re[c][spin][e] = cg * re[e];
+                  T.im[c][spin][e] = cg * im[e];
+                }
+                T.n[c][spin] = k;
+              }
+            }
+            t = (int)types.size();
+            types.push_back(T);
+            type_key.push_back({l, kappa, mj2});
+          }
+          fns.push_back(q4c::SpinorFn{offL, offS, t});
+        }
+        offS += 2 * lt + 1;
+        ++ks;
+      }
+      offL += 2 * l + 1;
+    }
+    if (ks != ps->atom_shell_off[a + 1])
+      return fail(Q4C_EINVAL, "spinor transform: the small plan has extra shells on an atom");
+    nL[a] = offL;
+    nS[a] = offS;
+  }
+  sp_off[pl->n_atoms] = (int32_t)fns.size();
+  q4c_plan *mp = const_cast<q4c_plan *>(pl);  // device tables cached on the plan
+  int rc;
+  if ((rc = upload(mp, types, &mp->d_sp_types)) != Q4C_OK) return rc;
+  if ((rc = upload(mp, fns, &mp->d_sp_fns)) != Q4C_OK) return rc;
+  if ((rc = upload(mp, sp_off, &mp->d_sp_off)) != Q4C_OK) return rc;
+  if ((rc = upload(mp, nL, &mp->d_sp_nL)) != Q4C_OK) return rc;
+  if ((rc = upload(mp, nS, &mp->d_sp_nS)) != Q4C_OK) return rc;
+  std::vector<int64_t> poffS(ps->pair_off.begin(), ps->pair_off.begin() + ps->n_pairs);
+  if ((rc = upload(mp, poffS, &mp->d_sp_poffS)) != Q4C_OK) return rc;
+  pl->sp_small = ps;
+  pl->sp_small_fn = ps->n_fn;
+  pl->sp_small_len = ps->store_len;
+  pl->sp_store_len_S = ps->store_len;
+  return Q4C_OK;
+}
+
+}  // namespace
+
+int q4c_spinor_transform(const q4c_plan *pl, const q4c_plan *ps, const double *hs_large_dev,
+                         const double *hs_small_dev, double *h_dev, double *s_dev, void *stream) {
+  if (!pl || !ps) return fail(Q4C_EINVAL, "NULL plan");
+  int rc = check_plan_dev(ps);
+  if (rc != Q4C_OK) return rc;
+  if ((rc = check_plan_dev(pl)) != Q4C_OK) return rc;
+  if (ps->device != pl->device) return fail(Q4C_EINVAL, "spinor transform: plans on different devices");
+  if (pl->store_len > 0 && (!hs_large_dev || !h_dev || !s_dev)) return fail(Q4C_EINVAL, "NULL H/S or output");
+  if (ps->store_len > 0 && !hs_small_dev) return fail(Q4C_EINVAL, "NULL small-component H/S");
+  if (pl->sp_small != ps || pl->sp_small_fn != ps->n_fn || pl->sp_small_len != ps->store_len) {
+    // tables for this small plan (validated; earlier copies stay allocated until destroy)
+    if ((rc = build_spinor_tables(pl, ps)) != Q4C_OK) {
+      pl->sp_small = nullptr;
+      return rc;
+    }
+  }
+  return q4c::launch_spinor_transform(pl, hs_large_dev, hs_small_dev, h_dev, s_dev, (hipStream_t)stream);
 }
 
 int q4c_integrate_HS(const q4c_plan *p, const double *v_dev, uint32_t flags, double *hs_dev, void *stream) {

@@ -238,3 +238,13 @@ def test_ket_potential_validation_and_hs_flop_count():
     nf = np.diff(fn_off).astype(np.float64)
     assert p.info["flops_alg_hs"] == pytest.approx(float(np.sum(3.0 * P * nf * nf)), rel=1e-15)
     assert p.info["flops_alg"] == pytest.approx(float(np.sum(10.0 * P * nf * nf)), rel=1e-15)
+
+
+def test_spinor_transform_needs_device_plans():
+    q, lib = _lib()
+    wl = W.config_small(nrad=10, nang=26)
+    p = _host_plan(q, wl)
+    rc = lib.q4c_spinor_transform(p.handle, p.handle, ctypes.c_void_p(1), ctypes.c_void_p(1), ctypes.c_void_p(1),
+                                  ctypes.c_void_p(1), None)
+    assert rc == q.Q4C_ENODEV
+    assert lib.q4c_spinor_transform(None, p.handle, None, None, None, None, None) == q.Q4C_EINVAL

@@ -142,6 +142,7 @@ def bench_hs(wl, timed, steps: int, cpu_frac: float, with_cpu: bool, components=
     wl_l = W.with_ket(wl, 7101)
     wl_s = W.small_component(wl_l, 7102)
     out = {"workload_gen_s": time.perf_counter() - t0}
+    kept = {}
     for name, w in (("large", wl_l), ("small", wl_s)):
         if name not in components:
             continue
@@ -184,7 +185,24 @@ def bench_hs(wl, timed, steps: int, cpu_frac: float, with_cpu: bool, components=
         }
         log("H/S %s component: %d functions, %.3f ms per call, k_contract_hs %.1f%% of FP64 peak" %
             (name, info["n_fn"], ms, 100 * achieved / PEAK_F64))
-        del hs, plan
+        kept[name] = (plan, hs)
+    if "large" in kept and "small" in kept:
+        # scalar -> spinor transformation of both components' H and S (Eq. 33)
+        (pl, hsl), (ps, hss) = kept["large"], kept["small"]
+        h_sp, s_sp = q.new_spinor(pl, dev), q.new_spinor(pl, dev)
+        call = lambda: q.q4c_spinor_transform(pl, ps, hsl, hss, h_sp, s_sp)
+        call()
+        ms = timed(call, steps)
+        Ll, Ls = pl.info["store_len"], ps.info["store_len"]
+        # algorithmic bytes: the two parts of both components read once, the two
+        # complex spinor blocks (4 elements per scalar element) written once
+        nbytes = 16.0 * (Ll + Ls) + 2 * 16.0 * 4 * Ll
+        out["spinor_transform"] = {
+            "ms": ms, "roofline": {"kernel": "k_spinor_transform", "bound": "hbm", "achieved": nbytes / (ms * 1e-3) / 1e9,
+                                   "peak": 8000.0, "unit": "GB/s", "frac": nbytes / (ms * 1e-3) / 8e12,
+                                   "bytes_alg": nbytes}}
+        log("spinor transform: %.3f ms, %.0f GB/s algorithmic" % (ms, nbytes / (ms * 1e-3) / 1e9))
+    kept.clear()
     if with_cpu:
         import oracle
         rng = np.random.default_rng(6102)

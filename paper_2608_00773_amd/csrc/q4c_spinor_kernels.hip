@@ -10,6 +10,7 @@
 // HBM-bound: the scalar blocks are read and the complex blocks written once.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "q4c_internal.h"
@@ -17,24 +18,38 @@
 namespace q4c {
 namespace {
 
-// One workgroup per atom pair; threads stride over the (mu, nu) elements.
+// One thread per output element, over all pairs at once: element g of the
+// spinor store belongs to the pair p with 4 pair_off[p] <= g < 4 pair_off[p+1]
+// (binary search), so the writes are contiguous and every workgroup is full.
 // Outputs: complex128 (re, im interleaved), 4 store_len (large plan) each,
 // block (2 nL_A) x (2 nL_B) row-major at complex offset 4 pair_off[p].
 __global__ __launch_bounds__(256) void k_spinor_transform(DevPlan d, const SpinorType *types, const SpinorFn *fns,
                                                           const int32_t *sp_off, const int32_t *nL,
                                                           const int32_t *nS, const int64_t *poffS,
-                                                          int64_t lenS, const double *hsL, const double *hsS,
-                                                          double *h_out, double *s_out) {
-  const int p = blockIdx.x;
-  const int A = d.pair_a[p], B = d.pair_b[p];
-  const int NA = sp_off[A + 1] - sp_off[A], NB = sp_off[B + 1] - sp_off[B];
-  const int nLB = nL[B], nSB = nS[B];
-  const int64_t oL = d.pair_off[p], oS = poffS[p], lenL = d.store_len;
-  const double *HL = hsL + oL, *SL = hsL + lenL + oL;
-  const double *HS = hsS + oS, *SS = hsS + lenS + oS;
-  const int64_t out0 = 4 * oL;  // complex offset of the pair's spinor block
-  for (int e = threadIdx.x; e < NA * NB; e += blockDim.x) {
+                                                          int64_t lenS, int64_t npairs, const double *hsL,
+                                                          const double *hsS, double *h_out, double *s_out) {
+  const int64_t lenL = d.store_len, total = 4 * lenL;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    // pair of element g: the last p with pair_off[p] <= g / 4
+    const int64_t key = g >> 2;
+    int64_t lo = 0, hi = npairs - 1;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if (d.pair_off[mid] <= key)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const int64_t p = lo;
+    const int A = d.pair_a[p], B = d.pair_b[p];
+    const int NB = sp_off[B + 1] - sp_off[B];
+    const int nLB = nL[B], nSB = nS[B];
+    const int64_t oL = d.pair_off[p], oS = poffS[p];
+    const int e = (int)(g - 4 * oL);
     const int mu = e / NB, nu = e - mu * NB;
+    const double *HL = hsL + oL, *SL = hsL + lenL + oL;
+    const double *HS = hsS + oS, *SS = hsS + lenS + oS;
     const SpinorFn fa = fns[sp_off[A] + mu], fb = fns[sp_off[B] + nu];
     const SpinorType &ta = types[fa.type], &tb = types[fb.type];
     double hre = 0.0, him = 0.0, sre = 0.0, sim = 0.0;
@@ -62,11 +77,10 @@ __global__ __launch_bounds__(256) void k_spinor_transform(DevPlan d, const Spino
         }
       }
     }
-    const int64_t o = 2 * (out0 + e);
-    h_out[o] = hre;
-    h_out[o + 1] = him;
-    s_out[o] = sre;
-    s_out[o + 1] = sim;
+    h_out[2 * g] = hre;
+    h_out[2 * g + 1] = him;
+    s_out[2 * g] = sre;
+    s_out[2 * g + 1] = sim;
   }
 }
 
@@ -77,9 +91,11 @@ int launch_spinor_transform(const q4c_plan *pl, const double *hs_large, const do
   if (pl->n_pairs == 0) return Q4C_OK;
   {
     TimedLaunch tl_(pl, Q4C_TIMER_SPINOR, s);
-    hipLaunchKernelGGL(k_spinor_transform, dim3((unsigned)pl->n_pairs), dim3(256), 0, s, pl->dp, pl->d_sp_types,
+    const int64_t total = 4 * pl->store_len;
+    const unsigned grid = (unsigned)std::min<int64_t>((total + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_spinor_transform, dim3(grid), dim3(256), 0, s, pl->dp, pl->d_sp_types,
                        pl->d_sp_fns, pl->d_sp_off, pl->d_sp_nL, pl->d_sp_nS, pl->d_sp_poffS, pl->sp_store_len_S,
-                       hs_large, hs_small, h_out, s_out);
+                       pl->n_pairs, hs_large, hs_small, h_out, s_out);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "k_spinor_transform");

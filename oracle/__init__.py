@@ -69,6 +69,7 @@ def _load():
                                         ip, ip, ctypes.c_int, dp, dp]
         lib.orc_pair_blocks_hs.argtypes = [bp, ctypes.POINTER(ctypes.c_int64), dp, ctypes.c_int64, dp, dp, dp, dp,
                                            dp, ctypes.c_int, ip, ip, ctypes.c_int, dp, dp]
+        lib.orc_density_grad_points.argtypes = [bp, ctypes.c_int64, dp, dp, dp, ctypes.c_int, ip, ip, dp, dp]
         lib.orc_density_points.argtypes = [bp, ctypes.c_int64, dp, dp, dp, dp, ctypes.c_double, ctypes.c_int,
                                            ip, ip, dp, ctypes.c_int, dp, dp]
         _lib = lib
@@ -408,4 +409,43 @@ def spinor_transform(pairs, blocks_large, blocks_small, GL, GS):
                 res[q] += GL[a][sp].conj().T @ blocks_large[p][q] @ GL[b][sp]
                 res[q] += GS[a][sp].conj().T @ blocks_small[p][q] @ GS[b][sp]
         out.append(res)
+    return out
+
+
+def spinor_density_to_scalar(pairs, D_blocks, GL, GS):
+    """The scalar density matrices of both components from a Hermitian spinor
+    density matrix given on the pair blocks (the reverse of Eq. 33, as the
+    paper's D'_ij = sum_mu,nu D_mu,nu G*_i,mu G_j,nu, summed over spins):
+        D'^c_AB = Re sum_sigma conj(G^c_A[sigma]) D_AB G^c_B[sigma]^T
+    times 2 on off-diagonal pairs (each stored block stands for its mirror),
+    so that a density sums every stored element once.
+    Returns a list of (C^L_AB float64[nL_A, nL_B], C^S_AB float64[nS_A, nS_B])."""
+    out = []
+    for p, (a, b) in enumerate(pairs):
+        f = 1.0 if a == b else 2.0
+        res = []
+        for G in (GL, GS):
+            acc = np.zeros((G[a].shape[1], G[b].shape[1]), dtype=np.complex128)
+            for sp in range(2):
+                acc += G[a][sp].conj() @ D_blocks[p] @ G[b][sp].T
+            res.append(f * acc.real)
+        out.append(tuple(res))
+    return out
+
+
+def density_grad(wl, pairs, coef_blocks, idx=None):
+    """n and its gradient at grid points `idx` (default all) from one real
+    coefficient block per pair (each stored element once): float64[npts, 4]
+    with columns n, dn/dx, dn/dy, dn/dz."""
+    lib = _load()
+    h = _BasisHandle(wl)
+    pairs = _c(pairs, np.int32).reshape(-1, 2)
+    pa, pb = _c(pairs[:, 0], np.int32), _c(pairs[:, 1], np.int32)
+    coef = _c(np.concatenate([np.asarray(c, dtype=np.float64).reshape(-1) for c in coef_blocks]), np.float64)
+    if idx is None:
+        idx = np.arange(wl.n_points)
+    x, y, z = (_c(np.asarray(t)[idx], np.float64) for t in (wl.x, wl.y, wl.z))
+    out = np.zeros((x.size, 4))
+    lib.orc_density_grad_points(h.ptr, x.size, _dp(x), _dp(y), _dp(z), int(pairs.shape[0]), _ip(pa), _ip(pb),
+                                _dp(coef), _dp(out))
     return out

@@ -511,3 +511,53 @@ int orc_density_points(const orc_basis *b, int64_t npts, const double *x, const 
   free(fb);
   return 0;
 }
+
+/*
+ * Density and its gradient at the listed points from one real coefficient
+ * block per atom pair (the scalar density matrix of one component, each
+ * stored element counted once):
+ *   n_g     = sum_pairs sum_ij C_ij phi_i phi_j
+ *   dn_g/da = sum_pairs sum_ij C_ij (d_a phi_i phi_j + phi_i d_a phi_j)
+ * (the density of Sec. II B / III A on the scalar basis, with the gradient a
+ * GGA functional needs).  coef: per pair nA x nB row-major.  out[4 g + k]:
+ * k = 0 n, 1..3 the x, y, z derivatives.  Sums are compensated.
+ */
+int orc_density_grad_points(const orc_basis *b, int64_t npts, const double *x, const double *y, const double *z,
+                            int npairs, const int32_t *pa, const int32_t *pb, const double *coef, double *out) {
+  int na = b->n_atoms;
+  int64_t *poff = (int64_t *)malloc(sizeof(int64_t) * (npairs + 1));
+  poff[0] = 0;
+  for (int p = 0; p < npairs; ++p) poff[p + 1] = poff[p] + (int64_t)atom_nfn(b, pa[p]) * atom_nfn(b, pb[p]);
+  int maxfn = 0;
+  for (int a = 0; a < na; ++a)
+    if (atom_nfn(b, a) > maxfn) maxfn = atom_nfn(b, a);
+  double *fa = (double *)malloc(sizeof(double) * maxfn * 4);
+  double *fb = (double *)malloc(sizeof(double) * maxfn * 4);
+  for (int64_t g = 0; g < npts; ++g) {
+    double s[4] = {0, 0, 0, 0}, c[4] = {0, 0, 0, 0};
+    for (int p = 0; p < npairs; ++p) {
+      int A = pa[p], B = pb[p];
+      double rA = atom_rcut(b, A), rB = atom_rcut(b, B);
+      double ax = x[g] - b->R[3 * A], ay = y[g] - b->R[3 * A + 1], az = z[g] - b->R[3 * A + 2];
+      double bx = x[g] - b->R[3 * B], by = y[g] - b->R[3 * B + 1], bz = z[g] - b->R[3 * B + 2];
+      if (!(ax * ax + ay * ay + az * az < rA * rA)) continue;
+      if (!(bx * bx + by * by + bz * bz < rB * rB)) continue;
+      int nA = atom_nfn(b, A), nB = atom_nfn(b, B);
+      double *ga = fa + nA, *gb = fb + nB;
+      atom_functions(b, A, x[g], y[g], z[g], fa, ga);
+      atom_functions(b, B, x[g], y[g], z[g], fb, gb);
+      const double *C = coef + poff[p];
+      for (int i = 0; i < nA; ++i)
+        for (int j = 0; j < nB; ++j) {
+          double cij = C[(int64_t)i * nB + j];
+          neu_add(&s[0], &c[0], cij * fa[i] * fb[j]);
+          for (int k = 0; k < 3; ++k) neu_add(&s[k + 1], &c[k + 1], cij * (ga[3 * i + k] * fb[j] + fa[i] * gb[3 * j + k]));
+        }
+    }
+    for (int k = 0; k < 4; ++k) out[4 * g + k] = s[k] + c[k];
+  }
+  free(poff);
+  free(fa);
+  free(fb);
+  return 0;
+}

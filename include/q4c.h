@@ -277,6 +277,31 @@ int q4c_integrate_HS(const q4c_plan *plan, const double *v_dev, uint32_t flags, 
 int q4c_spinor_transform(const q4c_plan *plan_large, const q4c_plan *plan_small, const double *hs_large_dev,
                          const double *hs_small_dev, double *h_dev, double *s_dev, void *stream);
 
+/* q4c_spinor_density_to_scalar: the reverse of q4c_spinor_transform for a
+ * density (the paper's D'_ij = sum_mu,nu D_mu,nu G*_i,mu G_j,nu, summed over
+ * spins, for each component; Sec. III A, density update): from a spinor
+ * density matrix D on the pair blocks (device complex128, the layout of the
+ * q4c_spinor_transform outputs; D_BA = D_AB^H implied), the scalar density
+ * matrices of the large and small components on their plans' pair layouts,
+ *   C^c_AB = f Re sum_s conj(G^c_A[s]) D_AB G^c_B[s]^T,  f = 2 if A != B,
+ * so that summing every stored element once gives the full density.
+ * cl_dev: store_len (large plan) doubles; cs_dev: store_len (small plan).
+ * Same plan pairing rules and tables as q4c_spinor_transform. */
+int q4c_spinor_density_to_scalar(const q4c_plan *plan_large, const q4c_plan *plan_small, const double *d_dev,
+                                 double *cl_dev, double *cs_dev, void *stream);
+
+/* density_gradient_on_grid: the density and its gradient, as a GGA
+ * functional needs them, from one coefficient part C (device, store_len
+ * doubles, e.g. a component's scalar density matrix from
+ * q4c_spinor_density_to_scalar; each stored element counted once):
+ *   n_g = sum_ij C_ij phi_i phi_j,  d n_g / d x_a = sum_ij C_ij (d_a phi_i phi_j + phi_i d_a phi_j)
+ * out_dev (device): [4][n_points] in user order: n, dn/dx, dn/dy, dn/dz
+ * (zero outside every support).  FP64 MFMA; fixed-order sums (bitwise
+ * repeatable).  Uses the launch shape of density_on_grid; the first call
+ * allocates the plan's gradient partials (4x the adjoint partials of the
+ * largest pass). */
+int density_gradient_on_grid(const q4c_plan *plan, const double *coef_dev, double *out_dev, void *stream);
+
 /* Coefficients on the stored elements from a Hermitian spinor density matrix
  * D given as spinor blocks (device complex128, 4 store_len, spinor layout)
  * such that density_on_grid yields Re Tr(D H) derivatives (Eq. 21/39):

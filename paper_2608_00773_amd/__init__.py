@@ -82,7 +82,7 @@ EXPORTS = ("q4c_plan_create", "q4c_plan_destroy", "q4c_plan_info", "q4c_plan_pai
            "q4c_plan_sync", "q4c_plan_profile", "q4c_plan_timers", "q4c_plan_split_stats", "q4c_status_string",
            "q4c_last_error", "q4c_plan_create_batched", "q4c_plan_systems", "q4c_plan_set_launch",
            "q4c_plan_get_launch", "q4c_plan_autotune", "q4c_plan_set_graphs", "q4c_plan_set_ket_potential",
-           "q4c_integrate_HS", "q4c_spinor_transform")
+           "q4c_integrate_HS", "q4c_spinor_transform", "q4c_spinor_density_to_scalar", "density_gradient_on_grid")
 
 
 def _load():
@@ -121,6 +121,8 @@ def _load():
         lib.q4c_plan_set_ket_potential.argtypes = [vp, vp, i64, vp]
         lib.q4c_integrate_HS.argtypes = [vp, vp, u32, vp, vp]
         lib.q4c_spinor_transform.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        lib.q4c_spinor_density_to_scalar.argtypes = [vp, vp, vp, vp, vp, vp]
+        lib.density_gradient_on_grid.argtypes = [vp, vp, vp, vp]
         lib.q4c_status_string.argtypes = [ctypes.c_int]
         lib.q4c_status_string.restype = ctypes.c_char_p
         lib.q4c_last_error.argtypes = []
@@ -366,6 +368,25 @@ def q4c_spinor_transform(plan_large: Plan, plan_small: Plan, hs_large, hs_small,
         _dev_ptr(hs_small, min_numel=2 * Ls, name="hs_small"), _dev_ptr(h_out, min_numel=8 * L, name="h_out"),
         _dev_ptr(s_out, min_numel=8 * L, name="s_out"), _stream_handle()))
     return h_out, s_out
+
+
+def q4c_spinor_density_to_scalar(plan_large: Plan, plan_small: Plan, d_spin, c_large, c_small):
+    """Scalar density matrices of both components (one part each) from a spinor
+    density matrix d_spin ([4 store_len, 2] float64, store_len of the large plan)."""
+    L, Ls = plan_large.info["store_len"], plan_small.info["store_len"]
+    _check(_load().q4c_spinor_density_to_scalar(
+        plan_large.handle, plan_small.handle, _dev_ptr(d_spin, min_numel=8 * L, name="d_spin"),
+        _dev_ptr(c_large, min_numel=L, name="c_large"), _dev_ptr(c_small, min_numel=Ls, name="c_small"),
+        _stream_handle()))
+    return c_large, c_small
+
+
+def density_gradient_on_grid(plan: Plan, coef, out):
+    """n and grad n ([4, n_points] float64) from one coefficient part ([store_len])."""
+    _check(_load().density_gradient_on_grid(plan.handle, _dev_ptr(coef, min_numel=plan.info["store_len"], name="coef"),
+                                            _dev_ptr(out, min_numel=4 * plan.info["n_points"], name="out"),
+                                            _stream_handle()))
+    return out
 
 
 def density_on_grid(plan: Plan, coef, terms: int = TERM_ALL, weight_mode: int = 0, out=None):

@@ -91,6 +91,13 @@ struct SpinorType {
   int32_t m[2][2][2];     // function offset within the shell (m' + l)
   double re[2][2][2], im[2][2][2];
 };
+// One scalar function of one component in the reverse transformation: the
+// spinor functions (atom-local) it enters, per spin, with their coefficients.
+struct ScalarRel {
+  int32_t n[2];
+  int32_t mu[2][4];
+  double re[2][4], im[2][4];
+};
 // One spinor function: atom-local offsets of its large and small shells, type.
 struct SpinorFn {
   int32_t offL, offS, type;
@@ -198,8 +205,13 @@ struct q4c_plan {
   mutable int32_t *d_sp_off = nullptr;  // [n_atoms + 1] first spinor function of each atom
   mutable int32_t *d_sp_nL = nullptr;   // [n_atoms] large-component functions per atom
   mutable int32_t *d_sp_nS = nullptr;   // [n_atoms] small-component functions per atom
-  mutable int64_t *d_sp_poffS = nullptr;  // [n_pairs] block offsets in the small plan's store
+  mutable int64_t *d_sp_poffS = nullptr;  // [n_pairs + 1] block offsets in the small plan's store
+  mutable q4c::ScalarRel *d_sp_relL = nullptr, *d_sp_relS = nullptr;  // reverse transformation, per scalar function
+  mutable int32_t *d_sp_fL = nullptr, *d_sp_fS = nullptr;  // [n_atoms] first scalar function of each atom
   mutable int64_t sp_store_len_S = 0;
+
+  // ---- density gradient partials (density_gradient_on_grid), allocated on first use
+  mutable double *d_grad_partial = nullptr;
 
   // ---- launch configuration (chosen by q4c_plan_autotune or set directly)
   q4c::LaunchCfg cfg_contract{}, cfg_density{}, cfg_hs{};
@@ -232,6 +244,10 @@ int launch_integrate(const q4c_plan *p, const double *v, int precision, uint32_t
 int launch_density(const q4c_plan *p, const double *coef, uint32_t terms, int weight_mode, double *out,
                    hipStream_t s);
 int launch_integrate_hs(const q4c_plan *p, const double *v, uint32_t flags, double *hs, hipStream_t s);
+int launch_density_grad(const q4c_plan *p, const double *coef, double *out, double *gpart, hipStream_t s);
+// spinor density -> scalar density matrices of both components (q4c_spinor_kernels.hip)
+int launch_spinor_to_scalar(const q4c_plan *pl, const double *d_spin, double *c_large, double *c_small,
+                            hipStream_t s);
 // scalar -> spinor transformation of two H/S stores (q4c_spinor_kernels.hip)
 int launch_spinor_transform(const q4c_plan *pl, const double *hs_large, const double *hs_small, double *h_out,
                             double *s_out, hipStream_t s);

@@ -828,13 +828,22 @@ constexpr int RSB = T + 2;
 // in LDS (loaded by DMA) and shared by the 4 waves; each wave owns 16 columns x 32 rows of C
 // in registers.  Two workgroups fit on a CU, so one computes while the other
 // stages its next chunk.
-template <bool PERSIST>
+//
+// GRAD: the density and its gradient for one real coefficient part C (the
+// scalar density matrix of a component): per point n = sum C_ij phi_i phi_j
+// and d_a n = sum C_ij (d_a phi_i phi_j + phi_i d_a phi_j), i.e. the four
+// products C^T Y_q (Y_q = phi, d_x phi, d_y phi, d_z phi of the rows) met
+// lane-locally by the column values: n += u_0 phi_j, d_a n += u_a phi_j +
+// u_0 d_a phi_j.  Four partials per point and column half.
+template <bool PERSIST, bool GRAD = false>
 __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t terms, const WorkItem *work,
                                                           const int32_t *order, int64_t w0, int64_t nw,
                                                           const double *coef, const double *panel,
                                                           double *partial, unsigned *tickets) {
+  constexpr int NO = GRAD ? 4 : 1;   // outputs per point
+  constexpr int NC = GRAD ? 1 : 5;   // coefficient parts
   __shared__ double sa[32 * RSA], sb[32 * RSB];
-  __shared__ double s_red[2][4][16];  // per-wave point sums, alternating chunks
+  __shared__ double s_red[2][4][NO][16];  // per-wave point sums, alternating chunks
   __shared__ int64_t s_pos;
   // slot data of the tile's 64 rows and the half's 32 columns (slot -1: padding)
   __shared__ int s_rslot[T], s_rfn[T], s_rnf[T], s_cslot[T / 2], s_cfn[T / 2], s_cnf[T / 2];
@@ -921,7 +930,7 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t te
   // (lj, li) when the 16 x 16 block is strictly upper inside one atom block
   // (no work item computes the mirrored block); c' on the W parts.  All
   // loads of a thread are independent and issued together.
-  double creg[5][8];
+  double creg[NC][8];
   {
     const int64_t L = d.store_len;
     const int cl = 16 * js + l16;
@@ -937,7 +946,7 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t te
       const int64_t e = po + (int64_t)(li - rfn) * cnf + (lj - cfn);
       const int64_t em = po + (int64_t)(lj - rfn) * cnf + (li - cfn);
 #pragma unroll
-      for (int q = 0; q < 5; ++q) {
+      for (int q = 0; q < NC; ++q) {
         double c = live ? coef[q * L + e] : 0.0;
         if (mir) c += mirror_sign(q) * coef[q * L + em];
         creg[q][ks] = q == 0 ? c : d.cprime * c;
@@ -945,15 +954,18 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t te
     }
   }
   const bool tLL = terms & Q4C_TERM_LL, tSS = terms & Q4C_TERM_SS, tSO = terms & Q4C_TERM_SO;
-  double *out = partial + 2 * d.work_part_off[wi] + half * P;
+  // partials of this column half: NO runs of P values
+  double *out = partial + 2 * NO * d.work_part_off[wi] + half * NO * P;
   const int jloc = 16 * js;  // half-local first column of this wave
 
   for (int k0 = 0; k0 < Pp; k0 += 16) {
     const int rb2 = (k0 >> 4) & 1;
     __syncthreads();  // previous chunk's images consumed, its per-wave sums visible
-    if (k0 > 0 && tid < 16 && k0 - 16 + tid < P)
-      out[k0 - 16 + tid] = (s_red[rb2 ^ 1][0][tid] + s_red[rb2 ^ 1][1][tid]) +
-                           (s_red[rb2 ^ 1][2][tid] + s_red[rb2 ^ 1][3][tid]);
+    if (k0 > 0 && tid < 16 * NO && k0 - 16 + (tid & 15) < P) {
+      const int o = tid >> 4, t = tid & 15;
+      out[o * P + k0 - 16 + t] = (s_red[rb2 ^ 1][0][o][t] + s_red[rb2 ^ 1][1][o][t]) +
+                                 (s_red[rb2 ^ 1][2][o][t] + s_red[rb2 ^ 1][3][o][t]);
+    }
     dma_chunk<NTD, 16, T, RSA>(pb, plane, np, r0, k0 >> 2, sa);
     dma_chunk<NTD, 16, T / 2, RSB>(pb, plane, np, c0, k0 >> 2, sb);
     __builtin_amdgcn_s_waitcnt(0);  // this thread's LDS DMA loads have landed
@@ -963,7 +975,53 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t te
     // (l16, lk) holds column j = lk + 4 r (of the wave's 16) at point pt = l16
     // and the product with Z is a lane-local multiply-add.
     double xacc[4] = {0.0, 0.0, 0.0, 0.0};
-    if (any) {
+    double xg[4][4];  // GRAD: n, d_x n, d_y n, d_z n per register
+#pragma unroll
+    for (int o = 0; o < 4; ++o)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) xg[o][r] = 0.0;
+    if (GRAD && any) {
+      double zt[4][4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          zt[q][r] = sb[(q * 8 + (l16 >> 1)) * RSB + 2 * (jloc + d_row_f64(lk, r)) + (l16 & 1)];
+      auto grad_terms = [&](auto k0c, auto k1c) {
+        constexpr int K0 = decltype(k0c)::value, K1 = decltype(k1c)::value;
+#pragma unroll
+        for (int yq = 0; yq < 4; ++yq) {
+          double ya[8];
+#pragma unroll
+          for (int ks = K0; ks < K1; ++ks)
+            ya[ks] = sa[(yq * 8 + (l16 >> 1)) * RSA + 2 * (iloc + 4 * ks + lk) + (l16 & 1)];
+          dbl4 u0 = dbl4{0.0, 0.0, 0.0, 0.0}, u1 = u0;
+#pragma unroll
+          for (int ks = K0; ks < K1; ks += 2) {
+            u0 = mfma64(creg[0][ks], ya[ks], u0);
+            u1 = mfma64(creg[0][ks + 1], ya[ks + 1], u1);
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const double u = u0[r] + u1[r];
+            if (yq == 0) {
+              xg[0][r] += u * zt[0][r];
+#pragma unroll
+              for (int a = 1; a < 4; ++a) xg[a][r] += u * zt[a][r];
+            } else {
+              xg[yq][r] += u * zt[0][r];
+            }
+          }
+        }
+      };
+      if (act[0] && act[1])
+        grad_terms(std::integral_constant<int, 0>{}, std::integral_constant<int, 8>{});
+      else if (act[0])
+        grad_terms(std::integral_constant<int, 0>{}, std::integral_constant<int, 4>{});
+      else
+        grad_terms(std::integral_constant<int, 4>{}, std::integral_constant<int, 8>{});
+    }
+    if (!GRAD && any) {
       // column values: Z[q][pt = l16][j = jloc + lk + 4 r]
       double zt[4][4];
 #pragma unroll
@@ -1069,16 +1127,22 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t te
       }
     }
     // sum over the wave's 16 columns: the 4 registers, then the 4 lane rows
-    double sx = (xacc[0] + xacc[1]) + (xacc[2] + xacc[3]);
-    sx += __shfl_xor(sx, 16);
-    sx += __shfl_xor(sx, 32);
-    if (lane < 16) s_red[rb2][wave][l16] = sx;
+#pragma unroll
+    for (int o = 0; o < NO; ++o) {
+      const double *xv = GRAD ? xg[o] : xacc;
+      double sx = (xv[0] + xv[1]) + (xv[2] + xv[3]);
+      sx += __shfl_xor(sx, 16);
+      sx += __shfl_xor(sx, 32);
+      if (lane < 16) s_red[rb2][wave][o][l16] = sx;
+    }
   }
   __syncthreads();  // the last chunk's per-wave sums
   {
     const int k0 = Pp - 16, rb2 = (k0 >> 4) & 1;
-    if (tid < 16 && k0 + tid < P)
-      out[k0 + tid] = (s_red[rb2][0][tid] + s_red[rb2][1][tid]) + (s_red[rb2][2][tid] + s_red[rb2][3][tid]);
+    if (tid < 16 * NO && k0 + (tid & 15) < P) {
+      const int o = tid >> 4, t = tid & 15;
+      out[o * P + k0 + t] = (s_red[rb2][0][o][t] + s_red[rb2][1][o][t]) + (s_red[rb2][2][o][t] + s_red[rb2][3][o][t]);
+    }
   }
   if (!PERSIST) break;
   pos = next_item(tickets, npos, order != nullptr, &s_pos);
@@ -1098,6 +1162,23 @@ __global__ void k_density_points(DevPlan d, int64_t b0, const double *partial, i
       s += pw[P + g];
     }
     out[d.perm[g0 + g]] = weight_mode ? d.pw[g0 + g] * s : s;
+  }
+}
+
+// GRAD partials: four runs of P values per column half; out is [4][n_points].
+__global__ void k_density_points_grad(DevPlan d, int64_t b0, const double *partial, double *out) {
+  const int64_t b = b0 + blockIdx.x;
+  const int g0 = d.batch_pt_off[b], P = d.batch_pt_off[b + 1] - g0;
+  const int64_t wa = d.batch_work_off[b], wb = d.batch_work_off[b + 1];
+  for (int e = threadIdx.x; e < 4 * P; e += blockDim.x) {
+    const int o = e / P, g = e - o * P;
+    double s = 0.0;
+    for (int64_t w = wa; w < wb; ++w) {
+      const double *pw = partial + 8 * d.work_part_off[w];
+      s += pw[o * P + g];
+      s += pw[4 * P + o * P + g];
+    }
+    out[o * d.n_points + d.perm[g0 + g]] = s;
   }
 }
 
@@ -1359,6 +1440,59 @@ int launch_density(const q4c_plan *p, const double *coef, uint32_t terms, int we
                            weight_mode, out);
       }
       if ((rc = check_launch("k_density_points")) != Q4C_OK) return rc;
+    }
+  }
+  return Q4C_OK;
+}
+
+int launch_density_grad(const q4c_plan *p, const double *coef, double *out, double *gpart, hipStream_t s) {
+  int rc;
+  if (p->n_points > 0) {
+    {
+      TimedLaunch tl_(p, Q4C_TIMER_OTHER, s);
+      const unsigned nb = (unsigned)std::min<int64_t>((4 * p->n_points + 255) / 256, 65535);
+      hipLaunchKernelGGL(k_fill, dim3(nb), dim3(256), 0, s, out, 4 * p->n_points, 0.0);
+    }
+    if ((rc = check_launch("k_fill")) != Q4C_OK) return rc;
+  }
+  const LaunchCfg cfg = p->cfg_density;
+  const int32_t *order = cfg.order ? p->d_order : nullptr;
+  unsigned *tick0 = p->d_tickets + p->passes.size() * kTicketsPerLaunch;
+  if (cfg.persistent > 0) {
+    hipLaunchKernelGGL(k_zero_u32, dim3(8), dim3(256), 0, s, tick0, (int64_t)p->passes.size() * kTicketsPerLaunch);
+    if ((rc = check_launch("k_zero_u32")) != Q4C_OK) return rc;
+  }
+  for (size_t ip = 0; ip < p->passes.size(); ++ip) {
+    const Pass &ps = p->passes[ip];
+    const int64_t nw = ps.w1 - ps.w0, nbt = ps.b1 - ps.b0, nt = ps.t1 - ps.t0;
+    unsigned *tickets = cfg.persistent > 0 ? tick0 + ip * kTicketsPerLaunch : nullptr;
+    const unsigned grid = (unsigned)(cfg.persistent > 0 ? std::min<int64_t>(cfg.persistent, 2 * nw) : 2 * nw);
+    double *panel = p->d_staging + ps.staging_len + ps.partial_len;
+    if (nt > 0) {
+      {
+        TimedLaunch tl_(p, Q4C_TIMER_TABULATE, s);
+        hipLaunchKernelGGL(k_panel<false>, dim3((unsigned)nt), dim3(256), 0, s, p->dp, p->d_ptile, ps.t0, nt, panel);
+      }
+      if ((rc = check_launch("k_panel")) != Q4C_OK) return rc;
+    }
+    if (nw > 0) {
+      {
+        TimedLaunch tl_(p, Q4C_TIMER_DENSITY_TILES, s);
+        if (tickets)
+          hipLaunchKernelGGL((k_density_tiles<true, true>), dim3(grid), dim3(NTD), 0, s, p->dp, 0u, p->d_work, order,
+                             ps.w0, nw, coef, panel, gpart, tickets);
+        else
+          hipLaunchKernelGGL((k_density_tiles<false, true>), dim3(grid), dim3(NTD), 0, s, p->dp, 0u, p->d_work,
+                             order, ps.w0, nw, coef, panel, gpart, tickets);
+      }
+      if ((rc = check_launch("k_density_tiles<grad>")) != Q4C_OK) return rc;
+    }
+    if (nbt > 0) {
+      {
+        TimedLaunch tl_(p, Q4C_TIMER_DENSITY_POINTS, s);
+        hipLaunchKernelGGL(k_density_points_grad, dim3((unsigned)nbt), dim3(256), 0, s, p->dp, ps.b0, gpart, out);
+      }
+      if ((rc = check_launch("k_density_points_grad")) != Q4C_OK) return rc;
     }
   }
   return Q4C_OK;

@@ -1190,6 +1190,33 @@ int build_spinor_tables(const q4c_plan *pl, const q4c_plan *ps) {
     nS[a] = offS;
   }
   sp_off[pl->n_atoms] = (int32_t)fns.size();
+  // reverse relations: for every scalar function of each component, the
+  // spinor functions of its atom it enters, per spin (at most 4 for the large
+  // component: two m_l of the complex harmonic x two kappa; 2 for the small)
+  std::vector<int32_t> fL(pl->n_atoms, 0), fS(pl->n_atoms, 0);
+  for (int a = 1; a < pl->n_atoms; ++a) {
+    fL[a] = fL[a - 1] + nL[a - 1];
+    fS[a] = fS[a - 1] + nS[a - 1];
+  }
+  std::vector<q4c::ScalarRel> relL(pl->n_atoms ? fL.back() + nL.back() : 0),
+      relS(pl->n_atoms ? fS.back() + nS.back() : 0);
+  for (auto &r : relL) r = q4c::ScalarRel{};
+  for (auto &r : relS) r = q4c::ScalarRel{};
+  for (int a = 0; a < pl->n_atoms; ++a)
+    for (int mu = 0; mu < sp_off[a + 1] - sp_off[a]; ++mu) {
+      const q4c::SpinorFn &f = fns[sp_off[a] + mu];
+      const q4c::SpinorType &T = types[f.type];
+      for (int c = 0; c < 2; ++c)
+        for (int spin = 0; spin < 2; ++spin)
+          for (int k = 0; k < T.n[c][spin]; ++k) {
+            q4c::ScalarRel &r = c == 0 ? relL[fL[a] + f.offL + T.m[c][spin][k]] : relS[fS[a] + f.offS + T.m[c][spin][k]];
+            const int e = r.n[spin]++;
+            if (e >= 4) return fail(Q4C_EUNSUPPORTED, "spinor transform: more than 4 spinors per scalar function");
+            r.mu[spin][e] = mu;
+            r.re[spin][e] = T.re[c][spin][k];
+            r.im[spin][e] = T.im[c][spin][k];
+          }
+    }
   q4c_plan *mp = const_cast<q4c_plan *>(pl);  // device tables cached on the plan
   int rc;
   if ((rc = upload(mp, types, &mp->d_sp_types)) != Q4C_OK) return rc;
@@ -1197,8 +1224,12 @@ int build_spinor_tables(const q4c_plan *pl, const q4c_plan *ps) {
   if ((rc = upload(mp, sp_off, &mp->d_sp_off)) != Q4C_OK) return rc;
   if ((rc = upload(mp, nL, &mp->d_sp_nL)) != Q4C_OK) return rc;
   if ((rc = upload(mp, nS, &mp->d_sp_nS)) != Q4C_OK) return rc;
-  std::vector<int64_t> poffS(ps->pair_off.begin(), ps->pair_off.begin() + ps->n_pairs);
+  std::vector<int64_t> poffS(ps->pair_off.begin(), ps->pair_off.begin() + ps->n_pairs + 1);
   if ((rc = upload(mp, poffS, &mp->d_sp_poffS)) != Q4C_OK) return rc;
+  if ((rc = upload(mp, relL, &mp->d_sp_relL)) != Q4C_OK) return rc;
+  if ((rc = upload(mp, relS, &mp->d_sp_relS)) != Q4C_OK) return rc;
+  if ((rc = upload(mp, fL, &mp->d_sp_fL)) != Q4C_OK) return rc;
+  if ((rc = upload(mp, fS, &mp->d_sp_fS)) != Q4C_OK) return rc;
   pl->sp_small = ps;
   pl->sp_small_fn = ps->n_fn;
   pl->sp_small_len = ps->store_len;
@@ -1225,6 +1256,42 @@ int q4c_spinor_transform(const q4c_plan *pl, const q4c_plan *ps, const double *h
     }
   }
   return q4c::launch_spinor_transform(pl, hs_large_dev, hs_small_dev, h_dev, s_dev, (hipStream_t)stream);
+}
+
+int q4c_spinor_density_to_scalar(const q4c_plan *pl, const q4c_plan *ps, const double *d_dev, double *cl_dev,
+                                 double *cs_dev, void *stream) {
+  if (!pl || !ps) return fail(Q4C_EINVAL, "NULL plan");
+  int rc = check_plan_dev(ps);
+  if (rc != Q4C_OK) return rc;
+  if ((rc = check_plan_dev(pl)) != Q4C_OK) return rc;
+  if (ps->device != pl->device) return fail(Q4C_EINVAL, "spinor transform: plans on different devices");
+  if (pl->store_len > 0 && (!d_dev || !cl_dev)) return fail(Q4C_EINVAL, "NULL density or output");
+  if (ps->store_len > 0 && !cs_dev) return fail(Q4C_EINVAL, "NULL small-component output");
+  if (pl->sp_small != ps || pl->sp_small_fn != ps->n_fn || pl->sp_small_len != ps->store_len) {
+    if ((rc = build_spinor_tables(pl, ps)) != Q4C_OK) {
+      pl->sp_small = nullptr;
+      return rc;
+    }
+  }
+  return q4c::launch_spinor_to_scalar(pl, d_dev, cl_dev, cs_dev, (hipStream_t)stream);
+}
+
+int density_gradient_on_grid(const q4c_plan *p, const double *coef_dev, double *out_dev, void *stream) {
+  if (!p) return fail(Q4C_EINVAL, "NULL plan");
+  if (p->store_len > 0 && !coef_dev) return fail(Q4C_EINVAL, "NULL coefficients");
+  if (p->n_points > 0 && !out_dev) return fail(Q4C_EINVAL, "NULL output");
+  int rc = check_plan_dev(p);
+  if (rc != Q4C_OK) return rc;
+  if (!p->d_grad_partial) {
+    // four partials per point and column half: 4x the adjoint's partial region of the largest pass
+    int64_t mx = 0;
+    for (const auto &ps : p->passes) mx = std::max(mx, ps.partial_len);
+    void *ptr = nullptr;
+    if ((rc = device_alloc(const_cast<q4c_plan *>(p), (size_t)(4 * mx + 16) * sizeof(double), &ptr)) != Q4C_OK)
+      return rc;
+    p->d_grad_partial = (double *)ptr;
+  }
+  return q4c::launch_density_grad(p, coef_dev, out_dev, p->d_grad_partial, (hipStream_t)stream);
 }
 
 int q4c_integrate_HS(const q4c_plan *p, const double *v_dev, uint32_t flags, double *hs_dev, void *stream) {

@@ -1,4 +1,4 @@
-// Scalar -> spinor transformation of H and S (paper Sec. III A, Eq. 33, with
+// Scalar <-> spinor transformations.  Forward, of H and S (paper Sec. III A, Eq. 33, with
 // the transformation matrices of Eq. 14): for every atom pair (A, B),
 //   X+_AB = sum over components c (large, small) and spins s of
 //           G^c_A[s]^H X^c_AB G^c_B[s],      X = H, S,
@@ -84,6 +84,51 @@ __global__ __launch_bounds__(256) void k_spinor_transform(DevPlan d, const Spino
   }
 }
 
+// The reverse: scalar density matrices of one component from a spinor
+// density matrix D given on the pair blocks (same layout as the transform's
+// output), C_ij = f Re sum_spin sum_mu,nu conj(G_i,mu) D_mu,nu G_j,nu with
+// f = 2 on off-diagonal pairs (each stored block stands for its mirror).
+// One thread per element of the component's store.
+__global__ __launch_bounds__(256) void k_spinor_to_scalar(DevPlan d, const ScalarRel *rel, const int32_t *fofs,
+                                                          const int32_t *ncnt, const int64_t *poff, int64_t len,
+                                                          int64_t npairs, const int32_t *sp_off, const double *dsp,
+                                                          double *c_out) {
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < len; g += (int64_t)gridDim.x * blockDim.x) {
+    // pair of element g in this component's store: the last p with poff[p] <= g
+    int64_t lo = 0, hi = npairs - 1;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if (poff[mid] <= g)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const int64_t p = lo;
+    const int A = d.pair_a[p], B = d.pair_b[p];
+    const int e = (int)(g - poff[p]);
+    const int nBc = ncnt[B];                       // this component's functions on B
+    const int NB = sp_off[B + 1] - sp_off[B];      // spinor functions on B
+    const int i = e / nBc, j = e - i * nBc;
+    const ScalarRel &ri = rel[fofs[A] + i], &rj = rel[fofs[B] + j];
+    const double *D = dsp + 8 * d.pair_off[p];  // the pair's complex spinor block (re, im)
+    double acc = 0.0;
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp)
+      for (int k1 = 0; k1 < ri.n[sp]; ++k1) {
+        const double ar = ri.re[sp][k1], ai = ri.im[sp][k1];
+        const int64_t row = (int64_t)ri.mu[sp][k1] * NB;
+        for (int k2 = 0; k2 < rj.n[sp]; ++k2) {
+          const double br = rj.re[sp][k2], bi = rj.im[sp][k2];
+          // conj(a) b = (ar br + ai bi) + i (ar bi - ai br); the real part of that times D
+          const double wr = ar * br + ai * bi, wi = ar * bi - ai * br;
+          const int64_t o = 2 * (row + rj.mu[sp][k2]);
+          acc += wr * D[o] - wi * D[o + 1];
+        }
+      }
+    c_out[g] = (A == B ? 1.0 : 2.0) * acc;
+  }
+}
+
 }  // namespace
 
 int launch_spinor_transform(const q4c_plan *pl, const double *hs_large, const double *hs_small, double *h_out,
@@ -99,6 +144,30 @@ int launch_spinor_transform(const q4c_plan *pl, const double *hs_large, const do
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "k_spinor_transform");
+  return Q4C_OK;
+}
+
+}  // namespace q4c
+
+namespace q4c {
+
+int launch_spinor_to_scalar(const q4c_plan *pl, const double *d_spin, double *c_large, double *c_small,
+                            hipStream_t s) {
+  if (pl->n_pairs == 0) return Q4C_OK;
+  {
+    TimedLaunch tl_(pl, Q4C_TIMER_SPINOR, s);
+    const int64_t lenL = pl->store_len, lenS = pl->sp_store_len_S;
+    if (lenL > 0)
+      hipLaunchKernelGGL(k_spinor_to_scalar, dim3((unsigned)std::min<int64_t>((lenL + 255) / 256, 65536)), dim3(256),
+                         0, s, pl->dp, pl->d_sp_relL, pl->d_sp_fL, pl->d_sp_nL, pl->dp.pair_off, lenL, pl->n_pairs,
+                         pl->d_sp_off, d_spin, c_large);
+    if (lenS > 0)
+      hipLaunchKernelGGL(k_spinor_to_scalar, dim3((unsigned)std::min<int64_t>((lenS + 255) / 256, 65536)), dim3(256),
+                         0, s, pl->dp, pl->d_sp_relS, pl->d_sp_fS, pl->d_sp_nS, pl->d_sp_poffS, lenS, pl->n_pairs,
+                         pl->d_sp_off, d_spin, c_small);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "k_spinor_to_scalar");
   return Q4C_OK;
 }
 

@@ -248,3 +248,13 @@ def test_spinor_transform_needs_device_plans():
                                   ctypes.c_void_p(1), None)
     assert rc == q.Q4C_ENODEV
     assert lib.q4c_spinor_transform(None, p.handle, None, None, None, None, None) == q.Q4C_EINVAL
+
+
+def test_density_update_calls_need_device_plans():
+    q, lib = _lib()
+    wl = W.config_small(nrad=10, nang=26)
+    p = _host_plan(q, wl)
+    one = ctypes.c_void_p(1)
+    assert lib.q4c_spinor_density_to_scalar(p.handle, p.handle, one, one, one, None) == q.Q4C_ENODEV
+    assert lib.density_gradient_on_grid(p.handle, one, one, None) == q.Q4C_ENODEV
+    assert lib.density_gradient_on_grid(None, one, one, None) == q.Q4C_EINVAL

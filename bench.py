@@ -202,6 +202,45 @@ def bench_hs(wl, timed, steps: int, cpu_frac: float, with_cpu: bool, components=
                                    "peak": 8000.0, "unit": "GB/s", "frac": nbytes / (ms * 1e-3) / 8e12,
                                    "bytes_alg": nbytes}}
         log("spinor transform: %.3f ms, %.0f GB/s algorithmic" % (ms, nbytes / (ms * 1e-3) / 1e9))
+        # forward density update from a seeded spinor density matrix: the scalar
+        # density matrices of both components, then n and grad n of each
+        pairs_l, po_l = pl.pairs()
+        d_host = np.zeros((4 * Ll, 2))
+        for p_, blk in enumerate(W.spinor_density(wl_l, pairs_l, 5101)):
+            c_ = np.asarray(blk).reshape(-1)
+            d_host[4 * po_l[p_]:4 * po_l[p_ + 1], 0] = c_.real
+            d_host[4 * po_l[p_]:4 * po_l[p_ + 1], 1] = c_.imag
+        d_sp = torch.from_numpy(d_host).to(dev)
+        cl = torch.empty(Ll, dtype=torch.float64, device=dev)
+        cs = torch.empty(Ls, dtype=torch.float64, device=dev)
+        gl = torch.empty((4, pl.info["n_points"]), dtype=torch.float64, device=dev)
+        gs = torch.empty((4, ps.info["n_points"]), dtype=torch.float64, device=dev)
+
+        def upd():
+            q.q4c_spinor_density_to_scalar(pl, ps, d_sp, cl, cs)
+            q.density_gradient_on_grid(pl, cl, gl)
+            q.density_gradient_on_grid(ps, cs, gs)
+        upd()
+        ms_upd = timed(upd, steps)
+        dens = {"ms": ms_upd, "points_per_s": pl.info["n_active"] / (ms_upd * 1e-3)}
+        for cname, plan_, c_, g_ in (("large", pl, cl, gl), ("small", ps, cs, gs)):
+            plan_.profile(True)
+            for _ in range(steps):
+                q.density_gradient_on_grid(plan_, c_, g_)
+            tim = plan_.timers()
+            plan_.profile(False)
+            nt = max(tim["density_tiles"][1], 1)
+            t_t = tim["density_tiles"][0] / nt * 1e-3
+            per = tim["density_tiles"][1] / steps
+            f_alg = 0.4 * plan_.info["flops_alg"]  # sum_B 4 P n^2: C^T phi and C^T grad phi
+            ach = f_alg / per / t_t
+            dens[cname] = {"kernels_ms_per_call": {k: v_[0] / steps for k, v_ in tim.items() if v_[1]},
+                           "roofline": {"kernel": "k_density_tiles<grad>", "bound": "mfma", "achieved": ach / 1e12,
+                                        "peak": PEAK_F64 / 1e12, "unit": "TFLOP/s", "frac": ach / PEAK_F64,
+                                        "avg_launch_ms": t_t * 1e3, "launches_per_call": per,
+                                        "flops_alg_per_call": f_alg}}
+        out["density_update"] = dens
+        log("density update (D -> scalar, n and grad n of both components): %.3f ms" % ms_upd)
     kept.clear()
     if with_cpu:
         import oracle

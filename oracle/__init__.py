@@ -449,3 +449,35 @@ def density_grad(wl, pairs, coef_blocks, idx=None):
     lib.orc_density_grad_points(h.ptr, x.size, _dp(x), _dp(y), _dp(z), int(pairs.shape[0]), _ip(pa), _ip(pb),
                                 _dp(coef), _dp(out))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Periodic systems: Bloch sums of unit-cell integrals (Sec. II C, Eq. 26-28)
+# ---------------------------------------------------------------------------
+
+def bloch_sum(cell_atom, shift, pairs, blocks, k_points):
+    """O_ab(k) = sum over ordered pairs (A', B') of image atoms of the cell
+    atoms a, b of exp(i k.(T_B' - T_A')) O_A'B' (the unit-cell integrals of
+    the image-extended system summed with the Bloch phases; Eq. 27 with the
+    restricted sum of Eq. 28).  blocks: per stored pair (A' <= B') float64
+    [n_parts, nA', nB']; the other orientation is O_B'A' = s_q O_A'B'^T with
+    s_q = -1 for the spin-orbit parts q >= 2 of a five-part store, +1
+    otherwise.  k_points: [n_k, 3] (bohr^-1); shift: [n_atoms, 3] (bohr).
+    Returns {(a, b): complex128[n_k, n_parts, n_a, n_b]} for a <= b."""
+    k_points = np.asarray(k_points, dtype=np.float64).reshape(-1, 3)
+    out = {}
+    for p, (A, B) in enumerate(pairs):
+        blk = np.asarray(blocks[p])
+        npart = blk.shape[0]
+        sgn = np.array([(-1.0 if (npart == 5 and q >= 2) else 1.0) for q in range(npart)])
+        orients = [(A, B, blk)]
+        if A != B:
+            orients.append((B, A, sgn[:, None, None] * np.transpose(blk, (0, 2, 1))))
+        for (X, Y, M) in orients:
+            a, b = int(cell_atom[X]), int(cell_atom[Y])
+            if a > b:
+                continue
+            ph = np.exp(1j * (k_points @ (np.asarray(shift[Y]) - np.asarray(shift[X]))))
+            acc = out.setdefault((a, b), np.zeros((k_points.shape[0],) + M.shape, dtype=np.complex128))
+            acc += ph[:, None, None, None] * M[None]
+    return out

@@ -335,9 +335,11 @@ def custom_basis(Z, shells_per_atom, rcut, nint, tapered=True):
 # ----------------------------------------------------------------------------
 
 def atom_grids(R: np.ndarray, Z: np.ndarray, nrad_of, nang_of, seed: int, r_comp: float,
-               rm: float = 1.0, chunk_atoms: Optional[int] = None):
+               rm: float = 1.0, chunk_atoms: Optional[int] = None, R_partition: Optional[np.ndarray] = None):
     """Overlapping atom-centred grids (radial shells x rotated Fibonacci sphere)
-    with Becke partition weights.  Returns x, y, z, w, owner."""
+    with Becke partition weights.  Returns x, y, z, w, owner.  R_partition
+    (optional) is the atom list the partition runs over; atoms of R must be its
+    first entries (periodic cells: the cell's atoms, then their images)."""
     rng = np.random.default_rng(np.random.PCG64(seed))
     xs, ys, zs, ws, own = [], [], [], [], []
     cache = {}
@@ -359,7 +361,7 @@ def atom_grids(R: np.ndarray, Z: np.ndarray, nrad_of, nang_of, seed: int, r_comp
     z = np.ascontiguousarray(np.concatenate(zs))
     wq = np.concatenate(ws)
     owner = np.ascontiguousarray(np.concatenate(own))
-    wb = becke(R, x, y, z, owner, r_comp)
+    wb = becke(R if R_partition is None else R_partition, x, y, z, owner, r_comp)
     return x, y, z, np.ascontiguousarray(wq * wb), owner
 
 
@@ -785,6 +787,100 @@ def small_component(wl: Workload, seed: int, alpha_range=(0.3, 30.0)) -> Workloa
         shell_alpha=np.array(sa).reshape(-1, 3), shell_gcoef=np.array(sc).reshape(-1, 3),
         shell_u_off=None, u_coef=None, shell_eps=None)
     return ket_tables(ws, np.array(eps))
+
+
+# ----------------------------------------------------------------------------
+# Periodic cells (the paper's solids: Sec. II C, Sec. III A)
+# ----------------------------------------------------------------------------
+
+def periodic_noise(lat, x, y, z, seed: int, amp: float = 1e-2, nwaves: int = 8):
+    """amp * (1/8) sum_k cos(G_k . r + phi_k) with G_k reciprocal lattice vectors
+    2 pi L^-T n, n integer in [-2, 2]^3 (not 0): lattice-periodic noise."""
+    rng = np.random.default_rng(np.random.PCG64(seed))
+    B = 2.0 * np.pi * np.linalg.inv(np.asarray(lat)).T
+    out = np.zeros_like(x)
+    for _ in range(nwaves):
+        n = np.zeros(3)
+        while not np.any(n):
+            n = rng.integers(-2, 3, size=3).astype(np.float64)
+        G = B @ n
+        ph = rng.uniform(0.0, 2.0 * np.pi)
+        out += np.cos(G[0] * x + G[1] * y + G[2] * z + ph)
+    return amp * out / nwaves
+
+
+CSPBBR3_CELL = ((55, (0.0, 0.0, 0.0)), (82, (0.5, 0.5, 0.5)), (35, (0.5, 0.5, 0.0)), (35, (0.5, 0.0, 0.5)),
+                (35, (0.0, 0.5, 0.5)))  # cubic perovskite ABX3: A corner, B body centre, X face centres
+
+
+def config_periodic(cells=(1, 1, 1), a_ang: float = 5.87, species=CSPBBR3_CELL, recipe: str = "main",
+                    nrad: int = 40, nang: int = 110, k: int = 6, nint: int = 512, rcut_ang: float = 6.0,
+                    distort_ang: float = 0.1):
+    """A periodic cubic-perovskite cell (CsPbBr3-like: the paper's benchmark
+    solid), n1 x n2 x n3 primitive cells with seeded displacements, as a plan
+    workload: the cell's atoms first, then every periodic image whose
+    functions reach the cell (its distance to the cell box below the cutoff).
+    The grid holds the cell atoms' grids only, with Becke weights over all
+    atoms (cell and images), so it integrates exactly one cell of a periodic
+    integrand; v is the cut-and-shifted smeared-nucleus potential of every atom
+    within 12 angstrom plus smooth noise.  meta: n_cell_atoms, cell_atom
+    (image -> cell atom), shift (lattice translation of each atom, bohr),
+    lattice (rows = lattice vectors, bohr).  The Becke competing radius is 5
+    angstrom (as for the slabs)."""
+    rng = np.random.default_rng(np.random.PCG64(1000 + k))
+    n1, n2, n3 = cells
+    a = a_ang * ANGSTROM
+    lat = np.diag([n1 * a, n2 * a, n3 * a])
+    Zc, Rc = [], []
+    for i in range(n1):
+        for j in range(n2):
+            for l in range(n3):
+                for z, f in species:
+                    Zc.append(z)
+                    Rc.append((np.array([i, j, l], dtype=np.float64) + np.array(f)) * a)
+    Zc = np.array(Zc, dtype=np.int32)
+    Rc = np.array(Rc) + rng.uniform(-1, 1, size=(len(Zc), 3)) * distort_ang * ANGSTROM
+    rcut = rcut_ang * ANGSTROM
+    lo, hi = np.zeros(3), np.diag(lat)
+
+    def images(reach):
+        out = []
+        m = [int(np.ceil(reach / lat[d, d])) + 1 for d in range(3)]
+        for t1 in range(-m[0], m[0] + 1):
+            for t2 in range(-m[1], m[1] + 1):
+                for t3 in range(-m[2], m[2] + 1):
+                    if t1 == t2 == t3 == 0:
+                        continue
+                    T = np.array([t1, t2, t3], dtype=np.float64) @ lat
+                    for c in range(len(Zc)):
+                        p = Rc[c] + T
+                        if np.linalg.norm(p - np.clip(p, lo, hi)) < reach:
+                            out.append((c, T))
+        return out
+
+    img = images(rcut)
+    r_comp = 5.0 * ANGSTROM
+    Z = np.concatenate([Zc, np.array([Zc[c] for c, _ in img], dtype=np.int32)]).astype(np.int32)
+    R = np.concatenate([Rc, np.array([Rc[c] + T for c, T in img]).reshape(-1, 3)])
+    cell_atom = np.concatenate([np.arange(len(Zc)), np.array([c for c, _ in img], dtype=np.int64)]).astype(np.int32)
+    shift = np.concatenate([np.zeros((len(Zc), 3)), np.array([T for _, T in img]).reshape(-1, 3)])
+    basis = make_basis(Z, recipe, 2000 + k, rcut, nint)
+    # partition over every atom a competing radius away from any point where a
+    # function of the plan lives (those lie within 2 rcut of the cell)
+    pimg = images(2 * rcut + r_comp + 1.0)
+    Rw = np.concatenate([R, np.array([Rc[c] + T for c, T in pimg
+                                      if not any(c == c2 and np.allclose(T, T2) for c2, T2 in img)]).reshape(-1, 3)])
+    grid = atom_grids(Rc, Zc, lambda z: nrad, lambda z: nang, 3000 + k, r_comp=r_comp, R_partition=Rw)
+    # potential: every atom within 12 angstrom of such points, cut and shifted at 12 angstrom
+    vimg = images(2 * rcut + 12.0 * ANGSTROM + 1.0)
+    Rp = np.concatenate([Rc, np.array([Rc[c] + T for c, T in vimg]).reshape(-1, 3)])
+    Zp = np.concatenate([Zc, np.array([Zc[c] for c, _ in vimg], dtype=np.int32)])
+    v = model_potential(Rp, Zp, grid[0], grid[1], grid[2], r_cut=12.0 * ANGSTROM)
+    v = v + periodic_noise(lat, grid[0], grid[1], grid[2], 4000 + k)
+    return _assemble("periodic-%dx%dx%d" % tuple(cells), Z, R, basis, grid, v,
+                     meta=dict(config="periodic-perovskite-%dx%dx%d" % tuple(cells), p_max=300,
+                               n_cell_atoms=len(Zc), cell_atom=cell_atom, shift=shift, lattice=lat,
+                               seeds=dict(geometry=1000 + k, basis=2000 + k, grid=3000 + k, noise=4000 + k)))
 
 
 def pin_workload(Z, R_bohr, shells_per_atom, nrad=300, ntheta=12, nphi=24, rcut=6.0 * ANGSTROM, nint=2048,

@@ -481,3 +481,34 @@ def bloch_sum(cell_atom, shift, pairs, blocks, k_points):
             acc = out.setdefault((a, b), np.zeros((k_points.shape[0],) + M.shape, dtype=np.complex128))
             acc += ph[:, None, None, None] * M[None]
     return out
+
+
+def bloch_density(cell_atom, shift, pairs, rho, k_points, k_weights, nfn):
+    """Density-matrix coefficients on the stored image pairs from k-space
+    density matrices (Sec. II C, the periodic density matrix and density):
+    D_A'B' = sum_k w_k exp(i k.(T_B' - T_A')) rho_ab(k), a, b the cell atoms
+    of A', B', with rho_ab(k) = rho_ba(k)^H when a > b (Hermitian rho, e.g.
+    sum_l f_l C*_al C_bl).  The density of the extended system is
+    n(r) = Re sum over ordered image pairs D phi phi; with the stored pairs
+    (A' <= B') standing for both orders the coefficient of a stored element is
+    f Re D_A'B' with f = 2 for A' != B' and 1 for A' = B'.
+    rho: {(a, b): complex128[n_k, n_parts, n_a, n_b]} for a <= b (the layout
+    of bloch_sum's output); nfn: functions per plan atom.
+    Returns per stored pair float64 [n_parts, nA', nB']."""
+    k_points = np.asarray(k_points, dtype=np.float64).reshape(-1, 3)
+    k_weights = np.asarray(k_weights, dtype=np.float64).reshape(-1)
+    n_parts = next(iter(rho.values())).shape[1]
+    out = []
+    for A, B in pairs:
+        a, b = int(cell_atom[A]), int(cell_atom[B])
+        if a <= b:
+            r = rho[(a, b)]                                      # [n_k, n_parts, nA, nB]
+        else:
+            r = np.conj(np.transpose(rho[(b, a)], (0, 1, 3, 2)))  # rho_ab = rho_ba^H
+        ph = k_weights * np.exp(1j * (k_points @ (np.asarray(shift[B]) - np.asarray(shift[A]))))
+        D = np.einsum("k,kqij->qij", ph, r)
+        f = 1.0 if A == B else 2.0
+        blk = f * D.real
+        assert blk.shape == (n_parts, int(nfn[A]), int(nfn[B]))
+        out.append(blk)
+    return out

@@ -75,7 +75,7 @@ def parse():
     ap.add_argument("--mode", choices=["full", "step", "forward", "adjoint", "hs"], default="full",
                     help="step/forward/adjoint: run only the whole step or that one call `steps` times "
                          "(for profiler runs) and print its time; hs: only the H/S leg")
-    ap.add_argument("--workload", choices=["cluster", "slab", "pepi", "molecules"], default="cluster",
+    ap.add_argument("--workload", choices=["cluster", "slab", "pepi", "molecules", "periodic"], default="cluster",
                     help="molecules: 64 independent molecules (8..80 atoms), one batched plan (autotuned launch "
                          "shapes, HIP graph replay) against 64 sequential per-molecule plans; prints its own line")
     ap.add_argument("--contract-order", type=int, choices=[0, 1], default=None,
@@ -393,6 +393,8 @@ def main():
         wl = W.config_slab()
     elif a.workload == "pepi":
         wl = W.config_pepi_3383()
+    elif a.workload == "periodic":
+        wl = W.config_periodic(cells=(2, 2, 2), nrad=60, nang=302)
     else:
         wl = W.config_cluster(n_atoms=a.n_atoms)
     t_gen = time.perf_counter() - t0
@@ -543,7 +545,8 @@ def main():
         "config": {
             "workload": "%s, %d atoms, %d NAOs, %d points (%d active), %d batches <= 300 pts" %
                         ({"cluster": "random cluster (Pb/I/H,C,N)", "slab": "perovskite-like slab",
-                          "pepi": "(6x6)x2 perovskite-like slab"}[a.workload],
+                          "pepi": "(6x6)x2 perovskite-like slab",
+                          "periodic": "periodic 2x2x2 CsPbBr3-like supercell (40 atoms) with its images"}[a.workload],
                          wl.n_atoms, info["n_fn"], info["n_points"], n_act, info["n_batches"]),
             "precision": a.precision,
             "step": "q4c_integrate_H (all parts + W spinor) + density_on_grid (adjoint, all terms)",
@@ -572,6 +575,59 @@ def main():
         "workload_gen_s": t_gen,
         "wall_timed_s": wall,
     }
+    if a.workload == "periodic":
+        # Bloch sums of the store at 8 seeded k-points (Sec. II C)
+        m = wl.meta
+        plan.set_cells(m["n_cell_atoms"], m["cell_atom"], m["shift"])
+        cpa, cpo = plan.cell_pairs()
+        B = 2 * np.pi * np.linalg.inv(m["lattice"]).T
+        kp = np.random.default_rng(8601).uniform(-0.5, 0.5, size=(8, 3)) @ B.T
+        bout = torch.empty((kp.shape[0], 5, int(cpo[-1]), 2), dtype=torch.float64, device=dev)
+        q.q4c_integrate_H(plan, v, prec, 0, store)
+        bl = lambda: q.q4c_bloch_sum(plan, 5, store, kp, bout)
+        bl()
+        nrep = max(3, a.steps // 4)
+        ms_b = timed(bl, nrep)
+        # k_bloch_sum alone (HIP events on the launch stream): algorithmic
+        # bytes = the 5 store parts read once + the complex output written once
+        plan.profile(True)
+        for _ in range(nrep):
+            bl()
+        tim = plan.timers()
+        plan.profile(False)
+        k_ms = tim["bloch"][0] / max(1, tim["bloch"][1])
+        alg_b = 8.0 * 5 * plan.info["store_len"] + 16.0 * kp.shape[0] * 5 * int(cpo[-1])
+        res["bloch"] = {"n_k": int(kp.shape[0]), "ms_per_call": ms_b, "cell_atoms": int(m["n_cell_atoms"]),
+                        "cell_pairs": int(len(cpa)), "cell_store_len": int(cpo[-1]),
+                        "k_bloch_sum_ms": k_ms, "alg_bytes": alg_b,
+                        "roofline": {"bound": "hbm", "achieved": alg_b / (k_ms * 1e-3) / 1e9, "peak": 8000.0,
+                                     "unit": "GB/s", "frac": alg_b / (k_ms * 1e-3) / 1e9 / 8000.0}}
+        log("Bloch sums: %d k-points x 5 parts x %d elements: %.3f ms per call, k_bloch_sum %.3f ms (%.0f GB/s alg.)"
+            % (kp.shape[0], int(cpo[-1]), ms_b, k_ms, alg_b / (k_ms * 1e-3) / 1e9))
+        # the reverse: one k-space density matrix part at the same k-points
+        # (seeded values; the kernel's work does not depend on them) to
+        # coefficients on the stored image pairs.  Algorithmic bytes: rho read
+        # once + the coefficients written once.
+        rho = torch.from_numpy(np.random.default_rng(8602).standard_normal((kp.shape[0], 1, int(cpo[-1]), 2))).to(dev)
+        kw = np.full(kp.shape[0], 1.0 / kp.shape[0])
+        coef_k = torch.empty((1, plan.info["store_len"]), dtype=torch.float64, device=dev)
+        bd = lambda: q.q4c_bloch_density(plan, 1, rho, kp, kw, coef_k)
+        bd()
+        ms_d = timed(bd, nrep)
+        plan.profile(True)
+        for _ in range(nrep):
+            bd()
+        tim = plan.timers()
+        plan.profile(False)
+        kd_ms = tim["bloch"][0] / max(1, tim["bloch"][1])
+        alg_d = 16.0 * kp.shape[0] * int(cpo[-1]) + 8.0 * plan.info["store_len"]
+        res["bloch"]["density_matrix"] = {
+            "ms_per_call": ms_d, "k_bloch_density_ms": kd_ms, "alg_bytes": alg_d,
+            "reads_per_k_bytes": 16.0 * plan.info["store_len"],
+            "roofline": {"bound": "hbm", "achieved": alg_d / (kd_ms * 1e-3) / 1e9, "peak": 8000.0, "unit": "GB/s",
+                         "frac": alg_d / (kd_ms * 1e-3) / 1e9 / 8000.0}}
+        log("Bloch density matrix: %d k-points -> %d stored elements: %.3f ms per call, k_bloch_density %.3f ms"
+            % (kp.shape[0], plan.info["store_len"], ms_d, kd_ms))
     if not a.no_hs and a.workload == "cluster":
         res["hs"] = bench_hs(wl, timed, a.steps, 0.2 * a.cpu_sample, not a.no_cpu_baseline)
     if not a.no_cpu_baseline and a.workload == "cluster":

@@ -302,6 +302,64 @@ int q4c_spinor_density_to_scalar(const q4c_plan *plan_large, const q4c_plan *pla
  * largest pass). */
 int density_gradient_on_grid(const q4c_plan *plan, const double *coef_dev, double *out_dev, void *stream);
 
+/* Periodic systems (paper Sec. II C).  A plan for a solid holds the atoms of
+ * a reference cell and those of their periodic images whose functions reach
+ * the cell, with a grid that covers the cell once (its own atoms' grids,
+ * partitioned over all atoms); its integrals are then the unit-cell
+ * integrals O^uc of Eq. 26 between every pair of those functions.
+ *
+ * q4c_plan_set_cells: for every atom a of the plan, the reference-cell atom
+ * it copies (cell_atom[a] in 0..n_cell_atoms-1) and its lattice translation
+ * T(a) (shift[3a..3a+2], bohr; zero for the cell's own atoms).  Host arrays,
+ * copied.  Q4C_EINVAL if an index is out of range, a shift is not finite, a
+ * cell atom has no copy, or an image's basis differs from its cell atom's;
+ * Q4C_EUNSUPPORTED on a batched plan. */
+int q4c_plan_set_cells(q4c_plan *plan, int32_t n_cell_atoms, const int32_t *cell_atom, const double *shift);
+
+/* The output layout of q4c_bloch_sum: the cell pairs (a, b), a <= b, that at
+ * least one stored pair of their images reaches, in ascending (a, b) order,
+ * and the offsets of their n_a x n_b blocks (n_cell_pairs + 1 entries).
+ * Any pointer may be NULL. */
+int q4c_plan_cell_pairs(const q4c_plan *plan, int64_t *n_cell_pairs, int32_t *pair_atoms, int64_t *pair_off);
+
+/* q4c_bloch_sum: the Bloch sums (Eq. 27 with the restricted sum of Eq. 28)
+ *   O_ab(k) = sum over pairs (a', b') of images of a and b of
+ *             exp(i k.(T(b') - T(a'))) O^uc_a'b'
+ * of the first n_parts parts of a store of this plan (device; n_parts 1, 2
+ * or 5: a q4c_integrate_H store, whose parts 2..4 are antisymmetric, or a
+ * q4c_integrate_HS output, n_parts <= 2; Q4C_EINVAL otherwise), at n_k
+ * k-points (host, 3 n_k, bohr^-1).  out_dev (device, complex128 as re, im):
+ * [n_k][n_parts][cell store length] with the blocks at the cell-pair
+ * offsets, row-major; O_ba(k) = O_ab(k)^H (symmetric parts) is implied.
+ * Q4C_EINVAL without q4c_plan_set_cells.  Copies the k-points and waits for
+ * that copy.  The k-points and their phases exp(i k.T) (64 k-points at a
+ * time, 16 bytes per contribution and k-point) live in plan-owned device
+ * buffers, allocated on first use and grown on demand: calls on one plan must
+ * not overlap. */
+int q4c_bloch_sum(const q4c_plan *plan, int32_t n_parts, const double *store_dev, int32_t n_k,
+                  const double *k_points, double *out_dev, void *stream);
+
+/* q4c_bloch_density: the reverse of q4c_bloch_sum, the periodic density
+ * matrix of Sec. II C.  From k-space density matrices rho(k) of the cell's
+ * functions (Hermitian, e.g. sum over states of f_l C*_al(k) C_bl(k)), the
+ * real-space density matrix of every stored image pair (A', B'),
+ *   D_A'B' = sum_k w_k exp(i k.(T(B') - T(A'))) rho_ab(k),
+ * a, b the cell atoms of A', B', rho_ab = rho_ba^H when a > b, returned as the
+ * coefficients the density calls take: coef = f Re D, f = 2 for A' != B'
+ * (the stored block stands for both orders) and 1 for A' = B'.  Then
+ * density_gradient_on_grid (n_parts 1) or density_on_grid give the density of
+ * the extended system on the cell's grid.
+ * rho_dev: device complex128 (re, im) [n_k][n_parts][cell store length] in the
+ * layout of q4c_bloch_sum's output (blocks of the cell pairs a <= b only);
+ * n_parts 1 or 2 (Hermitian parts, e.g. one scalar density matrix per
+ * component), else Q4C_EINVAL.  k_points (host, 3 n_k, bohr^-1), k_weights
+ * (host, n_k).  coef_out_dev (device, n_parts store_len doubles) is
+ * overwritten; n_k = 0 gives zeros.  Shares the k and phase buffers of
+ * q4c_bloch_sum (calls on one plan must not overlap) and waits for the
+ * k-point copy. */
+int q4c_bloch_density(const q4c_plan *plan, int32_t n_parts, const double *rho_dev, int32_t n_k,
+                      const double *k_points, const double *k_weights, double *coef_out_dev, void *stream);
+
 /* Coefficients on the stored elements from a Hermitian spinor density matrix
  * D given as spinor blocks (device complex128, 4 store_len, spinor layout)
  * such that density_on_grid yields Re Tr(D H) derivatives (Eq. 21/39):
@@ -320,7 +378,7 @@ enum {
   Q4C_TIMER_CONTRACT = 1,
   Q4C_TIMER_REDUCE = 2,
   Q4C_TIMER_SPINOR = 3,
-  Q4C_TIMER_BROADCAST = 4,   /* reserved (no kernel of this kind runs) */
+  Q4C_TIMER_BLOCH = 4,       /* k_bloch_sum of q4c_bloch_sum (its phase kernel counts as other) */
   Q4C_TIMER_DENSITY_TILES = 5,
   Q4C_TIMER_DENSITY_POINTS = 6,
   Q4C_TIMER_OTHER = 7,

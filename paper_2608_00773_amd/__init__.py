@@ -20,7 +20,7 @@ Q4C_OK = 0
 Q4C_EINVAL, Q4C_ENOMEM, Q4C_EHIP, Q4C_ENOTIMPL, Q4C_EUNSUPPORTED, Q4C_ESIZE, Q4C_ENONFINITE, Q4C_ENODEV = \
     -1, -2, -3, -4, -5, -6, -7, -8
 PREC_F64, PREC_SPLIT_F32, PREC_F32 = 0, 1, 2
-TIMER_NAMES = ("tabulate", "contract", "reduce", "spinor", "broadcast", "density_tiles", "density_points", "other")
+TIMER_NAMES = ("tabulate", "contract", "reduce", "spinor", "bloch", "density_tiles", "density_points", "other")
 ACCUMULATE, ASSEMBLE_W, ASSEMBLE_V, CHECK_FINITE = 1, 2, 4, 8
 PLAN_HOST_ONLY = 1
 TERM_LL, TERM_SS, TERM_SO, TERM_ALL = 1, 2, 4, 7
@@ -82,7 +82,8 @@ EXPORTS = ("q4c_plan_create", "q4c_plan_destroy", "q4c_plan_info", "q4c_plan_pai
            "q4c_plan_sync", "q4c_plan_profile", "q4c_plan_timers", "q4c_plan_split_stats", "q4c_status_string",
            "q4c_last_error", "q4c_plan_create_batched", "q4c_plan_systems", "q4c_plan_set_launch",
            "q4c_plan_get_launch", "q4c_plan_autotune", "q4c_plan_set_graphs", "q4c_plan_set_ket_potential",
-           "q4c_integrate_HS", "q4c_spinor_transform", "q4c_spinor_density_to_scalar", "density_gradient_on_grid")
+           "q4c_integrate_HS", "q4c_spinor_transform", "q4c_spinor_density_to_scalar", "density_gradient_on_grid",
+           "q4c_plan_set_cells", "q4c_plan_cell_pairs", "q4c_bloch_sum", "q4c_bloch_density")
 
 
 def _load():
@@ -123,6 +124,10 @@ def _load():
         lib.q4c_spinor_transform.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         lib.q4c_spinor_density_to_scalar.argtypes = [vp, vp, vp, vp, vp, vp]
         lib.density_gradient_on_grid.argtypes = [vp, vp, vp, vp]
+        lib.q4c_plan_set_cells.argtypes = [vp, i32, vp, vp]
+        lib.q4c_plan_cell_pairs.argtypes = [vp, ctypes.POINTER(i64), vp, vp]
+        lib.q4c_bloch_sum.argtypes = [vp, i32, vp, i32, vp, vp, vp]
+        lib.q4c_bloch_density.argtypes = [vp, i32, vp, i32, vp, vp, vp, vp]
         lib.q4c_status_string.argtypes = [ctypes.c_int]
         lib.q4c_status_string.restype = ctypes.c_char_p
         lib.q4c_last_error.argtypes = []
@@ -301,6 +306,22 @@ class Plan:
         tab = np.ascontiguousarray(np.concatenate(tabs))
         _check(_load().q4c_plan_set_ket_potential(self._h, off.ctypes.data, int(tab.size), tab.ctypes.data))
 
+    def set_cells(self, n_cell_atoms: int, cell_atom, shift):
+        """Periodic cell map (q4c_plan_set_cells): cell atom and lattice
+        translation (bohr) of every atom of the plan."""
+        ca = np.ascontiguousarray(cell_atom, dtype=np.int32)
+        sh = np.ascontiguousarray(shift, dtype=np.float64).reshape(-1)
+        _check(_load().q4c_plan_set_cells(self._h, int(n_cell_atoms), ca.ctypes.data, sh.ctypes.data))
+
+    def cell_pairs(self):
+        """(pair_atoms int32[n, 2], pair_off int64[n + 1]) of the Bloch-sum output."""
+        n = ctypes.c_int64()
+        _check(_load().q4c_plan_cell_pairs(self._h, ctypes.byref(n), None, None))
+        pa = np.zeros((n.value, 2), dtype=np.int32)
+        po = np.zeros(n.value + 1, dtype=np.int64)
+        _check(_load().q4c_plan_cell_pairs(self._h, ctypes.byref(n), pa.ctypes.data, po.ctypes.data))
+        return pa, po
+
     def set_launch(self, kernel: int, order: int, persistent: int):
         _check(_load().q4c_plan_set_launch(self._h, int(kernel), int(order), int(persistent)))
 
@@ -386,6 +407,38 @@ def density_gradient_on_grid(plan: Plan, coef, out):
     _check(_load().density_gradient_on_grid(plan.handle, _dev_ptr(coef, min_numel=plan.info["store_len"], name="coef"),
                                             _dev_ptr(out, min_numel=4 * plan.info["n_points"], name="out"),
                                             _stream_handle()))
+    return out
+
+
+def q4c_bloch_sum(plan: Plan, n_parts: int, store, k_points, out):
+    """Bloch sums of the first n_parts parts of `store` at k_points ([n_k, 3],
+    host) into out ([n_k, n_parts, cell_len, 2] float64, complex as re, im)."""
+    kp = np.ascontiguousarray(k_points, dtype=np.float64).reshape(-1, 3)
+    _, po = plan.cell_pairs()
+    _check(_load().q4c_bloch_sum(plan.handle, int(n_parts), _dev_ptr(store, min_numel=n_parts * plan.info["store_len"],
+                                                                     name="store"),
+                                 int(kp.shape[0]), kp.ctypes.data,
+                                 _dev_ptr(out, min_numel=2 * kp.shape[0] * n_parts * int(po[-1]), name="out"),
+                                 _stream_handle()))
+    return out
+
+
+def q4c_bloch_density(plan: Plan, n_parts: int, rho, k_points, k_weights, out):
+    """Coefficients on the stored image pairs (n_parts x store_len, device)
+    from k-space density matrices rho ([n_k, n_parts, cell_len, 2] float64,
+    device, the layout of q4c_bloch_sum's output) at k_points ([n_k, 3]) with
+    weights k_weights ([n_k]) (host)."""
+    kp = np.ascontiguousarray(k_points, dtype=np.float64).reshape(-1, 3)
+    kw = np.ascontiguousarray(k_weights, dtype=np.float64).reshape(-1)
+    if kw.size != kp.shape[0]:
+        raise ValueError("one weight per k-point")
+    _, po = plan.cell_pairs()
+    nk = int(kp.shape[0])
+    rp = _dev_ptr(rho, min_numel=2 * nk * n_parts * int(po[-1]), name="rho") if nk > 0 else None
+    _check(_load().q4c_bloch_density(plan.handle, int(n_parts), rp, nk, kp.ctypes.data if nk else None,
+                                     kw.ctypes.data if nk else None,
+                                     _dev_ptr(out, min_numel=n_parts * plan.info["store_len"], name="out"),
+                                     _stream_handle()))
     return out
 
 

@@ -210,6 +210,24 @@ struct q4c_plan {
   mutable int32_t *d_sp_fL = nullptr, *d_sp_fS = nullptr;  // [n_atoms] first scalar function of each atom
   mutable int64_t sp_store_len_S = 0;
 
+  // ---- periodic cells (q4c_plan_set_cells): cell pairs a <= b of the
+  // reference cell's atoms and the stored pairs contributing to each
+  int32_t n_cell_atoms = 0;
+  std::vector<int32_t> cell_atom;       // [n_atoms]
+  std::vector<int32_t> cp_a, cp_b;      // [n_cell_pairs]
+  std::vector<int64_t> cp_off;          // [n_cell_pairs + 1] block offsets (n_a n_b each)
+  int32_t *d_cp_a = nullptr, *d_cp_b = nullptr;
+  int64_t *d_cp_off = nullptr, *d_ct_off = nullptr;  // contributions of cell pair c: [ct_off[c], ct_off[c+1])
+  int32_t *d_ct_pair = nullptr, *d_ct_flag = nullptr;  // stored pair; 1: transposed orientation
+  double *d_ct_T = nullptr;             // [3 per contribution] translation of the phase exp(i k.T)
+  int64_t n_contrib = 0;                // contributions over all cell pairs
+  int32_t *d_pc_cp = nullptr, *d_pc_flag = nullptr;  // per stored pair: cell pair; 1: reached transposed (a > b)
+  double *d_pc_T = nullptr;             // [3 per stored pair] T_B' - T_A'
+  mutable double *d_kpts = nullptr;     // k-points (3 n_k) and weights (n_k) of the last call (grown on demand)
+  mutable int64_t kpts_cap = 0;
+  mutable double *d_bloch_ph = nullptr; // phases of one k chunk: kBlochKChunk max(n_contrib, n_pairs) complex
+  mutable int64_t bloch_ph_cap = 0;     // doubles
+
   // ---- density gradient partials (density_gradient_on_grid), allocated on first use
   mutable double *d_grad_partial = nullptr;
 
@@ -245,6 +263,13 @@ int launch_density(const q4c_plan *p, const double *coef, uint32_t terms, int we
                    hipStream_t s);
 int launch_integrate_hs(const q4c_plan *p, const double *v, uint32_t flags, double *hs, hipStream_t s);
 int launch_density_grad(const q4c_plan *p, const double *coef, double *out, double *gpart, hipStream_t s);
+// Bloch sums of a store over the plan's cell pairs (q4c_bloch_kernels.hip),
+// k-points in chunks of kBlochKChunk; phase: 2 kBlochKChunk n_contrib doubles
+constexpr int kBlochKChunk = 64;
+int launch_bloch_sum(const q4c_plan *p, int n_parts, const double *store, int n_k, const double *kpts_dev,
+                     double *phase, double *out, hipStream_t s);
+int launch_bloch_density(const q4c_plan *p, int n_parts, const double *rho, int n_k, const double *kpts_dev,
+                         const double *kw_dev, double *phase, double *coef, hipStream_t s);
 // spinor density -> scalar density matrices of both components (q4c_spinor_kernels.hip)
 int launch_spinor_to_scalar(const q4c_plan *pl, const double *d_spin, double *c_large, double *c_small,
                             hipStream_t s);

@@ -16,6 +16,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <map>
 #include <new>
 #include <stdexcept>
 #include <numeric>
@@ -1292,6 +1293,167 @@ int density_gradient_on_grid(const q4c_plan *p, const double *coef_dev, double *
     p->d_grad_partial = (double *)ptr;
   }
   return q4c::launch_density_grad(p, coef_dev, out_dev, p->d_grad_partial, (hipStream_t)stream);
+}
+
+int q4c_plan_set_cells(q4c_plan *p, int32_t n_cell_atoms, const int32_t *cell_atom, const double *shift) {
+  if (!p) return fail(Q4C_EINVAL, "NULL plan");
+  if (n_cell_atoms <= 0 || n_cell_atoms > p->n_atoms) return fail(Q4C_EINVAL, "n_cell_atoms out of range");
+  if (p->n_atoms > 0 && (!cell_atom || !shift)) return fail(Q4C_EINVAL, "NULL cell map");
+  if (p->n_systems != 1) return fail(Q4C_EUNSUPPORTED, "periodic cells need a single-system plan");
+  std::vector<int32_t> nf(n_cell_atoms, -1);
+  for (int a = 0; a < p->n_atoms; ++a) {
+    const int c = cell_atom[a];
+    if (c < 0 || c >= n_cell_atoms) return fail(Q4C_EINVAL, "cell_atom out of range");
+    if (!finite_all(shift + 3 * a, 3)) return fail(Q4C_EINVAL, "non-finite shift");
+    const int n = p->atom_fn_off[a + 1] - p->atom_fn_off[a];
+    if (nf[c] < 0) nf[c] = n;
+    if (nf[c] != n) return fail(Q4C_EINVAL, "an image has a different basis than its cell atom");
+  }
+  for (int c = 0; c < n_cell_atoms; ++c)
+    if (nf[c] < 0) return fail(Q4C_EINVAL, "a cell atom has no copy in the plan");
+  // contributions per cell pair (a <= b): every stored pair (A', B') in the
+  // orientation whose cell atoms ascend (both orientations when A' != B' and
+  // both map to one cell atom)
+  std::map<std::pair<int, int>, std::vector<std::pair<int64_t, int>>> contrib;  // -> (pair, flag)
+  for (int64_t q = 0; q < p->n_pairs; ++q) {
+    const int A = p->pair_a[q], B = p->pair_b[q];
+    const int a = cell_atom[A], b = cell_atom[B];
+    if (a <= b) contrib[{a, b}].push_back({q, 0});
+    if (A != B && b <= a) contrib[{b, a}].push_back({q, 1});
+  }
+  std::vector<int32_t> ca, cb, ct_pair, ct_flag;
+  std::vector<int64_t> coff(1, 0), ctoff(1, 0);
+  std::vector<double> ct_T;
+  for (auto &kv : contrib) {
+    const int a = kv.first.first, b = kv.first.second;
+    ca.push_back(a);
+    cb.push_back(b);
+    coff.push_back(coff.back() + (int64_t)nf[a] * nf[b]);
+    for (auto &e : kv.second) {
+      const int A = p->pair_a[e.first], B = p->pair_b[e.first];
+      // phase exp(i k.(T_col - T_row)): rows of the target block are the row atom's images
+      const int rowat = e.second ? B : A, colat = e.second ? A : B;
+      ct_pair.push_back((int32_t)e.first);
+      ct_flag.push_back(e.second);
+      for (int d = 0; d < 3; ++d) ct_T.push_back(shift[3 * colat + d] - shift[3 * rowat + d]);
+    }
+    ctoff.push_back((int64_t)ct_pair.size());
+  }
+  p->n_cell_atoms = n_cell_atoms;
+  p->cell_atom.assign(cell_atom, cell_atom + p->n_atoms);
+  p->cp_a = ca;
+  p->cp_b = cb;
+  p->cp_off = coff;
+  p->n_contrib = (int64_t)ct_pair.size();
+  // per stored pair: its cell pair (a <= b), whether it is reached transposed
+  // (cell atoms a > b), and T_B' - T_A' (the reverse sum)
+  std::map<std::pair<int, int>, int32_t> cp_index;
+  for (size_t c = 0; c < ca.size(); ++c) cp_index[{ca[c], cb[c]}] = (int32_t)c;
+  std::vector<int32_t> pc_cp(p->n_pairs), pc_flag(p->n_pairs);
+  std::vector<double> pc_T(3 * p->n_pairs);
+  for (int64_t q = 0; q < p->n_pairs; ++q) {
+    const int A = p->pair_a[q], B = p->pair_b[q];
+    const int a = cell_atom[A], b = cell_atom[B];
+    pc_cp[q] = cp_index.at({std::min(a, b), std::max(a, b)});
+    pc_flag[q] = a > b ? 1 : 0;
+    for (int d = 0; d < 3; ++d) pc_T[3 * q + d] = shift[3 * B + d] - shift[3 * A + d];
+  }
+  if (!p->on_device) return Q4C_OK;
+  int rc = check_plan_dev(p);
+  if (rc != Q4C_OK) return rc;
+  // device copies; earlier ones stay allocated until the plan is destroyed
+  if ((rc = upload(p, ca, &p->d_cp_a)) != Q4C_OK) return rc;
+  if ((rc = upload(p, cb, &p->d_cp_b)) != Q4C_OK) return rc;
+  if ((rc = upload(p, coff, &p->d_cp_off)) != Q4C_OK) return rc;
+  if ((rc = upload(p, ctoff, &p->d_ct_off)) != Q4C_OK) return rc;
+  if ((rc = upload(p, ct_pair, &p->d_ct_pair)) != Q4C_OK) return rc;
+  if ((rc = upload(p, ct_flag, &p->d_ct_flag)) != Q4C_OK) return rc;
+  if ((rc = upload(p, ct_T, &p->d_ct_T)) != Q4C_OK) return rc;
+  if ((rc = upload(p, pc_cp, &p->d_pc_cp)) != Q4C_OK) return rc;
+  if ((rc = upload(p, pc_flag, &p->d_pc_flag)) != Q4C_OK) return rc;
+  if ((rc = upload(p, pc_T, &p->d_pc_T)) != Q4C_OK) return rc;
+  return Q4C_OK;
+}
+
+int q4c_plan_cell_pairs(const q4c_plan *p, int64_t *n_cell_pairs, int32_t *pair_atoms, int64_t *pair_off) {
+  if (!p) return fail(Q4C_EINVAL, "NULL plan");
+  if (p->n_cell_atoms == 0) return fail(Q4C_EINVAL, "no periodic cell set (q4c_plan_set_cells)");
+  if (n_cell_pairs) *n_cell_pairs = (int64_t)p->cp_a.size();
+  if (pair_atoms)
+    for (size_t c = 0; c < p->cp_a.size(); ++c) {
+      pair_atoms[2 * c] = p->cp_a[c];
+      pair_atoms[2 * c + 1] = p->cp_b[c];
+    }
+  if (pair_off) std::copy(p->cp_off.begin(), p->cp_off.end(), pair_off);
+  return Q4C_OK;
+}
+
+// Copies n_k k-points (and weights) into the plan's k buffer [3 n_k points,
+// n_k weights], grows the phase table to a chunk of the larger of the
+// contribution and pair counts, and waits for the copy (the host arrays may
+// go away after the call).
+static int stage_kpoints(const q4c_plan *p, int32_t n_k, const double *k_points, const double *k_weights,
+                         void *stream) {
+  int rc;
+  if (p->kpts_cap < 4 * (int64_t)n_k) {
+    void *ptr = nullptr;
+    if ((rc = device_alloc(const_cast<q4c_plan *>(p), (size_t)(4 * n_k) * sizeof(double), &ptr)) != Q4C_OK)
+      return rc;
+    p->d_kpts = (double *)ptr;
+    p->kpts_cap = 4 * (int64_t)n_k;
+  }
+  const int64_t ph_len = 2 * (int64_t)q4c::kBlochKChunk * std::max<int64_t>(p->n_contrib, p->n_pairs);
+  if (p->bloch_ph_cap < ph_len) {
+    void *ptr = nullptr;
+    if ((rc = device_alloc(const_cast<q4c_plan *>(p), (size_t)ph_len * sizeof(double), &ptr)) != Q4C_OK) return rc;
+    p->d_bloch_ph = (double *)ptr;
+    p->bloch_ph_cap = ph_len;
+  }
+  if (n_k == 0) return Q4C_OK;
+  hipError_t e = hipMemcpyAsync(p->d_kpts, k_points, (size_t)(3 * n_k) * sizeof(double), hipMemcpyHostToDevice,
+                                (hipStream_t)stream);
+  if (e != hipSuccess) return q4c::hip_fail(e, "hipMemcpyAsync k-points");
+  if (k_weights) {
+    e = hipMemcpyAsync(p->d_kpts + 3 * (int64_t)n_k, k_weights, (size_t)n_k * sizeof(double), hipMemcpyHostToDevice,
+                       (hipStream_t)stream);
+    if (e != hipSuccess) return q4c::hip_fail(e, "hipMemcpyAsync k-weights");
+  }
+  e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return q4c::hip_fail(e, "hipStreamSynchronize");
+  return Q4C_OK;
+}
+
+int q4c_bloch_sum(const q4c_plan *p, int32_t n_parts, const double *store_dev, int32_t n_k, const double *k_points,
+                  double *out_dev, void *stream) {
+  if (!p) return fail(Q4C_EINVAL, "NULL plan");
+  // 3 or 4 parts would cut the spin-orbit triple of a five-part store
+  if (n_parts != 1 && n_parts != 2 && n_parts != 5) return fail(Q4C_EINVAL, "n_parts must be 1, 2 or 5");
+  if (n_k < 0) return fail(Q4C_EINVAL, "negative n_k");
+  int rc = check_plan_dev(p);
+  if (rc != Q4C_OK) return rc;
+  if (p->n_cell_atoms == 0) return fail(Q4C_EINVAL, "no periodic cell set (q4c_plan_set_cells)");
+  if (n_k == 0 || p->cp_a.empty()) return Q4C_OK;
+  if (!k_points || !store_dev || !out_dev) return fail(Q4C_EINVAL, "NULL argument");
+  if (!finite_all(k_points, 3 * (int64_t)n_k)) return fail(Q4C_EINVAL, "non-finite k-point");
+  if ((rc = stage_kpoints(p, n_k, k_points, nullptr, stream)) != Q4C_OK) return rc;
+  return q4c::launch_bloch_sum(p, n_parts, store_dev, n_k, p->d_kpts, p->d_bloch_ph, out_dev, (hipStream_t)stream);
+}
+
+int q4c_bloch_density(const q4c_plan *p, int32_t n_parts, const double *rho_dev, int32_t n_k, const double *k_points,
+                      const double *k_weights, double *coef_out_dev, void *stream) {
+  if (!p) return fail(Q4C_EINVAL, "NULL plan");
+  if (n_parts != 1 && n_parts != 2) return fail(Q4C_EINVAL, "n_parts must be 1 or 2 (Hermitian parts)");
+  if (n_k < 0) return fail(Q4C_EINVAL, "negative n_k");
+  int rc = check_plan_dev(p);
+  if (rc != Q4C_OK) return rc;
+  if (p->n_cell_atoms == 0) return fail(Q4C_EINVAL, "no periodic cell set (q4c_plan_set_cells)");
+  if (p->store_len == 0) return Q4C_OK;
+  if (!coef_out_dev || (n_k > 0 && (!rho_dev || !k_points || !k_weights))) return fail(Q4C_EINVAL, "NULL argument");
+  if (n_k > 0 && !finite_all(k_points, 3 * (int64_t)n_k)) return fail(Q4C_EINVAL, "non-finite k-point");
+  if (n_k > 0 && !finite_all(k_weights, (int64_t)n_k)) return fail(Q4C_EINVAL, "non-finite k-weight");
+  if ((rc = stage_kpoints(p, n_k, k_points, k_weights, stream)) != Q4C_OK) return rc;
+  return q4c::launch_bloch_density(p, n_parts, rho_dev, n_k, p->d_kpts, p->d_kpts + 3 * (int64_t)n_k, p->d_bloch_ph,
+                                   coef_out_dev, (hipStream_t)stream);
 }
 
 int q4c_integrate_HS(const q4c_plan *p, const double *v_dev, uint32_t flags, double *hs_dev, void *stream) {

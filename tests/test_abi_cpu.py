@@ -258,3 +258,45 @@ def test_density_update_calls_need_device_plans():
     assert lib.q4c_spinor_density_to_scalar(p.handle, p.handle, one, one, one, None) == q.Q4C_ENODEV
     assert lib.density_gradient_on_grid(p.handle, one, one, None) == q.Q4C_ENODEV
     assert lib.density_gradient_on_grid(None, one, one, None) == q.Q4C_EINVAL
+
+
+def test_periodic_cells_validation_and_layout():
+    """q4c_plan_set_cells checks its map; the cell-pair layout is the set of
+    (a <= b) reached by a stored pair of images, in ascending order."""
+    q, lib = _lib()
+    # Pb (26 functions) and N (5): images of the two have different bases
+    wl = W.config_periodic(species=((82, (0.0, 0.0, 0.0)), (7, (0.5, 0.5, 0.5))), a_ang=4.5, recipe="main",
+                           nrad=10, nang=26, k=62)
+    p = _host_plan(q, wl)
+    m = wl.meta
+    p.set_cells(m["n_cell_atoms"], m["cell_atom"], m["shift"])
+    pa, po = p.cell_pairs()
+    pairs, _ = p.pairs()
+    ca = m["cell_atom"]
+    want = sorted({(min(ca[a], ca[b]), max(ca[a], ca[b])) for a, b in pairs})
+    assert [tuple(x) for x in pa] == want
+    nfn = wl.atom_nfn()
+    n_cell = [int(nfn[list(ca).index(c)]) for c in range(m["n_cell_atoms"])]
+    assert list(np.diff(po)) == [n_cell[a] * n_cell[b] for a, b in want]
+    bad = m["cell_atom"].copy()
+    bad[-1] = m["n_cell_atoms"]
+    with pytest.raises(q.Q4CError) as e:
+        p.set_cells(m["n_cell_atoms"], bad, m["shift"])
+    assert e.value.status == q.Q4C_EINVAL
+    bad = m["cell_atom"].copy()
+    bad[-1] = 1 - bad[-1]  # an image of Pb mapped to N (different basis) or the reverse
+    with pytest.raises(q.Q4CError) as e:
+        p.set_cells(m["n_cell_atoms"], bad, m["shift"])
+    assert e.value.status == q.Q4C_EINVAL
+    rc = lib.q4c_bloch_sum(p.handle, 5, ctypes.c_void_p(1), 1, ctypes.c_void_p(1), ctypes.c_void_p(1), None)
+    assert rc == q.Q4C_ENODEV
+    for n_parts in (0, 3, 4, 6):  # 3 or 4 would split the spin-orbit parts
+        rc = lib.q4c_bloch_sum(p.handle, n_parts, ctypes.c_void_p(1), 1, ctypes.c_void_p(1), ctypes.c_void_p(1), None)
+        assert rc == q.Q4C_EINVAL, n_parts
+    one = ctypes.c_void_p(1)
+    for n_parts in (0, 3, 5):  # Hermitian parts only
+        rc = lib.q4c_bloch_density(p.handle, n_parts, one, 1, one, one, one, None)
+        assert rc == q.Q4C_EINVAL, n_parts
+    assert lib.q4c_bloch_density(p.handle, 1, one, 1, one, one, one, None) == q.Q4C_ENODEV
+    assert lib.q4c_bloch_density(p.handle, 1, one, -1, one, one, one, None) == q.Q4C_EINVAL
+    assert lib.q4c_bloch_density(None, 1, one, 1, one, one, one, None) == q.Q4C_EINVAL

@@ -232,10 +232,13 @@ def bench_hs(wl, timed, steps: int, cpu_frac: float, with_cpu: bool, components=
             nt = max(tim["density_tiles"][1], 1)
             t_t = tim["density_tiles"][0] / nt * 1e-3
             per = tim["density_tiles"][1] / steps
-            f_alg = 0.4 * plan_.info["flops_alg"]  # sum_B 4 P n^2: C^T phi and C^T grad phi
+            # sum_B 2 P n^2: the one symmetric product Y = C phi per batch that
+            # n = phi^T C phi and grad n = 2 grad phi^T C phi need (flops_alg
+            # counts 10 P n^2)
+            f_alg = 0.2 * plan_.info["flops_alg"]
             ach = f_alg / per / t_t
             dens[cname] = {"kernels_ms_per_call": {k: v_[0] / steps for k, v_ in tim.items() if v_[1]},
-                           "roofline": {"kernel": "k_density_tiles<grad>", "bound": "mfma", "achieved": ach / 1e12,
+                           "roofline": {"kernel": "k_grad_tiles", "bound": "mfma", "achieved": ach / 1e12,
                                         "peak": PEAK_F64 / 1e12, "unit": "TFLOP/s", "frac": ach / PEAK_F64,
                                         "avg_launch_ms": t_t * 1e3, "launches_per_call": per,
                                         "flops_alg_per_call": f_alg}}

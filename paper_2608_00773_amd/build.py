@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libq4c.so")
 SOURCES = ["q4c_plan.cpp", "q4c_kernels.hip", "q4c_hs_kernels.hip", "q4c_spinor_kernels.hip",
-           "q4c_bloch_kernels.hip"]
+           "q4c_bloch_kernels.hip", "q4c_grad_kernels.hip"]
 ARCH = os.environ.get("Q4C_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -263,6 +263,9 @@ int launch_density(const q4c_plan *p, const double *coef, uint32_t terms, int we
                    hipStream_t s);
 int launch_integrate_hs(const q4c_plan *p, const double *v, uint32_t flags, double *hs, hipStream_t s);
 int launch_density_grad(const q4c_plan *p, const double *coef, double *out, double *gpart, hipStream_t s);
+// k_grad_tiles over work items [w0, w0 + nw) of a pass (q4c_grad_kernels.hip)
+int launch_grad_tiles(const q4c_plan *p, int64_t w0, int64_t nw, const int32_t *order, const double *coef,
+                      const double *panel, double *gpart, unsigned *tickets, unsigned grid, hipStream_t s);
 // Bloch sums of a store over the plan's cell pairs (q4c_bloch_kernels.hip),
 // k-points in chunks of kBlochKChunk; phase: 2 kBlochKChunk n_contrib doubles
 constexpr int kBlochKChunk = 64;

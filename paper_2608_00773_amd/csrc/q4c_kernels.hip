@@ -828,20 +828,13 @@ constexpr int RSB = T + 2;
 // in LDS (loaded by DMA) and shared by the 4 waves; each wave owns 16 columns x 32 rows of C
 // in registers.  Two workgroups fit on a CU, so one computes while the other
 // stages its next chunk.
-//
-// GRAD: the density and its gradient for one real coefficient part C (the
-// scalar density matrix of a component): per point n = sum C_ij phi_i phi_j
-// and d_a n = sum C_ij (d_a phi_i phi_j + phi_i d_a phi_j), i.e. the four
-// products C^T Y_q (Y_q = phi, d_x phi, d_y phi, d_z phi of the rows) met
-// lane-locally by the column values: n += u_0 phi_j, d_a n += u_a phi_j +
-// u_0 d_a phi_j.  Four partials per point and column half.
-template <bool PERSIST, bool GRAD = false>
+template <bool PERSIST>
 __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t terms, const WorkItem *work,
                                                           const int32_t *order, int64_t w0, int64_t nw,
                                                           const double *coef, const double *panel,
                                                           double *partial, unsigned *tickets) {
-  constexpr int NO = GRAD ? 4 : 1;   // outputs per point
-  constexpr int NC = GRAD ? 1 : 5;   // coefficient parts
+  constexpr int NO = 1;   // outputs per point
+  constexpr int NC = 5;   // coefficient parts
   __shared__ double sa[32 * RSA], sb[32 * RSB];
   __shared__ double s_red[2][4][NO][16];  // per-wave point sums, alternating chunks
   __shared__ int64_t s_pos;
@@ -975,53 +968,7 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t te
     // (l16, lk) holds column j = lk + 4 r (of the wave's 16) at point pt = l16
     // and the product with Z is a lane-local multiply-add.
     double xacc[4] = {0.0, 0.0, 0.0, 0.0};
-    double xg[4][4];  // GRAD: n, d_x n, d_y n, d_z n per register
-#pragma unroll
-    for (int o = 0; o < 4; ++o)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) xg[o][r] = 0.0;
-    if (GRAD && any) {
-      double zt[4][4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          zt[q][r] = sb[(q * 8 + (l16 >> 1)) * RSB + 2 * (jloc + d_row_f64(lk, r)) + (l16 & 1)];
-      auto grad_terms = [&](auto k0c, auto k1c) {
-        constexpr int K0 = decltype(k0c)::value, K1 = decltype(k1c)::value;
-#pragma unroll
-        for (int yq = 0; yq < 4; ++yq) {
-          double ya[8];
-#pragma unroll
-          for (int ks = K0; ks < K1; ++ks)
-            ya[ks] = sa[(yq * 8 + (l16 >> 1)) * RSA + 2 * (iloc + 4 * ks + lk) + (l16 & 1)];
-          dbl4 u0 = dbl4{0.0, 0.0, 0.0, 0.0}, u1 = u0;
-#pragma unroll
-          for (int ks = K0; ks < K1; ks += 2) {
-            u0 = mfma64(creg[0][ks], ya[ks], u0);
-            u1 = mfma64(creg[0][ks + 1], ya[ks + 1], u1);
-          }
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const double u = u0[r] + u1[r];
-            if (yq == 0) {
-              xg[0][r] += u * zt[0][r];
-#pragma unroll
-              for (int a = 1; a < 4; ++a) xg[a][r] += u * zt[a][r];
-            } else {
-              xg[yq][r] += u * zt[0][r];
-            }
-          }
-        }
-      };
-      if (act[0] && act[1])
-        grad_terms(std::integral_constant<int, 0>{}, std::integral_constant<int, 8>{});
-      else if (act[0])
-        grad_terms(std::integral_constant<int, 0>{}, std::integral_constant<int, 4>{});
-      else
-        grad_terms(std::integral_constant<int, 4>{}, std::integral_constant<int, 8>{});
-    }
-    if (!GRAD && any) {
+    if (any) {
       // column values: Z[q][pt = l16][j = jloc + lk + 4 r]
       double zt[4][4];
 #pragma unroll
@@ -1129,7 +1076,7 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t te
     // sum over the wave's 16 columns: the 4 registers, then the 4 lane rows
 #pragma unroll
     for (int o = 0; o < NO; ++o) {
-      const double *xv = GRAD ? xg[o] : xacc;
+      const double *xv = xacc;
       double sx = (xv[0] + xv[1]) + (xv[2] + xv[3]);
       sx += __shfl_xor(sx, 16);
       sx += __shfl_xor(sx, 32);
@@ -1165,7 +1112,7 @@ __global__ void k_density_points(DevPlan d, int64_t b0, const double *partial, i
   }
 }
 
-// GRAD partials: four runs of P values per column half; out is [4][n_points].
+// Gradient partials of k_grad_tiles: four runs of P values per column half; out is [4][n_points].
 __global__ void k_density_points_grad(DevPlan d, int64_t b0, const double *partial, double *out) {
   const int64_t b = b0 + blockIdx.x;
   const int g0 = d.batch_pt_off[b], P = d.batch_pt_off[b + 1] - g0;
@@ -1478,14 +1425,9 @@ int launch_density_grad(const q4c_plan *p, const double *coef, double *out, doub
     if (nw > 0) {
       {
         TimedLaunch tl_(p, Q4C_TIMER_DENSITY_TILES, s);
-        if (tickets)
-          hipLaunchKernelGGL((k_density_tiles<true, true>), dim3(grid), dim3(NTD), 0, s, p->dp, 0u, p->d_work, order,
-                             ps.w0, nw, coef, panel, gpart, tickets);
-        else
-          hipLaunchKernelGGL((k_density_tiles<false, true>), dim3(grid), dim3(NTD), 0, s, p->dp, 0u, p->d_work,
-                             order, ps.w0, nw, coef, panel, gpart, tickets);
+        rc = launch_grad_tiles(p, ps.w0, nw, order, coef, panel, gpart, tickets, grid, s);
       }
-      if ((rc = check_launch("k_density_tiles<grad>")) != Q4C_OK) return rc;
+      if (rc != Q4C_OK) return rc;
     }
     if (nbt > 0) {
       {

@@ -8,21 +8,21 @@
 //
 // Two kernels per chunk of at most KB k-points:
 //   k_bloch_phase  exp(i k.T) once per (contribution, k-point), [t][k] layout;
-//   k_bloch_sum    one thread per (part, cell element): it reads each of its
-//                  stored values once per KC k-points and keeps KC complex
-//                  accumulators in registers, so the store is streamed
-//                  ceil(n_k / KC) times and no sine or cosine is evaluated
-//                  per element.  The contributions of a cell pair are a short
-//                  list shared by all of its elements (uniform loads).
+//   k_bloch_sum    one workgroup per (cell pair, part): the cell pair's
+//                  contributions and their phases are staged in LDS, each
+//                  thread keeps a few elements x KC k-points of complex sums
+//                  in registers, so the store is streamed ceil(n_k / KC)
+//                  times and no sine or cosine is evaluated per element.
 // The reverse direction (q4c_bloch_density, the periodic density matrix of
 // the same section) reuses k_bloch_phase with k-point weights, per stored
-// pair, and k_bloch_density sums one stored element per thread.
+// pair, and k_bloch_density runs one workgroup per stored pair.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstdint>
 
 #include "q4c_internal.h"
+#include "q4c_device.h"
 
 namespace q4c {
 namespace {
@@ -46,103 +46,142 @@ __global__ __launch_bounds__(256) void k_bloch_phase(int n_k, int64_t n_ct, cons
   }
 }
 
+constexpr int BS_EPT = 2;  // cell elements per thread per pass
+constexpr int BS_TB = 64;  // contributions staged in LDS at a time
+
+// One workgroup per (cell pair c, part q): the contributions' store offsets,
+// column counts, orientations and phases for KC k-points are staged in LDS
+// (BS_TB contributions at a time) and read as broadcasts; each thread holds
+// BS_EPT elements x KC k-points of complex sums, so that one staged phase
+// serves BS_EPT elements and every stored value is read once per pass.
 // ph: [n_ct][n_k] complex phases of this chunk; out: [n_k][n_parts][clen] complex.
 __global__ __launch_bounds__(256) void k_bloch_sum(DevPlan d, int n_parts, int64_t ncp, const int64_t *cp_off,
                                                    const int64_t *ct_off, const int32_t *ct_pair,
                                                    const int32_t *ct_flag, int n_k, const double *ph,
-                                                   const double *store, double *out) {
+                                                   const double *__restrict__ store, double *__restrict__ out) {
+  __shared__ int64_t s_off[BS_TB];
+  __shared__ int s_nbp[BS_TB], s_tr[BS_TB];
+  __shared__ double s_ph[BS_TB][KC][2];
+  const int64_t c = blockIdx.x / n_parts;
+  const int q = (int)(blockIdx.x - c * n_parts);
   const int64_t clen = cp_off[ncp];
-  const int64_t total = (int64_t)n_parts * clen;
-  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t e = g % clen;
-    const int q = (int)(g / clen);
-    // cell pair of element e: the last c with cp_off[c] <= e
-    int64_t lo = 0, hi = ncp - 1;
-    while (lo < hi) {
-      const int64_t mid = (lo + hi + 1) >> 1;
-      if (cp_off[mid] <= e)
-        lo = mid;
-      else
-        hi = mid - 1;
+  const int64_t e0 = cp_off[c], blk = cp_off[c + 1] - e0;
+  const int64_t t0 = ct_off[c], nt = ct_off[c + 1] - t0;
+  const double sq = (n_parts == 5 && q >= 2) ? -1.0 : 1.0;
+  const int64_t L = d.store_len;
+  // columns of the cell-pair block: those of the stored block (direct) or
+  // its rows (transposed), the same for every contribution of the cell pair
+  const int64_t p0 = ct_pair[t0];
+  const int ncol = ct_flag[t0] ? d.pair_na[p0] : d.pair_nb[p0];
+  const int tid = threadIdx.x;
+  for (int64_t eb = 0; eb < blk; eb += 256 * BS_EPT) {
+    int ei[BS_EPT], ej[BS_EPT];
+    bool ev[BS_EPT];
+#pragma unroll
+    for (int x = 0; x < BS_EPT; ++x) {
+      const int64_t le = eb + tid + 256 * x;
+      ev[x] = le < blk;
+      ei[x] = ev[x] ? (int)(le / ncol) : 0;
+      ej[x] = ev[x] ? (int)(le - (int64_t)ei[x] * ncol) : 0;
     }
-    const int64_t c = lo;
-    const int64_t le = e - cp_off[c];
-    const double sq = (n_parts == 5 && q >= 2) ? -1.0 : 1.0;
-    const double *sp = store + (int64_t)q * d.store_len;
-    const int64_t t0 = ct_off[c], t1 = ct_off[c + 1];
     for (int k0 = 0; k0 < n_k; k0 += KC) {
-      double re[KC], im[KC];
+      double re[BS_EPT][KC], im[BS_EPT][KC];
 #pragma unroll
-      for (int kk = 0; kk < KC; ++kk) re[kk] = im[kk] = 0.0;
-      for (int64_t t = t0; t < t1; ++t) {
-        const int64_t p = ct_pair[t];
-        const int nbp = d.pair_nb[p];  // columns of the stored block
-        // target block is n_row x n_col with n_col = nbp (direct) or nap (transposed)
-        const bool tr = ct_flag[t] != 0;
-        const int ncol = tr ? d.pair_na[p] : nbp;
-        const int i = (int)(le / ncol), j = (int)(le - (int64_t)i * ncol);
-        const double v = tr ? sq * sp[d.pair_off[p] + (int64_t)j * nbp + i] : sp[d.pair_off[p] + (int64_t)i * nbp + j];
-        const double *pt = ph + 2 * (t * n_k + k0);
+      for (int x = 0; x < BS_EPT; ++x)
 #pragma unroll
-        for (int kk = 0; kk < KC; ++kk)
-          if (k0 + kk < n_k) {
-            re[kk] += pt[2 * kk] * v;
-            im[kk] += pt[2 * kk + 1] * v;
+        for (int kk = 0; kk < KC; ++kk) re[x][kk] = im[x][kk] = 0.0;
+      for (int64_t tb = 0; tb < nt; tb += BS_TB) {
+        const int nb = (int)min<int64_t>(BS_TB, nt - tb);
+        __syncthreads();  // the previous batch is consumed
+        for (int x = tid; x < nb; x += 256) {
+          const int64_t pp = ct_pair[t0 + tb + x];
+          s_off[x] = (int64_t)q * L + d.pair_off[pp];
+          s_nbp[x] = d.pair_nb[pp];
+          s_tr[x] = ct_flag[t0 + tb + x];
+        }
+        for (int x = tid; x < nb * KC; x += 256) {
+          const int tt = x / KC, kk = x - tt * KC;
+          const bool in = k0 + kk < n_k;
+          const double *pt = ph + 2 * ((t0 + tb + tt) * n_k + k0 + kk);
+          s_ph[tt][kk][0] = in ? pt[0] : 0.0;
+          s_ph[tt][kk][1] = in ? pt[1] : 0.0;
+        }
+        __syncthreads();  // the batch is visible
+        for (int tt = 0; tt < nb; ++tt) {
+          const int64_t off = s_off[tt];
+          const int nbp = s_nbp[tt];
+          const bool tr = s_tr[tt] != 0;
+          double v[BS_EPT];
+#pragma unroll
+          for (int x = 0; x < BS_EPT; ++x) {
+            const int64_t a = tr ? off + (int64_t)ej[x] * nbp + ei[x] : off + (int64_t)ei[x] * nbp + ej[x];
+            v[x] = ev[x] ? store[a] : 0.0;
+            if (tr) v[x] *= sq;
           }
+#pragma unroll
+          for (int kk = 0; kk < KC; ++kk) {
+            const double cs = s_ph[tt][kk][0], sn = s_ph[tt][kk][1];
+#pragma unroll
+            for (int x = 0; x < BS_EPT; ++x) {
+              re[x][kk] += cs * v[x];
+              im[x][kk] += sn * v[x];
+            }
+          }
+        }
       }
 #pragma unroll
-      for (int kk = 0; kk < KC; ++kk)
-        if (k0 + kk < n_k) {
-          const int64_t o = ((int64_t)(k0 + kk) * n_parts + q) * clen + e;
-          out[2 * o] = re[kk];
-          out[2 * o + 1] = im[kk];
+      for (int x = 0; x < BS_EPT; ++x)
+        if (ev[x]) {
+#pragma unroll
+          for (int kk = 0; kk < KC; ++kk)
+            if (k0 + kk < n_k) {
+              const int64_t o = ((int64_t)(k0 + kk) * n_parts + q) * clen + e0 + eb + tid + 256 * x;
+              out[2 * o] = re[x][kk];
+              out[2 * o + 1] = im[x][kk];
+            }
         }
     }
   }
 }
 
 // The reverse direction (the periodic density matrix of Sec. II C): one
-// thread per (part, stored element (i, j) of image pair p = (A', B')):
+// workgroup per stored image pair p = (A', B') (grouped by cell pair, so that
+// a cell pair's rho is re-read from one L2), one thread per element (i, j):
 //   coef = f Re sum_k w_k exp(i k.(T_B' - T_A')) rho_ab(k)[i][j],
 // rho_ab(k)[i][j] = conj(rho_ba(k)[j][i]) when the cell atoms run a > b,
 // f = 2 off the self pairs.  ph: [n_pairs][n_k] weighted phases of this
-// chunk; rho: this chunk's [n_k][n_parts][clen] complex; acc: add to coef.
+// chunk (uniform per workgroup); rho: this chunk's [n_k][n_parts][clen]
+// complex; acc: add to coef.
 __global__ __launch_bounds__(256) void k_bloch_density(DevPlan d, int n_parts, int64_t n_pairs, int64_t ncp,
                                                        const int64_t *cp_off, const int32_t *pc_cp,
-                                                       const int32_t *pc_flag, int n_k, const double *ph,
-                                                       const double *rho, int acc, double *coef) {
+                                                       const int32_t *pc_flag, const int32_t *pc_order, int n_k,
+                                                       const double *__restrict__ ph,
+                                                       const double *__restrict__ rho, int acc,
+                                                       double *__restrict__ coef) {
+  // the image pairs of one cell pair run one after another on one XCD
+  const int64_t p = pc_order[xcd_map(blockIdx.x, n_pairs)];
   const int64_t L = d.store_len;
   const int64_t clen = cp_off[ncp];
-  const int64_t total = (int64_t)n_parts * L;
-  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
-    const int q = (int)(g / L);
-    const int64_t e = g - (int64_t)q * L;
-    // stored pair of element e: the last p with pair_off[p] <= e
-    int64_t lo = 0, hi = n_pairs - 1;
-    while (lo < hi) {
-      const int64_t mid = (lo + hi + 1) >> 1;
-      if (d.pair_off[mid] <= e)
-        lo = mid;
-      else
-        hi = mid - 1;
+  const int na = d.pair_na[p], nb = d.pair_nb[p];
+  const int64_t blk = (int64_t)na * nb, po = d.pair_off[p];
+  const bool tr = pc_flag[p] != 0;
+  const int64_t ce0 = cp_off[pc_cp[p]];
+  const double sg = tr ? 1.0 : -1.0;  // Re(e^{i t} r) = c Re r - s Im r; conj(r): c Re r + s Im r
+  const double f = d.pair_a[p] == d.pair_b[p] ? 1.0 : 2.0;
+  const double *pp = ph + 2 * p * n_k;
+  for (int q = 0; q < n_parts; ++q)
+    for (int64_t e = threadIdx.x; e < blk; e += blockDim.x) {
+      const int i = (int)(e / nb), j = (int)(e - (int64_t)i * nb);
+      // element of the cell-pair block: (i, j) of (a, b), or (j, i) of (b, a)
+      const int64_t ce = ce0 + (tr ? (int64_t)j * na + i : (int64_t)i * nb + j);
+      double s = 0.0;
+      for (int k = 0; k < n_k; ++k) {
+        const double *r = rho + 2 * (((int64_t)k * n_parts + q) * clen + ce);
+        s += pp[2 * k] * r[0] + sg * pp[2 * k + 1] * r[1];
+      }
+      double *o = coef + (int64_t)q * L + po + e;
+      *o = acc ? *o + f * s : f * s;
     }
-    const int64_t p = lo;
-    const int64_t le = e - d.pair_off[p];
-    const int na = d.pair_na[p], nb = d.pair_nb[p];
-    const int i = (int)(le / nb), j = (int)(le - (int64_t)i * nb);
-    const bool tr = pc_flag[p] != 0;
-    // element of the cell-pair block: (i, j) of (a, b), or (j, i) of (b, a)
-    const int64_t ce = cp_off[pc_cp[p]] + (tr ? (int64_t)j * na + i : (int64_t)i * nb + j);
-    const double sg = tr ? 1.0 : -1.0;  // Re(e^{i t} r) = c Re r - s Im r; conj(r): c Re r + s Im r
-    const double *pp = ph + 2 * p * n_k;
-    double s = 0.0;
-    for (int k = 0; k < n_k; ++k) {
-      const double *r = rho + 2 * (((int64_t)k * n_parts + q) * clen + ce);
-      s += pp[2 * k] * r[0] + sg * pp[2 * k + 1] * r[1];
-    }
-    const double f = d.pair_a[p] == d.pair_b[p] ? 1.0 : 2.0;
-    coef[g] = acc ? coef[g] + f * s : f * s;
-  }
 }
 
 }  // namespace
@@ -166,8 +205,7 @@ int launch_bloch_sum(const q4c_plan *p, int n_parts, const double *store, int n_
     if (e != hipSuccess) return hip_fail(e, "k_bloch_phase");
     {
       TimedLaunch tl_(p, Q4C_TIMER_BLOCH, s);
-      const int64_t tot = (int64_t)n_parts * clen;
-      const unsigned grid = (unsigned)std::min<int64_t>((tot + 255) / 256, 65536);
+      const unsigned grid = (unsigned)(ncp * n_parts);
       hipLaunchKernelGGL(k_bloch_sum, dim3(grid), dim3(256), 0, s, p->dp, n_parts, ncp, p->d_cp_off, p->d_ct_off,
                          p->d_ct_pair, p->d_ct_flag, nk, (const double *)phase, store,
                          out + 2 * (int64_t)k0 * n_parts * clen);
@@ -198,10 +236,8 @@ int launch_bloch_density(const q4c_plan *p, int n_parts, const double *rho, int 
     if (e != hipSuccess) return hip_fail(e, "k_bloch_phase");
     {
       TimedLaunch tl_(p, Q4C_TIMER_BLOCH, s);
-      const int64_t tot = (int64_t)n_parts * L;
-      const unsigned grid = (unsigned)std::min<int64_t>((tot + 255) / 256, 65536);
-      hipLaunchKernelGGL(k_bloch_density, dim3(grid), dim3(256), 0, s, p->dp, n_parts, np_, ncp, p->d_cp_off,
-                         p->d_pc_cp, p->d_pc_flag, nk, (const double *)phase,
+      hipLaunchKernelGGL(k_bloch_density, dim3((unsigned)np_), dim3(256), 0, s, p->dp, n_parts, np_, ncp,
+                         p->d_cp_off, p->d_pc_cp, p->d_pc_flag, p->d_pc_order, nk, (const double *)phase,
                          rho + 2 * (int64_t)k0 * n_parts * clen, k0 > 0 ? 1 : 0, coef);
     }
     e = hipGetLastError();

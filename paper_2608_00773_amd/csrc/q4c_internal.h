@@ -223,6 +223,7 @@ struct q4c_plan {
   int64_t n_contrib = 0;                // contributions over all cell pairs
   int32_t *d_pc_cp = nullptr, *d_pc_flag = nullptr;  // per stored pair: cell pair; 1: reached transposed (a > b)
   double *d_pc_T = nullptr;             // [3 per stored pair] T_B' - T_A'
+  int32_t *d_pc_order = nullptr;        // stored pairs sorted by cell pair
   mutable double *d_kpts = nullptr;     // k-points (3 n_k) and weights (n_k) of the last call (grown on demand)
   mutable int64_t kpts_cap = 0;
   mutable double *d_bloch_ph = nullptr; // phases of one k chunk: kBlochKChunk max(n_contrib, n_pairs) complex

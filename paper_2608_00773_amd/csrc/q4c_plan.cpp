@@ -1358,6 +1358,11 @@ int q4c_plan_set_cells(q4c_plan *p, int32_t n_cell_atoms, const int32_t *cell_at
     pc_flag[q] = a > b ? 1 : 0;
     for (int d = 0; d < 3; ++d) pc_T[3 * q + d] = shift[3 * B + d] - shift[3 * A + d];
   }
+  // stored pairs grouped by cell pair (the reverse sum reads a cell pair's
+  // rho for all of its image pairs; consecutive ones share an XCD's L2)
+  std::vector<int32_t> pc_order(p->n_pairs);
+  for (int64_t q = 0; q < p->n_pairs; ++q) pc_order[q] = (int32_t)q;
+  std::stable_sort(pc_order.begin(), pc_order.end(), [&](int32_t x, int32_t y) { return pc_cp[x] < pc_cp[y]; });
   if (!p->on_device) return Q4C_OK;
   int rc = check_plan_dev(p);
   if (rc != Q4C_OK) return rc;
@@ -1372,6 +1377,7 @@ int q4c_plan_set_cells(q4c_plan *p, int32_t n_cell_atoms, const int32_t *cell_at
   if ((rc = upload(p, pc_cp, &p->d_pc_cp)) != Q4C_OK) return rc;
   if ((rc = upload(p, pc_flag, &p->d_pc_flag)) != Q4C_OK) return rc;
   if ((rc = upload(p, pc_T, &p->d_pc_T)) != Q4C_OK) return rc;
+  if ((rc = upload(p, pc_order, &p->d_pc_order)) != Q4C_OK) return rc;
   return Q4C_OK;
 }
 

@@ -20,7 +20,8 @@ namespace {
 
 // One thread per output element, over all pairs at once: element g of the
 // spinor store belongs to the pair p with 4 pair_off[p] <= g < 4 pair_off[p+1]
-// (binary search), so the writes are contiguous and every workgroup is full.
+// (found once per workgroup block, then a few steps per thread), so the
+// writes are contiguous and every workgroup is full.
 // Outputs: complex128 (re, im interleaved), 4 store_len (large plan) each,
 // block (2 nL_A) x (2 nL_B) row-major at complex offset 4 pair_off[p].
 __global__ __launch_bounds__(256) void k_spinor_transform(DevPlan d, const SpinorType *types, const SpinorFn *fns,
@@ -29,10 +30,12 @@ __global__ __launch_bounds__(256) void k_spinor_transform(DevPlan d, const Spino
                                                           int64_t lenS, int64_t npairs, const double *hsL,
                                                           const double *hsS, double *h_out, double *s_out) {
   const int64_t lenL = d.store_len, total = 4 * lenL;
-  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
-       g += (int64_t)gridDim.x * blockDim.x) {
-    // pair of element g: the last p with pair_off[p] <= g / 4
-    const int64_t key = g >> 2;
+  for (int64_t g0 = blockIdx.x * (int64_t)blockDim.x; g0 < total; g0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t g = g0 + threadIdx.x;
+    // pair of the block's first element (the last p with 4 pair_off[p] <= g0):
+    // a search on a workgroup-uniform key, then a short scan per thread (a
+    // block of 256 elements spans few pairs)
+    const int64_t key = g0 >> 2;
     int64_t lo = 0, hi = npairs - 1;
     while (lo < hi) {
       const int64_t mid = (lo + hi + 1) >> 1;
@@ -41,7 +44,9 @@ __global__ __launch_bounds__(256) void k_spinor_transform(DevPlan d, const Spino
       else
         hi = mid - 1;
     }
-    const int64_t p = lo;
+    if (g >= total) continue;
+    int64_t p = lo;
+    while (p + 1 < npairs && 4 * d.pair_off[p + 1] <= g) ++p;
     const int A = d.pair_a[p], B = d.pair_b[p];
     const int NB = sp_off[B + 1] - sp_off[B];
     const int nLB = nL[B], nSB = nS[B];

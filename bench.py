@@ -238,7 +238,7 @@ def bench_hs(wl, timed, steps: int, cpu_frac: float, with_cpu: bool, components=
             f_alg = 0.2 * plan_.info["flops_alg"]
             ach = f_alg / per / t_t
             dens[cname] = {"kernels_ms_per_call": {k: v_[0] / steps for k, v_ in tim.items() if v_[1]},
-                           "roofline": {"kernel": "k_grad_tiles", "bound": "mfma", "achieved": ach / 1e12,
+                           "roofline": {"kernel": "k_grad_gemm", "bound": "mfma", "achieved": ach / 1e12,
                                         "peak": PEAK_F64 / 1e12, "unit": "TFLOP/s", "frac": ach / PEAK_F64,
                                         "avg_launch_ms": t_t * 1e3, "launches_per_call": per,
                                         "flops_alg_per_call": f_alg}}

@@ -1,12 +1,26 @@
-// The tile kernel of density_gradient_on_grid: the density and its gradient
-// from one real coefficient part C on the stored pairs (a scalar density
-// matrix of one component, the forward density update of Eq. 39 with the
-// gradient a GGA needs).  The panel tabulation, the per-point sums and the
-// launches around it are in q4c_kernels.hip.
+// The kernels of density_gradient_on_grid: the density and its gradient from
+// one real coefficient part C on the stored pairs (a scalar density matrix of
+// one component: the forward density update of Eq. 39 with the gradient a
+// GGA needs).  Per batch with functions phi_1..phi_n at its points,
+//   n = sum over stored elements C_ij phi_i phi_j = phi^T M phi,
+//   grad n = 2 grad phi^T M phi,
+// with M the symmetric n x n matrix of the batch (half of each stored
+// off-diagonal element on both sides, the symmetric part of a self pair's
+// block).  So per batch one product Y = M Phi (2 P n^2 flops, on FP64 MFMA)
+// and lane-local dot products of Y with phi and grad phi.
+//   k_grad_cdense  M of every batch of a pass, dense (np x np, zero padding);
+//   k_grad_gemm    one workgroup per (batch, 64-point tile, 64-function tile
+//                  i): Y_i(pt) = sum_j phi_j(pt) M_ji over 16-function K
+//                  chunks (phi slice and M slice by LDS DMA, double
+//                  buffered), then n and grad n partials over its functions;
+//   k_grad_points  the partials of a point over the function tiles, in order.
+// (Gathering the M slices from the store inside the product instead of
+// materialising M was slower: two dependent memory round trips per 16
+// functions do not hide behind 16 MFMAs.)
+// The panel tabulation and the launches around these are in q4c_kernels.hip.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
-#include <type_traits>
 
 #include "q4c_internal.h"
 #include "q4c_device.h"
@@ -14,38 +28,15 @@
 namespace q4c {
 namespace {
 
-constexpr int NTG = 256;     // 4 waves = 2 column slices x 2 row halves of a column half
-constexpr int RSA = 2 * T + 2;   // LDS row stride of the 64 row functions (2 mod 16: 16 points hit distinct banks)
-constexpr int RSB = T + 2;       // ... of the 32 column functions
-
-// LDS DMA of components [Q0, Q1) of one 16-point chunk of W functions from
-// row0 into dst (the image layout of dma_chunk, from component Q0: element
-// (q, pt, f) at ((q - Q0) * 8 + pt / 2) * RS + 2 f + pt % 2).  Every wave issues the same number of
-// load instructions whatever np is, so that a partial vmcnt wait counts the
-// same loads in every wave: lanes below W whose function lies at or beyond np
-// load function np - 1 instead (into padding entries that lie only in 16 x 16
-// blocks that are never multiplied); lanes from W on are masked off.
-template <int W, int RS, int Q0, int Q1>
-__device__ __forceinline__ void dma_comps(const double *pb, int64_t plane, int np, int row0, int ks0, double *dst) {
-  constexpr int RPQ = 8;  // point pairs per component
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int f = min(row0 + lane, np - 1);
-#pragma unroll
-  for (int k = 0; k < (Q1 - Q0) * RPQ / (NTG / 64); ++k) {
-    const int r = Q0 * RPQ + wave + k * (NTG / 64);
-    const int q = r / RPQ, u = r % RPQ;
-    if (W == 64 || lane < W)
-      __builtin_amdgcn_global_load_lds((const void *)(pb + q * plane + ((int64_t)(ks0 + (u >> 1)) * np + f) * 4 + 2 * (u & 1)),
-                                       (lds_void *)(dst + (r - Q0 * RPQ) * RS), 16, 0, 0);
-  }
-}
+constexpr int GT = 64;    // points and functions per output tile
+constexpr int GK = 16;    // functions per K chunk
+constexpr int GS = 1024;  // doubles per slice image (64 x 16)
 
 // Workgroup barrier after this wave's LDS operations have completed and at
 // most VM of its vector-memory operations remain outstanding (s_waitcnt
-// vmcnt(VM) lgkmcnt(0); VM = 63 waits for none).  The LDS DMA loads count in
-// vmcnt.  __syncthreads would
-// also fence global memory, i.e. wait for every outstanding load; the memory
-// clobber keeps the compiler from moving memory accesses across the barrier.
+// vmcnt(VM) lgkmcnt(0)).  The LDS DMA loads count in vmcnt.  __syncthreads
+// would also fence global memory; the memory clobber keeps the compiler from
+// moving memory accesses across the barrier.
 template <int VM>
 __device__ __forceinline__ void barrier_vm() {
   static_assert(VM >= 0 && VM < 64, "vmcnt field");
@@ -53,261 +44,275 @@ __device__ __forceinline__ void barrier_vm() {
   asm volatile("s_barrier" ::: "memory");
 }
 
-// One half of a work item (positions 2 w + half): for the tile's 64 rows i
-// and the half's 32 columns j with effective coefficients K (the stored
-// coefficient, plus its mirror inside one atom block's strictly upper 16 x 16
-// blocks), per point
-//   n     = sum_ij K_ij phi_i phi_j      = sum_j u_j phi_j,
-//   d_a n = sum_ij K_ij d_a(phi_i phi_j) = sum_j u_j d_a phi_j + sum_i v_i d_a phi_i,
-// with u = K^T phi_rows and v = K phi_cols: two MFMA products per 16-point
-// chunk (8 + 8 FP64 MFMAs per wave, four independent chains issued together
-// and consumed once), the rest lane-local.  Each wave holds its 32 x 16 slice
-// of K twice in registers: as the first operand of K^T phi (lane = column) and
-// of K phi (lane = row).  Four partials per point and column half, written in
-// the layout the per-point sum reads.
-template <bool PERSIST>
-__global__ __launch_bounds__(NTG, 2) void k_grad_tiles(DevPlan d, const WorkItem *work, const int32_t *order,
-                                                       int64_t w0, int64_t nw, const double *coef,
-                                                       const double *panel, double *partial, unsigned *tickets) {
-  // chunk images: phi (the MFMA operands; two buffers, the next chunk's
-  // arrives while this one is multiplied) and the three gradient components
-  __shared__ double sa0[2][8 * RSA], sa1[24 * RSA], sb0[2][8 * RSB], sb1[24 * RSB];
-  __shared__ double s_red[2][4][4][16];  // per-wave point sums of n, d_x n, d_y n, d_z n, alternating chunks
-  __shared__ int64_t s_pos;
-  __shared__ int s_rslot[T], s_rfn[T], s_cslot[T / 2], s_cfn[T / 2], s_cnf[T / 2];
-  // stored pair of (row slot, column slot) for the slots the tile spans (-1:
-  // lower atom-block triangle or not a stored pair)
-  __shared__ int s_pq[T * T / 2];
-  const int64_t npos = 2 * nw;
-  int64_t pos = PERSIST ? next_item(tickets, npos, order != nullptr, &s_pos)
-                        : (order ? (int64_t)blockIdx.x : xcd_map(blockIdx.x, npos));
-  while (!PERSIST || pos < npos) {
-  const int half = (int)(pos & 1);
-  const int64_t wi = w0 + (order ? order[w0 + (pos >> 1)] : (pos >> 1));
-  const WorkItem it = work[wi];
-  const int b = it.batch;
+// packed slot data of a batch function: slot, the slot's first function and
+// its function count
+__device__ __forceinline__ int fslot(int64_t v) { return (int)(v & 0xFFFFF); }
+__device__ __forceinline__ int ffirst(int64_t v) { return (int)((v >> 20) & 0xFFFFF); }
+__device__ __forceinline__ int fcount(int64_t v) { return (int)(v >> 40); }
+
+constexpr int CD_NMAX = 2048;  // batch functions whose slot data fits in LDS
+constexpr int CD_PO = 2048;    // entries of the (row slot, batch slot) pair-offset table in LDS
+constexpr int CD_ROWS = 64;    // rows of M per workgroup
+
+// M of one 64-row block of one batch: M_rc for r in the block, all c < np.
+// Slots (relevant atoms) ascend with the batch's functions and with the atom
+// index, so slot lo < hi is the stored pair (atom(lo), atom(hi)), rows = lo's
+// functions.  The columns' slot data and the pair offsets of (the block's
+// row slots, every slot of the batch) are set up in LDS first, so that each
+// element costs one or two loads from the store, all independent.
+__global__ __launch_bounds__(256) void k_grad_cdense(DevPlan d, const int32_t *items, int64_t it0,
+                                                     const int64_t *cd_off, const int64_t *fninfo,
+                                                     const double *coef, double *cd) {
+  __shared__ int64_t s_ci[CD_NMAX];
+  __shared__ int64_t s_po[CD_PO];
+  const int64_t it = it0 + blockIdx.x;
+  const int b = items[2 * it], rb = items[2 * it + 1];
+  const int f0 = d.batch_fn_off[b], n = d.batch_fn_off[b + 1] - f0, np = (int)pad16(n);
+  const int sbase = d.batch_slot_off[b], ns = d.batch_slot_off[b + 1] - sbase;
+  const int64_t spb = d.batch_sp_off[b];
+  double *M = cd + cd_off[b];
+  const int r0 = CD_ROWS * rb;
+  const int rlast = min(r0 + CD_ROWS, n) - 1;
+  auto stored_po = [&](int rs, int cs) -> int64_t {
+    const int lo = min(rs, cs), hi = max(rs, cs);
+    const int q = d.sp_pair[spb + (int64_t)lo * ns - (int64_t)lo * (lo - 1) / 2 + (hi - lo)];
+    return q >= 0 ? d.pair_off[q] : (int64_t)-1;
+  };
+  // the block's row slots rs0..rs1 (rows past n: none)
+  const int rs0 = r0 < n ? fslot(fninfo[f0 + r0]) : 0;
+  const int rs1 = r0 < n ? fslot(fninfo[f0 + rlast]) : -1;
+  const int nrs = rs1 - rs0 + 1;
+  const bool ci_lds = n <= CD_NMAX, po_lds = (int64_t)nrs * ns <= CD_PO;  // workgroup-uniform
+  if (ci_lds)
+    for (int c = threadIdx.x; c < n; c += blockDim.x) s_ci[c] = fninfo[f0 + c];
+  if (po_lds)
+    for (int t = threadIdx.x; t < nrs * ns; t += blockDim.x) s_po[t] = stored_po(rs0 + t / ns, t % ns);
+  __syncthreads();  // tables visible
+  // four elements per thread at a time, their loads unconditional (element
+  // 0 of the store stands in for an absent one) and in flight together
+  const int ne = min(CD_ROWS, np - r0) * np;
+  for (int x0 = threadIdx.x; x0 < ne; x0 += 4 * blockDim.x) {
+    int64_t a1[4], a2[4];
+    bool live[4], self[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int x = x0 + u * blockDim.x;
+      const int rl = x / np;
+      const int r = r0 + rl, c = x - rl * np;
+      const bool in = x < ne && r < n && c < n;
+      const int rr = in ? r : 0, cc = in ? c : 0;
+      const int64_t ir_ = ci_lds ? s_ci[rr] : fninfo[f0 + rr], ic_ = ci_lds ? s_ci[cc] : fninfo[f0 + cc];
+      const int rs = fslot(ir_), cs = fslot(ic_);
+      const int64_t po = !in ? -1 : (po_lds ? s_po[(rs - rs0) * ns + cs] : stored_po(rs, cs));
+      const int ir = rr - ffirst(ir_), ic = cc - ffirst(ic_), rn = fcount(ir_), cn = fcount(ic_);
+      live[u] = po >= 0;
+      self[u] = rs == cs;
+      a1[u] = !live[u] ? 0 : (rs <= cs ? po + (int64_t)ir * cn + ic : po + (int64_t)ic * rn + ir);
+      a2[u] = live[u] && self[u] ? po + (int64_t)ic * cn + ir : 0;  // the self pair's transposed element
+    }
+    double c1[4], c2[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      c1[u] = coef[a1[u]];
+      c2[u] = coef[a2[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int x = x0 + u * blockDim.x;
+      if (x < ne) {
+        const int rl = x / np;
+        M[(int64_t)(r0 + rl) * np + (x - rl * np)] = live[u] ? 0.5 * (c1[u] + (self[u] ? c2[u] : 0.0)) : 0.0;
+      }
+    }
+  }
+}
+
+// LDS DMA of K chunk j0: the phi slice (panel component 0, 16 groups of 4
+// points from pt0, functions j0..j0+15; image [group][function][point % 4],
+// the panel's own order) and the M slice (rows j0..j0+15, columns
+// i0..i0+63; image [row][column]).  Four wave-wide loads per wave, two rows
+// of 512 bytes each.  Groups past the batch's points and columns past np
+// load valid entries instead: they only feed tile rows and columns the
+// epilogue skips.
+__device__ __forceinline__ void gemm_dma(const double *pb, int np, int Pp, int pt0, int j0, const double *M, int i0,
+                                         double *sA, double *sB) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int half = lane >> 5, piece = lane & 31;
+#pragma unroll
+  for (int k = wave; k < 8; k += 4) {
+    const int g = min((pt0 >> 2) + 2 * k + half, (Pp >> 2) - 1);
+    __builtin_amdgcn_global_load_lds(
+        (const void *)(pb + ((int64_t)g * np + j0 + (piece >> 1)) * 4 + 2 * (piece & 1)),
+        (lds_void *)(sA + k * 128), 16, 0, 0);
+    const int col = min(i0 + 2 * piece, np - 2);
+    __builtin_amdgcn_global_load_lds((const void *)(M + (int64_t)(j0 + 2 * k + half) * np + col),
+                                     (lds_void *)(sB + k * 128), 16, 0, 0);
+  }
+}
+
+// One output tile: 4 waves, wave w owns points 32 (w & 1) .. +31 and functions
+// 32 (w >> 1) .. +31 of the tile as 2 x 2 blocks of 16 x 16 (FP64 MFMA
+// 16x16x4: A = phi [point][j], B = M [j][i]).  Per K chunk each wave reads its
+// 16 operands from the current buffers into registers, then issues the next
+// chunk's DMA into the other buffers, then its 16 MFMAs.  Epilogue: per
+// (point, function) of the wave the products with phi, 2 d_x phi, 2 d_y phi,
+// 2 d_z phi, summed over the wave's functions (lane shuffles) and over the two
+// waves of a point range (LDS), written as 4 x 64 partials of the tile.
+__global__ __launch_bounds__(256, 2) void k_grad_gemm(DevPlan d, const int32_t *items, int64_t it0, int64_t nit,
+                                                      const int64_t *cd_off, const int64_t *part_off,
+                                                      const double *cd, const double *panel, double *part) {
+  __shared__ double sA0[GS], sA1[GS], sB0[GS], sB1[GS];
+  __shared__ double s_red[2][GT][4];
+  const int64_t it = it0 + xcd_map(blockIdx.x, nit);
+  const int b = items[3 * it], tp = items[3 * it + 1], ti = items[3 * it + 2];
   const int g0 = d.batch_pt_off[b], P = d.batch_pt_off[b + 1] - g0;
-  const int f0 = d.batch_fn_off[b], n = d.batch_fn_off[b + 1] - f0;
-  const int sbase = d.batch_slot_off[b];
-  const int r0 = it.ti * T, c0 = it.tj * T + 32 * half;
+  const int n = d.batch_fn_off[b + 1] - d.batch_fn_off[b];
   const int Pp = (int)pad16(P), np = (int)pad16(n);
+  const int pt0 = GT * tp, i0 = GT * ti;
   const double *pb = panel + d.panel_off[b];
   const int64_t plane = (int64_t)Pp * np;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int js = wave & 1, ih = wave >> 1;  // column slice, row half
+  const double *M = cd + cd_off[b];
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int l16 = lane & 15, lk = lane >> 4;
-  const int cb = c0 + 16 * js;  // column block of this wave
-  // row origin of this wave's two row blocks.  Column half 0 of a diagonal
-  // tile has 3 active blocks, (0,0), (0,1) and (1,1) in 16-blocks: block (1,1)
-  // moves from wave (ih 0, js 1) to the otherwise idle wave (ih 1, js 1).
-  const bool dg0 = it.ti == it.tj && half == 0;
-  const int iloc = (dg0 && ih == 1 && js == 1) ? 16 : 32 * ih;
-  bool act[2], upper[2];
+  const int mq = wave & 1, nq = wave >> 1;
+  dbl4 acc[2][2];
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int rb = r0 + iloc + 16 * h;
-    act[h] = block_active(rb, cb, n) && !(dg0 && ih == 0 && js == 1 && h == 1);
-    upper[h] = rb < cb;
-  }
-  if (tid < T + T / 2) {
-    const bool row = tid < T;
-    const int lf = row ? r0 + tid : c0 + tid - T;
-    SlotInfo si{-1, 0, 0, 0};
-    if (lf < n) si = slot_of(d, f0, sbase, lf);
-    if (row) {
-      s_rslot[tid] = si.slot;
-      s_rfn[tid] = si.fnoff;
-    } else {
-      s_cslot[tid - T] = si.slot;
-      s_cfn[tid - T] = si.fnoff;
-      s_cnf[tid - T] = si.nfn;
-    }
-  }
-  __syncthreads();  // slot tables visible
-  const int rs0 = s_rslot[0], cs0 = s_cslot[0];
-  int rs1 = rs0, cs1 = cs0;
-  if (rs0 >= 0) rs1 = s_rslot[min(T, n - r0) - 1];
-  if (cs0 >= 0) cs1 = s_cslot[min(T / 2, n - c0) - 1];
-  const int nrs = rs0 >= 0 ? rs1 - rs0 + 1 : 0, ncs = cs0 >= 0 ? cs1 - cs0 + 1 : 0;
-  {
-    const int ns = d.batch_slot_off[b + 1] - sbase;
-    const int64_t spb = d.batch_sp_off[b];
-    for (int t = tid; t < nrs * ncs; t += NTG) {
-      const int si = rs0 + t / ncs, sj = cs0 + t % ncs;
-      s_pq[t] = si <= sj ? d.sp_pair[spb + (int64_t)si * ns - (int64_t)si * (si - 1) / 2 + (sj - si)] : -1;
-    }
-  }
-  __syncthreads();  // pair offsets visible
-  // K at tile row rl (0..63) and half column cl (0..31) of row block h: the
-  // stored element of the two atoms' pair block (upper atom-block triangle),
-  // plus the mirrored element when the 16 x 16 block is strictly upper inside
-  // one atom block (no work item computes the mirrored block); 0 off the
-  // active blocks.
-  // Both loads are unconditional (element 0 of the store, always present,
-  // stands in for an absent element) and selected afterwards, so that the
-  // loads of all 16 elements of a thread are in flight together.
-  auto kval = [&](int rl, int cl, int h) -> double {
-    const int rslot = s_rslot[rl], cslot = s_cslot[cl];
-    const int pq = (act[h] && rslot >= 0 && cslot >= 0) ? s_pq[(rslot - rs0) * ncs + (cslot - cs0)] : -1;
-    const bool live = pq >= 0;
-    const int64_t po = d.pair_off[live ? pq : 0];
-    const bool mir = live && upper[h] && rslot == cslot;
-    const int li = r0 + rl, lj = c0 + cl;
-    const int rfn = s_rfn[rl], cfn = s_cfn[cl], cnf = s_cnf[cl];
-    const double c = coef[live ? po + (int64_t)(li - rfn) * cnf + (lj - cfn) : 0];
-    const double cm = coef[mir ? po + (int64_t)(lj - rfn) * cnf + (li - cfn) : 0];
-    return (live ? c : 0.0) + (mir ? cm : 0.0);
-  };
-  // kt: first operand of u = K^T phi_rows, lane (l16 = column, lk) step ks:
-  //     K[iloc + 4 ks + lk][16 js + l16];
-  // kr: first operand of v = K phi_cols, lane (l16 = row, lk) row block h,
-  //     step s: K[iloc + 16 h + l16][16 js + 4 s + lk].
-  double kt[8], kr[2][4];
+  for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-  for (int ks = 0; ks < 8; ++ks) kt[ks] = kval(iloc + 4 * ks + lk, 16 * js + l16, ks >> 2);
-#pragma unroll
-  for (int h = 0; h < 2; ++h)
-#pragma unroll
-    for (int s4 = 0; s4 < 4; ++s4) kr[h][s4] = kval(iloc + 16 * h + l16, 16 * js + 4 * s4 + lk, h);
-  // materialise the slices here: left to itself the compiler sinks the
-  // selects into the chunk loop, where the wait for their loads (unknown
-  // count across the back edge) would also wait for the chunk's DMA
-#pragma unroll
-  for (int ks = 0; ks < 8; ++ks) asm volatile("" : "+v"(kt[ks]));
-#pragma unroll
-  for (int h = 0; h < 2; ++h)
-#pragma unroll
-    for (int s4 = 0; s4 < 4; ++s4) asm volatile("" : "+v"(kr[h][s4]));
-  double *out = partial + 8 * d.work_part_off[wi] + half * 4 * P;
-  const int jloc = 16 * js;
-
-  // Per chunk: phi of this chunk is in LDS buffer pbuf (its DMA was issued
-  // during the previous chunk); phi goes to registers, then this chunk's
-  // gradient components and the next chunk's phi are issued together and land
-  // while the MFMAs run; one wait, then the lane-local products.
-  dma_comps<T, RSA, 0, 1>(pb, plane, np, r0, 0, sa0[0]);
-  dma_comps<T / 2, RSB, 0, 1>(pb, plane, np, c0, 0, sb0[0]);
-  for (int k0 = 0; k0 < Pp; k0 += 16) {
-    const int rb2 = (k0 >> 4) & 1, pbuf = rb2;
-    // this chunk's phi has landed everywhere; the previous chunk's images are
-    // consumed and its per-wave sums visible
+    for (int nb = 0; nb < 2; ++nb) acc[mb][nb] = dbl4{0.0, 0.0, 0.0, 0.0};
+  const int nk = np / GK;
+  gemm_dma(pb, np, Pp, pt0, 0, M, i0, sA0, sB0);
+  for (int kc = 0; kc < nk; ++kc) {
+    const bool odd = kc & 1;
+    // chunk kc has landed everywhere; every wave has read chunk kc - 1
     barrier_vm<0>();
-    if (k0 > 0 && tid < 64 && k0 - 16 + (tid & 15) < P) {
-      const int o = tid >> 4, t = tid & 15;
-      out[o * P + k0 - 16 + t] = (s_red[rb2 ^ 1][0][o][t] + s_red[rb2 ^ 1][1][o][t]) +
-                                 (s_red[rb2 ^ 1][2][o][t] + s_red[rb2 ^ 1][3][o][t]);
-    }
-    auto issue_loads = [&]() {
-      dma_comps<T, RSA, 1, 4>(pb, plane, np, r0, k0 >> 2, sa1);
-      dma_comps<T / 2, RSB, 1, 4>(pb, plane, np, c0, k0 >> 2, sb1);
-      if (k0 + 16 < Pp) {  // the next chunk's phi, into the other buffer (last read in the previous chunk)
-        dma_comps<T, RSA, 0, 1>(pb, plane, np, r0, (k0 + 16) >> 2, sa0[pbuf ^ 1]);
-        dma_comps<T / 2, RSB, 0, 1>(pb, plane, np, c0, (k0 + 16) >> 2, sb0[pbuf ^ 1]);
+    const double *sA = odd ? sA1 : sA0, *sB = odd ? sB1 : sB0;
+    double a[2][4], bb[2][4];
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb) {
+        const int pt = 32 * mq + 16 * mb + l16;
+        a[mb][ks] = sA[(pt >> 2) * 64 + (4 * ks + lk) * 4 + (pt & 3)];
       }
-    };
-    // image element (component q, point pt of the chunk, function f)
-    auto A0 = [&](int f) { return sa0[pbuf][(l16 >> 1) * RSA + 2 * f + (l16 & 1)]; };
-    auto A1 = [&](int a, int f) { return sa1[((a - 1) * 8 + (l16 >> 1)) * RSA + 2 * f + (l16 & 1)]; };
-    auto B0 = [&](int f) { return sb0[pbuf][(l16 >> 1) * RSB + 2 * f + (l16 & 1)]; };
-    auto B1 = [&](int a, int f) { return sb1[((a - 1) * 8 + (l16 >> 1)) * RSB + 2 * f + (l16 & 1)]; };
-    double xg[4][4];
 #pragma unroll
-    for (int o = 0; o < 4; ++o)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) xg[o][r] = 0.0;
-    // Both products over the K steps of the active row blocks [H0, H1), as
-    // straight-line code: all MFMAs issued before any result is read.
-    auto chunk = [&](auto h0c, auto h1c) {
-      constexpr int H0 = decltype(h0c)::value, H1 = decltype(h1c)::value;
-      double ya[8], yb[4];
-#pragma unroll
-      for (int ks = 4 * H0; ks < 4 * H1; ++ks) ya[ks] = A0(iloc + 4 * ks + lk);  // phi_i, B[k = i][n = pt]
-#pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4) yb[s4] = B0(jloc + 4 * s4 + lk);          // phi_j, B[k = j][n = pt]
-      // the reads of phi stay ahead of the DMA (no LDS read waits for a DMA
-      // in flight)
-      __builtin_amdgcn_sched_barrier(0);
-      issue_loads();
-      dbl4 u0 = dbl4{0.0, 0.0, 0.0, 0.0}, u1 = u0, v[2] = {u0, u0};
-#pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4) {
-        if (H1 - H0 == 2) {
-          u0 = mfma64(kt[2 * s4], ya[2 * s4], u0);
-          u1 = mfma64(kt[2 * s4 + 1], ya[2 * s4 + 1], u1);
-        } else if ((s4 & 1) == 0) {
-          u0 = mfma64(kt[4 * H0 + s4], ya[4 * H0 + s4], u0);
-          u1 = mfma64(kt[4 * H0 + s4 + 1], ya[4 * H0 + s4 + 1], u1);
-        }
-#pragma unroll
-        for (int h = H0; h < H1; ++h) v[h] = mfma64(kr[h][s4], yb[s4], v[h]);
-      }
-      __builtin_amdgcn_sched_barrier(0);  // every MFMA issued before the wait for the loads
-      barrier_vm<0>();                    // every wave's gradient images (and next phi) have landed
-      // column values at (pt = l16, j = jloc + lk + 4 r): phi, d_x, d_y, d_z
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int j = jloc + d_row_f64(lk, r);
-        const double u = u0[r] + u1[r];
-        xg[0][r] += u * B0(j);
-#pragma unroll
-        for (int a = 1; a < 4; ++a) xg[a][r] += u * B1(a, j);
-      }
-      // row values at (pt = l16, i = iloc + 16 h + lk + 4 r): d_x, d_y, d_z
-#pragma unroll
-      for (int h = H0; h < H1; ++h)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int i = iloc + 16 * h + d_row_f64(lk, r);
-#pragma unroll
-          for (int a = 1; a < 4; ++a) xg[a][r] += v[h][r] * A1(a, i);
-        }
-    };
-    if (act[0] && act[1])
-      chunk(std::integral_constant<int, 0>{}, std::integral_constant<int, 2>{});
-    else if (act[0])
-      chunk(std::integral_constant<int, 0>{}, std::integral_constant<int, 1>{});
-    else if (act[1])
-      chunk(std::integral_constant<int, 1>{}, std::integral_constant<int, 2>{});
-    else {
-      // no active block: the same loads and barriers as the others
-      issue_loads();
-      barrier_vm<0>();
+      for (int nb = 0; nb < 2; ++nb) bb[nb][ks] = sB[(4 * ks + lk) * GT + 32 * nq + 16 * nb + l16];
     }
-    // sum over the wave's 16 columns (and 32 rows): the 4 registers, then the 4 lane rows
+    // the operand reads stay ahead of the next DMA (no LDS read waits for a
+    // DMA in flight)
+    __builtin_amdgcn_sched_barrier(0);
+    if (kc + 1 < nk) gemm_dma(pb, np, Pp, pt0, GK * (kc + 1), M, i0, odd ? sA0 : sA1, odd ? sB0 : sB1);
 #pragma unroll
-    for (int o = 0; o < 4; ++o) {
-      double sx = (xg[o][0] + xg[o][1]) + (xg[o][2] + xg[o][3]);
-      sx += __shfl_xor(sx, 16);
-      sx += __shfl_xor(sx, 32);
-      if (lane < 16) s_red[rb2][wave][o][l16] = sx;
-    }
+    for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) acc[mb][nb] = mfma64(a[mb][ks], bb[nb][ks], acc[mb][nb]);
   }
-  barrier_vm<63>();  // the last chunk's per-wave sums
+  // epilogue: lane (l16, lk) register r of block (mb, nb) holds Y at point
+  // 32 mq + 16 mb + lk + 4 r of the tile and function 32 nq + 16 nb + l16
+  double o[2][4][4];  // [mb][r][n, d_x n, d_y n, d_z n]
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int pg = pt0 + 32 * mq + 16 * mb + d_row_f64(lk, r);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) o[mb][r][c] = 0.0;
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) {
+        const int fi = i0 + 32 * nq + 16 * nb + l16;
+        if (pg < P && fi < n) {
+          const double y = acc[mb][nb][r];
+          const double *e = pb + ((int64_t)(pg >> 2) * np + fi) * 4 + (pg & 3);
+          o[mb][r][0] += y * e[0];
+          o[mb][r][1] += 2.0 * y * e[plane];
+          o[mb][r][2] += 2.0 * y * e[2 * plane];
+          o[mb][r][3] += 2.0 * y * e[3 * plane];
+        }
+      }
+    }
+  // over the 16 functions of a block (the lanes l16 of a lane row)
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        double v = o[mb][r][c];
+        v += __shfl_xor(v, 1);
+        v += __shfl_xor(v, 2);
+        v += __shfl_xor(v, 4);
+        v += __shfl_xor(v, 8);
+        o[mb][r][c] = v;
+      }
+  if (l16 == 0) {
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) s_red[nq][32 * mq + 16 * mb + d_row_f64(lk, r)][c] = o[mb][r][c];
+  }
+  barrier_vm<63>();  // the waves' sums are visible
   {
-    const int k0 = Pp - 16, rb2 = (k0 >> 4) & 1;
-    if (tid < 64 && k0 + (tid & 15) < P) {
-      const int o = tid >> 4, t = tid & 15;
-      out[o * P + k0 + t] = (s_red[rb2][0][o][t] + s_red[rb2][1][o][t]) + (s_red[rb2][2][o][t] + s_red[rb2][3][o][t]);
-    }
+    const int pt = tid >> 2, c = tid & 3;
+    if (pt0 + pt < Pp)
+      part[part_off[b] + ((int64_t)ti * 4 + c) * Pp + pt0 + pt] = s_red[0][pt][c] + s_red[1][pt][c];
   }
-  if (!PERSIST) break;
-  pos = next_item(tickets, npos, order != nullptr, &s_pos);
+}
+
+// The partials of a point summed over the batch's function tiles in tile
+// order: out is [4][n_points] (n, d_x n, d_y n, d_z n) in user point order.
+__global__ void k_grad_points(DevPlan d, int64_t b0, const int64_t *part_off, const double *part, double *out) {
+  const int64_t b = b0 + blockIdx.x;
+  const int g0 = d.batch_pt_off[b], P = d.batch_pt_off[b + 1] - g0;
+  const int n = d.batch_fn_off[b + 1] - d.batch_fn_off[b];
+  const int Pp = (int)pad16(P), nti = ((int)pad16(n) + GT - 1) / GT;
+  const double *pp = part + part_off[b];
+  for (int e = threadIdx.x; e < 4 * P; e += blockDim.x) {
+    const int c = e / P, g = e - c * P;
+    double s = 0.0;
+    for (int t = 0; t < nti; ++t) s += pp[((int64_t)t * 4 + c) * Pp + g];
+    out[(int64_t)c * d.n_points + d.perm[g0 + g]] = s;
   }
 }
 
 }  // namespace
 
-int launch_grad_tiles(const q4c_plan *p, int64_t w0, int64_t nw, const int32_t *order, const double *coef,
-                      const double *panel, double *gpart, unsigned *tickets, unsigned grid, hipStream_t s) {
-  if (tickets)
-    hipLaunchKernelGGL(k_grad_tiles<true>, dim3(grid), dim3(NTG), 0, s, p->dp, p->d_work, order, w0, nw, coef, panel,
-                       gpart, tickets);
-  else
-    hipLaunchKernelGGL(k_grad_tiles<false>, dim3(grid), dim3(NTG), 0, s, p->dp, p->d_work, order, w0, nw, coef, panel,
-                       gpart, tickets);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return hip_fail(e, "k_grad_tiles");
+int launch_grad_pass(const q4c_plan *p, size_t ip, const double *coef, const double *panel, double *out,
+                     hipStream_t s) {
+  const Pass &ps = p->passes[ip];
+  const int64_t c0 = p->gr_cd_item_off[ip], nc = p->gr_cd_item_off[ip + 1] - c0;
+  const int64_t w0 = p->gr_item_off[ip], nw = p->gr_item_off[ip + 1] - w0;
+  if (nc > 0) {
+    {
+      TimedLaunch tl_(p, Q4C_TIMER_OTHER, s);
+      hipLaunchKernelGGL(k_grad_cdense, dim3((unsigned)nc), dim3(256), 0, s, p->dp, p->d_gr_cditems, c0,
+                         p->d_gr_cd_off, p->d_gr_fninfo, coef, p->d_gr_cd);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "k_grad_cdense");
+  }
+  if (nw > 0) {
+    {
+      TimedLaunch tl_(p, Q4C_TIMER_DENSITY_TILES, s);
+      hipLaunchKernelGGL(k_grad_gemm, dim3((unsigned)nw), dim3(256), 0, s, p->dp, p->d_gr_items, w0, nw,
+                         p->d_gr_cd_off, p->d_gr_part_off, (const double *)p->d_gr_cd, panel, p->d_gr_part);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "k_grad_gemm");
+  }
+  const int64_t nbt = ps.b1 - ps.b0;
+  if (nbt > 0) {
+    {
+      TimedLaunch tl_(p, Q4C_TIMER_DENSITY_POINTS, s);
+      hipLaunchKernelGGL(k_grad_points, dim3((unsigned)nbt), dim3(256), 0, s, p->dp, ps.b0, p->d_gr_part_off,
+                         (const double *)p->d_gr_part, out);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "k_grad_points");
+  }
   return Q4C_OK;
 }
 

@@ -229,8 +229,16 @@ struct q4c_plan {
   mutable double *d_bloch_ph = nullptr; // phases of one k chunk: kBlochKChunk max(n_contrib, n_pairs) complex
   mutable int64_t bloch_ph_cap = 0;     // doubles
 
-  // ---- density gradient partials (density_gradient_on_grid), allocated on first use
-  mutable double *d_grad_partial = nullptr;
+  // ---- density_gradient_on_grid tables, built on first use: per pass the
+  // items (batch, 64-point tile, 64-function tile) of the product and
+  // (batch, 64-row block) of the dense M, per batch the pass-relative offsets
+  // of its M (np x np) and partials (function tiles x 4 x Pp), and buffers
+  // for the largest pass
+  mutable std::vector<int64_t> gr_item_off, gr_cd_item_off;  // [n_passes + 1]
+  mutable int32_t *d_gr_items = nullptr, *d_gr_cditems = nullptr;
+  mutable int64_t *d_gr_cd_off = nullptr, *d_gr_part_off = nullptr;
+  mutable int64_t *d_gr_fninfo = nullptr;  // [fn_entries] slot | slot's first function << 20 | its count << 40
+  mutable double *d_gr_cd = nullptr, *d_gr_part = nullptr;
 
   // ---- launch configuration (chosen by q4c_plan_autotune or set directly)
   q4c::LaunchCfg cfg_contract{}, cfg_density{}, cfg_hs{};
@@ -263,10 +271,11 @@ int launch_integrate(const q4c_plan *p, const double *v, int precision, uint32_t
 int launch_density(const q4c_plan *p, const double *coef, uint32_t terms, int weight_mode, double *out,
                    hipStream_t s);
 int launch_integrate_hs(const q4c_plan *p, const double *v, uint32_t flags, double *hs, hipStream_t s);
-int launch_density_grad(const q4c_plan *p, const double *coef, double *out, double *gpart, hipStream_t s);
-// k_grad_tiles over work items [w0, w0 + nw) of a pass (q4c_grad_kernels.hip)
-int launch_grad_tiles(const q4c_plan *p, int64_t w0, int64_t nw, const int32_t *order, const double *coef,
-                      const double *panel, double *gpart, unsigned *tickets, unsigned grid, hipStream_t s);
+int launch_density_grad(const q4c_plan *p, const double *coef, double *out, hipStream_t s);
+// dense M, product and point sums of one pass of density_gradient_on_grid
+// (q4c_grad_kernels.hip), on the pass's panel
+int launch_grad_pass(const q4c_plan *p, size_t ip, const double *coef, const double *panel, double *out,
+                     hipStream_t s);
 // Bloch sums of a store over the plan's cell pairs (q4c_bloch_kernels.hip),
 // k-points in chunks of kBlochKChunk; phase: 2 kBlochKChunk n_contrib doubles
 constexpr int kBlochKChunk = 64;

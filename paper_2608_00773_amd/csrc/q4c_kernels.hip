@@ -1112,23 +1112,6 @@ __global__ void k_density_points(DevPlan d, int64_t b0, const double *partial, i
   }
 }
 
-// Gradient partials of k_grad_tiles: four runs of P values per column half; out is [4][n_points].
-__global__ void k_density_points_grad(DevPlan d, int64_t b0, const double *partial, double *out) {
-  const int64_t b = b0 + blockIdx.x;
-  const int g0 = d.batch_pt_off[b], P = d.batch_pt_off[b + 1] - g0;
-  const int64_t wa = d.batch_work_off[b], wb = d.batch_work_off[b + 1];
-  for (int e = threadIdx.x; e < 4 * P; e += blockDim.x) {
-    const int o = e / P, g = e - o * P;
-    double s = 0.0;
-    for (int64_t w = wa; w < wb; ++w) {
-      const double *pw = partial + 8 * d.work_part_off[w];
-      s += pw[o * P + g];
-      s += pw[4 * P + o * P + g];
-    }
-    out[o * d.n_points + d.perm[g0 + g]] = s;
-  }
-}
-
 __global__ void k_fill(double *p, int64_t n, double v) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = v;
@@ -1392,7 +1375,7 @@ int launch_density(const q4c_plan *p, const double *coef, uint32_t terms, int we
   return Q4C_OK;
 }
 
-int launch_density_grad(const q4c_plan *p, const double *coef, double *out, double *gpart, hipStream_t s) {
+int launch_density_grad(const q4c_plan *p, const double *coef, double *out, hipStream_t s) {
   int rc;
   if (p->n_points > 0) {
     {
@@ -1402,18 +1385,9 @@ int launch_density_grad(const q4c_plan *p, const double *coef, double *out, doub
     }
     if ((rc = check_launch("k_fill")) != Q4C_OK) return rc;
   }
-  const LaunchCfg cfg = p->cfg_density;
-  const int32_t *order = cfg.order ? p->d_order : nullptr;
-  unsigned *tick0 = p->d_tickets + p->passes.size() * kTicketsPerLaunch;
-  if (cfg.persistent > 0) {
-    hipLaunchKernelGGL(k_zero_u32, dim3(8), dim3(256), 0, s, tick0, (int64_t)p->passes.size() * kTicketsPerLaunch);
-    if ((rc = check_launch("k_zero_u32")) != Q4C_OK) return rc;
-  }
   for (size_t ip = 0; ip < p->passes.size(); ++ip) {
     const Pass &ps = p->passes[ip];
-    const int64_t nw = ps.w1 - ps.w0, nbt = ps.b1 - ps.b0, nt = ps.t1 - ps.t0;
-    unsigned *tickets = cfg.persistent > 0 ? tick0 + ip * kTicketsPerLaunch : nullptr;
-    const unsigned grid = (unsigned)(cfg.persistent > 0 ? std::min<int64_t>(cfg.persistent, 2 * nw) : 2 * nw);
+    const int64_t nt = ps.t1 - ps.t0;
     double *panel = p->d_staging + ps.staging_len + ps.partial_len;
     if (nt > 0) {
       {
@@ -1422,20 +1396,7 @@ int launch_density_grad(const q4c_plan *p, const double *coef, double *out, doub
       }
       if ((rc = check_launch("k_panel")) != Q4C_OK) return rc;
     }
-    if (nw > 0) {
-      {
-        TimedLaunch tl_(p, Q4C_TIMER_DENSITY_TILES, s);
-        rc = launch_grad_tiles(p, ps.w0, nw, order, coef, panel, gpart, tickets, grid, s);
-      }
-      if (rc != Q4C_OK) return rc;
-    }
-    if (nbt > 0) {
-      {
-        TimedLaunch tl_(p, Q4C_TIMER_DENSITY_POINTS, s);
-        hipLaunchKernelGGL(k_density_points_grad, dim3((unsigned)nbt), dim3(256), 0, s, p->dp, ps.b0, gpart, out);
-      }
-      if ((rc = check_launch("k_density_points_grad")) != Q4C_OK) return rc;
-    }
+    if ((rc = launch_grad_pass(p, ip, coef, panel, out, s)) != Q4C_OK) return rc;
   }
   return Q4C_OK;
 }

@@ -1277,22 +1277,78 @@ int q4c_spinor_density_to_scalar(const q4c_plan *pl, const q4c_plan *ps, const d
   return q4c::launch_spinor_to_scalar(pl, d_dev, cl_dev, cs_dev, (hipStream_t)stream);
 }
 
+// The work items and buffers of density_gradient_on_grid (built on its first
+// call): per pass the product's items (batch, 64-point tile, 64-function
+// tile) and the dense-M items (batch, 64-row block), per batch the
+// pass-relative offsets of its dense M (np x np doubles) and of its partials
+// (function tiles x 4 x Pp doubles), per batch function its packed slot data
+// (slot | slot's first function << 20 | its count << 40), and the M and
+// partial buffers of the largest pass.
+static int build_grad_tables(const q4c_plan *p) {
+  const int64_t nb = (int64_t)p->batch_pt_off.size() - 1;
+  std::vector<int32_t> items, cditems;
+  std::vector<int64_t> cd_off(std::max<int64_t>(nb, 1), 0), part_off(std::max<int64_t>(nb, 1), 0);
+  std::vector<int64_t> item_off(1, 0), cd_item_off(1, 0);
+  int64_t max_cd = 0, max_part = 0;
+  for (const auto &ps : p->passes) {
+    int64_t cd = 0, part = 0;
+    for (int64_t b = ps.b0; b < ps.b1; ++b) {
+      const int64_t Pp = q4c::pad16(p->batch_pt_off[b + 1] - p->batch_pt_off[b]);
+      const int64_t np = q4c::pad16(p->batch_fn_off[b + 1] - p->batch_fn_off[b]);
+      const int64_t ntp = (Pp + 63) / 64, nti = (np + 63) / 64;
+      cd_off[b] = cd;
+      part_off[b] = part;
+      cd += np * np;
+      part += nti * 4 * Pp;
+      for (int64_t tp = 0; tp < ntp; ++tp)
+        for (int64_t ti = 0; ti < nti; ++ti) {
+          items.push_back((int32_t)b);
+          items.push_back((int32_t)tp);
+          items.push_back((int32_t)ti);
+        }
+      for (int64_t rb = 0; rb < (np + 63) / 64; ++rb) {
+        cditems.push_back((int32_t)b);
+        cditems.push_back((int32_t)rb);
+      }
+    }
+    max_cd = std::max(max_cd, cd);
+    max_part = std::max(max_part, part);
+    item_off.push_back((int64_t)items.size() / 3);
+    cd_item_off.push_back((int64_t)cditems.size() / 2);
+  }
+  if (items.empty()) items.assign(3, 0);
+  if (cditems.empty()) cditems.assign(2, 0);
+  std::vector<int64_t> fninfo(std::max<size_t>(p->loc_slot.size(), 1), 0);
+  for (int64_t b = 0; b < nb; ++b)
+    for (int32_t e = p->batch_fn_off[b]; e < p->batch_fn_off[b + 1]; ++e) {
+      const int64_t sl = p->loc_slot[e], so = p->batch_slot_off[b] + sl;
+      fninfo[e] = sl | ((int64_t)p->slot_fnoff[so] << 20) | ((int64_t)p->slot_nfn[so] << 40);
+    }
+  q4c_plan *w = const_cast<q4c_plan *>(p);
+  int rc;
+  if ((rc = upload(w, fninfo, &w->d_gr_fninfo)) != Q4C_OK) return rc;
+  if ((rc = upload(w, items, &w->d_gr_items)) != Q4C_OK) return rc;
+  if ((rc = upload(w, cditems, &w->d_gr_cditems)) != Q4C_OK) return rc;
+  if ((rc = upload(w, cd_off, &w->d_gr_cd_off)) != Q4C_OK) return rc;
+  if ((rc = upload(w, part_off, &w->d_gr_part_off)) != Q4C_OK) return rc;
+  void *ptr = nullptr;
+  if ((rc = device_alloc(w, (size_t)(max_cd + 64) * sizeof(double), &ptr)) != Q4C_OK) return rc;
+  w->d_gr_cd = (double *)ptr;
+  if ((rc = device_alloc(w, (size_t)(max_part + 64) * sizeof(double), &ptr)) != Q4C_OK) return rc;
+  w->d_gr_part = (double *)ptr;
+  w->gr_item_off = item_off;
+  w->gr_cd_item_off = cd_item_off;
+  return Q4C_OK;
+}
+
 int density_gradient_on_grid(const q4c_plan *p, const double *coef_dev, double *out_dev, void *stream) {
   if (!p) return fail(Q4C_EINVAL, "NULL plan");
   if (p->store_len > 0 && !coef_dev) return fail(Q4C_EINVAL, "NULL coefficients");
   if (p->n_points > 0 && !out_dev) return fail(Q4C_EINVAL, "NULL output");
   int rc = check_plan_dev(p);
   if (rc != Q4C_OK) return rc;
-  if (!p->d_grad_partial) {
-    // four partials per point and column half: 4x the adjoint's partial region of the largest pass
-    int64_t mx = 0;
-    for (const auto &ps : p->passes) mx = std::max(mx, ps.partial_len);
-    void *ptr = nullptr;
-    if ((rc = device_alloc(const_cast<q4c_plan *>(p), (size_t)(4 * mx + 16) * sizeof(double), &ptr)) != Q4C_OK)
-      return rc;
-    p->d_grad_partial = (double *)ptr;
-  }
-  return q4c::launch_density_grad(p, coef_dev, out_dev, p->d_grad_partial, (hipStream_t)stream);
+  if (p->gr_item_off.empty() && (rc = build_grad_tables(p)) != Q4C_OK) return rc;
+  return q4c::launch_density_grad(p, coef_dev, out_dev, (hipStream_t)stream);
 }
 
 int q4c_plan_set_cells(q4c_plan *p, int32_t n_cell_atoms, const int32_t *cell_atom, const double *shift) {

@@ -50,65 +50,66 @@ __device__ __forceinline__ int fslot(int64_t v) { return (int)(v & 0xFFFFF); }
 __device__ __forceinline__ int ffirst(int64_t v) { return (int)((v >> 20) & 0xFFFFF); }
 __device__ __forceinline__ int fcount(int64_t v) { return (int)(v >> 40); }
 
-constexpr int CD_NMAX = 2048;  // batch functions whose slot data fits in LDS
-constexpr int CD_PO = 2048;    // entries of the (row slot, batch slot) pair-offset table in LDS
-constexpr int CD_ROWS = 64;    // rows of M per workgroup
+constexpr int CD_T = 64;       // M tile edge
+constexpr int CD_PO = 1024;    // entries of the (row slot, column slot) pair-offset table of a tile in LDS
 
-// M of one 64-row block of one batch: M_rc for r in the block, all c < np.
-// Slots (relevant atoms) ascend with the batch's functions and with the atom
-// index, so slot lo < hi is the stored pair (atom(lo), atom(hi)), rows = lo's
-// functions.  The columns' slot data and the pair offsets of (the block's
-// row slots, every slot of the batch) are set up in LDS first, so that each
-// element costs one or two loads from the store, all independent.
+// One upper-triangle tile (rt <= ct) of M of one batch: M_rc for the tile's
+// rows r and columns c, and by symmetry the mirrored tile M_cr.  Slots
+// (relevant atoms) ascend with the batch's functions and with the atom
+// index, so slot lo < hi is the stored pair (atom(lo), atom(hi)) with rows =
+// lo's functions; above the diagonal (r < c) the row slot never exceeds the
+// column slot and the store is read in its own orientation, coalesced along
+// c (a self pair also takes its transposed element).  The tile goes through
+// LDS so that both it and its mirror are written along rows.
 __global__ __launch_bounds__(256) void k_grad_cdense(DevPlan d, const int32_t *items, int64_t it0,
                                                      const int64_t *cd_off, const int64_t *fninfo,
                                                      const double *coef, double *cd) {
-  __shared__ int64_t s_ci[CD_NMAX];
+  __shared__ double s_t[CD_T][CD_T + 1];
+  __shared__ int64_t s_ri[CD_T], s_ci[CD_T];
   __shared__ int64_t s_po[CD_PO];
   const int64_t it = it0 + blockIdx.x;
-  const int b = items[2 * it], rb = items[2 * it + 1];
+  const int b = items[3 * it], rt = items[3 * it + 1], ct = items[3 * it + 2];
   const int f0 = d.batch_fn_off[b], n = d.batch_fn_off[b + 1] - f0, np = (int)pad16(n);
   const int sbase = d.batch_slot_off[b], ns = d.batch_slot_off[b + 1] - sbase;
   const int64_t spb = d.batch_sp_off[b];
   double *M = cd + cd_off[b];
-  const int r0 = CD_ROWS * rb;
-  const int rlast = min(r0 + CD_ROWS, n) - 1;
+  const int r0 = CD_T * rt, c0 = CD_T * ct;  // both below n (tiles start below np - 15)
+  const int nr = min(CD_T, np - r0), nc = min(CD_T, np - c0);
   auto stored_po = [&](int rs, int cs) -> int64_t {
     const int lo = min(rs, cs), hi = max(rs, cs);
     const int q = d.sp_pair[spb + (int64_t)lo * ns - (int64_t)lo * (lo - 1) / 2 + (hi - lo)];
     return q >= 0 ? d.pair_off[q] : (int64_t)-1;
   };
-  // the block's row slots rs0..rs1 (rows past n: none)
-  const int rs0 = r0 < n ? fslot(fninfo[f0 + r0]) : 0;
-  const int rs1 = r0 < n ? fslot(fninfo[f0 + rlast]) : -1;
-  const int nrs = rs1 - rs0 + 1;
-  const bool ci_lds = n <= CD_NMAX, po_lds = (int64_t)nrs * ns <= CD_PO;  // workgroup-uniform
-  if (ci_lds)
-    for (int c = threadIdx.x; c < n; c += blockDim.x) s_ci[c] = fninfo[f0 + c];
+  if (threadIdx.x < CD_T) s_ri[threadIdx.x] = fninfo[f0 + min(r0 + (int)threadIdx.x, n - 1)];
+  else if (threadIdx.x < 2 * CD_T) s_ci[threadIdx.x - CD_T] = fninfo[f0 + min(c0 + (int)threadIdx.x - CD_T, n - 1)];
+  __syncthreads();  // slot data visible
+  const int rs0 = fslot(s_ri[0]), rs1 = fslot(s_ri[min(CD_T, n - r0) - 1]);
+  const int cs0 = fslot(s_ci[0]), cs1 = fslot(s_ci[min(CD_T, n - c0) - 1]);
+  const int nrs = rs1 - rs0 + 1, ncs = cs1 - cs0 + 1;
+  const bool po_lds = nrs * ncs <= CD_PO;  // workgroup-uniform
   if (po_lds)
-    for (int t = threadIdx.x; t < nrs * ns; t += blockDim.x) s_po[t] = stored_po(rs0 + t / ns, t % ns);
-  __syncthreads();  // tables visible
-  // four elements per thread at a time, their loads unconditional (element
-  // 0 of the store stands in for an absent one) and in flight together
-  const int ne = min(CD_ROWS, np - r0) * np;
-  for (int x0 = threadIdx.x; x0 < ne; x0 += 4 * blockDim.x) {
+    for (int t = threadIdx.x; t < nrs * ncs; t += blockDim.x) s_po[t] = stored_po(rs0 + t / ncs, cs0 + t % ncs);
+  __syncthreads();  // pair offsets visible
+  // the tile's elements with r <= c (all of them off the diagonal), four per
+  // thread at a time, loads unconditional (element 0 of the store stands in
+  // for an absent one) and in flight together
+  for (int x0 = threadIdx.x; x0 < CD_T * CD_T; x0 += 4 * blockDim.x) {
     int64_t a1[4], a2[4];
     bool live[4], self[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int x = x0 + u * blockDim.x;
-      const int rl = x / np;
-      const int r = r0 + rl, c = x - rl * np;
-      const bool in = x < ne && r < n && c < n;
-      const int rr = in ? r : 0, cc = in ? c : 0;
-      const int64_t ir_ = ci_lds ? s_ci[rr] : fninfo[f0 + rr], ic_ = ci_lds ? s_ci[cc] : fninfo[f0 + cc];
-      const int rs = fslot(ir_), cs = fslot(ic_);
-      const int64_t po = !in ? -1 : (po_lds ? s_po[(rs - rs0) * ns + cs] : stored_po(rs, cs));
-      const int ir = rr - ffirst(ir_), ic = cc - ffirst(ic_), rn = fcount(ir_), cn = fcount(ic_);
+      const int rl = x / CD_T, cl = x % CD_T;
+      const int r = r0 + rl, c = c0 + cl;
+      const bool in = r < n && c < n && r <= c;
+      const int64_t ri = s_ri[rl], ci = s_ci[cl];
+      const int rs = fslot(ri), cs = fslot(ci);
+      const int64_t po = !in ? -1 : (po_lds ? s_po[(rs - rs0) * ncs + cs - cs0] : stored_po(rs, cs));
+      const int ir = r - ffirst(ri), ic = c - ffirst(ci), cn = fcount(ci);
       live[u] = po >= 0;
       self[u] = rs == cs;
-      a1[u] = !live[u] ? 0 : (rs <= cs ? po + (int64_t)ir * cn + ic : po + (int64_t)ic * rn + ir);
-      a2[u] = live[u] && self[u] ? po + (int64_t)ic * cn + ir : 0;  // the self pair's transposed element
+      a1[u] = live[u] ? po + (int64_t)ir * cn + ic : 0;                // rs <= cs here
+      a2[u] = live[u] && self[u] ? po + (int64_t)ic * cn + ir : 0;     // the self pair's transposed element
     }
     double c1[4], c2[4];
 #pragma unroll
@@ -119,12 +120,22 @@ __global__ __launch_bounds__(256) void k_grad_cdense(DevPlan d, const int32_t *i
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int x = x0 + u * blockDim.x;
-      if (x < ne) {
-        const int rl = x / np;
-        M[(int64_t)(r0 + rl) * np + (x - rl * np)] = live[u] ? 0.5 * (c1[u] + (self[u] ? c2[u] : 0.0)) : 0.0;
-      }
+      s_t[x / CD_T][x % CD_T] = live[u] ? 0.5 * (c1[u] + (self[u] ? c2[u] : 0.0)) : 0.0;
     }
   }
+  __syncthreads();  // the tile is in LDS
+  // the tile (r <= c part; on the diagonal tile the rest from its mirror) and,
+  // off the diagonal, its mirror, both along rows
+  for (int x = threadIdx.x; x < nr * nc; x += blockDim.x) {
+    const int rl = x / nc, cl = x % nc;
+    const double v = (rt == ct && rl > cl) ? s_t[cl][rl] : s_t[rl][cl];
+    M[(int64_t)(r0 + rl) * np + c0 + cl] = v;
+  }
+  if (rt != ct)
+    for (int x = threadIdx.x; x < nr * nc; x += blockDim.x) {
+      const int cl = x / nr, rl = x % nr;
+      M[(int64_t)(c0 + cl) * np + r0 + rl] = s_t[rl][cl];
+    }
 }
 
 // LDS DMA of K chunk j0: the phi slice (panel component 0, 16 groups of 4

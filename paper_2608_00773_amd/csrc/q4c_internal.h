@@ -231,7 +231,7 @@ struct q4c_plan {
 
   // ---- density_gradient_on_grid tables, built on first use: per pass the
   // items (batch, 64-point tile, 64-function tile) of the product and
-  // (batch, 64-row block) of the dense M, per batch the pass-relative offsets
+  // (batch, 64 x 64 tile rt <= ct) of the dense M, per batch the pass-relative offsets
   // of its M (np x np) and partials (function tiles x 4 x Pp), and buffers
   // for the largest pass
   mutable std::vector<int64_t> gr_item_off, gr_cd_item_off;  // [n_passes + 1]

@@ -1279,7 +1279,7 @@ int q4c_spinor_density_to_scalar(const q4c_plan *pl, const q4c_plan *ps, const d
 
 // The work items and buffers of density_gradient_on_grid (built on its first
 // call): per pass the product's items (batch, 64-point tile, 64-function
-// tile) and the dense-M items (batch, 64-row block), per batch the
+// tile) and the dense-M items (batch, 64 x 64 tile rt <= ct), per batch the
 // pass-relative offsets of its dense M (np x np doubles) and of its partials
 // (function tiles x 4 x Pp doubles), per batch function its packed slot data
 // (slot | slot's first function << 20 | its count << 40), and the M and
@@ -1306,18 +1306,20 @@ static int build_grad_tables(const q4c_plan *p) {
           items.push_back((int32_t)tp);
           items.push_back((int32_t)ti);
         }
-      for (int64_t rb = 0; rb < (np + 63) / 64; ++rb) {
-        cditems.push_back((int32_t)b);
-        cditems.push_back((int32_t)rb);
-      }
+      for (int64_t rt = 0; rt < nti; ++rt)
+        for (int64_t ct = rt; ct < nti; ++ct) {
+          cditems.push_back((int32_t)b);
+          cditems.push_back((int32_t)rt);
+          cditems.push_back((int32_t)ct);
+        }
     }
     max_cd = std::max(max_cd, cd);
     max_part = std::max(max_part, part);
     item_off.push_back((int64_t)items.size() / 3);
-    cd_item_off.push_back((int64_t)cditems.size() / 2);
+    cd_item_off.push_back((int64_t)cditems.size() / 3);
   }
   if (items.empty()) items.assign(3, 0);
-  if (cditems.empty()) cditems.assign(2, 0);
+  if (cditems.empty()) cditems.assign(3, 0);
   std::vector<int64_t> fninfo(std::max<size_t>(p->loc_slot.size(), 1), 0);
   for (int64_t b = 0; b < nb; ++b)
     for (int32_t e = p->batch_fn_off[b]; e < p->batch_fn_off[b + 1]; ++e) {

@@ -7,7 +7,8 @@ n and grad n at points <= 1e-12 of the largest |value| of that column over the
 checked points (FP64 sums of products of the same magnitudes).  End to end on
 the GPU: sum_g w_g n_g = Re sum D_mu,nu S+_mu,nu (the density convention
 n = Re sum D_mu,nu chi*_mu chi_nu integrated) with S+ from q4c_integrate_HS and
-q4c_spinor_transform."""
+q4c_spinor_transform.  A cloud of one-function atoms takes the gradient
+kernels' paths for tiles that span many atoms."""
 import numpy as np
 import pytest
 
@@ -145,3 +146,33 @@ def test_electron_count_end_to_end_on_gpu(q, case, request):
         rhs += (1.0 if a == b else 2.0) * float(np.real(np.sum(e["D"][p].reshape(-1) * blk)))
     print("%s: sum w n = %.15g, Re sum D S+ = %.15g" % (case, lhs, rhs), flush=True)
     assert abs(lhs - rhs) <= 1e-11 * float(np.sum(wl.w * (np.abs(nl) + np.abs(ns))))
+
+
+def test_density_gradient_single_function_atoms(q):
+    """100 atoms with one s function each in an 8 angstrom cube: every function
+    is its own slot, so a 64 x 64 tile of a batch's coefficient matrix spans up
+    to 64 x 64 slot pairs (beyond the LDS pair-offset table: the global lookup
+    path), and batches hold up to 100 functions (several function tiles,
+    ragged).  n and grad n at sampled points against the oracle, same bar."""
+    import torch
+    rng = np.random.default_rng(8311)
+    nat = 100
+    R = rng.uniform(0.0, 8.0 * W.ANGSTROM, size=(nat, 3))
+    shells = [[(0, (0.3, 1.0, 4.0), (0.5, 0.4, 0.3))] for _ in range(nat)]
+    wl = W.pin_workload(np.ones(nat, dtype=np.int32), R, shells, nrad=12, ntheta=4, nphi=8, nint=512,
+                        name="s-cloud")
+    plan = q.Plan(wl)
+    _, _, fo, _ = plan.batches()
+    assert np.max(np.diff(fo)) > 64
+    pairs, po = plan.pairs()
+    coef = np.random.default_rng(8312).standard_normal(plan.info["store_len"])
+    got = _grad(q, plan, torch.from_numpy(coef).cuda(), wl.n_points)
+    idx = np.sort(rng.choice(wl.n_points, 300, replace=False))
+    nfn = wl.atom_nfn()
+    blocks = [coef[po[p]:po[p + 1]].reshape(int(nfn[a]), int(nfn[b])) for p, (a, b) in enumerate(pairs)]
+    ref = oracle.density_grad(wl, pairs, blocks, idx=idx)
+    for k in range(4):
+        sc = np.max(np.abs(ref[:, k])) + 1e-300
+        err = np.max(np.abs(got[k, idx] - ref[:, k]))
+        print("s-cloud col %d: max |d| %.3g, scale %.3g" % (k, err, sc), flush=True)
+        assert err <= 1e-12 * sc

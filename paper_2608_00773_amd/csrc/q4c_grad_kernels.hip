@@ -161,18 +161,55 @@ __device__ __forceinline__ void gemm_dma(const double *pb, int np, int Pp, int p
   }
 }
 
+// LDS byte address of a __shared__ array element
+__device__ __forceinline__ uint32_t lds_addr(const double *p) {
+  return (uint32_t)(uintptr_t)(const lds_void *)(const void *)p;
+}
+
+// The 16 MFMA operands of one K chunk of a wave, A[mb][ks] at pa + 2048 mb +
+// 128 ks and B[nb][ks] at pb + 2048 ks + 128 nb (bytes), read in one asm
+// block that also waits for them.  Issued by hand so that the compiler, which
+// cannot tell these reads from the LDS DMA still in flight into the other
+// buffers, does not wait for that DMA first.
+__device__ __forceinline__ void read_operands(uint32_t pa, uint32_t pb, double (&a)[2][4], double (&b)[2][4]) {
+  asm volatile(
+      "ds_read_b64 %0, %16\n"
+      "ds_read_b64 %1, %16 offset:128\n"
+      "ds_read_b64 %2, %16 offset:256\n"
+      "ds_read_b64 %3, %16 offset:384\n"
+      "ds_read_b64 %4, %16 offset:2048\n"
+      "ds_read_b64 %5, %16 offset:2176\n"
+      "ds_read_b64 %6, %16 offset:2304\n"
+      "ds_read_b64 %7, %16 offset:2432\n"
+      "ds_read_b64 %8, %17\n"
+      "ds_read_b64 %9, %17 offset:2048\n"
+      "ds_read_b64 %10, %17 offset:4096\n"
+      "ds_read_b64 %11, %17 offset:6144\n"
+      "ds_read_b64 %12, %17 offset:128\n"
+      "ds_read_b64 %13, %17 offset:2176\n"
+      "ds_read_b64 %14, %17 offset:4224\n"
+      "ds_read_b64 %15, %17 offset:6272\n"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(a[0][0]), "=&v"(a[0][1]), "=&v"(a[0][2]), "=&v"(a[0][3]), "=&v"(a[1][0]), "=&v"(a[1][1]),
+        "=&v"(a[1][2]), "=&v"(a[1][3]), "=&v"(b[0][0]), "=&v"(b[0][1]), "=&v"(b[0][2]), "=&v"(b[0][3]),
+        "=&v"(b[1][0]), "=&v"(b[1][1]), "=&v"(b[1][2]), "=&v"(b[1][3])
+      : "v"(pa), "v"(pb)
+      : "memory");
+}
+
 // One output tile: 4 waves, wave w owns points 32 (w & 1) .. +31 and functions
 // 32 (w >> 1) .. +31 of the tile as 2 x 2 blocks of 16 x 16 (FP64 MFMA
-// 16x16x4: A = phi [point][j], B = M [j][i]).  Per K chunk each wave reads its
-// 16 operands from the current buffers into registers, then issues the next
-// chunk's DMA into the other buffers, then its 16 MFMAs.  Epilogue: per
+// 16x16x4: A = phi [point][j], B = M [j][i]).  Three buffers: while chunk kc
+// is multiplied, chunk kc + 1 may still be in flight and chunk kc + 2 is
+// issued.  Per K chunk each wave reads its 16 operands into registers, issues
+// the DMA of chunk kc + 2, then its 16 MFMAs.  Epilogue: per
 // (point, function) of the wave the products with phi, 2 d_x phi, 2 d_y phi,
 // 2 d_z phi, summed over the wave's functions (lane shuffles) and over the two
 // waves of a point range (LDS), written as 4 x 64 partials of the tile.
 __global__ __launch_bounds__(256, 2) void k_grad_gemm(DevPlan d, const int32_t *items, int64_t it0, int64_t nit,
                                                       const int64_t *cd_off, const int64_t *part_off,
                                                       const double *cd, const double *panel, double *part) {
-  __shared__ double sA0[GS], sA1[GS], sB0[GS], sB1[GS];
+  __shared__ double sA[3][GS], sB[3][GS];
   __shared__ double s_red[2][GT][4];
   const int64_t it = it0 + xcd_map(blockIdx.x, nit);
   const int b = items[3 * it], tp = items[3 * it + 1], ti = items[3 * it + 2];
@@ -192,27 +229,23 @@ __global__ __launch_bounds__(256, 2) void k_grad_gemm(DevPlan d, const int32_t *
 #pragma unroll
     for (int nb = 0; nb < 2; ++nb) acc[mb][nb] = dbl4{0.0, 0.0, 0.0, 0.0};
   const int nk = np / GK;
-  gemm_dma(pb, np, Pp, pt0, 0, M, i0, sA0, sB0);
+  // this lane's operand addresses within a buffer (A: point block 0, K step 0;
+  // B: function block 0, K step 0), bytes
+  const uint32_t oa = 8u * (uint32_t)((8 * mq + (l16 >> 2)) * 64 + 4 * lk + (l16 & 3));
+  const uint32_t ob = 8u * (uint32_t)(lk * GT + 32 * nq + l16);
+  gemm_dma(pb, np, Pp, pt0, 0, M, i0, sA[0], sB[0]);
+  if (nk > 1) gemm_dma(pb, np, Pp, pt0, GK, M, i0, sA[1], sB[1]);
   for (int kc = 0; kc < nk; ++kc) {
-    const bool odd = kc & 1;
-    // chunk kc has landed everywhere; every wave has read chunk kc - 1
-    barrier_vm<0>();
-    const double *sA = odd ? sA1 : sA0, *sB = odd ? sB1 : sB0;
+    const int buf = kc % 3;
+    // chunk kc has landed everywhere (chunk kc + 1, four loads per wave, may
+    // still be in flight); every wave has read chunk kc - 1
+    if (kc + 1 < nk)
+      barrier_vm<4>();
+    else
+      barrier_vm<0>();
     double a[2][4], bb[2][4];
-#pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
-#pragma unroll
-      for (int mb = 0; mb < 2; ++mb) {
-        const int pt = 32 * mq + 16 * mb + l16;
-        a[mb][ks] = sA[(pt >> 2) * 64 + (4 * ks + lk) * 4 + (pt & 3)];
-      }
-#pragma unroll
-      for (int nb = 0; nb < 2; ++nb) bb[nb][ks] = sB[(4 * ks + lk) * GT + 32 * nq + 16 * nb + l16];
-    }
-    // the operand reads stay ahead of the next DMA (no LDS read waits for a
-    // DMA in flight)
-    __builtin_amdgcn_sched_barrier(0);
-    if (kc + 1 < nk) gemm_dma(pb, np, Pp, pt0, GK * (kc + 1), M, i0, odd ? sA0 : sA1, odd ? sB0 : sB1);
+    read_operands(lds_addr(sA[buf]) + oa, lds_addr(sB[buf]) + ob, a, bb);
+    if (kc + 2 < nk) gemm_dma(pb, np, Pp, pt0, GK * (kc + 2), M, i0, sA[(kc + 2) % 3], sB[(kc + 2) % 3]);
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks)
 #pragma unroll

@@ -921,30 +921,42 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t te
   // read from the coefficient store: element (li, lj) of the pair block of
   // its two atoms (upper atom-block triangle only), plus the mirrored element
   // (lj, li) when the 16 x 16 block is strictly upper inside one atom block
-  // (no work item computes the mirrored block); c' on the W parts.  All
-  // loads of a thread are independent and issued together.
+  // (no work item computes the mirrored block); c' on the W parts.  Every
+  // load is issued before any is used (element 0 stands in where there is
+  // nothing to read), so a thread waits for its loads once.
   double creg[NC][8];
   {
     const int64_t L = d.store_len;
     const int cl = 16 * js + l16;
     const int cslot = s_cslot[cl], cfn = s_cfn[cl], cnf = s_cnf[cl];
+    int64_t ea[8], em[8];
+    bool live[8], mir[8];
 #pragma unroll
     for (int ks = 0; ks < 8; ++ks) {
       const int rl = iloc + 4 * ks + lk;
       const int li = r0 + rl;
       const int rslot = s_rslot[rl], rfn = s_rfn[rl];
       const int64_t po = (act[ks >> 2] && rslot >= 0 && cslot >= 0) ? s_poff[(rslot - rs0) * ncs + (cslot - cs0)] : -1;
-      const bool live = po >= 0;
-      const bool mir = live && upper[ks >> 2] && rslot == cslot;
-      const int64_t e = po + (int64_t)(li - rfn) * cnf + (lj - cfn);
-      const int64_t em = po + (int64_t)(lj - rfn) * cnf + (li - cfn);
+      live[ks] = po >= 0;
+      mir[ks] = live[ks] && upper[ks >> 2] && rslot == cslot;
+      ea[ks] = live[ks] ? po + (int64_t)(li - rfn) * cnf + (lj - cfn) : 0;
+      em[ks] = mir[ks] ? po + (int64_t)(lj - rfn) * cnf + (li - cfn) : 0;
+    }
+    double cv[NC][8], cm[NC][8];
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks)
 #pragma unroll
       for (int q = 0; q < NC; ++q) {
-        double c = live ? coef[q * L + e] : 0.0;
-        if (mir) c += mirror_sign(q) * coef[q * L + em];
+        cv[q][ks] = coef[q * L + ea[ks]];
+        cm[q][ks] = coef[q * L + em[ks]];
+      }
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks)
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        const double c = (live[ks] ? cv[q][ks] : 0.0) + (mir[ks] ? mirror_sign(q) * cm[q][ks] : 0.0);
         creg[q][ks] = q == 0 ? c : d.cprime * c;
       }
-    }
   }
   const bool tLL = terms & Q4C_TERM_LL, tSS = terms & Q4C_TERM_SS, tSO = terms & Q4C_TERM_SO;
   // partials of this column half: NO runs of P values

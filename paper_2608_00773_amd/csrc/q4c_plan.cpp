@@ -1320,7 +1320,12 @@ static int build_grad_tables(const q4c_plan *p) {
   }
   if (items.empty()) items.assign(3, 0);
   if (cditems.empty()) cditems.assign(3, 0);
+  // per relevant function: batch-local slot (20 bits), the slot's first
+  // batch-local function (20 bits) and its function count
   std::vector<int64_t> fninfo(std::max<size_t>(p->loc_slot.size(), 1), 0);
+  for (int64_t b = 0; b < nb; ++b)
+    if (p->batch_fn_off[b + 1] - p->batch_fn_off[b] >= (1 << 20))
+      return fail(Q4C_EUNSUPPORTED, "a batch has 2^20 or more relevant functions");
   for (int64_t b = 0; b < nb; ++b)
     for (int32_t e = p->batch_fn_off[b]; e < p->batch_fn_off[b + 1]; ++e) {
       const int64_t sl = p->loc_slot[e], so = p->batch_slot_off[b] + sl;

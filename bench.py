@@ -38,8 +38,8 @@ PREC = {"f64": 0, "split": 1, "f32": 2}
 # cost-sorted queue does not): any change to those sources makes the figure
 # stale, and it is then reported as null.
 TRAFFIC = {
-    ("1ace33522c8957375a36e50bedb7d43109b4394b9576b5b3fb64c8a8b1784172", "f64", 120, 0): 11.079e9 + 3.974e9,
-    ("1ace33522c8957375a36e50bedb7d43109b4394b9576b5b3fb64c8a8b1784172", "f64", 120, 1): 19.788e9 + 4.377e9,
+    ("ad7aac7d3a20d8cb922670a7fb2b7bc4fc93562515428e4bb8e24cb7217dfd64", "f64", 120, 0): 11.090e9 + 3.974e9,
+    ("ad7aac7d3a20d8cb922670a7fb2b7bc4fc93562515428e4bb8e24cb7217dfd64", "f64", 120, 1): 19.978e9 + 4.361e9,
 }
 
 # The same for k_contract_hs (q4c_integrate_HS) per component and work order,

@@ -1,0 +1,102 @@
+"""GPU edge cases through the C ABI: an empty grid, a grid with no point
+inside any cutoff, and batches of at most 1 and 7 points (every 16-point chunk
+mostly padding).
+
+Empty and unreached grids: every output is exactly zero (nothing is summed;
+the store, the spinor blocks, the adjoint and the density gradient are
+cleared, not left as they were).  Tiny batches: the FP64 bars of the parity
+tests against the oracle, |GPU - oracle| <= 1e-12 A_ij per element of H and
+<= 1e-12 of the largest value for the adjoint."""
+import numpy as np
+import pytest
+
+import oracle
+import workload as W
+from helpers import blocks_to_store, gpu_available, store_to_blocks
+
+pytestmark = pytest.mark.gpu
+
+NAN = float("nan")
+
+
+@pytest.fixture(scope="module")
+def q():
+    if not gpu_available():
+        pytest.skip("no GPU")
+    import paper_2608_00773_amd as q4c
+    return q4c
+
+
+def _outputs(q, plan, wl, precision, seed):
+    """H (store and both spinor blocks), the weighted adjoint and the density
+    gradient of one plan, every output pre-filled with NaN."""
+    import torch
+    v = torch.from_numpy(wl.v).cuda()
+    store = q.new_store(plan).fill_(NAN)
+    spin_w = q.new_spinor(plan).fill_(NAN)
+    spin_v = q.new_spinor(plan).fill_(NAN)
+    q.q4c_integrate_H(plan, v, precision, q.ASSEMBLE_W | q.ASSEMBLE_V, store, spin_w, spin_v)
+    L = plan.info["store_len"]
+    coef = torch.from_numpy(np.random.default_rng(seed).standard_normal((5, L))).cuda()
+    adj = torch.full((wl.n_points,), NAN, dtype=torch.float64, device="cuda")
+    q.density_on_grid(plan, coef, q.TERM_ALL, 1, adj)
+    grad = torch.full((4, wl.n_points), NAN, dtype=torch.float64, device="cuda")
+    q.density_gradient_on_grid(plan, coef[0].contiguous(), grad)
+    torch.cuda.synchronize()
+    return (store.cpu().numpy(), spin_w.cpu().numpy(), spin_v.cpu().numpy(), adj.cpu().numpy(),
+            grad.cpu().numpy())
+
+
+@pytest.mark.parametrize("case", ["empty", "unreached"])
+def test_empty_and_unreached_grids_give_zeros(q, case):
+    wl = W.config_small(nrad=10, nang=26)
+    if case == "empty":
+        wl = wl.subset_points(np.arange(0))
+    else:
+        wl = wl.translated([0.0, 0.0, 0.0])
+        wl.x = wl.x + 1e4  # every point far outside every cutoff
+    plan = q.Plan(wl)
+    assert plan.info["n_active"] == 0 and plan.info["n_batches"] == 0 and plan.info["n_pairs"] == 6
+    for precision in (q.PREC_F64, q.PREC_SPLIT_F32):
+        print("case %s precision %d: %d points" % (case, precision, wl.n_points), flush=True)
+        for a in _outputs(q, plan, wl, precision, seed=11):
+            assert np.all(a == 0.0), (case, precision)
+
+
+@pytest.mark.parametrize("p_max", [1, 7])
+def test_tiny_batches_against_oracle(q, p_max):
+    wl = W.config_small(nrad=16, nang=26)
+    pairs = W.atom_pairs(wl)
+    plan = q.Plan(wl, p_max=p_max)
+    sizes = np.diff(plan.batches()[0])
+    assert sizes.max() <= p_max and sizes.min() >= 1
+    print("p_max %d: %d batches over %d active points" % (p_max, plan.info["n_batches"], plan.info["n_active"]),
+          flush=True)
+    store, _, _, adj, _ = _outputs(q, plan, wl, q.PREC_F64, seed=12)
+    _, po = plan.pairs()
+    nfn = wl.atom_nfn()
+    got = store_to_blocks(store, pairs, po, nfn)
+    ref, scale = oracle.pair_blocks(wl, pairs, with_abs=True)
+    worst = 0.0
+    for g, r, s in zip(got, ref, scale):
+        err = np.abs(g - r)
+        assert np.all(err[s == 0] == 0)
+        nz = s > 0
+        worst = max(worst, float(np.max(np.where(nz, err / np.where(nz, s, 1.0), 0.0))))
+    assert worst <= 1e-12, worst
+    # the adjoint with the same coefficients as _outputs drew
+    coef = np.random.default_rng(12).standard_normal((5, plan.info["store_len"]))
+    blocks = store_to_blocks(coef, pairs, po, nfn)
+    assert np.array_equal(blocks_to_store(blocks, po), coef)
+    want = oracle.density(wl, pairs, blocks, weight_mode=1)
+    assert np.max(np.abs(adj - want)) <= 1e-12 * np.max(np.abs(want))
+
+
+def test_tiny_batches_split_matches_f64(q):
+    """Split precision on batches of at most 7 points: within the 1e-8 Ha bar
+    of the FP64 store of the same plan."""
+    wl = W.config_small(nrad=16, nang=26)
+    plan = q.Plan(wl, p_max=7)
+    f64 = _outputs(q, plan, wl, q.PREC_F64, seed=13)[0]
+    split = _outputs(q, plan, wl, q.PREC_SPLIT_F32, seed=13)[0]
+    assert np.max(np.abs(split - f64)) <= 1e-8

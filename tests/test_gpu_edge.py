@@ -1,6 +1,6 @@
 """GPU edge cases through the C ABI: an empty grid, a grid with no point
 inside any cutoff, and batches of at most 1 and 7 points (every 16-point chunk
-mostly padding).
+mostly padding), and grid points exactly on a nucleus.
 
 Empty and unreached grids: every output is exactly zero (nothing is summed;
 the store, the spinor blocks, the adjoint and the density gradient are
@@ -100,3 +100,42 @@ def test_tiny_batches_split_matches_f64(q):
     f64 = _outputs(q, plan, wl, q.PREC_F64, seed=13)[0]
     split = _outputs(q, plan, wl, q.PREC_SPLIT_F32, seed=13)[0]
     assert np.max(np.abs(split - f64)) <= 1e-8
+
+
+def test_points_at_nuclei_against_oracle(q):
+    """Grid points exactly on each nucleus (s = 0: the (R'/s) r term of the
+    gradient takes its limit 0) added to a small grid: H, the adjoint and the
+    density gradient against the oracle at the FP64 bars."""
+    import dataclasses
+    base = W.config_small(nrad=12, nang=26)
+    na = base.R.shape[0]
+    rng = np.random.default_rng(14)
+    cat = lambda a, b: np.concatenate([a, b])
+    wl = dataclasses.replace(base, x=cat(base.x, base.R[:, 0]), y=cat(base.y, base.R[:, 1]),
+                             z=cat(base.z, base.R[:, 2]), w=cat(base.w, rng.uniform(0.05, 0.2, na)),
+                             pt_atom=cat(base.pt_atom, np.arange(na, dtype=base.pt_atom.dtype)),
+                             v=cat(base.v, rng.uniform(-2.0, -1.0, na)))
+    pairs = W.atom_pairs(wl)
+    plan = q.Plan(wl)
+    print("points at nuclei: %d points, %d active" % (wl.n_points, plan.info["n_active"]), flush=True)
+    store, _, _, adj, grad = _outputs(q, plan, wl, q.PREC_F64, seed=15)
+    _, po = plan.pairs()
+    nfn = wl.atom_nfn()
+    got = store_to_blocks(store, pairs, po, nfn)
+    ref, scale = oracle.pair_blocks(wl, pairs, with_abs=True)
+    for g, r, s in zip(got, ref, scale):
+        err = np.abs(g - r)
+        assert np.all(err[s == 0] == 0)
+        nz = s > 0
+        assert np.max(np.where(nz, err / np.where(nz, s, 1.0), 0.0)) <= 1e-12
+    coef = np.random.default_rng(15).standard_normal((5, plan.info["store_len"]))
+    blocks = store_to_blocks(coef, pairs, po, nfn)
+    want = oracle.density(wl, pairs, blocks, weight_mode=1)
+    assert np.max(np.abs(adj - want)) <= 1e-12 * np.max(np.abs(want))
+    gref = oracle.density_grad(wl, pairs, [b[0] for b in blocks])
+    for k in range(4):
+        sc = np.max(np.abs(gref[:, k])) + 1e-300
+        assert np.max(np.abs(grad[k] - gref[:, k])) <= 1e-12 * sc, k
+    # the added points themselves
+    tail = slice(base.n_points, wl.n_points)
+    assert np.all(np.isfinite(grad[:, tail])) and np.all(np.isfinite(adj[tail]))

@@ -47,20 +47,50 @@ def _outputs(q, plan, wl, precision, seed):
             grad.cpu().numpy())
 
 
+def _degenerate(wl, case):
+    """The workload without points, or with every point far outside every cutoff."""
+    if case == "empty":
+        return wl.subset_points(np.arange(0))
+    wl = wl.translated([0.0, 0.0, 0.0])
+    wl.x = wl.x + 1e4
+    return wl
+
+
 @pytest.mark.parametrize("case", ["empty", "unreached"])
 def test_empty_and_unreached_grids_give_zeros(q, case):
-    wl = W.config_small(nrad=10, nang=26)
-    if case == "empty":
-        wl = wl.subset_points(np.arange(0))
-    else:
-        wl = wl.translated([0.0, 0.0, 0.0])
-        wl.x = wl.x + 1e4  # every point far outside every cutoff
+    wl = _degenerate(W.config_small(nrad=10, nang=26), case)
     plan = q.Plan(wl)
     assert plan.info["n_active"] == 0 and plan.info["n_batches"] == 0 and plan.info["n_pairs"] == 6
     for precision in (q.PREC_F64, q.PREC_SPLIT_F32):
         print("case %s precision %d: %d points" % (case, precision, wl.n_points), flush=True)
         for a in _outputs(q, plan, wl, precision, seed=11):
             assert np.all(a == 0.0), (case, precision)
+
+
+@pytest.mark.parametrize("case", ["empty", "unreached"])
+def test_hs_and_spinor_transform_on_degenerate_grids(q, case):
+    """H and S of both components and the spinor transform on an empty or
+    unreached grid: exact zeros everywhere (outputs pre-filled with NaN)."""
+    import torch
+    large = W.with_ket(W.config_small(nrad=10, nang=26), 7301)
+    small = W.small_component(large, 7302)
+    plans, hs = [], []
+    for wl in (_degenerate(large, case), _degenerate(small, case)):
+        plan = q.Plan(wl)
+        plan.set_ket_potential(wl)
+        assert plan.info["n_active"] == 0
+        print("case %s: H/S of a component with %d functions" % (case, plan.info["n_fn"]), flush=True)
+        out = q.new_hs(plan).fill_(NAN)
+        q.q4c_integrate_HS(plan, torch.from_numpy(wl.v).cuda(), 0, out)
+        plans.append(plan)
+        hs.append(out)
+    L = plans[0].info["store_len"]
+    h = torch.full((8 * L,), NAN, dtype=torch.float64, device="cuda")
+    s_ = torch.full((8 * L,), NAN, dtype=torch.float64, device="cuda")
+    q.q4c_spinor_transform(plans[0], plans[1], hs[0], hs[1], h, s_)
+    torch.cuda.synchronize()
+    for a in (hs[0], hs[1], h, s_):
+        assert bool(torch.all(a == 0.0)), case
 
 
 @pytest.mark.parametrize("p_max", [1, 7])

@@ -380,7 +380,7 @@ def bench_molecules(a):
 def main():
     a = parse()
     if a.gpus != 1:
-        print("bench.py measures one GPU only; this build has no multi-GPU path (requested --gpus %d)" % a.gpus,
+        print("bench.py measures one GPU only: the library has no multi-GPU path (requested --gpus %d)" % a.gpus,
               file=sys.stderr)
         sys.exit(2)
     if a.workload == "molecules":

@@ -38,8 +38,8 @@ PREC = {"f64": 0, "split": 1, "f32": 2}
 # cost-sorted queue does not): any change to those sources makes the figure
 # stale, and it is then reported as null.
 TRAFFIC = {
-    ("ad7aac7d3a20d8cb922670a7fb2b7bc4fc93562515428e4bb8e24cb7217dfd64", "f64", 120, 0): 11.090e9 + 3.974e9,
-    ("ad7aac7d3a20d8cb922670a7fb2b7bc4fc93562515428e4bb8e24cb7217dfd64", "f64", 120, 1): 19.978e9 + 4.361e9,
+    ("4a6b3292980c6a95d3e6a34bc1d93b2435e74d13ec1870ffb4e4585e5c8b515a", "f64", 120, 0): 11.081e9 + 3.973e9,
+    ("4a6b3292980c6a95d3e6a34bc1d93b2435e74d13ec1870ffb4e4585e5c8b515a", "f64", 120, 1): 19.719e9 + 4.374e9,
 }
 
 # The same for k_contract_hs (q4c_integrate_HS) per component and work order,

@@ -179,22 +179,22 @@ __global__ void k_tabulate(DevPlan d, int64_t b0, int deriv, double *out) {
 // ---------------------------------------------------------------------------
 
 struct TileMeta {
-  double ax[2 * T], ay[2 * T], az[2 * T];  // centres
-  double rc[2 * T];                        // cutoffs (0 for padding)
-  double k1[2 * T], k2[2 * T];             // nint^2 / rcut, rcut / nint^2
-  int64_t coef[2 * T];                     // offset of the shell's table
-  int64_t uoff[2 * T];                     // offset of the shell's ket-potential table (H/S panels)
-  int nint[2 * T], lm[2 * T];
-  int order[2 * T];                        // per side: tile columns sorted by lm
+  double ax[T], ay[T], az[T];  // centres
+  double rc[T];                // cutoffs (0 for padding)
+  double k1[T], k2[T];         // nint^2 / rcut, rcut / nint^2
+  int64_t coef[T];             // offset of the shell's table
+  int64_t uoff[T];             // offset of the shell's ket-potential table (H/S panels)
+  int nint[T], lm[T];
+  int order[T];                // tile functions sorted by lm
 };
 
-// Stage metadata of the tile's functions (threads 0 .. 2T-1) and, per side,
-// an ordering by lm so that lanes working on neighbouring items mostly take
-// the same solid-harmonic branch.
-__device__ __forceinline__ void load_tile_meta(const DevPlan &d, TileMeta &M, int f0, int n, int r0, int c0) {
+// Stage metadata of the tile's functions (threads 0 .. T-1) and an ordering
+// by lm, so that lanes working on neighbouring items mostly take the same
+// solid-harmonic branch.
+__device__ __forceinline__ void load_tile_meta(const DevPlan &d, TileMeta &M, int f0, int n, int r0) {
   const int tid = threadIdx.x;
-  if (tid < 2 * T) {
-    const int lf = (tid < T ? r0 : c0) + (tid & (T - 1));
+  if (tid < T) {
+    const int lf = r0 + tid;
     if (lf < n) {
       const int fn = d.loc_fn[f0 + lf];
       const int a = d.fn_atom[fn], shlm = d.fn_shlm[fn], sh = shlm >> 5;
@@ -219,13 +219,11 @@ __device__ __forceinline__ void load_tile_meta(const DevPlan &d, TileMeta &M, in
     }
   }
   __syncthreads();
-  if (tid < 2 * T) {
-    const int side = tid / T, k = tid - side * T;
-    const int *lmv = M.lm + side * T;
-    const int mine = lmv[k];
+  if (tid < T) {
+    const int mine = M.lm[tid];
     int rank = 0;
-    for (int o = 0; o < T; ++o) rank += (lmv[o] < mine) || (lmv[o] == mine && o < k);
-    M.order[side * T + rank] = k;
+    for (int o = 0; o < T; ++o) rank += (M.lm[o] < mine) || (M.lm[o] == mine && o < tid);
+    M.order[rank] = tid;
   }
 }
 
@@ -353,9 +351,10 @@ template <bool HS>
 __global__ __launch_bounds__(256) void k_panel(DevPlan d, const WorkItem *tiles, int64_t t0, int64_t nt,
                                                double *panel) {
   constexpr int NQ = HS ? 2 : 4;  // components: phi, psi (H/S) or phi and its gradient
+  constexpr int CP = 8;           // points per chunk: a small stage keeps 7 workgroups on a CU
   __shared__ TileMeta M;
-  __shared__ double st[4 * 16 * PLD];
-  __shared__ double s_gx[4][16];
+  __shared__ double st[NQ * CP * PLD];
+  __shared__ double s_gx[4][CP];
   const WorkItem it = tiles[t0 + xcd_map(blockIdx.x, nt)];
   const int b = it.batch;
   const int g0 = d.batch_pt_off[b], P = d.batch_pt_off[b + 1] - g0;
@@ -363,54 +362,55 @@ __global__ __launch_bounds__(256) void k_panel(DevPlan d, const WorkItem *tiles,
   const int Pp = (int)pad16(P), np = (int)pad16(n);
   const int r0 = it.ti * T;
   const int nrow = np - r0 < T ? np - r0 : T;  // panel rows of this tile
-  load_tile_meta(d, M, f0, n, r0, r0);
+  load_tile_meta(d, M, f0, n, r0);
   __syncthreads();
   double *pb = panel + d.panel_off[b];
-  for (int g16 = 0; g16 < Pp; g16 += 16) {
-    for (int e = threadIdx.x; e < T * 16; e += 256) {
-      const int k = e >> 4, pt = e & 15;
+  for (int g8 = 0; g8 < Pp; g8 += CP) {
+    for (int e = threadIdx.x; e < T * CP; e += 256) {
+      const int k = e / CP, pt = e % CP;
       const int fl = M.order[k];
       double f = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
-      const int g = g16 + pt;
+      const int g = g8 + pt;
       if (HS) {
         if (M.nint[fl] > 0 && g < P) tab_meta_hs(d, M, fl, d.px[g0 + g], d.py[g0 + g], d.pz[g0 + g], f, fx);
       } else {
         if (M.nint[fl] > 0 && g < P) tab_meta(d, M, fl, d.px[g0 + g], d.py[g0 + g], d.pz[g0 + g], f, fx, fy, fz);
       }
-      st[(0 * 16 + pt) * PLD + fl] = f;
-      st[(1 * 16 + pt) * PLD + fl] = fx;
+      st[(0 * CP + pt) * PLD + fl] = f;
+      st[(1 * CP + pt) * PLD + fl] = fx;
       if (!HS) {
-        st[(2 * 16 + pt) * PLD + fl] = fy;
-        st[(3 * 16 + pt) * PLD + fl] = fz;
+        st[(2 * CP + pt) * PLD + fl] = fy;
+        st[(3 * CP + pt) * PLD + fl] = fz;
       }
     }
     __syncthreads();
     if (!HS) {
       // largest |d phi / d x_a| per point over the tile's functions: thread
-      // (pt, group of 4 functions), then the 4 groups of a wave, then the waves
-      const int pt = threadIdx.x & 15, fg = threadIdx.x >> 4;
+      // (pt, pair of functions), then the 8 pairs of a wave, then the waves
+      const int pt = threadIdx.x % CP, fg = threadIdx.x / CP;
       double m = 0.0;
 #pragma unroll
       for (int q = 1; q < 4; ++q)
 #pragma unroll
-        for (int k = 0; k < 4; ++k) m = fmax(m, fabs(st[(q * 16 + pt) * PLD + 4 * fg + k]));
+        for (int k = 0; k < 2; ++k) m = fmax(m, fabs(st[(q * CP + pt) * PLD + 2 * fg + k]));
+      m = fmax(m, __shfl_xor(m, 8));
       m = fmax(m, __shfl_xor(m, 16));
       m = fmax(m, __shfl_xor(m, 32));
-      if ((threadIdx.x & 63) < 16) s_gx[threadIdx.x >> 6][pt] = m;
+      if ((threadIdx.x & 63) < CP) s_gx[threadIdx.x >> 6][pt] = m;
     }
     // (q, point quad) runs: rows r0 .. r0 + nrow - 1, 4 points each, contiguous
 #pragma unroll
     for (int q = 0; q < NQ; ++q)
 #pragma unroll
-      for (int p4 = 0; p4 < 4; ++p4) {
+      for (int p4 = 0; p4 < CP / 4; ++p4) {
         const int e = threadIdx.x;  // 256 = 64 rows x 4 points
         const int il = e >> 2, pp = e & 3;
         if (il < nrow)
-          pb[((int64_t)(q * (Pp >> 2) + (g16 >> 2) + p4) * np + r0 + il) * 4 + pp] = st[(q * 16 + 4 * p4 + pp) * PLD + il];
+          pb[((int64_t)(q * (Pp >> 2) + (g8 >> 2) + p4) * np + r0 + il) * 4 + pp] = st[(q * CP + 4 * p4 + pp) * PLD + il];
       }
     __syncthreads();  // s_gx written; st consumed
-    if (!HS && threadIdx.x < 16)
-      pb[(int64_t)4 * Pp * np + (int64_t)it.ti * Pp + g16 + threadIdx.x] =
+    if (!HS && threadIdx.x < CP)
+      pb[(int64_t)4 * Pp * np + (int64_t)it.ti * Pp + g8 + threadIdx.x] =
           fmax(fmax(s_gx[0][threadIdx.x], s_gx[1][threadIdx.x]), fmax(s_gx[2][threadIdx.x], s_gx[3][threadIdx.x]));
   }
 }

@@ -51,7 +51,7 @@ __device__ __forceinline__ int ffirst(int64_t v) { return (int)((v >> 20) & 0xFF
 __device__ __forceinline__ int fcount(int64_t v) { return (int)(v >> 40); }
 
 constexpr int CD_T = 64;       // M tile edge
-constexpr int CD_PO = 1024;    // entries of the (row slot, column slot) pair-offset table of a tile in LDS
+constexpr int CD_PO = 256;     // entries of the (row slot, column slot) pair-offset table of a tile in LDS
 
 // One upper-triangle tile (rt <= ct) of M of one batch: M_rc for the tile's
 // rows r and columns c, and by symmetry the mirrored tile M_cr.  Slots

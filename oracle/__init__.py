@@ -64,14 +64,14 @@ def _load():
                                            ctypes.c_double, dp, dp]
         lib.orc_radial.argtypes = [dp, ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp]
         lib.orc_n_functions.argtypes = [bp]
-        lib.orc_tabulate.argtypes = [bp, ctypes.c_int64, dp, dp, dp, dp, dp]
+        lib.orc_tabulate.argtypes = [bp, ctypes.c_int64, dp, dp, dp, dp, dp, dp, dp]
         lib.orc_pair_blocks.argtypes = [bp, ctypes.c_int64, dp, dp, dp, dp, dp, ctypes.c_double, ctypes.c_int,
                                         ip, ip, ctypes.c_int, dp, dp]
         lib.orc_pair_blocks_hs.argtypes = [bp, ctypes.POINTER(ctypes.c_int64), dp, ctypes.c_int64, dp, dp, dp, dp,
                                            dp, ctypes.c_int, ip, ip, ctypes.c_int, dp, dp]
-        lib.orc_density_grad_points.argtypes = [bp, ctypes.c_int64, dp, dp, dp, ctypes.c_int, ip, ip, dp, dp]
+        lib.orc_density_grad_points.argtypes = [bp, ctypes.c_int64, dp, dp, dp, ctypes.c_int, ip, ip, dp, dp, dp]
         lib.orc_density_points.argtypes = [bp, ctypes.c_int64, dp, dp, dp, dp, ctypes.c_double, ctypes.c_int,
-                                           ip, ip, dp, ctypes.c_int, dp, dp]
+                                           ip, ip, dp, ctypes.c_int, dp, dp, dp]
         _lib = lib
     return _lib
 
@@ -125,16 +125,23 @@ def radial(table: np.ndarray, rcut: float, s: float):
     return v.value, d.value
 
 
-def tabulate(wl, x, y, z):
-    """phi [npts, nfn] and grad phi [npts, nfn, 3] of every function (brute force)."""
+def tabulate(wl, x, y, z, with_abs: bool = False):
+    """phi [npts, nfn] and grad phi [npts, nfn, 3] of every function (brute force).
+
+    with_abs: also the magnitudes of the terms each value is summed from (the
+    radial cubic's sum_k |c_k t^k| times the sum of |monomials| of S_lm, and
+    the gradient analogues), the error scale of each tabulated value."""
     lib = _load()
     h = _BasisHandle(wl)
     x, y, z = _c(x, np.float64), _c(y, np.float64), _c(z, np.float64)
     nfn = lib.orc_n_functions(h.ptr)
     phi = np.zeros((x.size, nfn))
     grad = np.zeros((x.size, nfn, 3))
-    lib.orc_tabulate(h.ptr, x.size, _dp(x), _dp(y), _dp(z), _dp(phi), _dp(grad))
-    return phi, grad
+    aphi = np.zeros_like(phi) if with_abs else None
+    agrad = np.zeros_like(grad) if with_abs else None
+    lib.orc_tabulate(h.ptr, x.size, _dp(x), _dp(y), _dp(z), _dp(phi), _dp(grad),
+                     _dp(aphi) if with_abs else None, _dp(agrad) if with_abs else None)
+    return (phi, grad, aphi, agrad) if with_abs else (phi, grad)
 
 
 def pair_blocks(wl, pairs: np.ndarray, v: Optional[np.ndarray] = None, screened: bool = True,
@@ -199,10 +206,15 @@ def pair_blocks_hs(wl, pairs: np.ndarray, v: Optional[np.ndarray] = None, screen
 
 
 def density(wl, pairs: np.ndarray, coef_blocks: Sequence[np.ndarray], idx: Optional[np.ndarray] = None,
-            weight_mode: int = 0, with_parts: bool = False):
+            weight_mode: int = 0, with_parts: bool = False, with_scale: bool = False):
     """Density / adjoint at grid points `idx` (default all) from per-pair
     coefficient blocks float64[5, nA, nB] (V, Ws, x, y, z; each stored element
-    counts once)."""
+    counts once).
+
+    with_parts: also the unweighted parts [npts, 3] (nL, nS scalar, nS spin-orbit).
+    with_scale: also the per-point error scale of each part [npts, 3]
+    (unweighted; see orc_density_points): sum over its terms of |C| times the
+    magnitudes of the two function factors.  Returned last."""
     lib = _load()
     h = _BasisHandle(wl)
     pairs = _c(pairs, np.int32).reshape(-1, 2)
@@ -213,10 +225,25 @@ def density(wl, pairs: np.ndarray, coef_blocks: Sequence[np.ndarray], idx: Optio
     x, y, z, w = (_c(t[idx], np.float64) for t in (wl.x, wl.y, wl.z, wl.w))
     out = np.zeros(x.size)
     parts = np.zeros((x.size, 3)) if with_parts else None
+    scale = np.zeros((x.size, 3)) if with_scale else None
     lib.orc_density_points(h.ptr, x.size, _dp(x), _dp(y), _dp(z), _dp(w), float(wl.c_light),
                            int(pairs.shape[0]), _ip(pa), _ip(pb), _dp(coef), int(weight_mode), _dp(out),
-                           _dp(parts) if with_parts else None)
-    return (out, parts) if with_parts else out
+                           _dp(parts) if with_parts else None, _dp(scale) if with_scale else None)
+    res = (out,)
+    if with_parts:
+        res += (parts,)
+    if with_scale:
+        res += (scale,)
+    return res if len(res) > 1 else out
+
+
+def density_scale(scale_parts: np.ndarray, w: Optional[np.ndarray] = None, terms: int = 7) -> np.ndarray:
+    """Per-point error scale of the selected terms (bit 1 LL, 2 SS scalar, 4 SS
+    spin-orbit) from density(..., with_scale=True), times |w_g| when the
+    weights are given (the adjoint, weight mode 1)."""
+    sel = [k for k in range(3) if terms & (1 << k)]
+    sc = np.sum(scale_parts[:, sel], axis=1)
+    return sc * np.abs(w) if w is not None else sc
 
 
 # ---------------------------------------------------------------------------
@@ -433,10 +460,11 @@ def spinor_density_to_scalar(pairs, D_blocks, GL, GS):
     return out
 
 
-def density_grad(wl, pairs, coef_blocks, idx=None):
+def density_grad(wl, pairs, coef_blocks, idx=None, with_scale: bool = False):
     """n and its gradient at grid points `idx` (default all) from one real
     coefficient block per pair (each stored element once): float64[npts, 4]
-    with columns n, dn/dx, dn/dy, dn/dz."""
+    with columns n, dn/dx, dn/dy, dn/dz.  with_scale: also the per-point error
+    scale of each column (see orc_density_grad_points)."""
     lib = _load()
     h = _BasisHandle(wl)
     pairs = _c(pairs, np.int32).reshape(-1, 2)
@@ -446,9 +474,10 @@ def density_grad(wl, pairs, coef_blocks, idx=None):
         idx = np.arange(wl.n_points)
     x, y, z = (_c(np.asarray(t)[idx], np.float64) for t in (wl.x, wl.y, wl.z))
     out = np.zeros((x.size, 4))
+    scale = np.zeros((x.size, 4)) if with_scale else None
     lib.orc_density_grad_points(h.ptr, x.size, _dp(x), _dp(y), _dp(z), int(pairs.shape[0]), _ip(pa), _ip(pb),
-                                _dp(coef), _dp(out))
-    return out
+                                _dp(coef), _dp(out), _dp(scale) if with_scale else None)
+    return (out, scale) if with_scale else out
 
 
 # ---------------------------------------------------------------------------

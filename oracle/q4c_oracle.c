@@ -149,6 +149,45 @@ void orc_solid_harmonic(int l, int m, double x, double y, double z, double *S, d
   g[2] = pref * (A * Qz);
 }
 
+/*
+ * Magnitude bounds of S_lm and grad S_lm at (x, y, z): the sums of |terms|
+ * of their polynomials in x, y, z.  With the factorisation above,
+ * S = pref A Q, every monomial of Re/Im (x+iy)^m is bounded in sum by
+ * (|x|+|y|)^m and every monomial of Q = sum_j a_j z^j rho^e (rho = x^2 + y^2
+ * + z^2, whose terms are all positive) by sum_j |a_j| |z|^j rho^e; the same
+ * holds term by term for the derivatives.  A value computed from any
+ * expansion of S then carries a rounding error of a few ulps of Sm (resp.
+ * gm), also where S itself cancels (near its nodal planes).
+ */
+static void solid_harmonic_mag(int l, int m, double x, double y, double z, double *Sm, double *gm) {
+  int am = m < 0 ? -m : m;
+  double K = sqrt((2.0 * l + 1.0) * fact(l - am) / (4.0 * M_PI * fact(l + am)));
+  double pref = (m == 0) ? K : sqrt(2.0) * K;
+  double ax = fabs(x), ay = fabs(y), az = fabs(z);
+  double Am = ipow(ax + ay, am), Ad = am > 0 ? am * ipow(ax + ay, am - 1) : 0.0;
+  double a[8];
+  legendre_deriv(l, am, a);
+  double rho = x * x + y * y + z * z;
+  double Q = 0.0, Qx = 0.0, Qy = 0.0, Qz = 0.0;
+  for (int j = 0; j <= l - am; ++j) {
+    if (a[j] == 0.0) continue;
+    int e = (l - am - j) / 2;
+    double c = fabs(a[j]), zj = ipow(az, j), re = ipow(rho, e);
+    Q += c * zj * re;
+    if (e >= 1) {
+      double re1 = ipow(rho, e - 1);
+      Qx += c * zj * e * re1 * 2.0 * ax;
+      Qy += c * zj * e * re1 * 2.0 * ay;
+      Qz += c * zj * e * re1 * 2.0 * az;
+    }
+    if (j >= 1) Qz += c * j * ipow(az, j - 1) * re;
+  }
+  *Sm = pref * Am * Q;
+  gm[0] = pref * (Ad * Q + Am * Qx);
+  gm[1] = pref * (Ad * Q + Am * Qy);
+  gm[2] = pref * Am * Qz;
+}
+
 /* ------------------------------------------------------------------ */
 /* Radial table                                                        */
 /* ------------------------------------------------------------------ */
@@ -233,6 +272,44 @@ static void atom_functions_c(const orc_basis *b, int a, double px, double py, do
   }
 }
 
+/*
+ * As atom_functions_c, with the magnitudes of the terms each value is summed
+ * from: the radial cubic's sum_k |c_k t^k| (and derivative analogue) times
+ * the magnitude bound of S_lm (and of its gradient) from solid_harmonic_mag.
+ * These bound the rounding of a value computed in any order at any point,
+ * including near the nodal planes of S_lm; they are the error scale of a
+ * single tabulated value and of the density at one point.
+ */
+static void atom_functions_m(const orc_basis *b, int a, double px, double py, double pz, double *phi,
+                             double *grad, double *aphi, double *agrad) {
+  double dx = px - b->R[3 * a], dy = py - b->R[3 * a + 1], dz = pz - b->R[3 * a + 2];
+  double s = sqrt(dx * dx + dy * dy + dz * dz);
+  int f = 0;
+  for (int sh = b->atom_shell_off[a]; sh < b->atom_shell_off[a + 1]; ++sh) {
+    int l = b->shell_l[sh];
+    double Rt, dRt, cR, cdR;
+    radial_eval(b->coef + b->shell_coef_off[sh], b->shell_nint[sh], b->shell_rcut[sh], s, &Rt, &dRt, &cR, &cdR);
+    double u[3] = {0.0, 0.0, 0.0}, au[3] = {0.0, 0.0, 0.0};
+    if (s > 0.0) {
+      u[0] = dRt * dx / s;
+      u[1] = dRt * dy / s;
+      u[2] = dRt * dz / s;
+      au[0] = cdR * fabs(dx) / s;
+      au[1] = cdR * fabs(dy) / s;
+      au[2] = cdR * fabs(dz) / s;
+    }
+    for (int m = -l; m <= l; ++m, ++f) {
+      double S, gS[3], Sm, gm[3];
+      orc_solid_harmonic(l, m, dx, dy, dz, &S, gS);
+      solid_harmonic_mag(l, m, dx, dy, dz, &Sm, gm);
+      phi[f] = Rt * S;
+      for (int c = 0; c < 3; ++c) grad[3 * f + c] = u[c] * S + Rt * gS[c];
+      aphi[f] = cR * Sm;
+      for (int c = 0; c < 3; ++c) agrad[3 * f + c] = au[c] * Sm + cR * gm[c];
+    }
+  }
+}
+
 static void atom_functions(const orc_basis *b, int a, double px, double py, double pz, double *phi,
                            double *grad) {
   atom_functions_c(b, a, px, py, pz, phi, grad, NULL, NULL);
@@ -244,14 +321,19 @@ int orc_n_functions(const orc_basis *b) {
   return n;
 }
 
-/* phi[g*nfn + i], grad[(g*nfn + i)*3 + c] for all functions at all points. */
+/* phi[g*nfn + i], grad[(g*nfn + i)*3 + c] for all functions at all points;
+ * aphi / agrad (optional, same layout): the magnitudes of atom_functions_m. */
 void orc_tabulate(const orc_basis *b, int64_t npts, const double *x, const double *y, const double *z,
-                  double *phi, double *grad) {
+                  double *phi, double *grad, double *aphi, double *agrad) {
   int nfn = orc_n_functions(b);
   for (int64_t g = 0; g < npts; ++g) {
     int f0 = 0;
     for (int a = 0; a < b->n_atoms; ++a) {
-      atom_functions(b, a, x[g], y[g], z[g], phi + g * nfn + f0, grad + (g * nfn + f0) * 3);
+      if (aphi)
+        atom_functions_m(b, a, x[g], y[g], z[g], phi + g * nfn + f0, grad + (g * nfn + f0) * 3,
+                         aphi + g * nfn + f0, agrad + (g * nfn + f0) * 3);
+      else
+        atom_functions(b, a, x[g], y[g], z[g], phi + g * nfn + f0, grad + (g * nfn + f0) * 3);
       f0 += atom_nfn(b, a);
     }
   }
@@ -455,10 +537,16 @@ int orc_pair_blocks_hs(const orc_basis *b, const int64_t *shell_u_off, const dou
  * orc_pair_blocks output).  Each stored element counts once.
  * out[g] = (weight_mode ? w_g : 1) * (nL + nSs + nSo); parts (optional)
  * receives [g*3 + 0..2] = nL, nSs, nSo (unweighted).
+ * scale (optional, [g*3 + 0..2], unweighted): the error scale of each part at
+ * the point, the sum over its terms of |C| times the magnitudes of the two
+ * function factors (atom_functions_m): |C^V| |phi_i| |phi_j|,
+ * c' |C^Ws| sum_a |d_a phi_i| |d_a phi_j| and
+ * c' |C^m| (|d_b phi_i| |d_c phi_j| + |d_c phi_i| |d_b phi_j|).  Any order of
+ * summing the terms stays within a small multiple of unit roundoff times it.
  */
 int orc_density_points(const orc_basis *b, int64_t npts, const double *x, const double *y, const double *z,
                        const double *w, double c_light, int npairs, const int32_t *pa, const int32_t *pb,
-                       const double *coef, int weight_mode, double *out, double *parts) {
+                       const double *coef, int weight_mode, double *out, double *parts, double *scale) {
   const double cp = 1.0 / (4.0 * c_light * c_light);
   int na = b->n_atoms;
   int64_t *poff = (int64_t *)malloc(sizeof(int64_t) * (npairs + 1));
@@ -467,10 +555,11 @@ int orc_density_points(const orc_basis *b, int64_t npts, const double *x, const 
   int maxfn = 0;
   for (int a = 0; a < na; ++a)
     if (atom_nfn(b, a) > maxfn) maxfn = atom_nfn(b, a);
-  double *fa = (double *)malloc(sizeof(double) * maxfn * 4);
-  double *fb = (double *)malloc(sizeof(double) * maxfn * 4);
+  double *fa = (double *)malloc(sizeof(double) * maxfn * 8);
+  double *fb = (double *)malloc(sizeof(double) * maxfn * 8);
   for (int64_t g = 0; g < npts; ++g) {
     double sL = 0, cL = 0, sS = 0, cS = 0, sO = 0, cO = 0;
+    double mL = 0, mS = 0, mO = 0;
     for (int p = 0; p < npairs; ++p) {
       int A = pa[p], B = pb[p];
       double rA = atom_rcut(b, A), rB = atom_rcut(b, B);
@@ -481,8 +570,15 @@ int orc_density_points(const orc_basis *b, int64_t npts, const double *x, const 
       int nA = atom_nfn(b, A), nB = atom_nfn(b, B);
       int64_t blk = (int64_t)nA * nB;
       double *ga = fa + nA, *gb = fb + nB;
-      atom_functions(b, A, x[g], y[g], z[g], fa, ga);
-      atom_functions(b, B, x[g], y[g], z[g], fb, gb);
+      double *xa = fa + 4 * nA, *xb = fb + 4 * nB; /* magnitudes */
+      double *ya = xa + nA, *yb = xb + nB;
+      if (scale) {
+        atom_functions_m(b, A, x[g], y[g], z[g], fa, ga, xa, ya);
+        atom_functions_m(b, B, x[g], y[g], z[g], fb, gb, xb, yb);
+      } else {
+        atom_functions(b, A, x[g], y[g], z[g], fa, ga);
+        atom_functions(b, B, x[g], y[g], z[g], fb, gb);
+      }
       const double *C = coef + poff[p];
       for (int i = 0; i < nA; ++i) {
         const double *gi = ga + 3 * i;
@@ -494,6 +590,14 @@ int orc_density_points(const orc_basis *b, int64_t npts, const double *x, const 
           neu_add(&sO, &cO, C[2 * blk + e] * (gi[1] * gj[2] - gi[2] * gj[1]));
           neu_add(&sO, &cO, C[3 * blk + e] * (gi[2] * gj[0] - gi[0] * gj[2]));
           neu_add(&sO, &cO, C[4 * blk + e] * (gi[0] * gj[1] - gi[1] * gj[0]));
+          if (scale) {
+            const double *hi = ya + 3 * i, *hj = yb + 3 * j;
+            mL += fabs(C[e]) * xa[i] * xb[j];
+            mS += fabs(C[blk + e]) * (hi[0] * hj[0] + hi[1] * hj[1] + hi[2] * hj[2]);
+            mO += fabs(C[2 * blk + e]) * (hi[1] * hj[2] + hi[2] * hj[1]) +
+                  fabs(C[3 * blk + e]) * (hi[2] * hj[0] + hi[0] * hj[2]) +
+                  fabs(C[4 * blk + e]) * (hi[0] * hj[1] + hi[1] * hj[0]);
+          }
         }
       }
     }
@@ -504,6 +608,11 @@ int orc_density_points(const orc_basis *b, int64_t npts, const double *x, const 
       parts[3 * g] = nL;
       parts[3 * g + 1] = nS;
       parts[3 * g + 2] = nO;
+    }
+    if (scale) {
+      scale[3 * g] = mL;
+      scale[3 * g + 1] = cp * mS;
+      scale[3 * g + 2] = cp * mO;
     }
   }
   free(poff);
@@ -521,9 +630,13 @@ int orc_density_points(const orc_basis *b, int64_t npts, const double *x, const 
  * (the density of Sec. II B / III A on the scalar basis, with the gradient a
  * GGA functional needs).  coef: per pair nA x nB row-major.  out[4 g + k]:
  * k = 0 n, 1..3 the x, y, z derivatives.  Sums are compensated.
+ * scale (optional, same layout): the error scale of each output, the sum over
+ * its terms of |C_ij| times the magnitudes of the factors (atom_functions_m):
+ * |phi_i| |phi_j| for n, |d_a phi_i| |phi_j| + |phi_i| |d_a phi_j| for dn/da.
  */
 int orc_density_grad_points(const orc_basis *b, int64_t npts, const double *x, const double *y, const double *z,
-                            int npairs, const int32_t *pa, const int32_t *pb, const double *coef, double *out) {
+                            int npairs, const int32_t *pa, const int32_t *pb, const double *coef, double *out,
+                            double *scale) {
   int na = b->n_atoms;
   int64_t *poff = (int64_t *)malloc(sizeof(int64_t) * (npairs + 1));
   poff[0] = 0;
@@ -531,10 +644,10 @@ int orc_density_grad_points(const orc_basis *b, int64_t npts, const double *x, c
   int maxfn = 0;
   for (int a = 0; a < na; ++a)
     if (atom_nfn(b, a) > maxfn) maxfn = atom_nfn(b, a);
-  double *fa = (double *)malloc(sizeof(double) * maxfn * 4);
-  double *fb = (double *)malloc(sizeof(double) * maxfn * 4);
+  double *fa = (double *)malloc(sizeof(double) * maxfn * 8);
+  double *fb = (double *)malloc(sizeof(double) * maxfn * 8);
   for (int64_t g = 0; g < npts; ++g) {
-    double s[4] = {0, 0, 0, 0}, c[4] = {0, 0, 0, 0};
+    double s[4] = {0, 0, 0, 0}, c[4] = {0, 0, 0, 0}, m[4] = {0, 0, 0, 0};
     for (int p = 0; p < npairs; ++p) {
       int A = pa[p], B = pb[p];
       double rA = atom_rcut(b, A), rB = atom_rcut(b, B);
@@ -544,17 +657,32 @@ int orc_density_grad_points(const orc_basis *b, int64_t npts, const double *x, c
       if (!(bx * bx + by * by + bz * bz < rB * rB)) continue;
       int nA = atom_nfn(b, A), nB = atom_nfn(b, B);
       double *ga = fa + nA, *gb = fb + nB;
-      atom_functions(b, A, x[g], y[g], z[g], fa, ga);
-      atom_functions(b, B, x[g], y[g], z[g], fb, gb);
+      double *xa = fa + 4 * nA, *xb = fb + 4 * nB; /* magnitudes */
+      double *ya = xa + nA, *yb = xb + nB;
+      if (scale) {
+        atom_functions_m(b, A, x[g], y[g], z[g], fa, ga, xa, ya);
+        atom_functions_m(b, B, x[g], y[g], z[g], fb, gb, xb, yb);
+      } else {
+        atom_functions(b, A, x[g], y[g], z[g], fa, ga);
+        atom_functions(b, B, x[g], y[g], z[g], fb, gb);
+      }
       const double *C = coef + poff[p];
       for (int i = 0; i < nA; ++i)
         for (int j = 0; j < nB; ++j) {
           double cij = C[(int64_t)i * nB + j];
           neu_add(&s[0], &c[0], cij * fa[i] * fb[j]);
           for (int k = 0; k < 3; ++k) neu_add(&s[k + 1], &c[k + 1], cij * (ga[3 * i + k] * fb[j] + fa[i] * gb[3 * j + k]));
+          if (scale) {
+            double ac = fabs(cij);
+            m[0] += ac * xa[i] * xb[j];
+            for (int k = 0; k < 3; ++k) m[k + 1] += ac * (ya[3 * i + k] * xb[j] + xa[i] * yb[3 * j + k]);
+          }
         }
     }
-    for (int k = 0; k < 4; ++k) out[4 * g + k] = s[k] + c[k];
+    for (int k = 0; k < 4; ++k) {
+      out[4 * g + k] = s[k] + c[k];
+      if (scale) scale[4 * g + k] = m[k];
+    }
   }
   free(poff);
   free(fa);

@@ -60,3 +60,15 @@ def spinor_from_blocks(blocks, pair_off) -> np.ndarray:
 def rel_to_scale(got, ref, scale, floor=0.0):
     """max |got - ref| / (scale + floor) elementwise."""
     return float(np.max(np.abs(got - ref) / (scale + floor))) if np.size(got) else 0.0
+
+
+def per_point_worst(got, ref, scale):
+    """max |got - ref| / scale over the entries whose scale is positive; where
+    the scale is 0 (no term reaches the entry: outside every support) the two
+    must agree exactly.  The scale of an entry is the oracle's sum of the
+    magnitudes of the terms it is summed from."""
+    got, ref, scale = (np.asarray(t, dtype=np.float64) for t in (got, ref, scale))
+    zero = ~(scale > 0)
+    assert np.array_equal(got[zero], ref[zero]), "entries with no terms differ"
+    nz = ~zero
+    return float(np.max(np.abs(got[nz] - ref[nz]) / scale[nz])) if np.any(nz) else 0.0

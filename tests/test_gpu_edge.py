@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 import workload as W
-from helpers import blocks_to_store, gpu_available, store_to_blocks
+from helpers import blocks_to_store, gpu_available, per_point_worst, store_to_blocks
 
 pytestmark = pytest.mark.gpu
 
@@ -118,8 +118,8 @@ def test_tiny_batches_against_oracle(q, p_max):
     coef = np.random.default_rng(12).standard_normal((5, plan.info["store_len"]))
     blocks = store_to_blocks(coef, pairs, po, nfn)
     assert np.array_equal(blocks_to_store(blocks, po), coef)
-    want = oracle.density(wl, pairs, blocks, weight_mode=1)
-    assert np.max(np.abs(adj - want)) <= 1e-12 * np.max(np.abs(want))
+    want, sc = oracle.density(wl, pairs, blocks, weight_mode=1, with_scale=True)
+    assert per_point_worst(adj, want, oracle.density_scale(sc, wl.w)) <= 1e-12
 
 
 def test_tiny_batches_split_matches_f64(q):
@@ -160,12 +160,11 @@ def test_points_at_nuclei_against_oracle(q):
         assert np.max(np.where(nz, err / np.where(nz, s, 1.0), 0.0)) <= 1e-12
     coef = np.random.default_rng(15).standard_normal((5, plan.info["store_len"]))
     blocks = store_to_blocks(coef, pairs, po, nfn)
-    want = oracle.density(wl, pairs, blocks, weight_mode=1)
-    assert np.max(np.abs(adj - want)) <= 1e-12 * np.max(np.abs(want))
-    gref = oracle.density_grad(wl, pairs, [b[0] for b in blocks])
+    want, sc = oracle.density(wl, pairs, blocks, weight_mode=1, with_scale=True)
+    assert per_point_worst(adj, want, oracle.density_scale(sc, wl.w)) <= 1e-12
+    gref, gsc = oracle.density_grad(wl, pairs, [b[0] for b in blocks], with_scale=True)
     for k in range(4):
-        sc = np.max(np.abs(gref[:, k])) + 1e-300
-        assert np.max(np.abs(grad[k] - gref[:, k])) <= 1e-12 * sc, k
+        assert per_point_worst(grad[k], gref[:, k], gsc[:, k]) <= 1e-12, k
     # the added points themselves
     tail = slice(base.n_points, wl.n_points)
     assert np.all(np.isfinite(grad[:, tail])) and np.all(np.isfinite(adj[tail]))

@@ -15,7 +15,7 @@ import pytest
 
 import oracle
 import workload as W
-from helpers import gpu_available
+from helpers import gpu_available, per_point_worst
 
 pytestmark = pytest.mark.gpu
 
@@ -168,7 +168,7 @@ def test_g_functions_tabulate_and_integrate_H(q, medium_sc):
     got = out.cpu().numpy()
     pt_off, pidx, fn_off, fidx = plan.batches()
     sel = pidx[:pt_off[nb]]
-    phi, grad = oracle.tabulate(ws, ws.x[sel], ws.y[sel], ws.z[sel])
+    phi, grad, aphi, agrad = oracle.tabulate(ws, ws.x[sel], ws.y[sel], ws.z[sel], with_abs=True)
     o, worst = 0, 0.0
     for b in range(nb):
         P = pt_off[b + 1] - pt_off[b]
@@ -177,8 +177,10 @@ def test_g_functions_tabulate_and_integrate_H(q, medium_sc):
         o += 4 * P * len(fns)
         rows = slice(pt_off[b], pt_off[b + 1])
         ref = np.concatenate([phi[rows][:, fns][None], np.moveaxis(grad[rows][:, fns, :], 2, 0)], axis=0)
-        worst = max(worst, float(np.max(np.abs(blk - ref))) / (np.max(np.abs(ref)) + 1e-300))
-    assert worst < 1e-13, worst
+        sref = np.concatenate([aphi[rows][:, fns][None], np.moveaxis(agrad[rows][:, fns, :], 2, 0)], axis=0)
+        worst = max(worst, per_point_worst(blk, ref, sref))
+    print("g-function tabulation: worst |d| / own scale %.3g" % worst, flush=True)
+    assert worst <= 1e-12, worst
     # W path: sampled pairs of heavy atoms (their small components carry g shells)
     v = torch.from_numpy(ws.v).cuda()
     store = q.new_store(plan)

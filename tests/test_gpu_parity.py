@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import workload as W
-from helpers import gpu_available, spinor_to_blocks, store_to_blocks
+from helpers import gpu_available, per_point_worst, spinor_to_blocks, store_to_blocks
 
 pytestmark = pytest.mark.gpu
 
@@ -102,7 +102,7 @@ def test_nao_tabulate_matches_oracle(q, small):
     torch.cuda.synchronize()
     got = out.cpu().numpy()
     pt_off, pidx, fn_off, fidx = plan.batches()
-    phi, grad = oracle.tabulate(wl, wl.x[pidx], wl.y[pidx], wl.z[pidx])
+    phi, grad, aphi, agrad = oracle.tabulate(wl, wl.x[pidx], wl.y[pidx], wl.z[pidx], with_abs=True)
     o = 0
     worst = 0.0
     for b in range(nb):
@@ -113,10 +113,12 @@ def test_nao_tabulate_matches_oracle(q, small):
         o += 4 * P * nf
         rows = slice(pt_off[b], pt_off[b + 1])
         ref = np.concatenate([phi[rows][:, fns][None], np.moveaxis(grad[rows][:, fns, :], 2, 0)], axis=0)
-        sc = np.max(np.abs(ref)) + 1e-300
-        worst = max(worst, float(np.max(np.abs(blk - ref))) / sc)
+        sref = np.concatenate([aphi[rows][:, fns][None], np.moveaxis(agrad[rows][:, fns, :], 2, 0)], axis=0)
+        # every value against the magnitude of its own terms
+        worst = max(worst, per_point_worst(blk, ref, sref))
     assert o == n
-    assert worst < 1e-13, worst
+    print("nao_tabulate: worst |d| / own scale %.3g" % worst)
+    assert worst <= 1e-12, worst
 
 
 def test_tabulate_values_only_and_size_errors(q, small):
@@ -232,9 +234,10 @@ def test_density_matches_oracle(q, small):
         q.density_on_grid(plan, coef, q.TERM_ALL, mode, out)
         torch.cuda.synchronize()
         got = out.cpu().numpy()
-        ref = oracle.density(wl, pairs, coef_blocks, weight_mode=mode)
-        sc = np.max(np.abs(ref))
-        assert np.max(np.abs(got - ref)) <= 1e-12 * sc, np.max(np.abs(got - ref)) / sc
+        ref, sc = oracle.density(wl, pairs, coef_blocks, weight_mode=mode, with_scale=True)
+        # every point against its own scale (R15 applied to Eq. 39)
+        worst = per_point_worst(got, ref, oracle.density_scale(sc, wl.w if mode else None))
+        assert worst <= 1e-12, (mode, worst)
 
 
 def test_density_terms_and_dot_product(q, small):
@@ -329,7 +332,8 @@ def test_density_multitile(q, medium):
     rng = np.random.default_rng(79)
     coef_blocks = [rng.standard_normal((5, nfn[a], nfn[b])) for a, b in pairs]
     idx = np.sort(rng.choice(wl.n_points, size=1500, replace=False))
-    ref = oracle.density(wl, pairs, coef_blocks, idx=idx, weight_mode=1)
+    ref, sc = oracle.density(wl, pairs, coef_blocks, idx=idx, weight_mode=1, with_scale=True)
+    sc = oracle.density_scale(sc, wl.w[idx])
     from helpers import blocks_to_store
     for p_max, staging in ((300, 0), (64, 1 << 20)):
         plan = q.Plan(wl, p_max=p_max, staging_bytes=staging)
@@ -340,7 +344,7 @@ def test_density_multitile(q, medium):
         torch.cuda.synchronize()
         got = out.cpu().numpy()
         assert np.all(np.isfinite(got))
-        assert np.max(np.abs(got[idx] - ref)) <= 1e-12 * np.max(np.abs(ref)), (p_max, staging)
+        assert per_point_worst(got[idx], ref, sc) <= 1e-12, (p_max, staging)
 
 
 def test_staging_passes_do_not_change_results(q, medium):

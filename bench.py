@@ -27,19 +27,25 @@ if ROOT not in sys.path:
 METRIC = "H-integration grid points/s & MFMA util: split-FP32 vs FP64 at ≤1e-8 Ha"
 PEAK_F64 = 78.6e12    # MI355X dense FP64 MFMA, flop/s
 PEAK_F32 = 157.3e12   # MI355X dense FP32 MFMA, flop/s
+PEAK_HBM = 8.0e12     # MI355X HBM3E, bytes/s
 PREC = {"f64": 0, "split": 1, "f32": 2}
 
-# HBM bytes per k_contract launch on the default cluster workload, from two
-# rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE), each scaled by what the same
-# counter reads for an elementwise copy of 1 GiB (read x1.9999, write x1.0000).
-# Keyed by the SHA-256 of the kernel sources the counters were taken on
-# (q4c_kernels.hip and q4c_device.h), the precision, the atom count and the
-# work order of the launch (batch order keeps a batch's tiles on one L2, the
-# cost-sorted queue does not): any change to those sources makes the figure
-# stale, and it is then reported as null.
+# HBM bytes per launch of the path's kernels on the default cluster workload,
+# from two rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE), each scaled by what
+# the same counter reads for an elementwise copy of 1 GiB (read x1.9999, write
+# x1.0000).  Keyed by kernel, the SHA-256 of the kernel sources the counters
+# were taken on (q4c_kernels.hip and q4c_device.h), the precision, the workload
+# and the work order of the launch (batch order keeps a batch's tiles on one
+# L2, the cost-sorted queue does not; None for kernels without one): any
+# change to those sources makes the figure stale, and it is then reported as
+# null.
+_R1 = "4a6b3292980c6a95d3e6a34bc1d93b2435e74d13ec1870ffb4e4585e5c8b515a"
 TRAFFIC = {
-    ("4a6b3292980c6a95d3e6a34bc1d93b2435e74d13ec1870ffb4e4585e5c8b515a", "f64", 120, 0): 11.081e9 + 3.973e9,
-    ("4a6b3292980c6a95d3e6a34bc1d93b2435e74d13ec1870ffb4e4585e5c8b515a", "f64", 120, 1): 19.719e9 + 4.374e9,
+    ("k_contract", _R1, "f64", "cluster-120", 0): 11.081e9 + 3.973e9,
+    ("k_contract", _R1, "f64", "cluster-120", 1): 19.719e9 + 4.374e9,
+    ("k_density_tiles", _R1, "f64", "cluster-120", 0): 9.939e9 + 0.144e9,
+    ("k_panel", _R1, "f64", "cluster-120", None): 0.085e9 + 5.952e9,
+    ("k_reduce", _R1, "f64", "cluster-120", None): 3.586e9 + 0.019e9,
 }
 
 # The same for k_contract_hs (q4c_integrate_HS) per component and work order,
@@ -70,7 +76,8 @@ def parse():
                     help="keep the default launch shapes (one workgroup per work item) and eager launches")
     ap.add_argument("--no-graphs", action="store_true",
                     help="autotune but launch eagerly (for per-dispatch counter collection)")
-    ap.add_argument("--cpu-sample", type=float, default=0.05, help="fraction of grid points for the oracle timing")
+    ap.add_argument("--cpu-sample", type=float, default=0.1,
+                    help="fraction of grid points for the oracle timing on all host threads (one thread: a tenth)")
     ap.add_argument("--n-atoms", type=int, default=120)
     ap.add_argument("--mode", choices=["full", "step", "forward", "adjoint", "hs"], default="full",
                     help="step/forward/adjoint: run only the whole step or that one call `steps` times "
@@ -102,26 +109,62 @@ def contraction_peak(prec: str) -> float:
     return 10.0 / (1.0 / PEAK_F64 + 9.0 / PEAK_F32)
 
 
-def cpu_baseline(wl, frac: float, seed: int = 6002):
-    """Time the oracle on a seeded sample of grid points (all atom pairs)."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl, plan, gbar, frac_all: float, frac_one: float, seed: int = 6002):
+    """The oracle timed on the host cores for the same step as the GPU line:
+    the forward pair blocks (all five parts of every atom pair) plus the
+    adjoint (w_g times the density of the seeded upstream gradient gbar,
+    weight mode 1) at a seeded sample of the grid points.  The oracle runs
+    OpenMP over pairs (forward) and over points (adjoint); each element's
+    summation order does not depend on the thread count.  Timed on all host
+    threads on a sample of frac_all of the points, and on one thread on a
+    sample of frac_one.  Points/s counts active sample points, as the GPU
+    figure does."""
     import numpy as np
     import oracle
-    import workload as W
     rng = np.random.default_rng(seed)
-    idx = np.sort(rng.choice(wl.n_points, size=max(1, int(frac * wl.n_points)), replace=False))
-    sub = wl.subset_points(idx)
-    pairs = W.atom_pairs(wl)
+    pairs, po = plan.pairs()
+    nfn = wl.atom_nfn()
+    g = gbar.cpu().numpy()
+    blocks = [g[:, po[p]:po[p + 1]].reshape(5, int(nfn[a]), int(nfn[b])) for p, (a, b) in enumerate(pairs)]
     rc = wl.atom_rcut()
-    d2 = ((sub.x[:, None] - wl.R[None, :, 0]) ** 2 + (sub.y[:, None] - wl.R[None, :, 1]) ** 2 +
-          (sub.z[:, None] - wl.R[None, :, 2]) ** 2)
-    n_act = int(np.sum(np.any(d2 < rc[None, :] ** 2, axis=1)))
     oracle.build()
-    t0 = time.perf_counter()
-    oracle.pair_blocks(sub, pairs)
-    dt = time.perf_counter() - t0
-    return {"value": n_act / dt, "unit": "points/s", "cores": 1, "kind": "oracle",
-            "sample": "%d of %d grid points (%d active, seed %d), all %d atom pairs, %.1f s" %
-                      (idx.size, wl.n_points, n_act, seed, len(pairs), dt)}
+    nthreads = oracle.max_threads()
+
+    def run(frac, threads):
+        idx = np.sort(rng.choice(wl.n_points, size=max(1, int(frac * wl.n_points)), replace=False))
+        sub = wl.subset_points(idx)
+        d2 = ((sub.x[:, None] - wl.R[None, :, 0]) ** 2 + (sub.y[:, None] - wl.R[None, :, 1]) ** 2 +
+              (sub.z[:, None] - wl.R[None, :, 2]) ** 2)
+        n_act = int(np.sum(np.any(d2 < rc[None, :] ** 2, axis=1)))
+        oracle.set_threads(threads)
+        t0 = time.perf_counter()
+        oracle.pair_blocks(sub, pairs)
+        t1 = time.perf_counter()
+        oracle.density(wl, pairs, blocks, idx=idx, weight_mode=1)
+        t2 = time.perf_counter()
+        return {"value": n_act / (t2 - t0), "unit": "points/s", "cores": threads, "kind": "oracle",
+                "sample": "%d of %d grid points (%d active, seed %d), forward over all %d atom pairs %.1f s + "
+                          "adjoint at the same points %.1f s" % (idx.size, wl.n_points, n_act, seed, len(pairs),
+                                                                 t1 - t0, t2 - t1),
+                "forward_s": t1 - t0, "adjoint_s": t2 - t1}
+
+    res = run(frac_all, nthreads)
+    res["single_core"] = run(frac_one, 1)
+    oracle.set_threads(nthreads)
+    res["nproc"] = os.cpu_count()
+    res["cpu_model"] = cpu_model()
+    return res
 
 
 def bench_hs(wl, timed, steps: int, cpu_frac: float, with_cpu: bool, components=("large", "small"),
@@ -468,6 +511,19 @@ def main():
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / k
 
+    def timed_each(fn, k, warm):
+        """Milliseconds of each of k calls (HIP events on the current stream) after warm untimed ones."""
+        for _ in range(warm):
+            fn()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(k)]
+        torch.cuda.synchronize()
+        for e0, e1 in ev:
+            e0.record()
+            fn()
+            e1.record()
+        torch.cuda.synchronize()
+        return [e0.elapsed_time(e1) for e0, e1 in ev]
+
     if a.calib_copy_mib:
         n = a.calib_copy_mib * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device=dev)
@@ -504,34 +560,59 @@ def main():
         step(prec)
     tim = plan.timers()
     plan.profile(False)
-    n_contract = max(tim["contract"][1], 1)
-    t_contract = tim["contract"][0] / n_contract * 1e-3  # s per launch
-    launches_per_step = tim["contract"][1] / a.steps
-    flops_launch = info["flops_alg"] / launches_per_step
-    achieved = flops_launch / t_contract
-    peak = contraction_peak(a.precision)
+    info = plan.info
+    n_act = info["n_active"]
+    ksha = source_sha("q4c_kernels.hip", "q4c_device.h")
+    c_order = plan.get_launch(q.KERNEL_CONTRACT)[0]
+    d_order = plan.get_launch(q.KERNEL_DENSITY)[0]
+    wkey = "%s-%d" % (a.workload, wl.n_atoms)
 
-    # forward-only throughput and error of each precision against the FP64 path
-    fwd = {}
-    outs = {}
-    hot = {}
+    def kernel_roofline(name, timer, bound, work_per_step, peak, unit, order=None):
+        """achieved = algorithmic work of one launch / average launch time of
+        the kernel (HIP events around each launch over the timed steps)."""
+        n = max(tim[timer][1], 1)
+        t = tim[timer][0] / n * 1e-3
+        per_step = tim[timer][1] / a.steps
+        work = work_per_step / max(per_step, 1e-300)
+        scale = 1e12 if unit == "TFLOP/s" else 1e9
+        return {"kernel": name, "bound": bound, "achieved": work / t / scale, "peak": peak / scale, "unit": unit,
+                "frac": work / t / peak, "traffic": TRAFFIC.get((name, ksha, a.precision, wkey, order)),
+                "alg_per_launch": work, "avg_launch_ms": t * 1e3, "launches_per_step": per_step,
+                "ms_per_step": tim[timer][0] / a.steps}
+
+    rl = [
+        kernel_roofline("k_contract", "contract", "mfma", info["flops_alg"], contraction_peak(a.precision),
+                        "TFLOP/s", c_order),
+        kernel_roofline("k_density_tiles", "density_tiles", "mfma", info["flops_alg"], PEAK_F64, "TFLOP/s",
+                        d_order),
+        # tabulation: 32 B (phi and its gradient, FP64) per (point, relevant function), forward and adjoint
+        kernel_roofline("k_panel", "tabulate", "hbm", 2 * 32.0 * info["tab_elems"], PEAK_HBM, "GB/s"),
+        # batch-to-global sum: the staged partial blocks read once, the five parts written once
+        kernel_roofline("k_reduce", "reduce", "hbm", info["staging_bytes"] + 40.0 * info["store_len"], PEAK_HBM,
+                        "GB/s"),
+    ]
+    dominant = max(rl, key=lambda r: r["ms_per_step"])
+
+    # q4c_integrate_H alone (the metric's t_H): each precision, all five parts
+    # and the W spinor, median of 20 calls timed one by one after 3 warm-ups;
+    # error of each split mode against the FP64 path
+    h_only, outs, hot = {}, {}, {}
     for name, p in PREC.items():
         st = q.new_store(plan, dev)
         call = lambda: q.q4c_integrate_H(plan, v, p, q.ASSEMBLE_W, st, spin)
-        call()  # untimed first call (captures its graph when graphs are on)
-        fwd[name] = timed(call, max(3, a.steps // 4))
+        ms_list = timed_each(call, 20, 3)
+        med = float(np.median(ms_list))
+        h_only[name] = {"ms_median": med, "points_per_s": n_act / (med * 1e-3),
+                        "gflops_alg": info["flops_alg"] / (med * 1e-3) / 1e9, "ms_min": float(np.min(ms_list))}
         outs[name] = st
         if name != "f64":
             h, t = plan.split_stats()
             hot[name] = h / max(t, 1)
+    for name in h_only:
+        h_only[name]["speedup_vs_f64"] = h_only["f64"]["ms_median"] / h_only[name]["ms_median"]
     err = {n: [float(torch.max(torch.abs(outs[n][k] - outs["f64"][k]))) for k in range(5)] for n in outs}
-    ms_adj = timed(lambda: q.density_on_grid(plan, gbar, q.TERM_ALL, 1, grad), max(3, a.steps // 4))
+    ms_adj = float(np.median(timed_each(lambda: q.density_on_grid(plan, gbar, q.TERM_ALL, 1, grad), 20, 3)))
 
-    ksha = source_sha("q4c_kernels.hip", "q4c_device.h")
-    c_order = plan.get_launch(q.KERNEL_CONTRACT)[0]
-    traffic = TRAFFIC.get((ksha, a.precision, a.n_atoms, c_order)) if a.workload == "cluster" else None
-
-    n_act = info["n_active"]
     res = {
         "metric": METRIC,
         "value": n_act / (ms_step * 1e-3),
@@ -555,23 +636,16 @@ def main():
             "step": "q4c_integrate_H (all parts + W spinor) + density_on_grid (adjoint, all terms)",
             "flops_alg_per_H": info["flops_alg"],
         },
-        "roofline": {
-            "kernel": "k_contract",
-            "bound": "mfma",
-            "achieved": achieved / 1e12,
-            "peak": peak / 1e12,
-            "unit": "TFLOP/s",
-            "frac": achieved / peak,
-            "traffic": traffic,
-            "avg_launch_ms": t_contract * 1e3,
-            "launches_per_step": launches_per_step,
-        },
+        "roofline": {k: dominant[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic", "kernel",
+                                              "avg_launch_ms")},
+        "roofline_kernels": rl,
+        "h_only": h_only,
+        "h_only_points_per_s": h_only[a.precision]["points_per_s"],
+        "adjoint_ms_median": ms_adj,
         "launch": {"contract": plan.get_launch(q.KERNEL_CONTRACT), "density": plan.get_launch(q.KERNEL_DENSITY),
                    "graphs": tune is not None and not a.no_graphs, "autotune_table": tune},
         "kernels_ms_per_step": {k: v_[0] / a.steps for k, v_ in tim.items() if v_[1]},
-        "forward_ms": fwd,
-        "forward_points_per_s": {k: n_act / (t * 1e-3) for k, t in fwd.items()},
-        "adjoint_ms": ms_adj,
+        "staging_bytes_per_call": info["staging_bytes"],
         "max_abs_diff_vs_f64_Ha": {k: dict(zip(q.PART_NAMES, e)) for k, e in err.items() if k != "f64"},
         "w_chunks_on_f64_mfma": hot,
         "plan_s": t_plan,
@@ -632,9 +706,9 @@ def main():
         log("Bloch density matrix: %d k-points -> %d stored elements: %.3f ms per call, k_bloch_density %.3f ms"
             % (kp.shape[0], plan.info["store_len"], ms_d, kd_ms))
     if not a.no_hs and a.workload == "cluster":
-        res["hs"] = bench_hs(wl, timed, a.steps, 0.2 * a.cpu_sample, not a.no_cpu_baseline)
+        res["hs"] = bench_hs(wl, timed, a.steps, 0.02 * a.cpu_sample, not a.no_cpu_baseline)
     if not a.no_cpu_baseline and a.workload == "cluster":
-        res["cpu_baseline"] = cpu_baseline(wl, a.cpu_sample)
+        res["cpu_baseline"] = cpu_baseline(wl, plan, gbar, a.cpu_sample, 0.1 * a.cpu_sample)
     print(json.dumps(res), flush=True)
 
 

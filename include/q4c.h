@@ -142,6 +142,9 @@ typedef struct {
   int32_t n_systems;       /* independent systems (1 unless q4c_plan_create_batched) */
   int64_t scratch_bytes;   /* device scratch of the plan (largest pass: staging, partials, panels) */
   double flops_alg_hs;     /* sum_B 3 P_B n_B^2: the three contractions of one q4c_integrate_HS */
+  int64_t staging_bytes;   /* per-batch partial blocks of one q4c_integrate_H, all passes: written by the
+                              contraction, read once by the batch-to-global sum */
+  int64_t tab_elems;       /* sum_B P_B n_B: (point, relevant function) pairs of all batches */
 } q4c_info;
 
 /* Build a plan: batching (recursive median bisection of the active points to
@@ -413,7 +416,9 @@ int q4c_plan_get_launch(const q4c_plan *plan, int32_t kernel, int32_t *order, in
  * overwritten), and, when coef_dev / out_dev are given, of the adjoint kernel
  * with density_on_grid(coef_dev, all terms, weight mode 1) into out_dev;
  * median of reps timed calls after one warm-up, HIP events on `stream`.
- * Keeps the fastest shape of each kernel on the plan and, if table is not
+ * Keeps the fastest shape of each kernel on the plan (a batch-order shape
+ * within 2% of the fastest wins over the cost-sorted order, which reads more
+ * HBM) and, if table is not
  * NULL, writes up to table_len entries (kernel, order, persistent, ms);
  * *n_entries = number of candidates timed.  Synchronises the stream.  Batch
  * size is a plan-time choice (q4c_opts.p_max): tune it by building plans. */

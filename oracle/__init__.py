@@ -40,7 +40,8 @@ def build(force: bool = False) -> str:
     """Compile the oracle with gcc (no GPU toolchain involved)."""
     if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
         tmp = _SO + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-ffp-contract=off", _SRC, "-o", tmp, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-ffp-contract=off", "-fopenmp", _SRC, "-o", tmp,
+                               "-lm"])
         os.replace(tmp, _SO)
     return _SO
 
@@ -72,8 +73,22 @@ def _load():
         lib.orc_density_grad_points.argtypes = [bp, ctypes.c_int64, dp, dp, dp, ctypes.c_int, ip, ip, dp, dp, dp]
         lib.orc_density_points.argtypes = [bp, ctypes.c_int64, dp, dp, dp, dp, ctypes.c_double, ctypes.c_int,
                                            ip, ip, dp, ctypes.c_int, dp, dp, dp]
+        lib.orc_max_threads.argtypes = []
+        lib.orc_max_threads.restype = ctypes.c_int
+        lib.orc_set_threads.argtypes = [ctypes.c_int]
+        lib.orc_set_threads.restype = None
         _lib = lib
     return _lib
+
+
+def max_threads() -> int:
+    """Threads the oracle's parallel loops use (OpenMP over pairs or points;
+    each element's summation order does not depend on it)."""
+    return int(_load().orc_max_threads())
+
+
+def set_threads(n: int) -> None:
+    _load().orc_set_threads(int(n))
 
 
 def _c(a, dt):

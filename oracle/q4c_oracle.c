@@ -45,6 +45,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef struct {
   int32_t n_atoms;
@@ -372,12 +375,17 @@ int orc_pair_blocks(const orc_basis *b, int64_t npts, const double *x, const dou
                     const double *w, const double *v, double c_light, int npairs, const int32_t *pa,
                     const int32_t *pb, int screened, double *out, double *absout) {
   const double cp = 1.0 / (4.0 * c_light * c_light);
-  int64_t off = 0;
+  int64_t *offs = (int64_t *)malloc(sizeof(int64_t) * (npairs + 1));
+  offs[0] = 0;
+  for (int p = 0; p < npairs; ++p) offs[p + 1] = offs[p] + 5 * (int64_t)atom_nfn(b, pa[p]) * atom_nfn(b, pb[p]);
+  /* pairs are independent: one thread per pair, each element summed in point order */
+#pragma omp parallel for schedule(dynamic, 1)
   for (int p = 0; p < npairs; ++p) {
     int A = pa[p], B = pb[p];
     int nA = atom_nfn(b, A), nB = atom_nfn(b, B);
     double rA = atom_rcut(b, A), rB = atom_rcut(b, B);
     int64_t blk = (int64_t)nA * nB;
+    const int64_t off = offs[p];
     double *sum = (double *)calloc(5 * blk, sizeof(double));
     double *cmp = (double *)calloc(5 * blk, sizeof(double));
     double *abs_ = (double *)calloc(5 * blk, sizeof(double));
@@ -427,13 +435,13 @@ int orc_pair_blocks(const orc_basis *b, int64_t npts, const double *x, const dou
         if (absout) absout[off + q * blk + e] = abs_[q * blk + e] * sc;
       }
     }
-    off += 5 * blk;
     free(sum);
     free(cmp);
     free(abs_);
     free(fa);
     free(fb);
   }
+  free(offs);
   return 0;
 }
 
@@ -471,12 +479,16 @@ int orc_pair_blocks_hs(const orc_basis *b, const int64_t *shell_u_off, const dou
                        const double *x, const double *y, const double *z, const double *w, const double *v,
                        int npairs, const int32_t *pa, const int32_t *pb, int screened, double *out,
                        double *absout) {
-  int64_t off = 0;
+  int64_t *offs = (int64_t *)malloc(sizeof(int64_t) * (npairs + 1));
+  offs[0] = 0;
+  for (int p = 0; p < npairs; ++p) offs[p + 1] = offs[p] + 2 * (int64_t)atom_nfn(b, pa[p]) * atom_nfn(b, pb[p]);
+#pragma omp parallel for schedule(dynamic, 1)
   for (int p = 0; p < npairs; ++p) {
     int A = pa[p], B = pb[p];
     int nA = atom_nfn(b, A), nB = atom_nfn(b, B);
     double rA = atom_rcut(b, A), rB = atom_rcut(b, B);
     int64_t blk = (int64_t)nA * nB;
+    const int64_t off = offs[p];
     double *sum = (double *)calloc(2 * blk, sizeof(double));
     double *cmp = (double *)calloc(2 * blk, sizeof(double));
     double *abs_ = (double *)calloc(2 * blk, sizeof(double));
@@ -515,13 +527,13 @@ int orc_pair_blocks_hs(const orc_basis *b, const int64_t *shell_u_off, const dou
       out[off + e] = sum[e] + cmp[e];
       if (absout) absout[off + e] = abs_[e];
     }
-    off += 2 * blk;
     free(sum);
     free(cmp);
     free(abs_);
     free(fa);
     free(fb);
   }
+  free(offs);
   return 0;
 }
 
@@ -555,8 +567,12 @@ int orc_density_points(const orc_basis *b, int64_t npts, const double *x, const 
   int maxfn = 0;
   for (int a = 0; a < na; ++a)
     if (atom_nfn(b, a) > maxfn) maxfn = atom_nfn(b, a);
+  /* points are independent: each thread sums its points' terms in pair order */
+#pragma omp parallel
+  {
   double *fa = (double *)malloc(sizeof(double) * maxfn * 8);
   double *fb = (double *)malloc(sizeof(double) * maxfn * 8);
+#pragma omp for schedule(dynamic, 16)
   for (int64_t g = 0; g < npts; ++g) {
     double sL = 0, cL = 0, sS = 0, cS = 0, sO = 0, cO = 0;
     double mL = 0, mS = 0, mO = 0;
@@ -615,9 +631,10 @@ int orc_density_points(const orc_basis *b, int64_t npts, const double *x, const 
       scale[3 * g + 2] = cp * mO;
     }
   }
-  free(poff);
   free(fa);
   free(fb);
+  }
+  free(poff);
   return 0;
 }
 
@@ -644,8 +661,12 @@ int orc_density_grad_points(const orc_basis *b, int64_t npts, const double *x, c
   int maxfn = 0;
   for (int a = 0; a < na; ++a)
     if (atom_nfn(b, a) > maxfn) maxfn = atom_nfn(b, a);
+  /* points are independent: each thread sums its points' terms in pair order */
+#pragma omp parallel
+  {
   double *fa = (double *)malloc(sizeof(double) * maxfn * 8);
   double *fb = (double *)malloc(sizeof(double) * maxfn * 8);
+#pragma omp for schedule(dynamic, 16)
   for (int64_t g = 0; g < npts; ++g) {
     double s[4] = {0, 0, 0, 0}, c[4] = {0, 0, 0, 0}, m[4] = {0, 0, 0, 0};
     for (int p = 0; p < npairs; ++p) {
@@ -684,8 +705,27 @@ int orc_density_grad_points(const orc_basis *b, int64_t npts, const double *x, c
       if (scale) scale[4 * g + k] = m[k];
     }
   }
-  free(poff);
   free(fa);
   free(fb);
+  }
+  free(poff);
   return 0;
+}
+
+/* Threads used by the parallel loops above (OpenMP; 1 without it), and a
+ * way to set them: the CPU baseline is timed on all host cores and on one. */
+int orc_max_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
 }

@@ -66,7 +66,8 @@ class _Info(ctypes.Structure):
                 ("store_len", ctypes.c_int64), ("fn_entries", ctypes.c_int64), ("max_batch_points", ctypes.c_int64),
                 ("max_batch_fn", ctypes.c_int64), ("n_work", ctypes.c_int64), ("n_passes", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64), ("flops_alg", ctypes.c_double), ("n_systems", ctypes.c_int32),
-                ("scratch_bytes", ctypes.c_int64), ("flops_alg_hs", ctypes.c_double)]
+                ("scratch_bytes", ctypes.c_int64), ("flops_alg_hs", ctypes.c_double), ("staging_bytes", ctypes.c_int64),
+                ("tab_elems", ctypes.c_int64)]
 
 
 class _TuneEntry(ctypes.Structure):

@@ -62,13 +62,16 @@ def rel_to_scale(got, ref, scale, floor=0.0):
     return float(np.max(np.abs(got - ref) / (scale + floor))) if np.size(got) else 0.0
 
 
-def per_point_worst(got, ref, scale):
-    """max |got - ref| / scale over the entries whose scale is positive; where
-    the scale is 0 (no term reaches the entry: outside every support) the two
-    must agree exactly.  The scale of an entry is the oracle's sum of the
-    magnitudes of the terms it is summed from."""
+def per_point_worst(got, ref, scale, floor=0.0):
+    """max |got - ref| / (scale + floor) over the entries whose scale is
+    positive; where the scale is 0 (no term reaches the entry: outside every
+    support) the two must agree exactly.  The scale of an entry is the
+    oracle's sum of the magnitudes of the terms it is summed from.  floor
+    (absolute) covers values in the FP64 subnormal range (below 2.2e-308),
+    where each operation may lose up to 2^-1074 absolutely and no relative
+    bar can hold: tails of tight Gaussians reach it inside the cutoff."""
     got, ref, scale = (np.asarray(t, dtype=np.float64) for t in (got, ref, scale))
     zero = ~(scale > 0)
     assert np.array_equal(got[zero], ref[zero]), "entries with no terms differ"
     nz = ~zero
-    return float(np.max(np.abs(got[nz] - ref[nz]) / scale[nz])) if np.any(nz) else 0.0
+    return float(np.max(np.abs(got[nz] - ref[nz]) / (scale[nz] + floor))) if np.any(nz) else 0.0

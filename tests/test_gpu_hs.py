@@ -178,8 +178,8 @@ def test_g_functions_tabulate_and_integrate_H(q, medium_sc):
         rows = slice(pt_off[b], pt_off[b + 1])
         ref = np.concatenate([phi[rows][:, fns][None], np.moveaxis(grad[rows][:, fns, :], 2, 0)], axis=0)
         sref = np.concatenate([aphi[rows][:, fns][None], np.moveaxis(agrad[rows][:, fns, :], 2, 0)], axis=0)
-        worst = max(worst, per_point_worst(blk, ref, sref))
-    print("g-function tabulation: worst |d| / own scale %.3g" % worst, flush=True)
+        worst = max(worst, per_point_worst(blk, ref, sref, floor=1e-300))
+    print("g-function tabulation: worst |d| / (own scale + 1e-300) %.3g" % worst, flush=True)
     assert worst <= 1e-12, worst
     # W path: sampled pairs of heavy atoms (their small components carry g shells)
     v = torch.from_numpy(ws.v).cuda()

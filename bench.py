@@ -613,6 +613,19 @@ def main():
     err = {n: [float(torch.max(torch.abs(outs[n][k] - outs["f64"][k]))) for k in range(5)] for n in outs}
     ms_adj = float(np.median(timed_each(lambda: q.density_on_grid(plan, gbar, q.TERM_ALL, 1, grad), 20, 3)))
 
+    # nao_tabulate (the ABI call; the same tabulation as the panels) over the
+    # first quarter of the batches: FP64 phi and grad phi, 32 B written per
+    # (point, relevant function), HIP events around each call
+    nb_t = max(1, info["n_batches"] // 4)
+    n_t = plan.tabulate_size(0, nb_t, 1)
+    tab_out = torch.empty(n_t, dtype=torch.float64, device=dev)
+    ms_tab = float(np.median(timed_each(lambda: q.nao_tabulate(plan, 0, nb_t, 1, tab_out), 10, 2)))
+    del tab_out
+    tab_bytes = 8.0 * n_t
+    nao_tab = {"batches": nb_t, "ms_median": ms_tab, "bytes_alg": tab_bytes,
+               "roofline": {"kernel": "k_tabulate", "bound": "hbm", "achieved": tab_bytes / (ms_tab * 1e-3) / 1e9,
+                            "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": tab_bytes / (ms_tab * 1e-3) / PEAK_HBM}}
+
     res = {
         "metric": METRIC,
         "value": n_act / (ms_step * 1e-3),
@@ -642,6 +655,7 @@ def main():
         "h_only": h_only,
         "h_only_points_per_s": h_only[a.precision]["points_per_s"],
         "adjoint_ms_median": ms_adj,
+        "nao_tabulate": nao_tab,
         "launch": {"contract": plan.get_launch(q.KERNEL_CONTRACT), "density": plan.get_launch(q.KERNEL_DENSITY),
                    "graphs": tune is not None and not a.no_graphs, "autotune_table": tune},
         "kernels_ms_per_step": {k: v_[0] / a.steps for k, v_ in tim.items() if v_[1]},

@@ -120,7 +120,7 @@ typedef struct {
   int32_t p_max;            /* max points per batch; <= 0 selects 300 */
   int32_t flags;            /* Q4C_PLAN_* */
   int64_t staging_bytes;    /* per-plan scratch budget (staged batch results and
-                               operand panels); <= 0 selects 16 GiB.  Batches are
+                               operand panels); <= 0 selects 32 GiB.  Batches are
                                processed in passes that fit the budget. */
   double split_threshold;   /* split-precision routing bound in hartree (see
                                q4c_integrate_H); <= 0 selects 3e-11 */
@@ -188,17 +188,50 @@ int q4c_plan_pairs(const q4c_plan *plan, int32_t *pair_atoms, int64_t *pair_off)
 int q4c_plan_batches(const q4c_plan *plan, int64_t *pt_off, int64_t *point_index, int64_t *fn_off,
                      int32_t *fn_index);
 
-/* Number of doubles nao_tabulate writes for batches [b0, b1). */
-int q4c_tabulate_size(const q4c_plan *plan, int64_t b0, int64_t b1, int32_t deriv, int64_t *n_doubles);
+/* Sparse pair store layout of a plan (the outputs the caller allocates). */
+typedef struct {
+  int64_t n_pairs;
+  int64_t store_len;     /* doubles per real part (sum over pairs of nA nB) */
+  int64_t part_bytes;    /* one real part: 8 store_len */
+  int64_t store_bytes;   /* the five real parts of q4c_integrate_H: 40 store_len */
+  int64_t hs_bytes;      /* the two parts (H, S) of q4c_integrate_HS: 16 store_len */
+  int64_t spinor_bytes;  /* one set of complex128 spinor blocks (2 nA x 2 nB per pair): 64 store_len */
+} q4c_layout;
+
+/* q4c_store_layout: sizes of the store, and (each optional, NULL to skip)
+ * the pair list (pair_atoms[2p], pair_atoms[2p+1] = (A, B), A <= B, in (A, B)
+ * order), the block offsets pair_off[n_pairs + 1] (doubles into one real
+ * part; spinor blocks start at complex offset 4 pair_off[p]) and the block
+ * shapes pair_nfn[2p], pair_nfn[2p+1] = (nA, nB).  Host buffers.  Paper
+ * Sec. III A: the locally indexed dense blocks of the sparse matrices. */
+int q4c_store_layout(const q4c_plan *plan, q4c_layout *layout, int32_t *pair_atoms, int64_t *pair_off,
+                     int32_t *pair_nfn);
+
+/* Element types of nao_tabulate. */
+enum {
+  Q4C_DTYPE_F64 = 0,      /* binary64 values */
+  Q4C_DTYPE_F32_HILO = 1  /* each value x as two binary32: hi = fl32(x), lo = fl32(x - hi)
+                             (x = hi + lo to about 2^-48 relative), the split operands of
+                             FP32 MFMA products */
+};
+
+/* Number of values nao_tabulate writes for batches [b0, b1) (8 bytes each
+ * for both element types). */
+int q4c_tabulate_size(const q4c_plan *plan, int64_t b0, int64_t b1, int32_t deriv, int64_t *n_values);
 
 /* nao_tabulate: values (deriv = 0) or values and gradients (deriv = 1) of the
- * relevant functions of batches [b0, b1) at their points (Eq. 12a, App. B).
- * Output (device, FP64): batch after batch; batch b is a [ncomp][P_b][n_b]
- * array (ncomp = 1 or 4: phi, d/dx, d/dy, d/dz), points in the batch order of
- * q4c_plan_batches, functions in the order of fn_index.  out_len (doubles)
- * must be at least q4c_tabulate_size(); else Q4C_ESIZE. */
-int nao_tabulate(const q4c_plan *plan, int64_t b0, int64_t b1, int32_t deriv, double *out_dev, int64_t out_len,
-                 void *stream);
+ * relevant functions of batches [b0, b1) at their points (Eq. 12a, App. B),
+ * computed as the integration calls compute them (one workgroup per batch
+ * and 64-function tile, the tile's shell data staged in LDS).
+ * Output (device): batch after batch, ncomp = 1 or 4 components (phi, d/dx,
+ * d/dy, d/dz), points in the batch order of q4c_plan_batches, functions in
+ * the order of fn_index:
+ *   Q4C_DTYPE_F64:      double [ncomp][P_b][n_b]
+ *   Q4C_DTYPE_F32_HILO: float  [ncomp][2][P_b][n_b] (the hi plane, then the lo plane)
+ * Both use 8 q4c_tabulate_size() bytes; out_bytes below that gives
+ * Q4C_ESIZE, an unknown dtype Q4C_EINVAL. */
+int nao_tabulate(const q4c_plan *plan, int64_t b0, int64_t b1, int32_t deriv, int32_t dtype, void *out_dev,
+                 int64_t out_bytes, void *stream);
 
 /* q4c_integrate_H: the five real parts of the atom-pair store from the
  * potential v (device, [n_points], user order, hartree):

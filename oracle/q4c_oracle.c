@@ -221,6 +221,20 @@ static void radial_eval(const double *tab, int nint, double rcut, double s, doub
   if (cder) *cder = (fabs(c[1]) + fabs(2.0 * c[2] * t) + fabs(3.0 * c[3] * t * t)) / h;
 }
 
+/* Magnitude of the terms of Rt''(s): sum_k k (k-1) |c_k t^(k-2)| / h^2. */
+static double radial_d2_mag(const double *tab, int nint, double rcut, double s) {
+  if (!(s < rcut)) return 0.0;
+  int j = (int)floor(nint * sqrt(s / rcut));
+  if (j > nint - 1) j = nint - 1;
+  if (j < 0) j = 0;
+  double rj = rcut * ((double)j / nint) * ((double)j / nint);
+  double rj1 = rcut * ((double)(j + 1) / nint) * ((double)(j + 1) / nint);
+  double h = rj1 - rj;
+  double t = (s - rj) / h;
+  const double *c = tab + 4 * (int64_t)j;
+  return (fabs(2.0 * c[2]) + fabs(6.0 * c[3] * t)) / (h * h);
+}
+
 void orc_radial(const double *tab, int nint, double rcut, double s, double *val, double *der) {
   radial_eval(tab, nint, rcut, s, val, der, NULL, NULL);
 }
@@ -278,10 +292,15 @@ static void atom_functions_c(const orc_basis *b, int a, double px, double py, do
 /*
  * As atom_functions_c, with the magnitudes of the terms each value is summed
  * from: the radial cubic's sum_k |c_k t^k| (and derivative analogue) times
- * the magnitude bound of S_lm (and of its gradient) from solid_harmonic_mag.
- * These bound the rounding of a value computed in any order at any point,
- * including near the nodal planes of S_lm; they are the error scale of a
- * single tabulated value and of the density at one point.
+ * the magnitude bound of S_lm (and of its gradient) from solid_harmonic_mag,
+ * plus the value's sensitivity to the rounding of the distance: a distance
+ * s known to a few ulps moves Rt by Rt'(s) s u, which dominates in the steep
+ * tails of tight functions (|Rt'/Rt| = 2 alpha s for a Gaussian), so the
+ * scale of phi adds |Rt'| s |S| and that of d_c phi adds
+ * (|Rt''| s + |Rt'|) |d_c| / s |S| + |Rt'| s |d_c S| (term magnitudes
+ * again).  These bound the rounding of a value computed in any order at any
+ * point, including near the nodal planes of S_lm; they are the error scale
+ * of a single tabulated value and of the density at one point.
  */
 static void atom_functions_m(const orc_basis *b, int a, double px, double py, double pz, double *phi,
                              double *grad, double *aphi, double *agrad) {
@@ -291,24 +310,28 @@ static void atom_functions_m(const orc_basis *b, int a, double px, double py, do
   for (int sh = b->atom_shell_off[a]; sh < b->atom_shell_off[a + 1]; ++sh) {
     int l = b->shell_l[sh];
     double Rt, dRt, cR, cdR;
-    radial_eval(b->coef + b->shell_coef_off[sh], b->shell_nint[sh], b->shell_rcut[sh], s, &Rt, &dRt, &cR, &cdR);
+    const double *tab = b->coef + b->shell_coef_off[sh];
+    radial_eval(tab, b->shell_nint[sh], b->shell_rcut[sh], s, &Rt, &dRt, &cR, &cdR);
+    const double cd2R = radial_d2_mag(tab, b->shell_nint[sh], b->shell_rcut[sh], s);
     double u[3] = {0.0, 0.0, 0.0}, au[3] = {0.0, 0.0, 0.0};
     if (s > 0.0) {
       u[0] = dRt * dx / s;
       u[1] = dRt * dy / s;
       u[2] = dRt * dz / s;
-      au[0] = cdR * fabs(dx) / s;
-      au[1] = cdR * fabs(dy) / s;
-      au[2] = cdR * fabs(dz) / s;
+      /* term magnitudes of Rt'(s) d_c / s and their sensitivity to s */
+      au[0] = (cdR + cd2R * s + cdR) * fabs(dx) / s;
+      au[1] = (cdR + cd2R * s + cdR) * fabs(dy) / s;
+      au[2] = (cdR + cd2R * s + cdR) * fabs(dz) / s;
     }
+    const double cRs = cR + cdR * s; /* term magnitudes of Rt(s) and its sensitivity to s */
     for (int m = -l; m <= l; ++m, ++f) {
       double S, gS[3], Sm, gm[3];
       orc_solid_harmonic(l, m, dx, dy, dz, &S, gS);
       solid_harmonic_mag(l, m, dx, dy, dz, &Sm, gm);
       phi[f] = Rt * S;
       for (int c = 0; c < 3; ++c) grad[3 * f + c] = u[c] * S + Rt * gS[c];
-      aphi[f] = cR * Sm;
-      for (int c = 0; c < 3; ++c) agrad[3 * f + c] = au[c] * Sm + cR * gm[c];
+      aphi[f] = cRs * Sm;
+      for (int c = 0; c < 3; ++c) agrad[3 * f + c] = au[c] * Sm + cRs * gm[c];
     }
   }
 }

@@ -24,6 +24,7 @@ TIMER_NAMES = ("tabulate", "contract", "reduce", "spinor", "bloch", "density_til
 ACCUMULATE, ASSEMBLE_W, ASSEMBLE_V, CHECK_FINITE = 1, 2, 4, 8
 PLAN_HOST_ONLY = 1
 TERM_LL, TERM_SS, TERM_SO, TERM_ALL = 1, 2, 4, 7
+DTYPE_F64, DTYPE_F32_HILO = 0, 1
 PART_NAMES = ("V", "Ws", "Wso_x", "Wso_y", "Wso_z")
 
 
@@ -78,7 +79,13 @@ class _TuneEntry(ctypes.Structure):
 KERNEL_CONTRACT, KERNEL_DENSITY, KERNEL_HS = 0, 1, 2
 
 
+class _StoreLayout(ctypes.Structure):
+    _fields_ = [("n_pairs", ctypes.c_int64), ("store_len", ctypes.c_int64), ("part_bytes", ctypes.c_int64),
+                ("store_bytes", ctypes.c_int64), ("hs_bytes", ctypes.c_int64), ("spinor_bytes", ctypes.c_int64)]
+
+
 EXPORTS = ("q4c_plan_create", "q4c_plan_destroy", "q4c_plan_info", "q4c_plan_pairs", "q4c_plan_batches",
+           "q4c_store_layout",
            "q4c_tabulate_size", "nao_tabulate", "q4c_integrate_H", "density_on_grid", "q4c_coef_from_spinor",
            "q4c_plan_sync", "q4c_plan_profile", "q4c_plan_timers", "q4c_plan_split_stats", "q4c_status_string",
            "q4c_last_error", "q4c_plan_create_batched", "q4c_plan_systems", "q4c_plan_set_launch",
@@ -104,7 +111,8 @@ def _load():
         lib.q4c_plan_pairs.argtypes = [vp, vp, vp]
         lib.q4c_plan_batches.argtypes = [vp, vp, vp, vp, vp]
         lib.q4c_tabulate_size.argtypes = [vp, i64, i64, i32, ctypes.POINTER(i64)]
-        lib.nao_tabulate.argtypes = [vp, i64, i64, i32, vp, i64, vp]
+        lib.nao_tabulate.argtypes = [vp, i64, i64, i32, i32, vp, i64, vp]
+        lib.q4c_store_layout.argtypes = [vp, ctypes.POINTER(_StoreLayout), vp, vp, vp]
         lib.q4c_integrate_H.argtypes = [vp, vp, i32, u32, vp, vp, vp, vp]
         lib.density_on_grid.argtypes = [vp, vp, u32, i32, vp, vp]
         lib.q4c_coef_from_spinor.argtypes = [vp, vp, vp, vp]
@@ -248,6 +256,18 @@ class Plan:
         _check(_load().q4c_plan_pairs(self._h, pa.ctypes.data, po.ctypes.data))
         return pa[:2 * n].reshape(n, 2), po
 
+    def store_layout(self):
+        """q4c_store_layout: sizes, pair list, block offsets and block shapes."""
+        lay = _StoreLayout()
+        n = self.info["n_pairs"]
+        pa = np.zeros(2 * max(n, 1), dtype=np.int32)
+        po = np.zeros(n + 1, dtype=np.int64)
+        nf = np.zeros(2 * max(n, 1), dtype=np.int32)
+        _check(_load().q4c_store_layout(self._h, ctypes.byref(lay), pa.ctypes.data, po.ctypes.data, nf.ctypes.data))
+        out = {f: getattr(lay, f) for f, _ in _StoreLayout._fields_}
+        out.update(pair_atoms=pa[:2 * n].reshape(n, 2), pair_off=po, pair_nfn=nf[:2 * n].reshape(n, 2))
+        return out
+
     def batches(self):
         nb, na, fe = self.info["n_batches"], self.info["n_active"], self.info["fn_entries"]
         pt_off = np.zeros(nb + 1, dtype=np.int64)
@@ -353,11 +373,14 @@ class Plan:
 # C-ABI calls on torch device tensors
 # ---------------------------------------------------------------------------
 
-def nao_tabulate(plan: Plan, b0: int, b1: int, deriv: int, out):
-    """Write the batch panels of batches [b0, b1) into `out` (float64 CUDA tensor)."""
+def nao_tabulate(plan: Plan, b0: int, b1: int, deriv: int, out, dtype: int = DTYPE_F64):
+    """phi (and grad phi) of batches [b0, b1) into `out`: a float64 CUDA tensor
+    for DTYPE_F64, a float32 one (hi and lo planes) for DTYPE_F32_HILO."""
     need = plan.tabulate_size(b0, b1, deriv)
-    _check(_load().nao_tabulate(plan.handle, int(b0), int(b1), int(deriv), _dev_ptr(out, name="out"),
-                                int(out.numel()), _stream_handle()))
+    dt = "float32" if dtype == DTYPE_F32_HILO else "float64"
+    ptr = _dev_ptr(out, dt, name="out")
+    _check(_load().nao_tabulate(plan.handle, int(b0), int(b1), int(deriv), int(dtype), ptr,
+                                int(out.numel() * out.element_size()), _stream_handle()))
     return need
 
 

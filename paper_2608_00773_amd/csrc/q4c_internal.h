@@ -164,6 +164,7 @@ struct q4c_plan {
   std::vector<int32_t> untouched_pairs;
   std::vector<int64_t> batch_work_off, tab_off, panel_off;
   std::vector<q4c::WorkItem> ptile;  // (batch, function tile) list of the panel kernel
+  std::vector<int64_t> batch_tile_off;  // [n_batches + 1] first ptile item of each batch
   std::vector<int32_t> work_order;   // per pass, pass-relative work indices by decreasing cost
   std::vector<int32_t> sp_pair;      // see DevPlan::sp_pair
   std::vector<int64_t> batch_sp_off;
@@ -240,6 +241,12 @@ struct q4c_plan {
   mutable int64_t *d_gr_fninfo = nullptr;  // [fn_entries] slot | slot's first function << 20 | its count << 40
   mutable double *d_gr_cd = nullptr, *d_gr_part = nullptr;
 
+  // ---- what the panel region holds after the calls enqueued so far: the
+  // W-path panels (phi, grad phi) of pass panel_pass, or -1 (nothing usable:
+  // H/S panels, or unknown).  Calls on one plan are stream-ordered, so the
+  // host can track it.
+  mutable int64_t panel_pass = -1;
+
   // ---- launch configuration (chosen by q4c_plan_autotune or set directly)
   q4c::LaunchCfg cfg_contract{}, cfg_density{}, cfg_hs{};
   bool use_graphs = false;
@@ -265,11 +272,13 @@ void set_error(const std::string &msg);
 int hip_fail(hipError_t e, const char *what);
 
 // kernel launchers (q4c_kernels.hip)
-int launch_tabulate(const q4c_plan *p, int64_t b0, int64_t b1, int deriv, double *out, hipStream_t s);
+int launch_tabulate(const q4c_plan *p, int64_t b0, int64_t b1, int deriv, int dtype, void *out, hipStream_t s);
 int launch_integrate(const q4c_plan *p, const double *v, int precision, uint32_t flags, double *store,
                      double *spin_w, double *spin_v, hipStream_t s);
+// resident_pass >= 0: the plan's panel region already holds the W-path
+// panels of that pass (left by the previous call), which is then not tabulated
 int launch_density(const q4c_plan *p, const double *coef, uint32_t terms, int weight_mode, double *out,
-                   hipStream_t s);
+                   int64_t resident_pass, hipStream_t s);
 int launch_integrate_hs(const q4c_plan *p, const double *v, uint32_t flags, double *hs, hipStream_t s);
 int launch_density_grad(const q4c_plan *p, const double *coef, double *out, hipStream_t s);
 // dense M, product and point sums of one pass of density_gradient_on_grid

@@ -1,7 +1,8 @@
 // HIP kernels of libq4c for CDNA4 (gfx950).
 //
 //  k_tabulate        nao_tabulate: phi and grad phi of a batch's relevant
-//                    functions at its points (Eq. 12a, App. B).
+//                    functions at its points (Eq. 12a, App. B), as the
+//                    panels compute them; FP64 or FP32 hi + lo output.
 //  k_om              w_g v_g per active point (the weighting of Eq. 29).
 //  k_panel           per (batch, 64-function tile): phi and grad phi at all
 //                    batch points into the batch's operand panel (HBM).
@@ -21,9 +22,10 @@
 //  k_spinor          2x2-spinor assembly of the W and V blocks.
 //  k_density_tiles,
 //  k_density_points  density_on_grid: the transpose of the steps above
-//                    (Eq. 39): each half work item reads its coefficients
-//                    from the store, contracts a_g^T C b_g at its points on
-//                    MFMA, and every point sums its partials in a fixed order.
+//                    (Eq. 39): each quarter of a work item reads its
+//                    coefficients from the store, contracts a_g^T C b_g at its
+//                    points on MFMA, and every point sums its partials in a
+//                    fixed order.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -108,63 +110,6 @@ __device__ __forceinline__ void solid_harmonic(int lm, double x, double y, doubl
       gy = 6.0 * C43 * x * y * z; gz = -C43 * (x * x * x - 3.0 * x * y * y); break;
     default: S = C44 * (x * x * x * x - 6.0 * x * x * y * y + y * y * y * y); gx = 4.0 * C44 * (x * x * x - 3.0 * x * y * y);
       gy = 4.0 * C44 * (y * y * y - 3.0 * x * x * y); gz = 0.0; break;
-  }
-}
-
-// phi and grad phi of global function fn at point (px, py, pz):
-// phi = Rt(s) S_lm(d), grad phi = Rt'(s) (d / s) S_lm + Rt(s) grad S_lm, d = p - R_A.
-__device__ __forceinline__ void tab_one(const DevPlan &d, int fn, double px, double py, double pz, double &f,
-                                        double &fx, double &fy, double &fz) {
-  const int a = d.fn_atom[fn];
-  const int shlm = d.fn_shlm[fn];
-  const int sh = shlm >> 5;
-  const double dx = px - d.R[3 * a], dy = py - d.R[3 * a + 1], dz = pz - d.R[3 * a + 2];
-  const double s2 = dx * dx + dy * dy + dz * dz;
-  const double rc = d.shell_rcut[sh];
-  const double s = sqrt(s2);
-  if (!(s < rc)) {
-    f = fx = fy = fz = 0.0;
-    return;
-  }
-  // interval j with r_j = rcut (j / n)^2 <= s < r_{j+1}
-  const int n = d.shell_nint[sh];
-  int j = (int)sqrt(s * d.shell_knot[2 * sh]);
-  j = j > n - 1 ? n - 1 : j;
-  const double fj = (double)j;
-  const double dd = s - fj * fj * d.shell_knot[2 * sh + 1];  // s - r_j
-  // coefficients in d = s - r_j (scaled at plan time)
-  const dbl4 c = *reinterpret_cast<const dbl4 *>(d.coef + d.shell_coef_off[sh] + 4 * (int64_t)j);
-  const double R = ((c[3] * dd + c[2]) * dd + c[1]) * dd + c[0];
-  const double dR = (3.0 * c[3] * dd + 2.0 * c[2]) * dd + c[1];
-  double S, gx, gy, gz;
-  solid_harmonic(shlm & 31, dx, dy, dz, S, gx, gy, gz);
-  const double q = s > 0.0 ? dR / s : 0.0;
-  f = R * S;
-  fx = q * dx * S + R * gx;
-  fy = q * dy * S + R * gy;
-  fz = q * dz * S + R * gz;
-}
-
-// ---------------------------------------------------------------------------
-// nao_tabulate
-// ---------------------------------------------------------------------------
-
-__global__ void k_tabulate(DevPlan d, int64_t b0, int deriv, double *out) {
-  const int64_t b = b0 + blockIdx.x;
-  const int g0 = d.batch_pt_off[b], P = d.batch_pt_off[b + 1] - g0;
-  const int f0 = d.batch_fn_off[b], n = d.batch_fn_off[b + 1] - f0;
-  double *o = out + (deriv ? 4 : 1) * (d.tab_off[b] - d.tab_off[b0]);
-  const int64_t plane = (int64_t)P * n;
-  for (int64_t it = threadIdx.x; it < plane; it += blockDim.x) {
-    const int g = (int)(it / n), i = (int)(it - (int64_t)g * n);
-    double f, fx, fy, fz;
-    tab_one(d, d.loc_fn[f0 + i], d.px[g0 + g], d.py[g0 + g], d.pz[g0 + g], f, fx, fy, fz);
-    o[it] = f;
-    if (deriv) {
-      o[plane + it] = fx;
-      o[2 * plane + it] = fy;
-      o[3 * plane + it] = fz;
-    }
   }
 }
 
@@ -310,6 +255,67 @@ __device__ __forceinline__ void tab_meta_hs(const DevPlan &d, const TileMeta &M,
   solid_harmonic(M.lm[m], dx, dy, dz, S, gx, gy, gz);
   f = R * S;
   psi = 0.5 * U * f;
+}
+
+// ---------------------------------------------------------------------------
+// nao_tabulate: one workgroup per (batch, 64-function tile) of the requested
+// batch range, the same tabulation as the panels (tile metadata in LDS,
+// functions taken in lm order), staged in LDS per 8 points and written as
+// runs of the tile's functions: out is [ncomp][P][n] per batch (FP64), or
+// [ncomp][2][P][n] floats with the hi and lo planes (F32_HILO).
+// ---------------------------------------------------------------------------
+
+template <bool HILO>
+__global__ __launch_bounds__(256) void k_tabulate(DevPlan d, const WorkItem *tiles, int64_t t0, int64_t b0, int deriv,
+                                                  void *out) {
+  constexpr int CP = 8;
+  constexpr int SR = T + 1;
+  __shared__ TileMeta M;
+  __shared__ double st[4 * CP * SR];
+  const WorkItem it = tiles[t0 + blockIdx.x];
+  const int b = it.batch;
+  const int g0 = d.batch_pt_off[b], P = d.batch_pt_off[b + 1] - g0;
+  const int f0 = d.batch_fn_off[b], n = d.batch_fn_off[b + 1] - f0;
+  const int r0 = it.ti * T;
+  const int nrow = n - r0 < T ? n - r0 : T;
+  const int nq = deriv ? 4 : 1;
+  const int64_t plane = (int64_t)P * n;
+  const int64_t base = (int64_t)nq * (d.tab_off[b] - d.tab_off[b0]);  // values before this batch
+  load_tile_meta(d, M, f0, n, r0);
+  __syncthreads();
+  for (int g8 = 0; g8 < P; g8 += CP) {
+    for (int e = threadIdx.x; e < T * CP; e += 256) {
+      const int k = e / CP, pt = e % CP;
+      const int fl = M.order[k];
+      double f = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
+      const int g = g8 + pt;
+      if (M.nint[fl] > 0 && g < P) tab_meta(d, M, fl, d.px[g0 + g], d.py[g0 + g], d.pz[g0 + g], f, fx, fy, fz);
+      st[(0 * CP + pt) * SR + fl] = f;
+      st[(1 * CP + pt) * SR + fl] = fx;
+      st[(2 * CP + pt) * SR + fl] = fy;
+      st[(3 * CP + pt) * SR + fl] = fz;
+    }
+    __syncthreads();
+    // (component, point) rows of the tile's functions: 256 threads = 4 rows x 64 functions
+    for (int e = threadIdx.x; e < nq * CP * T; e += 256) {
+      const int fl = e % T, row = e / T;
+      const int q = row / CP, pt = row % CP;
+      const int g = g8 + pt;
+      if (fl < nrow && g < P) {
+        const double x = st[(q * CP + pt) * SR + fl];
+        const int64_t o = (int64_t)g * n + r0 + fl;
+        if (HILO) {
+          float *of = static_cast<float *>(out) + 2 * (base + q * plane);
+          const float hi = (float)x;
+          of[o] = hi;
+          of[plane + o] = (float)(x - (double)hi);
+        } else {
+          static_cast<double *>(out)[base + q * plane + o] = x;
+        }
+      }
+    }
+    __syncthreads();  // st consumed
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -812,96 +818,96 @@ __global__ void k_spinor(DevPlan d, const double *store, double *spin_w, double 
 // Adjoint / density
 // ---------------------------------------------------------------------------
 
-// Copy the coefficient blocks of every stored pair to each of its staged
-// (batch, pair) blocks: the transpose of k_reduce.
-constexpr int NTD = 256;       // adjoint workgroup: 4 waves = 2 column slices x 2 row halves of a half tile
-// adjoint LDS chunk images (layout of dma_chunk): row (q, u) of the 64 row
-// functions every RSA doubles, of the 32 column functions every RSB; both
-// are 2 mod 16, so 16 lanes reading 16 consecutive points of one function
-// hit distinct banks
-constexpr int RSA = 2 * T + 2;
-constexpr int RSB = T + 2;
+// The adjoint runs per quarter of a work item: a 32 x 32 block of the
+// batch's coefficient matrix (rows ti*64 + 32 rh .., columns tj*64 + 32 ch ..),
+// four waves with one 16 x 16 block each.  Positions 4 w + qd, qd = 2 rh + ch.
+constexpr int NTD = 256;
+constexpr int QW = 32;              // functions per side of a quarter
+// LDS image of one 16-point chunk of 32 functions (layout of dma_chunk): row
+// (q, u) every RSQ doubles; 2 mod 16, so 16 lanes reading 16 consecutive
+// points of one function hit distinct banks
+constexpr int RSQ = 2 * QW + 2;
+constexpr int QIMG = 4 * 8 * RSQ;   // doubles per image: 4 components x 8 point pairs
 
-// One half of a work item (positions 2 w + half): partial[g] = sum over the
-// tile's 64 rows and the half's 32 columns of a_g^T C b_g for all selected
-// terms.  The chunk's row functions (64) and column functions (32) are staged
-// in LDS (loaded by DMA) and shared by the 4 waves; each wave owns 16 columns x 32 rows of C
-// in registers.  Two workgroups fit on a CU, so one computes while the other
-// stages its next chunk.
+// A quarter has work iff its rows and columns start inside the batch's n
+// functions and it is not below the diagonal of a diagonal tile.
+__device__ __forceinline__ bool quarter_valid(const WorkItem &it, int qd, int n) {
+  const int rh = qd >> 1, ch = qd & 1;
+  return it.ti * T + 32 * rh < n && it.tj * T + 32 * ch < n && !(it.ti == it.tj && rh > ch);
+}
+
+// partial[g] of quarter qd (P doubles at 4 work_part_off[w] + qd P) = sum over
+// its stored elements ij of the selected terms at point g:
+//   C^V phi_i phi_j + c' C^Ws grad phi_i . grad phi_j + c' sum_m C^m (grad phi_i x grad phi_j)_m
+// (Eq. 39 on the scalar basis).  Per wave, the 16 x 16 coefficient block sits
+// in registers as the MFMA's first operand (5 parts x 4 K steps of 4 rows),
+// and per 16-point chunk four accumulators collect (C^T Y) grouped by the
+// column component Z they are multiplied with afterwards:
+//   u_phi = C^V phi,  u_x = C^Ws dx - C^z dy + C^y dz,
+//   u_y = C^z dx + C^Ws dy - C^x dz,  u_z = -C^y dx + C^x dy + C^Ws dz
+// (rows i, the K index: Y = the row functions' values at the chunk's points),
+// then one lane-local drain sum_j u . Z per chunk.  Chunk images arrive by LDS
+// DMA, double-buffered: the next chunk's loads are in flight while this one
+// is multiplied (one barrier per chunk); two workgroups fit on a CU.
 template <bool PERSIST>
 __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t terms, const WorkItem *work,
                                                           const int32_t *order, int64_t w0, int64_t nw,
                                                           const double *coef, const double *panel,
                                                           double *partial, unsigned *tickets) {
-  constexpr int NO = 1;   // outputs per point
-  constexpr int NC = 5;   // coefficient parts
-  __shared__ double sa[32 * RSA], sb[32 * RSB];
-  __shared__ double s_red[2][4][NO][16];  // per-wave point sums, alternating chunks
+  constexpr int NC = 5;  // coefficient parts
+  __shared__ double img[2][2][QIMG];     // [buffer][row image, column image]
+  __shared__ double s_red[2][4][16];     // per-wave point sums, alternating chunks
   __shared__ int64_t s_pos;
-  // slot data of the tile's 64 rows and the half's 32 columns (slot -1: padding)
-  __shared__ int s_rslot[T], s_rfn[T], s_rnf[T], s_cslot[T / 2], s_cfn[T / 2], s_cnf[T / 2];
+  // slot data of the quarter's 32 rows and 32 columns (slot -1: beyond n)
+  __shared__ int s_rslot[QW], s_rfn[QW], s_cslot[QW], s_cfn[QW], s_cnf[QW];
   // store offset of the pair block of (row slot, column slot) for the slots
-  // the tile spans (-1: lower atom-block triangle or not a stored pair)
-  __shared__ int64_t s_poff[T * T / 2];
-  const int64_t npos = 2 * nw;
+  // the quarter spans (-1: lower atom-block triangle or not a stored pair)
+  __shared__ int64_t s_poff[QW * QW];
+  const int64_t npos = 4 * nw;
   int64_t pos = PERSIST ? next_item(tickets, npos, order != nullptr, &s_pos)
                         : (order ? (int64_t)blockIdx.x : xcd_map(blockIdx.x, npos));
   while (!PERSIST || pos < npos) {
-  const int half = (int)(pos & 1);
-  const int64_t wi = w0 + (order ? order[w0 + (pos >> 1)] : (pos >> 1));
+  const int qd = (int)(pos & 3);
+  const int64_t wi = w0 + (order ? order[w0 + (pos >> 2)] : (pos >> 2));
   const WorkItem it = work[wi];
   const int b = it.batch;
-  const int g0 = d.batch_pt_off[b], P = d.batch_pt_off[b + 1] - g0;
   const int f0 = d.batch_fn_off[b], n = d.batch_fn_off[b + 1] - f0;
+  if (quarter_valid(it, qd, n)) {  // workgroup-uniform
+  const int g0 = d.batch_pt_off[b], P = d.batch_pt_off[b + 1] - g0;
   const int sbase = d.batch_slot_off[b];
-  const int r0 = it.ti * T, c0 = it.tj * T + 32 * half;
+  const int r0 = it.ti * T + 32 * (qd >> 1), c0 = it.tj * T + 32 * (qd & 1);
   const int Pp = (int)pad16(P), np = (int)pad16(n);
   const double *pb = panel + d.panel_off[b];
   const int64_t plane = (int64_t)Pp * np;
   const int tid = threadIdx.x;
   // wave index as a scalar: conditions derived from it stay uniform
   const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int js = wave & 1, ih = wave >> 1;  // column slice, row half
+  const int rb = wave >> 1, cb = wave & 1;  // this wave's 16 x 16 block in the quarter
   const int l16 = lane & 15, lk = lane >> 4;
-  const int cb = c0 + 16 * js;  // column block of this wave
-  const int lj = cb + l16;
-  // row origin of this wave's two row blocks.  Column half 0 of a diagonal
-  // tile has 3 active blocks, (0,0), (0,1) and (1,1) in 16-blocks: block (1,1)
-  // moves from wave (ih 0, js 1) to the otherwise idle wave (ih 1, js 1), so
-  // no wave of that half carries two.
-  const bool dg0 = it.ti == it.tj && half == 0;
-  const int iloc = (dg0 && ih == 1 && js == 1) ? 16 : 32 * ih;
-  bool act[2], upper[2];
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int rb = r0 + iloc + 16 * h;
-    act[h] = block_active(rb, cb, n) && !(dg0 && ih == 0 && js == 1 && h == 1);
-    upper[h] = rb < cb;
-  }
-  const bool any = act[0] || act[1];
-  if (tid < T + T / 2) {
-    const bool row = tid < T;
-    const int lf = row ? r0 + tid : c0 + tid - T;
+  const int rowb = r0 + 16 * rb, colb = c0 + 16 * cb;
+  const bool act = block_active(rowb, colb, n);
+  const bool upper = rowb < colb;
+  const int lj = colb + l16;
+  if (tid < 2 * QW) {
+    const bool row = tid < QW;
+    const int lf = row ? r0 + tid : c0 + tid - QW;
     SlotInfo si{-1, 0, 0, 0};
     if (lf < n) si = slot_of(d, f0, sbase, lf);
     if (row) {
       s_rslot[tid] = si.slot;
       s_rfn[tid] = si.fnoff;
-      s_rnf[tid] = si.nfn;
     } else {
-      s_cslot[tid - T] = si.slot;
-      s_cfn[tid - T] = si.fnoff;
-      s_cnf[tid - T] = si.nfn;
+      s_cslot[tid - QW] = si.slot;
+      s_cfn[tid - QW] = si.fnoff;
+      s_cnf[tid - QW] = si.nfn;
     }
   }
   __syncthreads();  // slot tables visible
-  // slot ranges of the tile's rows and the half's columns (slots ascend with
-  // the functions; padding rows and columns carry slot -1)
+  // slot ranges of the quarter's rows and columns (slots ascend with the
+  // functions; rows and columns beyond n carry slot -1)
   const int rs0 = s_rslot[0], cs0 = s_cslot[0];
-  int rs1 = rs0, cs1 = cs0;
-  if (rs0 >= 0) rs1 = s_rslot[min(T, n - r0) - 1];
-  if (cs0 >= 0) cs1 = s_cslot[min(T / 2, n - c0) - 1];
-  const int nrs = rs0 >= 0 ? rs1 - rs0 + 1 : 0, ncs = cs0 >= 0 ? cs1 - cs0 + 1 : 0;
+  const int rs1 = s_rslot[min(QW, n - r0) - 1], cs1 = s_cslot[min(QW, n - c0) - 1];
+  const int nrs = rs1 - rs0 + 1, ncs = cs1 - cs0 + 1;
   {
     const int ns = d.batch_slot_off[b + 1] - sbase;
     const int64_t spb = d.batch_sp_off[b];
@@ -916,209 +922,129 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t te
       s_poff[t] = po;
     }
   }
+  // the first chunk's images load while the coefficients are read
+  dma_chunk<NTD, 16, QW, RSQ>(pb, plane, np, r0, 0, img[0][0]);
+  dma_chunk<NTD, 16, QW, RSQ>(pb, plane, np, c0, 0, img[0][1]);
   __syncthreads();  // pair offsets visible
-  // coefficient slice: rows i = r0 + iloc + 4 ks + lk (ks = 0..7), column lj,
-  // read from the coefficient store: element (li, lj) of the pair block of
-  // its two atoms (upper atom-block triangle only), plus the mirrored element
-  // (lj, li) when the 16 x 16 block is strictly upper inside one atom block
-  // (no work item computes the mirrored block); c' on the W parts.  Every
-  // load is issued before any is used (element 0 stands in where there is
-  // nothing to read), so a thread waits for its loads once.
-  double creg[NC][8];
+  // coefficient block: rows i = rowb + 4 ks + lk (ks = 0..3), column lj, read
+  // from the store: element (li, lj) of the pair block of its two atoms
+  // (upper atom-block triangle only), plus the mirrored element (lj, li) when
+  // the 16 x 16 block is strictly upper inside one atom block (no work item
+  // computes the mirrored block); c' on the W parts, zero for unselected
+  // terms.  Every load is issued before any is used.
+  double creg[NC][4];
   {
     const int64_t L = d.store_len;
-    const int cl = 16 * js + l16;
+    const int cl = 16 * cb + l16;
     const int cslot = s_cslot[cl], cfn = s_cfn[cl], cnf = s_cnf[cl];
-    int64_t ea[8], em[8];
-    bool live[8], mir[8];
+    int64_t ea[4], em[4];
+    bool live[4], mir[4];
 #pragma unroll
-    for (int ks = 0; ks < 8; ++ks) {
-      const int rl = iloc + 4 * ks + lk;
+    for (int ks = 0; ks < 4; ++ks) {
+      const int rl = 16 * rb + 4 * ks + lk;
       const int li = r0 + rl;
       const int rslot = s_rslot[rl], rfn = s_rfn[rl];
-      const int64_t po = (act[ks >> 2] && rslot >= 0 && cslot >= 0) ? s_poff[(rslot - rs0) * ncs + (cslot - cs0)] : -1;
+      const int64_t po = (act && rslot >= 0 && cslot >= 0) ? s_poff[(rslot - rs0) * ncs + (cslot - cs0)] : -1;
       live[ks] = po >= 0;
-      mir[ks] = live[ks] && upper[ks >> 2] && rslot == cslot;
+      mir[ks] = live[ks] && upper && rslot == cslot;
       ea[ks] = live[ks] ? po + (int64_t)(li - rfn) * cnf + (lj - cfn) : 0;
       em[ks] = mir[ks] ? po + (int64_t)(lj - rfn) * cnf + (li - cfn) : 0;
     }
-    double cv[NC][8], cm[NC][8];
+    double cv[NC][4], cm[NC][4];
 #pragma unroll
-    for (int ks = 0; ks < 8; ++ks)
+    for (int ks = 0; ks < 4; ++ks)
 #pragma unroll
       for (int q = 0; q < NC; ++q) {
         cv[q][ks] = coef[q * L + ea[ks]];
         cm[q][ks] = coef[q * L + em[ks]];
       }
+    const bool on[NC] = {(terms & Q4C_TERM_LL) != 0, (terms & Q4C_TERM_SS) != 0, (terms & Q4C_TERM_SO) != 0,
+                         (terms & Q4C_TERM_SO) != 0, (terms & Q4C_TERM_SO) != 0};
 #pragma unroll
-    for (int ks = 0; ks < 8; ++ks)
+    for (int ks = 0; ks < 4; ++ks)
 #pragma unroll
       for (int q = 0; q < NC; ++q) {
         const double c = (live[ks] ? cv[q][ks] : 0.0) + (mir[ks] ? mirror_sign(q) * cm[q][ks] : 0.0);
-        creg[q][ks] = q == 0 ? c : d.cprime * c;
+        creg[q][ks] = on[q] ? (q == 0 ? c : d.cprime * c) : 0.0;
       }
   }
-  const bool tLL = terms & Q4C_TERM_LL, tSS = terms & Q4C_TERM_SS, tSO = terms & Q4C_TERM_SO;
-  // partials of this column half: NO runs of P values
-  double *out = partial + 2 * NO * d.work_part_off[wi] + half * NO * P;
-  const int jloc = 16 * js;  // half-local first column of this wave
+  double *out = partial + 4 * d.work_part_off[wi] + qd * P;
 
   for (int k0 = 0; k0 < Pp; k0 += 16) {
-    const int rb2 = (k0 >> 4) & 1;
-    __syncthreads();  // previous chunk's images consumed, its per-wave sums visible
-    if (k0 > 0 && tid < 16 * NO && k0 - 16 + (tid & 15) < P) {
-      const int o = tid >> 4, t = tid & 15;
-      out[o * P + k0 - 16 + t] = (s_red[rb2 ^ 1][0][o][t] + s_red[rb2 ^ 1][1][o][t]) +
-                                 (s_red[rb2 ^ 1][2][o][t] + s_red[rb2 ^ 1][3][o][t]);
+    const int bi = (k0 >> 4) & 1;
+    __builtin_amdgcn_s_waitcnt(0);  // this thread's loads of this chunk have landed
+    __syncthreads();                // ... everyone's; the previous chunk is consumed, its sums visible
+    if (k0 > 0 && tid < 16 && k0 - 16 + tid < P)
+      out[k0 - 16 + tid] = (s_red[bi ^ 1][0][tid] + s_red[bi ^ 1][1][tid]) +
+                           (s_red[bi ^ 1][2][tid] + s_red[bi ^ 1][3][tid]);
+    if (k0 + 16 < Pp) {
+      dma_chunk<NTD, 16, QW, RSQ>(pb, plane, np, r0, (k0 + 16) >> 2, img[bi ^ 1][0]);
+      dma_chunk<NTD, 16, QW, RSQ>(pb, plane, np, c0, (k0 + 16) >> 2, img[bi ^ 1][1]);
     }
-    dma_chunk<NTD, 16, T, RSA>(pb, plane, np, r0, k0 >> 2, sa);
-    dma_chunk<NTD, 16, T / 2, RSB>(pb, plane, np, c0, k0 >> 2, sb);
-    __builtin_amdgcn_s_waitcnt(0);  // this thread's LDS DMA loads have landed
-    __syncthreads();                // the chunk images are visible
-    // X[j][pt] = sum over the selected terms of (C^T Y)[j][pt] Z[pt][j]: the
-    // MFMA takes the coefficients as its first operand, so register r of lane
-    // (l16, lk) holds column j = lk + 4 r (of the wave's 16) at point pt = l16
-    // and the product with Z is a lane-local multiply-add.
-    double xacc[4] = {0.0, 0.0, 0.0, 0.0};
-    if (any) {
-      // column values: Z[q][pt = l16][j = jloc + lk + 4 r]
+    double x = 0.0;
+    if (act) {
+      const double *ia = img[bi][0], *ib = img[bi][1];
+      // column values Z[q][pt = l16][j = 16 cb + lk + 4 r]: register r of the
+      // MFMA result of lane (l16, lk) is column lk + 4 r of the block at point l16
       double zt[4][4];
 #pragma unroll
       for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-          zt[q][r] = sb[(q * 8 + (l16 >> 1)) * RSB + 2 * (jloc + d_row_f64(lk, r)) + (l16 & 1)];
-      // All terms over the K steps [K0, K1) of active row blocks, as straight-line
-      // code: no branch between the MFMAs of a chain.  Terms grouped by the row
-      // component Y (points x functions):
-      //   Y=phi: (V, phi); Y=dx: (Ws, dx), (Wso_y, -dz), (Wso_z, +dy);
-      //   Y=dy: (Ws, dy), (Wso_x, +dz), (Wso_z, -dx); Y=dz: (Ws, dz), (Wso_x, -dy), (Wso_y, +dx)
-      auto all_terms = [&](auto k0c, auto k1c) {
-        constexpr int K0 = decltype(k0c)::value, K1 = decltype(k1c)::value;
+        for (int r = 0; r < 4; ++r) zt[q][r] = ib[(q * 8 + (l16 >> 1)) * RSQ + 2 * (16 * cb + d_row_f64(lk, r)) + (l16 & 1)];
+      dbl4 uf = dbl4{0.0, 0.0, 0.0, 0.0}, ux = uf, uy = uf, uz = uf;
 #pragma unroll
-        for (int yq = 0; yq < 4; ++yq) {
-          double ya[8];
-#pragma unroll
-          for (int ks = K0; ks < K1; ++ks)
-            ya[ks] = sa[(yq * 8 + (l16 >> 1)) * RSA + 2 * (iloc + 4 * ks + lk) + (l16 & 1)];
-          if (yq == 0) {
-            dbl4 u0 = dbl4{0.0, 0.0, 0.0, 0.0}, u1 = u0;
-#pragma unroll
-            for (int ks = K0; ks < K1; ks += 2) {
-              u0 = mfma64(creg[0][ks], ya[ks], u0);
-              u1 = mfma64(creg[0][ks + 1], ya[ks + 1], u1);
-            }
-#pragma unroll
-            for (int r = 0; r < 4; ++r) xacc[r] += (u0[r] + u1[r]) * zt[0][r];
-          } else {
-            const int c2 = yq == 1 ? 3 : 2, z2 = yq == 1 ? 3 : (yq == 2 ? 3 : 2);
-            const double g2 = yq == 2 ? 1.0 : -1.0;
-            const int c3 = yq == 3 ? 3 : 4, z3 = yq == 1 ? 2 : 1;
-            const double g3 = yq == 2 ? -1.0 : 1.0;
-            dbl4 u1 = dbl4{0.0, 0.0, 0.0, 0.0}, u2 = u1, u3 = u1;
-#pragma unroll
-            for (int ks = K0; ks < K1; ++ks) {
-              u1 = mfma64(creg[1][ks], ya[ks], u1);
-              u2 = mfma64(creg[c2][ks], ya[ks], u2);
-              u3 = mfma64(creg[c3][ks], ya[ks], u3);
-            }
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-              xacc[r] += u1[r] * zt[yq][r] + g2 * u2[r] * zt[z2][r] + g3 * u3[r] * zt[z3][r];
-          }
-        }
-      };
-      if (terms == Q4C_TERM_ALL) {
-        if (act[0] && act[1])
-          all_terms(std::integral_constant<int, 0>{}, std::integral_constant<int, 8>{});
-        else if (act[0])
-          all_terms(std::integral_constant<int, 0>{}, std::integral_constant<int, 4>{});
-        else
-          all_terms(std::integral_constant<int, 4>{}, std::integral_constant<int, 8>{});
-      } else {
-      // selected terms (general path)
-      // terms grouped by the row component Y (points x functions):
-      //   Y=phi: (V, phi); Y=dx: (Ws, dx), (Wso_y, -dz), (Wso_z, +dy);
-      //   Y=dy: (Ws, dy), (Wso_x, +dz), (Wso_z, -dx); Y=dz: (Ws, dz), (Wso_x, -dy), (Wso_y, +dx)
-#pragma unroll
-      for (int yq = 0; yq < 4; ++yq) {
-        if (yq == 0 ? !tLL : !(tSS || tSO)) continue;
-        // second operand: Y[yq][pt = l16][i = iloc + 4 ks + lk]
-        double ya[8];
-#pragma unroll
-        for (int ks = 0; ks < 8; ++ks)
-          ya[ks] = sa[(yq * 8 + (l16 >> 1)) * RSA + 2 * (iloc + 4 * ks + lk) + (l16 & 1)];
-        // the terms sharing this Y run as independent MFMA chains, interleaved
-        // over the K steps; a lone term uses two chains (even / odd steps)
-        if (yq == 0) {
-          dbl4 u0 = dbl4{0.0, 0.0, 0.0, 0.0}, u1 = u0;
-#pragma unroll
-          for (int ks = 0; ks < 8; ks += 2) {
-            if (act[ks >> 2]) {
-              u0 = mfma64(creg[0][ks], ya[ks], u0);
-              u1 = mfma64(creg[0][ks + 1], ya[ks + 1], u1);
-            }
-          }
-#pragma unroll
-          for (int r = 0; r < 4; ++r) xacc[r] += (u0[r] + u1[r]) * zt[0][r];
-        } else {
-          // (coefficient part, column comp, sign) of the three terms
-          const int c1 = 1, z1 = yq;
-          const int c2 = yq == 1 ? 3 : (yq == 2 ? 2 : 2), z2 = yq == 1 ? 3 : (yq == 2 ? 3 : 2);
-          const double g2 = yq == 1 ? -1.0 : (yq == 2 ? 1.0 : -1.0);
-          const int c3 = yq == 1 ? 4 : (yq == 2 ? 4 : 3), z3 = yq == 1 ? 2 : (yq == 2 ? 1 : 1);
-          const double g3 = yq == 1 ? 1.0 : (yq == 2 ? -1.0 : 1.0);
-          dbl4 u1 = dbl4{0.0, 0.0, 0.0, 0.0}, u2 = u1, u3 = u1;
-#pragma unroll
-          for (int ks = 0; ks < 8; ++ks) {
-            if (act[ks >> 2]) {
-              if (tSS) u1 = mfma64(creg[c1][ks], ya[ks], u1);
-              if (tSO) {
-                u2 = mfma64(creg[c2][ks], ya[ks], u2);
-                u3 = mfma64(creg[c3][ks], ya[ks], u3);
-              }
-            }
-          }
-#pragma unroll
-          for (int r = 0; r < 4; ++r) xacc[r] += u1[r] * zt[z1][r] + g2 * u2[r] * zt[z2][r] + g3 * u3[r] * zt[z3][r];
-        }
+      for (int ks = 0; ks < 4; ++ks) {
+        // row values Y[q][pt = l16][i = 16 rb + 4 ks + lk]: the K index is lk
+        const int col = 2 * (16 * rb + 4 * ks + lk) + (l16 & 1);
+        const double y0 = ia[(0 * 8 + (l16 >> 1)) * RSQ + col], y1 = ia[(1 * 8 + (l16 >> 1)) * RSQ + col];
+        const double y2 = ia[(2 * 8 + (l16 >> 1)) * RSQ + col], y3 = ia[(3 * 8 + (l16 >> 1)) * RSQ + col];
+        uf = mfma64(creg[0][ks], y0, uf);
+        ux = mfma64(creg[1][ks], y1, ux);
+        uy = mfma64(creg[4][ks], y1, uy);
+        uz = mfma64(creg[3][ks], -y1, uz);
+        ux = mfma64(creg[4][ks], -y2, ux);
+        uy = mfma64(creg[1][ks], y2, uy);
+        uz = mfma64(creg[2][ks], y2, uz);
+        ux = mfma64(creg[3][ks], y3, ux);
+        uy = mfma64(creg[2][ks], -y3, uy);
+        uz = mfma64(creg[1][ks], y3, uz);
       }
-      }
-    }
-    // sum over the wave's 16 columns: the 4 registers, then the 4 lane rows
 #pragma unroll
-    for (int o = 0; o < NO; ++o) {
-      const double *xv = xacc;
-      double sx = (xv[0] + xv[1]) + (xv[2] + xv[3]);
-      sx += __shfl_xor(sx, 16);
-      sx += __shfl_xor(sx, 32);
-      if (lane < 16) s_red[rb2][wave][o][l16] = sx;
+      for (int r = 0; r < 4; ++r) x += (uf[r] * zt[0][r] + ux[r] * zt[1][r]) + (uy[r] * zt[2][r] + uz[r] * zt[3][r]);
+      // sum over the block's 16 columns: the 4 registers (above), then the 4 lane rows
+      x += __shfl_xor(x, 16);
+      x += __shfl_xor(x, 32);
     }
+    if (lane < 16) s_red[bi][wave][l16] = x;
   }
   __syncthreads();  // the last chunk's per-wave sums
   {
-    const int k0 = Pp - 16, rb2 = (k0 >> 4) & 1;
-    if (tid < 16 * NO && k0 + (tid & 15) < P) {
-      const int o = tid >> 4, t = tid & 15;
-      out[o * P + k0 + t] = (s_red[rb2][0][o][t] + s_red[rb2][1][o][t]) + (s_red[rb2][2][o][t] + s_red[rb2][3][o][t]);
-    }
+    const int k0 = Pp - 16, bi = (k0 >> 4) & 1;
+    if (tid < 16 && k0 + tid < P)
+      out[k0 + tid] = (s_red[bi][0][tid] + s_red[bi][1][tid]) + (s_red[bi][2][tid] + s_red[bi][3][tid]);
   }
+  }  // quarter_valid
   if (!PERSIST) break;
   pos = next_item(tickets, npos, order != nullptr, &s_pos);
   }
 }
 
-// Point sums: out[perm[g]] = (w_g if weighted) * sum over the batch's work items (in order).
-__global__ void k_density_points(DevPlan d, int64_t b0, const double *partial, int weight_mode, double *out) {
+// Point sums: out[perm[g]] = (w_g if weighted) * sum over the batch's work
+// items (in order) and their valid quarters (in order).
+__global__ void k_density_points(DevPlan d, const WorkItem *work, int64_t b0, const double *partial, int weight_mode,
+                                 double *out) {
   const int64_t b = b0 + blockIdx.x;
   const int g0 = d.batch_pt_off[b], P = d.batch_pt_off[b + 1] - g0;
+  const int n = d.batch_fn_off[b + 1] - d.batch_fn_off[b];
   const int64_t wa = d.batch_work_off[b], wb = d.batch_work_off[b + 1];
   for (int g = threadIdx.x; g < P; g += blockDim.x) {
     double s = 0.0;
     for (int64_t w = wa; w < wb; ++w) {
-      const double *pw = partial + 2 * d.work_part_off[w];
-      s += pw[g];
-      s += pw[P + g];
+      const WorkItem it = work[w];
+      const double *pw = partial + 4 * d.work_part_off[w];
+#pragma unroll
+      for (int qd = 0; qd < 4; ++qd)
+        if (quarter_valid(it, qd, n)) s += pw[qd * P + g];
     }
     out[d.perm[g0 + g]] = weight_mode ? d.pw[g0 + g] * s : s;
   }
@@ -1165,10 +1091,15 @@ static int check_launch(const char *what) {
   return Q4C_OK;
 }
 
-int launch_tabulate(const q4c_plan *p, int64_t b0, int64_t b1, int deriv, double *out, hipStream_t s) {
+int launch_tabulate(const q4c_plan *p, int64_t b0, int64_t b1, int deriv, int dtype, void *out, hipStream_t s) {
+  const int64_t t0 = p->batch_tile_off[b0], nt = p->batch_tile_off[b1] - t0;
+  if (nt <= 0) return Q4C_OK;
   {
     TimedLaunch tl_(p, Q4C_TIMER_TABULATE, s);
-    hipLaunchKernelGGL(k_tabulate, dim3((unsigned)(b1 - b0)), dim3(256), 0, s, p->dp, b0, deriv, out);
+    if (dtype == Q4C_DTYPE_F32_HILO)
+      hipLaunchKernelGGL(k_tabulate<true>, dim3((unsigned)nt), dim3(256), 0, s, p->dp, p->d_ptile, t0, b0, deriv, out);
+    else
+      hipLaunchKernelGGL(k_tabulate<false>, dim3((unsigned)nt), dim3(256), 0, s, p->dp, p->d_ptile, t0, b0, deriv, out);
   }
   return check_launch("k_tabulate");
 }
@@ -1331,7 +1262,7 @@ int launch_integrate_hs(const q4c_plan *p, const double *v, uint32_t flags, doub
 }
 
 int launch_density(const q4c_plan *p, const double *coef, uint32_t terms, int weight_mode, double *out,
-                   hipStream_t s) {
+                   int64_t resident_pass, hipStream_t s) {
   int rc;
   if (p->n_points > 0) {
     {
@@ -1348,12 +1279,17 @@ int launch_density(const q4c_plan *p, const double *coef, uint32_t terms, int we
     hipLaunchKernelGGL(k_zero_u32, dim3(8), dim3(256), 0, s, tick0, (int64_t)p->passes.size() * kTicketsPerLaunch);
     if ((rc = check_launch("k_zero_u32")) != Q4C_OK) return rc;
   }
-  for (size_t ip = 0; ip < p->passes.size(); ++ip) {
+  // passes from the last one down: the first one may find its panels resident
+  // (the forward call ends with its last pass); each point's partials lie in
+  // one pass, so the order of the passes does not change any result
+  for (size_t ipr = p->passes.size(); ipr-- > 0;) {
+    const size_t ip = ipr;
     const Pass &ps = p->passes[ip];
-    const int64_t nw = ps.w1 - ps.w0, nbt = ps.b1 - ps.b0, nt = ps.t1 - ps.t0;
+    const int64_t nw = ps.w1 - ps.w0, nbt = ps.b1 - ps.b0;
+    const int64_t nt = (int64_t)ip == resident_pass ? 0 : ps.t1 - ps.t0;
     unsigned *tickets = cfg.persistent > 0 ? tick0 + ip * kTicketsPerLaunch : nullptr;
-    // two workgroup positions (column halves) per work item
-    const unsigned grid = (unsigned)(cfg.persistent > 0 ? std::min<int64_t>(cfg.persistent, 2 * nw) : 2 * nw);
+    // four workgroup positions (quarters) per work item
+    const unsigned grid = (unsigned)(cfg.persistent > 0 ? std::min<int64_t>(cfg.persistent, 4 * nw) : 4 * nw);
     double *partial = p->d_staging + ps.staging_len;
     double *panel = partial + ps.partial_len;
     if (nt > 0) {
@@ -1378,7 +1314,7 @@ int launch_density(const q4c_plan *p, const double *coef, uint32_t terms, int we
     if (nbt > 0) {
       {
         TimedLaunch tl_(p, Q4C_TIMER_DENSITY_POINTS, s);
-        hipLaunchKernelGGL(k_density_points, dim3((unsigned)nbt), dim3(256), 0, s, p->dp, ps.b0, partial,
+        hipLaunchKernelGGL(k_density_points, dim3((unsigned)nbt), dim3(256), 0, s, p->dp, p->d_work, ps.b0, partial,
                            weight_mode, out);
       }
       if ((rc = check_launch("k_density_points")) != Q4C_OK) return rc;

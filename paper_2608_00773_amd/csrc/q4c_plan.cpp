@@ -82,8 +82,11 @@ bool finite_all(const double *p, int64_t n) {
 }
 
 // Recursive median bisection along the axis of largest extent until a batch
-// holds at most pmax points.  Ties are broken by index, so the result does not
-// depend on the nth_element implementation.
+// holds at most pmax points.  The cut goes at the multiple of 16 points
+// nearest the median (once a half holds 16 points or more), so every batch
+// but the last of each system fills whole 16-point chunks of the MFMA
+// contractions.  Ties are broken by index, so the result does not depend on
+// the nth_element implementation.
 void bisect(std::vector<int32_t> &idx, int64_t lo, int64_t hi, int pmax, const double *const xyz[3],
             std::vector<int64_t> &ends) {
   struct Seg {
@@ -111,7 +114,9 @@ void bisect(std::vector<int32_t> &idx, int64_t lo, int64_t hi, int pmax, const d
     for (int d = 1; d < 3; ++d)
       if (mx[d] - mn[d] > mx[ax] - mn[ax]) ax = d;
     const double *c = xyz[ax];
-    int64_t mid = s.lo + n / 2;
+    const int64_t half = n / 2;
+    const int64_t left = half >= 16 ? std::min<int64_t>((half + 8) / 16 * 16, n - 1) : half;
+    int64_t mid = s.lo + left;
     std::nth_element(idx.begin() + s.lo, idx.begin() + mid, idx.begin() + s.hi,
                      [c](int32_t a, int32_t b) { return c[a] < c[b] || (c[a] == c[b] && a < b); });
     stack.push_back({mid, s.hi});
@@ -484,12 +489,13 @@ int build_host(q4c_plan *p, const q4c_basis *b, const q4c_grid *g, const std::ve
       }
     }
     int nt = (nb_fn + T - 1) / T;
-    int64_t bpart = 2 * (int64_t)(nt * (nt + 1) / 2) * (g1 - g0);  // two column halves per work item
+    int64_t bpart = 4 * (int64_t)(nt * (nt + 1) / 2) * (g1 - g0);  // four quarters per work item
     // panel (4 components) and, after it, the per-(tile, point) largest gradient magnitude
     int64_t bpanel = 4 * q4c::pad16(g1 - g0) * q4c::pad16(nb_fn) + (int64_t)nt * q4c::pad16(g1 - g0);
     if (bt > cur.b0 && (staging + partial + panel + bstage + bpart + bpanel > budget_doubles)) close_pass(bt);
     p->panel_off.push_back(panel);
     panel += bpanel;
+    p->batch_tile_off.push_back((int64_t)p->ptile.size());
     for (int t = 0; t < nt; ++t) p->ptile.push_back(q4c::WorkItem{(int32_t)bt, (int16_t)t, (int16_t)t});
     // slot-pair -> stored pair table (upper triangle)
     {
@@ -530,9 +536,9 @@ int build_host(q4c_plan *p, const q4c_basis *b, const q4c_grid *g, const std::ve
     for (int ti = 0; ti < nt; ++ti)
       for (int tj = ti; tj < nt; ++tj) {
         p->work.push_back(q4c::WorkItem{(int32_t)bt, (int16_t)ti, (int16_t)tj});
-        // adjoint partials of this work item: two column halves of P doubles at 2 * work_part_off
-        p->work_part_off.push_back(partial / 2);
-        partial += 2 * (g1 - g0);
+        // adjoint partials of this work item: four quarters of P doubles at 4 * work_part_off
+        p->work_part_off.push_back(partial / 4);
+        partial += 4 * (g1 - g0);
       }
     p->max_batch_points = std::max<int64_t>(p->max_batch_points, g1 - g0);
     p->max_batch_fn = std::max<int64_t>(p->max_batch_fn, nb_fn);
@@ -540,6 +546,7 @@ int build_host(q4c_plan *p, const q4c_basis *b, const q4c_grid *g, const std::ve
     p->flops_alg_hs += 3.0 * (double)(g1 - g0) * (double)nb_fn * (double)nb_fn;
   }
   close_pass(p->n_batches);
+  p->batch_tile_off.push_back((int64_t)p->ptile.size());
   p->red_inc_off.push_back((int64_t)p->inc_src.size());
   p->batch_work_off.assign(p->n_batches + 1, 0);
   for (auto &w : p->work) p->batch_work_off[w.batch + 1]++;
@@ -753,7 +760,7 @@ int create_plan(const q4c_basis *basis, const q4c_grid *grid, const q4c_opts *op
       if (opts->split_threshold > 0.0) p->split_tau = opts->split_threshold;
     }
     if (p->p_max < 1) p->p_max = 300;
-    if (p->staging_budget <= 0) p->staging_budget = (int64_t)16 << 30;
+    if (p->staging_budget <= 0) p->staging_budget = (int64_t)32 << 30;
     rc = build_host(p, basis, grid, sys_atom_off, pt_sys);
     if (rc == Q4C_OK && !(p->flags & Q4C_PLAN_HOST_ONLY)) rc = build_device(p);
   } catch (const std::bad_alloc &) {
@@ -919,6 +926,30 @@ int q4c_plan_batches(const q4c_plan *p, int64_t *pt_off, int64_t *point_index, i
   return Q4C_OK;
 }
 
+int q4c_store_layout(const q4c_plan *p, q4c_layout *layout, int32_t *pair_atoms, int64_t *pair_off,
+                     int32_t *pair_nfn) {
+  if (!p || !layout) return fail(Q4C_EINVAL, "NULL argument");
+  layout->n_pairs = p->n_pairs;
+  layout->store_len = p->store_len;
+  layout->part_bytes = 8 * p->store_len;
+  layout->store_bytes = 40 * p->store_len;
+  layout->hs_bytes = 16 * p->store_len;
+  layout->spinor_bytes = 64 * p->store_len;
+  for (int64_t q = 0; q < p->n_pairs; ++q) {
+    if (pair_atoms) {
+      pair_atoms[2 * q] = p->pair_a[q];
+      pair_atoms[2 * q + 1] = p->pair_b[q];
+    }
+    if (pair_nfn) {
+      pair_nfn[2 * q] = p->pair_na[q];
+      pair_nfn[2 * q + 1] = p->pair_nb[q];
+    }
+  }
+  if (pair_off)
+    for (int64_t q = 0; q <= p->n_pairs; ++q) pair_off[q] = p->pair_off[q];
+  return Q4C_OK;
+}
+
 int q4c_tabulate_size(const q4c_plan *p, int64_t b0, int64_t b1, int32_t deriv, int64_t *n) {
   if (!p || !n) return fail(Q4C_EINVAL, "NULL argument");
   if (b0 < 0 || b1 < b0 || b1 > p->n_batches) return fail(Q4C_EINVAL, "batch range outside the plan");
@@ -930,17 +961,18 @@ int q4c_tabulate_size(const q4c_plan *p, int64_t b0, int64_t b1, int32_t deriv, 
   return Q4C_OK;
 }
 
-int nao_tabulate(const q4c_plan *p, int64_t b0, int64_t b1, int32_t deriv, double *out_dev, int64_t out_len,
-                 void *stream) {
+int nao_tabulate(const q4c_plan *p, int64_t b0, int64_t b1, int32_t deriv, int32_t dtype, void *out_dev,
+                 int64_t out_bytes, void *stream) {
   int64_t need = 0;
   int rc = q4c_tabulate_size(p, b0, b1, deriv, &need);
   if (rc != Q4C_OK) return rc;
-  if (out_len < need) return fail(Q4C_ESIZE, "output buffer too small for nao_tabulate");
+  if (dtype != Q4C_DTYPE_F64 && dtype != Q4C_DTYPE_F32_HILO) return fail(Q4C_EINVAL, "unknown dtype");
+  if (out_bytes < 8 * need) return fail(Q4C_ESIZE, "output buffer too small for nao_tabulate");
   if (need > 0 && !out_dev) return fail(Q4C_EINVAL, "NULL output");
   rc = check_plan_dev(p);
   if (rc != Q4C_OK) return rc;
   if (need == 0) return Q4C_OK;
-  return q4c::launch_tabulate(p, b0, b1, deriv, out_dev, (hipStream_t)stream);
+  return q4c::launch_tabulate(p, b0, b1, deriv, dtype, out_dev, (hipStream_t)stream);
 }
 
 namespace {
@@ -1023,14 +1055,19 @@ int q4c_integrate_H(const q4c_plan *p, const double *v_dev, int32_t precision, u
     if (rc != Q4C_OK) return rc;
     if (!ok) return fail(Q4C_ENONFINITE, "potential contains NaN or Inf");
   }
+  p->panel_pass = -1;
   if (p->use_graphs && !p->profiling) {
     const uint32_t f = flags & ~(uint32_t)Q4C_CHECK_FINITE;
-    return run_graph(p, 0, v_dev, store_dev, spin_w_dev, spin_v_dev, precision, f, 0, (hipStream_t)stream,
-                     [&](hipStream_t cs) {
-                       return q4c::launch_integrate(p, v_dev, precision, f, store_dev, spin_w_dev, spin_v_dev, cs);
-                     });
+    rc = run_graph(p, 0, v_dev, store_dev, spin_w_dev, spin_v_dev, precision, f, 0, (hipStream_t)stream,
+                   [&](hipStream_t cs) {
+                     return q4c::launch_integrate(p, v_dev, precision, f, store_dev, spin_w_dev, spin_v_dev, cs);
+                   });
+  } else {
+    rc = q4c::launch_integrate(p, v_dev, precision, flags, store_dev, spin_w_dev, spin_v_dev, (hipStream_t)stream);
   }
-  return q4c::launch_integrate(p, v_dev, precision, flags, store_dev, spin_w_dev, spin_v_dev, (hipStream_t)stream);
+  // every pass tabulates its W-path panels; the last pass's stay resident
+  if (rc == Q4C_OK) p->panel_pass = (int64_t)p->passes.size() - 1;
+  return rc;
 }
 
 int q4c_plan_set_ket_potential(q4c_plan *p, const int64_t *shell_u_off, int64_t n_u, const double *u_coef) {
@@ -1358,7 +1395,11 @@ int density_gradient_on_grid(const q4c_plan *p, const double *coef_dev, double *
   int rc = check_plan_dev(p);
   if (rc != Q4C_OK) return rc;
   if (p->gr_item_off.empty() && (rc = build_grad_tables(p)) != Q4C_OK) return rc;
-  return q4c::launch_density_grad(p, coef_dev, out_dev, (hipStream_t)stream);
+  p->panel_pass = -1;
+  rc = q4c::launch_density_grad(p, coef_dev, out_dev, (hipStream_t)stream);
+  // every pass tabulates its W-path panels; the last pass's stay resident
+  if (rc == Q4C_OK) p->panel_pass = (int64_t)p->passes.size() - 1;
+  return rc;
 }
 
 int q4c_plan_set_cells(q4c_plan *p, int32_t n_cell_atoms, const int32_t *cell_atom, const double *shift) {
@@ -1542,6 +1583,7 @@ int q4c_integrate_HS(const q4c_plan *p, const double *v_dev, uint32_t flags, dou
     if (rc != Q4C_OK) return rc;
     if (!ok) return fail(Q4C_ENONFINITE, "potential contains NaN or Inf");
   }
+  p->panel_pass = -1;  // the H/S panels replace the W-path panels
   return q4c::launch_integrate_hs(p, v_dev, flags & ~(uint32_t)Q4C_CHECK_FINITE, hs_dev, (hipStream_t)stream);
 }
 
@@ -1554,10 +1596,21 @@ int density_on_grid(const q4c_plan *p, const double *coef_dev, uint32_t terms, i
   if (p->n_points > 0 && !out_dev) return fail(Q4C_EINVAL, "NULL output");
   int rc = check_plan_dev(p);
   if (rc != Q4C_OK) return rc;
+  // panels the previous call left resident are used, not tabulated again;
+  // only the first pass this call runs (the last one) can find its own: any
+  // pass it tabulates may overwrite another pass's region
+  const int64_t resident = p->panel_pass == (int64_t)p->passes.size() - 1 ? p->panel_pass : -1;
+  p->panel_pass = -1;
   if (p->use_graphs && !p->profiling)
-    return run_graph(p, 1, coef_dev, out_dev, nullptr, nullptr, terms, weight_mode, 0, (hipStream_t)stream,
-                     [&](hipStream_t cs) { return q4c::launch_density(p, coef_dev, terms, weight_mode, out_dev, cs); });
-  return q4c::launch_density(p, coef_dev, terms, weight_mode, out_dev, (hipStream_t)stream);
+    rc = run_graph(p, 1, coef_dev, out_dev, nullptr, nullptr, terms, weight_mode, resident, (hipStream_t)stream,
+                   [&](hipStream_t cs) {
+                     return q4c::launch_density(p, coef_dev, terms, weight_mode, out_dev, resident, cs);
+                   });
+  else
+    rc = q4c::launch_density(p, coef_dev, terms, weight_mode, out_dev, resident, (hipStream_t)stream);
+  // the passes ran from the last one down: pass 0's panels are resident
+  if (rc == Q4C_OK && !p->passes.empty()) p->panel_pass = 0;
+  return rc;
 }
 
 int q4c_plan_set_graphs(q4c_plan *p, int enable) {
@@ -1656,7 +1709,7 @@ int q4c_plan_autotune(q4c_plan *p, const double *v_dev, int32_t precision, doubl
           rc = time_call([&] { return q4c::launch_integrate(p, v_dev, precision, 0, store_dev, nullptr, nullptr, s); },
                          &ms);
         else
-          rc = time_call([&] { return q4c::launch_density(p, coef_dev, Q4C_TERM_ALL, 1, out_dev, s); }, &ms);
+          rc = time_call([&] { return q4c::launch_density(p, coef_dev, Q4C_TERM_ALL, 1, out_dev, -1, s); }, &ms);
         if (rc != Q4C_OK) break;
         if (table && n_out < table_len) table[n_out] = q4c_tune_entry{kernel, order, cand_p[ip], ms};
         ++n_out;
@@ -1677,6 +1730,7 @@ int q4c_plan_autotune(q4c_plan *p, const double *v_dev, int32_t precision, doubl
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  p->panel_pass = -1;
   p->profiling = prof;
   p->use_graphs = graphs;
   if (n_entries) *n_entries = n_out;

@@ -62,6 +62,42 @@ def test_host_only_plan_and_nodev_errors():
     assert rc == q.Q4C_ENODEV
 
 
+def test_store_layout_matches_pairs_and_sizes():
+    """q4c_store_layout (Sec. III A: locally indexed dense pair blocks): the
+    pair list and offsets equal q4c_plan_pairs, the block shapes are the
+    atoms' function counts, the byte sizes follow from store_len."""
+    q, lib = _lib()
+    wl = W.config_small(nrad=10, nang=26)
+    p = _host_plan(q, wl)
+    lay = p.store_layout()
+    pairs, po = p.pairs()
+    nfn = wl.atom_nfn()
+    L = p.info["store_len"]
+    assert lay["n_pairs"] == len(pairs) and lay["store_len"] == L
+    assert np.array_equal(lay["pair_atoms"], pairs) and np.array_equal(lay["pair_off"], po)
+    assert np.array_equal(lay["pair_nfn"], np.stack([nfn[pairs[:, 0]], nfn[pairs[:, 1]]], axis=1))
+    assert np.array_equal(np.diff(po), lay["pair_nfn"][:, 0] * lay["pair_nfn"][:, 1])
+    assert (lay["part_bytes"], lay["store_bytes"], lay["hs_bytes"], lay["spinor_bytes"]) == (8 * L, 40 * L, 16 * L,
+                                                                                         64 * L)
+    out = q._StoreLayout()
+    assert lib.q4c_store_layout(p.handle, ctypes.byref(out), None, None, None) == q.Q4C_OK
+    assert out.store_len == L
+    assert lib.q4c_store_layout(p.handle, None, None, None, None) == q.Q4C_EINVAL
+
+
+def test_nao_tabulate_argument_checks():
+    q, lib = _lib()
+    wl = W.config_small(nrad=10, nang=26)
+    p = _host_plan(q, wl)
+    n = p.tabulate_size(0, 2, 1)
+    buf = ctypes.c_void_p(1)
+    assert lib.nao_tabulate(p.handle, 0, 2, 1, 7, buf, 8 * n, None) == q.Q4C_EINVAL  # unknown dtype
+    for dt in (q.DTYPE_F64, q.DTYPE_F32_HILO):
+        assert lib.nao_tabulate(p.handle, 0, 2, 1, dt, buf, 8 * n - 1, None) == q.Q4C_ESIZE
+        assert lib.nao_tabulate(p.handle, 0, 2, 1, dt, buf, 8 * n, None) == q.Q4C_ENODEV
+    assert lib.nao_tabulate(p.handle, 2, 1, 1, 0, buf, 8 * n, None) == q.Q4C_EINVAL
+
+
 def test_argument_validation():
     q, lib = _lib()
     wl = W.config_small(nrad=10, nang=26)
@@ -79,7 +115,7 @@ def test_argument_validation():
     n = ctypes.c_int64()
     assert lib.q4c_tabulate_size(p.handle, 0, p.info["n_batches"] + 1, 1, ctypes.byref(n)) == q.Q4C_EINVAL
     assert lib.q4c_tabulate_size(p.handle, 0, 1, 2, ctypes.byref(n)) == q.Q4C_EINVAL
-    assert lib.nao_tabulate(p.handle, 0, 1, 1, ctypes.c_void_p(1), 0, None) == q.Q4C_ESIZE
+    assert lib.nao_tabulate(p.handle, 0, 1, 1, 0, ctypes.c_void_p(1), 0, None) == q.Q4C_ESIZE
 
 
 def test_unsupported_l_and_malformed_basis():

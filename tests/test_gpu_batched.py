@@ -141,7 +141,10 @@ def test_autotune_keeps_results(env):
     for kernel in (q.KERNEL_CONTRACT, q.KERNEL_DENSITY):
         rows = [t for t in table if t[0] == kernel]
         best = min(rows, key=lambda t: t[3])
-        assert pb.get_launch(kernel) == (best[1], best[2])
+        best0 = min([t for t in rows if t[1] == 0], key=lambda t: t[3])
+        # the fastest shape, or the fastest batch-order shape within 2% of it
+        want = best0 if best0[3] <= 1.02 * best[3] else best
+        assert pb.get_launch(kernel) == (want[1], want[2])
         assert all(t[3] > 0 for t in rows)
     st, out = _run(q, torch, pb, env["v"], env["coef"], q.PREC_F64)
     assert torch.equal(st, st0)

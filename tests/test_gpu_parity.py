@@ -119,6 +119,20 @@ def test_nao_tabulate_matches_oracle(q, small):
     assert o == n
     print("nao_tabulate: worst |d| / (own scale + 1e-300) %.3g" % worst)
     assert worst <= 1e-12, worst
+    # FP32 hi + lo output: per batch [4][2][P][n] floats, hi = fl32(x) and
+    # lo = fl32(x - hi) of the FP64 values, bit for bit
+    hl = torch.full((2 * n,), float("nan"), dtype=torch.float32, device="cuda")
+    q.nao_tabulate(plan, 0, nb, 1, hl, q.DTYPE_F32_HILO)
+    torch.cuda.synchronize()
+    hl = hl.cpu().numpy()
+    o = 0
+    for b in range(nb):
+        m = (pt_off[b + 1] - pt_off[b]) * (fn_off[b + 1] - fn_off[b])
+        x = got[o:o + 4 * m].reshape(4, m)
+        h = hl[2 * o:2 * o + 8 * m].reshape(4, 2, m)
+        hi = x.astype(np.float32)
+        assert np.array_equal(h[:, 0], hi) and np.array_equal(h[:, 1], (x - hi.astype(np.float64)).astype(np.float32))
+        o += 4 * m
 
 
 def test_tabulate_values_only_and_size_errors(q, small):
@@ -417,3 +431,41 @@ def test_split_rejects_batches_over_1024_points(q, small):
         q.q4c_integrate_H(plan, v, q.PREC_F32, 0, st)
     assert e.value.status == q.Q4C_EUNSUPPORTED
     q.q4c_integrate_H(plan, v, q.PREC_F64, 0, st)  # FP64 has no such limit
+
+
+def test_adjoint_reuses_resident_panels_bitwise(q, medium):
+    """density_on_grid after q4c_integrate_H takes the operand panels the
+    forward call left resident for its last staging pass instead of
+    tabulating them again, and runs the passes from the last one down.  Its
+    output must be bitwise that of a call that tabulates every pass (after
+    q4c_integrate_HS has replaced the panels), with one pass and with many,
+    eagerly and under graph replay."""
+    torch = _torch()
+    wl = W.with_ket(medium[0], 7011)
+    rng = np.random.default_rng(83)
+    v = torch.from_numpy(wl.v).cuda()
+    for staging in (0, 1 << 20):
+        plan = q.Plan(wl, staging_bytes=staging)
+        plan.set_ket_potential(wl)
+        print("passes:", plan.info["n_passes"], flush=True)
+        coef = torch.from_numpy(rng.standard_normal((5, plan.info["store_len"]))).cuda()
+        st, hs = q.new_store(plan), q.new_hs(plan)
+        fresh = torch.empty(wl.n_points, dtype=torch.float64, device="cuda")
+        q.q4c_integrate_HS(plan, v, 0, hs)  # panels now hold H/S values: every pass tabulates
+        q.density_on_grid(plan, coef, q.TERM_ALL, 1, fresh)
+        for graphs in (False, True):
+            plan.set_graphs(graphs)
+            for rep in range(3):
+                reused = torch.full_like(fresh, float("nan"))
+                q.q4c_integrate_H(plan, v, q.PREC_F64, 0, st)
+                q.density_on_grid(plan, coef, q.TERM_ALL, 1, reused)
+                again = torch.full_like(fresh, float("nan"))
+                q.density_on_grid(plan, coef, q.TERM_ALL, 1, again)  # pass 0 resident now
+                q.q4c_integrate_HS(plan, v, 0, hs)
+                after_hs = torch.full_like(fresh, float("nan"))
+                q.density_on_grid(plan, coef, q.TERM_ALL, 1, after_hs)
+                torch.cuda.synchronize()
+                assert torch.equal(reused, fresh), (staging, graphs, rep)
+                assert torch.equal(again, fresh), (staging, graphs, rep)
+                assert torch.equal(after_hs, fresh), (staging, graphs, rep)
+        plan.set_graphs(False)

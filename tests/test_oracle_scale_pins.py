@@ -157,3 +157,34 @@ def test_density_grad_scale_bounds(small):
     _, sc = oracle.density(wl, pairs, [np.stack([b[0]] + [0 * b[0]] * 4) for b in blocks], idx=idx,
                            with_scale=True)
     assert np.allclose(gs[:, 0], sc[:, 0], rtol=1e-13, atol=0)
+
+
+def test_tabulation_scale_covers_distance_rounding():
+    """Moving a point away from an atom by a relative eps changes each of that
+    atom's values by about eps s |dvalue/ds|; the scale carries this
+    sensitivity (needed in the steep tails of tight functions, where a
+    one-ulp difference in s moves the value far more than one ulp).  The
+    move also scales S_lm ~ s^l (l <= 4 here), hence the factor l + 2.5."""
+    wl = W.small_component(W.with_ket(W.config_small(nrad=16, nang=26), 7001), 7002)
+    a = 0
+    rng = np.random.default_rng(9103)
+    n = 400
+    r = rng.uniform(0.05, 0.99 * float(wl.shell_rcut.max()), n)
+    u = rng.standard_normal((n, 3))
+    u /= np.linalg.norm(u, axis=1)[:, None]
+    eps = 1e-9
+    p0 = wl.R[a] + r[:, None] * u
+    p1 = wl.R[a] + (r * (1 + eps))[:, None] * u
+    f0 = int(np.sum([2 * int(wl.shell_l[s]) + 1 for s in range(wl.atom_shell_off[a])]))
+    f1 = f0 + int(wl.atom_nfn()[a])
+    phi0, g0, aphi, agrad = oracle.tabulate(wl, p0[:, 0], p0[:, 1], p0[:, 2], with_abs=True)
+    phi1, g1 = oracle.tabulate(wl, p1[:, 0], p1[:, 1], p1[:, 2])
+    sl = slice(f0, f1)
+    nz = aphi[:, sl] > 1e-250
+    assert np.all(np.abs(phi1[:, sl] - phi0[:, sl])[nz] <= 6.5 * eps * aphi[:, sl][nz])
+    nzg = agrad[:, sl, :] > 1e-250
+    assert np.all(np.abs(g1[:, sl, :] - g0[:, sl, :])[nzg] <= 6.5 * eps * agrad[:, sl, :][nzg])
+    # without the sensitivity term the plain term magnitudes would not cover it
+    # somewhere in the tails: the largest relative change exceeds eps there
+    rel = np.max(np.abs(phi1[:, sl] - phi0[:, sl])[nz] / (np.abs(phi0[:, sl])[nz] + 1e-300))
+    assert rel > 10 * eps

@@ -585,8 +585,11 @@ def main():
                         "TFLOP/s", c_order),
         kernel_roofline("k_density_tiles", "density_tiles", "mfma", info["flops_alg"], PEAK_F64, "TFLOP/s",
                         d_order),
-        # tabulation: 32 B (phi and its gradient, FP64) per (point, relevant function), forward and adjoint
-        kernel_roofline("k_panel", "tabulate", "hbm", 2 * 32.0 * info["tab_elems"], PEAK_HBM, "GB/s"),
+        # tabulation: 32 B (phi and its gradient, FP64) per (point, relevant function) per
+        # tabulation of all passes; the adjoint tabulates only passes whose panels are not resident
+        kernel_roofline("k_panel", "tabulate", "hbm",
+                        32.0 * info["tab_elems"] * tim["tabulate"][1] / a.steps / max(info["n_passes"], 1),
+                        PEAK_HBM, "GB/s"),
         # batch-to-global sum: the staged partial blocks read once, the five parts written once
         kernel_roofline("k_reduce", "reduce", "hbm", info["staging_bytes"] + 40.0 * info["store_len"], PEAK_HBM,
                         "GB/s"),
@@ -596,7 +599,7 @@ def main():
     # q4c_integrate_H alone (the metric's t_H): each precision, all five parts
     # and the W spinor, median of 20 calls timed one by one after 3 warm-ups;
     # error of each split mode against the FP64 path
-    h_only, outs, hot = {}, {}, {}
+    h_only, outs = {}, {}
     for name, p in PREC.items():
         st = q.new_store(plan, dev)
         call = lambda: q.q4c_integrate_H(plan, v, p, q.ASSEMBLE_W, st, spin)
@@ -605,9 +608,6 @@ def main():
         h_only[name] = {"ms_median": med, "points_per_s": n_act / (med * 1e-3),
                         "gflops_alg": info["flops_alg"] / (med * 1e-3) / 1e9, "ms_min": float(np.min(ms_list))}
         outs[name] = st
-        if name != "f64":
-            h, t = plan.split_stats()
-            hot[name] = h / max(t, 1)
     for name in h_only:
         h_only[name]["speedup_vs_f64"] = h_only["f64"]["ms_median"] / h_only[name]["ms_median"]
     err = {n: [float(torch.max(torch.abs(outs[n][k] - outs["f64"][k]))) for k in range(5)] for n in outs}
@@ -661,7 +661,6 @@ def main():
         "kernels_ms_per_step": {k: v_[0] / a.steps for k, v_ in tim.items() if v_[1]},
         "staging_bytes_per_call": info["staging_bytes"],
         "max_abs_diff_vs_f64_Ha": {k: dict(zip(q.PART_NAMES, e)) for k, e in err.items() if k != "f64"},
-        "w_chunks_on_f64_mfma": hot,
         "plan_s": t_plan,
         "workload_gen_s": t_gen,
         "wall_timed_s": wall,

@@ -61,16 +61,37 @@ enum {
   Q4C_ENODEV = -8        /* plan has no device data (host-only plan or no GPU) */
 };
 
-/* precision of the per-batch contractions */
+/* precision of the per-batch contractions (paper Sec. III A, Eq. 29/31):
+ * V always runs on FP64 MFMA (its elements reach ~1e2 Ha, beyond what FP32
+ * accumulation can hold to 1e-8 Ha).  The W parts (9 of the 10 P n^2 flops
+ * of a batch):
+ *   Q4C_PREC_F64        FP64 MFMA, FP64 accumulation.
+ *   Q4C_PREC_F32        FP32 MFMA on FP32 operands (gradients tabulated in
+ *                       FP32, the weight w v applied in FP64 and rounded);
+ *                       every element's FP32 partial sum covers 16 points (at
+ *                       most 48 products) and is then added to an FP64 sum.
+ *                       Bound: |error| <= gamma_52 A_ij + (FP32 underflow:
+ *                       below 1e-25 Ha) + FP64 rounding, with
+ *                       gamma_k = k u / (1 - k u), u = 2^-24 (gamma_52 ~ 3.1e-6)
+ *                       and A_ij the sum over all points of the magnitudes of
+ *                       the element's terms (c' sum_g |w_g v_g| sum |d phi_i|
+ *                       |d phi_j| over the products entering it).
+ *   Q4C_PREC_SPLIT_F32  as F32 with each operand split into hi = fl32(x) and
+ *                       lo = fl32(x - hi) and every product taken as
+ *                       hi hi + hi lo + lo hi (three FP32 MFMAs): operand
+ *                       rounding drops to about 2^-48, and a 16-point partial
+ *                       sum has up to 144 products: gamma_150 A_ij.
+ * Batch partial sums are added to the store in FP64 in a fixed order. */
 enum {
-  Q4C_PREC_F64 = 0,      /* FP64 MFMA, FP64 accumulation */
-  Q4C_PREC_SPLIT_F32 = 1, /* FP32 MFMA on hi+lo split operands (three products),
-                             FP32 per-batch accumulation, FP64 batch-to-global
-                             sums; the V part stays on FP64 MFMA */
-  Q4C_PREC_F32 = 2        /* as Q4C_PREC_SPLIT_F32 with single FP32 operands
-                             (one product): the W parts' error is dominated by
-                             the FP32 accumulation either way */
+  Q4C_PREC_F64 = 0,
+  Q4C_PREC_SPLIT_F32 = 1,
+  Q4C_PREC_F32 = 2
 };
+
+/* parts of q4c_integrate_H (bit set): V, the scalar W part Ws, the three
+ * spin-orbit parts Wso_x,y,z.  Parts not selected are neither computed nor
+ * written (their store elements keep their values). */
+enum { Q4C_PART_V = 1u, Q4C_PART_WS = 2u, Q4C_PART_WSO = 4u, Q4C_PART_ALL = 7u };
 
 /* flags of q4c_integrate_H */
 enum {
@@ -122,8 +143,6 @@ typedef struct {
   int64_t staging_bytes;    /* per-plan scratch budget (staged batch results and
                                operand panels); <= 0 selects 32 GiB.  Batches are
                                processed in passes that fit the budget. */
-  double split_threshold;   /* split-precision routing bound in hartree (see
-                               q4c_integrate_H); <= 0 selects 3e-11 */
 } q4c_opts;
 
 typedef struct {
@@ -233,19 +252,17 @@ int q4c_tabulate_size(const q4c_plan *plan, int64_t b0, int64_t b1, int32_t deri
 int nao_tabulate(const q4c_plan *plan, int64_t b0, int64_t b1, int32_t deriv, int32_t dtype, void *out_dev,
                  int64_t out_bytes, void *stream);
 
-/* q4c_integrate_H: the five real parts of the atom-pair store from the
- * potential v (device, [n_points], user order, hartree):
- * store_dev[0..5 store_len) = V, Ws, Wso_x, Wso_y, Wso_z with c' applied.
- * Q4C_PREC_F64 runs the per-batch contractions on FP64 MFMA.  The split
- * modes run V on FP64 MFMA (its elements reach ~1e2 Ha) and the four W parts
- * per 16-point chunk either on FP32 MFMA (FP32 operands, or hi+lo split
- * operands for Q4C_PREC_SPLIT_F32, FP32 accumulation over the batch) or, when
- * the chunk's bound 2^-24 c' 48 max|grad phi| max|w v grad phi| exceeds the
- * plan's split_threshold, on FP64 MFMA; the FP32 partial sums join the FP64
- * ones once per batch tile.  Batch partial sums are added to the store in
- * FP64 in a fixed order, so repeated calls are bitwise identical.  With Q4C_ASSEMBLE_W / _V the spinor blocks are written
- * to spin_w_dev / spin_v_dev (complex128, 4 store_len elements each). */
-int q4c_integrate_H(const q4c_plan *plan, const double *v_dev, int32_t precision, uint32_t flags,
+/* q4c_integrate_H: the selected real parts of the atom-pair store from the
+ * potential v (device, [n_points], user order, hartree) (Eq. 29 summed over
+ * batches, Eq. 31; W from Eq. 16a with the kinetic balance of Eq. 8b):
+ * store_dev[0..5 store_len) = V, Ws, Wso_x, Wso_y, Wso_z with c' applied,
+ * parts not in `parts` untouched.  precision: Q4C_PREC_* (see there; V is
+ * FP64 in every precision).  Batch partial sums are added to the store in
+ * FP64 in a fixed order, so repeated calls are bitwise identical.  With
+ * Q4C_ASSEMBLE_W / _V the spinor blocks are written to spin_w_dev /
+ * spin_v_dev (complex128, 4 store_len elements each); ASSEMBLE_W needs Ws and
+ * Wso selected, ASSEMBLE_V needs V (else Q4C_EINVAL, as for parts = 0). */
+int q4c_integrate_H(const q4c_plan *plan, const double *v_dev, int32_t precision, uint32_t parts, uint32_t flags,
                     double *store_dev, double *spin_w_dev, double *spin_v_dev, void *stream);
 
 /* density_on_grid: for coefficients C on the stored elements (device,
@@ -255,10 +272,18 @@ int q4c_integrate_H(const q4c_plan *plan, const double *v_dev, int32_t precision
  * (paper Eq. 39 on the scalar basis).  out_dev[g] (device, [n_points], user
  * order) = n_g (weight_mode 0) or w_g n_g (weight_mode 1).  With weight_mode 1
  * and C = dL/d(store), out is dL/dv: the exact adjoint of q4c_integrate_H.
- * terms selects Q4C_TERM_* (bit set). */
+ * terms selects Q4C_TERM_* (bit set).  precision: Q4C_PREC_F64 (FP64 MFMA),
+ * or Q4C_PREC_F32: the SS and SO terms (nine of the ten products) on FP32
+ * MFMA with coefficients and row values rounded to FP32, each 16-point
+ * chunk's FP32 sums over 32 rows (at most 96 products) drained into FP64:
+ * per point |error| <= gamma_98 (u = 2^-24, gamma_k = k u / (1 - k u),
+ * about 5.8e-6) times the magnitudes of its SS and SO terms (c' sum |C|
+ * |d phi_i| |d phi_j|, times |w_g| in weight mode 1), plus FP64 rounding and
+ * FP32 underflow below 2^-126; the LL term stays FP64.  Q4C_PREC_SPLIT_F32 is
+ * not offered here (Q4C_EINVAL). */
 enum { Q4C_TERM_LL = 1u, Q4C_TERM_SS = 2u, Q4C_TERM_SO = 4u, Q4C_TERM_ALL = 7u };
-int density_on_grid(const q4c_plan *plan, const double *coef_dev, uint32_t terms, int32_t weight_mode,
-                    double *out_dev, void *stream);
+int density_on_grid(const q4c_plan *plan, const double *coef_dev, uint32_t terms, int32_t precision,
+                    int32_t weight_mode, double *out_dev, void *stream);
 
 /* The paper's own Q4C Hamiltonian integrand (Sec. II, Eq. 19), evaluated on
  * the scalar functions of one component as in Eq. 29.  A plan built from the
@@ -422,9 +447,6 @@ enum {
 };
 int q4c_plan_profile(q4c_plan *plan, int enable);
 
-/* Chunks of the last split-precision q4c_integrate_H call routed to FP64 MFMA
- * and chunks in total (waits for the call to finish). */
-int q4c_plan_split_stats(const q4c_plan *plan, int64_t *fp64_chunks, int64_t *total_chunks);
 int q4c_plan_timers(q4c_plan *plan, double *ms, int64_t *launches);
 
 /* Launch shape of the contraction kernels (k_contract of q4c_integrate_H,

@@ -25,6 +25,7 @@ ACCUMULATE, ASSEMBLE_W, ASSEMBLE_V, CHECK_FINITE = 1, 2, 4, 8
 PLAN_HOST_ONLY = 1
 TERM_LL, TERM_SS, TERM_SO, TERM_ALL = 1, 2, 4, 7
 DTYPE_F64, DTYPE_F32_HILO = 0, 1
+PART_V, PART_WS, PART_WSO, PART_ALL = 1, 2, 4, 7
 PART_NAMES = ("V", "Ws", "Wso_x", "Wso_y", "Wso_z")
 
 
@@ -58,7 +59,7 @@ class _Grid(ctypes.Structure):
 
 class _Opts(ctypes.Structure):
     _fields_ = [("c_light", ctypes.c_double), ("p_max", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("staging_bytes", ctypes.c_int64), ("split_threshold", ctypes.c_double)]
+                ("staging_bytes", ctypes.c_int64)]
 
 
 class _Info(ctypes.Structure):
@@ -87,7 +88,7 @@ class _StoreLayout(ctypes.Structure):
 EXPORTS = ("q4c_plan_create", "q4c_plan_destroy", "q4c_plan_info", "q4c_plan_pairs", "q4c_plan_batches",
            "q4c_store_layout",
            "q4c_tabulate_size", "nao_tabulate", "q4c_integrate_H", "density_on_grid", "q4c_coef_from_spinor",
-           "q4c_plan_sync", "q4c_plan_profile", "q4c_plan_timers", "q4c_plan_split_stats", "q4c_status_string",
+           "q4c_plan_sync", "q4c_plan_profile", "q4c_plan_timers", "q4c_status_string",
            "q4c_last_error", "q4c_plan_create_batched", "q4c_plan_systems", "q4c_plan_set_launch",
            "q4c_plan_get_launch", "q4c_plan_autotune", "q4c_plan_set_graphs", "q4c_plan_set_ket_potential",
            "q4c_integrate_HS", "q4c_spinor_transform", "q4c_spinor_density_to_scalar", "density_gradient_on_grid",
@@ -113,13 +114,12 @@ def _load():
         lib.q4c_tabulate_size.argtypes = [vp, i64, i64, i32, ctypes.POINTER(i64)]
         lib.nao_tabulate.argtypes = [vp, i64, i64, i32, i32, vp, i64, vp]
         lib.q4c_store_layout.argtypes = [vp, ctypes.POINTER(_StoreLayout), vp, vp, vp]
-        lib.q4c_integrate_H.argtypes = [vp, vp, i32, u32, vp, vp, vp, vp]
-        lib.density_on_grid.argtypes = [vp, vp, u32, i32, vp, vp]
+        lib.q4c_integrate_H.argtypes = [vp, vp, i32, u32, u32, vp, vp, vp, vp]
+        lib.density_on_grid.argtypes = [vp, vp, u32, i32, i32, vp, vp]
         lib.q4c_coef_from_spinor.argtypes = [vp, vp, vp, vp]
         lib.q4c_plan_sync.argtypes = [vp, vp]
         lib.q4c_plan_profile.argtypes = [vp, ctypes.c_int]
         lib.q4c_plan_timers.argtypes = [vp, vp, vp]
-        lib.q4c_plan_split_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
         lib.q4c_plan_create_batched.argtypes = [i32, ctypes.POINTER(_Basis), ctypes.POINTER(_Grid),
                                                 ctypes.POINTER(_Opts), ctypes.POINTER(vp)]
         lib.q4c_plan_systems.argtypes = [vp, vp, vp, vp, vp, vp]
@@ -197,7 +197,7 @@ class Plan:
     the union is system-major and every call runs all systems at once."""
 
     def __init__(self, wl, p_max: Optional[int] = None, c_light: Optional[float] = None, host_only: bool = False,
-                 staging_bytes: int = 0, split_threshold: float = 0.0):
+                 staging_bytes: int = 0):
         lib = _load()
         systems = list(wl) if isinstance(wl, (list, tuple)) else [wl]
         first = systems[0]
@@ -216,7 +216,7 @@ class Plan:
         if p_max is None:
             p_max = int(getattr(first, "meta", {}).get("p_max", 300))
         o = _Opts(float(c_light if c_light is not None else getattr(first, "c_light", 0.0)), int(p_max),
-                  PLAN_HOST_ONLY if host_only else 0, int(staging_bytes), float(split_threshold))
+                  PLAN_HOST_ONLY if host_only else 0, int(staging_bytes))
         h = ctypes.c_void_p()
         if isinstance(wl, (list, tuple)):
             B = (_Basis * len(descs))(*[d[0] for d in descs])
@@ -293,12 +293,6 @@ class Plan:
         n = np.zeros(len(TIMER_NAMES), dtype=np.int64)
         _check(_load().q4c_plan_timers(self._h, ms.ctypes.data, n.ctypes.data))
         return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(TIMER_NAMES)}
-
-    def split_stats(self):
-        """(FP64-routed chunks, total chunks) of the last split-precision call."""
-        a, b = ctypes.c_int64(), ctypes.c_int64()
-        _check(_load().q4c_plan_split_stats(self._h, ctypes.byref(a), ctypes.byref(b)))
-        return int(a.value), int(b.value)
 
     def sync(self):
         _check(_load().q4c_plan_sync(self._h, _stream_handle()))
@@ -385,11 +379,12 @@ def nao_tabulate(plan: Plan, b0: int, b1: int, deriv: int, out, dtype: int = DTY
 
 
 def q4c_integrate_H(plan: Plan, v, precision: int = PREC_F64, flags: int = 0, store=None, spin_w=None,
-                    spin_v=None):
-    """Integrate the five real parts into `store` ([5, store_len] float64)."""
+                    spin_v=None, parts: int = PART_ALL):
+    """Integrate the selected real parts into `store` ([5, store_len] float64;
+    unselected parts keep their values)."""
     L = plan.info["store_len"]
     _check(_load().q4c_integrate_H(
-        plan.handle, _dev_ptr(v, min_numel=plan.info["n_points"], name="v"), int(precision), int(flags),
+        plan.handle, _dev_ptr(v, min_numel=plan.info["n_points"], name="v"), int(precision), int(parts), int(flags),
         _dev_ptr(store, min_numel=5 * L, name="store"),
         _dev_ptr(spin_w, min_numel=8 * L, name="spin_w") if spin_w is not None else None,
         _dev_ptr(spin_v, min_numel=8 * L, name="spin_v") if spin_v is not None else None, _stream_handle()))
@@ -466,11 +461,12 @@ def q4c_bloch_density(plan: Plan, n_parts: int, rho, k_points, k_weights, out):
     return out
 
 
-def density_on_grid(plan: Plan, coef, terms: int = TERM_ALL, weight_mode: int = 0, out=None):
+def density_on_grid(plan: Plan, coef, terms: int = TERM_ALL, weight_mode: int = 0, out=None,
+                    precision: int = PREC_F64):
     L = plan.info["store_len"]
     _check(_load().density_on_grid(plan.handle, _dev_ptr(coef, min_numel=5 * L, name="coef"), int(terms),
-                                   int(weight_mode), _dev_ptr(out, min_numel=plan.info["n_points"], name="out"),
-                                   _stream_handle()))
+                                   int(precision), int(weight_mode),
+                                   _dev_ptr(out, min_numel=plan.info["n_points"], name="out"), _stream_handle()))
     return out
 
 

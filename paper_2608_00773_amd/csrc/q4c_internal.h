@@ -132,7 +132,6 @@ struct q4c_plan {
   int32_t p_max = 300;
   int32_t flags = 0;
   int64_t staging_budget = 0;
-  double split_tau = 3e-11;
 
   // ---- independent systems (one unless built by q4c_plan_create_batched)
   int32_t n_systems = 1;
@@ -189,11 +188,9 @@ struct q4c_plan {
   double *d_om = nullptr;  // [n_active + 16] point weights w_g v_g of the current call
   double *d_ucoef = nullptr;         // ket-potential tables (q4c_plan_set_ket_potential)
   int64_t *d_shell_us_off = nullptr;
-  unsigned long long *d_chunks = nullptr;  // [64][2]: FP64-routed and total chunks of the last split call
   double *d_staging = nullptr;
   int32_t *d_flag = nullptr;
   int32_t *d_order = nullptr;      // per pass: work items sorted by cost (pass-relative indices)
-  uint64_t *d_hotmask = nullptr;   // [n_work] split modes: 16-point chunks deferred to FP64
   unsigned *d_tickets = nullptr;   // [2][n_passes][kTicketsPerLaunch] persistent-launch queues
   int n_cu = 256;                  // compute units of the plan's device
 
@@ -270,15 +267,16 @@ struct q4c_plan {
 namespace q4c {
 void set_error(const std::string &msg);
 int hip_fail(hipError_t e, const char *what);
+int fail_status(int code, const char *msg);  // set_error(msg) and return code
 
 // kernel launchers (q4c_kernels.hip)
 int launch_tabulate(const q4c_plan *p, int64_t b0, int64_t b1, int deriv, int dtype, void *out, hipStream_t s);
-int launch_integrate(const q4c_plan *p, const double *v, int precision, uint32_t flags, double *store,
-                     double *spin_w, double *spin_v, hipStream_t s);
+int launch_integrate(const q4c_plan *p, const double *v, int precision, uint32_t parts, uint32_t flags,
+                     double *store, double *spin_w, double *spin_v, hipStream_t s);
 // resident_pass >= 0: the plan's panel region already holds the W-path
 // panels of that pass (left by the previous call), which is then not tabulated
-int launch_density(const q4c_plan *p, const double *coef, uint32_t terms, int weight_mode, double *out,
-                   int64_t resident_pass, hipStream_t s);
+int launch_density(const q4c_plan *p, const double *coef, uint32_t terms, int precision, int weight_mode,
+                   double *out, int64_t resident_pass, hipStream_t s);
 int launch_integrate_hs(const q4c_plan *p, const double *v, uint32_t flags, double *hs, hipStream_t s);
 int launch_density_grad(const q4c_plan *p, const double *coef, double *out, hipStream_t s);
 // dense M, product and point sums of one pass of density_gradient_on_grid

@@ -22,7 +22,7 @@
 //  k_spinor          2x2-spinor assembly of the W and V blocks.
 //  k_density_tiles,
 //  k_density_points  density_on_grid: the transpose of the steps above
-//                    (Eq. 39): each quarter of a work item reads its
+//                    (Eq. 39): each column half of a work item reads its
 //                    coefficients from the store, contracts a_g^T C b_g at its
 //                    points on MFMA, and every point sums its partials in a
 //                    fixed order.
@@ -338,29 +338,34 @@ __global__ void k_zero_u32(unsigned *p, int64_t n) {
 }
 
 // w_g v_g for every active point (batch order); 16 zero entries after the end.
-__global__ void k_om(DevPlan d, const double *v, double *om, unsigned long long *chunks) {
-  if (blockIdx.x == 0 && threadIdx.x < 128) chunks[threadIdx.x] = 0;
+__global__ void k_om(DevPlan d, const double *v, double *om) {
   const int64_t n = d.n_active;
   for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n + 16; g += (int64_t)gridDim.x * blockDim.x)
     om[g] = g < n ? d.pw[g] * v[d.perm[g]] : 0.0;
 }
 
 // One (batch, function tile of 64): tabulate the tile's functions at all
-// points of the batch into the panel, and record for every point the largest
-// |gradient component| over the tile's functions (after the batch's panel, at
-// 4 Pp np + ti Pp + point): the split-precision routing bound reads it.  Each group of 16 points is computed
-// in lm order (few divergent harmonic branches per wave) into LDS, then
-// written out as 16 contiguous 2 KB runs.
+// points of the batch into the panel.  Each group of 8 points is computed in
+// lm order (few divergent harmonic branches per wave) into LDS, then written
+// out as contiguous runs of the tile's functions.  Panel kinds:
+//   PK_F64:   phi, d/dx, d/dy, d/dz in FP64 (4 planes of Pp np doubles)
+//   PK_HS:    phi and psi = u phi / 2 in FP64 (2 planes)
+//   PK_F32:   phi in FP64 (1 plane), then d/dx, d/dy, d/dz as FP32 planes
+//             (Pp np floats each) after it
+//   PK_SPLIT: as PK_F32, then the three lo planes fl32(x - hi)
+// Every plane uses the 4-point interleave of panel_index (FP32 planes
+// counted in floats).
+enum { PK_F64 = 0, PK_HS = 1, PK_F32 = 2, PK_SPLIT = 3 };
 constexpr int PLD = T + 1;  // padded LDS row of the panel stage
 
-template <bool HS>
+template <int KIND>
 __global__ __launch_bounds__(256) void k_panel(DevPlan d, const WorkItem *tiles, int64_t t0, int64_t nt,
                                                double *panel) {
+  constexpr bool HS = KIND == PK_HS;
   constexpr int NQ = HS ? 2 : 4;  // components: phi, psi (H/S) or phi and its gradient
   constexpr int CP = 8;           // points per chunk: a small stage keeps 7 workgroups on a CU
   __shared__ TileMeta M;
   __shared__ double st[NQ * CP * PLD];
-  __shared__ double s_gx[4][CP];
   const WorkItem it = tiles[t0 + xcd_map(blockIdx.x, nt)];
   const int b = it.batch;
   const int g0 = d.batch_pt_off[b], P = d.batch_pt_off[b + 1] - g0;
@@ -371,6 +376,8 @@ __global__ __launch_bounds__(256) void k_panel(DevPlan d, const WorkItem *tiles,
   load_tile_meta(d, M, f0, n, r0);
   __syncthreads();
   double *pb = panel + d.panel_off[b];
+  float *pf = reinterpret_cast<float *>(pb + (int64_t)Pp * np);  // FP32 planes (PK_F32, PK_SPLIT)
+  const int64_t fplane = (int64_t)Pp * np;
   for (int g8 = 0; g8 < Pp; g8 += CP) {
     for (int e = threadIdx.x; e < T * CP; e += 256) {
       const int k = e / CP, pt = e % CP;
@@ -390,20 +397,6 @@ __global__ __launch_bounds__(256) void k_panel(DevPlan d, const WorkItem *tiles,
       }
     }
     __syncthreads();
-    if (!HS) {
-      // largest |d phi / d x_a| per point over the tile's functions: thread
-      // (pt, pair of functions), then the 8 pairs of a wave, then the waves
-      const int pt = threadIdx.x % CP, fg = threadIdx.x / CP;
-      double m = 0.0;
-#pragma unroll
-      for (int q = 1; q < 4; ++q)
-#pragma unroll
-        for (int k = 0; k < 2; ++k) m = fmax(m, fabs(st[(q * CP + pt) * PLD + 2 * fg + k]));
-      m = fmax(m, __shfl_xor(m, 8));
-      m = fmax(m, __shfl_xor(m, 16));
-      m = fmax(m, __shfl_xor(m, 32));
-      if ((threadIdx.x & 63) < CP) s_gx[threadIdx.x >> 6][pt] = m;
-    }
     // (q, point quad) runs: rows r0 .. r0 + nrow - 1, 4 points each, contiguous
 #pragma unroll
     for (int q = 0; q < NQ; ++q)
@@ -411,104 +404,75 @@ __global__ __launch_bounds__(256) void k_panel(DevPlan d, const WorkItem *tiles,
       for (int p4 = 0; p4 < CP / 4; ++p4) {
         const int e = threadIdx.x;  // 256 = 64 rows x 4 points
         const int il = e >> 2, pp = e & 3;
-        if (il < nrow)
-          pb[((int64_t)(q * (Pp >> 2) + (g8 >> 2) + p4) * np + r0 + il) * 4 + pp] = st[(q * CP + 4 * p4 + pp) * PLD + il];
+        if (il < nrow) {
+          const double x = st[(q * CP + 4 * p4 + pp) * PLD + il];
+          if (KIND == PK_F64 || KIND == PK_HS || q == 0) {
+            pb[((int64_t)(q * (Pp >> 2) + (g8 >> 2) + p4) * np + r0 + il) * 4 + pp] = x;
+          } else {
+            const int64_t o = ((int64_t)((q - 1) * (Pp >> 2) + (g8 >> 2) + p4) * np + r0 + il) * 4 + pp;
+            const float hi = (float)x;
+            pf[o] = hi;
+            if (KIND == PK_SPLIT) pf[3 * fplane + o] = (float)(x - (double)hi);
+          }
+        }
       }
-    __syncthreads();  // s_gx written; st consumed
-    if (!HS && threadIdx.x < CP)
-      pb[(int64_t)4 * Pp * np + (int64_t)it.ti * Pp + g8 + threadIdx.x] =
-          fmax(fmax(s_gx[0][threadIdx.x], s_gx[1][threadIdx.x]), fmax(s_gx[2][threadIdx.x], s_gx[3][threadIdx.x]));
+    __syncthreads();  // st consumed
   }
 }
 
-// Modes of the forward contraction: FP64; split (hi+lo FP32 operands) and
-// single FP32 operands for the W parts (V stays FP64), whose chunks with large
-// terms are deferred; MODE_HOT adds the deferred chunks' W parts in FP64.
-enum { MODE_F64 = 0, MODE_SPLIT = 1, MODE_F32 = 2, MODE_HOT = 3 };
-
-
-// Split modes: a chunk's W contribution is bounded by c' 48 A B with A the
-// largest |grad phi| of the tile's rows and B the largest |w v grad phi| of
-// its columns over the chunk's 16 points (16 points x 3 products per term);
-// with FP32 rounding 2^-24 that bounds the FP32 error of the chunk.
-constexpr double kU32 = 5.9604644775390625e-08;
+// Modes of the FP64 contraction: all five parts, or V alone (phi only: the
+// V part of the split precisions, and V-only calls).
+enum { MODE_F64 = 0, MODE_V = 1 };
 
 // Work item positions 0..nw-1 of a pass map to work items w0 + order[w0 + pos]
 // (order != NULL: cost-sorted) or w0 + pos.  tickets == NULL: one workgroup
 // per position; otherwise a persistent loop (next_item).
-//
-// Split modes (MODE_SPLIT, MODE_F32): V accumulates in FP64, the W parts in
-// FP32; a 16-point chunk whose W bound exceeds tau skips its W products here
-// and sets bit k0/16 of hotmask[w] (P <= 1024); MODE_HOT then runs those chunks'
-// W products in FP64 and adds them to the staged elements.
 template <int MODE, bool PERSIST>
 __global__ __launch_bounds__(NT, 2) void k_contract(DevPlan d, const WorkItem *work, const int32_t *order,
                                                     int64_t w0, int64_t nw, const double *om, const double *panel,
-                                                    double *staging, double tau, unsigned long long *chunks,
-                                                    unsigned *tickets, uint64_t *hotmask) {
-  constexpr bool SPLIT = MODE == MODE_SPLIT || MODE == MODE_F32;
-  constexpr bool HOTK = MODE == MODE_HOT;
-  __shared__ double sa[32 * DROW], sb[32 * DROW];
-  __shared__ double s_om[16];
+                                                    double *staging, unsigned *tickets) {
+  constexpr bool VONLY = MODE == MODE_V;
+  constexpr int NQ = VONLY ? 1 : 4;        // panel components multiplied
+  constexpr int NP = VONLY ? 1 : 5;        // parts accumulated
+  // Chunks of CH points in two LDS buffers, the next chunk's DMA in flight
+  // while this one is multiplied (one barrier per chunk)
+  constexpr int CH = VONLY ? 32 : 8;
+  constexpr int RPQ = CH / 2;              // LDS rows per component
+  constexpr int BUFD = NQ * RPQ * DROW;    // doubles per chunk image
+  __shared__ double sa[2 * BUFD], sb[2 * BUFD];
   __shared__ int64_t s_pos;
-  unsigned long long n_hot = 0, n_all = 0;
   int64_t pos = PERSIST ? next_item(tickets, nw, order != nullptr, &s_pos)
                         : (order ? (int64_t)blockIdx.x : xcd_map(blockIdx.x, nw));
   while (!PERSIST || pos < nw) {
   const int64_t wi = w0 + (order ? order[w0 + pos] : pos);
   const WorkItem it = work[wi];
-  const uint64_t hmask_in = HOTK ? hotmask[wi] : 0;  // MODE_HOT: chunks to add
-  uint64_t hmask = 0;                               // split modes: deferred chunks
   const int b = it.batch;
   const int g0 = d.batch_pt_off[b], P = d.batch_pt_off[b + 1] - g0;
   const int f0 = d.batch_fn_off[b], n = d.batch_fn_off[b + 1] - f0;
   const int sbase = d.batch_slot_off[b];
   const int r0 = it.ti * T, c0 = it.tj * T;
-  const bool diag = it.ti == it.tj;
   const int Pp = (int)pad16(P), np = (int)pad16(n);
   const double *pb = panel + d.panel_off[b];
   const int64_t plane = (int64_t)Pp * np;
   const int tid = threadIdx.x;
   // wave index as a scalar: conditions derived from it stay uniform
   const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  (void)diag;
   const int li16 = lane & 15, lk = lane >> 4;
   int brow[4], bcol[4];
   bool act[4];
   wave_blocks(r0, c0, n, wave, brow, bcol, act);
 
-  dbl4 acc[4][5];
+  dbl4 acc[4][NP];
 #pragma unroll
   for (int sl = 0; sl < 4; ++sl)
 #pragma unroll
-    for (int q = 0; q < 5; ++q) acc[sl][q] = dbl4{0.0, 0.0, 0.0, 0.0};
-  // FP32 accumulators of the four W parts (split modes)
-  flt4 accf[4][4];
-  if (SPLIT) {
-#pragma unroll
-    for (int sl = 0; sl < 4; ++sl)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) accf[sl][q] = flt4{0.f, 0.f, 0.f, 0.f};
-  }
+    for (int q = 0; q < NP; ++q) acc[sl][q] = dbl4{0.0, 0.0, 0.0, 0.0};
 
   const double cp = d.cprime;
-  // Chunks of 8 points in two LDS buffers, the next chunk's DMA in flight
-  // while this one is multiplied (one barrier per chunk); the split modes'
-  // FP64 routing is decided per 16 points.  MODE_HOT: 16-point chunks, one
-  // buffer, only the deferred ones.
-  constexpr int CH = HOTK ? 16 : 8;
-  constexpr bool DB = !HOTK;  // double-buffered chunk images
-  constexpr int RPQ = CH / 2;              // LDS rows per component
-  constexpr int BUFD = 4 * RPQ * DROW;     // doubles per chunk image
-  bool hot = true;  // W parts of the current 16 points on FP64 MFMA
-  // Double-buffered path: the global loads a chunk needs besides its image
-  // (w v at its points; the split modes' bound inputs of its 16 points) are
-  // issued one chunk ahead, with the next image's DMA, so that nothing
-  // consumed between the barrier and the last MFMA of a chunk waits on
-  // loads still in flight.
-  double omn[CH / 4];  // w v at points 4 ks + lk of the next chunk
-  double ga = 0.0, gb = 0.0, gw = 0.0;  // bound inputs of the next 16 points
-  const double *gmx = pb + 4 * plane;  // per-point gradient maxima of the row tiles
+  // w v at the points this lane's K index visits in the next chunk, loaded a
+  // chunk ahead with the next image's DMA, so that nothing consumed between
+  // the barrier and the last MFMA of a chunk waits on loads in flight
+  double omn[CH / 4];
   auto load_om = [&](int k) {
 #pragma unroll
     for (int ks = 0; ks < CH / 4; ++ks) {
@@ -516,85 +480,40 @@ __global__ __launch_bounds__(NT, 2) void k_contract(DevPlan d, const WorkItem *w
       omn[ks] = pt < P ? om[g0 + pt] : 0.0;
     }
   };
-  auto load_bound = [&](int k) {
-    // lanes 0..15: row tile maxima; lanes 16..31: column tile maxima and w v
-    ga = gb = gw = 0.0;
-    if (lane < 16) {
-      ga = gmx[(int64_t)it.ti * Pp + k + lane];
-    } else if (lane < 32 && k + lane - 16 < P) {
-      gb = gmx[(int64_t)it.tj * Pp + k + lane - 16];
-      gw = om[g0 + k + lane - 16];
-    }
-  };
-  if (DB) {
-    load_om(0);
-    if (SPLIT) load_bound(0);
-    dma_chunk<NT, CH>(pb, plane, np, r0, 0, sa);
-    dma_chunk<NT, CH>(pb, plane, np, c0, 0, sb);
-  }
+  load_om(0);
+  dma_chunk<NT, CH, T, DROW, NQ>(pb, plane, np, r0, 0, sa);
+  dma_chunk<NT, CH, T, DROW, NQ>(pb, plane, np, c0, 0, sb);
   for (int k0 = 0; k0 < Pp; k0 += CH) {
-    if (HOTK && !((hmask_in >> (k0 >> 4)) & 1)) continue;  // WG-uniform
-    const int bo = DB ? ((k0 / CH) & 1) * BUFD : 0;  // this chunk's buffer
-    double omv[CH / 4];  // FP64 path: w v at points 4 ks + lk of this chunk
-    double va = 0.0, vb = 0.0;  // split modes: bound inputs of this lane
-    if (!DB) {
-      __syncthreads();  // previous chunk's operands consumed
-      if (tid < 16) s_om[tid] = k0 + tid < P ? om[g0 + k0 + tid] : 0.0;
-      dma_chunk<NT, CH>(pb, plane, np, r0, k0 >> 2, sa);
-      dma_chunk<NT, CH>(pb, plane, np, c0, k0 >> 2, sb);
-      __builtin_amdgcn_s_waitcnt(0);  // this thread's LDS DMA loads have landed
-      __syncthreads();                // the chunk and s_om are visible
-    } else {
-      __builtin_amdgcn_s_waitcnt(0);  // this thread's loads of this chunk have landed
-      __syncthreads();                // ... everyone's; the previous chunk is consumed
+    const int bo = ((k0 / CH) & 1) * BUFD;  // this chunk's buffer
+    __builtin_amdgcn_s_waitcnt(0);  // this thread's loads of this chunk have landed
+    __syncthreads();                // ... everyone's; the previous chunk is consumed
+    double omv[CH / 4];
 #pragma unroll
-      for (int ks = 0; ks < CH / 4; ++ks) omv[ks] = omn[ks];
-      if (SPLIT && (k0 & 15) == 0) {
-        va = ga;
-        vb = gb * fabs(gw);
-      }
-      if (k0 + CH < Pp) {
-        const int nbo = BUFD - bo;
-        load_om(k0 + CH);
-        if (SPLIT && ((k0 + CH) & 15) == 0) load_bound(k0 + CH);
-        dma_chunk<NT, CH>(pb, plane, np, r0, (k0 + CH) >> 2, sa + nbo);
-        dma_chunk<NT, CH>(pb, plane, np, c0, (k0 + CH) >> 2, sb + nbo);
-      }
+    for (int ks = 0; ks < CH / 4; ++ks) omv[ks] = omn[ks];
+    if (k0 + CH < Pp) {
+      const int nbo = BUFD - bo;
+      load_om(k0 + CH);
+      dma_chunk<NT, CH, T, DROW, NQ>(pb, plane, np, r0, (k0 + CH) >> 2, sa + nbo);
+      dma_chunk<NT, CH, T, DROW, NQ>(pb, plane, np, c0, (k0 + CH) >> 2, sb + nbo);
     }
     const double *ca = sa + bo, *cb = sb + bo;
-    if (SPLIT && (k0 & 15) == 0) {
-      // bound of the 16 points k0 .. k0+15: A = largest |gradient component|
-      // of the row tile, B = largest |w v gradient component| of the column
-      // tile, from the panel's per-point maxima; every wave forms the same
-      // values, so the decision is uniform over the workgroup
-#pragma unroll
-      for (int off = 1; off < 64; off <<= 1) {
-        va = fmax(va, __shfl_xor(va, off));
-        vb = fmax(vb, __shfl_xor(vb, off));
-      }
-      // equal in every lane after the reductions; as a scalar the branches stay uniform
-      hot = __builtin_amdgcn_readfirstlane(kU32 * cp * 48.0 * va * vb > tau ? 1 : 0) != 0;
-      n_hot += hot ? 1 : 0;
-      n_all += 1;
-      if (hot) hmask |= (uint64_t)1 << (k0 >> 4);
-    }
 #pragma unroll
     for (int ks = 0; ks < CH / 4; ++ks) {
       // K index lk of step ks is point 4 ks + lk of the chunk; the column
       // operand takes its weight w v there (the weighting of Eq. 29)
       const int rowk = 2 * ks + (lk >> 1), ck = lk & 1;
-      const double omk = DB ? omv[ks] : s_om[4 * ks + lk];
+      const double omk = omv[ks];
 #pragma unroll
       for (int sl = 0; sl < 4; ++sl) {
         if (!act[sl]) continue;  // wave-uniform
-        double av[4], bv[4];
+        double av[NQ], bv[NQ];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < NQ; ++q) {
           av[q] = ca[(q * RPQ + rowk) * DROW + 2 * (brow[sl] + li16) + ck];
           bv[q] = cb[(q * RPQ + rowk) * DROW + 2 * (bcol[sl] + li16) + ck] * omk;
         }
-        if (!HOTK) acc[sl][0] = mfma64(av[0], bv[0], acc[sl][0]);
-        if (MODE == MODE_F64 || HOTK) {
+        acc[sl][0] = mfma64(av[0], bv[0], acc[sl][0]);
+        if (!VONLY) {
           acc[sl][1] = mfma64(av[1], bv[1], acc[sl][1]);
           acc[sl][2] = mfma64(av[2], bv[3], acc[sl][2]);
           acc[sl][3] = mfma64(av[3], bv[1], acc[sl][3]);
@@ -604,49 +523,6 @@ __global__ __launch_bounds__(NT, 2) void k_contract(DevPlan d, const WorkItem *w
           acc[sl][3] = mfma64(-av[1], bv[3], acc[sl][3]);
           acc[sl][4] = mfma64(-av[2], bv[1], acc[sl][4]);
           acc[sl][1] = mfma64(av[3], bv[3], acc[sl][1]);
-        } else if (hot) {
-          // deferred to MODE_HOT
-        } else if (MODE == MODE_F32) {
-          float af[4], bf[4];
-#pragma unroll
-          for (int q = 1; q < 4; ++q) {
-            af[q] = (float)av[q];
-            bf[q] = (float)bv[q];
-          }
-          accf[sl][0] = mfma32(af[1], bf[1], accf[sl][0]);
-          accf[sl][1] = mfma32(af[2], bf[3], accf[sl][1]);
-          accf[sl][2] = mfma32(af[3], bf[1], accf[sl][2]);
-          accf[sl][3] = mfma32(af[1], bf[2], accf[sl][3]);
-          accf[sl][0] = mfma32(af[2], bf[2], accf[sl][0]);
-          accf[sl][1] = mfma32(-af[3], bf[2], accf[sl][1]);
-          accf[sl][2] = mfma32(-af[1], bf[3], accf[sl][2]);
-          accf[sl][3] = mfma32(-af[2], bf[1], accf[sl][3]);
-          accf[sl][0] = mfma32(af[3], bf[3], accf[sl][0]);
-        } else if (MODE == MODE_SPLIT) {
-          // hi + lo split: x = hi + lo with hi = fl(x), lo = fl(x - hi);
-          // x y ~ hi_x hi_y + hi_x lo_y + lo_x hi_y (lo_x lo_y dropped)
-          float ah[4], al[4], bh[4], bl[4];
-#pragma unroll
-          for (int q = 1; q < 4; ++q) {
-            ah[q] = (float)av[q];
-            al[q] = (float)(av[q] - (double)ah[q]);
-            bh[q] = (float)bv[q];
-            bl[q] = (float)(bv[q] - (double)bh[q]);
-          }
-#define SPLIT3(ACC, AI, BI, SG)                                  \
-  ACC = mfma32(SG ah[AI], bh[BI], ACC);                          \
-  ACC = mfma32(SG ah[AI], bl[BI], ACC);                          \
-  ACC = mfma32(SG al[AI], bh[BI], ACC);
-          SPLIT3(accf[sl][0], 1, 1, +)
-          SPLIT3(accf[sl][0], 2, 2, +)
-          SPLIT3(accf[sl][0], 3, 3, +)
-          SPLIT3(accf[sl][1], 2, 3, +)
-          SPLIT3(accf[sl][1], 3, 2, -)
-          SPLIT3(accf[sl][2], 3, 1, +)
-          SPLIT3(accf[sl][2], 1, 3, -)
-          SPLIT3(accf[sl][3], 1, 2, +)
-          SPLIT3(accf[sl][3], 2, 1, -)
-#undef SPLIT3
         }
       }
     }
@@ -655,50 +531,214 @@ __global__ __launch_bounds__(NT, 2) void k_contract(DevPlan d, const WorkItem *w
 #pragma unroll
   for (int sl = 0; sl < 4; ++sl) {
     if (!act[sl]) continue;
-    const int cb = c0 + bcol[sl];
-    const int lj = cb + li16;
+    const int cbk = c0 + bcol[sl];
+    const int lj = cbk + li16;
     if (lj >= n) continue;
     const SlotInfo sj = slot_of(d, f0, sbase, lj);
     const int rb = r0 + brow[sl];
-    const bool upper = rb < cb;
+    const bool upper = rb < cbk;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      // V and, in FP64 modes, the W parts: FP64 MFMA rows lk + 4 r
+      // FP64 MFMA rows lk + 4 r
       const int li = rb + d_row_f64(lk, r);
-      if (li < n && !(HOTK && hmask_in == 0)) {
+      if (li < n) {
         const SlotInfo si = slot_of(d, f0, sbase, li);
         double vals[5];
         vals[0] = acc[sl][0][r];
 #pragma unroll
-        for (int q = 1; q < 5; ++q) vals[q] = cp * acc[sl][q][r];
-        if (MODE == MODE_F64)
-          stage_store<0, 5>(staging, si, sj, li, lj, upper, vals);
-        else if (HOTK)
-          stage_add<1, 5>(staging, si, sj, li, lj, upper, vals + 1);
-        else
-          stage_store<0, 1>(staging, si, sj, li, lj, upper, vals);
+        for (int q = 1; q < NP; ++q) vals[q] = cp * acc[sl][q][r];
+        stage_store<0, NP>(staging, si, sj, li, lj, upper, vals);
       }
-      if (SPLIT) {
-        // the W parts from the FP32 accumulators: FP32 MFMA rows 4 lk + r
-        const int lf = rb + d_row_f32(lk, r);
-        if (lf < n) {
-          const SlotInfo sf = slot_of(d, f0, sbase, lf);
-          double w[4];
+    }
+  }
+  if (!PERSIST) break;
+  pos = next_item(tickets, nw, order != nullptr, &s_pos);
+  }
+}
+
+// The four W parts on FP32 MFMA (precisions F32 and SPLIT_F32), from the FP32
+// gradient planes of a PK_F32 / PK_SPLIT panel; V runs beside it on FP64
+// (k_contract<MODE_V>).  Same work items, wave blocks and staging as
+// k_contract.  Per 16 points, every element's FP32 partial sum (of at most
+// 48 products: 16 points x 3) is converted to FP64 and added to an FP64
+// running sum, then restarted from zero, so FP32 rounding never accumulates
+// beyond one 16-point chunk: with unit roundoff u = 2^-24 each element's
+// error is at most gamma_52 = 52 u / (1 - 52 u) times the sum over all
+// points of the magnitudes of its terms (operands rounded to FP32 up to three
+// times, 48 products and additions), plus FP64 rounding and the loss of
+// relative precision of values below FP32's normal range (the far tails of
+// tight functions).  SPLIT: each operand x enters as hi = fl32(x) and
+// lo = fl32(x - hi), and every product as hi hi + hi lo + lo hi (three FP32
+// MFMAs): the operands' rounding drops to about 2^-48, and a 16-point partial
+// sum holds up to 144 products (gamma_150).
+template <bool SPLIT, bool PERSIST>
+__global__ __launch_bounds__(NT, 2) void k_contract_w(DevPlan d, const WorkItem *work, const int32_t *order,
+                                                      int64_t w0, int64_t nw, const double *om,
+                                                      const double *panel, double *staging, unsigned *tickets) {
+  // Chunks of CH points; an image row is one point quad of 64 functions
+  // (1 KB of floats, in the panel's own order: element (pt, f) of the quad at
+  // 4 f + pt % 4), rows (component q, quad) for q = 0..2 (d/dx, d/dy, d/dz),
+  // then, for SPLIT, the same rows of the lo planes.
+  constexpr int CH = SPLIT ? 8 : 16;
+  constexpr int NQR = CH / 4;                  // quads per chunk
+  constexpr int NPL = SPLIT ? 6 : 3;           // FP32 planes read
+  constexpr int ROWF = 4 * T;                  // floats per image row
+  constexpr int BUFF = NPL * NQR * ROWF;       // floats per chunk image
+  constexpr int FLUSH = 16;                    // points per FP32 partial sum
+  __shared__ __attribute__((aligned(16))) float fa[2 * BUFF], fb[2 * BUFF];
+  __shared__ int64_t s_pos;
+  int64_t pos = PERSIST ? next_item(tickets, nw, order != nullptr, &s_pos)
+                        : (order ? (int64_t)blockIdx.x : xcd_map(blockIdx.x, nw));
+  while (!PERSIST || pos < nw) {
+  const int64_t wi = w0 + (order ? order[w0 + pos] : pos);
+  const WorkItem it = work[wi];
+  const int b = it.batch;
+  const int g0 = d.batch_pt_off[b], P = d.batch_pt_off[b + 1] - g0;
+  const int f0 = d.batch_fn_off[b], n = d.batch_fn_off[b + 1] - f0;
+  const int sbase = d.batch_slot_off[b];
+  const int r0 = it.ti * T, c0 = it.tj * T;
+  const int Pp = (int)pad16(P), np = (int)pad16(n);
+  const int64_t fplane = (int64_t)Pp * np;
+  const float *pf = reinterpret_cast<const float *>(panel + d.panel_off[b] + fplane);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int li16 = lane & 15, lk = lane >> 4;
+  int brow[4], bcol[4];
+  bool act[4];
+  wave_blocks(r0, c0, n, wave, brow, bcol, act);
+
+  flt4 accf[4][4];   // FP32 partial sums of the current 16 points
+  dbl4 accw[4][4];   // FP64 running sums
 #pragma unroll
-          for (int q = 0; q < 4; ++q) w[q] = cp * (double)accf[sl][q][r];
-          stage_store<1, 5>(staging, sf, sj, lf, lj, upper, w);
+  for (int sl = 0; sl < 4; ++sl)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      accf[sl][q] = flt4{0.f, 0.f, 0.f, 0.f};
+      accw[sl][q] = dbl4{0.0, 0.0, 0.0, 0.0};
+    }
+  // LDS DMA of one chunk of 64 functions from row0 (a tile): image row r =
+  // (plane pl, quad qd) is the 1 KB run of plane pl (hi d/dx, d/dy, d/dz,
+  // then the lo planes) at point quad quad0 + qd, 16 bytes (4 points of one
+  // function) per lane.  Functions at or beyond np are not loaded (their
+  // blocks are never multiplied).
+  auto dma = [&](int row0, int quad0, float *dst) {
+    const bool ok = row0 + lane < np;
+#pragma unroll
+    for (int k = 0; k < NPL * NQR / 4; ++k) {
+      const int r = wave + 4 * k;
+      const int pl = r / NQR, qd = r % NQR;
+      if (ok)
+        __builtin_amdgcn_global_load_lds(
+            (const void *)(pf + (int64_t)pl * fplane + ((int64_t)(quad0 + qd) * np + row0 + lane) * 4),
+            (lds_void *)(dst + r * ROWF), 16, 0, 0);
+    }
+  };
+  double omn[CH / 4];
+  auto load_om = [&](int k) {
+#pragma unroll
+    for (int ks = 0; ks < CH / 4; ++ks) {
+      const int pt = k + 4 * ks + lk;
+      omn[ks] = pt < P ? om[g0 + pt] : 0.0;
+    }
+  };
+  load_om(0);
+  dma(r0, 0, fa);
+  dma(c0, 0, fb);
+  for (int k0 = 0; k0 < Pp; k0 += CH) {
+    const int bo = ((k0 / CH) & 1) * BUFF;
+    __builtin_amdgcn_s_waitcnt(0);  // this thread's loads of this chunk have landed
+    __syncthreads();                // ... everyone's; the previous chunk is consumed
+    double omv[CH / 4];
+#pragma unroll
+    for (int ks = 0; ks < CH / 4; ++ks) omv[ks] = omn[ks];
+    if (k0 + CH < Pp) {
+      load_om(k0 + CH);
+      dma(r0, (k0 + CH) >> 2, fa + BUFF - bo);
+      dma(c0, (k0 + CH) >> 2, fb + BUFF - bo);
+    }
+    const float *ca = fa + bo, *cb = fb + bo;
+#pragma unroll
+    for (int ks = 0; ks < CH / 4; ++ks) {
+      const double omk = omv[ks];
+#pragma unroll
+      for (int sl = 0; sl < 4; ++sl) {
+        if (!act[sl]) continue;  // wave-uniform
+        // A[i][k] = component q of row function brow + i at point 4 ks + k;
+        // B[k][j] = w v times component q of column function bcol + j there
+        float ah[3], bh[3], al[3], bl[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          ah[q] = ca[(q * NQR + ks) * ROWF + 4 * (brow[sl] + li16) + lk];
+          const float bx = cb[(q * NQR + ks) * ROWF + 4 * (bcol[sl] + li16) + lk];
+          if (SPLIT) {
+            al[q] = ca[((3 + q) * NQR + ks) * ROWF + 4 * (brow[sl] + li16) + lk];
+            const float bxl = cb[((3 + q) * NQR + ks) * ROWF + 4 * (bcol[sl] + li16) + lk];
+            const double x = omk * ((double)bx + (double)bxl);
+            bh[q] = (float)x;
+            bl[q] = (float)(x - (double)bh[q]);
+          } else {
+            bh[q] = (float)(omk * (double)bx);
+          }
+        }
+        // parts: Ws = dx dx + dy dy + dz dz; Wso_x = dy dz - dz dy;
+        // Wso_y = dz dx - dx dz; Wso_z = dx dy - dy dx (row x column)
+#define W32(ACC, AI, BI, SG)                                        \
+  ACC = mfma32(SG ah[AI], bh[BI], ACC);                             \
+  if (SPLIT) {                                                      \
+    ACC = mfma32(SG ah[AI], bl[BI], ACC);                           \
+    ACC = mfma32(SG al[AI], bh[BI], ACC);                           \
+  }
+        W32(accf[sl][0], 0, 0, +)
+        W32(accf[sl][1], 1, 2, +)
+        W32(accf[sl][2], 2, 0, +)
+        W32(accf[sl][3], 0, 1, +)
+        W32(accf[sl][0], 1, 1, +)
+        W32(accf[sl][1], 2, 1, -)
+        W32(accf[sl][2], 0, 2, -)
+        W32(accf[sl][3], 1, 0, -)
+        W32(accf[sl][0], 2, 2, +)
+#undef W32
+      }
+    }
+    if (((k0 + CH) % FLUSH) == 0 || k0 + CH >= Pp) {
+      // the 16-point FP32 partial sums join the FP64 running sums
+#pragma unroll
+      for (int sl = 0; sl < 4; ++sl) {
+        if (!act[sl]) continue;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) accw[sl][q][r] += (double)accf[sl][q][r];
+          accf[sl][q] = flt4{0.f, 0.f, 0.f, 0.f};
         }
       }
     }
   }
-  if (SPLIT && threadIdx.x == 0) hotmask[wi] = hmask;
+  const double cp = d.cprime;
+#pragma unroll
+  for (int sl = 0; sl < 4; ++sl) {
+    if (!act[sl]) continue;
+    const int cbk = c0 + bcol[sl];
+    const int lj = cbk + li16;
+    if (lj >= n) continue;
+    const SlotInfo sj = slot_of(d, f0, sbase, lj);
+    const int rb = r0 + brow[sl];
+    const bool upper = rb < cbk;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      // FP32 MFMA rows 4 lk + r
+      const int lf = rb + d_row_f32(lk, r);
+      if (lf < n) {
+        const SlotInfo sf = slot_of(d, f0, sbase, lf);
+        double w[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) w[q] = cp * accw[sl][q][r];
+        stage_store<1, 5>(staging, sf, sj, lf, lj, upper, w);
+      }
+    }
+  }
   if (!PERSIST) break;
   pos = next_item(tickets, nw, order != nullptr, &s_pos);
-  }
-  if (SPLIT && threadIdx.x == 0) {
-    const int slot = (int)(blockIdx.x & 63);
-    atomicAdd(&chunks[2 * slot], n_hot);
-    atomicAdd(&chunks[2 * slot + 1], n_all);
   }
 }
 
@@ -711,7 +751,7 @@ __global__ __launch_bounds__(NT, 2) void k_contract(DevPlan d, const WorkItem *w
 __global__ __launch_bounds__(256) void k_reduce(DevPlan d, int64_t r0, const int32_t *red_pair,
                                                 const uint8_t *red_first, const int64_t *red_inc_off,
                                                 const int64_t *inc_src, const double *staging, double *store,
-                                                int accumulate, int nq) {
+                                                int accumulate, int nq, unsigned part_mask) {
   __shared__ int64_t s_src[256];
   const int64_t r = r0 + blockIdx.x;
   const int p = red_pair[r];
@@ -727,7 +767,7 @@ __global__ __launch_bounds__(256) void k_reduce(DevPlan d, int64_t r0, const int
     for (int j = 0; j < 4; ++j) {
       const int e = e0 + j * 256 + threadIdx.x;
       sum[j] = 0.0;
-      if (e < m && add) {
+      if (e < m && add && ((part_mask >> (e / blk)) & 1)) {
         const int q = e / blk;
         sum[j] = store[q * d.store_len + po + (e - q * blk)];
       }
@@ -762,7 +802,7 @@ __global__ __launch_bounds__(256) void k_reduce(DevPlan d, int64_t r0, const int
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int e = e0 + j * 256 + threadIdx.x;
-      if (e < m) {
+      if (e < m && ((part_mask >> (e / blk)) & 1)) {
         const int q = e / blk;
         store[q * d.store_len + po + (e - q * blk)] = sum[j];
       }
@@ -770,13 +810,13 @@ __global__ __launch_bounds__(256) void k_reduce(DevPlan d, int64_t r0, const int
   }
 }
 
-// Pairs no batch touches are zero unless accumulating.
-__global__ void k_zero_pairs(DevPlan d, const int32_t *pairs, double *store, int nq) {
+// Pairs no batch touches are zero unless accumulating (selected parts).
+__global__ void k_zero_pairs(DevPlan d, const int32_t *pairs, double *store, int nq, unsigned part_mask) {
   const int p = pairs[blockIdx.x];
   const int64_t blk = (int64_t)d.pair_na[p] * d.pair_nb[p];
   for (int64_t e = threadIdx.x; e < nq * blk; e += blockDim.x) {
     const int q = (int)(e / blk);
-    store[q * d.store_len + d.pair_off[p] + (e - q * blk)] = 0.0;
+    if ((part_mask >> q) & 1) store[q * d.store_len + d.pair_off[p] + (e - q * blk)] = 0.0;
   }
 }
 
@@ -818,197 +858,296 @@ __global__ void k_spinor(DevPlan d, const double *store, double *spin_w, double 
 // Adjoint / density
 // ---------------------------------------------------------------------------
 
-// The adjoint runs per quarter of a work item: a 32 x 32 block of the
-// batch's coefficient matrix (rows ti*64 + 32 rh .., columns tj*64 + 32 ch ..),
-// four waves with one 16 x 16 block each.  Positions 4 w + qd, qd = 2 rh + ch.
+// The adjoint runs per column half of a work item: the tile's 64 rows and 32
+// of its columns (half h: columns tj*64 + 32 h ..), four waves, each with 32
+// rows and 16 columns.  Positions 2 w + h.
 constexpr int NTD = 256;
-constexpr int QW = 32;              // functions per side of a quarter
-// LDS image of one 16-point chunk of 32 functions (layout of dma_chunk): row
-// (q, u) every RSQ doubles; 2 mod 16, so 16 lanes reading 16 consecutive
-// points of one function hit distinct banks
-constexpr int RSQ = 2 * QW + 2;
-constexpr int QIMG = 4 * 8 * RSQ;   // doubles per image: 4 components x 8 point pairs
+// LDS image of one 16-point chunk of the 64 row functions (layout of
+// dma_chunk): row (q, u) every RSA doubles; 2 mod 16, so 16 lanes reading 16
+// consecutive points of one function hit distinct banks
+constexpr int RSA = 2 * T + 2;
+constexpr int AIMG = 4 * 8 * RSA;   // doubles per image: 4 components x 8 point pairs
 
-// A quarter has work iff its rows and columns start inside the batch's n
-// functions and it is not below the diagonal of a diagonal tile.
-__device__ __forceinline__ bool quarter_valid(const WorkItem &it, int qd, int n) {
-  const int rh = qd >> 1, ch = qd & 1;
-  return it.ti * T + 32 * rh < n && it.tj * T + 32 * ch < n && !(it.ti == it.tj && rh > ch);
-}
+// A column half has work iff its columns start inside the batch's n functions.
+__device__ __forceinline__ bool half_valid(const WorkItem &it, int h, int n) { return it.tj * T + 32 * h < n; }
 
-// partial[g] of quarter qd (P doubles at 4 work_part_off[w] + qd P) = sum over
-// its stored elements ij of the selected terms at point g:
+// partial[g] of half h (P doubles at 2 work_part_off[w] + h P) = sum over its
+// stored elements ij of the selected terms at point g:
 //   C^V phi_i phi_j + c' C^Ws grad phi_i . grad phi_j + c' sum_m C^m (grad phi_i x grad phi_j)_m
-// (Eq. 39 on the scalar basis).  Per wave, the 16 x 16 coefficient block sits
-// in registers as the MFMA's first operand (5 parts x 4 K steps of 4 rows),
-// and per 16-point chunk four accumulators collect (C^T Y) grouped by the
-// column component Z they are multiplied with afterwards:
+// (Eq. 39 on the scalar basis).  Per wave, the 32 x 16 coefficient block
+// sits in registers as the MFMA's first operand (5 parts x 8 K steps of 4
+// rows), and per 16-point chunk four accumulators collect (C^T Y) grouped by
+// the column component Z they are multiplied with afterwards:
 //   u_phi = C^V phi,  u_x = C^Ws dx - C^z dy + C^y dz,
 //   u_y = C^z dx + C^Ws dy - C^x dz,  u_z = -C^y dx + C^x dy + C^Ws dz
 // (rows i, the K index: Y = the row functions' values at the chunk's points),
-// then one lane-local drain sum_j u . Z per chunk.  Chunk images arrive by LDS
-// DMA, double-buffered: the next chunk's loads are in flight while this one
-// is multiplied (one barrier per chunk); two workgroups fit on a CU.
-template <bool PERSIST>
+// then one lane-local drain sum_j u . Z per chunk.  The row image arrives by
+// LDS DMA, double-buffered (the next chunk's loads in flight while this one
+// is multiplied, one barrier per chunk); each lane's 16 column values Z come
+// from the panel straight into registers, a chunk ahead.  Two workgroups fit
+// on a CU.
+// F32W (density_on_grid in FP32): the nine W-term products per K step run on
+// FP32 MFMA with the coefficients and row values rounded to FP32; each
+// chunk's FP32 sums over the wave's 32 rows (at most 96 products per column
+// and point) are drained into the FP64 point sum, so the FP32 error of a
+// point is at most gamma_98 (u = 2^-24) times the magnitudes of its W terms.
+// The V term stays FP64.
+template <bool F32W, bool PERSIST>
 __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t terms, const WorkItem *work,
                                                           const int32_t *order, int64_t w0, int64_t nw,
                                                           const double *coef, const double *panel,
                                                           double *partial, unsigned *tickets) {
   constexpr int NC = 5;  // coefficient parts
-  __shared__ double img[2][2][QIMG];     // [buffer][row image, column image]
+  __shared__ double img[2][AIMG];        // row images, alternating chunks
   __shared__ double s_red[2][4][16];     // per-wave point sums, alternating chunks
   __shared__ int64_t s_pos;
-  // slot data of the quarter's 32 rows and 32 columns (slot -1: beyond n)
-  __shared__ int s_rslot[QW], s_rfn[QW], s_cslot[QW], s_cfn[QW], s_cnf[QW];
+  // slot data of the tile's 64 rows and the half's 32 columns (slot -1: beyond n)
+  __shared__ int s_rslot[T], s_rfn[T], s_cslot[T / 2], s_cfn[T / 2], s_cnf[T / 2];
   // store offset of the pair block of (row slot, column slot) for the slots
-  // the quarter spans (-1: lower atom-block triangle or not a stored pair)
-  __shared__ int64_t s_poff[QW * QW];
-  const int64_t npos = 4 * nw;
+  // the half spans (-1: lower atom-block triangle or not a stored pair), when
+  // they are at most POFF_LDS pairs (atoms of 5 or more functions: at most
+  // 14 x 8); otherwise each lane looks its pairs up in the plan
+  constexpr int POFF_LDS = 256;
+  __shared__ int64_t s_poff[POFF_LDS];
+  const int64_t npos = 2 * nw;
   int64_t pos = PERSIST ? next_item(tickets, npos, order != nullptr, &s_pos)
                         : (order ? (int64_t)blockIdx.x : xcd_map(blockIdx.x, npos));
   while (!PERSIST || pos < npos) {
-  const int qd = (int)(pos & 3);
-  const int64_t wi = w0 + (order ? order[w0 + (pos >> 2)] : (pos >> 2));
+  const int half = (int)(pos & 1);
+  const int64_t wi = w0 + (order ? order[w0 + (pos >> 1)] : (pos >> 1));
   const WorkItem it = work[wi];
   const int b = it.batch;
   const int f0 = d.batch_fn_off[b], n = d.batch_fn_off[b + 1] - f0;
-  if (quarter_valid(it, qd, n)) {  // workgroup-uniform
+  if (half_valid(it, half, n)) {  // workgroup-uniform
   const int g0 = d.batch_pt_off[b], P = d.batch_pt_off[b + 1] - g0;
   const int sbase = d.batch_slot_off[b];
-  const int r0 = it.ti * T + 32 * (qd >> 1), c0 = it.tj * T + 32 * (qd & 1);
+  const int r0 = it.ti * T, c0 = it.tj * T + 32 * half;
   const int Pp = (int)pad16(P), np = (int)pad16(n);
   const double *pb = panel + d.panel_off[b];
   const int64_t plane = (int64_t)Pp * np;
   const int tid = threadIdx.x;
   // wave index as a scalar: conditions derived from it stay uniform
   const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int rb = wave >> 1, cb = wave & 1;  // this wave's 16 x 16 block in the quarter
+  const int js = wave & 1, ih = wave >> 1;  // column block, row half
   const int l16 = lane & 15, lk = lane >> 4;
-  const int rowb = r0 + 16 * rb, colb = c0 + 16 * cb;
-  const bool act = block_active(rowb, colb, n);
-  const bool upper = rowb < colb;
+  const int colb = c0 + 16 * js;
   const int lj = colb + l16;
-  if (tid < 2 * QW) {
-    const bool row = tid < QW;
-    const int lf = row ? r0 + tid : c0 + tid - QW;
+  // row origin of this wave's two 16-row blocks.  Column half 0 of a diagonal
+  // tile has 3 active blocks, (0,0), (0,1) and (1,1) in 16-blocks: block (1,1)
+  // moves from wave (ih 0, js 1) to the otherwise idle wave (ih 1, js 1), so
+  // no wave of that half carries two.
+  const bool dg0 = it.ti == it.tj && half == 0;
+  const int iloc = (dg0 && ih == 1 && js == 1) ? 16 : 32 * ih;
+  bool act[2], upper[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int rb = r0 + iloc + 16 * h;
+    act[h] = block_active(rb, colb, n) && !(dg0 && ih == 0 && js == 1 && h == 1);
+    upper[h] = rb < colb;
+  }
+  const bool any = act[0] || act[1];
+  if (tid < T + T / 2) {
+    const bool row = tid < T;
+    const int lf = row ? r0 + tid : c0 + tid - T;
     SlotInfo si{-1, 0, 0, 0};
     if (lf < n) si = slot_of(d, f0, sbase, lf);
     if (row) {
       s_rslot[tid] = si.slot;
       s_rfn[tid] = si.fnoff;
     } else {
-      s_cslot[tid - QW] = si.slot;
-      s_cfn[tid - QW] = si.fnoff;
-      s_cnf[tid - QW] = si.nfn;
+      s_cslot[tid - T] = si.slot;
+      s_cfn[tid - T] = si.fnoff;
+      s_cnf[tid - T] = si.nfn;
     }
   }
+  // the first chunk's row image loads while the coefficients are read
+  dma_chunk<NTD, 16, T, RSA>(pb, plane, np, r0, 0, img[0]);
   __syncthreads();  // slot tables visible
-  // slot ranges of the quarter's rows and columns (slots ascend with the
-  // functions; rows and columns beyond n carry slot -1)
+  // slot ranges of the tile's rows and the half's columns (slots ascend with
+  // the functions; rows and columns beyond n carry slot -1)
   const int rs0 = s_rslot[0], cs0 = s_cslot[0];
-  const int rs1 = s_rslot[min(QW, n - r0) - 1], cs1 = s_cslot[min(QW, n - c0) - 1];
+  const int rs1 = s_rslot[min(T, n - r0) - 1], cs1 = s_cslot[min(T / 2, n - c0) - 1];
   const int nrs = rs1 - rs0 + 1, ncs = cs1 - cs0 + 1;
-  {
-    const int ns = d.batch_slot_off[b + 1] - sbase;
-    const int64_t spb = d.batch_sp_off[b];
-    for (int t = tid; t < nrs * ncs; t += NTD) {
-      const int si = rs0 + t / ncs, sj = cs0 + t % ncs;
-      int64_t po = -1;
-      if (si <= sj) {
-        // upper-triangle index of (si, sj)
-        const int q = d.sp_pair[spb + (int64_t)si * ns - (int64_t)si * (si - 1) / 2 + (sj - si)];
-        if (q >= 0) po = d.pair_off[q];
-      }
-      s_poff[t] = po;
-    }
-  }
-  // the first chunk's images load while the coefficients are read
-  dma_chunk<NTD, 16, QW, RSQ>(pb, plane, np, r0, 0, img[0][0]);
-  dma_chunk<NTD, 16, QW, RSQ>(pb, plane, np, c0, 0, img[0][1]);
+  const int ns = d.batch_slot_off[b + 1] - sbase;
+  const int64_t spb = d.batch_sp_off[b];
+  // store offset of the pair block of slots (si, sj), -1 if none
+  auto pair_offset = [&](int si, int sj) -> int64_t {
+    if (si > sj) return -1;
+    // upper-triangle index of (si, sj)
+    const int q = d.sp_pair[spb + (int64_t)si * ns - (int64_t)si * (si - 1) / 2 + (sj - si)];
+    return q >= 0 ? d.pair_off[q] : -1;
+  };
+  const bool lds_table = nrs * ncs <= POFF_LDS;  // workgroup-uniform
+  if (lds_table)
+    for (int t = tid; t < nrs * ncs; t += NTD) s_poff[t] = pair_offset(rs0 + t / ncs, cs0 + t % ncs);
   __syncthreads();  // pair offsets visible
-  // coefficient block: rows i = rowb + 4 ks + lk (ks = 0..3), column lj, read
-  // from the store: element (li, lj) of the pair block of its two atoms
+  // coefficient slice: rows i = r0 + iloc + 4 ks + lk (ks = 0..7), column lj,
+  // read from the store: element (li, lj) of the pair block of its two atoms
   // (upper atom-block triangle only), plus the mirrored element (lj, li) when
   // the 16 x 16 block is strictly upper inside one atom block (no work item
   // computes the mirrored block); c' on the W parts, zero for unselected
-  // terms.  Every load is issued before any is used.
-  double creg[NC][4];
+  // terms.  The loads of each kind are issued together before any is used.
+  double creg[NC][8];
   {
     const int64_t L = d.store_len;
-    const int cl = 16 * cb + l16;
+    const int cl = 16 * js + l16;
     const int cslot = s_cslot[cl], cfn = s_cfn[cl], cnf = s_cnf[cl];
-    int64_t ea[4], em[4];
-    bool live[4], mir[4];
-#pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
-      const int rl = 16 * rb + 4 * ks + lk;
-      const int li = r0 + rl;
-      const int rslot = s_rslot[rl], rfn = s_rfn[rl];
-      const int64_t po = (act && rslot >= 0 && cslot >= 0) ? s_poff[(rslot - rs0) * ncs + (cslot - cs0)] : -1;
-      live[ks] = po >= 0;
-      mir[ks] = live[ks] && upper && rslot == cslot;
-      ea[ks] = live[ks] ? po + (int64_t)(li - rfn) * cnf + (lj - cfn) : 0;
-      em[ks] = mir[ks] ? po + (int64_t)(lj - rfn) * cnf + (li - cfn) : 0;
-    }
-    double cv[NC][4], cm[NC][4];
-#pragma unroll
-    for (int ks = 0; ks < 4; ++ks)
-#pragma unroll
-      for (int q = 0; q < NC; ++q) {
-        cv[q][ks] = coef[q * L + ea[ks]];
-        cm[q][ks] = coef[q * L + em[ks]];
-      }
+    int64_t em[8];
+    bool mir[8];
     const bool on[NC] = {(terms & Q4C_TERM_LL) != 0, (terms & Q4C_TERM_SS) != 0, (terms & Q4C_TERM_SO) != 0,
                          (terms & Q4C_TERM_SO) != 0, (terms & Q4C_TERM_SO) != 0};
+    {
+      int64_t ea[8];
+      bool live[8];
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks)
-#pragma unroll
-      for (int q = 0; q < NC; ++q) {
-        const double c = (live[ks] ? cv[q][ks] : 0.0) + (mir[ks] ? mirror_sign(q) * cm[q][ks] : 0.0);
-        creg[q][ks] = on[q] ? (q == 0 ? c : d.cprime * c) : 0.0;
+      for (int ks = 0; ks < 8; ++ks) {
+        const int rl = iloc + 4 * ks + lk;
+        const int li = r0 + rl;
+        const int rslot = s_rslot[rl], rfn = s_rfn[rl];
+        int64_t po = -1;
+        if (act[ks >> 2] && rslot >= 0 && cslot >= 0)
+          po = lds_table ? s_poff[(rslot - rs0) * ncs + (cslot - cs0)] : pair_offset(rslot, cslot);
+        live[ks] = po >= 0;
+        mir[ks] = live[ks] && upper[ks >> 2] && rslot == cslot;
+        ea[ks] = live[ks] ? po + (int64_t)(li - rfn) * cnf + (lj - cfn) : 0;
+        em[ks] = mir[ks] ? po + (int64_t)(lj - rfn) * cnf + (li - cfn) : 0;
       }
+#pragma unroll
+      for (int ks = 0; ks < 8; ++ks)
+#pragma unroll
+        for (int q = 0; q < NC; ++q) creg[q][ks] = coef[q * L + ea[ks]];
+#pragma unroll
+      for (int ks = 0; ks < 8; ++ks)
+#pragma unroll
+        for (int q = 0; q < NC; ++q) creg[q][ks] = live[ks] && on[q] ? creg[q][ks] : 0.0;
+    }
+    // mirrored elements: only strictly upper 16 x 16 blocks (wave-uniform) can have them
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (!upper[h]) continue;
+      double cm[NC][4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int q = 0; q < NC; ++q) cm[q][k] = coef[q * L + em[4 * h + k]];
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int q = 0; q < NC; ++q)
+          if (mir[4 * h + k] && on[q]) creg[q][4 * h + k] += mirror_sign(q) * cm[q][k];
+    }
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks)
+#pragma unroll
+      for (int q = 1; q < NC; ++q) creg[q][ks] *= d.cprime;
   }
-  double *out = partial + 4 * d.work_part_off[wi] + qd * P;
+  // F32W: the W coefficients as FP32 MFMA operands
+  float cw[4][8];
+  if (F32W) {
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) cw[q][ks] = (float)creg[q + 1][ks];
+  }
+  // column values of a chunk: Z[q][pt = k + l16][j]; result register r of
+  // lane (l16, lk) is column j = lk + 4 r at point l16 for FP64 MFMA, and
+  // j = 4 lk + r for FP32 MFMA (the W terms when F32W)
+  double zn[4][4];
+  auto load_z = [&](int k) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int jr = (F32W && q > 0) ? d_row_f32(lk, r) : d_row_f64(lk, r);
+        zn[q][r] = any ? pb[q * plane + ((int64_t)((k + l16) >> 2) * np + colb + jr) * 4 + (l16 & 3)] : 0.0;
+      }
+  };
+  load_z(0);
+  double *out = partial + 2 * d.work_part_off[wi] + half * P;
 
   for (int k0 = 0; k0 < Pp; k0 += 16) {
     const int bi = (k0 >> 4) & 1;
-    __builtin_amdgcn_s_waitcnt(0);  // this thread's loads of this chunk have landed
+    __builtin_amdgcn_s_waitcnt(0);  // this thread's loads of this chunk (image, Z) have landed
     __syncthreads();                // ... everyone's; the previous chunk is consumed, its sums visible
     if (k0 > 0 && tid < 16 && k0 - 16 + tid < P)
       out[k0 - 16 + tid] = (s_red[bi ^ 1][0][tid] + s_red[bi ^ 1][1][tid]) +
                            (s_red[bi ^ 1][2][tid] + s_red[bi ^ 1][3][tid]);
+    double zt[4][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) zt[q][r] = zn[q][r];
     if (k0 + 16 < Pp) {
-      dma_chunk<NTD, 16, QW, RSQ>(pb, plane, np, r0, (k0 + 16) >> 2, img[bi ^ 1][0]);
-      dma_chunk<NTD, 16, QW, RSQ>(pb, plane, np, c0, (k0 + 16) >> 2, img[bi ^ 1][1]);
+      dma_chunk<NTD, 16, T, RSA>(pb, plane, np, r0, (k0 + 16) >> 2, img[bi ^ 1]);
+      load_z(k0 + 16);
     }
     double x = 0.0;
-    if (act) {
-      const double *ia = img[bi][0], *ib = img[bi][1];
-      // column values Z[q][pt = l16][j = 16 cb + lk + 4 r]: register r of the
-      // MFMA result of lane (l16, lk) is column lk + 4 r of the block at point l16
-      double zt[4][4];
+    if (any && F32W) {
+      const double *ia = img[bi];
+      dbl4 uf = dbl4{0.0, 0.0, 0.0, 0.0};
+      flt4 vx = flt4{0.f, 0.f, 0.f, 0.f}, vy = vx, vz = vx;
+      auto ksteps = [&](auto k0c, auto k1c) {
+        constexpr int K0 = decltype(k0c)::value, K1 = decltype(k1c)::value;
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
+        for (int ks = K0; ks < K1; ++ks) {
+          const int col = 2 * (iloc + 4 * ks + lk) + (l16 & 1);
+          const double y0 = ia[(0 * 8 + (l16 >> 1)) * RSA + col];
+          const float y1 = (float)ia[(1 * 8 + (l16 >> 1)) * RSA + col];
+          const float y2 = (float)ia[(2 * 8 + (l16 >> 1)) * RSA + col];
+          const float y3 = (float)ia[(3 * 8 + (l16 >> 1)) * RSA + col];
+          uf = mfma64(creg[0][ks], y0, uf);
+          vx = mfma32(cw[0][ks], y1, vx);
+          vy = mfma32(cw[3][ks], y1, vy);
+          vz = mfma32(cw[2][ks], -y1, vz);
+          vx = mfma32(cw[3][ks], -y2, vx);
+          vy = mfma32(cw[0][ks], y2, vy);
+          vz = mfma32(cw[1][ks], y2, vz);
+          vx = mfma32(cw[2][ks], y3, vx);
+          vy = mfma32(cw[1][ks], -y3, vy);
+          vz = mfma32(cw[0][ks], y3, vz);
+        }
+      };
+      if (act[0] && act[1])
+        ksteps(std::integral_constant<int, 0>{}, std::integral_constant<int, 8>{});
+      else if (act[0])
+        ksteps(std::integral_constant<int, 0>{}, std::integral_constant<int, 4>{});
+      else
+        ksteps(std::integral_constant<int, 4>{}, std::integral_constant<int, 8>{});
 #pragma unroll
-        for (int r = 0; r < 4; ++r) zt[q][r] = ib[(q * 8 + (l16 >> 1)) * RSQ + 2 * (16 * cb + d_row_f64(lk, r)) + (l16 & 1)];
+      for (int r = 0; r < 4; ++r)
+        x += (uf[r] * zt[0][r] + (double)vx[r] * zt[1][r]) + ((double)vy[r] * zt[2][r] + (double)vz[r] * zt[3][r]);
+      x += __shfl_xor(x, 16);
+      x += __shfl_xor(x, 32);
+    } else if (any) {
+      const double *ia = img[bi];
       dbl4 uf = dbl4{0.0, 0.0, 0.0, 0.0}, ux = uf, uy = uf, uz = uf;
+      // the K steps of active 16-row blocks, as straight-line code
+      auto ksteps = [&](auto k0c, auto k1c) {
+        constexpr int K0 = decltype(k0c)::value, K1 = decltype(k1c)::value;
 #pragma unroll
-      for (int ks = 0; ks < 4; ++ks) {
-        // row values Y[q][pt = l16][i = 16 rb + 4 ks + lk]: the K index is lk
-        const int col = 2 * (16 * rb + 4 * ks + lk) + (l16 & 1);
-        const double y0 = ia[(0 * 8 + (l16 >> 1)) * RSQ + col], y1 = ia[(1 * 8 + (l16 >> 1)) * RSQ + col];
-        const double y2 = ia[(2 * 8 + (l16 >> 1)) * RSQ + col], y3 = ia[(3 * 8 + (l16 >> 1)) * RSQ + col];
-        uf = mfma64(creg[0][ks], y0, uf);
-        ux = mfma64(creg[1][ks], y1, ux);
-        uy = mfma64(creg[4][ks], y1, uy);
-        uz = mfma64(creg[3][ks], -y1, uz);
-        ux = mfma64(creg[4][ks], -y2, ux);
-        uy = mfma64(creg[1][ks], y2, uy);
-        uz = mfma64(creg[2][ks], y2, uz);
-        ux = mfma64(creg[3][ks], y3, ux);
-        uy = mfma64(creg[2][ks], -y3, uy);
-        uz = mfma64(creg[1][ks], y3, uz);
-      }
+        for (int ks = K0; ks < K1; ++ks) {
+          // row values Y[q][pt = l16][i = iloc + 4 ks + lk]: the K index is lk
+          const int col = 2 * (iloc + 4 * ks + lk) + (l16 & 1);
+          const double y0 = ia[(0 * 8 + (l16 >> 1)) * RSA + col], y1 = ia[(1 * 8 + (l16 >> 1)) * RSA + col];
+          const double y2 = ia[(2 * 8 + (l16 >> 1)) * RSA + col], y3 = ia[(3 * 8 + (l16 >> 1)) * RSA + col];
+          uf = mfma64(creg[0][ks], y0, uf);
+          ux = mfma64(creg[1][ks], y1, ux);
+          uy = mfma64(creg[4][ks], y1, uy);
+          uz = mfma64(creg[3][ks], -y1, uz);
+          ux = mfma64(creg[4][ks], -y2, ux);
+          uy = mfma64(creg[1][ks], y2, uy);
+          uz = mfma64(creg[2][ks], y2, uz);
+          ux = mfma64(creg[3][ks], y3, ux);
+          uy = mfma64(creg[2][ks], -y3, uy);
+          uz = mfma64(creg[1][ks], y3, uz);
+        }
+      };
+      if (act[0] && act[1])
+        ksteps(std::integral_constant<int, 0>{}, std::integral_constant<int, 8>{});
+      else if (act[0])
+        ksteps(std::integral_constant<int, 0>{}, std::integral_constant<int, 4>{});
+      else
+        ksteps(std::integral_constant<int, 4>{}, std::integral_constant<int, 8>{});
 #pragma unroll
       for (int r = 0; r < 4; ++r) x += (uf[r] * zt[0][r] + ux[r] * zt[1][r]) + (uy[r] * zt[2][r] + uz[r] * zt[3][r]);
       // sum over the block's 16 columns: the 4 registers (above), then the 4 lane rows
@@ -1023,14 +1162,14 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t te
     if (tid < 16 && k0 + tid < P)
       out[k0 + tid] = (s_red[bi][0][tid] + s_red[bi][1][tid]) + (s_red[bi][2][tid] + s_red[bi][3][tid]);
   }
-  }  // quarter_valid
+  }  // half_valid
   if (!PERSIST) break;
   pos = next_item(tickets, npos, order != nullptr, &s_pos);
   }
 }
 
 // Point sums: out[perm[g]] = (w_g if weighted) * sum over the batch's work
-// items (in order) and their valid quarters (in order).
+// items (in order) and their valid column halves (in order).
 __global__ void k_density_points(DevPlan d, const WorkItem *work, int64_t b0, const double *partial, int weight_mode,
                                  double *out) {
   const int64_t b = b0 + blockIdx.x;
@@ -1041,10 +1180,9 @@ __global__ void k_density_points(DevPlan d, const WorkItem *work, int64_t b0, co
     double s = 0.0;
     for (int64_t w = wa; w < wb; ++w) {
       const WorkItem it = work[w];
-      const double *pw = partial + 4 * d.work_part_off[w];
-#pragma unroll
-      for (int qd = 0; qd < 4; ++qd)
-        if (quarter_valid(it, qd, n)) s += pw[qd * P + g];
+      const double *pw = partial + 2 * d.work_part_off[w];
+      s += pw[g];
+      if (half_valid(it, 1, n)) s += pw[P + g];
     }
     out[d.perm[g0 + g]] = weight_mode ? d.pw[g0 + g] * s : s;
   }
@@ -1104,84 +1242,87 @@ int launch_tabulate(const q4c_plan *p, int64_t b0, int64_t b1, int deriv, int dt
   return check_launch("k_tabulate");
 }
 
-int launch_integrate(const q4c_plan *p, const double *v, int precision, uint32_t flags, double *store,
-                     double *spin_w, double *spin_v, hipStream_t s) {
+// Launch one contraction kernel over work positions [w0, w0 + nw) of a pass,
+// persistent (tickets) or one workgroup per position.
+template <typename K>
+static void launch_work(K kernel_p, K kernel_1, unsigned grid, bool persistent, hipStream_t s, const DevPlan &dp,
+                        const WorkItem *work, const int32_t *order, int64_t w0, int64_t nw, const double *om,
+                        const double *panel, double *staging, unsigned *tickets) {
+  if (persistent)
+    hipLaunchKernelGGL(kernel_p, dim3(grid), dim3(NT), 0, s, dp, work, order, w0, nw, om, panel, staging, tickets);
+  else
+    hipLaunchKernelGGL(kernel_1, dim3(grid), dim3(NT), 0, s, dp, work, order, w0, nw, om, panel, staging, tickets);
+}
+
+int launch_integrate(const q4c_plan *p, const double *v, int precision, uint32_t parts, uint32_t flags,
+                     double *store, double *spin_w, double *spin_v, hipStream_t s) {
   const int accumulate = (flags & Q4C_ACCUMULATE) ? 1 : 0;
+  const bool wantV = parts & Q4C_PART_V, wantW = parts & (Q4C_PART_WS | Q4C_PART_WSO);
+  // store parts written: 0 V, 1 Ws, 2..4 Wso
+  const unsigned pmask = (wantV ? 1u : 0u) | ((parts & Q4C_PART_WS) ? 2u : 0u) | ((parts & Q4C_PART_WSO) ? 28u : 0u);
+  // FP64 with W parts: one kernel for all five (PK_F64 panels); otherwise V
+  // on FP64 from phi alone and the W parts on FP32 (PK_F32 / PK_SPLIT panels)
+  const bool full64 = precision == Q4C_PREC_F64 && wantW;
+  const int kind = full64 ? PK_F64 : (precision == Q4C_PREC_SPLIT_F32 && wantW ? PK_SPLIT : PK_F32);
   int rc;
   {
     TimedLaunch tl_(p, Q4C_TIMER_OTHER, s);
     const unsigned nb = (unsigned)std::min<int64_t>((p->n_active + 16 + 255) / 256, 65535);
-    hipLaunchKernelGGL(k_om, dim3(nb), dim3(256), 0, s, p->dp, v, p->d_om, p->d_chunks);
+    hipLaunchKernelGGL(k_om, dim3(nb), dim3(256), 0, s, p->dp, v, p->d_om);
   }
   if ((rc = check_launch("k_om")) != Q4C_OK) return rc;
   const LaunchCfg cfg = p->cfg_contract;
   const int32_t *order = cfg.order ? p->d_order : nullptr;
+  const int64_t np_ = (int64_t)p->passes.size();
   if (cfg.persistent > 0) {
-    hipLaunchKernelGGL(k_zero_u32, dim3(8), dim3(256), 0, s, p->d_tickets,
-                       (int64_t)p->passes.size() * kTicketsPerLaunch);
+    // ticket queues: [V or all-parts kernel][W kernel] x passes
+    hipLaunchKernelGGL(k_zero_u32, dim3(8), dim3(256), 0, s, p->d_tickets, 2 * np_ * kTicketsPerLaunch);
     if ((rc = check_launch("k_zero_u32")) != Q4C_OK) return rc;
   }
   for (size_t ip = 0; ip < p->passes.size(); ++ip) {
     const Pass &ps = p->passes[ip];
     const int64_t nw = ps.w1 - ps.w0, nt = ps.t1 - ps.t0, nr = ps.r1 - ps.r0;
-    unsigned *tickets = cfg.persistent > 0 ? p->d_tickets + ip * kTicketsPerLaunch : nullptr;
-    const unsigned grid = (unsigned)(cfg.persistent > 0 ? std::min<int64_t>(cfg.persistent, nw) : nw);
+    const bool pers = cfg.persistent > 0;
+    unsigned *tick_a = pers ? p->d_tickets + ip * kTicketsPerLaunch : nullptr;
+    unsigned *tick_w = pers ? p->d_tickets + (np_ + ip) * kTicketsPerLaunch : nullptr;
+    const unsigned grid = (unsigned)(pers ? std::min<int64_t>(cfg.persistent, nw) : nw);
     double *panel = p->d_staging + ps.staging_len + ps.partial_len;
     if (nt > 0) {
       {
         TimedLaunch tl_(p, Q4C_TIMER_TABULATE, s);
-        hipLaunchKernelGGL(k_panel<false>, dim3((unsigned)nt), dim3(256), 0, s, p->dp, p->d_ptile, ps.t0, nt, panel);
+        if (kind == PK_F64)
+          hipLaunchKernelGGL(k_panel<PK_F64>, dim3((unsigned)nt), dim3(256), 0, s, p->dp, p->d_ptile, ps.t0, nt, panel);
+        else if (kind == PK_SPLIT)
+          hipLaunchKernelGGL(k_panel<PK_SPLIT>, dim3((unsigned)nt), dim3(256), 0, s, p->dp, p->d_ptile, ps.t0, nt,
+                             panel);
+        else
+          hipLaunchKernelGGL(k_panel<PK_F32>, dim3((unsigned)nt), dim3(256), 0, s, p->dp, p->d_ptile, ps.t0, nt, panel);
       }
       if ((rc = check_launch("k_panel")) != Q4C_OK) return rc;
     }
     if (nw > 0) {
-      {
-        TimedLaunch tl_(p, Q4C_TIMER_CONTRACT, s);
-        if (precision == Q4C_PREC_F64)
-          {
-          if (tickets)
-            hipLaunchKernelGGL((k_contract<MODE_F64, true>), dim3(grid), dim3(NT), 0, s, p->dp, p->d_work, order, ps.w0,
-                               nw, p->d_om, panel, p->d_staging, p->split_tau, p->d_chunks, tickets, p->d_hotmask);
-          else
-            hipLaunchKernelGGL((k_contract<MODE_F64, false>), dim3(grid), dim3(NT), 0, s, p->dp, p->d_work, order, ps.w0,
-                               nw, p->d_om, panel, p->d_staging, p->split_tau, p->d_chunks, tickets, p->d_hotmask);
-        }
-        else if (precision == Q4C_PREC_F32)
-          {
-          if (tickets)
-            hipLaunchKernelGGL((k_contract<MODE_F32, true>), dim3(grid), dim3(NT), 0, s, p->dp, p->d_work, order, ps.w0,
-                               nw, p->d_om, panel, p->d_staging, p->split_tau, p->d_chunks, tickets, p->d_hotmask);
-          else
-            hipLaunchKernelGGL((k_contract<MODE_F32, false>), dim3(grid), dim3(NT), 0, s, p->dp, p->d_work, order, ps.w0,
-                               nw, p->d_om, panel, p->d_staging, p->split_tau, p->d_chunks, tickets, p->d_hotmask);
-        }
-        else
-          {
-          if (tickets)
-            hipLaunchKernelGGL((k_contract<MODE_SPLIT, true>), dim3(grid), dim3(NT), 0, s, p->dp, p->d_work, order, ps.w0,
-                               nw, p->d_om, panel, p->d_staging, p->split_tau, p->d_chunks, tickets, p->d_hotmask);
-          else
-            hipLaunchKernelGGL((k_contract<MODE_SPLIT, false>), dim3(grid), dim3(NT), 0, s, p->dp, p->d_work, order, ps.w0,
-                               nw, p->d_om, panel, p->d_staging, p->split_tau, p->d_chunks, tickets, p->d_hotmask);
-        }
-      }
-      if ((rc = check_launch("k_contract")) != Q4C_OK) return rc;
-      if (precision != Q4C_PREC_F64) {
-        // the deferred chunks' W parts in FP64, one workgroup per work item
-        {
-          TimedLaunch tl_(p, Q4C_TIMER_CONTRACT, s);
-          hipLaunchKernelGGL((k_contract<MODE_HOT, false>), dim3((unsigned)nw), dim3(NT), 0, s, p->dp, p->d_work,
-                             nullptr, ps.w0, nw, p->d_om, panel, p->d_staging, p->split_tau, p->d_chunks, nullptr,
-                             p->d_hotmask);
-        }
-        if ((rc = check_launch("k_contract<hot>")) != Q4C_OK) return rc;
+      TimedLaunch tl_(p, Q4C_TIMER_CONTRACT, s);
+      if (full64) {
+        launch_work(k_contract<MODE_F64, true>, k_contract<MODE_F64, false>, grid, pers, s, p->dp, p->d_work, order,
+                    ps.w0, nw, p->d_om, panel, p->d_staging, tick_a);
+      } else {
+        if (wantV)
+          launch_work(k_contract<MODE_V, true>, k_contract<MODE_V, false>, grid, pers, s, p->dp, p->d_work, order,
+                      ps.w0, nw, p->d_om, panel, p->d_staging, tick_a);
+        if (wantW && precision == Q4C_PREC_SPLIT_F32)
+          launch_work(k_contract_w<true, true>, k_contract_w<true, false>, grid, pers, s, p->dp, p->d_work, order,
+                      ps.w0, nw, p->d_om, panel, p->d_staging, tick_w);
+        else if (wantW)
+          launch_work(k_contract_w<false, true>, k_contract_w<false, false>, grid, pers, s, p->dp, p->d_work, order,
+                      ps.w0, nw, p->d_om, panel, p->d_staging, tick_w);
       }
     }
+    if (nw > 0 && (rc = check_launch("k_contract")) != Q4C_OK) return rc;
     if (nr > 0) {
       {
         TimedLaunch tl_(p, Q4C_TIMER_REDUCE, s);
         hipLaunchKernelGGL(k_reduce, dim3((unsigned)nr), dim3(256), 0, s, p->dp, ps.r0, p->d_red_pair, p->d_red_first,
-                           p->d_red_inc_off, p->d_inc_src, p->d_staging, store, accumulate, 5);
+                           p->d_red_inc_off, p->d_inc_src, p->d_staging, store, accumulate, 5, pmask);
       }
       if ((rc = check_launch("k_reduce")) != Q4C_OK) return rc;
     }
@@ -1190,7 +1331,7 @@ int launch_integrate(const q4c_plan *p, const double *v, int precision, uint32_t
     {
       TimedLaunch tl_(p, Q4C_TIMER_OTHER, s);
       hipLaunchKernelGGL(k_zero_pairs, dim3((unsigned)p->untouched_pairs.size()), dim3(256), 0, s, p->dp,
-                         p->d_untouched, store, 5);
+                         p->d_untouched, store, 5, pmask);
     }
     if ((rc = check_launch("k_zero_pairs")) != Q4C_OK) return rc;
   }
@@ -1211,7 +1352,7 @@ int launch_integrate_hs(const q4c_plan *p, const double *v, uint32_t flags, doub
   {
     TimedLaunch tl_(p, Q4C_TIMER_OTHER, s);
     const unsigned nb = (unsigned)std::min<int64_t>((p->n_active + 16 + 255) / 256, 65535);
-    hipLaunchKernelGGL(k_om, dim3(nb), dim3(256), 0, s, p->dp, v, p->d_om, p->d_chunks);
+    hipLaunchKernelGGL(k_om, dim3(nb), dim3(256), 0, s, p->dp, v, p->d_om);
   }
   if ((rc = check_launch("k_om")) != Q4C_OK) return rc;
   const LaunchCfg cfg = p->cfg_hs;
@@ -1230,7 +1371,7 @@ int launch_integrate_hs(const q4c_plan *p, const double *v, uint32_t flags, doub
     if (nt > 0) {
       {
         TimedLaunch tl_(p, Q4C_TIMER_TABULATE, s);
-        hipLaunchKernelGGL(k_panel<true>, dim3((unsigned)nt), dim3(256), 0, s, p->dp, p->d_ptile, ps.t0, nt, panel);
+        hipLaunchKernelGGL(k_panel<PK_HS>, dim3((unsigned)nt), dim3(256), 0, s, p->dp, p->d_ptile, ps.t0, nt, panel);
       }
       if ((rc = check_launch("k_panel<hs>")) != Q4C_OK) return rc;
     }
@@ -1245,7 +1386,7 @@ int launch_integrate_hs(const q4c_plan *p, const double *v, uint32_t flags, doub
       {
         TimedLaunch tl_(p, Q4C_TIMER_REDUCE, s);
         hipLaunchKernelGGL(k_reduce, dim3((unsigned)nr), dim3(256), 0, s, p->dp, ps.r0, p->d_red_pair, p->d_red_first,
-                           p->d_red_inc_off, p->d_inc_src, p->d_staging, hs, accumulate, 2);
+                           p->d_red_inc_off, p->d_inc_src, p->d_staging, hs, accumulate, 2, 3u);
       }
       if ((rc = check_launch("k_reduce")) != Q4C_OK) return rc;
     }
@@ -1254,15 +1395,15 @@ int launch_integrate_hs(const q4c_plan *p, const double *v, uint32_t flags, doub
     {
       TimedLaunch tl_(p, Q4C_TIMER_OTHER, s);
       hipLaunchKernelGGL(k_zero_pairs, dim3((unsigned)p->untouched_pairs.size()), dim3(256), 0, s, p->dp,
-                         p->d_untouched, hs, 2);
+                         p->d_untouched, hs, 2, 3u);
     }
     if ((rc = check_launch("k_zero_pairs")) != Q4C_OK) return rc;
   }
   return Q4C_OK;
 }
 
-int launch_density(const q4c_plan *p, const double *coef, uint32_t terms, int weight_mode, double *out,
-                   int64_t resident_pass, hipStream_t s) {
+int launch_density(const q4c_plan *p, const double *coef, uint32_t terms, int precision, int weight_mode,
+                   double *out, int64_t resident_pass, hipStream_t s) {
   int rc;
   if (p->n_points > 0) {
     {
@@ -1288,26 +1429,35 @@ int launch_density(const q4c_plan *p, const double *coef, uint32_t terms, int we
     const int64_t nw = ps.w1 - ps.w0, nbt = ps.b1 - ps.b0;
     const int64_t nt = (int64_t)ip == resident_pass ? 0 : ps.t1 - ps.t0;
     unsigned *tickets = cfg.persistent > 0 ? tick0 + ip * kTicketsPerLaunch : nullptr;
-    // four workgroup positions (quarters) per work item
-    const unsigned grid = (unsigned)(cfg.persistent > 0 ? std::min<int64_t>(cfg.persistent, 4 * nw) : 4 * nw);
+    // two workgroup positions (column halves) per work item
+    const unsigned grid = (unsigned)(cfg.persistent > 0 ? std::min<int64_t>(cfg.persistent, 2 * nw) : 2 * nw);
     double *partial = p->d_staging + ps.staging_len;
     double *panel = partial + ps.partial_len;
     if (nt > 0) {
       {
         TimedLaunch tl_(p, Q4C_TIMER_TABULATE, s);
-        hipLaunchKernelGGL(k_panel<false>, dim3((unsigned)nt), dim3(256), 0, s, p->dp, p->d_ptile, ps.t0, nt, panel);
+        hipLaunchKernelGGL(k_panel<PK_F64>, dim3((unsigned)nt), dim3(256), 0, s, p->dp, p->d_ptile, ps.t0, nt, panel);
       }
       if ((rc = check_launch("k_panel")) != Q4C_OK) return rc;
     }
     if (nw > 0) {
       {
         TimedLaunch tl_(p, Q4C_TIMER_DENSITY_TILES, s);
-        if (tickets)
-          hipLaunchKernelGGL(k_density_tiles<true>, dim3(grid), dim3(NTD), 0, s, p->dp, terms, p->d_work, order, ps.w0,
-                             nw, coef, panel, partial, tickets);
-        else
-          hipLaunchKernelGGL(k_density_tiles<false>, dim3(grid), dim3(NTD), 0, s, p->dp, terms, p->d_work, order,
-                             ps.w0, nw, coef, panel, partial, tickets);
+        if (precision == Q4C_PREC_F32) {
+          if (tickets)
+            hipLaunchKernelGGL((k_density_tiles<true, true>), dim3(grid), dim3(NTD), 0, s, p->dp, terms, p->d_work,
+                               order, ps.w0, nw, coef, panel, partial, tickets);
+          else
+            hipLaunchKernelGGL((k_density_tiles<true, false>), dim3(grid), dim3(NTD), 0, s, p->dp, terms, p->d_work,
+                               order, ps.w0, nw, coef, panel, partial, tickets);
+        } else {
+          if (tickets)
+            hipLaunchKernelGGL((k_density_tiles<false, true>), dim3(grid), dim3(NTD), 0, s, p->dp, terms, p->d_work,
+                               order, ps.w0, nw, coef, panel, partial, tickets);
+          else
+            hipLaunchKernelGGL((k_density_tiles<false, false>), dim3(grid), dim3(NTD), 0, s, p->dp, terms, p->d_work,
+                               order, ps.w0, nw, coef, panel, partial, tickets);
+        }
       }
       if ((rc = check_launch("k_density_tiles")) != Q4C_OK) return rc;
     }
@@ -1340,7 +1490,7 @@ int launch_density_grad(const q4c_plan *p, const double *coef, double *out, hipS
     if (nt > 0) {
       {
         TimedLaunch tl_(p, Q4C_TIMER_TABULATE, s);
-        hipLaunchKernelGGL(k_panel<false>, dim3((unsigned)nt), dim3(256), 0, s, p->dp, p->d_ptile, ps.t0, nt, panel);
+        hipLaunchKernelGGL(k_panel<PK_F64>, dim3((unsigned)nt), dim3(256), 0, s, p->dp, p->d_ptile, ps.t0, nt, panel);
       }
       if ((rc = check_launch("k_panel")) != Q4C_OK) return rc;
     }

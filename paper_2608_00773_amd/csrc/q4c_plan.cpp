@@ -489,9 +489,9 @@ int build_host(q4c_plan *p, const q4c_basis *b, const q4c_grid *g, const std::ve
       }
     }
     int nt = (nb_fn + T - 1) / T;
-    int64_t bpart = 4 * (int64_t)(nt * (nt + 1) / 2) * (g1 - g0);  // four quarters per work item
-    // panel (4 components) and, after it, the per-(tile, point) largest gradient magnitude
-    int64_t bpanel = 4 * q4c::pad16(g1 - g0) * q4c::pad16(nb_fn) + (int64_t)nt * q4c::pad16(g1 - g0);
+    int64_t bpart = 2 * (int64_t)(nt * (nt + 1) / 2) * (g1 - g0);  // two column halves per work item
+    // panel: 4 FP64 components (or phi in FP64 and up to 6 FP32 gradient planes: as much)
+    int64_t bpanel = 4 * q4c::pad16(g1 - g0) * q4c::pad16(nb_fn);
     if (bt > cur.b0 && (staging + partial + panel + bstage + bpart + bpanel > budget_doubles)) close_pass(bt);
     p->panel_off.push_back(panel);
     panel += bpanel;
@@ -536,9 +536,9 @@ int build_host(q4c_plan *p, const q4c_basis *b, const q4c_grid *g, const std::ve
     for (int ti = 0; ti < nt; ++ti)
       for (int tj = ti; tj < nt; ++tj) {
         p->work.push_back(q4c::WorkItem{(int32_t)bt, (int16_t)ti, (int16_t)tj});
-        // adjoint partials of this work item: four quarters of P doubles at 4 * work_part_off
-        p->work_part_off.push_back(partial / 4);
-        partial += 4 * (g1 - g0);
+        // adjoint partials of this work item: two column halves of P doubles at 2 * work_part_off
+        p->work_part_off.push_back(partial / 2);
+        partial += 2 * (g1 - g0);
       }
     p->max_batch_points = std::max<int64_t>(p->max_batch_points, g1 - g0);
     p->max_batch_fn = std::max<int64_t>(p->max_batch_fn, nb_fn);
@@ -650,9 +650,6 @@ int build_device(q4c_plan *p) {
   if (rc != Q4C_OK) return rc;
   rc = device_alloc(p, (size_t)(p->n_active + 16) * sizeof(double), (void **)&p->d_om);
   if (rc != Q4C_OK) return rc;
-  rc = device_alloc(p, 128 * sizeof(unsigned long long), (void **)&p->d_chunks);
-  if (rc != Q4C_OK) return rc;
-  if (hipMemset(p->d_chunks, 0, 128 * sizeof(unsigned long long)) != hipSuccess) return fail(Q4C_EHIP, "hipMemset");
   {
     const size_t nt = 2 * std::max<size_t>(p->passes.size(), 1) * q4c::kTicketsPerLaunch;
     rc = device_alloc(p, nt * sizeof(unsigned), (void **)&p->d_tickets);
@@ -660,8 +657,6 @@ int build_device(q4c_plan *p) {
     if (hipMemset(p->d_tickets, 0, nt * sizeof(unsigned)) != hipSuccess) return fail(Q4C_EHIP, "hipMemset");
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0) p->n_cu = ncu;
-    rc = device_alloc(p, std::max<size_t>(p->work.size(), 1) * sizeof(uint64_t), (void **)&p->d_hotmask);
-    if (rc != Q4C_OK) return rc;
   }
   d.R = R;
   d.fn_atom = fn_atom;
@@ -737,6 +732,10 @@ TimedLaunch::~TimedLaunch() {
 }
 
 void set_error(const std::string &msg) { g_last_error = msg; }
+int fail_status(int code, const char *msg) {
+  g_last_error = msg;
+  return code;
+}
 int hip_fail(hipError_t e, const char *what) {
   g_last_error = std::string(what) + ": " + hipGetErrorString(e);
   return Q4C_EHIP;
@@ -757,7 +756,6 @@ int create_plan(const q4c_basis *basis, const q4c_grid *grid, const q4c_opts *op
       if (opts->p_max > 0) p->p_max = opts->p_max;
       p->flags = opts->flags;
       p->staging_budget = opts->staging_bytes;
-      if (opts->split_threshold > 0.0) p->split_tau = opts->split_threshold;
     }
     if (p->p_max < 1) p->p_max = 300;
     if (p->staging_budget <= 0) p->staging_budget = (int64_t)32 << 30;
@@ -1034,21 +1032,23 @@ void drop_graphs(q4c_plan *p) {
 }
 }  // namespace
 
-int q4c_integrate_H(const q4c_plan *p, const double *v_dev, int32_t precision, uint32_t flags, double *store_dev,
-                    double *spin_w_dev, double *spin_v_dev, void *stream) {
+int q4c_integrate_H(const q4c_plan *p, const double *v_dev, int32_t precision, uint32_t parts, uint32_t flags,
+                    double *store_dev, double *spin_w_dev, double *spin_v_dev, void *stream) {
   if (!p) return fail(Q4C_EINVAL, "NULL plan");
   if (precision != Q4C_PREC_F64 && precision != Q4C_PREC_SPLIT_F32 && precision != Q4C_PREC_F32)
     return fail(Q4C_EINVAL, "unknown precision");
+  if (parts == 0 || (parts & ~(uint32_t)Q4C_PART_ALL)) return fail(Q4C_EINVAL, "bad part selection");
   if (flags & ~(uint32_t)(Q4C_ACCUMULATE | Q4C_ASSEMBLE_W | Q4C_ASSEMBLE_V | Q4C_CHECK_FINITE))
     return fail(Q4C_EINVAL, "unknown flag");
+  if ((flags & Q4C_ASSEMBLE_W) && (parts & (Q4C_PART_WS | Q4C_PART_WSO)) != (Q4C_PART_WS | Q4C_PART_WSO))
+    return fail(Q4C_EINVAL, "the W spinor blocks need the Ws and Wso parts");
+  if ((flags & Q4C_ASSEMBLE_V) && !(parts & Q4C_PART_V)) return fail(Q4C_EINVAL, "the V spinor blocks need V");
   if (p->n_points > 0 && !v_dev) return fail(Q4C_EINVAL, "NULL potential");
   if (p->store_len > 0 && !store_dev) return fail(Q4C_EINVAL, "NULL store");
   if ((flags & Q4C_ASSEMBLE_W) && p->store_len > 0 && !spin_w_dev) return fail(Q4C_EINVAL, "NULL W spinor output");
   if ((flags & Q4C_ASSEMBLE_V) && p->store_len > 0 && !spin_v_dev) return fail(Q4C_EINVAL, "NULL V spinor output");
   int rc = check_plan_dev(p);
   if (rc != Q4C_OK) return rc;
-  if (precision != Q4C_PREC_F64 && q4c::pad16(p->max_batch_points) > 64 * 16)
-    return fail(Q4C_EUNSUPPORTED, "split precisions need batches of at most 1024 points (p_max)");
   if (flags & Q4C_CHECK_FINITE) {
     bool ok = true;
     rc = q4c::launch_check_finite(p, v_dev, (hipStream_t)stream, &ok);
@@ -1058,15 +1058,19 @@ int q4c_integrate_H(const q4c_plan *p, const double *v_dev, int32_t precision, u
   p->panel_pass = -1;
   if (p->use_graphs && !p->profiling) {
     const uint32_t f = flags & ~(uint32_t)Q4C_CHECK_FINITE;
-    rc = run_graph(p, 0, v_dev, store_dev, spin_w_dev, spin_v_dev, precision, f, 0, (hipStream_t)stream,
+    rc = run_graph(p, 0, v_dev, store_dev, spin_w_dev, spin_v_dev, precision, f, parts, (hipStream_t)stream,
                    [&](hipStream_t cs) {
-                     return q4c::launch_integrate(p, v_dev, precision, f, store_dev, spin_w_dev, spin_v_dev, cs);
+                     return q4c::launch_integrate(p, v_dev, precision, parts, f, store_dev, spin_w_dev, spin_v_dev,
+                                                  cs);
                    });
   } else {
-    rc = q4c::launch_integrate(p, v_dev, precision, flags, store_dev, spin_w_dev, spin_v_dev, (hipStream_t)stream);
+    rc = q4c::launch_integrate(p, v_dev, precision, parts, flags, store_dev, spin_w_dev, spin_v_dev,
+                               (hipStream_t)stream);
   }
-  // every pass tabulates its W-path panels; the last pass's stay resident
-  if (rc == Q4C_OK) p->panel_pass = (int64_t)p->passes.size() - 1;
+  // an FP64 call with W parts tabulates FP64 panels of phi and its gradient
+  // (the adjoint's operands) in every pass; the last pass's stay resident
+  if (rc == Q4C_OK && precision == Q4C_PREC_F64 && (parts & (Q4C_PART_WS | Q4C_PART_WSO)))
+    p->panel_pass = (int64_t)p->passes.size() - 1;
   return rc;
 }
 
@@ -1587,10 +1591,12 @@ int q4c_integrate_HS(const q4c_plan *p, const double *v_dev, uint32_t flags, dou
   return q4c::launch_integrate_hs(p, v_dev, flags & ~(uint32_t)Q4C_CHECK_FINITE, hs_dev, (hipStream_t)stream);
 }
 
-int density_on_grid(const q4c_plan *p, const double *coef_dev, uint32_t terms, int32_t weight_mode, double *out_dev,
-                    void *stream) {
+int density_on_grid(const q4c_plan *p, const double *coef_dev, uint32_t terms, int32_t precision, int32_t weight_mode,
+                    double *out_dev, void *stream) {
   if (!p) return fail(Q4C_EINVAL, "NULL plan");
   if (terms == 0 || (terms & ~(uint32_t)Q4C_TERM_ALL)) return fail(Q4C_EINVAL, "bad term selection");
+  if (precision != Q4C_PREC_F64 && precision != Q4C_PREC_F32)
+    return fail(Q4C_EINVAL, "density_on_grid precision must be Q4C_PREC_F64 or Q4C_PREC_F32");
   if (weight_mode != 0 && weight_mode != 1) return fail(Q4C_EINVAL, "weight_mode must be 0 or 1");
   if (p->store_len > 0 && !coef_dev) return fail(Q4C_EINVAL, "NULL coefficients");
   if (p->n_points > 0 && !out_dev) return fail(Q4C_EINVAL, "NULL output");
@@ -1602,12 +1608,12 @@ int density_on_grid(const q4c_plan *p, const double *coef_dev, uint32_t terms, i
   const int64_t resident = p->panel_pass == (int64_t)p->passes.size() - 1 ? p->panel_pass : -1;
   p->panel_pass = -1;
   if (p->use_graphs && !p->profiling)
-    rc = run_graph(p, 1, coef_dev, out_dev, nullptr, nullptr, terms, weight_mode, resident, (hipStream_t)stream,
-                   [&](hipStream_t cs) {
-                     return q4c::launch_density(p, coef_dev, terms, weight_mode, out_dev, resident, cs);
+    rc = run_graph(p, 1, coef_dev, out_dev, nullptr, nullptr, terms | ((int64_t)precision << 8), weight_mode, resident,
+                   (hipStream_t)stream, [&](hipStream_t cs) {
+                     return q4c::launch_density(p, coef_dev, terms, precision, weight_mode, out_dev, resident, cs);
                    });
   else
-    rc = q4c::launch_density(p, coef_dev, terms, weight_mode, out_dev, resident, (hipStream_t)stream);
+    rc = q4c::launch_density(p, coef_dev, terms, precision, weight_mode, out_dev, resident, (hipStream_t)stream);
   // the passes ran from the last one down: pass 0's panels are resident
   if (rc == Q4C_OK && !p->passes.empty()) p->panel_pass = 0;
   return rc;
@@ -1691,9 +1697,9 @@ int q4c_plan_autotune(q4c_plan *p, const double *v_dev, int32_t precision, doubl
   };
   for (int kernel = 0; kernel < 2 && rc == Q4C_OK; ++kernel) {
     if (kernel == Q4C_KERNEL_DENSITY && !coef_dev) break;
-    // workgroups that fit on the chip at once: two per CU for the FP64
-    // contraction and the adjoint, one per CU for the split contraction
-    const int occ = (kernel == Q4C_KERNEL_CONTRACT && precision != Q4C_PREC_F64) ? 1 : 2;
+    // workgroups that fit on the chip at once: two per CU for every
+    // contraction kernel and the adjoint
+    const int occ = 2;
     const int cand_p[3] = {0, occ * p->n_cu, 2 * occ * p->n_cu};
     q4c::LaunchCfg best{};
     double best_ms = 1e300;
@@ -1706,10 +1712,12 @@ int q4c_plan_autotune(q4c_plan *p, const double *v_dev, int32_t precision, doubl
         c.persistent = cand_p[ip];
         double ms = 0.0;
         if (kernel == Q4C_KERNEL_CONTRACT)
-          rc = time_call([&] { return q4c::launch_integrate(p, v_dev, precision, 0, store_dev, nullptr, nullptr, s); },
-                         &ms);
+          rc = time_call([&] {
+            return q4c::launch_integrate(p, v_dev, precision, Q4C_PART_ALL, 0, store_dev, nullptr, nullptr, s);
+          }, &ms);
         else
-          rc = time_call([&] { return q4c::launch_density(p, coef_dev, Q4C_TERM_ALL, 1, out_dev, -1, s); }, &ms);
+          rc = time_call([&] { return q4c::launch_density(p, coef_dev, Q4C_TERM_ALL, Q4C_PREC_F64, 1, out_dev, -1, s); },
+                         &ms);
         if (rc != Q4C_OK) break;
         if (table && n_out < table_len) table[n_out] = q4c_tune_entry{kernel, order, cand_p[ip], ms};
         ++n_out;
@@ -1759,24 +1767,6 @@ int q4c_plan_profile(q4c_plan *p, int enable) {
   if (!p) return fail(Q4C_EINVAL, "NULL plan");
   if (!p->on_device) return fail(Q4C_ENODEV, "plan has no device data");
   p->profiling = enable != 0;
-  return Q4C_OK;
-}
-
-int q4c_plan_split_stats(const q4c_plan *p, int64_t *fp64_chunks, int64_t *total_chunks) {
-  int rc = check_plan_dev(p);
-  if (rc != Q4C_OK) return rc;
-  if (!fp64_chunks || !total_chunks) return fail(Q4C_EINVAL, "NULL argument");
-  unsigned long long h[128];
-  hipError_t e = hipDeviceSynchronize();
-  if (e == hipSuccess) e = hipMemcpy(h, p->d_chunks, sizeof(h), hipMemcpyDeviceToHost);
-  if (e != hipSuccess) return q4c::hip_fail(e, "hipMemcpy");
-  int64_t a = 0, t = 0;
-  for (int i = 0; i < 64; ++i) {
-    a += (int64_t)h[2 * i];
-    t += (int64_t)h[2 * i + 1];
-  }
-  *fp64_chunks = a;
-  *total_chunks = t;
   return Q4C_OK;
 }
 

@@ -62,6 +62,37 @@ def rel_to_scale(got, ref, scale, floor=0.0):
     return float(np.max(np.abs(got - ref) / (scale + floor))) if np.size(got) else 0.0
 
 
+def gamma(k: int) -> float:
+    """gamma_k = k u / (1 - k u) with the FP32 unit roundoff u = 2^-24."""
+    return k * 2.0 ** -24 / (1 - k * 2.0 ** -24)
+
+
+# The stated bound of the split precisions' W elements: FP32 partial sums over
+# 16 points, then FP64.  Per 16 points an element sums at most 48 products
+# (16 points x 3) with its operands rounded to FP32 at most three times
+# (panel, weight, product with the weight): gamma_52 of the magnitudes of its
+# terms for Q4C_PREC_F32; with hi + lo operands every product is three FP32
+# products, 144 per 16 points: gamma_150 for Q4C_PREC_SPLIT_F32.  Values below
+# FP32's normal range (2^-126) lose their relative precision; the far tails of
+# tight functions reach it, hence an absolute floor, far below any bar.
+SPLIT_GAMMA = {1: gamma(150), 2: gamma(52)}
+SPLIT_FLOOR = 1e-25  # Ha
+
+
+def split_bound_worst(got_blocks, ref_blocks, scale_blocks, precision):
+    """Largest |got - ref| / ((gamma + 1e-12) A_ij + floor) over the W parts
+    (1..4) of every element, A_ij the oracle's per-element scale."""
+    worst = 0.0
+    g_ = SPLIT_GAMMA[precision] + 1e-12
+    for g, r, s in zip(got_blocks, ref_blocks, scale_blocks):
+        g, r, s = g[1:], r[1:], s[1:]
+        nz = s > 0
+        assert np.all(g[~nz] == r[~nz])
+        if np.any(nz):
+            worst = max(worst, float(np.max(np.abs(g - r)[nz] / (g_ * s[nz] + SPLIT_FLOOR))))
+    return worst
+
+
 def per_point_worst(got, ref, scale, floor=0.0):
     """max |got - ref| / (scale + floor) over the entries whose scale is
     positive; where the scale is 0 (no term reaches the entry: outside every

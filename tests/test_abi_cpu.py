@@ -56,9 +56,9 @@ def test_host_only_plan_and_nodev_errors():
     p = _host_plan(q, wl)
     assert p.info["n_atoms"] == 3 and p.info["n_fn"] == 42
     assert p.info["device_bytes"] == 0
-    rc = lib.q4c_integrate_H(p.handle, ctypes.c_void_p(1), 0, 0, ctypes.c_void_p(1), None, None, None)
+    rc = lib.q4c_integrate_H(p.handle, ctypes.c_void_p(1), 0, 7, 0, ctypes.c_void_p(1), None, None, None)
     assert rc == q.Q4C_ENODEV
-    rc = lib.density_on_grid(p.handle, ctypes.c_void_p(1), 7, 0, ctypes.c_void_p(1), None)
+    rc = lib.density_on_grid(p.handle, ctypes.c_void_p(1), 7, 0, 0, ctypes.c_void_p(1), None)
     assert rc == q.Q4C_ENODEV
 
 
@@ -85,6 +85,21 @@ def test_store_layout_matches_pairs_and_sizes():
     assert lib.q4c_store_layout(p.handle, None, None, None, None) == q.Q4C_EINVAL
 
 
+def test_integrate_part_selection_checks():
+    """parts (Q4C_PART_*) must be a nonempty subset; spinor assembly needs its parts."""
+    q, lib = _lib()
+    p = _host_plan(q, W.config_small(nrad=10, nang=26))
+    one = ctypes.c_void_p(1)
+    call = lambda parts, flags: lib.q4c_integrate_H(p.handle, one, 0, parts, flags, one, one, one, None)
+    assert call(0, 0) == q.Q4C_EINVAL
+    assert call(8, 0) == q.Q4C_EINVAL
+    assert call(q.PART_V | q.PART_WS, q.ASSEMBLE_W) == q.Q4C_EINVAL
+    assert call(q.PART_WS | q.PART_WSO, q.ASSEMBLE_V) == q.Q4C_EINVAL
+    for parts in (1, 2, 4, 3, 6, 7):
+        assert call(parts, 0) == q.Q4C_ENODEV  # valid: fails only for want of device data
+    assert call(7, q.ASSEMBLE_W | q.ASSEMBLE_V) == q.Q4C_ENODEV
+
+
 def test_nao_tabulate_argument_checks():
     q, lib = _lib()
     wl = W.config_small(nrad=10, nang=26)
@@ -103,15 +118,17 @@ def test_argument_validation():
     wl = W.config_small(nrad=10, nang=26)
     p = _host_plan(q, wl)
     # bad precision / flags / terms / weight mode are rejected before any device work
-    assert lib.q4c_integrate_H(p.handle, ctypes.c_void_p(1), 7, 0, ctypes.c_void_p(1), None, None, None) == q.Q4C_EINVAL
-    assert lib.q4c_integrate_H(p.handle, ctypes.c_void_p(1), 0, 1 << 10, ctypes.c_void_p(1), None, None,
+    assert lib.q4c_integrate_H(p.handle, ctypes.c_void_p(1), 7, 7, 0, ctypes.c_void_p(1), None, None, None) == q.Q4C_EINVAL
+    assert lib.q4c_integrate_H(p.handle, ctypes.c_void_p(1), 0, 7, 1 << 10, ctypes.c_void_p(1), None, None,
                                None) == q.Q4C_EINVAL
-    assert lib.q4c_integrate_H(p.handle, None, 0, 0, ctypes.c_void_p(1), None, None, None) == q.Q4C_EINVAL
-    assert lib.q4c_integrate_H(p.handle, ctypes.c_void_p(1), 0, q.ASSEMBLE_W, ctypes.c_void_p(1), None, None,
+    assert lib.q4c_integrate_H(p.handle, None, 0, 7, 0, ctypes.c_void_p(1), None, None, None) == q.Q4C_EINVAL
+    assert lib.q4c_integrate_H(p.handle, ctypes.c_void_p(1), 0, 7, q.ASSEMBLE_W, ctypes.c_void_p(1), None, None,
                                None) == q.Q4C_EINVAL
-    assert lib.density_on_grid(p.handle, ctypes.c_void_p(1), 0, 0, ctypes.c_void_p(1), None) == q.Q4C_EINVAL
-    assert lib.density_on_grid(p.handle, ctypes.c_void_p(1), 7, 2, ctypes.c_void_p(1), None) == q.Q4C_EINVAL
-    assert lib.q4c_integrate_H(None, ctypes.c_void_p(1), 0, 0, ctypes.c_void_p(1), None, None, None) == q.Q4C_EINVAL
+    assert lib.density_on_grid(p.handle, ctypes.c_void_p(1), 0, 0, 0, ctypes.c_void_p(1), None) == q.Q4C_EINVAL
+    assert lib.density_on_grid(p.handle, ctypes.c_void_p(1), 7, 0, 2, ctypes.c_void_p(1), None) == q.Q4C_EINVAL
+    assert lib.density_on_grid(p.handle, ctypes.c_void_p(1), 7, q.PREC_SPLIT_F32, 1, ctypes.c_void_p(1), None) == q.Q4C_EINVAL
+    assert lib.density_on_grid(p.handle, ctypes.c_void_p(1), 7, 9, 1, ctypes.c_void_p(1), None) == q.Q4C_EINVAL
+    assert lib.q4c_integrate_H(None, ctypes.c_void_p(1), 0, 7, 0, ctypes.c_void_p(1), None, None, None) == q.Q4C_EINVAL
     n = ctypes.c_int64()
     assert lib.q4c_tabulate_size(p.handle, 0, p.info["n_batches"] + 1, 1, ctypes.byref(n)) == q.Q4C_EINVAL
     assert lib.q4c_tabulate_size(p.handle, 0, 1, 2, ctypes.byref(n)) == q.Q4C_EINVAL

@@ -15,7 +15,7 @@ import pytest
 
 import oracle
 import workload as W
-from helpers import blocks_to_store, gpu_available, per_point_worst, store_to_blocks
+from helpers import blocks_to_store, gpu_available, per_point_worst, split_bound_worst, store_to_blocks
 
 pytestmark = pytest.mark.gpu
 
@@ -154,27 +154,31 @@ def test_spinor_density_gradient_dot_product(env):
 
 def test_fullsize_split_error_bar(env):
     """Split-FP32 (hi+lo) and single-FP32 W parts within 1e-8 Ha: against the
-    oracle on sampled pair blocks, and over every stored element against the
-    FP64 path (itself within 1e-12 A_ij of the oracle), with some chunks routed
-    to FP64 MFMA by the bound."""
+    oracle on sampled pair blocks (and within the stated per-element bound
+    there), and over every stored element against the FP64 path (itself
+    within 1e-12 A_ij of the oracle)."""
     q, torch, wl, plan, pairs, po = env["q"], env["torch"], env["wl"], env["plan"], env["pairs"], env["po"]
     sel = _sample_pairs(pairs, wl)
-    ref = oracle.pair_blocks(wl, pairs[sel])
+    ref, scale = oracle.pair_blocks(wl, pairs[sel], with_abs=True)
     nfn = wl.atom_nfn()
     f64 = torch.from_numpy(env["store"]).cuda()
     for prec in (q.PREC_SPLIT_F32, q.PREC_F32):
         st = q.new_store(plan)
         q.q4c_integrate_H(plan, env["v"], prec, 0, st)
         torch.cuda.synchronize()
-        hot, tot = plan.split_stats()
-        assert 0 < hot < tot
         s = st.cpu().numpy()
         err = 0.0
+        got = []
         for k, p in enumerate(sel):
             a, b = pairs[p]
             g = s[:, po[p]:po[p + 1]].reshape(5, nfn[a], nfn[b])
+            got.append(g)
             err = max(err, float(np.max(np.abs(g - ref[k]))))
-        assert err <= 1e-8, (prec, err)
-        assert float(torch.max(torch.abs(st - f64))) <= 1e-8
+        worst = split_bound_worst(got, ref, scale, prec)
+        d_all = float(torch.max(torch.abs(st - f64)))
+        print("precision %d: sampled blocks max |d| %.3g Ha (worst / bound %.3g), all elements vs FP64 %.3g Ha" %
+              (prec, err, worst, d_all), flush=True)
+        assert err <= 1e-8 and worst <= 1.0, (prec, err, worst)
+        assert d_all <= 1e-8
         # V stays FP64: identical to the FP64 path
         assert torch.equal(st[0], f64[0])

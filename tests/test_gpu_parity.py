@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import workload as W
-from helpers import gpu_available, per_point_worst, spinor_to_blocks, store_to_blocks
+from helpers import gamma, gpu_available, per_point_worst, spinor_to_blocks, split_bound_worst, store_to_blocks
 
 pytestmark = pytest.mark.gpu
 
@@ -254,6 +254,39 @@ def test_density_matches_oracle(q, small):
         assert worst <= 1e-12, (mode, worst)
 
 
+def test_density_f32_stated_bound(q, small):
+    """density_on_grid in FP32 (SS and SO terms on FP32 MFMA): every point
+    within gamma_98 (u = 2^-24) of the magnitudes of its SS and SO terms plus
+    the FP64 bar on all terms; the LL term alone equals the FP64 path bit for
+    bit (it stays FP64)."""
+    torch = _torch()
+    wl, pairs, _, _ = small
+    plan = q.Plan(wl)
+    _, po = plan.pairs()
+    nfn = wl.atom_nfn()
+    rng = np.random.default_rng(79)
+    coef_blocks = [rng.standard_normal((5, nfn[a], nfn[b])) for a, b in pairs]
+    from helpers import blocks_to_store
+    coef = torch.from_numpy(blocks_to_store(coef_blocks, po)).cuda()
+    for mode in (0, 1):
+        out = torch.full((wl.n_points,), float("nan"), dtype=torch.float64, device="cuda")
+        q.density_on_grid(plan, coef, q.TERM_ALL, mode, out, precision=q.PREC_F32)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        ref, sc = oracle.density(wl, pairs, coef_blocks, weight_mode=mode, with_scale=True)
+        w = wl.w if mode else None
+        bound = gamma(98) * oracle.density_scale(sc, w, terms=6) + 1e-12 * oracle.density_scale(sc, w)
+        worst = per_point_worst(got, ref, bound, floor=1e-30)
+        print("F32 adjoint, weight mode %d: worst |d| / bound %.3g" % (mode, worst), flush=True)
+        assert worst <= 1.0, (mode, worst)
+    ll = {}
+    for prec in (q.PREC_F64, q.PREC_F32):
+        ll[prec] = torch.empty(wl.n_points, dtype=torch.float64, device="cuda")
+        q.density_on_grid(plan, coef, q.TERM_LL, 1, ll[prec], precision=prec)
+    torch.cuda.synchronize()
+    assert torch.equal(ll[q.PREC_F64], ll[q.PREC_F32])
+
+
 def test_density_terms_and_dot_product(q, small):
     """Adjoint identity through the library alone: <density(C, weighted), dv> = <C, H(dv)>."""
     torch = _torch()
@@ -346,19 +379,24 @@ def test_density_multitile(q, medium):
     rng = np.random.default_rng(79)
     coef_blocks = [rng.standard_normal((5, nfn[a], nfn[b])) for a, b in pairs]
     idx = np.sort(rng.choice(wl.n_points, size=1500, replace=False))
-    ref, sc = oracle.density(wl, pairs, coef_blocks, idx=idx, weight_mode=1, with_scale=True)
-    sc = oracle.density_scale(sc, wl.w[idx])
+    ref, scp = oracle.density(wl, pairs, coef_blocks, idx=idx, weight_mode=1, with_scale=True)
+    sc = oracle.density_scale(scp, wl.w[idx])
+    bound32 = gamma(98) * oracle.density_scale(scp, wl.w[idx], terms=6) + 1e-12 * sc
     from helpers import blocks_to_store
     for p_max, staging in ((300, 0), (64, 1 << 20)):
         plan = q.Plan(wl, p_max=p_max, staging_bytes=staging)
         _, po = plan.pairs()
         coef = torch.from_numpy(blocks_to_store(coef_blocks, po)).cuda()
-        out = torch.full((wl.n_points,), float("nan"), dtype=torch.float64, device="cuda")
-        q.density_on_grid(plan, coef, q.TERM_ALL, 1, out)
-        torch.cuda.synchronize()
-        got = out.cpu().numpy()
-        assert np.all(np.isfinite(got))
-        assert per_point_worst(got[idx], ref, sc) <= 1e-12, (p_max, staging)
+        for prec in (q.PREC_F64, q.PREC_F32):
+            out = torch.full((wl.n_points,), float("nan"), dtype=torch.float64, device="cuda")
+            q.density_on_grid(plan, coef, q.TERM_ALL, 1, out, precision=prec)
+            torch.cuda.synchronize()
+            got = out.cpu().numpy()
+            assert np.all(np.isfinite(got))
+            if prec == q.PREC_F64:
+                assert per_point_worst(got[idx], ref, sc) <= 1e-12, (p_max, staging)
+            else:
+                assert per_point_worst(got[idx], ref, bound32, floor=1e-30) <= 1.0, (p_max, staging)
 
 
 def test_staging_passes_do_not_change_results(q, medium):
@@ -389,48 +427,64 @@ def test_staging_passes_do_not_change_results(q, medium):
         assert torch.equal(x, y)
 
 
-def test_split_all_chunks_deferred_equals_f64(q, medium):
-    """With a vanishing routing bound every 16-point chunk's W products are
-    deferred to FP64 (added to zeros in the same MFMA order): the split and
-    FP32 stores then equal the FP64 store bit for bit.  A huge bound defers
-    none and keeps the 1e-8 Ha bar against the FP64 path only as an error
-    report (no chunk on FP64)."""
+def test_split_precisions_stated_bound_and_long_batches(q, medium):
+    """The split precisions (FP32 W parts, FP64 V) against the oracle on every
+    element of the multi-tile case, with batches of at most 300 and of at
+    most 1,024 points: each W element within the stated bound (gamma of the
+    16-point FP32 partial sums times the magnitudes of its terms, plus the
+    FP32 underflow floor), within 1e-8 Ha, and V bitwise equal to the FP64
+    path's."""
+    torch = _torch()
+    wl, pairs, ref, scale = medium
+    v = torch.from_numpy(wl.v).cuda()
+    for p_max in (300, 1024):
+        plan = q.Plan(wl, p_max=p_max)
+        print("p_max %d: largest batch %d points" % (p_max, plan.info["max_batch_points"]), flush=True)
+        _, po = plan.pairs()
+        f64 = q.new_store(plan)
+        q.q4c_integrate_H(plan, v, q.PREC_F64, 0, f64)
+        for prec in (q.PREC_SPLIT_F32, q.PREC_F32):
+            st = q.new_store(plan)
+            q.q4c_integrate_H(plan, v, prec, 0, st)
+            torch.cuda.synchronize()
+            assert torch.equal(st[0], f64[0]), (p_max, prec)
+            got = store_to_blocks(st.cpu().numpy(), pairs, po, wl.atom_nfn())
+            worst = split_bound_worst(got, ref, scale, prec)
+            err = max(float(np.max(np.abs(g[1:] - r[1:]))) for g, r in zip(got, ref))
+            print("  precision %d: max |W - oracle| %.3g Ha, worst / bound %.3g" % (prec, err, worst), flush=True)
+            assert worst <= 1.0 and err <= SPLIT_ABS, (p_max, prec, worst, err)
+
+
+def test_parts_mask(q, medium):
+    """Selected parts equal the all-parts call bit for bit; parts not selected
+    keep what the store held; V-only and W-only calls in every precision."""
     torch = _torch()
     wl = medium[0]
+    plan = q.Plan(wl)
     v = torch.from_numpy(wl.v).cuda()
-    ref = q.new_store(q.Plan(wl))
-    q.q4c_integrate_H(q.Plan(wl), v, q.PREC_F64, 0, ref)
-    plan = q.Plan(wl, split_threshold=1e-300)
-    for prec in (q.PREC_SPLIT_F32, q.PREC_F32):
-        st = q.new_store(plan)
-        q.q4c_integrate_H(plan, v, prec, 0, st)
+    rows = {"V": [0], "WS": [1], "WSO": [2, 3, 4]}
+    bits = {"V": q.PART_V, "WS": q.PART_WS, "WSO": q.PART_WSO}
+    for prec in (q.PREC_F64, q.PREC_F32, q.PREC_SPLIT_F32):
+        full = q.new_store(plan)
+        q.q4c_integrate_H(plan, v, prec, 0, full)
+        for sel in (("V",), ("WS",), ("WSO",), ("V", "WS"), ("WS", "WSO")):
+            parts = sum(bits[k] for k in sel)
+            st = torch.full_like(full, 7.0)
+            q.q4c_integrate_H(plan, v, prec, 0, st, parts=parts)
+            torch.cuda.synchronize()
+            on = sorted(r for k in sel for r in rows[k])
+            off = [r for r in range(5) if r not in on]
+            assert torch.equal(st[on], full[on]), (prec, sel)
+            assert bool(torch.all(st[off] == 7.0)), (prec, sel)
+        # accumulate one part onto another call's result
+        acc = full.clone()
+        q.q4c_integrate_H(plan, v, prec, q.ACCUMULATE, acc, parts=q.PART_V)
         torch.cuda.synchronize()
-        hot, tot = plan.split_stats()
-        # chunks whose bound is exactly zero (every W product is zero) stay on FP32
-        assert tot > 0 and hot > 0.9 * tot
-        assert torch.equal(st, ref), prec
-    cold = q.Plan(wl, split_threshold=1e300)
-    st = q.new_store(cold)
-    q.q4c_integrate_H(cold, v, q.PREC_F32, 0, st)
-    torch.cuda.synchronize()
-    hot, tot = cold.split_stats()
-    assert hot == 0 and tot > 0
-    assert torch.equal(st[0], ref[0])
-    print("no chunk on FP64: max |W - W_f64| = %.3g Ha" % float(torch.max(torch.abs(st[1:] - ref[1:]))), flush=True)
-
-
-def test_split_rejects_batches_over_1024_points(q, small):
-    torch = _torch()
-    wl = small[0]
-    plan = q.Plan(wl, p_max=2048)
-    if plan.info["max_batch_points"] <= 1024:
-        pytest.skip("workload too small for a batch above 1024 points")
-    v = torch.from_numpy(wl.v).cuda()
-    st = q.new_store(plan)
-    with pytest.raises(q.Q4CError) as e:
-        q.q4c_integrate_H(plan, v, q.PREC_F32, 0, st)
-    assert e.value.status == q.Q4C_EUNSUPPORTED
-    q.q4c_integrate_H(plan, v, q.PREC_F64, 0, st)  # FP64 has no such limit
+        assert torch.equal(acc[1:], full[1:])
+        # the batch sums are added one by one onto the stored value
+        assert float(torch.max(torch.abs(acc[0] - 2 * full[0]))) <= 1e-13 * float(torch.max(torch.abs(full[0])))
+    with pytest.raises(q.Q4CError):
+        q.q4c_integrate_H(plan, v, q.PREC_F64, q.ASSEMBLE_W, q.new_store(plan), q.new_spinor(plan), parts=q.PART_WS)
 
 
 def test_adjoint_reuses_resident_panels_bitwise(q, medium):

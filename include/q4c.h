@@ -400,6 +400,24 @@ int q4c_plan_cell_pairs(const q4c_plan *plan, int64_t *n_cell_pairs, int32_t *pa
 int q4c_bloch_sum(const q4c_plan *plan, int32_t n_parts, const double *store_dev, int32_t n_k,
                   const double *k_points, double *out_dev, void *stream);
 
+/* q4c_bloch_sum_noalloc: q4c_bloch_sum for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): no allocation, no host copy, no synchronisation.
+ * The k-points come as a device array (k_points_dev: 3 n_k doubles, bohr^-1;
+ * not checked for finiteness), and the phase table of each chunk of
+ * k-points lives in a fixed device array of the library
+ * (Q4C_NOALLOC_SCRATCH_BYTES = 4 MiB on each device it runs on, held until
+ * the process ends): the k-points are processed in chunks whose phases
+ * (16 bytes per contribution and k-point) fit, so a plan whose one k-point
+ * needs more gives Q4C_ESIZE.  Every call on a GPU shares that GPU's array
+ * (each chunk's phases are written before they are read, nothing needs to
+ * start at zero): calls that overlap in time on one GPU race, so serialise
+ * them (one stream).  Other arguments, layout and results as
+ * q4c_bloch_sum (bitwise equal). */
+#define Q4C_NOALLOC_SCRATCH_BYTES (4u << 20)
+int q4c_bloch_sum_noalloc(const q4c_plan *plan, int32_t n_parts, const double *store_dev, int32_t n_k,
+                          const double *k_points_dev, double *out_dev, void *stream);
+
 /* q4c_bloch_density: the reverse of q4c_bloch_sum, the periodic density
  * matrix of Sec. II C.  From k-space density matrices rho(k) of the cell's
  * functions (Hermitian, e.g. sum over states of f_l C*_al(k) C_bl(k)), the

@@ -92,7 +92,8 @@ EXPORTS = ("q4c_plan_create", "q4c_plan_destroy", "q4c_plan_info", "q4c_plan_pai
            "q4c_last_error", "q4c_plan_create_batched", "q4c_plan_systems", "q4c_plan_set_launch",
            "q4c_plan_get_launch", "q4c_plan_autotune", "q4c_plan_set_graphs", "q4c_plan_set_ket_potential",
            "q4c_integrate_HS", "q4c_spinor_transform", "q4c_spinor_density_to_scalar", "density_gradient_on_grid",
-           "q4c_plan_set_cells", "q4c_plan_cell_pairs", "q4c_bloch_sum", "q4c_bloch_density")
+           "q4c_plan_set_cells", "q4c_plan_cell_pairs", "q4c_bloch_sum", "q4c_bloch_density",
+           "q4c_bloch_sum_noalloc")
 
 
 def _load():
@@ -137,6 +138,7 @@ def _load():
         lib.q4c_plan_cell_pairs.argtypes = [vp, ctypes.POINTER(i64), vp, vp]
         lib.q4c_bloch_sum.argtypes = [vp, i32, vp, i32, vp, vp, vp]
         lib.q4c_bloch_density.argtypes = [vp, i32, vp, i32, vp, vp, vp, vp]
+        lib.q4c_bloch_sum_noalloc.argtypes = [vp, i32, vp, i32, vp, vp, vp]
         lib.q4c_status_string.argtypes = [ctypes.c_int]
         lib.q4c_status_string.restype = ctypes.c_char_p
         lib.q4c_last_error.argtypes = []
@@ -439,6 +441,18 @@ def q4c_bloch_sum(plan: Plan, n_parts: int, store, k_points, out):
                                  int(kp.shape[0]), kp.ctypes.data,
                                  _dev_ptr(out, min_numel=2 * kp.shape[0] * n_parts * int(po[-1]), name="out"),
                                  _stream_handle()))
+    return out
+
+
+def q4c_bloch_sum_noalloc(plan: Plan, n_parts: int, store, k_points_dev, out):
+    """q4c_bloch_sum with the k-points on the device (k_points_dev: float64 CUDA
+    tensor [n_k, 3]) and the library's fixed scratch: allocates nothing."""
+    n_k = int(k_points_dev.numel() // 3)
+    _, po = plan.cell_pairs()
+    _check(_load().q4c_bloch_sum_noalloc(
+        plan.handle, int(n_parts), _dev_ptr(store, min_numel=n_parts * plan.info["store_len"], name="store"), n_k,
+        _dev_ptr(k_points_dev, min_numel=3 * n_k, name="k_points_dev"),
+        _dev_ptr(out, min_numel=2 * n_k * n_parts * int(po[-1]), name="out"), _stream_handle()))
     return out
 
 

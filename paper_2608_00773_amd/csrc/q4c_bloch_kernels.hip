@@ -20,9 +20,18 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <mutex>
+#include <optional>
 
 #include "q4c_internal.h"
 #include "q4c_device.h"
+
+// Fixed device scratch of q4c_bloch_sum_noalloc (the phase table of one
+// k-point chunk), for callers that cannot allocate.  Each device the library
+// runs on holds its own copy until the process ends; every call on a device
+// shares it.  Host code must not pass this name to a kernel (it is a host
+// stand-in there): it uses the device address from hipGetSymbolAddress.
+static __device__ __align__(256) double scratch[q4c::kNoAllocScratchDoubles];
 
 namespace q4c {
 namespace {
@@ -186,16 +195,21 @@ __global__ __launch_bounds__(256) void k_bloch_density(DevPlan d, int n_parts, i
 
 }  // namespace
 
-int launch_bloch_sum(const q4c_plan *p, int n_parts, const double *store, int n_k, const double *kpts_dev,
-                     double *phase, double *out, hipStream_t s) {
+// Phase table, then the sums, for chunks of at most kchunk (<= KB) k-points;
+// phase holds 2 kchunk n_contrib doubles.  timed: record the plan's profiling
+// events (created on demand) when profiling is on.
+static int launch_bloch_sum_chunks(const q4c_plan *p, int n_parts, const double *store, int n_k,
+                                   const double *kpts_dev, double *phase, int kchunk, bool timed, double *out,
+                                   hipStream_t s) {
   const int64_t ncp = (int64_t)p->cp_a.size();
   const int64_t clen = p->cp_off.back();
   const int64_t n_ct = p->n_contrib;
   if ((int64_t)n_k * n_parts * clen == 0) return Q4C_OK;
-  for (int k0 = 0; k0 < n_k; k0 += KB) {
-    const int nk = std::min(KB, n_k - k0);
+  for (int k0 = 0; k0 < n_k; k0 += kchunk) {
+    const int nk = std::min(kchunk, n_k - k0);
     {
-      TimedLaunch tl_(p, Q4C_TIMER_OTHER, s);
+      std::optional<TimedLaunch> tl_;
+      if (timed) tl_.emplace(p, Q4C_TIMER_OTHER, s);
       const int64_t tot = (int64_t)nk * n_ct;
       const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((tot + 255) / 256, 65536));
       hipLaunchKernelGGL(k_bloch_phase, dim3(grid), dim3(256), 0, s, nk, n_ct, kpts_dev + 3 * (int64_t)k0,
@@ -204,7 +218,8 @@ int launch_bloch_sum(const q4c_plan *p, int n_parts, const double *store, int n_
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "k_bloch_phase");
     {
-      TimedLaunch tl_(p, Q4C_TIMER_BLOCH, s);
+      std::optional<TimedLaunch> tl_;
+      if (timed) tl_.emplace(p, Q4C_TIMER_BLOCH, s);
       const unsigned grid = (unsigned)(ncp * n_parts);
       hipLaunchKernelGGL(k_bloch_sum, dim3(grid), dim3(256), 0, s, p->dp, n_parts, ncp, p->d_cp_off, p->d_ct_off,
                          p->d_ct_pair, p->d_ct_flag, nk, (const double *)phase, store,
@@ -214,6 +229,44 @@ int launch_bloch_sum(const q4c_plan *p, int n_parts, const double *store, int n_
     if (e != hipSuccess) return hip_fail(e, "k_bloch_sum");
   }
   return Q4C_OK;
+}
+
+int launch_bloch_sum(const q4c_plan *p, int n_parts, const double *store, int n_k, const double *kpts_dev,
+                     double *phase, double *out, hipStream_t s) {
+  return launch_bloch_sum_chunks(p, n_parts, store, n_k, kpts_dev, phase, KB, true, out, s);
+}
+
+// Device address of `scratch` per device, looked up once per device (with
+// that device current) on its first use.
+static std::mutex g_scratch_mu;
+static double *g_scratch_dev[kMaxDevices] = {};
+
+int noalloc_scratch(int device, double **ptr) {
+  if (device < 0 || device >= kMaxDevices) return fail_status(Q4C_EUNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    void *addr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    g_scratch_dev[device] = static_cast<double *>(addr);
+  }
+  *ptr = g_scratch_dev[device];
+  return Q4C_OK;
+}
+
+int launch_bloch_sum_noalloc(const q4c_plan *p, int n_parts, const double *store, int n_k, const double *kpts_dev,
+                             double *out, hipStream_t s) {
+  double *phase = nullptr;
+  int rc = noalloc_scratch(p->device, &phase);
+  if (rc != Q4C_OK) return rc;
+  // the phases of one k-point take 2 n_contrib doubles: as many k-points per
+  // chunk as the scratch holds (at most KB)
+  const int64_t per_k = 2 * std::max<int64_t>(p->n_contrib, 1);
+  if (per_k > kNoAllocScratchDoubles)
+    return fail_status(Q4C_ESIZE, "the phases of one k-point exceed the fixed scratch of q4c_bloch_sum_noalloc");
+  const int kchunk = (int)std::min<int64_t>(KB, kNoAllocScratchDoubles / per_k);
+  // no profiling events here: creating one may allocate
+  return launch_bloch_sum_chunks(p, n_parts, store, n_k, kpts_dev, phase, kchunk, false, out, s);
 }
 
 int launch_bloch_density(const q4c_plan *p, int n_parts, const double *rho, int n_k, const double *kpts_dev,

@@ -288,6 +288,14 @@ int launch_grad_pass(const q4c_plan *p, size_t ip, const double *coef, const dou
 constexpr int kBlochKChunk = 64;
 int launch_bloch_sum(const q4c_plan *p, int n_parts, const double *store, int n_k, const double *kpts_dev,
                      double *phase, double *out, hipStream_t s);
+// q4c_bloch_sum_noalloc: the phase table in the library's fixed device
+// scratch (kNoAllocScratchDoubles per device, address looked up once per
+// device), k-points already on the device
+constexpr int64_t kNoAllocScratchDoubles = (int64_t)1 << 19;  // 4 MiB
+constexpr int kMaxDevices = 64;
+int noalloc_scratch(int device, double **ptr);
+int launch_bloch_sum_noalloc(const q4c_plan *p, int n_parts, const double *store, int n_k, const double *kpts_dev,
+                             double *out, hipStream_t s);
 int launch_bloch_density(const q4c_plan *p, int n_parts, const double *rho, int n_k, const double *kpts_dev,
                          const double *kw_dev, double *phase, double *coef, hipStream_t s);
 // spinor density -> scalar density matrices of both components (q4c_spinor_kernels.hip)

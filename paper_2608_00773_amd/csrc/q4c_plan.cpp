@@ -1556,6 +1556,19 @@ int q4c_bloch_sum(const q4c_plan *p, int32_t n_parts, const double *store_dev, i
   return q4c::launch_bloch_sum(p, n_parts, store_dev, n_k, p->d_kpts, p->d_bloch_ph, out_dev, (hipStream_t)stream);
 }
 
+int q4c_bloch_sum_noalloc(const q4c_plan *p, int32_t n_parts, const double *store_dev, int32_t n_k,
+                          const double *k_points_dev, double *out_dev, void *stream) {
+  if (!p) return fail(Q4C_EINVAL, "NULL plan");
+  if (n_parts != 1 && n_parts != 2 && n_parts != 5) return fail(Q4C_EINVAL, "n_parts must be 1, 2 or 5");
+  if (n_k < 0) return fail(Q4C_EINVAL, "negative n_k");
+  int rc = check_plan_dev(p);  // makes the plan's device current
+  if (rc != Q4C_OK) return rc;
+  if (p->n_cell_atoms == 0) return fail(Q4C_EINVAL, "no periodic cell set (q4c_plan_set_cells)");
+  if (n_k == 0 || p->cp_a.empty()) return Q4C_OK;
+  if (!k_points_dev || !store_dev || !out_dev) return fail(Q4C_EINVAL, "NULL argument");
+  return q4c::launch_bloch_sum_noalloc(p, n_parts, store_dev, n_k, k_points_dev, out_dev, (hipStream_t)stream);
+}
+
 int q4c_bloch_density(const q4c_plan *p, int32_t n_parts, const double *rho_dev, int32_t n_k, const double *k_points,
                       const double *k_weights, double *coef_out_dev, void *stream) {
   if (!p) return fail(Q4C_EINVAL, "NULL plan");

@@ -27,8 +27,9 @@ if ROOT not in sys.path:
 METRIC = "H-integration grid points/s & MFMA util: split-FP32 vs FP64 at ≤1e-8 Ha"
 PEAK_F64 = 78.6e12    # MI355X dense FP64 MFMA, flop/s
 PEAK_F32 = 157.3e12   # MI355X dense FP32 MFMA, flop/s
+PEAK_BF16 = 2.5e15    # MI355X dense BF16 MFMA, flop/s
 PEAK_HBM = 8.0e12     # MI355X HBM3E, bytes/s
-PREC = {"f64": 0, "split": 1, "f32": 2}
+PREC = {"f64": 0, "split": 1, "f32": 2, "bf16x3": 3}
 
 # HBM bytes per launch of the path's kernels on the default cluster workload,
 # from two rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE), each scaled by what
@@ -103,9 +104,13 @@ def parse():
 def contraction_peak(prec: str) -> float:
     """Peak of the contraction kernel for its operand types: 1 of the 10 P n^2
     algorithmic flops (V) runs on FP64 MFMA in every mode; the other 9 (W parts)
-    run on FP64 MFMA (f64) or FP32 MFMA (split, f32)."""
+    run on FP64 MFMA (f64), FP32 MFMA (split, f32: one FP32 product per
+    product, the hi/lo mode's extra two counted as its own overhead) or BF16
+    MFMA with six BF16 products per product (bf16x3)."""
     if prec == "f64":
         return PEAK_F64
+    if prec == "bf16x3":
+        return 10.0 / (1.0 / PEAK_F64 + 9.0 * 6.0 / PEAK_BF16)
     return 10.0 / (1.0 / PEAK_F64 + 9.0 / PEAK_F32)
 
 
@@ -612,6 +617,8 @@ def main():
         h_only[name]["speedup_vs_f64"] = h_only["f64"]["ms_median"] / h_only[name]["ms_median"]
     err = {n: [float(torch.max(torch.abs(outs[n][k] - outs["f64"][k]))) for k in range(5)] for n in outs}
     ms_adj = float(np.median(timed_each(lambda: q.density_on_grid(plan, gbar, q.TERM_ALL, 1, grad), 20, 3)))
+    ms_adj32 = float(np.median(timed_each(
+        lambda: q.density_on_grid(plan, gbar, q.TERM_ALL, 1, grad, precision=q.PREC_F32), 20, 3)))
 
     # nao_tabulate (the ABI call; the same tabulation as the panels) over the
     # first quarter of the batches: FP64 phi and grad phi, 32 B written per
@@ -637,7 +644,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"f64": "f64", "split": "f32-hi/lo+f64", "f32": "f32+f64"}[a.precision],
+        "dtype": {"f64": "f64", "split": "f32-hi/lo+f64", "f32": "f32+f64", "bf16x3": "bf16x3+f64"}[a.precision],
         "data": "synthetic",
         "config": {
             "workload": "%s, %d atoms, %d NAOs, %d points (%d active), %d batches <= 300 pts" %
@@ -655,6 +662,7 @@ def main():
         "h_only": h_only,
         "h_only_points_per_s": h_only[a.precision]["points_per_s"],
         "adjoint_ms_median": ms_adj,
+        "adjoint_ms_median_f32": ms_adj32,
         "nao_tabulate": nao_tab,
         "launch": {"contract": plan.get_launch(q.KERNEL_CONTRACT), "density": plan.get_launch(q.KERNEL_DENSITY),
                    "graphs": tune is not None and not a.no_graphs, "autotune_table": tune},

@@ -69,6 +69,17 @@ __device__ __forceinline__ flt4 mfma32(float a, float b, flt4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// BF16 MFMA 16x16x32 with FP32 accumulation; each operand is 8 BF16 values
+// (16 bytes) per lane: lane l holds A[l % 16][8 (l / 16) + e] and
+// B[8 (l / 16) + e][l % 16], e = 0..7 (element e in bits 16 (e % 2) of word
+// e / 2); register r of D is D[4 (l / 16) + r][l % 16].
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ flt4 mfma_bf16(u32x4 a, u32x4 b, flt4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0,
+                                                 0, 0);
+}
+
 // Staging address of element (li, lj) of a batch (local function indices) for
 // part q, given the slot data of li (row) and lj (column).
 struct SlotInfo {

@@ -353,14 +353,38 @@ __global__ void k_om(DevPlan d, const double *v, double *om) {
 //   PK_F32:   phi in FP64 (1 plane), then d/dx, d/dy, d/dz as FP32 planes
 //             (Pp np floats each) after it
 //   PK_SPLIT: as PK_F32, then the three lo planes fl32(x - hi)
-// Every plane uses the 4-point interleave of panel_index (FP32 planes
-// counted in floats).
-enum { PK_F64 = 0, PK_HS = 1, PK_F32 = 2, PK_SPLIT = 3 };
+//   PK_BF16:  phi in FP64 (1 plane), then the BF16 region: for side s (0:
+//             the gradient itself, row operand; 1: w v times the gradient,
+//             column operand), component q and split part t, plane
+//             s 9 + 3 q + t of (Pp / 8) point octets x np functions x 8
+//             points (16 bytes per function and octet)
+// The FP64 and FP32 planes use the 4-point interleave of panel_index (FP32
+// planes counted in floats).
+enum { PK_F64 = 0, PK_HS = 1, PK_F32 = 2, PK_SPLIT = 3, PK_BF16 = 4 };
+
+// BF16 (8 significant bits) three-way split of two values a, b at once:
+// each is rounded to FP32, and each part is the BF16 nearest (ties to even)
+// to what the previous parts leave; the remainders are exact in FP32, so
+// |x - x1 - x2 - x3| <= (2^-24 + 2^-24) |x|.  Part k of both values comes
+// as one word wk (a in the low half, b in the high half), from one packed
+// conversion per part.
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{a, b}, bf16x2));
+}
+__device__ __forceinline__ void split3_bf16x2(double a, double b, uint32_t &w1, uint32_t &w2, uint32_t &w3) {
+  const float fa = (float)a, fb = (float)b;
+  w1 = pack_bf16(fa, fb);
+  const float ra = fa - __uint_as_float(w1 << 16), rb = fb - __uint_as_float(w1 & 0xffff0000u);
+  w2 = pack_bf16(ra, rb);
+  w3 = pack_bf16(ra - __uint_as_float(w2 << 16), rb - __uint_as_float(w2 & 0xffff0000u));
+}
 constexpr int PLD = T + 1;  // padded LDS row of the panel stage
 
 template <int KIND>
 __global__ __launch_bounds__(256) void k_panel(DevPlan d, const WorkItem *tiles, int64_t t0, int64_t nt,
-                                               double *panel) {
+                                               double *panel, const double *om) {
   constexpr bool HS = KIND == PK_HS;
   constexpr int NQ = HS ? 2 : 4;  // components: phi, psi (H/S) or phi and its gradient
   constexpr int CP = 8;           // points per chunk: a small stage keeps 7 workgroups on a CU
@@ -398,8 +422,9 @@ __global__ __launch_bounds__(256) void k_panel(DevPlan d, const WorkItem *tiles,
     }
     __syncthreads();
     // (q, point quad) runs: rows r0 .. r0 + nrow - 1, 4 points each, contiguous
+    constexpr int NQW = KIND == PK_BF16 ? 1 : NQ;  // PK_BF16: phi here, the gradient below
 #pragma unroll
-    for (int q = 0; q < NQ; ++q)
+    for (int q = 0; q < NQW; ++q)
 #pragma unroll
       for (int p4 = 0; p4 < CP / 4; ++p4) {
         const int e = threadIdx.x;  // 256 = 64 rows x 4 points
@@ -416,6 +441,32 @@ __global__ __launch_bounds__(256) void k_panel(DevPlan d, const WorkItem *tiles,
           }
         }
       }
+    if (KIND == PK_BF16) {
+      // one task per (side, component, function): the 8 points of this octet,
+      // split into three BF16 parts, 16 bytes per part
+      u32x4 *pbf = reinterpret_cast<u32x4 *>(pb + fplane);
+      const int64_t noct = Pp >> 3;
+      for (int t = threadIdx.x; t < 2 * 3 * T; t += 256) {
+        const int il = t % T, q = (t / T) % 3, side = t / (3 * T);
+        if (il >= nrow) continue;
+        u32x4 w[3];
+#pragma unroll
+        for (int e = 0; e < CP; e += 2) {
+          double xa = st[((q + 1) * CP + e) * PLD + il], xb = st[((q + 1) * CP + e + 1) * PLD + il];
+          if (side) {
+            xa *= g8 + e < P ? om[g0 + g8 + e] : 0.0;
+            xb *= g8 + e + 1 < P ? om[g0 + g8 + e + 1] : 0.0;
+          }
+          uint32_t w1, w2, w3;
+          split3_bf16x2(xa, xb, w1, w2, w3);
+          w[0][e >> 1] = w1;
+          w[1][e >> 1] = w2;
+          w[2][e >> 1] = w3;
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) pbf[((int64_t)(side * 9 + 3 * q + k) * noct + (g8 >> 3)) * np + r0 + il] = w[k];
+      }
+    }
     __syncthreads();  // st consumed
   }
 }
@@ -739,6 +790,267 @@ __global__ __launch_bounds__(NT, 2) void k_contract_w(DevPlan d, const WorkItem 
   }
   if (!PERSIST) break;
   pos = next_item(tickets, nw, order != nullptr, &s_pos);
+  }
+}
+
+// BF16X3 precision: V on FP64 MFMA and the four W parts on BF16 MFMA with
+// three-way split operands (PK_BF16 panels), in one kernel.  One workgroup
+// per column half (32 columns) of a work item's 64 x 64 tile; wave w takes
+// the 16-row block w against the half's two 16-column blocks, so each A
+// operand it reads serves both.  Per 16-point chunk the four images (FP64 phi
+// of rows and columns, BF16 gradient parts of rows and of w v times the
+// gradient of columns) arrive by LDS DMA, double-buffered, with w v of the
+// chunk's points.
+// W products: a b ~ a1 b1 + a2 b1 + a1 b2 + a1 b3 + a2 b2 + a3 b1 (the terms
+// of order 2^-16 and above), three MFMAs of K = 32 per component pair: the
+// K index runs over two slots of the chunk's 16 points, slot 0 (lanes with
+// lk < 2) holding one part and slot 1 another ([a1|a2] x [b1|b1],
+// [a1|a1] x [b2|b3], [a2|a3] x [b2|b1]).  Dropped terms and split remainders
+// are below 3 2^-23 |a b|.  The spin-orbit parts keep their positive and
+// negative products in separate FP32 sums (no operand is negated).  Each
+// chunk's FP32 sums start from zero and are added into FP64 running sums
+// (the spin-orbit pair as their FP32 difference).
+template <bool PERSIST>
+__global__ __launch_bounds__(NT, 2) void k_contract_b3(DevPlan d, const WorkItem *work, const int32_t *order,
+                                                       int64_t w0, int64_t nw, const double *om,
+                                                       const double *panel, double *staging, unsigned *tickets) {
+  constexpr int CH = 16;            // points per chunk
+  constexpr int RBF = 18 * 64;      // 16-byte items of the row BF16 image: 18 rows (plane, octet) x 64 functions
+  constexpr int CBF = 18 * 32;      // ... of the column image (32 functions)
+  constexpr int RD = 8 * DROW;      // doubles of the row phi image: 8 point pairs x 64 functions x 2
+  constexpr int CDW = 2 * 32;       // doubles per row of the column phi image
+  constexpr int CD = 8 * CDW;
+  // chunk images (double-buffered), reused after the last chunk to stage the
+  // half tile's results for coalesced writes
+  constexpr int IMG_BYTES = 2 * 16 * (RBF + CBF) + 2 * 8 * (RD + CD);
+  __shared__ __attribute__((aligned(16))) unsigned char smem[IMG_BYTES];
+  u32x4(*sr)[RBF] = reinterpret_cast<u32x4(*)[RBF]>(smem);
+  u32x4(*sc)[CBF] = reinterpret_cast<u32x4(*)[CBF]>(smem + 2 * 16 * RBF);
+  double(*dr)[RD] = reinterpret_cast<double(*)[RD]>(smem + 2 * 16 * (RBF + CBF));
+  double(*dc)[CD] = reinterpret_cast<double(*)[CD]>(smem + 2 * 16 * (RBF + CBF) + 2 * 8 * RD);
+  __shared__ double som[2][CH];
+  __shared__ int64_t s_pos;
+  // slot data of the tile's 64 rows and the half's 32 columns (slot -1: beyond n)
+  __shared__ int s_rslot[T], s_rfn[T], s_rnf[T], s_cslot[T / 2], s_cfn[T / 2], s_cnf[T / 2];
+  __shared__ int64_t s_rrow[T];
+  const int64_t npos = 2 * nw;
+  int64_t pos = PERSIST ? next_item(tickets, npos, order != nullptr, &s_pos)
+                        : (order ? (int64_t)blockIdx.x : xcd_map(blockIdx.x, npos));
+  while (!PERSIST || pos < npos) {
+  const int half = (int)(pos & 1);
+  const int64_t wi = w0 + (order ? order[w0 + (pos >> 1)] : (pos >> 1));
+  const WorkItem it = work[wi];
+  const int b = it.batch;
+  const int f0 = d.batch_fn_off[b], n = d.batch_fn_off[b + 1] - f0;
+  if (it.tj * T + 32 * half < n) {  // workgroup-uniform: the half has columns
+  const int g0 = d.batch_pt_off[b], P = d.batch_pt_off[b + 1] - g0;
+  const int sbase = d.batch_slot_off[b];
+  const int r0 = it.ti * T, c0 = it.tj * T + 32 * half;
+  const int Pp = (int)pad16(P), np = (int)pad16(n);
+  const double *pb = panel + d.panel_off[b];
+  const int64_t fplane = (int64_t)Pp * np, noct = Pp >> 3;
+  const u32x4 *pbf = reinterpret_cast<const u32x4 *>(pb + fplane);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int l16 = lane & 15, lk = lane >> 4;
+  const int rb = 16 * wave;  // this wave's row block (tile-local)
+  bool act[2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) act[c] = block_active(r0 + rb, c0 + 16 * c, n);
+
+  // the chunk of 16 points from k0 into buffer bf, by buffer loads straight
+  // into LDS: the batch's panel is one buffer, each lane's offset is fixed for
+  // the work item and the chunk and image row go into the scalar offset.
+  // Lanes whose function lies at or beyond np load nothing.
+  const __amdgpu_buffer_rsrc_t prs =
+      __builtin_amdgcn_make_buffer_rsrc((void *)pb, (short)0, (int)(44 * fplane), 0x00020000);
+  const bool okr = r0 + lane < np, okc = c0 + (lane & 31) < np;
+  const uint32_t vrow = lane * 16u, vcol = (lane & 31) * 16u + (lane >> 5) * (uint32_t)np * 16u;
+  const uint32_t vprow = lane * 32u, vpcol = (lane & 31) * 32u + (lane >> 5) * 16u;
+  auto dma = [&](int k0, int bf) {
+    const int og = k0 >> 3;
+    for (int k = wave; k < 27; k += 4) {
+      if (k < 18) {  // row image row (plane k / 2, octet k % 2), 64 functions
+        const uint32_t so = 8u * (uint32_t)fplane + (uint32_t)((((k >> 1) * noct + og + (k & 1)) * np + r0) * 16);
+        if (okr) __builtin_amdgcn_raw_ptr_buffer_load_lds(prs, (lds_void *)(&sr[bf][k * 64]), 16, vrow, so, 0, 0);
+      } else {  // column image rows (plane, octet 0) and (plane, octet 1), 32 functions each
+        const int pl = k - 18;
+        const uint32_t so = 8u * (uint32_t)fplane + (uint32_t)((((9 + pl) * noct + og) * np + c0) * 16);
+        if (okc) __builtin_amdgcn_raw_ptr_buffer_load_lds(prs, (lds_void *)(&sc[bf][pl * 64]), 16, vcol, so, 0, 0);
+      }
+    }
+    // FP64 phi: image row u = point pair u of the chunk (16 bytes per function)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {  // rows: two point pairs per wave
+      const int u = wave + 4 * h;
+      const uint32_t so = (uint32_t)(((((k0 >> 2) + (u >> 1)) * np + r0) * 4 + 2 * (u & 1)) * 8);
+      if (okr) __builtin_amdgcn_raw_ptr_buffer_load_lds(prs, (lds_void *)(&dr[bf][u * DROW]), 16, vprow, so, 0, 0);
+    }
+    {  // columns: point pairs 2 w and 2 w + 1 (one quad) per wave
+      const uint32_t so = (uint32_t)(((((k0 >> 2) + wave) * np + c0) * 4) * 8);
+      if (okc)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(prs, (lds_void *)(&dc[bf][2 * wave * CDW]), 16, vpcol, so, 0, 0);
+    }
+  };
+
+  dbl4 accw[2][4];   // FP64 running sums of Ws, Wso_x, Wso_y, Wso_z
+  dbl4 accv[2];      // V
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) accw[c][q] = dbl4{0.0, 0.0, 0.0, 0.0};
+    accv[c] = dbl4{0.0, 0.0, 0.0, 0.0};
+  }
+  double omr = tid < CH ? om[g0 + tid] : 0.0;  // om holds 16 zeros past its end
+  dma(0, 0);
+  if (tid < T + T / 2) {
+    const bool row = tid < T;
+    const int lf = row ? r0 + tid : c0 + tid - T;
+    SlotInfo si{-1, 0, 0, 0};
+    if (lf < n) si = slot_of(d, f0, sbase, lf);
+    if (row) {
+      s_rslot[tid] = si.slot;
+      s_rfn[tid] = si.fnoff;
+      s_rnf[tid] = si.nfn;
+      s_rrow[tid] = si.row_off;
+    } else {
+      s_cslot[tid - T] = si.slot;
+      s_cfn[tid - T] = si.fnoff;
+      s_cnf[tid - T] = si.nfn;
+    }
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  if (tid < CH) som[0][tid] = omr;
+  const int slot = lk >> 1, oc = lk & 1;
+  // split parts of the A and B operands of MFMA s for this lane's slot
+  const int ta0 = slot ? 1 : 0, ta2 = slot ? 2 : 1;  // A: s = 0 [1|2], s = 1 [1|1], s = 2 [2|3]
+  const int tb1 = slot ? 2 : 1, tb2 = slot ? 0 : 1;  // B: s = 0 [1|1], s = 1 [2|3], s = 2 [2|1]
+  for (int k0 = 0; k0 < Pp; k0 += CH) {
+    const int bi = (k0 / CH) & 1;
+    __syncthreads();  // this chunk's images and w v visible; the previous chunk is consumed
+    if (k0 + CH < Pp) {
+      omr = tid < CH ? om[g0 + k0 + CH + tid] : 0.0;
+      dma(k0 + CH, bi ^ 1);
+    }
+    // the chunk's products for the active column blocks (a compile-time set:
+    // both, or one on diagonal and edge tiles), as straight-line code
+    auto chunk = [&](auto a0c, auto a1c) {
+      constexpr bool ACT[2] = {decltype(a0c)::value, decltype(a1c)::value};
+      // V: four K steps of 4 points on FP64 MFMA (the FP64 path's order)
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        const int rowk = 2 * ks + (lk >> 1), ck = lk & 1;
+        const double omk = som[bi][4 * ks + lk];
+        const double av = dr[bi][rowk * DROW + 2 * (rb + l16) + ck];
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+          if (ACT[c]) accv[c] = mfma64(av, dc[bi][rowk * CDW + 2 * (16 * c + l16) + ck] * omk, accv[c]);
+      }
+      // W: this chunk's FP32 sums, Ws then (+, -) of Wso_x, Wso_y, Wso_z
+      flt4 accf[2][7];
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int q = 0; q < 7; ++q) accf[c][q] = flt4{0.f, 0.f, 0.f, 0.f};
+      // A operands of the row block, all components and split pairs
+      u32x4 fa[3][3];
+#pragma unroll
+      for (int qa = 0; qa < 3; ++qa) {
+        const int base = rb + l16;
+        fa[qa][0] = sr[bi][((3 * qa + ta0) * 2 + oc) * 64 + base];
+        fa[qa][1] = sr[bi][((3 * qa + 0) * 2 + oc) * 64 + base];
+        fa[qa][2] = sr[bi][((3 * qa + ta2) * 2 + oc) * 64 + base];
+      }
+#pragma unroll
+      for (int qb = 0; qb < 3; ++qb) {
+        u32x4 gb[2][3];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          if (!ACT[c]) continue;
+          const int base = 16 * c + l16;
+          gb[c][0] = sc[bi][((3 * qb + 0) * 2 + oc) * 32 + base];
+          gb[c][1] = sc[bi][((3 * qb + tb1) * 2 + oc) * 32 + base];
+          gb[c][2] = sc[bi][((3 * qb + tb2) * 2 + oc) * 32 + base];
+        }
+        // FP32 sum of (row component qa, column component qb): Ws on the
+        // diagonal; y z -> 1, z y -> 2, z x -> 3, x z -> 4, x y -> 5, y x -> 6
+#pragma unroll
+        for (int sp = 0; sp < 3; ++sp)
+#pragma unroll
+          for (int qa = 0; qa < 3; ++qa) {
+            constexpr int MAP[3][3] = {{0, 5, 4}, {6, 0, 1}, {3, 2, 0}};
+            const int t = MAP[qa][qb];
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+              if (ACT[c]) accf[c][t] = mfma_bf16(fa[qa][sp], gb[c][sp], accf[c][t]);
+          }
+      }
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        if (!ACT[c]) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          accw[c][0][r] += (double)accf[c][0][r];
+#pragma unroll
+          for (int m = 0; m < 3; ++m) accw[c][1 + m][r] += (double)(accf[c][1 + 2 * m][r] - accf[c][2 + 2 * m][r]);
+        }
+      }
+    };
+    if (act[0] && act[1])
+      chunk(std::true_type{}, std::true_type{});
+    else if (act[0])
+      chunk(std::true_type{}, std::false_type{});
+    else if (act[1])
+      chunk(std::false_type{}, std::true_type{});
+    __builtin_amdgcn_s_waitcnt(0);  // the next chunk's images and w v have landed
+    if (k0 + CH < Pp && tid < CH) som[bi ^ 1][tid] = omr;
+  }
+  // the half tile's results go through LDS (parts 0..2, then 3..4; rows of
+  // 33 doubles), then every thread writes whole runs of staged rows: element
+  // (i, j) of the half by thread (i 32 + j) mod 256, the mirrored element of a
+  // strictly upper block of one atom as well
+  const double cp = d.cprime;
+  double *E = reinterpret_cast<double *>(smem);
+  constexpr int ES = 33;
+#pragma unroll
+  for (int round = 0; round < 2; ++round) {
+    const int q0 = round ? 3 : 0, nq = round ? 2 : 3;
+    __syncthreads();  // the images (or the previous round) are consumed
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      if (!act[c]) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = 16 * c + l16;
+        if (round == 0) E[(0 * T + rb + d_row_f64(lk, r)) * ES + j] = accv[c][r];
+#pragma unroll
+        for (int q = 1; q < 5; ++q)
+          if (q >= q0 && q < q0 + nq) E[((q - q0) * T + rb + d_row_f32(lk, r)) * ES + j] = cp * accw[c][q - 1][r];
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < T * (T / 2); e += NT) {
+      const int i = e >> 5, j = e & 31;
+      const int li = r0 + i, lj = c0 + j;
+      if (!block_active(r0 + (i & ~15), c0 + (j & ~15), n) || li >= n || lj >= n) continue;
+      const int si = s_rslot[i], sj = s_cslot[j];
+      if (si > sj) continue;  // lower atom-block triangle: not stored
+      const int nfi = s_rnf[i], nfj = s_cnf[j], fi = s_rfn[i], fj = s_cfn[j];
+      const int64_t blk = s_rrow[i] + 5 * (int64_t)nfi * (fj - fi);
+      const int64_t pq = (int64_t)nfi * nfj;
+      const int64_t el = (int64_t)(li - fi) * nfj + (lj - fj);
+      const bool mirror = si == sj && r0 + (i & ~15) < c0 + (j & ~15);
+      const int64_t em = (int64_t)(lj - fi) * nfj + (li - fj);
+      for (int qq = 0; qq < nq; ++qq) {
+        const double x = E[(qq * T + i) * ES + j];
+        staging[blk + (q0 + qq) * pq + el] = x;
+        if (mirror) staging[blk + (q0 + qq) * pq + em] = mirror_sign(q0 + qq) * x;
+      }
+    }
+  }
+  }  // the half has columns
+  if (!PERSIST) break;
+  pos = next_item(tickets, npos, order != nullptr, &s_pos);
   }
 }
 
@@ -1262,8 +1574,12 @@ int launch_integrate(const q4c_plan *p, const double *v, int precision, uint32_t
   const unsigned pmask = (wantV ? 1u : 0u) | ((parts & Q4C_PART_WS) ? 2u : 0u) | ((parts & Q4C_PART_WSO) ? 28u : 0u);
   // FP64 with W parts: one kernel for all five (PK_F64 panels); otherwise V
   // on FP64 from phi alone and the W parts on FP32 (PK_F32 / PK_SPLIT panels)
+  // BF16X3 with W parts: one kernel for all five (PK_BF16 panels)
   const bool full64 = precision == Q4C_PREC_F64 && wantW;
-  const int kind = full64 ? PK_F64 : (precision == Q4C_PREC_SPLIT_F32 && wantW ? PK_SPLIT : PK_F32);
+  const bool fused_b3 = precision == Q4C_PREC_BF16X3 && wantW;
+  const int kind = full64 ? PK_F64
+                   : fused_b3 ? PK_BF16
+                              : (precision == Q4C_PREC_SPLIT_F32 && wantW ? PK_SPLIT : PK_F32);
   int rc;
   {
     TimedLaunch tl_(p, Q4C_TIMER_OTHER, s);
@@ -1291,12 +1607,17 @@ int launch_integrate(const q4c_plan *p, const double *v, int precision, uint32_t
       {
         TimedLaunch tl_(p, Q4C_TIMER_TABULATE, s);
         if (kind == PK_F64)
-          hipLaunchKernelGGL(k_panel<PK_F64>, dim3((unsigned)nt), dim3(256), 0, s, p->dp, p->d_ptile, ps.t0, nt, panel);
+          hipLaunchKernelGGL(k_panel<PK_F64>, dim3((unsigned)nt), dim3(256), 0, s, p->dp, p->d_ptile, ps.t0, nt, panel,
+                           (const double *)nullptr);
+        else if (kind == PK_BF16)
+          hipLaunchKernelGGL(k_panel<PK_BF16>, dim3((unsigned)nt), dim3(256), 0, s, p->dp, p->d_ptile, ps.t0, nt,
+                             panel, (const double *)p->d_om);
         else if (kind == PK_SPLIT)
           hipLaunchKernelGGL(k_panel<PK_SPLIT>, dim3((unsigned)nt), dim3(256), 0, s, p->dp, p->d_ptile, ps.t0, nt,
-                             panel);
+                             panel, (const double *)nullptr);
         else
-          hipLaunchKernelGGL(k_panel<PK_F32>, dim3((unsigned)nt), dim3(256), 0, s, p->dp, p->d_ptile, ps.t0, nt, panel);
+          hipLaunchKernelGGL(k_panel<PK_F32>, dim3((unsigned)nt), dim3(256), 0, s, p->dp, p->d_ptile, ps.t0, nt, panel,
+                             (const double *)nullptr);
       }
       if ((rc = check_launch("k_panel")) != Q4C_OK) return rc;
     }
@@ -1305,6 +1626,11 @@ int launch_integrate(const q4c_plan *p, const double *v, int precision, uint32_t
       if (full64) {
         launch_work(k_contract<MODE_F64, true>, k_contract<MODE_F64, false>, grid, pers, s, p->dp, p->d_work, order,
                     ps.w0, nw, p->d_om, panel, p->d_staging, tick_a);
+      } else if (fused_b3) {
+        // one workgroup per column half of each work item
+        const unsigned grid2 = (unsigned)(pers ? std::min<int64_t>(cfg.persistent, 2 * nw) : 2 * nw);
+        launch_work(k_contract_b3<true>, k_contract_b3<false>, grid2, pers, s, p->dp, p->d_work, order, ps.w0, nw,
+                    p->d_om, panel, p->d_staging, tick_a);
       } else {
         if (wantV)
           launch_work(k_contract<MODE_V, true>, k_contract<MODE_V, false>, grid, pers, s, p->dp, p->d_work, order,
@@ -1371,7 +1697,8 @@ int launch_integrate_hs(const q4c_plan *p, const double *v, uint32_t flags, doub
     if (nt > 0) {
       {
         TimedLaunch tl_(p, Q4C_TIMER_TABULATE, s);
-        hipLaunchKernelGGL(k_panel<PK_HS>, dim3((unsigned)nt), dim3(256), 0, s, p->dp, p->d_ptile, ps.t0, nt, panel);
+        hipLaunchKernelGGL(k_panel<PK_HS>, dim3((unsigned)nt), dim3(256), 0, s, p->dp, p->d_ptile, ps.t0, nt, panel,
+                           (const double *)nullptr);
       }
       if ((rc = check_launch("k_panel<hs>")) != Q4C_OK) return rc;
     }
@@ -1436,7 +1763,8 @@ int launch_density(const q4c_plan *p, const double *coef, uint32_t terms, int pr
     if (nt > 0) {
       {
         TimedLaunch tl_(p, Q4C_TIMER_TABULATE, s);
-        hipLaunchKernelGGL(k_panel<PK_F64>, dim3((unsigned)nt), dim3(256), 0, s, p->dp, p->d_ptile, ps.t0, nt, panel);
+        hipLaunchKernelGGL(k_panel<PK_F64>, dim3((unsigned)nt), dim3(256), 0, s, p->dp, p->d_ptile, ps.t0, nt, panel,
+                           (const double *)nullptr);
       }
       if ((rc = check_launch("k_panel")) != Q4C_OK) return rc;
     }
@@ -1490,7 +1818,8 @@ int launch_density_grad(const q4c_plan *p, const double *coef, double *out, hipS
     if (nt > 0) {
       {
         TimedLaunch tl_(p, Q4C_TIMER_TABULATE, s);
-        hipLaunchKernelGGL(k_panel<PK_F64>, dim3((unsigned)nt), dim3(256), 0, s, p->dp, p->d_ptile, ps.t0, nt, panel);
+        hipLaunchKernelGGL(k_panel<PK_F64>, dim3((unsigned)nt), dim3(256), 0, s, p->dp, p->d_ptile, ps.t0, nt, panel,
+                           (const double *)nullptr);
       }
       if ((rc = check_launch("k_panel")) != Q4C_OK) return rc;
     }

@@ -491,7 +491,8 @@ int build_host(q4c_plan *p, const q4c_basis *b, const q4c_grid *g, const std::ve
     int nt = (nb_fn + T - 1) / T;
     int64_t bpart = 2 * (int64_t)(nt * (nt + 1) / 2) * (g1 - g0);  // two column halves per work item
     // panel: 4 FP64 components (or phi in FP64 and up to 6 FP32 gradient planes: as much)
-    int64_t bpanel = 4 * q4c::pad16(g1 - g0) * q4c::pad16(nb_fn);
+    // panel: 4 FP64 planes, or 1 FP64 plane + 18 BF16 planes (PK_BF16) = 5.5
+    int64_t bpanel = 11 * q4c::pad16(g1 - g0) * q4c::pad16(nb_fn) / 2;
     if (bt > cur.b0 && (staging + partial + panel + bstage + bpart + bpanel > budget_doubles)) close_pass(bt);
     p->panel_off.push_back(panel);
     panel += bpanel;
@@ -1035,7 +1036,8 @@ void drop_graphs(q4c_plan *p) {
 int q4c_integrate_H(const q4c_plan *p, const double *v_dev, int32_t precision, uint32_t parts, uint32_t flags,
                     double *store_dev, double *spin_w_dev, double *spin_v_dev, void *stream) {
   if (!p) return fail(Q4C_EINVAL, "NULL plan");
-  if (precision != Q4C_PREC_F64 && precision != Q4C_PREC_SPLIT_F32 && precision != Q4C_PREC_F32)
+  if (precision != Q4C_PREC_F64 && precision != Q4C_PREC_SPLIT_F32 && precision != Q4C_PREC_F32 &&
+      precision != Q4C_PREC_BF16X3)
     return fail(Q4C_EINVAL, "unknown precision");
   if (parts == 0 || (parts & ~(uint32_t)Q4C_PART_ALL)) return fail(Q4C_EINVAL, "bad part selection");
   if (flags & ~(uint32_t)(Q4C_ACCUMULATE | Q4C_ASSEMBLE_W | Q4C_ASSEMBLE_V | Q4C_CHECK_FINITE))
@@ -1673,7 +1675,8 @@ int q4c_plan_autotune(q4c_plan *p, const double *v_dev, int32_t precision, doubl
                       void *stream) {
   int rc = check_plan_dev(p);
   if (rc != Q4C_OK) return rc;
-  if (precision != Q4C_PREC_F64 && precision != Q4C_PREC_SPLIT_F32 && precision != Q4C_PREC_F32)
+  if (precision != Q4C_PREC_F64 && precision != Q4C_PREC_SPLIT_F32 && precision != Q4C_PREC_F32 &&
+      precision != Q4C_PREC_BF16X3)
     return fail(Q4C_EINVAL, "unknown precision");
   if ((p->n_points > 0 && !v_dev) || (p->store_len > 0 && !store_dev))
     return fail(Q4C_EINVAL, "the potential and a store buffer are required");

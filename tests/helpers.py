@@ -75,7 +75,14 @@ def gamma(k: int) -> float:
 # products, 144 per 16 points: gamma_150 for Q4C_PREC_SPLIT_F32.  Values below
 # FP32's normal range (2^-126) lose their relative precision; the far tails of
 # tight functions reach it, hence an absolute floor, far below any bar.
-SPLIT_GAMMA = {1: gamma(150), 2: gamma(52)}
+# Q4C_PREC_BF16X3 (BF16 MFMA, operands split into three BF16 parts): the
+# split and the dropped terms cost 3 units of 2^-23 per product, and the
+# MFMA's FP32 sums over one 16-point chunk at most 7 + 36 (groups of 8
+# products aligned to their largest, then added to the accumulator: 9 MFMAs
+# of 4 groups per element), the spin-orbit difference and the FP64 addition
+# 2 more: 48 2^-23, and 50 with the magnitudes of the six kept terms in place
+# of |a b|.
+SPLIT_GAMMA = {1: gamma(150), 2: gamma(52), 3: 50 * 2.0 ** -23}
 SPLIT_FLOOR = 1e-25  # Ha
 
 

@@ -61,7 +61,7 @@ def test_empty_and_unreached_grids_give_zeros(q, case):
     wl = _degenerate(W.config_small(nrad=10, nang=26), case)
     plan = q.Plan(wl)
     assert plan.info["n_active"] == 0 and plan.info["n_batches"] == 0 and plan.info["n_pairs"] == 6
-    for precision in (q.PREC_F64, q.PREC_SPLIT_F32):
+    for precision in (q.PREC_F64, q.PREC_SPLIT_F32, q.PREC_BF16X3):
         print("case %s precision %d: %d points" % (case, precision, wl.n_points), flush=True)
         for a in _outputs(q, plan, wl, precision, seed=11):
             assert np.all(a == 0.0), (case, precision)
@@ -128,8 +128,9 @@ def test_tiny_batches_split_matches_f64(q):
     wl = W.config_small(nrad=16, nang=26)
     plan = q.Plan(wl, p_max=7)
     f64 = _outputs(q, plan, wl, q.PREC_F64, seed=13)[0]
-    split = _outputs(q, plan, wl, q.PREC_SPLIT_F32, seed=13)[0]
-    assert np.max(np.abs(split - f64)) <= 1e-8
+    for prec in (q.PREC_SPLIT_F32, q.PREC_BF16X3):
+        split = _outputs(q, plan, wl, prec, seed=13)[0]
+        assert np.max(np.abs(split - f64)) <= 1e-8, prec
 
 
 def test_points_at_nuclei_against_oracle(q):

@@ -153,7 +153,7 @@ def test_spinor_density_gradient_dot_product(env):
 
 
 def test_fullsize_split_error_bar(env):
-    """Split-FP32 (hi+lo) and single-FP32 W parts within 1e-8 Ha: against the
+    """Split-FP32 (hi+lo), single-FP32 and BF16x3 W parts within 1e-8 Ha: against the
     oracle on sampled pair blocks (and within the stated per-element bound
     there), and over every stored element against the FP64 path (itself
     within 1e-12 A_ij of the oracle)."""
@@ -162,7 +162,7 @@ def test_fullsize_split_error_bar(env):
     ref, scale = oracle.pair_blocks(wl, pairs[sel], with_abs=True)
     nfn = wl.atom_nfn()
     f64 = torch.from_numpy(env["store"]).cuda()
-    for prec in (q.PREC_SPLIT_F32, q.PREC_F32):
+    for prec in (q.PREC_SPLIT_F32, q.PREC_F32, q.PREC_BF16X3):
         st = q.new_store(plan)
         q.q4c_integrate_H(plan, env["v"], prec, 0, st)
         torch.cuda.synchronize()

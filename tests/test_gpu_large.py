@@ -86,7 +86,7 @@ def _check_split(env, sel, ref):
     q, torch, wl, plan, pairs, po = env["q"], env["torch"], env["wl"], env["plan"], env["pairs"], env["po"]
     f64 = env["store"]
     nfn = wl.atom_nfn()
-    for prec in (q.PREC_SPLIT_F32, q.PREC_F32):
+    for prec in (q.PREC_SPLIT_F32, q.PREC_F32, q.PREC_BF16X3):
         st = q.new_store(plan)
         q.q4c_integrate_H(plan, env["v"], prec, 0, st)
         torch.cuda.synchronize()

@@ -62,7 +62,7 @@ def test_molecules64_batched_graphs_equal_sequential_bitwise(env):
     assert len(table) == 12
     pb.set_graphs(True)
     ref = {}
-    for prec in (q.PREC_F64, q.PREC_SPLIT_F32):
+    for prec in (q.PREC_F64, q.PREC_SPLIT_F32, q.PREC_BF16X3):
         _batched(env, prec)  # captures the graphs
         ref[prec] = _batched(env, prec)  # replays them
     pb.set_graphs(False)

@@ -218,13 +218,15 @@ def test_integrate_accumulate(q, small):
     assert not torch.equal(b, a)
 
 
-def test_integrate_split_small(q, small):
+@pytest.mark.parametrize("prec", [1, 3])
+def test_integrate_split_small(q, small, prec):
     wl, pairs, ref, scale = small
-    plan, store, _, _ = _run(q, wl, precision=1)
+    plan, store, _, _ = _run(q, wl, precision=prec)
     _, po = plan.pairs()
     got = store_to_blocks(store, pairs, po, wl.atom_nfn())
     err = [np.max(np.abs(g[k] - r[k])) for g, r in zip(got, ref) for k in range(5)]
     assert max(err) <= SPLIT_ABS, max(err)
+    assert split_bound_worst(got, ref, scale, prec) <= 1.0
     # V stays on FP64 MFMA: FP64 bar
     worst = 0.0
     for g, r, s in zip(got, ref, scale):
@@ -363,7 +365,7 @@ def test_integrate_f64_multitile(q, medium, p_max, staging):
 
 def test_integrate_split_multitile(q, medium):
     wl, pairs, ref, scale = medium
-    for prec in (1, 2):
+    for prec in (1, 2, 3):
         plan, store, _, _ = _run(q, wl, precision=prec, assemble=False)
         _, po = plan.pairs()
         got = store_to_blocks(store, pairs, po, wl.atom_nfn())
@@ -413,7 +415,7 @@ def test_staging_passes_do_not_change_results(q, medium):
         print("passes:", plan.info["n_passes"], flush=True)
         coef = torch.from_numpy(np.random.default_rng(7301).standard_normal((5, plan.info["store_len"]))).cuda()
         res = []
-        for prec in (q.PREC_F64, q.PREC_SPLIT_F32):
+        for prec in (q.PREC_F64, q.PREC_SPLIT_F32, q.PREC_BF16X3):
             st = q.new_store(plan)
             q.q4c_integrate_H(plan, v, prec, 0, st)
             res.append(st)
@@ -443,7 +445,7 @@ def test_split_precisions_stated_bound_and_long_batches(q, medium):
         _, po = plan.pairs()
         f64 = q.new_store(plan)
         q.q4c_integrate_H(plan, v, q.PREC_F64, 0, f64)
-        for prec in (q.PREC_SPLIT_F32, q.PREC_F32):
+        for prec in (q.PREC_SPLIT_F32, q.PREC_F32, q.PREC_BF16X3):
             st = q.new_store(plan)
             q.q4c_integrate_H(plan, v, prec, 0, st)
             torch.cuda.synchronize()
@@ -464,7 +466,7 @@ def test_parts_mask(q, medium):
     v = torch.from_numpy(wl.v).cuda()
     rows = {"V": [0], "WS": [1], "WSO": [2, 3, 4]}
     bits = {"V": q.PART_V, "WS": q.PART_WS, "WSO": q.PART_WSO}
-    for prec in (q.PREC_F64, q.PREC_F32, q.PREC_SPLIT_F32):
+    for prec in (q.PREC_F64, q.PREC_F32, q.PREC_SPLIT_F32, q.PREC_BF16X3):
         full = q.new_store(plan)
         q.q4c_integrate_H(plan, v, prec, 0, full)
         for sel in (("V",), ("WS",), ("WSO",), ("V", "WS"), ("WS", "WSO")):

@@ -13,6 +13,7 @@
 namespace q4c {
 namespace {
 
+typedef double dbl2 __attribute__((ext_vector_type(2)));
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 typedef float flt4 __attribute__((ext_vector_type(4)));
 

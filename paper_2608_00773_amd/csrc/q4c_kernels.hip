@@ -520,14 +520,17 @@ __global__ __launch_bounds__(NT, 2) void k_contract(DevPlan d, const WorkItem *w
     for (int q = 0; q < NP; ++q) acc[sl][q] = dbl4{0.0, 0.0, 0.0, 0.0};
 
   const double cp = d.cprime;
-  // w v at the points this lane's K index visits in the next chunk, loaded a
-  // chunk ahead with the next image's DMA, so that nothing consumed between
-  // the barrier and the last MFMA of a chunk waits on loads in flight
+  // K steps go in pairs over 8 points: K index lk of the first step of the
+  // pair is point 2 lk of the 8, of the second point 2 lk + 1 (one 16-byte
+  // LDS read per operand gives a lane both).  w v at the points this lane's
+  // K index visits in the next chunk, loaded a chunk ahead with the next
+  // image's DMA, so that nothing consumed between the barrier and the last
+  // MFMA of a chunk waits on loads in flight
   double omn[CH / 4];
   auto load_om = [&](int k) {
 #pragma unroll
     for (int ks = 0; ks < CH / 4; ++ks) {
-      const int pt = k + 4 * ks + lk;
+      const int pt = k + 8 * (ks >> 1) + 2 * lk + (ks & 1);
       omn[ks] = pt < P ? om[g0 + pt] : 0.0;
     }
   };
@@ -549,19 +552,28 @@ __global__ __launch_bounds__(NT, 2) void k_contract(DevPlan d, const WorkItem *w
     }
     const double *ca = sa + bo, *cb = sb + bo;
 #pragma unroll
-    for (int ks = 0; ks < CH / 4; ++ks) {
-      // K index lk of step ks is point 4 ks + lk of the chunk; the column
-      // operand takes its weight w v there (the weighting of Eq. 29)
-      const int rowk = 2 * ks + (lk >> 1), ck = lk & 1;
-      const double omk = omv[ks];
+    for (int kp = 0; kp < CH / 8; ++kp) {
+      // image row 4 kp + lk holds points 8 kp + 2 lk and 8 kp + 2 lk + 1 of
+      // the chunk; the column operand takes its weight w v there (the
+      // weighting of Eq. 29)
+      const int row = 4 * kp + lk;
 #pragma unroll
       for (int sl = 0; sl < 4; ++sl) {
         if (!act[sl]) continue;  // wave-uniform
+        dbl2 ap[NQ], bp[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          ap[q] = *reinterpret_cast<const dbl2 *>(&ca[(q * RPQ + row) * DROW + 2 * (brow[sl] + li16)]);
+          bp[q] = *reinterpret_cast<const dbl2 *>(&cb[(q * RPQ + row) * DROW + 2 * (bcol[sl] + li16)]);
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+        const double omk = omv[2 * kp + h];
         double av[NQ], bv[NQ];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-          av[q] = ca[(q * RPQ + rowk) * DROW + 2 * (brow[sl] + li16) + ck];
-          bv[q] = cb[(q * RPQ + rowk) * DROW + 2 * (bcol[sl] + li16) + ck] * omk;
+          av[q] = ap[q][h];
+          bv[q] = bp[q][h] * omk;
         }
         acc[sl][0] = mfma64(av[0], bv[0], acc[sl][0]);
         if (!VONLY) {
@@ -574,6 +586,7 @@ __global__ __launch_bounds__(NT, 2) void k_contract(DevPlan d, const WorkItem *w
           acc[sl][3] = mfma64(-av[1], bv[3], acc[sl][3]);
           acc[sl][4] = mfma64(-av[2], bv[1], acc[sl][4]);
           acc[sl][1] = mfma64(av[3], bv[3], acc[sl][1]);
+        }
         }
       }
     }
@@ -936,15 +949,23 @@ __global__ __launch_bounds__(NT, 2) void k_contract_b3(DevPlan d, const WorkItem
     // both, or one on diagonal and edge tiles), as straight-line code
     auto chunk = [&](auto a0c, auto a1c) {
       constexpr bool ACT[2] = {decltype(a0c)::value, decltype(a1c)::value};
-      // V: four K steps of 4 points on FP64 MFMA (the FP64 path's order)
+      // V: four K steps of 4 points on FP64 MFMA, in pairs over 8 points as
+      // in the FP64 path (the same order)
 #pragma unroll
-      for (int ks = 0; ks < 4; ++ks) {
-        const int rowk = 2 * ks + (lk >> 1), ck = lk & 1;
-        const double omk = som[bi][4 * ks + lk];
-        const double av = dr[bi][rowk * DROW + 2 * (rb + l16) + ck];
+      for (int kp = 0; kp < 2; ++kp) {
+        const int row = 4 * kp + lk;
+        const dbl2 ap = *reinterpret_cast<const dbl2 *>(&dr[bi][row * DROW + 2 * (rb + l16)]);
+        dbl2 bp[2];
 #pragma unroll
         for (int c = 0; c < 2; ++c)
-          if (ACT[c]) accv[c] = mfma64(av, dc[bi][rowk * CDW + 2 * (16 * c + l16) + ck] * omk, accv[c]);
+          if (ACT[c]) bp[c] = *reinterpret_cast<const dbl2 *>(&dc[bi][row * CDW + 2 * (16 * c + l16)]);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const double omk = som[bi][8 * kp + 2 * lk + h];
+#pragma unroll
+          for (int c = 0; c < 2; ++c)
+            if (ACT[c]) accv[c] = mfma64(ap[h], bp[c][h] * omk, accv[c]);
+        }
       }
       // W: this chunk's FP32 sums, Ws then (+, -) of Wso_x, Wso_y, Wso_z
       flt4 accf[2][7];
@@ -1060,11 +1081,12 @@ __global__ __launch_bounds__(NT, 2) void k_contract_b3(DevPlan d, const WorkItem
 // one).  The sum is a single sequential chain in batch order, so results
 // repeat bit for bit and do not depend on how batches are split into passes.
 // Loads of four incidences are issued together.
-__global__ __launch_bounds__(256) void k_reduce(DevPlan d, int64_t r0, const int32_t *red_pair,
+constexpr int NTR = 256;  // threads of a k_reduce workgroup
+__global__ __launch_bounds__(NTR) void k_reduce(DevPlan d, int64_t r0, const int32_t *red_pair,
                                                 const uint8_t *red_first, const int64_t *red_inc_off,
                                                 const int64_t *inc_src, const double *staging, double *store,
                                                 int accumulate, int nq, unsigned part_mask) {
-  __shared__ int64_t s_src[256];
+  __shared__ int64_t s_src[NTR];
   const int64_t r = r0 + blockIdx.x;
   const int p = red_pair[r];
   const int blk = d.pair_na[p] * d.pair_nb[p];
@@ -1072,20 +1094,20 @@ __global__ __launch_bounds__(256) void k_reduce(DevPlan d, int64_t r0, const int
   const bool add = accumulate || !red_first[r];
   const int64_t po = d.pair_off[p];
   const int m = nq * blk;  // parts 0 .. nq-1 of the staged blocks (the first nq of five)
-  // each thread owns elements e = tid, tid + 256, ... (at most 4 at a time in registers)
-  for (int e0 = 0; e0 < m; e0 += 4 * 256) {
+  // each thread owns elements e = tid, tid + NTR, ... (4 at a time in registers)
+  for (int e0 = 0; e0 < m; e0 += 4 * NTR) {
     double sum[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int e = e0 + j * 256 + threadIdx.x;
+      const int e = e0 + j * NTR + threadIdx.x;
       sum[j] = 0.0;
       if (e < m && add && ((part_mask >> (e / blk)) & 1)) {
         const int q = e / blk;
         sum[j] = store[q * d.store_len + po + (e - q * blk)];
       }
     }
-    for (int64_t kb = k0; kb < k1; kb += 256) {
-      const int nk = (int)(k1 - kb < 256 ? k1 - kb : 256);
+    for (int64_t kb = k0; kb < k1; kb += NTR) {
+      const int nk = (int)(k1 - kb < NTR ? k1 - kb : NTR);
       __syncthreads();  // previous offsets consumed
       if (threadIdx.x < nk) s_src[threadIdx.x] = inc_src[kb + threadIdx.x];
       __syncthreads();
@@ -1094,7 +1116,7 @@ __global__ __launch_bounds__(256) void k_reduce(DevPlan d, int64_t r0, const int
         double a[4][8];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const int e = e0 + j * 256 + threadIdx.x;
+          const int e = e0 + j * NTR + threadIdx.x;
 #pragma unroll
           for (int u = 0; u < 8; ++u) a[j][u] = e < m ? staging[s_src[k + u] + e] : 0.0;
         }
@@ -1106,14 +1128,14 @@ __global__ __launch_bounds__(256) void k_reduce(DevPlan d, int64_t r0, const int
       for (; k < nk; ++k) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const int e = e0 + j * 256 + threadIdx.x;
+          const int e = e0 + j * NTR + threadIdx.x;
           if (e < m) sum[j] += staging[s_src[k] + e];
         }
       }
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int e = e0 + j * 256 + threadIdx.x;
+      const int e = e0 + j * NTR + threadIdx.x;
       if (e < m && ((part_mask >> (e / blk)) & 1)) {
         const int q = e / blk;
         store[q * d.store_len + po + (e - q * blk)] = sum[j];
@@ -1647,7 +1669,7 @@ int launch_integrate(const q4c_plan *p, const double *v, int precision, uint32_t
     if (nr > 0) {
       {
         TimedLaunch tl_(p, Q4C_TIMER_REDUCE, s);
-        hipLaunchKernelGGL(k_reduce, dim3((unsigned)nr), dim3(256), 0, s, p->dp, ps.r0, p->d_red_pair, p->d_red_first,
+        hipLaunchKernelGGL(k_reduce, dim3((unsigned)nr), dim3(NTR), 0, s, p->dp, ps.r0, p->d_red_pair, p->d_red_first,
                            p->d_red_inc_off, p->d_inc_src, p->d_staging, store, accumulate, 5, pmask);
       }
       if ((rc = check_launch("k_reduce")) != Q4C_OK) return rc;
@@ -1712,7 +1734,7 @@ int launch_integrate_hs(const q4c_plan *p, const double *v, uint32_t flags, doub
     if (nr > 0) {
       {
         TimedLaunch tl_(p, Q4C_TIMER_REDUCE, s);
-        hipLaunchKernelGGL(k_reduce, dim3((unsigned)nr), dim3(256), 0, s, p->dp, ps.r0, p->d_red_pair, p->d_red_first,
+        hipLaunchKernelGGL(k_reduce, dim3((unsigned)nr), dim3(NTR), 0, s, p->dp, ps.r0, p->d_red_pair, p->d_red_first,
                            p->d_red_inc_off, p->d_inc_src, p->d_staging, hs, accumulate, 2, 3u);
       }
       if ((rc = check_launch("k_reduce")) != Q4C_OK) return rc;

@@ -29,7 +29,7 @@ PEAK_F64 = 78.6e12    # MI355X dense FP64 MFMA, flop/s
 PEAK_F32 = 157.3e12   # MI355X dense FP32 MFMA, flop/s
 PEAK_BF16 = 2.5e15    # MI355X dense BF16 MFMA, flop/s
 PEAK_HBM = 8.0e12     # MI355X HBM3E, bytes/s
-PREC = {"f64": 0, "split": 1, "f32": 2, "bf16x3": 3}
+PREC = {"f64": 0, "split": 1, "f32": 2, "bf16x3": 3, "f64valu": 4}
 
 # HBM bytes per launch of the path's kernels on the default cluster workload,
 # from two rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE), each scaled by what
@@ -107,8 +107,8 @@ def contraction_peak(prec: str) -> float:
     run on FP64 MFMA (f64), FP32 MFMA (split, f32: one FP32 product per
     product, the hi/lo mode's extra two counted as its own overhead) or BF16
     MFMA with six BF16 products per product (bf16x3)."""
-    if prec == "f64":
-        return PEAK_F64
+    if prec in ("f64", "f64valu"):
+        return PEAK_F64  # the FP64 vector peak equals the FP64 matrix peak on MI355X
     if prec == "bf16x3":
         return 10.0 / (1.0 / PEAK_F64 + 9.0 * 6.0 / PEAK_BF16)
     return 10.0 / (1.0 / PEAK_F64 + 9.0 / PEAK_F32)
@@ -644,7 +644,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"f64": "f64", "split": "f32-hi/lo+f64", "f32": "f32+f64", "bf16x3": "bf16x3+f64"}[a.precision],
+        "dtype": {"f64": "f64", "split": "f32-hi/lo+f64", "f32": "f32+f64", "bf16x3": "bf16x3+f64",
+                  "f64valu": "f64"}[a.precision],
         "data": "synthetic",
         "config": {
             "workload": "%s, %d atoms, %d NAOs, %d points (%d active), %d batches <= 300 pts" %

@@ -99,12 +99,17 @@ enum {
  *                       FP32 underflow (below 1e-25 Ha) and FP64 rounding.
  *                       V runs in the same kernel on FP64 MFMA, in the same
  *                       order as Q4C_PREC_F64 (bitwise the same V).
+ *   Q4C_PREC_F64_VALU   all five parts in FP64 on the vector ALU, no matrix
+ *                       cores: the plain FP64 baseline the reduced
+ *                       precisions are compared with (FP64 bar, summation
+ *                       point by point; not bitwise Q4C_PREC_F64).
  * Batch partial sums are added to the store in FP64 in a fixed order. */
 enum {
   Q4C_PREC_F64 = 0,
   Q4C_PREC_SPLIT_F32 = 1,
   Q4C_PREC_F32 = 2,
-  Q4C_PREC_BF16X3 = 3
+  Q4C_PREC_BF16X3 = 3,
+  Q4C_PREC_F64_VALU = 4
 };
 
 /* parts of q4c_integrate_H (bit set): V, the scalar W part Ws, the three

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libq4c.so")
 Q4C_OK = 0
 Q4C_EINVAL, Q4C_ENOMEM, Q4C_EHIP, Q4C_ENOTIMPL, Q4C_EUNSUPPORTED, Q4C_ESIZE, Q4C_ENONFINITE, Q4C_ENODEV = \
     -1, -2, -3, -4, -5, -6, -7, -8
-PREC_F64, PREC_SPLIT_F32, PREC_F32, PREC_BF16X3 = 0, 1, 2, 3
+PREC_F64, PREC_SPLIT_F32, PREC_F32, PREC_BF16X3, PREC_F64_VALU = 0, 1, 2, 3, 4
 TIMER_NAMES = ("tabulate", "contract", "reduce", "spinor", "bloch", "density_tiles", "density_points", "other")
 ACCUMULATE, ASSEMBLE_W, ASSEMBLE_V, CHECK_FINITE = 1, 2, 4, 8
 PLAN_HOST_ONLY = 1

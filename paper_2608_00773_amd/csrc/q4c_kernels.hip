@@ -620,6 +620,112 @@ __global__ __launch_bounds__(NT, 2) void k_contract(DevPlan d, const WorkItem *w
   }
 }
 
+// The plain FP64 baseline (precision F64_VALU): the five parts of a work
+// item on the vector ALU, no matrix cores.  Same work items, FP64 panels,
+// chunk DMA and staging as k_contract<MODE_F64>; each thread owns a 4 x 4
+// patch of the 64 x 64 tile (rows 4 (t / 16), columns 4 (t % 16)) and adds
+// every point's ten products to its 80 FP64 sums with fused multiply-adds,
+// point after point.  Patches in blocks no work item computes (below the
+// diagonal, beyond n) skip the arithmetic.
+__global__ __launch_bounds__(NT, 1) void k_contract_valu(DevPlan d, const WorkItem *work, const int32_t *order,
+                                                         int64_t w0, int64_t nw, const double *om,
+                                                         const double *panel, double *staging, unsigned *tickets) {
+  (void)tickets;
+  constexpr int NQ = 4, CH = 8, RPQ = CH / 2;
+  constexpr int BUFD = NQ * RPQ * DROW;  // doubles per chunk image
+  __shared__ double sa[2 * BUFD], sb[2 * BUFD];
+  __shared__ double s_om[2][CH];
+  const int64_t pos = order ? (int64_t)blockIdx.x : xcd_map(blockIdx.x, nw);
+  const int64_t wi = w0 + (order ? order[w0 + pos] : pos);
+  const WorkItem it = work[wi];
+  const int b = it.batch;
+  const int g0 = d.batch_pt_off[b], P = d.batch_pt_off[b + 1] - g0;
+  const int f0 = d.batch_fn_off[b], n = d.batch_fn_off[b + 1] - f0;
+  const int sbase = d.batch_slot_off[b];
+  const int r0 = it.ti * T, c0 = it.tj * T;
+  const int Pp = (int)pad16(P), np = (int)pad16(n);
+  const double *pb = panel + d.panel_off[b];
+  const int64_t plane = (int64_t)Pp * np;
+  const int tid = threadIdx.x;
+  const int pr = 4 * (tid >> 4), pc = 4 * (tid & 15);  // the thread's patch (tile-local)
+  const int rb = pr & ~15, cb = pc & ~15;
+  const bool live = block_active(r0 + rb, c0 + cb, n);
+  double acc[5][4][4];
+#pragma unroll
+  for (int q = 0; q < 5; ++q)
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[q][a][c] = 0.0;
+  double omr = tid < CH ? om[g0 + tid] : 0.0;  // om holds 16 zeros past its end
+  dma_chunk<NT, CH, T, DROW, NQ>(pb, plane, np, r0, 0, sa);
+  dma_chunk<NT, CH, T, DROW, NQ>(pb, plane, np, c0, 0, sb);
+  __builtin_amdgcn_s_waitcnt(0);
+  if (tid < CH) s_om[0][tid] = omr;
+  for (int k0 = 0; k0 < Pp; k0 += CH) {
+    const int bi = (k0 / CH) & 1;
+    __syncthreads();  // this chunk visible; the previous one consumed
+    if (k0 + CH < Pp) {
+      omr = tid < CH ? om[g0 + k0 + CH + tid] : 0.0;
+      dma_chunk<NT, CH, T, DROW, NQ>(pb, plane, np, r0, (k0 + CH) >> 2, sa + (bi ^ 1) * BUFD);
+      dma_chunk<NT, CH, T, DROW, NQ>(pb, plane, np, c0, (k0 + CH) >> 2, sb + (bi ^ 1) * BUFD);
+    }
+    if (live) {
+      const double *ca = sa + bi * BUFD, *cbp = sb + bi * BUFD;
+      for (int u = 0; u < RPQ; ++u) {  // point pairs of the chunk
+        // component q of functions pr + a (rows) and pc + c (columns) at
+        // points 2u, 2u + 1 (16 bytes each)
+        dbl2 av[NQ][4], bv[NQ][4];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+#pragma unroll
+          for (int a = 0; a < 4; ++a) {
+            av[q][a] = *reinterpret_cast<const dbl2 *>(&ca[(q * RPQ + u) * DROW + 2 * (pr + a)]);
+            bv[q][a] = *reinterpret_cast<const dbl2 *>(&cbp[(q * RPQ + u) * DROW + 2 * (pc + a)]);
+          }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const double w = s_om[bi][2 * u + h];
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+              const double x0 = av[0][a][h], x1 = av[1][a][h], x2 = av[2][a][h], x3 = av[3][a][h];
+              const double y0 = w * bv[0][c][h], y1 = w * bv[1][c][h], y2 = w * bv[2][c][h], y3 = w * bv[3][c][h];
+              acc[0][a][c] = fma(x0, y0, acc[0][a][c]);
+              acc[1][a][c] = fma(x1, y1, fma(x2, y2, fma(x3, y3, acc[1][a][c])));
+              acc[2][a][c] = fma(x2, y3, fma(-x3, y2, acc[2][a][c]));
+              acc[3][a][c] = fma(x3, y1, fma(-x1, y3, acc[3][a][c]));
+              acc[4][a][c] = fma(x1, y2, fma(-x2, y1, acc[4][a][c]));
+            }
+        }
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0);  // the next chunk's images and w v have landed
+    if (k0 + CH < Pp && tid < CH) s_om[bi ^ 1][tid] = omr;
+  }
+  if (!live) return;
+  const double cp = d.cprime;
+  const bool upper = r0 + rb < c0 + cb;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int lj = c0 + pc + c;
+    if (lj >= n) continue;
+    const SlotInfo sj = slot_of(d, f0, sbase, lj);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int li = r0 + pr + a;
+      if (li >= n) continue;
+      const SlotInfo si = slot_of(d, f0, sbase, li);
+      double vals[5];
+      vals[0] = acc[0][a][c];
+#pragma unroll
+      for (int q = 1; q < 5; ++q) vals[q] = cp * acc[q][a][c];
+      stage_store<0, 5>(staging, si, sj, li, lj, upper, vals);
+    }
+  }
+}
+
 // The four W parts on FP32 MFMA (precisions F32 and SPLIT_F32), from the FP32
 // gradient planes of a PK_F32 / PK_SPLIT panel; V runs beside it on FP64
 // (k_contract<MODE_V>).  Same work items, wave blocks and staging as
@@ -1597,9 +1703,9 @@ int launch_integrate(const q4c_plan *p, const double *v, int precision, uint32_t
   // FP64 with W parts: one kernel for all five (PK_F64 panels); otherwise V
   // on FP64 from phi alone and the W parts on FP32 (PK_F32 / PK_SPLIT panels)
   // BF16X3 with W parts: one kernel for all five (PK_BF16 panels)
-  const bool full64 = precision == Q4C_PREC_F64 && wantW;
+  const bool full64 = (precision == Q4C_PREC_F64 || precision == Q4C_PREC_F64_VALU) && wantW;
   const bool fused_b3 = precision == Q4C_PREC_BF16X3 && wantW;
-  const int kind = full64 ? PK_F64
+  const int kind = (full64 || precision == Q4C_PREC_F64_VALU) ? PK_F64
                    : fused_b3 ? PK_BF16
                               : (precision == Q4C_PREC_SPLIT_F32 && wantW ? PK_SPLIT : PK_F32);
   int rc;
@@ -1645,7 +1751,11 @@ int launch_integrate(const q4c_plan *p, const double *v, int precision, uint32_t
     }
     if (nw > 0) {
       TimedLaunch tl_(p, Q4C_TIMER_CONTRACT, s);
-      if (full64) {
+      if (precision == Q4C_PREC_F64_VALU) {
+        // the plain FP64 baseline: one workgroup per work item, every part
+        hipLaunchKernelGGL(k_contract_valu, dim3((unsigned)nw), dim3(NT), 0, s, p->dp, p->d_work, order, ps.w0, nw,
+                           p->d_om, panel, p->d_staging, (unsigned *)nullptr);
+      } else if (full64) {
         launch_work(k_contract<MODE_F64, true>, k_contract<MODE_F64, false>, grid, pers, s, p->dp, p->d_work, order,
                     ps.w0, nw, p->d_om, panel, p->d_staging, tick_a);
       } else if (fused_b3) {

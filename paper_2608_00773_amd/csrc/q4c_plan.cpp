@@ -1037,7 +1037,7 @@ int q4c_integrate_H(const q4c_plan *p, const double *v_dev, int32_t precision, u
                     double *store_dev, double *spin_w_dev, double *spin_v_dev, void *stream) {
   if (!p) return fail(Q4C_EINVAL, "NULL plan");
   if (precision != Q4C_PREC_F64 && precision != Q4C_PREC_SPLIT_F32 && precision != Q4C_PREC_F32 &&
-      precision != Q4C_PREC_BF16X3)
+      precision != Q4C_PREC_BF16X3 && precision != Q4C_PREC_F64_VALU)
     return fail(Q4C_EINVAL, "unknown precision");
   if (parts == 0 || (parts & ~(uint32_t)Q4C_PART_ALL)) return fail(Q4C_EINVAL, "bad part selection");
   if (flags & ~(uint32_t)(Q4C_ACCUMULATE | Q4C_ASSEMBLE_W | Q4C_ASSEMBLE_V | Q4C_CHECK_FINITE))
@@ -1676,7 +1676,7 @@ int q4c_plan_autotune(q4c_plan *p, const double *v_dev, int32_t precision, doubl
   int rc = check_plan_dev(p);
   if (rc != Q4C_OK) return rc;
   if (precision != Q4C_PREC_F64 && precision != Q4C_PREC_SPLIT_F32 && precision != Q4C_PREC_F32 &&
-      precision != Q4C_PREC_BF16X3)
+      precision != Q4C_PREC_BF16X3 && precision != Q4C_PREC_F64_VALU)
     return fail(Q4C_EINVAL, "unknown precision");
   if ((p->n_points > 0 && !v_dev) || (p->store_len > 0 && !store_dev))
     return fail(Q4C_EINVAL, "the potential and a store buffer are required");

@@ -162,9 +162,22 @@ def test_tabulate_values_only_and_size_errors(q, small):
     assert e.value.status == q.Q4C_ESIZE
 
 
-def test_integrate_f64_small(q, small):
+@pytest.mark.parametrize("prec", [0, 4])
+def test_integrate_f64_small(q, small, prec):
+    """FP64 on the matrix cores and the plain FP64 baseline on the vector ALU:
+    every element within 1e-12 A_ij of the oracle."""
     wl, pairs, ref, scale = small
-    plan, store, spin_w, spin_v = _run(q, wl)
+    plan, store, spin_w, spin_v = _run(q, wl, precision=prec)
+    _, po = plan.pairs()
+    got = store_to_blocks(store, pairs, po, wl.atom_nfn())
+    _compare_f64(got, ref, scale)
+
+
+def test_integrate_f64_valu_multitile(q, medium):
+    """The plain FP64 baseline on the multi-tile case (diagonal, edge and
+    ragged tiles, batches of up to 300 points): the FP64 bar on every element."""
+    wl, pairs, ref, scale = medium
+    plan, store, _, _ = _run(q, wl, precision=4, assemble=False)
     _, po = plan.pairs()
     got = store_to_blocks(store, pairs, po, wl.atom_nfn())
     _compare_f64(got, ref, scale)

@@ -353,11 +353,10 @@ __global__ void k_om(DevPlan d, const double *v, double *om) {
 //   PK_F32:   phi in FP64 (1 plane), then d/dx, d/dy, d/dz as FP32 planes
 //             (Pp np floats each) after it
 //   PK_SPLIT: as PK_F32, then the three lo planes fl32(x - hi)
-//   PK_BF16:  phi in FP64 (1 plane), then the BF16 region: for side s (0:
-//             the gradient itself, row operand; 1: w v times the gradient,
-//             column operand), component q and split part t, plane
-//             s 9 + 3 q + t of (Pp / 8) point octets x np functions x 8
-//             points (16 bytes per function and octet)
+//   PK_BF16:  phi in FP64 (1 plane), then the BF16 region: for component q
+//             and split part t of sqrt|w v| times the gradient (formed in
+//             FP64), plane 3 q + t of (Pp / 8) point octets x np functions x
+//             8 points (16 bytes per function and octet)
 // The FP64 and FP32 planes use the 4-point interleave of panel_index (FP32
 // planes counted in floats).
 enum { PK_F64 = 0, PK_HS = 1, PK_F32 = 2, PK_SPLIT = 3, PK_BF16 = 4 };
@@ -442,21 +441,22 @@ __global__ __launch_bounds__(256) void k_panel(DevPlan d, const WorkItem *tiles,
         }
       }
     if (KIND == PK_BF16) {
-      // one task per (side, component, function): the 8 points of this octet,
-      // split into three BF16 parts, 16 bytes per part
+      // one task per (component, function): the 8 points of this octet,
+      // sqrt|w v| times the gradient split into three BF16 parts, 16 bytes
+      // per part
       u32x4 *pbf = reinterpret_cast<u32x4 *>(pb + fplane);
       const int64_t noct = Pp >> 3;
-      for (int t = threadIdx.x; t < 2 * 3 * T; t += 256) {
-        const int il = t % T, q = (t / T) % 3, side = t / (3 * T);
+      double sw[CP];
+#pragma unroll
+      for (int e = 0; e < CP; ++e) sw[e] = g8 + e < P ? sqrt(fabs(om[g0 + g8 + e])) : 0.0;
+      for (int t = threadIdx.x; t < 3 * T; t += 256) {
+        const int il = t % T, q = t / T;
         if (il >= nrow) continue;
         u32x4 w[3];
 #pragma unroll
         for (int e = 0; e < CP; e += 2) {
-          double xa = st[((q + 1) * CP + e) * PLD + il], xb = st[((q + 1) * CP + e + 1) * PLD + il];
-          if (side) {
-            xa *= g8 + e < P ? om[g0 + g8 + e] : 0.0;
-            xb *= g8 + e + 1 < P ? om[g0 + g8 + e + 1] : 0.0;
-          }
+          const double xa = sw[e] * st[((q + 1) * CP + e) * PLD + il];
+          const double xb = sw[e + 1] * st[((q + 1) * CP + e + 1) * PLD + il];
           uint32_t w1, w2, w3;
           split3_bf16x2(xa, xb, w1, w2, w3);
           w[0][e >> 1] = w1;
@@ -464,7 +464,7 @@ __global__ __launch_bounds__(256) void k_panel(DevPlan d, const WorkItem *tiles,
           w[2][e >> 1] = w3;
         }
 #pragma unroll
-        for (int k = 0; k < 3; ++k) pbf[((int64_t)(side * 9 + 3 * q + k) * noct + (g8 >> 3)) * np + r0 + il] = w[k];
+        for (int k = 0; k < 3; ++k) pbf[((int64_t)(3 * q + k) * noct + (g8 >> 3)) * np + r0 + il] = w[k];
       }
     }
     __syncthreads();  // st consumed
@@ -917,9 +917,10 @@ __global__ __launch_bounds__(NT, 2) void k_contract_w(DevPlan d, const WorkItem 
 // per column half (32 columns) of a work item's 64 x 64 tile; wave w takes
 // the 16-row block w against the half's two 16-column blocks, so each A
 // operand it reads serves both.  Per 16-point chunk the four images (FP64 phi
-// of rows and columns, BF16 gradient parts of rows and of w v times the
-// gradient of columns) arrive by LDS DMA, double-buffered, with w v of the
-// chunk's points.
+// and the BF16 parts of sqrt|w v| times the gradient, of rows and of
+// columns) arrive by LDS DMA, double-buffered, with w v of the chunk's
+// points.  The row operand takes the sign of w v (its BF16 sign bits
+// flipped), so each product is w v times the two gradient components.
 // W products: a b ~ a1 b1 + a2 b1 + a1 b2 + a1 b3 + a2 b2 + a3 b1 (the terms
 // of order 2^-16 and above), three MFMAs of K = 32 per component pair: the
 // K index runs over two slots of the chunk's 16 points, slot 0 (lanes with
@@ -982,7 +983,7 @@ __global__ __launch_bounds__(NT, 2) void k_contract_b3(DevPlan d, const WorkItem
   // the work item and the chunk and image row go into the scalar offset.
   // Lanes whose function lies at or beyond np load nothing.
   const __amdgpu_buffer_rsrc_t prs =
-      __builtin_amdgcn_make_buffer_rsrc((void *)pb, (short)0, (int)(44 * fplane), 0x00020000);
+      __builtin_amdgcn_make_buffer_rsrc((void *)pb, (short)0, (int)(26 * fplane), 0x00020000);
   const bool okr = r0 + lane < np, okc = c0 + (lane & 31) < np;
   const uint32_t vrow = lane * 16u, vcol = (lane & 31) * 16u + (lane >> 5) * (uint32_t)np * 16u;
   const uint32_t vprow = lane * 32u, vpcol = (lane & 31) * 32u + (lane >> 5) * 16u;
@@ -994,7 +995,7 @@ __global__ __launch_bounds__(NT, 2) void k_contract_b3(DevPlan d, const WorkItem
         if (okr) __builtin_amdgcn_raw_ptr_buffer_load_lds(prs, (lds_void *)(&sr[bf][k * 64]), 16, vrow, so, 0, 0);
       } else {  // column image rows (plane, octet 0) and (plane, octet 1), 32 functions each
         const int pl = k - 18;
-        const uint32_t so = 8u * (uint32_t)fplane + (uint32_t)((((9 + pl) * noct + og) * np + c0) * 16);
+        const uint32_t so = 8u * (uint32_t)fplane + (uint32_t)(((pl * noct + og) * np + c0) * 16);
         if (okc) __builtin_amdgcn_raw_ptr_buffer_load_lds(prs, (lds_void *)(&sc[bf][pl * 64]), 16, vcol, so, 0, 0);
       }
     }
@@ -1079,14 +1080,23 @@ __global__ __launch_bounds__(NT, 2) void k_contract_b3(DevPlan d, const WorkItem
       for (int c = 0; c < 2; ++c)
 #pragma unroll
         for (int q = 0; q < 7; ++q) accf[c][q] = flt4{0.f, 0.f, 0.f, 0.f};
+      // the sign of w v at this lane's 8 points (octet oc), on the BF16 sign
+      // bits of the row operand
+      u32x4 sgn;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const uint64_t ua = (uint64_t)__double_as_longlong(som[bi][8 * oc + 2 * m]);
+        const uint64_t ub = (uint64_t)__double_as_longlong(som[bi][8 * oc + 2 * m + 1]);
+        sgn[m] = ((uint32_t)(ua >> 48) & 0x8000u) | ((uint32_t)(ub >> 32) & 0x80000000u);
+      }
       // A operands of the row block, all components and split pairs
       u32x4 fa[3][3];
 #pragma unroll
       for (int qa = 0; qa < 3; ++qa) {
         const int base = rb + l16;
-        fa[qa][0] = sr[bi][((3 * qa + ta0) * 2 + oc) * 64 + base];
-        fa[qa][1] = sr[bi][((3 * qa + 0) * 2 + oc) * 64 + base];
-        fa[qa][2] = sr[bi][((3 * qa + ta2) * 2 + oc) * 64 + base];
+        fa[qa][0] = sr[bi][((3 * qa + ta0) * 2 + oc) * 64 + base] ^ sgn;
+        fa[qa][1] = sr[bi][((3 * qa + 0) * 2 + oc) * 64 + base] ^ sgn;
+        fa[qa][2] = sr[bi][((3 * qa + ta2) * 2 + oc) * 64 + base] ^ sgn;
       }
 #pragma unroll
       for (int qb = 0; qb < 3; ++qb) {

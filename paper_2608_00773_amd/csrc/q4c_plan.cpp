@@ -491,8 +491,8 @@ int build_host(q4c_plan *p, const q4c_basis *b, const q4c_grid *g, const std::ve
     int nt = (nb_fn + T - 1) / T;
     int64_t bpart = 2 * (int64_t)(nt * (nt + 1) / 2) * (g1 - g0);  // two column halves per work item
     // panel: 4 FP64 components (or phi in FP64 and up to 6 FP32 gradient planes: as much)
-    // panel: 4 FP64 planes, or 1 FP64 plane + 18 BF16 planes (PK_BF16) = 5.5
-    int64_t bpanel = 11 * q4c::pad16(g1 - g0) * q4c::pad16(nb_fn) / 2;
+    // panel: 4 FP64 planes (the largest kind)
+    int64_t bpanel = 4 * q4c::pad16(g1 - g0) * q4c::pad16(nb_fn);
     if (bt > cur.b0 && (staging + partial + panel + bstage + bpart + bpanel > budget_doubles)) close_pass(bt);
     p->panel_off.push_back(panel);
     panel += bpanel;

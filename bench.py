@@ -40,13 +40,15 @@ PREC = {"f64": 0, "split": 1, "f32": 2, "bf16x3": 3, "f64valu": 4}
 # L2, the cost-sorted queue does not; None for kernels without one): any
 # change to those sources makes the figure stale, and it is then reported as
 # null.
-_R1 = "4a6b3292980c6a95d3e6a34bc1d93b2435e74d13ec1870ffb4e4585e5c8b515a"
+_KS = "17e8fdbdbb1ad1eb1b4e3c94863612b6e994eb63421cf50b2eab45eb52cb48a1"
 TRAFFIC = {
-    ("k_contract", _R1, "f64", "cluster-120", 0): 11.081e9 + 3.973e9,
-    ("k_contract", _R1, "f64", "cluster-120", 1): 19.719e9 + 4.374e9,
-    ("k_density_tiles", _R1, "f64", "cluster-120", 0): 9.939e9 + 0.144e9,
-    ("k_panel", _R1, "f64", "cluster-120", None): 0.085e9 + 5.952e9,
-    ("k_reduce", _R1, "f64", "cluster-120", None): 3.586e9 + 0.019e9,
+    ("k_contract", _KS, "f64", "cluster-120", 0): 30.88e9 + 8.33e9,
+    ("k_density_tiles", _KS, "f64", "cluster-120", 0): 42.80e9 + 0.22e9,
+    ("k_panel", _KS, "f64", "cluster-120", None): 0.17e9 + 11.49e9,
+    ("k_reduce", _KS, "f64", "cluster-120", None): 7.19e9 + 0.03e9,
+    ("k_contract", _KS, "bf16x3", "cluster-120", 0): 26.56e9 + 7.74e9,
+    ("k_panel", _KS, "bf16x3", "cluster-120", None): 0.15e9 + 9.33e9,
+    ("k_reduce", _KS, "bf16x3", "cluster-120", None): 7.19e9 + 0.03e9,
 }
 
 # The same for k_contract_hs (q4c_integrate_HS) per component and work order,

@@ -335,7 +335,8 @@ int q4c_plan_set_ket_potential(q4c_plan *plan, const int64_t *shell_u_off, int64
  * part of the q4c_integrate_H store.  FP64 MFMA; batch sums added in a fixed
  * order (bitwise repeatable).  flags: Q4C_ACCUMULATE adds to hs_dev,
  * Q4C_CHECK_FINITE rejects a non-finite v (Q4C_ENONFINITE).  Q4C_EINVAL if no
- * ket potential is set.  Runs eagerly (no graph capture). */
+ * ket potential is set.  With graphs on (q4c_plan_set_graphs) each distinct
+ * (v_dev, hs_dev, flags) is captured once and replayed. */
 int q4c_integrate_HS(const q4c_plan *plan, const double *v_dev, uint32_t flags, double *hs_dev, void *stream);
 
 /* q4c_spinor_transform: the scalar -> spinor transformation of H and S

@@ -1603,7 +1603,11 @@ int q4c_integrate_HS(const q4c_plan *p, const double *v_dev, uint32_t flags, dou
     if (!ok) return fail(Q4C_ENONFINITE, "potential contains NaN or Inf");
   }
   p->panel_pass = -1;  // the H/S panels replace the W-path panels
-  return q4c::launch_integrate_hs(p, v_dev, flags & ~(uint32_t)Q4C_CHECK_FINITE, hs_dev, (hipStream_t)stream);
+  const uint32_t f = flags & ~(uint32_t)Q4C_CHECK_FINITE;
+  if (p->use_graphs && !p->profiling)
+    return run_graph(p, 2, v_dev, hs_dev, nullptr, nullptr, f, 0, 0, (hipStream_t)stream,
+                     [&](hipStream_t cs) { return q4c::launch_integrate_hs(p, v_dev, f, hs_dev, cs); });
+  return q4c::launch_integrate_hs(p, v_dev, f, hs_dev, (hipStream_t)stream);
 }
 
 int density_on_grid(const q4c_plan *p, const double *coef_dev, uint32_t terms, int32_t precision, int32_t weight_mode,

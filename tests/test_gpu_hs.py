@@ -143,6 +143,34 @@ def test_hs_repeatable_accumulate_and_launch_shapes(q, medium_sc):
     assert not np.array_equal(acc, a)
 
 
+def test_hs_graph_replay_bitwise(q, medium_sc):
+    """q4c_integrate_HS captured in a HIP graph and replayed several times,
+    with eager torch work and synchronisations between the replays, and
+    after a new ket potential (the captured graph is dropped): every replay
+    equals the eager result bit for bit."""
+    import torch
+    wl = medium_sc[0]
+    _, ref = _run_hs(q, wl)
+    plan = q.Plan(wl)
+    plan.set_ket_potential(wl)
+    plan.set_graphs(True)
+    v = torch.from_numpy(wl.v).cuda()
+    hs = q.new_hs(plan)
+    for rep in range(4):
+        hs.fill_(float("nan"))
+        q.q4c_integrate_HS(plan, v, 0, hs)
+        junk = torch.randn(1 << 16, device="cuda").sum()  # eager work between replays
+        torch.cuda.synchronize()
+        assert np.array_equal(hs.cpu().numpy(), ref), rep
+        del junk
+    plan.set_ket_potential(wl)  # the same table again: new device copies, graphs dropped
+    hs.fill_(float("nan"))
+    q.q4c_integrate_HS(plan, v, 0, hs)
+    torch.cuda.synchronize()
+    assert np.array_equal(hs.cpu().numpy(), ref)
+    plan.set_graphs(False)
+
+
 def test_hs_requires_ket_potential(q, small_lc):
     import torch
     wl = small_lc[0]

@@ -52,12 +52,14 @@ __global__ __launch_bounds__(NT, 2) void k_contract_hs(DevPlan d, const WorkItem
   for (int sl = 0; sl < 4; ++sl)
 #pragma unroll
     for (int q = 0; q < 3; ++q) acc[sl][q] = dbl4{0.0, 0.0, 0.0, 0.0};
-  // weights at points 4 ks + lk of the next chunk: w v and w
+  // K steps in pairs over 8 points (K index lk: point 2 lk of the 8, then
+  // 2 lk + 1), one 16-byte LDS read per operand for both; weights at the
+  // points this lane's K index visits in the next chunk: w v and w
   double omn[CH / 4], wn[CH / 4];
   auto load_w = [&](int k) {
 #pragma unroll
     for (int ks = 0; ks < CH / 4; ++ks) {
-      const int pt = k + 4 * ks + lk;
+      const int pt = k + 8 * (ks >> 1) + 2 * lk + (ks & 1);
       omn[ks] = pt < P ? om[g0 + pt] : 0.0;
       wn[ks] = pt < P ? d.pw[g0 + pt] : 0.0;
     }
@@ -83,20 +85,24 @@ __global__ __launch_bounds__(NT, 2) void k_contract_hs(DevPlan d, const WorkItem
     }
     const double *ca = sa + bo, *cb = sb + bo;
 #pragma unroll
-    for (int ks = 0; ks < CH / 4; ++ks) {
-      const int rowk = 2 * ks + (lk >> 1), ck = lk & 1;
+    for (int kp = 0; kp < CH / 8; ++kp) {
+      const int row = 4 * kp + lk;  // image row: points 8 kp + 2 lk, + 1
 #pragma unroll
       for (int sl = 0; sl < 4; ++sl) {
         if (!act[sl]) continue;  // wave-uniform
-        const double fi = ca[rowk * DROW + 2 * (brow[sl] + li16) + ck];
-        const double pi_ = ca[(RPQ + rowk) * DROW + 2 * (brow[sl] + li16) + ck];
-        const double fj = cb[rowk * DROW + 2 * (bcol[sl] + li16) + ck];
-        const double pj = cb[(RPQ + rowk) * DROW + 2 * (bcol[sl] + li16) + ck];
-        const double bw = wv[ks] * fj;                  // w phi_j
-        const double bh = omv[ks] * fj + wv[ks] * pj;   // w v phi_j + w psi_j
-        acc[sl][0] = mfma64(fi, bh, acc[sl][0]);
-        acc[sl][1] = mfma64(fi, bw, acc[sl][1]);
-        acc[sl][2] = mfma64(pi_, bw, acc[sl][2]);
+        const dbl2 fi2 = *reinterpret_cast<const dbl2 *>(&ca[row * DROW + 2 * (brow[sl] + li16)]);
+        const dbl2 pi2 = *reinterpret_cast<const dbl2 *>(&ca[(RPQ + row) * DROW + 2 * (brow[sl] + li16)]);
+        const dbl2 fj2 = *reinterpret_cast<const dbl2 *>(&cb[row * DROW + 2 * (bcol[sl] + li16)]);
+        const dbl2 pj2 = *reinterpret_cast<const dbl2 *>(&cb[(RPQ + row) * DROW + 2 * (bcol[sl] + li16)]);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int ks = 2 * kp + h;
+          const double bw = wv[ks] * fj2[h];                    // w phi_j
+          const double bh = omv[ks] * fj2[h] + wv[ks] * pj2[h];  // w v phi_j + w psi_j
+          acc[sl][0] = mfma64(fi2[h], bh, acc[sl][0]);
+          acc[sl][1] = mfma64(fi2[h], bw, acc[sl][1]);
+          acc[sl][2] = mfma64(pi2[h], bw, acc[sl][2]);
+        }
       }
     }
   }

@@ -1499,18 +1499,39 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t te
 #pragma unroll
       for (int q = 0; q < 4; ++q) cw[q][ks] = (float)creg[q + 1][ks];
   }
-  // column values of a chunk: Z[q][pt = k + l16][j]; result register r of
-  // lane (l16, lk) is column j = lk + 4 r at point l16 for FP64 MFMA, and
-  // j = 4 lk + r for FP32 MFMA (the W terms when F32W)
+  // column values of a chunk.  FP64 (TR): the MFMA takes the row values as
+  // its first operand (lane l16 supplying point 4 (l16 % 4) + l16 / 4) and
+  // the coefficients as its second, so result register r of lane (l16, lk)
+  // is point 4 lk + r at column colb + l16: each lane's four points of a
+  // component are one 32-byte quad of the panel, two 16-byte loads.  F32W:
+  // coefficients first, register r is column lk + 4 r (FP64 MFMA) or
+  // 4 lk + r (FP32 MFMA) at point l16.
+  constexpr bool TR = !F32W;
+  const int ptA = TR ? 4 * (l16 & 3) + (l16 >> 2) : l16;  // the point this lane supplies to the row operand
   double zn[4][4];
   auto load_z = [&](int k) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < 4; ++q) {
+      if (TR) {
+        if (any) {
+          const dbl2 *zq = reinterpret_cast<const dbl2 *>(pb + q * plane + ((int64_t)((k >> 2) + lk) * np + colb + l16) * 4);
+          const dbl2 z01 = zq[0], z23 = zq[1];
+          zn[q][0] = z01[0];
+          zn[q][1] = z01[1];
+          zn[q][2] = z23[0];
+          zn[q][3] = z23[1];
+        } else {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int jr = (F32W && q > 0) ? d_row_f32(lk, r) : d_row_f64(lk, r);
-        zn[q][r] = any ? pb[q * plane + ((int64_t)((k + l16) >> 2) * np + colb + jr) * 4 + (l16 & 3)] : 0.0;
+          for (int r = 0; r < 4; ++r) zn[q][r] = 0.0;
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int jr = (F32W && q > 0) ? d_row_f32(lk, r) : d_row_f64(lk, r);
+          zn[q][r] = any ? pb[q * plane + ((int64_t)((k + l16) >> 2) * np + colb + jr) * 4 + (l16 & 3)] : 0.0;
+        }
       }
+    }
   };
   load_z(0);
   double *out = partial + 2 * d.work_part_off[wi] + half * P;
@@ -1576,20 +1597,21 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t te
         constexpr int K0 = decltype(k0c)::value, K1 = decltype(k1c)::value;
 #pragma unroll
         for (int ks = K0; ks < K1; ++ks) {
-          // row values Y[q][pt = l16][i = iloc + 4 ks + lk]: the K index is lk
-          const int col = 2 * (iloc + 4 * ks + lk) + (l16 & 1);
-          const double y0 = ia[(0 * 8 + (l16 >> 1)) * RSA + col], y1 = ia[(1 * 8 + (l16 >> 1)) * RSA + col];
-          const double y2 = ia[(2 * 8 + (l16 >> 1)) * RSA + col], y3 = ia[(3 * 8 + (l16 >> 1)) * RSA + col];
-          uf = mfma64(creg[0][ks], y0, uf);
-          ux = mfma64(creg[1][ks], y1, ux);
-          uy = mfma64(creg[4][ks], y1, uy);
-          uz = mfma64(creg[3][ks], -y1, uz);
-          ux = mfma64(creg[4][ks], -y2, ux);
-          uy = mfma64(creg[1][ks], y2, uy);
-          uz = mfma64(creg[2][ks], y2, uz);
-          ux = mfma64(creg[3][ks], y3, ux);
-          uy = mfma64(creg[2][ks], -y3, uy);
-          uz = mfma64(creg[1][ks], y3, uz);
+          // row values Y[q][pt = ptA][i = iloc + 4 ks + lk]: the K index is lk;
+          // row values first, so the result is points x columns
+          const int col = 2 * (iloc + 4 * ks + lk) + (ptA & 1);
+          const double y0 = ia[(0 * 8 + (ptA >> 1)) * RSA + col], y1 = ia[(1 * 8 + (ptA >> 1)) * RSA + col];
+          const double y2 = ia[(2 * 8 + (ptA >> 1)) * RSA + col], y3 = ia[(3 * 8 + (ptA >> 1)) * RSA + col];
+          uf = mfma64(y0, creg[0][ks], uf);
+          ux = mfma64(y1, creg[1][ks], ux);
+          uy = mfma64(y1, creg[4][ks], uy);
+          uz = mfma64(-y1, creg[3][ks], uz);
+          ux = mfma64(-y2, creg[4][ks], ux);
+          uy = mfma64(y2, creg[1][ks], uy);
+          uz = mfma64(y2, creg[2][ks], uz);
+          ux = mfma64(y3, creg[3][ks], ux);
+          uy = mfma64(-y3, creg[2][ks], uy);
+          uz = mfma64(y3, creg[1][ks], uz);
         }
       };
       if (act[0] && act[1])
@@ -1598,13 +1620,27 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t te
         ksteps(std::integral_constant<int, 0>{}, std::integral_constant<int, 4>{});
       else
         ksteps(std::integral_constant<int, 4>{}, std::integral_constant<int, 8>{});
+      // per point (register r: point 4 lk + r), the sum over the 16 columns
+      // (lanes l16 of the row): halve the points per lane twice (xor 8, 4),
+      // then finish the sum (xor 2, 1); lane l16 ends with point 4 lk + r*,
+      // r* = 2 (l16 >> 3 & 1) + (l16 >> 2 & 1)
+      double xr[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) x += (uf[r] * zt[0][r] + ux[r] * zt[1][r]) + (uy[r] * zt[2][r] + uz[r] * zt[3][r]);
-      // sum over the block's 16 columns: the 4 registers (above), then the 4 lane rows
-      x += __shfl_xor(x, 16);
-      x += __shfl_xor(x, 32);
+      for (int r = 0; r < 4; ++r) xr[r] = (uf[r] * zt[0][r] + ux[r] * zt[1][r]) + (uy[r] * zt[2][r] + uz[r] * zt[3][r]);
+      const bool h8 = (l16 & 8) != 0, h4 = (l16 & 4) != 0;
+      double s0 = h8 ? xr[2] : xr[0], s1 = h8 ? xr[3] : xr[1];
+      s0 += __shfl_xor(h8 ? xr[0] : xr[2], 8);
+      s1 += __shfl_xor(h8 ? xr[1] : xr[3], 8);
+      x = h4 ? s1 : s0;
+      x += __shfl_xor(h4 ? s0 : s1, 4);
+      x += __shfl_xor(x, 2);
+      x += __shfl_xor(x, 1);
     }
-    if (lane < 16) s_red[bi][wave][l16] = x;
+    if (TR) {
+      if ((l16 & 3) == 0) s_red[bi][wave][4 * lk + 2 * ((l16 >> 3) & 1) + ((l16 >> 2) & 1)] = x;
+    } else {
+      if (lane < 16) s_red[bi][wave][l16] = x;
+    }
   }
   __syncthreads();  // the last chunk's per-wave sums
   {

@@ -1411,7 +1411,21 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t te
     }
   }
   // the first chunk's row image loads while the coefficients are read
-  dma_chunk<NTD, 16, T, RSA>(pb, plane, np, r0, 0, img[0]);
+  // the row image of a chunk by buffer loads straight into LDS: image row
+  // r = (component r / 8, point pair r % 8) holds 16 bytes per function; the
+  // lane offset is fixed, the chunk and image row go into the scalar offset
+  const __amdgpu_buffer_rsrc_t prs =
+      __builtin_amdgcn_make_buffer_rsrc((void *)pb, (short)0, (int)(32 * plane), 0x00020000);
+  const bool okr = r0 + lane < np;
+  auto dma_rows = [&](int ks0, double *dst) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int r = wave + 4 * k, q = r >> 3, u = r & 7;
+      const uint32_t so = (uint32_t)((q * plane + ((int64_t)(ks0 + (u >> 1)) * np + r0) * 4 + 2 * (u & 1)) * 8);
+      if (okr) __builtin_amdgcn_raw_ptr_buffer_load_lds(prs, (lds_void *)(dst + r * RSA), 16, lane * 32u, so, 0, 0);
+    }
+  };
+  dma_rows(0, img[0]);
   __syncthreads();  // slot tables visible
   // slot ranges of the tile's rows and the half's columns (slots ascend with
   // the functions; rows and columns beyond n carry slot -1)
@@ -1549,7 +1563,7 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t te
 #pragma unroll
       for (int r = 0; r < 4; ++r) zt[q][r] = zn[q][r];
     if (k0 + 16 < Pp) {
-      dma_chunk<NTD, 16, T, RSA>(pb, plane, np, r0, (k0 + 16) >> 2, img[bi ^ 1]);
+      dma_rows((k0 + 16) >> 2, img[bi ^ 1]);
       load_z(k0 + 16);
     }
     double x = 0.0;

@@ -1197,7 +1197,7 @@ __global__ __launch_bounds__(NT, 2) void k_contract_b3(DevPlan d, const WorkItem
 // one).  The sum is a single sequential chain in batch order, so results
 // repeat bit for bit and do not depend on how batches are split into passes.
 // Loads of four incidences are issued together.
-constexpr int NTR = 256;  // threads of a k_reduce workgroup
+constexpr int NTR = 1024;  // threads of a k_reduce workgroup
 __global__ __launch_bounds__(NTR) void k_reduce(DevPlan d, int64_t r0, const int32_t *red_pair,
                                                 const uint8_t *red_first, const int64_t *red_inc_off,
                                                 const int64_t *inc_src, const double *staging, double *store,

@@ -128,6 +128,14 @@ def test_argument_validation():
     assert lib.density_on_grid(p.handle, ctypes.c_void_p(1), 7, 0, 2, ctypes.c_void_p(1), None) == q.Q4C_EINVAL
     assert lib.density_on_grid(p.handle, ctypes.c_void_p(1), 7, q.PREC_SPLIT_F32, 1, ctypes.c_void_p(1), None) == q.Q4C_EINVAL
     assert lib.density_on_grid(p.handle, ctypes.c_void_p(1), 7, 9, 1, ctypes.c_void_p(1), None) == q.Q4C_EINVAL
+    for prec in (q.PREC_BF16X3, q.PREC_F64_VALU):  # forward-only precisions
+        assert lib.density_on_grid(p.handle, ctypes.c_void_p(1), 7, prec, 1, ctypes.c_void_p(1), None) == q.Q4C_EINVAL
+    # every forward precision passes validation and then needs a device
+    for prec in (q.PREC_F64, q.PREC_SPLIT_F32, q.PREC_F32, q.PREC_BF16X3, q.PREC_F64_VALU):
+        assert lib.q4c_integrate_H(p.handle, ctypes.c_void_p(1), prec, 7, 0, ctypes.c_void_p(1), None, None,
+                                   None) == q.Q4C_ENODEV
+    assert lib.q4c_integrate_H(p.handle, ctypes.c_void_p(1), 5, 7, 0, ctypes.c_void_p(1), None, None,
+                               None) == q.Q4C_EINVAL
     assert lib.q4c_integrate_H(None, ctypes.c_void_p(1), 0, 7, 0, ctypes.c_void_p(1), None, None, None) == q.Q4C_EINVAL
     n = ctypes.c_int64()
     assert lib.q4c_tabulate_size(p.handle, 0, p.info["n_batches"] + 1, 1, ctypes.byref(n)) == q.Q4C_EINVAL

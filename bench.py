@@ -40,22 +40,22 @@ PREC = {"f64": 0, "split": 1, "f32": 2, "bf16x3": 3, "f64valu": 4}
 # L2, the cost-sorted queue does not; None for kernels without one): any
 # change to those sources makes the figure stale, and it is then reported as
 # null.
-_KS = "17e8fdbdbb1ad1eb1b4e3c94863612b6e994eb63421cf50b2eab45eb52cb48a1"
+_KS = "bd9dddd226195d1d9550bf8c6b11d901e28ce9017226a5ba2b957c3c8ebe9095"
 TRAFFIC = {
-    ("k_contract", _KS, "f64", "cluster-120", 0): 30.88e9 + 8.33e9,
-    ("k_density_tiles", _KS, "f64", "cluster-120", 0): 42.80e9 + 0.22e9,
+    ("k_contract", _KS, "f64", "cluster-120", 0): 30.66e9 + 8.34e9,
+    ("k_density_tiles", _KS, "f64", "cluster-120", 0): 41.08e9 + 0.21e9,
     ("k_panel", _KS, "f64", "cluster-120", None): 0.17e9 + 11.49e9,
-    ("k_reduce", _KS, "f64", "cluster-120", None): 7.19e9 + 0.03e9,
-    ("k_contract", _KS, "bf16x3", "cluster-120", 0): 26.56e9 + 7.74e9,
-    ("k_panel", _KS, "bf16x3", "cluster-120", None): 0.15e9 + 9.33e9,
-    ("k_reduce", _KS, "bf16x3", "cluster-120", None): 7.19e9 + 0.03e9,
+    ("k_reduce", _KS, "f64", "cluster-120", None): 7.28e9 + 0.03e9,
+    ("k_contract", _KS, "bf16x3", "cluster-120", 0): 28.38e9 + 7.74e9,
+    ("k_panel", _KS, "bf16x3", "cluster-120", None): 0.15e9 + 9.34e9,
+    ("k_reduce", _KS, "bf16x3", "cluster-120", None): 7.28e9 + 0.03e9,
 }
 
 # The same for k_contract_hs (q4c_integrate_HS) per component and work order,
 # keyed by the SHA-256 of q4c_hs_kernels.hip and q4c_device.h.
 HS_TRAFFIC = {
-    ("83b3d5b5224536fad91acb8995cda311856d88c1ac0aa6a2dc4c581ba2e04bea", "large", 120, 0): 6.109e9 + 3.061e9,
-    ("83b3d5b5224536fad91acb8995cda311856d88c1ac0aa6a2dc4c581ba2e04bea", "small", 120, 0): 6.398e9 + 7.028e9,
+    ("126fbdd2a75052cf312bb5537d84087bab3e7d99a8db89fcef23863de0ecc596", "large", 120, 0): 6.538e9 + 3.097e9,
+    ("126fbdd2a75052cf312bb5537d84087bab3e7d99a8db89fcef23863de0ecc596", "small", 120, 0): 6.884e9 + 7.300e9,
 }
 
 
@@ -307,8 +307,9 @@ def bench_hs(wl, timed, steps: int, cpu_frac: float, with_cpu: bool, components=
         t0 = time.perf_counter()
         oracle.pair_blocks_hs(sub, pairs)
         dt = time.perf_counter() - t0
-        out["cpu_oracle_large"] = {"value": idx.size / dt, "unit": "input points/s", "cores": 1, "kind": "oracle",
-                                   "sample": "%d of %d grid points (seed 6102), all %d atom pairs, %.1f s" %
+        out["cpu_oracle_large"] = {"value": idx.size / dt, "unit": "input points/s", "cores": oracle.max_threads(),
+                                   "kind": "oracle",
+                                   "sample": "%d of %d grid points (seed 6102), all %d atom pairs, %.2f s" %
                                              (idx.size, wl.n_points, len(pairs), dt)}
     return out
 
@@ -732,7 +733,7 @@ def main():
         log("Bloch density matrix: %d k-points -> %d stored elements: %.3f ms per call, k_bloch_density %.3f ms"
             % (kp.shape[0], plan.info["store_len"], ms_d, kd_ms))
     if not a.no_hs and a.workload == "cluster":
-        res["hs"] = bench_hs(wl, timed, a.steps, 0.02 * a.cpu_sample, not a.no_cpu_baseline)
+        res["hs"] = bench_hs(wl, timed, a.steps, 0.2 * a.cpu_sample, not a.no_cpu_baseline)
     if not a.no_cpu_baseline and a.workload == "cluster":
         res["cpu_baseline"] = cpu_baseline(wl, plan, gbar, a.cpu_sample, 0.1 * a.cpu_sample)
     print(json.dumps(res), flush=True)

@@ -7,6 +7,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <utility>
+#include <type_traits>
 
 #include "q4c_internal.h"
 
@@ -61,6 +63,46 @@ __device__ __forceinline__ int64_t next_item(unsigned *tickets, int64_t nw, bool
   return *s_pos;
 }
 
+// The same queues for a workgroup that draws its next ticket while it still
+// works on the current item: draw_ticket (one thread) adds to its XCD's queue
+// (or the global one) and the result is first needed after the item, so the
+// atomic's round trip hides behind the item's work; ticket_pos turns the
+// ticket into a position and, once the own queue is drained, takes one from
+// the other XCDs' queues as next_item does.  A drained queue's counter may
+// grow past its range; it is never read as a position.
+__device__ __forceinline__ unsigned draw_ticket(unsigned *tickets, bool global_queue) {
+  return atomicAdd(&tickets[global_queue ? 0 : (int)(blockIdx.x & 7) * kTicketStride], 1u);
+}
+
+__device__ __forceinline__ int64_t ticket_pos(unsigned *tickets, int64_t nw, bool global_queue, unsigned tk) {
+  if (global_queue) return (int64_t)tk < nw ? (int64_t)tk : nw;
+  const int x0 = (int)(blockIdx.x & 7);
+  {
+    const int64_t lo = nw * x0 / 8, hi = nw * (x0 + 1) / 8;
+    if (lo + (int64_t)tk < hi) return lo + (int64_t)tk;
+  }
+  for (int k = 1; k < 8; ++k) {
+    const int x = (x0 + k) & 7;
+    const int64_t lo = nw * x / 8, hi = nw * (x + 1) / 8;
+    if (hi <= lo) continue;
+    if ((int64_t)__hip_atomic_load(&tickets[x * kTicketStride], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= hi - lo)
+      continue;
+    const int64_t t = atomicAdd(&tickets[x * kTicketStride], 1u);
+    if (lo + t < hi) return lo + t;
+  }
+  return nw;
+}
+
+// lane exchange within rows of 16 lanes by DPP (no LDS traffic): lane i reads
+// lane 15 - i (row mirror), 8 (i / 8) + 7 - i % 8 (half-row mirror), i ^ 2 or
+// i ^ 1 (quad permutes); a double moves as its two 32-bit halves
+constexpr int DPP_QUAD_XOR1 = 0xB1, DPP_QUAD_XOR2 = 0x4E, DPP_ROW_MIRROR = 0x140, DPP_ROW_HALF_MIRROR = 0x141;
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
 
 __device__ __forceinline__ dbl4 mfma64(double a, double b, dbl4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -95,6 +137,16 @@ __device__ __forceinline__ SlotInfo slot_of(const DevPlan &d, int fbase, int sba
   s.nfn = d.slot_nfn[sbase + s.slot];
   s.row_off = d.slot_row_off[sbase + s.slot];
   return s;
+}
+
+// Slot, the slot's first local function and its function count of
+// batch-local function lf, from the packed table (one load).
+struct SlotFn {
+  int slot, fnoff, nfn;
+};
+__device__ __forceinline__ SlotFn slot_fn(const DevPlan &d, int fbase, int lf) {
+  const int64_t v = d.loc_info[fbase + lf];
+  return SlotFn{(int)(v & 0xFFFFF), (int)((v >> 20) & 0xFFFFF), (int)(v >> 40)};
 }
 
 // The five parts: 0 V, 1 Ws, 2 Wso_x, 3 Wso_y, 4 Wso_z.  Mirror sign under
@@ -199,6 +251,22 @@ __device__ __forceinline__ int d_row_f32(int lk, int r) { return 4 * lk + r; }
 // once.
 constexpr int DROW = 2 * T;  // doubles per LDS row
 typedef __attribute__((address_space(3))) void lds_void;
+
+// LDS byte address of a __shared__ array element
+__device__ __forceinline__ uint32_t lds_addr(const double *p) {
+  return (uint32_t)(uintptr_t)(const lds_void *)(const void *)p;
+}
+
+// Calls f(std::integral_constant<int, K>) for K = K0, K0 + S, ... < K1, as
+// straight-line code with K a constant expression in f.
+template <int K0, int S, class F, int... I>
+__device__ __forceinline__ void static_for_seq(F &&f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, K0 + S * I>{}), ...);
+}
+template <int K0, int K1, int S = 1, class F>
+__device__ __forceinline__ void static_for(F &&f) {
+  static_for_seq<K0, S>(f, std::make_integer_sequence<int, (K1 - K0 + S - 1) / S>{});
+}
 
 // Issue the LDS DMA loads of one chunk of CH points (panel K steps ks0 ..
 // ks0 + CH/4 - 1) of functions row0 .. row0+T-1 into dst (4 * CH/2 rows of

@@ -161,11 +161,6 @@ __device__ __forceinline__ void gemm_dma(const double *pb, int np, int Pp, int p
   }
 }
 
-// LDS byte address of a __shared__ array element
-__device__ __forceinline__ uint32_t lds_addr(const double *p) {
-  return (uint32_t)(uintptr_t)(const lds_void *)(const void *)p;
-}
-
 // The 16 MFMA operands of one K chunk of a wave, A[mb][ks] at pa + 2048 mb +
 // 128 ks and B[nb][ks] at pb + 2048 ks + 128 nb (bytes), read in one asm
 // block that also waits for them.  Issued by hand so that the compiler, which

@@ -44,6 +44,7 @@ struct DevPlan {
   const int32_t *batch_fn_off;      // [n_batches + 1]
   const int32_t *loc_fn;            // [fn_entries] global function
   const int32_t *loc_slot;          // [fn_entries] slot (relevant atom) within the batch
+  const int64_t *loc_info;          // [fn_entries] slot | slot's first local function << 20 | its function count << 40
   const int32_t *batch_slot_off;    // [n_batches + 1]
   const int32_t *slot_fnoff;        // [n_slots] local function offset of the slot
   const int32_t *slot_nfn;          // [n_slots]
@@ -56,6 +57,7 @@ struct DevPlan {
   // per batch, for slot pairs si <= sj (upper triangle, row-major): the stored
   // pair of the two atoms, or -1; batch b's table starts at batch_sp_off[b]
   const int32_t *sp_pair;
+  const int64_t *sp_poff;           // the same table holding the pair's store offset (pair_off), or -1
   const int64_t *batch_sp_off;      // [n_batches + 1]
   const int64_t *tab_off;           // [n_batches + 1] prefix of P_b n_b (nao_tabulate layout)
   const int64_t *panel_off;         // [n_batches] pass-relative offset of the batch's operand panel
@@ -186,6 +188,7 @@ struct q4c_plan {
   int32_t *d_untouched = nullptr;
   q4c::WorkItem *d_ptile = nullptr;
   double *d_om = nullptr;  // [n_active + 16] point weights w_g v_g of the current call
+  double *d_coef_fold = nullptr;  // [5][store_len + 16] the adjoint's coefficients of the current call (k_coef_fold)
   double *d_ucoef = nullptr;         // ket-potential tables (q4c_plan_set_ket_potential)
   int64_t *d_shell_us_off = nullptr;
   double *d_staging = nullptr;

@@ -1342,15 +1342,39 @@ __device__ __forceinline__ bool half_valid(const WorkItem &it, int h, int n) { r
 // and point) are drained into the FP64 point sum, so the FP32 error of a
 // point is at most gamma_98 (u = 2^-24) times the magnitudes of its W terms.
 // The V term stays FP64.
+// The row values of K steps KS and KS + 1 of one lane, four components
+// each: component q of step k at LDS byte address a + 64 RSA q + 64 k.  Read
+// in one asm block that also waits for them, by hand: the compiler cannot
+// tell these reads from the next chunk's LDS DMA into the other image buffer
+// and would otherwise wait for that DMA before the first read.
+template <int KS>
+__device__ __forceinline__ void read_rows2(uint32_t a, double (&y)[2][4]) {
+  constexpr int QS = 64 * RSA, K = 64 * KS;
+  asm volatile(
+      "ds_read_b64 %0, %8 offset:%9\n"
+      "ds_read_b64 %1, %8 offset:%10\n"
+      "ds_read_b64 %2, %8 offset:%11\n"
+      "ds_read_b64 %3, %8 offset:%12\n"
+      "ds_read_b64 %4, %8 offset:%13\n"
+      "ds_read_b64 %5, %8 offset:%14\n"
+      "ds_read_b64 %6, %8 offset:%15\n"
+      "ds_read_b64 %7, %8 offset:%16\n"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(y[0][0]), "=&v"(y[0][1]), "=&v"(y[0][2]), "=&v"(y[0][3]), "=&v"(y[1][0]), "=&v"(y[1][1]),
+        "=&v"(y[1][2]), "=&v"(y[1][3])
+      : "v"(a), "i"(K), "i"(K + QS), "i"(K + 2 * QS), "i"(K + 3 * QS), "i"(K + 64), "i"(K + 64 + QS),
+        "i"(K + 64 + 2 * QS), "i"(K + 64 + 3 * QS)
+      : "memory");
+}
+
 template <bool F32W, bool PERSIST>
-__global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t terms, const WorkItem *work,
-                                                          const int32_t *order, int64_t w0, int64_t nw,
-                                                          const double *coef, const double *panel,
-                                                          double *partial, unsigned *tickets) {
+__global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, const WorkItem *work, const int32_t *order,
+                                                          int64_t w0, int64_t nw, const double *cf,
+                                                          const double *panel, double *partial, unsigned *tickets) {
   constexpr int NC = 5;  // coefficient parts
   __shared__ double img[2][AIMG];        // row images, alternating chunks
   __shared__ double s_red[2][4][16];     // per-wave point sums, alternating chunks
-  __shared__ int64_t s_pos;
+  __shared__ int64_t s_pos, s_next[2];
   // slot data of the tile's 64 rows and the half's 32 columns (slot -1: beyond n)
   __shared__ int s_rslot[T], s_rfn[T], s_cslot[T / 2], s_cfn[T / 2], s_cnf[T / 2];
   // store offset of the pair block of (row slot, column slot) for the slots
@@ -1362,7 +1386,11 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t te
   const int64_t npos = 2 * nw;
   int64_t pos = PERSIST ? next_item(tickets, npos, order != nullptr, &s_pos)
                         : (order ? (int64_t)blockIdx.x : xcd_map(blockIdx.x, npos));
+  int par = 0;
   while (!PERSIST || pos < npos) {
+  // the next item's ticket, drawn now and first needed after this item
+  unsigned tk = 0;
+  if (PERSIST && threadIdx.x == 0) tk = draw_ticket(tickets, order != nullptr);
   const int half = (int)(pos & 1);
   const int64_t wi = w0 + (order ? order[w0 + (pos >> 1)] : (pos >> 1));
   const WorkItem it = work[wi];
@@ -1396,24 +1424,12 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t te
     upper[h] = rb < colb;
   }
   const bool any = act[0] || act[1];
-  if (tid < T + T / 2) {
-    const bool row = tid < T;
-    const int lf = row ? r0 + tid : c0 + tid - T;
-    SlotInfo si{-1, 0, 0, 0};
-    if (lf < n) si = slot_of(d, f0, sbase, lf);
-    if (row) {
-      s_rslot[tid] = si.slot;
-      s_rfn[tid] = si.fnoff;
-    } else {
-      s_cslot[tid - T] = si.slot;
-      s_cfn[tid - T] = si.fnoff;
-      s_cnf[tid - T] = si.nfn;
-    }
-  }
-  // the first chunk's row image loads while the coefficients are read
-  // the row image of a chunk by buffer loads straight into LDS: image row
-  // r = (component r / 8, point pair r % 8) holds 16 bytes per function; the
-  // lane offset is fixed, the chunk and image row go into the scalar offset
+  // The item's loads go out in as few round trips as their dependences allow:
+  // the first chunk's row image and column values together with the slot
+  // data, then the pair offsets, then the coefficients.
+  // The row image of a chunk comes by buffer loads straight into LDS: image
+  // row r = (component r / 8, point pair r % 8) holds 16 bytes per function;
+  // the lane offset is fixed, the chunk and image row go into the scalar offset.
   const __amdgpu_buffer_rsrc_t prs =
       __builtin_amdgcn_make_buffer_rsrc((void *)pb, (short)0, (int)(32 * plane), 0x00020000);
   const bool okr = r0 + lane < np;
@@ -1426,93 +1442,6 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t te
     }
   };
   dma_rows(0, img[0]);
-  __syncthreads();  // slot tables visible
-  // slot ranges of the tile's rows and the half's columns (slots ascend with
-  // the functions; rows and columns beyond n carry slot -1)
-  const int rs0 = s_rslot[0], cs0 = s_cslot[0];
-  const int rs1 = s_rslot[min(T, n - r0) - 1], cs1 = s_cslot[min(T / 2, n - c0) - 1];
-  const int nrs = rs1 - rs0 + 1, ncs = cs1 - cs0 + 1;
-  const int ns = d.batch_slot_off[b + 1] - sbase;
-  const int64_t spb = d.batch_sp_off[b];
-  // store offset of the pair block of slots (si, sj), -1 if none
-  auto pair_offset = [&](int si, int sj) -> int64_t {
-    if (si > sj) return -1;
-    // upper-triangle index of (si, sj)
-    const int q = d.sp_pair[spb + (int64_t)si * ns - (int64_t)si * (si - 1) / 2 + (sj - si)];
-    return q >= 0 ? d.pair_off[q] : -1;
-  };
-  const bool lds_table = nrs * ncs <= POFF_LDS;  // workgroup-uniform
-  if (lds_table)
-    for (int t = tid; t < nrs * ncs; t += NTD) s_poff[t] = pair_offset(rs0 + t / ncs, cs0 + t % ncs);
-  __syncthreads();  // pair offsets visible
-  // coefficient slice: rows i = r0 + iloc + 4 ks + lk (ks = 0..7), column lj,
-  // read from the store: element (li, lj) of the pair block of its two atoms
-  // (upper atom-block triangle only), plus the mirrored element (lj, li) when
-  // the 16 x 16 block is strictly upper inside one atom block (no work item
-  // computes the mirrored block); c' on the W parts, zero for unselected
-  // terms.  The loads of each kind are issued together before any is used.
-  double creg[NC][8];
-  {
-    const int64_t L = d.store_len;
-    const int cl = 16 * js + l16;
-    const int cslot = s_cslot[cl], cfn = s_cfn[cl], cnf = s_cnf[cl];
-    int64_t em[8];
-    bool mir[8];
-    const bool on[NC] = {(terms & Q4C_TERM_LL) != 0, (terms & Q4C_TERM_SS) != 0, (terms & Q4C_TERM_SO) != 0,
-                         (terms & Q4C_TERM_SO) != 0, (terms & Q4C_TERM_SO) != 0};
-    {
-      int64_t ea[8];
-      bool live[8];
-#pragma unroll
-      for (int ks = 0; ks < 8; ++ks) {
-        const int rl = iloc + 4 * ks + lk;
-        const int li = r0 + rl;
-        const int rslot = s_rslot[rl], rfn = s_rfn[rl];
-        int64_t po = -1;
-        if (act[ks >> 2] && rslot >= 0 && cslot >= 0)
-          po = lds_table ? s_poff[(rslot - rs0) * ncs + (cslot - cs0)] : pair_offset(rslot, cslot);
-        live[ks] = po >= 0;
-        mir[ks] = live[ks] && upper[ks >> 2] && rslot == cslot;
-        ea[ks] = live[ks] ? po + (int64_t)(li - rfn) * cnf + (lj - cfn) : 0;
-        em[ks] = mir[ks] ? po + (int64_t)(lj - rfn) * cnf + (li - cfn) : 0;
-      }
-#pragma unroll
-      for (int ks = 0; ks < 8; ++ks)
-#pragma unroll
-        for (int q = 0; q < NC; ++q) creg[q][ks] = coef[q * L + ea[ks]];
-#pragma unroll
-      for (int ks = 0; ks < 8; ++ks)
-#pragma unroll
-        for (int q = 0; q < NC; ++q) creg[q][ks] = live[ks] && on[q] ? creg[q][ks] : 0.0;
-    }
-    // mirrored elements: only strictly upper 16 x 16 blocks (wave-uniform) can have them
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      if (!upper[h]) continue;
-      double cm[NC][4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k)
-#pragma unroll
-        for (int q = 0; q < NC; ++q) cm[q][k] = coef[q * L + em[4 * h + k]];
-#pragma unroll
-      for (int k = 0; k < 4; ++k)
-#pragma unroll
-        for (int q = 0; q < NC; ++q)
-          if (mir[4 * h + k] && on[q]) creg[q][4 * h + k] += mirror_sign(q) * cm[q][k];
-    }
-#pragma unroll
-    for (int ks = 0; ks < 8; ++ks)
-#pragma unroll
-      for (int q = 1; q < NC; ++q) creg[q][ks] *= d.cprime;
-  }
-  // F32W: the W coefficients as FP32 MFMA operands
-  float cw[4][8];
-  if (F32W) {
-#pragma unroll
-    for (int ks = 0; ks < 8; ++ks)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) cw[q][ks] = (float)creg[q + 1][ks];
-  }
   // column values of a chunk.  FP64 (TR): the MFMA takes the row values as
   // its first operand (lane l16 supplying point 4 (l16 % 4) + l16 / 4) and
   // the coefficients as its second, so result register r of lane (l16, lk)
@@ -1548,6 +1477,68 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t te
     }
   };
   load_z(0);
+  if (tid < T + T / 2) {
+    const bool row = tid < T;
+    const int lf = row ? r0 + tid : c0 + tid - T;
+    SlotFn si{-1, 0, 0};
+    if (lf < n) si = slot_fn(d, f0, lf);
+    if (row) {
+      s_rslot[tid] = si.slot;
+      s_rfn[tid] = si.fnoff;
+    } else {
+      s_cslot[tid - T] = si.slot;
+      s_cfn[tid - T] = si.fnoff;
+      s_cnf[tid - T] = si.nfn;
+    }
+  }
+  __syncthreads();  // slot tables visible
+  // slot ranges of the tile's rows and the half's columns (slots ascend with
+  // the functions; rows and columns beyond n carry slot -1)
+  const int rs0 = s_rslot[0], cs0 = s_cslot[0];
+  const int rs1 = s_rslot[min(T, n - r0) - 1], cs1 = s_cslot[min(T / 2, n - c0) - 1];
+  const int nrs = rs1 - rs0 + 1, ncs = cs1 - cs0 + 1;
+  const int ns = d.batch_slot_off[b + 1] - sbase;
+  const int64_t spb = d.batch_sp_off[b];
+  // store offset of the pair block of slots (si, sj), -1 if none
+  auto pair_offset = [&](int si, int sj) -> int64_t {
+    if (si > sj) return -1;
+    // upper-triangle index of (si, sj)
+    return d.sp_poff[spb + (int64_t)si * ns - (int64_t)si * (si - 1) / 2 + (sj - si)];
+  };
+  const bool lds_table = nrs * ncs <= POFF_LDS;  // workgroup-uniform
+  if (lds_table)
+    for (int t = tid; t < nrs * ncs; t += NTD) s_poff[t] = pair_offset(rs0 + t / ncs, cs0 + t % ncs);
+  __syncthreads();  // pair offsets visible
+  // coefficient slice: rows i = r0 + iloc + 4 ks + lk (ks = 0..7), column lj:
+  // element (li, lj) of the folded coefficients (k_coef_fold) in the pair
+  // block of its two atoms (upper atom-block triangle only); lanes without a
+  // stored element read the zeros past the end of each part
+  double creg[NC][8];
+  {
+    const int64_t Lf = d.store_len + 16;
+    const int cl = 16 * js + l16;
+    const int cslot = s_cslot[cl], cfn = s_cfn[cl], cnf = s_cnf[cl];
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+      const int rl = iloc + 4 * ks + lk;
+      const int li = r0 + rl;
+      const int rslot = s_rslot[rl], rfn = s_rfn[rl];
+      int64_t po = -1;
+      if (act[ks >> 2] && rslot >= 0 && cslot >= 0)
+        po = lds_table ? s_poff[(rslot - rs0) * ncs + (cslot - cs0)] : pair_offset(rslot, cslot);
+      const int64_t ea = po >= 0 ? po + (int64_t)(li - rfn) * cnf + (lj - cfn) : d.store_len;
+#pragma unroll
+      for (int q = 0; q < NC; ++q) creg[q][ks] = cf[q * Lf + ea];
+    }
+  }
+  // F32W: the W coefficients as FP32 MFMA operands
+  float cw[4][8];
+  if (F32W) {
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) cw[q][ks] = (float)creg[q + 1][ks];
+  }
   double *out = partial + 2 * d.work_part_off[wi] + half * P;
 
   for (int k0 = 0; k0 < Pp; k0 += 16) {
@@ -1568,18 +1559,23 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t te
     }
     double x = 0.0;
     if (any && F32W) {
-      const double *ia = img[bi];
+      // this lane's row values of K step 0, component 0 (point ptA, row iloc + lk)
+      const uint32_t ybase = lds_addr(img[bi]) + 8u * (uint32_t)((ptA >> 1) * RSA + 2 * (iloc + lk) + (ptA & 1));
       dbl4 uf = dbl4{0.0, 0.0, 0.0, 0.0};
       flt4 vx = flt4{0.f, 0.f, 0.f, 0.f}, vy = vx, vz = vx;
       auto ksteps = [&](auto k0c, auto k1c) {
         constexpr int K0 = decltype(k0c)::value, K1 = decltype(k1c)::value;
+        static_for<K0, K1, 2>([&](auto kpc) {
+        constexpr int KP = decltype(kpc)::value;
+        double yy[2][4];
+        read_rows2<KP>(ybase, yy);
 #pragma unroll
-        for (int ks = K0; ks < K1; ++ks) {
-          const int col = 2 * (iloc + 4 * ks + lk) + (l16 & 1);
-          const double y0 = ia[(0 * 8 + (l16 >> 1)) * RSA + col];
-          const float y1 = (float)ia[(1 * 8 + (l16 >> 1)) * RSA + col];
-          const float y2 = (float)ia[(2 * 8 + (l16 >> 1)) * RSA + col];
-          const float y3 = (float)ia[(3 * 8 + (l16 >> 1)) * RSA + col];
+        for (int h = 0; h < 2; ++h) {
+          const int ks = KP + h;
+          const double y0 = yy[h][0];
+          const float y1 = (float)yy[h][1];
+          const float y2 = (float)yy[h][2];
+          const float y3 = (float)yy[h][3];
           uf = mfma64(creg[0][ks], y0, uf);
           vx = mfma32(cw[0][ks], y1, vx);
           vy = mfma32(cw[3][ks], y1, vy);
@@ -1591,6 +1587,7 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t te
           vy = mfma32(cw[1][ks], -y3, vy);
           vz = mfma32(cw[0][ks], y3, vz);
         }
+        });
       };
       if (act[0] && act[1])
         ksteps(std::integral_constant<int, 0>{}, std::integral_constant<int, 8>{});
@@ -1604,18 +1601,22 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t te
       x += __shfl_xor(x, 16);
       x += __shfl_xor(x, 32);
     } else if (any) {
-      const double *ia = img[bi];
+      // this lane's row values of K step 0, component 0 (point ptA, row iloc + lk)
+      const uint32_t ybase = lds_addr(img[bi]) + 8u * (uint32_t)((ptA >> 1) * RSA + 2 * (iloc + lk) + (ptA & 1));
       dbl4 uf = dbl4{0.0, 0.0, 0.0, 0.0}, ux = uf, uy = uf, uz = uf;
       // the K steps of active 16-row blocks, as straight-line code
       auto ksteps = [&](auto k0c, auto k1c) {
         constexpr int K0 = decltype(k0c)::value, K1 = decltype(k1c)::value;
+        static_for<K0, K1, 2>([&](auto kpc) {
+        constexpr int KP = decltype(kpc)::value;
+        double yy[2][4];
+        read_rows2<KP>(ybase, yy);
 #pragma unroll
-        for (int ks = K0; ks < K1; ++ks) {
+        for (int h = 0; h < 2; ++h) {
           // row values Y[q][pt = ptA][i = iloc + 4 ks + lk]: the K index is lk;
           // row values first, so the result is points x columns
-          const int col = 2 * (iloc + 4 * ks + lk) + (ptA & 1);
-          const double y0 = ia[(0 * 8 + (ptA >> 1)) * RSA + col], y1 = ia[(1 * 8 + (ptA >> 1)) * RSA + col];
-          const double y2 = ia[(2 * 8 + (ptA >> 1)) * RSA + col], y3 = ia[(3 * 8 + (ptA >> 1)) * RSA + col];
+          const int ks = KP + h;
+          const double y0 = yy[h][0], y1 = yy[h][1], y2 = yy[h][2], y3 = yy[h][3];
           uf = mfma64(y0, creg[0][ks], uf);
           ux = mfma64(y1, creg[1][ks], ux);
           uy = mfma64(y1, creg[4][ks], uy);
@@ -1627,6 +1628,7 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t te
           uy = mfma64(-y3, creg[2][ks], uy);
           uz = mfma64(y3, creg[1][ks], uz);
         }
+        });
       };
       if (act[0] && act[1])
         ksteps(std::integral_constant<int, 0>{}, std::integral_constant<int, 8>{});
@@ -1643,12 +1645,12 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t te
       for (int r = 0; r < 4; ++r) xr[r] = (uf[r] * zt[0][r] + ux[r] * zt[1][r]) + (uy[r] * zt[2][r] + uz[r] * zt[3][r]);
       const bool h8 = (l16 & 8) != 0, h4 = (l16 & 4) != 0;
       double s0 = h8 ? xr[2] : xr[0], s1 = h8 ? xr[3] : xr[1];
-      s0 += __shfl_xor(h8 ? xr[0] : xr[2], 8);
-      s1 += __shfl_xor(h8 ? xr[1] : xr[3], 8);
+      s0 += dpp_f64<DPP_ROW_MIRROR>(h8 ? xr[0] : xr[2]);
+      s1 += dpp_f64<DPP_ROW_MIRROR>(h8 ? xr[1] : xr[3]);
       x = h4 ? s1 : s0;
-      x += __shfl_xor(h4 ? s0 : s1, 4);
-      x += __shfl_xor(x, 2);
-      x += __shfl_xor(x, 1);
+      x += dpp_f64<DPP_ROW_HALF_MIRROR>(h4 ? s0 : s1);
+      x += dpp_f64<DPP_QUAD_XOR2>(x);
+      x += dpp_f64<DPP_QUAD_XOR1>(x);
     }
     if (TR) {
       if ((l16 & 3) == 0) s_red[bi][wave][4 * lk + 2 * ((l16 >> 3) & 1) + ((l16 >> 2) & 1)] = x;
@@ -1664,7 +1666,47 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, uint32_t te
   }
   }  // half_valid
   if (!PERSIST) break;
-  pos = next_item(tickets, npos, order != nullptr, &s_pos);
+  // two slots in turn: a workgroup's thread 0 may write the next slot before
+  // every thread has read this one
+  if (threadIdx.x == 0) s_next[par] = ticket_pos(tickets, npos, order != nullptr, tk);
+  __syncthreads();
+  pos = s_next[par];
+  par ^= 1;
+  }
+}
+
+// The adjoint's coefficients, folded once per call.  Eq. 39 sums every stored
+// element ij of the selected terms; the adjoint's work items cover the upper
+// 16 x 16 blocks of each batch, so in the diagonal block of one atom element
+// (i, j), i < j, takes C_q(i, j) + s_q C_q(j, i) (s_q = +1 for V and Ws, -1
+// for the spin-orbit parts, whose terms change sign under i <-> j), (i, i)
+// keeps C_q(i, i) and i > j is zero: every term is then carried once.  Blocks
+// of two atoms are copied.  c' multiplies the W parts, unselected terms are
+// zero, and each part ends in 16 zeros (row stride store_len + 16), the
+// element of lanes without a stored one.  One workgroup per pair.
+__global__ void k_coef_fold(DevPlan d, const double *coef, uint32_t terms, double *cf) {
+  const int64_t L = d.store_len, Lf = L + 16;
+  const int64_t q = blockIdx.x;
+  const bool on[5] = {(terms & Q4C_TERM_LL) != 0, (terms & Q4C_TERM_SS) != 0, (terms & Q4C_TERM_SO) != 0,
+                      (terms & Q4C_TERM_SO) != 0, (terms & Q4C_TERM_SO) != 0};
+  if (q == 0 && threadIdx.x < 16)
+    for (int p = 0; p < 5; ++p) cf[p * Lf + L + threadIdx.x] = 0.0;
+  const int64_t po = d.pair_off[q];
+  const int na = d.pair_na[q], nb = d.pair_nb[q];
+  const bool diag = d.pair_a[q] == d.pair_b[q];
+  for (int t = threadIdx.x; t < na * nb; t += blockDim.x) {
+    const int i = t / nb, j = t - i * nb;
+#pragma unroll
+    for (int p = 0; p < 5; ++p) {
+      double c = coef[p * L + po + t];
+      if (diag) {
+        if (i < j)
+          c += mirror_sign(p) * coef[p * L + po + (int64_t)j * nb + i];
+        else if (i > j)
+          c = 0.0;
+      }
+      cf[p * Lf + po + t] = on[p] ? (p > 0 ? c * d.cprime : c) : 0.0;
+    }
   }
 }
 
@@ -1932,6 +1974,14 @@ int launch_density(const q4c_plan *p, const double *coef, uint32_t terms, int pr
     }
     if ((rc = check_launch("k_fill")) != Q4C_OK) return rc;
   }
+  if (p->n_pairs > 0) {
+    {
+      TimedLaunch tl_(p, Q4C_TIMER_OTHER, s);
+      hipLaunchKernelGGL(k_coef_fold, dim3((unsigned)p->n_pairs), dim3(256), 0, s, p->dp, coef, terms,
+                         p->d_coef_fold);
+    }
+    if ((rc = check_launch("k_coef_fold")) != Q4C_OK) return rc;
+  }
   const LaunchCfg cfg = p->cfg_density;
   const int32_t *order = cfg.order ? p->d_order : nullptr;
   unsigned *tick0 = p->d_tickets + p->passes.size() * kTicketsPerLaunch;
@@ -1965,18 +2015,18 @@ int launch_density(const q4c_plan *p, const double *coef, uint32_t terms, int pr
         TimedLaunch tl_(p, Q4C_TIMER_DENSITY_TILES, s);
         if (precision == Q4C_PREC_F32) {
           if (tickets)
-            hipLaunchKernelGGL((k_density_tiles<true, true>), dim3(grid), dim3(NTD), 0, s, p->dp, terms, p->d_work,
-                               order, ps.w0, nw, coef, panel, partial, tickets);
+            hipLaunchKernelGGL((k_density_tiles<true, true>), dim3(grid), dim3(NTD), 0, s, p->dp, p->d_work, order,
+                               ps.w0, nw, p->d_coef_fold, panel, partial, tickets);
           else
-            hipLaunchKernelGGL((k_density_tiles<true, false>), dim3(grid), dim3(NTD), 0, s, p->dp, terms, p->d_work,
-                               order, ps.w0, nw, coef, panel, partial, tickets);
+            hipLaunchKernelGGL((k_density_tiles<true, false>), dim3(grid), dim3(NTD), 0, s, p->dp, p->d_work, order,
+                               ps.w0, nw, p->d_coef_fold, panel, partial, tickets);
         } else {
           if (tickets)
-            hipLaunchKernelGGL((k_density_tiles<false, true>), dim3(grid), dim3(NTD), 0, s, p->dp, terms, p->d_work,
-                               order, ps.w0, nw, coef, panel, partial, tickets);
+            hipLaunchKernelGGL((k_density_tiles<false, true>), dim3(grid), dim3(NTD), 0, s, p->dp, p->d_work, order,
+                               ps.w0, nw, p->d_coef_fold, panel, partial, tickets);
           else
-            hipLaunchKernelGGL((k_density_tiles<false, false>), dim3(grid), dim3(NTD), 0, s, p->dp, terms, p->d_work,
-                               order, ps.w0, nw, coef, panel, partial, tickets);
+            hipLaunchKernelGGL((k_density_tiles<false, false>), dim3(grid), dim3(NTD), 0, s, p->dp, p->d_work, order,
+                               ps.w0, nw, p->d_coef_fold, panel, partial, tickets);
         }
       }
       if ((rc = check_launch("k_density_tiles")) != Q4C_OK) return rc;

@@ -644,12 +644,35 @@ int build_device(q4c_plan *p) {
     p->dp.sp_pair = spp;
     p->dp.batch_sp_off = spo;
   }
+  {
+    // packed slot data per batch function and store offsets per slot pair: the
+    // adjoint reads them in one round trip each instead of two
+    int64_t n_b = (int64_t)p->batch_fn_off.size() - 1;
+    std::vector<int64_t> linfo(std::max<size_t>(p->loc_slot.size(), 1), 0);
+    for (int64_t b = 0; b < n_b; ++b) {
+      if (p->batch_fn_off[b + 1] - p->batch_fn_off[b] >= (1 << 20))
+        return fail(Q4C_EUNSUPPORTED, "a batch has 2^20 or more relevant functions");
+      for (int32_t e = p->batch_fn_off[b]; e < p->batch_fn_off[b + 1]; ++e) {
+        const int64_t sl = p->loc_slot[e], so = p->batch_slot_off[b] + sl;
+        linfo[e] = sl | ((int64_t)p->slot_fnoff[so] << 20) | ((int64_t)p->slot_nfn[so] << 40);
+      }
+    }
+    std::vector<int64_t> sppo(std::max<size_t>(p->sp_pair.size(), 1), -1);
+    for (size_t t = 0; t < p->sp_pair.size(); ++t) sppo[t] = p->sp_pair[t] >= 0 ? p->pair_off[p->sp_pair[t]] : -1;
+    int64_t *li, *sp;
+    UP(linfo, li);
+    UP(sppo, sp);
+    d.loc_info = li;
+    d.sp_poff = sp;
+  }
 #undef UP
   rc = device_alloc(p, (size_t)p->max_scratch * sizeof(double), (void **)&p->d_staging);
   if (rc != Q4C_OK) return rc;
   rc = device_alloc(p, 64, (void **)&p->d_flag);
   if (rc != Q4C_OK) return rc;
   rc = device_alloc(p, (size_t)(p->n_active + 16) * sizeof(double), (void **)&p->d_om);
+  if (rc != Q4C_OK) return rc;
+  rc = device_alloc(p, (size_t)5 * (p->store_len + 16) * sizeof(double), (void **)&p->d_coef_fold);
   if (rc != Q4C_OK) return rc;
   {
     const size_t nt = 2 * std::max<size_t>(p->passes.size(), 1) * q4c::kTicketsPerLaunch;

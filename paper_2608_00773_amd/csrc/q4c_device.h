@@ -139,6 +139,22 @@ __device__ __forceinline__ SlotInfo slot_of(const DevPlan &d, int fbase, int sba
   return s;
 }
 
+// A value every lane holds alike, as a scalar (wave-uniform) one.
+__device__ __forceinline__ int64_t uniform_i64(int64_t v) {
+  const int lo = __builtin_amdgcn_readfirstlane((int)(v & 0xFFFFFFFF));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+__device__ __forceinline__ AdjPos adj_uniform(const AdjPos &a) {
+  int w[16];
+  __builtin_memcpy(w, &a, sizeof(w));
+#pragma unroll
+  for (int i = 0; i < 16; ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+  AdjPos r;
+  __builtin_memcpy(&r, w, sizeof(w));
+  return r;
+}
+
 // Slot, the slot's first local function and its function count of
 // batch-local function lf, from the packed table (one load).
 struct SlotFn {

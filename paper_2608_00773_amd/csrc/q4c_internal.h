@@ -75,6 +75,21 @@ struct LaunchCfg {
   int32_t persistent = 0;
 };
 
+// One adjoint position: a column half (32 columns from tj * 64 + 32 half) of
+// work item (batch, ti, tj) whose columns start inside the batch, with the
+// batch data its kernel needs (64 bytes, one load).
+struct AdjPos {
+  int32_t batch;
+  int16_t ti, tj;
+  int32_t half, f0;
+  int32_t n, g0, P, sbase;
+  int32_t ns, pad_;
+  int64_t panel_off;  // pass relative
+  int64_t spb;        // batch_sp_off of the batch
+  int64_t part;       // pass-relative offset of the half's P partials
+};
+static_assert(sizeof(AdjPos) == 64, "AdjPos is 64 bytes");
+
 struct Pass {
   int64_t b0, b1;        // batch range
   int64_t w0, w1;        // work range
@@ -83,6 +98,7 @@ struct Pass {
   int64_t staging_len;   // doubles
   int64_t partial_len;   // doubles (adjoint partials, stored after the staging)
   int64_t panel_len;     // doubles (operand panels, stored after the partials)
+  int64_t ap0, ap1;      // adjoint positions (d_adjpos, d_adjpos_cost)
 };
 
 // Scalar -> spinor transformation (Eq. 33): coefficients of one spinor type
@@ -188,6 +204,8 @@ struct q4c_plan {
   int32_t *d_untouched = nullptr;
   q4c::WorkItem *d_ptile = nullptr;
   double *d_om = nullptr;  // [n_active + 16] point weights w_g v_g of the current call
+  q4c::AdjPos *d_adjpos = nullptr;       // adjoint positions per pass, batch order
+  q4c::AdjPos *d_adjpos_cost = nullptr;  // the same, work items by decreasing cost
   double *d_coef_fold = nullptr;  // [5][store_len + 16] the adjoint's coefficients of the current call (k_coef_fold)
   double *d_ucoef = nullptr;         // ket-potential tables (q4c_plan_set_ket_potential)
   int64_t *d_shell_us_off = nullptr;

@@ -1321,27 +1321,6 @@ constexpr int AIMG = 4 * 8 * RSA;   // doubles per image: 4 components x 8 point
 // A column half has work iff its columns start inside the batch's n functions.
 __device__ __forceinline__ bool half_valid(const WorkItem &it, int h, int n) { return it.tj * T + 32 * h < n; }
 
-// partial[g] of half h (P doubles at 2 work_part_off[w] + h P) = sum over its
-// stored elements ij of the selected terms at point g:
-//   C^V phi_i phi_j + c' C^Ws grad phi_i . grad phi_j + c' sum_m C^m (grad phi_i x grad phi_j)_m
-// (Eq. 39 on the scalar basis).  Per wave, the 32 x 16 coefficient block
-// sits in registers as the MFMA's first operand (5 parts x 8 K steps of 4
-// rows), and per 16-point chunk four accumulators collect (C^T Y) grouped by
-// the column component Z they are multiplied with afterwards:
-//   u_phi = C^V phi,  u_x = C^Ws dx - C^z dy + C^y dz,
-//   u_y = C^z dx + C^Ws dy - C^x dz,  u_z = -C^y dx + C^x dy + C^Ws dz
-// (rows i, the K index: Y = the row functions' values at the chunk's points),
-// then one lane-local drain sum_j u . Z per chunk.  The row image arrives by
-// LDS DMA, double-buffered (the next chunk's loads in flight while this one
-// is multiplied, one barrier per chunk); each lane's 16 column values Z come
-// from the panel straight into registers, a chunk ahead.  Two workgroups fit
-// on a CU.
-// F32W (density_on_grid in FP32): the nine W-term products per K step run on
-// FP32 MFMA with the coefficients and row values rounded to FP32; each
-// chunk's FP32 sums over the wave's 32 rows (at most 96 products per column
-// and point) are drained into the FP64 point sum, so the FP32 error of a
-// point is at most gamma_98 (u = 2^-24) times the magnitudes of its W terms.
-// The V term stays FP64.
 // The row values of K steps KS and KS + 1 of one lane, four components
 // each: component q of step k at LDS byte address a + 64 RSA q + 64 k.  Read
 // in one asm block that also waits for them, by hand: the compiler cannot
@@ -1367,54 +1346,157 @@ __device__ __forceinline__ void read_rows2(uint32_t a, double (&y)[2][4]) {
       : "memory");
 }
 
+// Slot data and pair offsets of one adjoint position (column half of a work
+// item) in LDS: the tile's 64 rows and the half's 32 columns (slot -1:
+// beyond n), the store offset of the pair block of (row slot, column slot)
+// for the slots the half spans (-1: lower atom-block triangle or not a stored
+// pair) when they are at most ADJ_POFF pairs (atoms of 5 or more functions:
+// at most 14 x 8; otherwise each lane looks its pairs up in the plan), and
+// the slot ranges.
+constexpr int ADJ_POFF = 256;
+struct AdjTab {
+  int rslot[T], rfn[T], cslot[T / 2], cfn[T / 2], cnf[T / 2];
+  int64_t poff[ADJ_POFF];
+  int rs0, cs0, ncs, lds_table;
+};
+
+// Filling an AdjTab takes two dependent rounds of loads, each ended by a
+// barrier: the slot data (threads 0 .. 95, one packed load each), then the
+// pair offsets of the slot ranges (one load per thread).  Each round is
+// written as its loads (issue) and its LDS writes (put).
+struct AdjSlotLoad {
+  int64_t v;
+  bool row, ok;
+};
+__device__ __forceinline__ AdjSlotLoad adj_slot_issue(const DevPlan &d, const AdjPos &D) {
+  const int tid = threadIdx.x;
+  AdjSlotLoad s{0, tid < T, false};
+  if (tid < T + T / 2) {
+    const int lf = s.row ? D.ti * T + tid : D.tj * T + 32 * D.half + tid - T;
+    s.ok = lf < D.n;
+    if (s.ok) s.v = d.loc_info[D.f0 + lf];
+  }
+  return s;
+}
+__device__ __forceinline__ void adj_slot_put(const AdjSlotLoad &s, AdjTab &tb) {
+  const int tid = threadIdx.x;
+  if (tid >= T + T / 2) return;
+  const int slot = s.ok ? (int)(s.v & 0xFFFFF) : -1;
+  const int fnoff = (int)((s.v >> 20) & 0xFFFFF), nfn = (int)(s.v >> 40);
+  if (s.row) {
+    tb.rslot[tid] = slot;
+    tb.rfn[tid] = fnoff;
+  } else {
+    tb.cslot[tid - T] = slot;
+    tb.cfn[tid - T] = fnoff;
+    tb.cnf[tid - T] = nfn;
+  }
+}
+// store offset of the pair block of slots (si, sj) of a batch, -1 if none
+__device__ __forceinline__ int64_t adj_pair_offset(const DevPlan &d, const AdjPos &D, int si, int sj) {
+  if (si > sj) return -1;
+  return d.sp_poff[D.spb + (int64_t)si * D.ns - (int64_t)si * (si - 1) / 2 + (sj - si)];
+}
+struct AdjPairLoad {
+  int64_t v;
+  int t;
+};
+// after the slot data are visible
+__device__ __forceinline__ AdjPairLoad adj_pair_issue(const DevPlan &d, const AdjPos &D, const AdjTab &tb) {
+  const int r0 = D.ti * T, c0 = D.tj * T + 32 * D.half;
+  const int rs0 = tb.rslot[0], cs0 = tb.cslot[0];
+  const int rs1 = tb.rslot[min(T, D.n - r0) - 1], cs1 = tb.cslot[min(T / 2, D.n - c0) - 1];
+  const int nrs = rs1 - rs0 + 1, ncs = cs1 - cs0 + 1;
+  AdjPairLoad a{-1, -1};
+  const int t = threadIdx.x;
+  if (nrs * ncs <= ADJ_POFF && t < nrs * ncs) {
+    a.t = t;
+    a.v = adj_pair_offset(d, D, rs0 + t / ncs, cs0 + t % ncs);
+  }
+  return a;
+}
+__device__ __forceinline__ void adj_pair_put(const AdjPos &D, const AdjPairLoad &a, AdjTab &tb) {
+  if (a.t >= 0) tb.poff[a.t] = a.v;
+  if (threadIdx.x == 0) {
+    const int r0 = D.ti * T, c0 = D.tj * T + 32 * D.half;
+    const int rs0 = tb.rslot[0], cs0 = tb.cslot[0];
+    const int rs1 = tb.rslot[min(T, D.n - r0) - 1], cs1 = tb.cslot[min(T / 2, D.n - c0) - 1];
+    const int nrs = rs1 - rs0 + 1, ncs = cs1 - cs0 + 1;
+    tb.rs0 = rs0;
+    tb.cs0 = cs0;
+    tb.ncs = ncs;
+    tb.lds_table = nrs * ncs <= ADJ_POFF;
+  }
+}
+
+// partial[g] of a position (P doubles at its pass-relative part offset) = sum
+// over its stored elements ij of the selected terms at point g:
+//   C^V phi_i phi_j + c' C^Ws grad phi_i . grad phi_j + c' sum_m C^m (grad phi_i x grad phi_j)_m
+// (Eq. 39 on the scalar basis).  A position is one column half of a work
+// item (the tile's 64 rows, 32 columns), four waves of 32 rows and 16 columns
+// each.  Per wave, the 32 x 16 coefficient block sits in registers as the
+// MFMA's second operand (5 parts x 8 K steps of 4 rows), and per 16-point
+// chunk four accumulators collect (Y^T C) grouped by the column component Z
+// they are multiplied with afterwards:
+//   u_phi = C^V phi,  u_x = C^Ws dx - C^z dy + C^y dz,
+//   u_y = C^z dx + C^Ws dy - C^x dz,  u_z = -C^y dx + C^x dy + C^Ws dz
+// (rows i, the K index: Y = the row functions' values at the chunk's points),
+// then one drain sum_j u . Z per chunk.  The row image arrives by LDS DMA,
+// double-buffered (the next chunk's loads in flight while this one is
+// multiplied, one barrier per chunk); each lane's 16 column values Z come from
+// the panel straight into registers, a chunk ahead.  Two workgroups fit on a
+// CU.  A persistent workgroup draws its next position's ticket when it starts
+// a position and turns it into a position after the last chunk.
+// F32W (density_on_grid in FP32): the nine W-term products per K step run on
+// FP32 MFMA with the coefficients and row values rounded to FP32; each
+// chunk's FP32 sums over the wave's 32 rows (at most 96 products per column
+// and point) are drained into the FP64 point sum, so the FP32 error of a
+// point is at most gamma_98 (u = 2^-24) times the magnitudes of its W terms.
+// The V term stays FP64.
 template <bool F32W, bool PERSIST>
-__global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, const WorkItem *work, const int32_t *order,
-                                                          int64_t w0, int64_t nw, const double *cf,
-                                                          const double *panel, double *partial, unsigned *tickets) {
+__global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, const AdjPos *apos, int64_t npos, int global_queue,
+                                                          const double *cf, const double *panel, double *partial,
+                                                          unsigned *tickets) {
   constexpr int NC = 5;  // coefficient parts
   __shared__ double img[2][AIMG];        // row images, alternating chunks
   __shared__ double s_red[2][4][16];     // per-wave point sums, alternating chunks
   __shared__ int64_t s_pos, s_next[2];
-  // slot data of the tile's 64 rows and the half's 32 columns (slot -1: beyond n)
-  __shared__ int s_rslot[T], s_rfn[T], s_cslot[T / 2], s_cfn[T / 2], s_cnf[T / 2];
-  // store offset of the pair block of (row slot, column slot) for the slots
-  // the half spans (-1: lower atom-block triangle or not a stored pair), when
-  // they are at most POFF_LDS pairs (atoms of 5 or more functions: at most
-  // 14 x 8); otherwise each lane looks its pairs up in the plan
-  constexpr int POFF_LDS = 256;
-  __shared__ int64_t s_poff[POFF_LDS];
-  const int64_t npos = 2 * nw;
-  int64_t pos = PERSIST ? next_item(tickets, npos, order != nullptr, &s_pos)
-                        : (order ? (int64_t)blockIdx.x : xcd_map(blockIdx.x, npos));
-  int par = 0;
-  while (!PERSIST || pos < npos) {
-  // the next item's ticket, drawn now and first needed after this item
-  unsigned tk = 0;
-  if (PERSIST && threadIdx.x == 0) tk = draw_ticket(tickets, order != nullptr);
-  const int half = (int)(pos & 1);
-  const int64_t wi = w0 + (order ? order[w0 + (pos >> 1)] : (pos >> 1));
-  const WorkItem it = work[wi];
-  const int b = it.batch;
-  const int f0 = d.batch_fn_off[b], n = d.batch_fn_off[b + 1] - f0;
-  if (half_valid(it, half, n)) {  // workgroup-uniform
-  const int g0 = d.batch_pt_off[b], P = d.batch_pt_off[b + 1] - g0;
-  const int sbase = d.batch_slot_off[b];
-  const int r0 = it.ti * T, c0 = it.tj * T + 32 * half;
-  const int Pp = (int)pad16(P), np = (int)pad16(n);
-  const double *pb = panel + d.panel_off[b];
-  const int64_t plane = (int64_t)Pp * np;
+  __shared__ AdjTab tb;                  // the position's slot and pair tables
+  const bool gq = global_queue != 0;
+  int64_t pos = PERSIST ? next_item(tickets, npos, gq, &s_pos) : (gq ? (int64_t)blockIdx.x : xcd_map(blockIdx.x, npos));
+  if (pos >= npos) return;  // workgroup-uniform
+  AdjPos D = adj_uniform(apos[pos]);
   const int tid = threadIdx.x;
   // wave index as a scalar: conditions derived from it stay uniform
   const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int js = wave & 1, ih = wave >> 1;  // column block, row half
   const int l16 = lane & 15, lk = lane >> 4;
+  // column values of a chunk.  FP64 (TR): the MFMA takes the row values as
+  // its first operand (lane l16 supplying point 4 (l16 % 4) + l16 / 4) and
+  // the coefficients as its second, so result register r of lane (l16, lk)
+  // is point 4 lk + r at column colb + l16: each lane's four points of a
+  // component are one 32-byte quad of the panel, two 16-byte loads.  F32W:
+  // coefficients first, register r is column lk + 4 r (FP64 MFMA) or
+  // 4 lk + r (FP32 MFMA) at point l16.
+  constexpr bool TR = !F32W;
+  const int ptA = TR ? 4 * (l16 & 3) + (l16 >> 2) : l16;  // the point this lane supplies to the row operand
+  int par = 0;
+  for (;;) {
+  // the next position's ticket, drawn now and first needed after the position
+  unsigned tk = 0;
+  if (PERSIST && tid == 0) tk = draw_ticket(tickets, gq);
+  const int n = D.n, P = D.P;
+  const int r0 = D.ti * T, c0 = D.tj * T + 32 * D.half;
+  const int Pp = (int)pad16(P), np = (int)pad16(n);
+  const double *pb = panel + D.panel_off;
+  const int64_t plane = (int64_t)Pp * np;
   const int colb = c0 + 16 * js;
   const int lj = colb + l16;
   // row origin of this wave's two 16-row blocks.  Column half 0 of a diagonal
   // tile has 3 active blocks, (0,0), (0,1) and (1,1) in 16-blocks: block (1,1)
   // moves from wave (ih 0, js 1) to the otherwise idle wave (ih 1, js 1), so
   // no wave of that half carries two.
-  const bool dg0 = it.ti == it.tj && half == 0;
+  const bool dg0 = D.ti == D.tj && D.half == 0;
   const int iloc = (dg0 && ih == 1 && js == 1) ? 16 : 32 * ih;
   bool act[2], upper[2];
 #pragma unroll
@@ -1424,9 +1506,6 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, const WorkI
     upper[h] = rb < colb;
   }
   const bool any = act[0] || act[1];
-  // The item's loads go out in as few round trips as their dependences allow:
-  // the first chunk's row image and column values together with the slot
-  // data, then the pair offsets, then the coefficients.
   // The row image of a chunk comes by buffer loads straight into LDS: image
   // row r = (component r / 8, point pair r % 8) holds 16 bytes per function;
   // the lane offset is fixed, the chunk and image row go into the scalar offset.
@@ -1441,16 +1520,6 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, const WorkI
       if (okr) __builtin_amdgcn_raw_ptr_buffer_load_lds(prs, (lds_void *)(dst + r * RSA), 16, lane * 32u, so, 0, 0);
     }
   };
-  dma_rows(0, img[0]);
-  // column values of a chunk.  FP64 (TR): the MFMA takes the row values as
-  // its first operand (lane l16 supplying point 4 (l16 % 4) + l16 / 4) and
-  // the coefficients as its second, so result register r of lane (l16, lk)
-  // is point 4 lk + r at column colb + l16: each lane's four points of a
-  // component are one 32-byte quad of the panel, two 16-byte loads.  F32W:
-  // coefficients first, register r is column lk + 4 r (FP64 MFMA) or
-  // 4 lk + r (FP32 MFMA) at point l16.
-  constexpr bool TR = !F32W;
-  const int ptA = TR ? 4 * (l16 & 3) + (l16 >> 2) : l16;  // the point this lane supplies to the row operand
   double zn[4][4];
   auto load_z = [&](int k) {
 #pragma unroll
@@ -1476,39 +1545,17 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, const WorkI
       }
     }
   };
+  // the first chunk's loads go out before anything else of the position
+  dma_rows(0, img[0]);
   load_z(0);
-  if (tid < T + T / 2) {
-    const bool row = tid < T;
-    const int lf = row ? r0 + tid : c0 + tid - T;
-    SlotFn si{-1, 0, 0};
-    if (lf < n) si = slot_fn(d, f0, lf);
-    if (row) {
-      s_rslot[tid] = si.slot;
-      s_rfn[tid] = si.fnoff;
-    } else {
-      s_cslot[tid - T] = si.slot;
-      s_cfn[tid - T] = si.fnoff;
-      s_cnf[tid - T] = si.nfn;
-    }
+  {
+    const AdjSlotLoad sl = adj_slot_issue(d, D);
+    adj_slot_put(sl, tb);
+    __syncthreads();  // slot data visible
+    const AdjPairLoad pl = adj_pair_issue(d, D, tb);
+    adj_pair_put(D, pl, tb);
+    __syncthreads();  // pair offsets visible
   }
-  __syncthreads();  // slot tables visible
-  // slot ranges of the tile's rows and the half's columns (slots ascend with
-  // the functions; rows and columns beyond n carry slot -1)
-  const int rs0 = s_rslot[0], cs0 = s_cslot[0];
-  const int rs1 = s_rslot[min(T, n - r0) - 1], cs1 = s_cslot[min(T / 2, n - c0) - 1];
-  const int nrs = rs1 - rs0 + 1, ncs = cs1 - cs0 + 1;
-  const int ns = d.batch_slot_off[b + 1] - sbase;
-  const int64_t spb = d.batch_sp_off[b];
-  // store offset of the pair block of slots (si, sj), -1 if none
-  auto pair_offset = [&](int si, int sj) -> int64_t {
-    if (si > sj) return -1;
-    // upper-triangle index of (si, sj)
-    return d.sp_poff[spb + (int64_t)si * ns - (int64_t)si * (si - 1) / 2 + (sj - si)];
-  };
-  const bool lds_table = nrs * ncs <= POFF_LDS;  // workgroup-uniform
-  if (lds_table)
-    for (int t = tid; t < nrs * ncs; t += NTD) s_poff[t] = pair_offset(rs0 + t / ncs, cs0 + t % ncs);
-  __syncthreads();  // pair offsets visible
   // coefficient slice: rows i = r0 + iloc + 4 ks + lk (ks = 0..7), column lj:
   // element (li, lj) of the folded coefficients (k_coef_fold) in the pair
   // block of its two atoms (upper atom-block triangle only); lanes without a
@@ -1517,15 +1564,17 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, const WorkI
   {
     const int64_t Lf = d.store_len + 16;
     const int cl = 16 * js + l16;
-    const int cslot = s_cslot[cl], cfn = s_cfn[cl], cnf = s_cnf[cl];
+    const int cslot = tb.cslot[cl], cfn = tb.cfn[cl], cnf = tb.cnf[cl];
+    const int rs0 = tb.rs0, cs0 = tb.cs0, ncs = tb.ncs;
+    const bool lds_table = tb.lds_table != 0;
 #pragma unroll
     for (int ks = 0; ks < 8; ++ks) {
       const int rl = iloc + 4 * ks + lk;
       const int li = r0 + rl;
-      const int rslot = s_rslot[rl], rfn = s_rfn[rl];
+      const int rslot = tb.rslot[rl], rfn = tb.rfn[rl];
       int64_t po = -1;
       if (act[ks >> 2] && rslot >= 0 && cslot >= 0)
-        po = lds_table ? s_poff[(rslot - rs0) * ncs + (cslot - cs0)] : pair_offset(rslot, cslot);
+        po = lds_table ? tb.poff[(rslot - rs0) * ncs + (cslot - cs0)] : adj_pair_offset(d, D, rslot, cslot);
       const int64_t ea = po >= 0 ? po + (int64_t)(li - rfn) * cnf + (lj - cfn) : d.store_len;
 #pragma unroll
       for (int q = 0; q < NC; ++q) creg[q][ks] = cf[q * Lf + ea];
@@ -1539,7 +1588,8 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, const WorkI
 #pragma unroll
       for (int q = 0; q < 4; ++q) cw[q][ks] = (float)creg[q + 1][ks];
   }
-  double *out = partial + 2 * d.work_part_off[wi] + half * P;
+  double *out = partial + D.part;
+
 
   for (int k0 = 0; k0 < Pp; k0 += 16) {
     const int bi = (k0 >> 4) & 1;
@@ -1664,14 +1714,15 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, const WorkI
     if (tid < 16 && k0 + tid < P)
       out[k0 + tid] = (s_red[bi][0][tid] + s_red[bi][1][tid]) + (s_red[bi][2][tid] + s_red[bi][3][tid]);
   }
-  }  // half_valid
-  if (!PERSIST) break;
-  // two slots in turn: a workgroup's thread 0 may write the next slot before
-  // every thread has read this one
-  if (threadIdx.x == 0) s_next[par] = ticket_pos(tickets, npos, order != nullptr, tk);
+  if (!PERSIST) return;
+  // two slots in turn: thread 0 may write the next slot before every thread
+  // has read this one
+  if (tid == 0) s_next[par] = ticket_pos(tickets, npos, gq, tk);
   __syncthreads();
-  pos = s_next[par];
+  pos = uniform_i64(s_next[par]);
   par ^= 1;
+  if (pos >= npos) return;
+  D = adj_uniform(apos[pos]);
   }
 }
 
@@ -1995,11 +2046,12 @@ int launch_density(const q4c_plan *p, const double *coef, uint32_t terms, int pr
   for (size_t ipr = p->passes.size(); ipr-- > 0;) {
     const size_t ip = ipr;
     const Pass &ps = p->passes[ip];
-    const int64_t nw = ps.w1 - ps.w0, nbt = ps.b1 - ps.b0;
+    const int64_t nw = ps.ap1 - ps.ap0, nbt = ps.b1 - ps.b0;
+    const AdjPos *apos = (cfg.order ? p->d_adjpos_cost : p->d_adjpos) + ps.ap0;
     const int64_t nt = (int64_t)ip == resident_pass ? 0 : ps.t1 - ps.t0;
     unsigned *tickets = cfg.persistent > 0 ? tick0 + ip * kTicketsPerLaunch : nullptr;
-    // two workgroup positions (column halves) per work item
-    const unsigned grid = (unsigned)(cfg.persistent > 0 ? std::min<int64_t>(cfg.persistent, 2 * nw) : 2 * nw);
+    // one workgroup position per column half of a work item
+    const unsigned grid = (unsigned)(cfg.persistent > 0 ? std::min<int64_t>(cfg.persistent, nw) : nw);
     double *partial = p->d_staging + ps.staging_len;
     double *panel = partial + ps.partial_len;
     if (nt > 0) {
@@ -2015,18 +2067,18 @@ int launch_density(const q4c_plan *p, const double *coef, uint32_t terms, int pr
         TimedLaunch tl_(p, Q4C_TIMER_DENSITY_TILES, s);
         if (precision == Q4C_PREC_F32) {
           if (tickets)
-            hipLaunchKernelGGL((k_density_tiles<true, true>), dim3(grid), dim3(NTD), 0, s, p->dp, p->d_work, order,
-                               ps.w0, nw, p->d_coef_fold, panel, partial, tickets);
+            hipLaunchKernelGGL((k_density_tiles<true, true>), dim3(grid), dim3(NTD), 0, s, p->dp, apos, nw,
+                               cfg.order, p->d_coef_fold, panel, partial, tickets);
           else
-            hipLaunchKernelGGL((k_density_tiles<true, false>), dim3(grid), dim3(NTD), 0, s, p->dp, p->d_work, order,
-                               ps.w0, nw, p->d_coef_fold, panel, partial, tickets);
+            hipLaunchKernelGGL((k_density_tiles<true, false>), dim3(grid), dim3(NTD), 0, s, p->dp, apos, nw,
+                               cfg.order, p->d_coef_fold, panel, partial, tickets);
         } else {
           if (tickets)
-            hipLaunchKernelGGL((k_density_tiles<false, true>), dim3(grid), dim3(NTD), 0, s, p->dp, p->d_work, order,
-                               ps.w0, nw, p->d_coef_fold, panel, partial, tickets);
+            hipLaunchKernelGGL((k_density_tiles<false, true>), dim3(grid), dim3(NTD), 0, s, p->dp, apos, nw,
+                               cfg.order, p->d_coef_fold, panel, partial, tickets);
           else
-            hipLaunchKernelGGL((k_density_tiles<false, false>), dim3(grid), dim3(NTD), 0, s, p->dp, p->d_work, order,
-                               ps.w0, nw, p->d_coef_fold, panel, partial, tickets);
+            hipLaunchKernelGGL((k_density_tiles<false, false>), dim3(grid), dim3(NTD), 0, s, p->dp, apos, nw,
+                               cfg.order, p->d_coef_fold, panel, partial, tickets);
         }
       }
       if ((rc = check_launch("k_density_tiles")) != Q4C_OK) return rc;

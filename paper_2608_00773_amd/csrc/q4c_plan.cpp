@@ -675,6 +675,44 @@ int build_device(q4c_plan *p) {
   rc = device_alloc(p, (size_t)5 * (p->store_len + 16) * sizeof(double), (void **)&p->d_coef_fold);
   if (rc != Q4C_OK) return rc;
   {
+    // adjoint positions: the column halves of the work items that start
+    // inside their batch, per pass, in batch order and in the work items'
+    // cost order
+    std::vector<q4c::AdjPos> ab, ac;
+    auto add = [&](std::vector<q4c::AdjPos> &v, int64_t w) {
+      const q4c::WorkItem &it = p->work[w];
+      const int b = it.batch;
+      const int f0 = p->batch_fn_off[b], n = p->batch_fn_off[b + 1] - f0;
+      const int g0 = p->batch_pt_off[b], P = p->batch_pt_off[b + 1] - g0;
+      for (int h = 0; h < 2; ++h) {
+        if (it.tj * q4c::kTile + 32 * h >= n) continue;
+        q4c::AdjPos a{};
+        a.batch = b;
+        a.ti = it.ti;
+        a.tj = it.tj;
+        a.half = h;
+        a.f0 = f0;
+        a.n = n;
+        a.g0 = g0;
+        a.P = P;
+        a.sbase = p->batch_slot_off[b];
+        a.ns = p->batch_slot_off[b + 1] - p->batch_slot_off[b];
+        a.panel_off = p->panel_off[b];
+        a.spb = p->batch_sp_off[b];
+        a.part = 2 * p->work_part_off[w] + (int64_t)h * P;
+        v.push_back(a);
+      }
+    };
+    for (q4c::Pass &ps : p->passes) {
+      ps.ap0 = (int64_t)ab.size();
+      for (int64_t w = ps.w0; w < ps.w1; ++w) add(ab, w);
+      for (int64_t i = 0; i < ps.w1 - ps.w0; ++i) add(ac, ps.w0 + p->work_order[ps.w0 + i]);
+      ps.ap1 = (int64_t)ab.size();
+    }
+    if ((rc = upload(p, ab, &p->d_adjpos)) != Q4C_OK) return rc;
+    if ((rc = upload(p, ac, &p->d_adjpos_cost)) != Q4C_OK) return rc;
+  }
+  {
     const size_t nt = 2 * std::max<size_t>(p->passes.size(), 1) * q4c::kTicketsPerLaunch;
     rc = device_alloc(p, nt * sizeof(unsigned), (void **)&p->d_tickets);
     if (rc != Q4C_OK) return rc;

@@ -268,6 +268,18 @@ __device__ __forceinline__ int d_row_f32(int lk, int r) { return 4 * lk + r; }
 constexpr int DROW = 2 * T;  // doubles per LDS row
 typedef __attribute__((address_space(3))) void lds_void;
 
+// Workgroup barrier after this wave's LDS operations have completed and at
+// most VM of its vector-memory operations remain outstanding (s_waitcnt
+// vmcnt(VM) lgkmcnt(0)).  The LDS DMA loads count in vmcnt.  __syncthreads
+// would also fence global memory; the memory clobber keeps the compiler from
+// moving memory accesses across the barrier.
+template <int VM>
+__device__ __forceinline__ void barrier_vm() {
+  static_assert(VM >= 0 && VM < 64, "vmcnt field");
+  __builtin_amdgcn_s_waitcnt((VM & 15) | ((VM >> 4) << 14) | (0x7 << 4));
+  asm volatile("s_barrier" ::: "memory");
+}
+
 // LDS byte address of a __shared__ array element
 __device__ __forceinline__ uint32_t lds_addr(const double *p) {
   return (uint32_t)(uintptr_t)(const lds_void *)(const void *)p;

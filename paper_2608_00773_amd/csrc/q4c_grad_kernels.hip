@@ -32,17 +32,6 @@ constexpr int GT = 64;    // points and functions per output tile
 constexpr int GK = 16;    // functions per K chunk
 constexpr int GS = 1024;  // doubles per slice image (64 x 16)
 
-// Workgroup barrier after this wave's LDS operations have completed and at
-// most VM of its vector-memory operations remain outstanding (s_waitcnt
-// vmcnt(VM) lgkmcnt(0)).  The LDS DMA loads count in vmcnt.  __syncthreads
-// would also fence global memory; the memory clobber keeps the compiler from
-// moving memory accesses across the barrier.
-template <int VM>
-__device__ __forceinline__ void barrier_vm() {
-  static_assert(VM >= 0 && VM < 64, "vmcnt field");
-  __builtin_amdgcn_s_waitcnt((VM & 15) | ((VM >> 4) << 14) | (0x7 << 4));
-  asm volatile("s_barrier" ::: "memory");
-}
 
 // packed slot data of a batch function: slot, the slot's first function and
 // its function count

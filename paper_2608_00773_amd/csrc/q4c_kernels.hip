@@ -1444,7 +1444,7 @@ __device__ __forceinline__ void adj_pair_put(const AdjPos &D, const AdjPairLoad 
 // then one drain sum_j u . Z per chunk.  The row image arrives by LDS DMA,
 // double-buffered (the next chunk's loads in flight while this one is
 // multiplied, one barrier per chunk); each lane's 16 column values Z come from
-// the panel straight into registers, a chunk ahead.  Two workgroups fit on a
+// the panel straight into registers, two chunks ahead.  Two workgroups fit on a
 // CU.  A persistent workgroup draws its next position's ticket when it starts
 // a position and turns it into a position after the last chunk.
 // F32W (density_on_grid in FP32): the nine W-term products per K step run on
@@ -1511,43 +1511,52 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, const AdjPo
   // the lane offset is fixed, the chunk and image row go into the scalar offset.
   const __amdgpu_buffer_rsrc_t prs =
       __builtin_amdgcn_make_buffer_rsrc((void *)pb, (short)0, (int)(32 * plane), 0x00020000);
-  const bool okr = r0 + lane < np;
   auto dma_rows = [&](int ks0, double *dst) {
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const int r = wave + 4 * k, q = r >> 3, u = r & 7;
       const uint32_t so = (uint32_t)((q * plane + ((int64_t)(ks0 + (u >> 1)) * np + r0) * 4 + 2 * (u & 1)) * 8);
-      if (okr) __builtin_amdgcn_raw_ptr_buffer_load_lds(prs, (lds_void *)(dst + r * RSA), 16, lane * 32u, so, 0, 0);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(prs, (lds_void *)(dst + r * RSA), 16, lane * 32u, so, 0, 0);
     }
   };
-  double zn[4][4];
-  auto load_z = [&](int k) {
+  // column values of two chunks in flight: zb[c & 1] holds chunk c's, loaded
+  // at the end of chunk c - 2.  Each wave issues the same ZLOADS buffer loads
+  // for every chunk, unconditionally (past the last chunk the last one is read
+  // again; columns of a wave without active blocks may lie beyond the panel,
+  // where a buffer load returns zero), so that at each chunk's barrier "this
+  // chunk's image and column values have landed" is "at most ZLOADS loads
+  // outstanding": only the next chunk's column loads, issued after the image
+  // DMA, remain in flight.
+  double zb[2][4][4];
+  auto load_z = [&](int k, auto zc) {
+    constexpr int ZB = decltype(zc)::value;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
+      const uint32_t qo = (uint32_t)(q * plane * 8);
       if (TR) {
-        if (any) {
-          const dbl2 *zq = reinterpret_cast<const dbl2 *>(pb + q * plane + ((int64_t)((k >> 2) + lk) * np + colb + l16) * 4);
-          const dbl2 z01 = zq[0], z23 = zq[1];
-          zn[q][0] = z01[0];
-          zn[q][1] = z01[1];
-          zn[q][2] = z23[0];
-          zn[q][3] = z23[1];
-        } else {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) zn[q][r] = 0.0;
-        }
+        const uint32_t zo = (uint32_t)(((int64_t)((k >> 2) + lk) * np + colb + l16) * 32);
+        const dbl2 z01 = __builtin_bit_cast(dbl2, __builtin_amdgcn_raw_buffer_load_b128(prs, zo, qo, 0));
+        const dbl2 z23 = __builtin_bit_cast(dbl2, __builtin_amdgcn_raw_buffer_load_b128(prs, zo + 16, qo, 0));
+        zb[ZB][q][0] = z01[0];
+        zb[ZB][q][1] = z01[1];
+        zb[ZB][q][2] = z23[0];
+        zb[ZB][q][3] = z23[1];
       } else {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int jr = (F32W && q > 0) ? d_row_f32(lk, r) : d_row_f64(lk, r);
-          zn[q][r] = any ? pb[q * plane + ((int64_t)((k + l16) >> 2) * np + colb + jr) * 4 + (l16 & 3)] : 0.0;
+          const uint32_t zo = (uint32_t)((((int64_t)((k + l16) >> 2) * np + colb + jr) * 4 + (l16 & 3)) * 8);
+          zb[ZB][q][r] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(prs, zo, qo, 0));
         }
       }
     }
   };
+  // column loads per chunk: one buffer load instruction each
+  constexpr int ZLOADS = TR ? 8 : 16;
   // the first chunk's loads go out before anything else of the position
   dma_rows(0, img[0]);
-  load_z(0);
+  load_z(0, std::integral_constant<int, 0>{});
+  load_z(min(16, Pp - 16), std::integral_constant<int, 1>{});
   {
     const AdjSlotLoad sl = adj_slot_issue(d, D);
     adj_slot_put(sl, tb);
@@ -1589,24 +1598,28 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, const AdjPo
       for (int q = 0; q < 4; ++q) cw[q][ks] = (float)creg[q + 1][ks];
   }
   double *out = partial + D.part;
+  // the coefficients (and the first chunks' loads) have landed before the
+  // chunks begin, so that no wait for them falls inside a chunk
+  __builtin_amdgcn_s_waitcnt(0);
 
 
-  for (int k0 = 0; k0 < Pp; k0 += 16) {
-    const int bi = (k0 >> 4) & 1;
-    __builtin_amdgcn_s_waitcnt(0);  // this thread's loads of this chunk (image, Z) have landed
-    __syncthreads();                // ... everyone's; the previous chunk is consumed, its sums visible
+  auto chunk = [&](int k0, auto zc) {
+    constexpr int bi = decltype(zc)::value;  // chunk parity: image buffer and column-value set
+    // this wave's image and column loads of this chunk have landed (only the
+    // next chunk's column loads may be outstanding) ... and everyone's; the
+    // previous chunk is consumed, its sums visible
+    barrier_vm<ZLOADS>();
     if (k0 > 0 && tid < 16 && k0 - 16 + tid < P)
       out[k0 - 16 + tid] = (s_red[bi ^ 1][0][tid] + s_red[bi ^ 1][1][tid]) +
                            (s_red[bi ^ 1][2][tid] + s_red[bi ^ 1][3][tid]);
-    double zt[4][4];
+    dma_rows(min(k0 + 16, Pp - 16) >> 2, img[bi ^ 1]);
+    // this chunk's column values landed before the barrier above; the empty
+    // asm makes them its own result, so the compiler, which cannot follow the
+    // loads across the barrier, places no wait for them inside the chunk
 #pragma unroll
     for (int q = 0; q < 4; ++q)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) zt[q][r] = zn[q][r];
-    if (k0 + 16 < Pp) {
-      dma_rows((k0 + 16) >> 2, img[bi ^ 1]);
-      load_z(k0 + 16);
-    }
+      asm volatile("" : "+v"(zb[bi][q][0]), "+v"(zb[bi][q][1]), "+v"(zb[bi][q][2]), "+v"(zb[bi][q][3]));
+    const double (&zt)[4][4] = zb[bi];
     double x = 0.0;
     if (any && F32W) {
       // this lane's row values of K step 0, component 0 (point ptA, row iloc + lk)
@@ -1707,7 +1720,15 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, const AdjPo
     } else {
       if (lane < 16) s_red[bi][wave][l16] = x;
     }
+    load_z(min(k0 + 32, Pp - 16), zc);
+  };
+  // pairs of chunks (even, odd) as straight-line code, then an odd last one
+  int k0 = 0;
+  for (; k0 + 32 <= Pp; k0 += 32) {
+    chunk(k0, std::integral_constant<int, 0>{});
+    chunk(k0 + 16, std::integral_constant<int, 1>{});
   }
+  if (k0 < Pp) chunk(k0, std::integral_constant<int, 0>{});
   __syncthreads();  // the last chunk's per-wave sums
   {
     const int k0 = Pp - 16, bi = (k0 >> 4) & 1;

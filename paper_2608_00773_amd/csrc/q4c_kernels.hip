@@ -1509,32 +1509,37 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, const AdjPo
   // The row image of a chunk comes by buffer loads straight into LDS: image
   // row r = (component r / 8, point pair r % 8) holds 16 bytes per function;
   // the lane offset is fixed, the chunk and image row go into the scalar offset.
+  // Lanes whose function lies at or beyond np, and column loads of a wave
+  // without active blocks, take an offset past the end of the buffer: the
+  // load is still issued (so every wave issues the same loads per chunk) but
+  // reads nothing and returns zero.
   const __amdgpu_buffer_rsrc_t prs =
       __builtin_amdgcn_make_buffer_rsrc((void *)pb, (short)0, (int)(32 * plane), 0x00020000);
+  constexpr uint32_t OOB = 0x80000000u;
+  const uint32_t vrow = r0 + lane < np ? lane * 32u : OOB;
   auto dma_rows = [&](int ks0, double *dst) {
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const int r = wave + 4 * k, q = r >> 3, u = r & 7;
       const uint32_t so = (uint32_t)((q * plane + ((int64_t)(ks0 + (u >> 1)) * np + r0) * 4 + 2 * (u & 1)) * 8);
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(prs, (lds_void *)(dst + r * RSA), 16, lane * 32u, so, 0, 0);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(prs, (lds_void *)(dst + r * RSA), 16, vrow, so, 0, 0);
     }
   };
   // column values of two chunks in flight: zb[c & 1] holds chunk c's, loaded
   // at the end of chunk c - 2.  Each wave issues the same ZLOADS buffer loads
   // for every chunk, unconditionally (past the last chunk the last one is read
-  // again; columns of a wave without active blocks may lie beyond the panel,
-  // where a buffer load returns zero), so that at each chunk's barrier "this
-  // chunk's image and column values have landed" is "at most ZLOADS loads
-  // outstanding": only the next chunk's column loads, issued after the image
-  // DMA, remain in flight.
+  // again), so that at each chunk's barrier "this chunk's image and column
+  // values have landed" is "at most ZLOADS loads outstanding": only the next
+  // chunk's column loads, issued after the image DMA, remain in flight.
   double zb[2][4][4];
+  const uint32_t zoob = any ? 0u : OOB;  // or-ed into the offsets: no branch around the loads
   auto load_z = [&](int k, auto zc) {
     constexpr int ZB = decltype(zc)::value;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const uint32_t qo = (uint32_t)(q * plane * 8);
       if (TR) {
-        const uint32_t zo = (uint32_t)(((int64_t)((k >> 2) + lk) * np + colb + l16) * 32);
+        const uint32_t zo = (uint32_t)(((int64_t)((k >> 2) + lk) * np + colb + l16) * 32) | zoob;
         const dbl2 z01 = __builtin_bit_cast(dbl2, __builtin_amdgcn_raw_buffer_load_b128(prs, zo, qo, 0));
         const dbl2 z23 = __builtin_bit_cast(dbl2, __builtin_amdgcn_raw_buffer_load_b128(prs, zo + 16, qo, 0));
         zb[ZB][q][0] = z01[0];
@@ -1545,7 +1550,7 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, const AdjPo
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int jr = (F32W && q > 0) ? d_row_f32(lk, r) : d_row_f64(lk, r);
-          const uint32_t zo = (uint32_t)((((int64_t)((k + l16) >> 2) * np + colb + jr) * 4 + (l16 & 3)) * 8);
+          const uint32_t zo = (uint32_t)((((int64_t)((k + l16) >> 2) * np + colb + jr) * 4 + (l16 & 3)) * 8) | zoob;
           zb[ZB][q][r] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(prs, zo, qo, 0));
         }
       }

@@ -45,6 +45,7 @@ struct DevPlan {
   const int32_t *loc_fn;            // [fn_entries] global function
   const int32_t *loc_slot;          // [fn_entries] slot (relevant atom) within the batch
   const int64_t *loc_info;          // [fn_entries] slot | slot's first local function << 20 | its function count << 40
+  const int64_t *loc_rowoff;        // [fn_entries] staging offset of the function's slot block row (pass relative)
   const int32_t *batch_slot_off;    // [n_batches + 1]
   const int32_t *slot_fnoff;        // [n_slots] local function offset of the slot
   const int32_t *slot_nfn;          // [n_slots]

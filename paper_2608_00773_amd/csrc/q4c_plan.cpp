@@ -645,24 +645,30 @@ int build_device(q4c_plan *p) {
     p->dp.batch_sp_off = spo;
   }
   {
-    // packed slot data per batch function and store offsets per slot pair: the
-    // adjoint reads them in one round trip each instead of two
+    // packed slot data and the slot's staging row per batch function, and
+    // store offsets per slot pair: the contraction epilogue and the adjoint
+    // read them in one round trip each instead of two
     int64_t n_b = (int64_t)p->batch_fn_off.size() - 1;
     std::vector<int64_t> linfo(std::max<size_t>(p->loc_slot.size(), 1), 0);
+    std::vector<int64_t> lrow(std::max<size_t>(p->loc_slot.size(), 1), 0);
     for (int64_t b = 0; b < n_b; ++b) {
       if (p->batch_fn_off[b + 1] - p->batch_fn_off[b] >= (1 << 20))
         return fail(Q4C_EUNSUPPORTED, "a batch has 2^20 or more relevant functions");
       for (int32_t e = p->batch_fn_off[b]; e < p->batch_fn_off[b + 1]; ++e) {
         const int64_t sl = p->loc_slot[e], so = p->batch_slot_off[b] + sl;
         linfo[e] = sl | ((int64_t)p->slot_fnoff[so] << 20) | ((int64_t)p->slot_nfn[so] << 40);
+        lrow[e] = p->slot_row_off[so];
       }
     }
     std::vector<int64_t> sppo(std::max<size_t>(p->sp_pair.size(), 1), -1);
     for (size_t t = 0; t < p->sp_pair.size(); ++t) sppo[t] = p->sp_pair[t] >= 0 ? p->pair_off[p->sp_pair[t]] : -1;
     int64_t *li, *sp;
+    int64_t *lr;
     UP(linfo, li);
+    UP(lrow, lr);
     UP(sppo, sp);
     d.loc_info = li;
+    d.loc_rowoff = lr;
     d.sp_poff = sp;
   }
 #undef UP

@@ -28,6 +28,10 @@ __global__ __launch_bounds__(NT, 2) void k_contract_hs(DevPlan d, const WorkItem
   constexpr int BUFD = NQ * RPQ * DROW;  // doubles per chunk image
   __shared__ double sa[2 * BUFD], sb[2 * BUFD];
   __shared__ int64_t s_pos;
+  // slot data of the tile's 64 rows and 64 columns for the epilogue, loaded
+  // when the work item starts (slot -1: beyond n)
+  __shared__ int s_fslot[2 * T], s_ffn[2 * T], s_fnf[2 * T];
+  __shared__ int64_t s_frow[2 * T];
   int64_t pos = PERSIST ? next_item(tickets, nw, order != nullptr, &s_pos)
                         : (order ? (int64_t)blockIdx.x : xcd_map(blockIdx.x, nw));
   while (!PERSIST || pos < nw) {
@@ -36,7 +40,6 @@ __global__ __launch_bounds__(NT, 2) void k_contract_hs(DevPlan d, const WorkItem
   const int b = it.batch;
   const int g0 = d.batch_pt_off[b], P = d.batch_pt_off[b + 1] - g0;
   const int f0 = d.batch_fn_off[b], n = d.batch_fn_off[b + 1] - f0;
-  const int sbase = d.batch_slot_off[b];
   const int r0 = it.ti * T, c0 = it.tj * T;
   const int Pp = (int)pad16(P), np = (int)pad16(n);
   const double *pb = panel + d.panel_off[b];
@@ -67,6 +70,18 @@ __global__ __launch_bounds__(NT, 2) void k_contract_hs(DevPlan d, const WorkItem
   load_w(0);
   dma_chunk<NT, CH, T, DROW, NQ>(pb, plane, np, r0, 0, sa);
   dma_chunk<NT, CH, T, DROW, NQ>(pb, plane, np, c0, 0, sb);
+  if (tid < 2 * T) {  // visible from the first chunk's barrier on
+    const int lf = tid < T ? r0 + tid : c0 + tid - T;
+    int64_t v = 0, ro = 0;
+    if (lf < n) {
+      v = d.loc_info[f0 + lf];
+      ro = d.loc_rowoff[f0 + lf];
+    }
+    s_fslot[tid] = lf < n ? (int)(v & 0xFFFFF) : -1;
+    s_ffn[tid] = (int)((v >> 20) & 0xFFFFF);
+    s_fnf[tid] = (int)(v >> 40);
+    s_frow[tid] = ro;
+  }
   for (int k0 = 0; k0 < Pp; k0 += CH) {
     const int bo = ((k0 / CH) & 1) * BUFD;
     double omv[CH / 4], wv[CH / 4];
@@ -113,14 +128,16 @@ __global__ __launch_bounds__(NT, 2) void k_contract_hs(DevPlan d, const WorkItem
     const int cb = c0 + bcol[sl];
     const int lj = cb + li16;
     if (lj >= n) continue;
-    const SlotInfo sj = slot_of(d, f0, sbase, lj);
+    const int cj = T + bcol[sl] + li16;
+    const SlotInfo sj{s_fslot[cj], s_ffn[cj], s_fnf[cj], s_frow[cj]};
     const int rb = r0 + brow[sl];
     const bool upper = rb < cb;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int li = rb + d_row_f64(lk, r);
       if (li < n) {
-        const SlotInfo si = slot_of(d, f0, sbase, li);
+        const int ri = li - r0;
+        const SlotInfo si{s_fslot[ri], s_ffn[ri], s_fnf[ri], s_frow[ri]};
         double vals[2];
         vals[0] = acc[sl][0][r] + acc[sl][2][r];
         vals[1] = acc[sl][1][r];

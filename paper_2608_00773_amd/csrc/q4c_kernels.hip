@@ -652,13 +652,16 @@ __global__ __launch_bounds__(NT, 1) void k_contract_valu(DevPlan d, const WorkIt
   constexpr int BUFD = NQ * RPQ * DROW;  // doubles per chunk image
   __shared__ double sa[2 * BUFD], sb[2 * BUFD];
   __shared__ double s_om[2][CH];
+  // slot data of the tile's 64 rows and 64 columns for the epilogue, loaded
+  // when the work item starts (slot -1: beyond n)
+  __shared__ int s_fslot[2 * T], s_ffn[2 * T], s_fnf[2 * T];
+  __shared__ int64_t s_frow[2 * T];
   const int64_t pos = order ? (int64_t)blockIdx.x : xcd_map(blockIdx.x, nw);
   const int64_t wi = w0 + (order ? order[w0 + pos] : pos);
   const WorkItem it = work[wi];
   const int b = it.batch;
   const int g0 = d.batch_pt_off[b], P = d.batch_pt_off[b + 1] - g0;
   const int f0 = d.batch_fn_off[b], n = d.batch_fn_off[b + 1] - f0;
-  const int sbase = d.batch_slot_off[b];
   const int r0 = it.ti * T, c0 = it.tj * T;
   const int Pp = (int)pad16(P), np = (int)pad16(n);
   const double *pb = panel + d.panel_off[b];
@@ -677,6 +680,18 @@ __global__ __launch_bounds__(NT, 1) void k_contract_valu(DevPlan d, const WorkIt
   double omr = tid < CH ? om[g0 + tid] : 0.0;  // om holds 16 zeros past its end
   dma_chunk<NT, CH, T, DROW, NQ>(pb, plane, np, r0, 0, sa);
   dma_chunk<NT, CH, T, DROW, NQ>(pb, plane, np, c0, 0, sb);
+  if (tid < 2 * T) {  // visible from the first chunk's barrier on
+    const int lf = tid < T ? r0 + tid : c0 + tid - T;
+    int64_t v = 0, ro = 0;
+    if (lf < n) {
+      v = d.loc_info[f0 + lf];
+      ro = d.loc_rowoff[f0 + lf];
+    }
+    s_fslot[tid] = lf < n ? (int)(v & 0xFFFFF) : -1;
+    s_ffn[tid] = (int)((v >> 20) & 0xFFFFF);
+    s_fnf[tid] = (int)(v >> 40);
+    s_frow[tid] = ro;
+  }
   __builtin_amdgcn_s_waitcnt(0);
   if (tid < CH) s_om[0][tid] = omr;
   for (int k0 = 0; k0 < Pp; k0 += CH) {
@@ -728,12 +743,14 @@ __global__ __launch_bounds__(NT, 1) void k_contract_valu(DevPlan d, const WorkIt
   for (int c = 0; c < 4; ++c) {
     const int lj = c0 + pc + c;
     if (lj >= n) continue;
-    const SlotInfo sj = slot_of(d, f0, sbase, lj);
+    const int cj = lj - c0 + T;
+    const SlotInfo sj{s_fslot[cj], s_ffn[cj], s_fnf[cj], s_frow[cj]};
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
       const int li = r0 + pr + a;
       if (li >= n) continue;
-      const SlotInfo si = slot_of(d, f0, sbase, li);
+      const int ri = li - r0;
+      const SlotInfo si{s_fslot[ri], s_ffn[ri], s_fnf[ri], s_frow[ri]};
       double vals[5];
       vals[0] = acc[0][a][c];
 #pragma unroll
@@ -774,6 +791,10 @@ __global__ __launch_bounds__(NT, 2) void k_contract_w(DevPlan d, const WorkItem 
   constexpr int FLUSH = 16;                    // points per FP32 partial sum
   __shared__ __attribute__((aligned(16))) float fa[2 * BUFF], fb[2 * BUFF];
   __shared__ int64_t s_pos;
+  // slot data of the tile's 64 rows and 64 columns for the epilogue, loaded
+  // when the work item starts (slot -1: beyond n)
+  __shared__ int s_fslot[2 * T], s_ffn[2 * T], s_fnf[2 * T];
+  __shared__ int64_t s_frow[2 * T];
   int64_t pos = PERSIST ? next_item(tickets, nw, order != nullptr, &s_pos)
                         : (order ? (int64_t)blockIdx.x : xcd_map(blockIdx.x, nw));
   while (!PERSIST || pos < nw) {
@@ -782,7 +803,6 @@ __global__ __launch_bounds__(NT, 2) void k_contract_w(DevPlan d, const WorkItem 
   const int b = it.batch;
   const int g0 = d.batch_pt_off[b], P = d.batch_pt_off[b + 1] - g0;
   const int f0 = d.batch_fn_off[b], n = d.batch_fn_off[b + 1] - f0;
-  const int sbase = d.batch_slot_off[b];
   const int r0 = it.ti * T, c0 = it.tj * T;
   const int Pp = (int)pad16(P), np = (int)pad16(n);
   const int64_t fplane = (int64_t)Pp * np;
@@ -831,6 +851,18 @@ __global__ __launch_bounds__(NT, 2) void k_contract_w(DevPlan d, const WorkItem 
   load_om(0);
   dma(r0, 0, fa);
   dma(c0, 0, fb);
+  if (tid < 2 * T) {  // visible from the first chunk's barrier on
+    const int lf = tid < T ? r0 + tid : c0 + tid - T;
+    int64_t v = 0, ro = 0;
+    if (lf < n) {
+      v = d.loc_info[f0 + lf];
+      ro = d.loc_rowoff[f0 + lf];
+    }
+    s_fslot[tid] = lf < n ? (int)(v & 0xFFFFF) : -1;
+    s_ffn[tid] = (int)((v >> 20) & 0xFFFFF);
+    s_fnf[tid] = (int)(v >> 40);
+    s_frow[tid] = ro;
+  }
   for (int k0 = 0; k0 < Pp; k0 += CH) {
     const int bo = ((k0 / CH) & 1) * BUFF;
     __builtin_amdgcn_s_waitcnt(0);  // this thread's loads of this chunk have landed
@@ -908,7 +940,8 @@ __global__ __launch_bounds__(NT, 2) void k_contract_w(DevPlan d, const WorkItem 
     const int cbk = c0 + bcol[sl];
     const int lj = cbk + li16;
     if (lj >= n) continue;
-    const SlotInfo sj = slot_of(d, f0, sbase, lj);
+    const int cj = T + bcol[sl] + li16;
+    const SlotInfo sj{s_fslot[cj], s_ffn[cj], s_fnf[cj], s_frow[cj]};
     const int rb = r0 + brow[sl];
     const bool upper = rb < cbk;
 #pragma unroll
@@ -916,7 +949,8 @@ __global__ __launch_bounds__(NT, 2) void k_contract_w(DevPlan d, const WorkItem 
       // FP32 MFMA rows 4 lk + r
       const int lf = rb + d_row_f32(lk, r);
       if (lf < n) {
-        const SlotInfo sf = slot_of(d, f0, sbase, lf);
+        const int ri = lf - r0;
+        const SlotInfo sf{s_fslot[ri], s_ffn[ri], s_fnf[ri], s_frow[ri]};
         double w[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) w[q] = cp * accw[sl][q][r];
@@ -981,7 +1015,6 @@ __global__ __launch_bounds__(NT, 2) void k_contract_b3(DevPlan d, const WorkItem
   const int f0 = d.batch_fn_off[b], n = d.batch_fn_off[b + 1] - f0;
   if (it.tj * T + 32 * half < n) {  // workgroup-uniform: the half has columns
   const int g0 = d.batch_pt_off[b], P = d.batch_pt_off[b + 1] - g0;
-  const int sbase = d.batch_slot_off[b];
   const int r0 = it.ti * T, c0 = it.tj * T + 32 * half;
   const int Pp = (int)pad16(P), np = (int)pad16(n);
   const double *pb = panel + d.panel_off[b];
@@ -1043,7 +1076,10 @@ __global__ __launch_bounds__(NT, 2) void k_contract_b3(DevPlan d, const WorkItem
     const bool row = tid < T;
     const int lf = row ? r0 + tid : c0 + tid - T;
     SlotInfo si{-1, 0, 0, 0};
-    if (lf < n) si = slot_of(d, f0, sbase, lf);
+    if (lf < n) {
+      const int64_t v = d.loc_info[f0 + lf];
+      si = SlotInfo{(int)(v & 0xFFFFF), (int)((v >> 20) & 0xFFFFF), (int)(v >> 40), row ? d.loc_rowoff[f0 + lf] : 0};
+    }
     if (row) {
       s_rslot[tid] = si.slot;
       s_rfn[tid] = si.fnoff;

@@ -32,30 +32,32 @@ PEAK_HBM = 8.0e12     # MI355X HBM3E, bytes/s
 PREC = {"f64": 0, "split": 1, "f32": 2, "bf16x3": 3, "f64valu": 4}
 
 # HBM bytes per launch of the path's kernels on the default cluster workload,
-# from two rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE), each scaled by what
-# the same counter reads for an elementwise copy of 1 GiB (read x1.9999, write
-# x1.0000).  Keyed by kernel, the SHA-256 of the kernel sources the counters
-# were taken on (q4c_kernels.hip and q4c_device.h), the precision, the workload
-# and the work order of the launch (batch order keeps a batch's tiles on one
-# L2, the cost-sorted queue does not; None for kernels without one): any
-# change to those sources makes the figure stale, and it is then reported as
-# null.
-_KS = "bd9dddd226195d1d9550bf8c6b11d901e28ce9017226a5ba2b957c3c8ebe9095"
+# from two rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE) of the timed
+# launches (not the autotuner's trials), each scaled by what the same counter
+# reads for an elementwise copy of 1 GiB (read x1.9999, write x1.0000).  Keyed
+# by kernel, the SHA-256 of the kernel sources the counters were taken on
+# (q4c_kernels.hip and q4c_device.h), the precision, the workload and the
+# launch shape: work order (batch order keeps a batch's tiles on one L2, the
+# cost-sorted queue does not) and whether the launch is persistent (None for
+# kernels without either).  Any change to those sources, or another launch
+# shape, makes the figure unknown, and it is then reported as null.
+_KS = "8ad28ef8f51a8d6976f870ab130bd643f62b269a08694b11904208262460a5b1"
 TRAFFIC = {
-    ("k_contract", _KS, "f64", "cluster-120", 0): 30.66e9 + 8.34e9,
-    ("k_density_tiles", _KS, "f64", "cluster-120", 0): 41.08e9 + 0.21e9,
+    ("k_contract", _KS, "f64", "cluster-120", (0, True)): 23.29e9 + 7.64e9,
+    ("k_density_tiles", _KS, "f64", "cluster-120", (0, True)): 40.00e9 + 0.21e9,
     ("k_panel", _KS, "f64", "cluster-120", None): 0.17e9 + 11.49e9,
     ("k_reduce", _KS, "f64", "cluster-120", None): 7.28e9 + 0.03e9,
-    ("k_contract", _KS, "bf16x3", "cluster-120", 0): 28.38e9 + 7.74e9,
+    ("k_contract", _KS, "bf16x3", "cluster-120", (0, False)): 9.42e9 + 7.04e9,
     ("k_panel", _KS, "bf16x3", "cluster-120", None): 0.15e9 + 9.34e9,
     ("k_reduce", _KS, "bf16x3", "cluster-120", None): 7.28e9 + 0.03e9,
 }
 
-# The same for k_contract_hs (q4c_integrate_HS) per component and work order,
+# The same for k_contract_hs (q4c_integrate_HS) per component and launch shape,
 # keyed by the SHA-256 of q4c_hs_kernels.hip and q4c_device.h.
+_HS = "cb0aff49a9a25371de0ac031f97c714b4eb5cac134fb2b2f87c77a566f1b5e53"
 HS_TRAFFIC = {
-    ("126fbdd2a75052cf312bb5537d84087bab3e7d99a8db89fcef23863de0ecc596", "large", 120, 0): 6.538e9 + 3.097e9,
-    ("126fbdd2a75052cf312bb5537d84087bab3e7d99a8db89fcef23863de0ecc596", "small", 120, 0): 6.884e9 + 7.300e9,
+    (_HS, "large", 120, (0, True)): 6.842e9 + 2.994e9,
+    (_HS, "small", 120, (0, True)): 7.154e9 + 7.042e9,
 }
 
 
@@ -232,7 +234,7 @@ def bench_hs(wl, timed, steps: int, cpu_frac: float, with_cpu: bool, components=
             "kernels_ms_per_call": {k: v_[0] / steps for k, v_ in tim.items() if v_[1]},
             "roofline": {"kernel": "k_contract_hs", "bound": "mfma", "achieved": achieved / 1e12,
                          "peak": PEAK_F64 / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_F64,
-                         "traffic": HS_TRAFFIC.get((hsha, name, int(wl.n_atoms), best[0])),
+                         "traffic": HS_TRAFFIC.get((hsha, name, int(wl.n_atoms), (best[0], best[1] > 0))),
                          "avg_launch_ms": t_c * 1e3, "launches_per_call": per_call},
         }
         log("H/S %s component: %d functions, %.3f ms per call, k_contract_hs %.1f%% of FP64 peak" %
@@ -573,11 +575,13 @@ def main():
     info = plan.info
     n_act = info["n_active"]
     ksha = source_sha("q4c_kernels.hip", "q4c_device.h")
-    c_order = plan.get_launch(q.KERNEL_CONTRACT)[0]
-    d_order = plan.get_launch(q.KERNEL_DENSITY)[0]
+    c_launch = plan.get_launch(q.KERNEL_CONTRACT)
+    d_launch = plan.get_launch(q.KERNEL_DENSITY)
+    c_shape = (c_launch[0], c_launch[1] > 0)  # work order, persistent
+    d_shape = (d_launch[0], d_launch[1] > 0)
     wkey = "%s-%d" % (a.workload, wl.n_atoms)
 
-    def kernel_roofline(name, timer, bound, work_per_step, peak, unit, order=None):
+    def kernel_roofline(name, timer, bound, work_per_step, peak, unit, shape=None):
         """achieved = algorithmic work of one launch / average launch time of
         the kernel (HIP events around each launch over the timed steps)."""
         n = max(tim[timer][1], 1)
@@ -586,15 +590,15 @@ def main():
         work = work_per_step / max(per_step, 1e-300)
         scale = 1e12 if unit == "TFLOP/s" else 1e9
         return {"kernel": name, "bound": bound, "achieved": work / t / scale, "peak": peak / scale, "unit": unit,
-                "frac": work / t / peak, "traffic": TRAFFIC.get((name, ksha, a.precision, wkey, order)),
+                "frac": work / t / peak, "traffic": TRAFFIC.get((name, ksha, a.precision, wkey, shape)),
                 "alg_per_launch": work, "avg_launch_ms": t * 1e3, "launches_per_step": per_step,
                 "ms_per_step": tim[timer][0] / a.steps}
 
     rl = [
         kernel_roofline("k_contract", "contract", "mfma", info["flops_alg"], contraction_peak(a.precision),
-                        "TFLOP/s", c_order),
+                        "TFLOP/s", c_shape),
         kernel_roofline("k_density_tiles", "density_tiles", "mfma", info["flops_alg"], PEAK_F64, "TFLOP/s",
-                        d_order),
+                        d_shape),
         # tabulation: 32 B (phi and its gradient, FP64) per (point, relevant function) per
         # tabulation of all passes; the adjoint tabulates only passes whose panels are not resident
         kernel_roofline("k_panel", "tabulate", "hbm",

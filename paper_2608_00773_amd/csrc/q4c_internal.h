@@ -167,6 +167,7 @@ struct q4c_plan {
 
   // ---- pairs
   int64_t n_pairs = 0, store_len = 0;
+  int64_t max_pair_block = 1;  // largest n_A n_B of a stored pair (the reduction's grid)
   std::vector<int32_t> pair_a, pair_b, pair_na, pair_nb;
   std::vector<int64_t> pair_off;
   std::vector<int64_t> atom_pair_start;  // [n_atoms + 1] pairs with first atom A

@@ -1252,8 +1252,11 @@ __global__ __launch_bounds__(NT, 2) void k_contract_b3(DevPlan d, const WorkItem
 // value (zero, or the stored value when a previous pass or ACCUMULATE left
 // one).  The sum is a single sequential chain in batch order, so results
 // repeat bit for bit and do not depend on how batches are split into passes.
-// Loads of four incidences are issued together.
-constexpr int NTR = 1024;  // threads of a k_reduce workgroup
+// Workgroup (x, y) takes elements y NTR .. y NTR + NTR - 1 of entry x, one per
+// thread (gridDim.y covers the largest entry), so the heavy atom pairs are
+// spread over many workgroups instead of setting the kernel's tail; the
+// loads of eight incidences are issued together.
+constexpr int NTR = 256;  // threads of a k_reduce workgroup
 __global__ __launch_bounds__(NTR) void k_reduce(DevPlan d, int64_t r0, const int32_t *red_pair,
                                                 const uint8_t *red_first, const int64_t *red_inc_off,
                                                 const int64_t *inc_src, const double *staging, double *store,
@@ -1262,58 +1265,32 @@ __global__ __launch_bounds__(NTR) void k_reduce(DevPlan d, int64_t r0, const int
   const int64_t r = r0 + blockIdx.x;
   const int p = red_pair[r];
   const int blk = d.pair_na[p] * d.pair_nb[p];
+  const int m = nq * blk;  // parts 0 .. nq-1 of the staged blocks (the first nq of five)
+  if ((int)blockIdx.y * NTR >= m) return;  // workgroup-uniform: past this entry's elements
   const int64_t k0 = red_inc_off[r], k1 = red_inc_off[r + 1];
   const bool add = accumulate || !red_first[r];
   const int64_t po = d.pair_off[p];
-  const int m = nq * blk;  // parts 0 .. nq-1 of the staged blocks (the first nq of five)
-  // each thread owns elements e = tid, tid + NTR, ... (4 at a time in registers)
-  for (int e0 = 0; e0 < m; e0 += 4 * NTR) {
-    double sum[4];
+  const int e = blockIdx.y * NTR + threadIdx.x;
+  const int q = e / blk;
+  const bool own = e < m && ((part_mask >> q) & 1);
+  double sum = own && add ? store[q * d.store_len + po + (e - q * blk)] : 0.0;
+  for (int64_t kb = k0; kb < k1; kb += NTR) {
+    const int nk = (int)(k1 - kb < NTR ? k1 - kb : NTR);
+    __syncthreads();  // previous offsets consumed
+    if (threadIdx.x < nk) s_src[threadIdx.x] = inc_src[kb + threadIdx.x];
+    __syncthreads();
+    int k = 0;
+    for (; k + 8 <= nk; k += 8) {
+      double a[8];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int e = e0 + j * NTR + threadIdx.x;
-      sum[j] = 0.0;
-      if (e < m && add && ((part_mask >> (e / blk)) & 1)) {
-        const int q = e / blk;
-        sum[j] = store[q * d.store_len + po + (e - q * blk)];
-      }
+      for (int u = 0; u < 8; ++u) a[u] = e < m ? staging[s_src[k + u] + e] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) sum += a[u];
     }
-    for (int64_t kb = k0; kb < k1; kb += NTR) {
-      const int nk = (int)(k1 - kb < NTR ? k1 - kb : NTR);
-      __syncthreads();  // previous offsets consumed
-      if (threadIdx.x < nk) s_src[threadIdx.x] = inc_src[kb + threadIdx.x];
-      __syncthreads();
-      int k = 0;
-      for (; k + 8 <= nk; k += 8) {
-        double a[4][8];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int e = e0 + j * NTR + threadIdx.x;
-#pragma unroll
-          for (int u = 0; u < 8; ++u) a[j][u] = e < m ? staging[s_src[k + u] + e] : 0.0;
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-          for (int u = 0; u < 8; ++u) sum[j] += a[j][u];
-      }
-      for (; k < nk; ++k) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int e = e0 + j * NTR + threadIdx.x;
-          if (e < m) sum[j] += staging[s_src[k] + e];
-        }
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int e = e0 + j * NTR + threadIdx.x;
-      if (e < m && ((part_mask >> (e / blk)) & 1)) {
-        const int q = e / blk;
-        store[q * d.store_len + po + (e - q * blk)] = sum[j];
-      }
-    }
+    for (; k < nk; ++k)
+      if (e < m) sum += staging[s_src[k] + e];
   }
+  if (own) store[q * d.store_len + po + (e - q * blk)] = sum;
 }
 
 // Pairs no batch touches are zero unless accumulating (selected parts).
@@ -1416,73 +1393,50 @@ struct AdjTab {
   int rs0, cs0, ncs, lds_table;
 };
 
-// Filling an AdjTab takes two dependent rounds of loads, each ended by a
-// barrier: the slot data (threads 0 .. 95, one packed load each), then the
-// pair offsets of the slot ranges (one load per thread).  Each round is
-// written as its loads (issue) and its LDS writes (put).
-struct AdjSlotLoad {
-  int64_t v;
-  bool row, ok;
-};
-__device__ __forceinline__ AdjSlotLoad adj_slot_issue(const DevPlan &d, const AdjPos &D) {
-  const int tid = threadIdx.x;
-  AdjSlotLoad s{0, tid < T, false};
-  if (tid < T + T / 2) {
-    const int lf = s.row ? D.ti * T + tid : D.tj * T + 32 * D.half + tid - T;
-    s.ok = lf < D.n;
-    if (s.ok) s.v = d.loc_info[D.f0 + lf];
-  }
-  return s;
-}
-__device__ __forceinline__ void adj_slot_put(const AdjSlotLoad &s, AdjTab &tb) {
-  const int tid = threadIdx.x;
-  if (tid >= T + T / 2) return;
-  const int slot = s.ok ? (int)(s.v & 0xFFFFF) : -1;
-  const int fnoff = (int)((s.v >> 20) & 0xFFFFF), nfn = (int)(s.v >> 40);
-  if (s.row) {
-    tb.rslot[tid] = slot;
-    tb.rfn[tid] = fnoff;
-  } else {
-    tb.cslot[tid - T] = slot;
-    tb.cfn[tid - T] = fnoff;
-    tb.cnf[tid - T] = nfn;
-  }
-}
 // store offset of the pair block of slots (si, sj) of a batch, -1 if none
 __device__ __forceinline__ int64_t adj_pair_offset(const DevPlan &d, const AdjPos &D, int si, int sj) {
   if (si > sj) return -1;
   return d.sp_poff[D.spb + (int64_t)si * D.ns - (int64_t)si * (si - 1) / 2 + (sj - si)];
 }
-struct AdjPairLoad {
-  int64_t v;
-  int t;
-};
-// after the slot data are visible
-__device__ __forceinline__ AdjPairLoad adj_pair_issue(const DevPlan &d, const AdjPos &D, const AdjTab &tb) {
+
+// Fills a position's AdjTab (every thread of the workgroup calls it): two
+// dependent rounds of loads, each ended by a barrier: the slot data (threads
+// 0 .. 95, one packed load each), then the pair offsets of the slot ranges
+// (one load per thread).
+__device__ __forceinline__ void adj_fill(const DevPlan &d, const AdjPos &D, AdjTab &tb) {
+  const int tid = threadIdx.x;
   const int r0 = D.ti * T, c0 = D.tj * T + 32 * D.half;
+  if (tid < T + T / 2) {
+    const bool row = tid < T;
+    const int lf = row ? r0 + tid : c0 + tid - T;
+    int64_t v = 0;
+    if (lf < D.n) v = d.loc_info[D.f0 + lf];
+    const int slot = lf < D.n ? (int)(v & 0xFFFFF) : -1;
+    const int fnoff = (int)((v >> 20) & 0xFFFFF), nfn = (int)(v >> 40);
+    if (row) {
+      tb.rslot[tid] = slot;
+      tb.rfn[tid] = fnoff;
+    } else {
+      tb.cslot[tid - T] = slot;
+      tb.cfn[tid - T] = fnoff;
+      tb.cnf[tid - T] = nfn;
+    }
+  }
+  __syncthreads();  // slot data visible
+  // slot ranges of the tile's rows and the half's columns (slots ascend with
+  // the functions; rows and columns beyond n carry slot -1)
   const int rs0 = tb.rslot[0], cs0 = tb.cslot[0];
   const int rs1 = tb.rslot[min(T, D.n - r0) - 1], cs1 = tb.cslot[min(T / 2, D.n - c0) - 1];
   const int nrs = rs1 - rs0 + 1, ncs = cs1 - cs0 + 1;
-  AdjPairLoad a{-1, -1};
-  const int t = threadIdx.x;
-  if (nrs * ncs <= ADJ_POFF && t < nrs * ncs) {
-    a.t = t;
-    a.v = adj_pair_offset(d, D, rs0 + t / ncs, cs0 + t % ncs);
-  }
-  return a;
-}
-__device__ __forceinline__ void adj_pair_put(const AdjPos &D, const AdjPairLoad &a, AdjTab &tb) {
-  if (a.t >= 0) tb.poff[a.t] = a.v;
-  if (threadIdx.x == 0) {
-    const int r0 = D.ti * T, c0 = D.tj * T + 32 * D.half;
-    const int rs0 = tb.rslot[0], cs0 = tb.cslot[0];
-    const int rs1 = tb.rslot[min(T, D.n - r0) - 1], cs1 = tb.cslot[min(T / 2, D.n - c0) - 1];
-    const int nrs = rs1 - rs0 + 1, ncs = cs1 - cs0 + 1;
+  const bool in_lds = nrs * ncs <= ADJ_POFF;  // workgroup-uniform
+  if (in_lds && tid < nrs * ncs) tb.poff[tid] = adj_pair_offset(d, D, rs0 + tid / ncs, cs0 + tid % ncs);
+  if (tid == 0) {
     tb.rs0 = rs0;
     tb.cs0 = cs0;
     tb.ncs = ncs;
-    tb.lds_table = nrs * ncs <= ADJ_POFF;
+    tb.lds_table = in_lds;
   }
+  __syncthreads();  // pair offsets visible
 }
 
 // partial[g] of a position (P doubles at its pass-relative part offset) = sum
@@ -1618,14 +1572,7 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, const AdjPo
   dma_rows(0, img[0]);
   load_z(0, std::integral_constant<int, 0>{});
   load_z(min(16, Pp - 16), std::integral_constant<int, 1>{});
-  {
-    const AdjSlotLoad sl = adj_slot_issue(d, D);
-    adj_slot_put(sl, tb);
-    __syncthreads();  // slot data visible
-    const AdjPairLoad pl = adj_pair_issue(d, D, tb);
-    adj_pair_put(D, pl, tb);
-    __syncthreads();  // pair offsets visible
-  }
+  adj_fill(d, D, tb);
   // coefficient slice: rows i = r0 + iloc + 4 ks + lk (ks = 0..7), column lj:
   // element (li, lj) of the folded coefficients (k_coef_fold) in the pair
   // block of its two atoms (upper atom-block triangle only); lanes without a
@@ -2014,8 +1961,9 @@ int launch_integrate(const q4c_plan *p, const double *v, int precision, uint32_t
     if (nr > 0) {
       {
         TimedLaunch tl_(p, Q4C_TIMER_REDUCE, s);
-        hipLaunchKernelGGL(k_reduce, dim3((unsigned)nr), dim3(NTR), 0, s, p->dp, ps.r0, p->d_red_pair, p->d_red_first,
-                           p->d_red_inc_off, p->d_inc_src, p->d_staging, store, accumulate, 5, pmask);
+        hipLaunchKernelGGL(k_reduce, dim3((unsigned)nr, (unsigned)((5 * p->max_pair_block + NTR - 1) / NTR)), dim3(NTR),
+                           0, s, p->dp, ps.r0, p->d_red_pair, p->d_red_first, p->d_red_inc_off, p->d_inc_src,
+                           p->d_staging, store, accumulate, 5, pmask);
       }
       if ((rc = check_launch("k_reduce")) != Q4C_OK) return rc;
     }
@@ -2079,8 +2027,9 @@ int launch_integrate_hs(const q4c_plan *p, const double *v, uint32_t flags, doub
     if (nr > 0) {
       {
         TimedLaunch tl_(p, Q4C_TIMER_REDUCE, s);
-        hipLaunchKernelGGL(k_reduce, dim3((unsigned)nr), dim3(NTR), 0, s, p->dp, ps.r0, p->d_red_pair, p->d_red_first,
-                           p->d_red_inc_off, p->d_inc_src, p->d_staging, hs, accumulate, 2, 3u);
+        hipLaunchKernelGGL(k_reduce, dim3((unsigned)nr, (unsigned)((2 * p->max_pair_block + NTR - 1) / NTR)), dim3(NTR),
+                           0, s, p->dp, ps.r0, p->d_red_pair, p->d_red_first, p->d_red_inc_off, p->d_inc_src,
+                           p->d_staging, hs, accumulate, 2, 3u);
       }
       if ((rc = check_launch("k_reduce")) != Q4C_OK) return rc;
     }

@@ -384,6 +384,7 @@ int build_host(q4c_plan *p, const q4c_basis *b, const q4c_grid *g, const std::ve
     p->pair_na[q] = p->atom_fn_off[a + 1] - p->atom_fn_off[a];
     p->pair_nb[q] = p->atom_fn_off[c + 1] - p->atom_fn_off[c];
     p->pair_off[q + 1] = p->pair_off[q] + (int64_t)p->pair_na[q] * p->pair_nb[q];
+    p->max_pair_block = std::max<int64_t>(p->max_pair_block, (int64_t)p->pair_na[q] * p->pair_nb[q]);
   }
   p->store_len = p->pair_off[p->n_pairs];
   p->sys_pair_off.assign(nsys + 1, 0);

@@ -32,24 +32,34 @@ PEAK_HBM = 8.0e12     # MI355X HBM3E, bytes/s
 PREC = {"f64": 0, "split": 1, "f32": 2, "bf16x3": 3, "f64valu": 4}
 
 # HBM bytes per launch of the path's kernels on the default cluster workload,
-# from two rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE) of the timed
-# launches (not the autotuner's trials), each scaled by what the same counter
-# reads for an elementwise copy of 1 GiB (read x1.9999, write x1.0000).  Keyed
-# by kernel, the SHA-256 of the kernel sources the counters were taken on
+# from two rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE), each scaled by what
+# the same counter reads for an elementwise copy of 1 GiB (read x2, write x1):
+# the timed launches, and per launch shape the autotuner's trial launches of
+# the same runs (persistent sizes 512 and 1024 read the same bytes).  Keyed by
+# kernel, the SHA-256 of the kernel sources the counters were taken on
 # (q4c_kernels.hip and q4c_device.h), the precision, the workload and the
-# launch shape: work order (batch order keeps a batch's tiles on one L2, the
-# cost-sorted queue does not) and whether the launch is persistent (None for
-# kernels without either).  Any change to those sources, or another launch
-# shape, makes the figure unknown, and it is then reported as null.
-_KS = "8ad28ef8f51a8d6976f870ab130bd643f62b269a08694b11904208262460a5b1"
+# launch shape: work order (0: batch order, which keeps a batch's tiles on one
+# L2; 1: the cost-sorted queue, which does not) and whether the launch is
+# persistent (None for kernels without either).  Any change to those sources
+# makes the figure unknown, and it is then reported as null.
+_KS = "c2e14a824f288f321a362b0e85db26392bea6c045aba82b821db27621919ac84"
 TRAFFIC = {
-    ("k_contract", _KS, "f64", "cluster-120", (0, True)): 23.29e9 + 7.64e9,
-    ("k_density_tiles", _KS, "f64", "cluster-120", (0, True)): 40.00e9 + 0.21e9,
-    ("k_panel", _KS, "f64", "cluster-120", None): 0.17e9 + 11.49e9,
-    ("k_reduce", _KS, "f64", "cluster-120", None): 7.28e9 + 0.03e9,
+    ("k_contract", _KS, "f64", "cluster-120", (0, False)): 21.64e9 + 7.44e9,
+    ("k_contract", _KS, "f64", "cluster-120", (0, True)): 23.31e9 + 7.64e9,
+    ("k_contract", _KS, "f64", "cluster-120", (1, False)): 42.80e9 + 7.70e9,
+    ("k_contract", _KS, "f64", "cluster-120", (1, True)): 39.87e9 + 7.96e9,
+    ("k_density_tiles", _KS, "f64", "cluster-120", (0, False)): 19.99e9 + 0.21e9,
+    ("k_density_tiles", _KS, "f64", "cluster-120", (0, True)): 40.31e9 + 0.21e9,
+    ("k_density_tiles", _KS, "f64", "cluster-120", (1, False)): 70.20e9 + 0.21e9,
+    ("k_density_tiles", _KS, "f64", "cluster-120", (1, True)): 69.92e9 + 0.21e9,
+    ("k_panel", _KS, "f64", "cluster-120", None): 0.17e9 + 11.48e9,
+    ("k_reduce", _KS, "f64", "cluster-120", None): 7.41e9 + 0.03e9,
     ("k_contract", _KS, "bf16x3", "cluster-120", (0, False)): 9.42e9 + 7.04e9,
+    ("k_contract", _KS, "bf16x3", "cluster-120", (0, True)): 9.79e9 + 7.68e9,
+    ("k_contract", _KS, "bf16x3", "cluster-120", (1, False)): 52.63e9 + 7.84e9,
+    ("k_contract", _KS, "bf16x3", "cluster-120", (1, True)): 47.21e9 + 7.79e9,
     ("k_panel", _KS, "bf16x3", "cluster-120", None): 0.15e9 + 9.34e9,
-    ("k_reduce", _KS, "bf16x3", "cluster-120", None): 7.28e9 + 0.03e9,
+    ("k_reduce", _KS, "bf16x3", "cluster-120", None): 7.41e9 + 0.03e9,
 }
 
 # The same for k_contract_hs (q4c_integrate_HS) per component and launch shape,

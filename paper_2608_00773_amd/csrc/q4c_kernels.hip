@@ -389,6 +389,7 @@ __global__ __launch_bounds__(256) void k_panel(DevPlan d, const WorkItem *tiles,
   constexpr int CP = 8;           // points per chunk: a small stage keeps 7 workgroups on a CU
   __shared__ TileMeta M;
   __shared__ double st[NQ * CP * PLD];
+  __shared__ double s_sw[CP];  // PK_BF16: sqrt|w v| at the chunk's points
   const WorkItem it = tiles[t0 + xcd_map(blockIdx.x, nt)];
   const int b = it.batch;
   const int g0 = d.batch_pt_off[b], P = d.batch_pt_off[b + 1] - g0;
@@ -402,6 +403,8 @@ __global__ __launch_bounds__(256) void k_panel(DevPlan d, const WorkItem *tiles,
   float *pf = reinterpret_cast<float *>(pb + (int64_t)Pp * np);  // FP32 planes (PK_F32, PK_SPLIT)
   const int64_t fplane = (int64_t)Pp * np;
   for (int g8 = 0; g8 < Pp; g8 += CP) {
+    if (KIND == PK_BF16 && threadIdx.x < CP)  // visible after the stage's barrier
+      s_sw[threadIdx.x] = g8 + (int)threadIdx.x < P ? sqrt(fabs(om[g0 + g8 + threadIdx.x])) : 0.0;
     for (int e = threadIdx.x; e < T * CP; e += 256) {
       const int k = e / CP, pt = e % CP;
       const int fl = M.order[k];
@@ -446,17 +449,14 @@ __global__ __launch_bounds__(256) void k_panel(DevPlan d, const WorkItem *tiles,
       // per part
       u32x4 *pbf = reinterpret_cast<u32x4 *>(pb + fplane);
       const int64_t noct = Pp >> 3;
-      double sw[CP];
-#pragma unroll
-      for (int e = 0; e < CP; ++e) sw[e] = g8 + e < P ? sqrt(fabs(om[g0 + g8 + e])) : 0.0;
       for (int t = threadIdx.x; t < 3 * T; t += 256) {
         const int il = t % T, q = t / T;
         if (il >= nrow) continue;
         u32x4 w[3];
 #pragma unroll
         for (int e = 0; e < CP; e += 2) {
-          const double xa = sw[e] * st[((q + 1) * CP + e) * PLD + il];
-          const double xb = sw[e + 1] * st[((q + 1) * CP + e + 1) * PLD + il];
+          const double xa = s_sw[e] * st[((q + 1) * CP + e) * PLD + il];
+          const double xb = s_sw[e + 1] * st[((q + 1) * CP + e + 1) * PLD + il];
           uint32_t w1, w2, w3;
           split3_bf16x2(xa, xb, w1, w2, w3);
           w[0][e >> 1] = w1;

@@ -350,9 +350,10 @@ __global__ void k_om(DevPlan d, const double *v, double *om) {
 // out as contiguous runs of the tile's functions.  Panel kinds:
 //   PK_F64:   phi, d/dx, d/dy, d/dz in FP64 (4 planes of Pp np doubles)
 //   PK_HS:    phi and psi = u phi / 2 in FP64 (2 planes)
-//   PK_F32:   phi in FP64 (1 plane), then d/dx, d/dy, d/dz as FP32 planes
-//             (Pp np floats each) after it
-//   PK_SPLIT: as PK_F32, then the three lo planes fl32(x - hi)
+//   PK_F32:   phi in FP64 (1 plane), then sqrt|w v| times d/dx, d/dy, d/dz
+//             (formed in FP64) as FP32 planes (Pp np floats each) after it
+//   PK_SPLIT: phi in FP64, then d/dx, d/dy, d/dz as FP32 hi planes fl32(x)
+//             and the three lo planes fl32(x - hi)
 //   PK_BF16:  phi in FP64 (1 plane), then the BF16 region: for component q
 //             and split part t of sqrt|w v| times the gradient (formed in
 //             FP64), plane 3 q + t of (Pp / 8) point octets x np functions x
@@ -403,7 +404,7 @@ __global__ __launch_bounds__(256) void k_panel(DevPlan d, const WorkItem *tiles,
   float *pf = reinterpret_cast<float *>(pb + (int64_t)Pp * np);  // FP32 planes (PK_F32, PK_SPLIT)
   const int64_t fplane = (int64_t)Pp * np;
   for (int g8 = 0; g8 < Pp; g8 += CP) {
-    if (KIND == PK_BF16 && threadIdx.x < CP)  // visible after the stage's barrier
+    if ((KIND == PK_BF16 || KIND == PK_F32) && threadIdx.x < CP)  // visible after the stage's barrier
       s_sw[threadIdx.x] = g8 + (int)threadIdx.x < P ? sqrt(fabs(om[g0 + g8 + threadIdx.x])) : 0.0;
     for (int e = threadIdx.x; e < T * CP; e += 256) {
       const int k = e / CP, pt = e % CP;
@@ -437,7 +438,7 @@ __global__ __launch_bounds__(256) void k_panel(DevPlan d, const WorkItem *tiles,
             pb[((int64_t)(q * (Pp >> 2) + (g8 >> 2) + p4) * np + r0 + il) * 4 + pp] = x;
           } else {
             const int64_t o = ((int64_t)((q - 1) * (Pp >> 2) + (g8 >> 2) + p4) * np + r0 + il) * 4 + pp;
-            const float hi = (float)x;
+            const float hi = KIND == PK_F32 ? (float)(s_sw[4 * p4 + pp] * x) : (float)x;
             pf[o] = hi;
             if (KIND == PK_SPLIT) pf[3 * fplane + o] = (float)(x - (double)hi);
           }
@@ -767,18 +768,21 @@ __global__ __launch_bounds__(NT, 1) void k_contract_valu(DevPlan d, const WorkIt
 // The four W parts on FP32 MFMA (precisions F32 and SPLIT_F32), from the FP32
 // gradient planes of a PK_F32 / PK_SPLIT panel; V runs beside it on FP64
 // (k_contract<MODE_V>).  Same work items, wave blocks and staging as
-// k_contract.  Per 16 points, every element's FP32 partial sum (of at most
-// 48 products: 16 points x 3) is converted to FP64 and added to an FP64
-// running sum, then restarted from zero, so FP32 rounding never accumulates
-// beyond one 16-point chunk: with unit roundoff u = 2^-24 each element's
-// error is at most gamma_52 = 52 u / (1 - 52 u) times the sum over all
-// points of the magnitudes of its terms (operands rounded to FP32 up to three
-// times, 48 products and additions), plus FP64 rounding and the loss of
-// relative precision of values below FP32's normal range (the far tails of
-// tight functions).  SPLIT: each operand x enters as hi = fl32(x) and
-// lo = fl32(x - hi), and every product as hi hi + hi lo + lo hi (three FP32
-// MFMAs): the operands' rounding drops to about 2^-48, and a 16-point partial
-// sum holds up to 144 products (gamma_150).
+// k_contract.  F32: both operands are sqrt|w v| times the gradient (formed in
+// FP64, rounded to FP32 once in the panel), the row operand with the sign of
+// w v.  Per 16 points, every element's FP32 partial sum (of at most 48
+// products: 16 points x 3) is converted to FP64 and added to an FP64 running
+// sum, then restarted from zero, so FP32 rounding never accumulates beyond
+// one 16-point chunk: with unit roundoff u = 2^-24 each element's error is at
+// most gamma_52 = 52 u / (1 - 52 u) times the sum over all points of the
+// magnitudes of its terms (two operands rounded to FP32, 48 products and
+// additions), plus FP64 rounding and the loss of relative precision of values
+// below FP32's normal range (the far tails of tight functions).  SPLIT: each
+// operand x enters as hi = fl32(x) and lo = fl32(x - hi) (the column operand
+// w v x formed in FP64 and split again), and every product as
+// hi hi + hi lo + lo hi (three FP32 MFMAs): the operands' rounding drops to
+// about 2^-48, and a 16-point partial sum holds up to 144 products
+// (gamma_150).
 template <bool SPLIT, bool PERSIST>
 __global__ __launch_bounds__(NT, 2) void k_contract_w(DevPlan d, const WorkItem *work, const int32_t *order,
                                                       int64_t w0, int64_t nw, const double *om,
@@ -844,11 +848,13 @@ __global__ __launch_bounds__(NT, 2) void k_contract_w(DevPlan d, const WorkItem 
             (lds_void *)(dst + r * ROWF), 16, 0, 0);
     }
   };
+  // w v at the points this lane's K index visits in the next chunk: points
+  // 4 ks + lk (SPLIT), or the four points of quad lk (otherwise)
   double omn[CH / 4];
   auto load_om = [&](int k) {
 #pragma unroll
     for (int ks = 0; ks < CH / 4; ++ks) {
-      const int pt = k + 4 * ks + lk;
+      const int pt = SPLIT ? k + 4 * ks + lk : k + 4 * lk + ks;
       omn[ks] = pt < P ? om[g0 + pt] : 0.0;
     }
   };
@@ -880,47 +886,78 @@ __global__ __launch_bounds__(NT, 2) void k_contract_w(DevPlan d, const WorkItem 
       dma(c0, (k0 + CH) >> 2, fb + BUFF - bo);
     }
     const float *ca = fa + bo, *cb = fb + bo;
+    if constexpr (!SPLIT) {
+      // The panel holds sqrt|w v| times the gradient, so each product is
+      // w v times two gradient components once the row operand takes the
+      // sign of w v.  MFMA m of the chunk sums over points 4 lk + m (K index
+      // lk): one 16-byte LDS read per operand gives a lane all four.
+      uint32_t sgn[4];
 #pragma unroll
-    for (int ks = 0; ks < CH / 4; ++ks) {
-      const double omk = omv[ks];
+      for (int m = 0; m < 4; ++m)
+        sgn[m] = (uint32_t)((uint64_t)__double_as_longlong(omv[m]) >> 32) & 0x80000000u;
 #pragma unroll
       for (int sl = 0; sl < 4; ++sl) {
         if (!act[sl]) continue;  // wave-uniform
-        // A[i][k] = component q of row function brow + i at point 4 ks + k;
-        // B[k][j] = w v times component q of column function bcol + j there
-        float ah[3], bh[3], al[3], bl[3];
+        flt4 a4[3], b4[3];
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-          ah[q] = ca[(q * NQR + ks) * ROWF + 4 * (brow[sl] + li16) + lk];
-          const float bx = cb[(q * NQR + ks) * ROWF + 4 * (bcol[sl] + li16) + lk];
-          if (SPLIT) {
+          a4[q] = *reinterpret_cast<const flt4 *>(&ca[(q * NQR + lk) * ROWF + 4 * (brow[sl] + li16)]);
+          b4[q] = *reinterpret_cast<const flt4 *>(&cb[(q * NQR + lk) * ROWF + 4 * (bcol[sl] + li16)]);
+#pragma unroll
+          for (int m = 0; m < 4; ++m) a4[q][m] = __uint_as_float(__float_as_uint(a4[q][m]) ^ sgn[m]);
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          // parts: Ws = dx dx + dy dy + dz dz; Wso_x = dy dz - dz dy;
+          // Wso_y = dz dx - dx dz; Wso_z = dx dy - dy dx (row x column)
+          accf[sl][0] = mfma32(a4[0][m], b4[0][m], accf[sl][0]);
+          accf[sl][1] = mfma32(a4[1][m], b4[2][m], accf[sl][1]);
+          accf[sl][2] = mfma32(a4[2][m], b4[0][m], accf[sl][2]);
+          accf[sl][3] = mfma32(a4[0][m], b4[1][m], accf[sl][3]);
+          accf[sl][0] = mfma32(a4[1][m], b4[1][m], accf[sl][0]);
+          accf[sl][1] = mfma32(-a4[2][m], b4[1][m], accf[sl][1]);
+          accf[sl][2] = mfma32(-a4[0][m], b4[2][m], accf[sl][2]);
+          accf[sl][3] = mfma32(-a4[1][m], b4[0][m], accf[sl][3]);
+          accf[sl][0] = mfma32(a4[2][m], b4[2][m], accf[sl][0]);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int ks = 0; ks < CH / 4; ++ks) {
+        const double omk = omv[ks];
+#pragma unroll
+        for (int sl = 0; sl < 4; ++sl) {
+          if (!act[sl]) continue;  // wave-uniform
+          // A[i][k] = component q of row function brow + i at point 4 ks + k
+          // (hi and lo); B[k][j] = w v times component q of column function
+          // bcol + j there, formed in FP64 from hi + lo and split again
+          float ah[3], bh[3], al[3], bl[3];
+#pragma unroll
+          for (int q = 0; q < 3; ++q) {
+            ah[q] = ca[(q * NQR + ks) * ROWF + 4 * (brow[sl] + li16) + lk];
+            const float bx = cb[(q * NQR + ks) * ROWF + 4 * (bcol[sl] + li16) + lk];
             al[q] = ca[((3 + q) * NQR + ks) * ROWF + 4 * (brow[sl] + li16) + lk];
             const float bxl = cb[((3 + q) * NQR + ks) * ROWF + 4 * (bcol[sl] + li16) + lk];
             const double x = omk * ((double)bx + (double)bxl);
             bh[q] = (float)x;
             bl[q] = (float)(x - (double)bh[q]);
-          } else {
-            bh[q] = (float)(omk * (double)bx);
           }
-        }
-        // parts: Ws = dx dx + dy dy + dz dz; Wso_x = dy dz - dz dy;
-        // Wso_y = dz dx - dx dz; Wso_z = dx dy - dy dx (row x column)
-#define W32(ACC, AI, BI, SG)                                        \
-  ACC = mfma32(SG ah[AI], bh[BI], ACC);                             \
-  if (SPLIT) {                                                      \
-    ACC = mfma32(SG ah[AI], bl[BI], ACC);                           \
-    ACC = mfma32(SG al[AI], bh[BI], ACC);                           \
-  }
-        W32(accf[sl][0], 0, 0, +)
-        W32(accf[sl][1], 1, 2, +)
-        W32(accf[sl][2], 2, 0, +)
-        W32(accf[sl][3], 0, 1, +)
-        W32(accf[sl][0], 1, 1, +)
-        W32(accf[sl][1], 2, 1, -)
-        W32(accf[sl][2], 0, 2, -)
-        W32(accf[sl][3], 1, 0, -)
-        W32(accf[sl][0], 2, 2, +)
+          // the same products, each as hi hi + hi lo + lo hi
+#define W32(ACC, AI, BI, SG)              \
+  ACC = mfma32(SG ah[AI], bh[BI], ACC);   \
+  ACC = mfma32(SG ah[AI], bl[BI], ACC);   \
+  ACC = mfma32(SG al[AI], bh[BI], ACC);
+          W32(accf[sl][0], 0, 0, +)
+          W32(accf[sl][1], 1, 2, +)
+          W32(accf[sl][2], 2, 0, +)
+          W32(accf[sl][3], 0, 1, +)
+          W32(accf[sl][0], 1, 1, +)
+          W32(accf[sl][1], 2, 1, -)
+          W32(accf[sl][2], 0, 2, -)
+          W32(accf[sl][3], 1, 0, -)
+          W32(accf[sl][0], 2, 2, +)
 #undef W32
+        }
       }
     }
     if (((k0 + CH) % FLUSH) == 0 || k0 + CH >= Pp) {
@@ -1927,7 +1964,7 @@ int launch_integrate(const q4c_plan *p, const double *v, int precision, uint32_t
                              panel, (const double *)nullptr);
         else
           hipLaunchKernelGGL(k_panel<PK_F32>, dim3((unsigned)nt), dim3(256), 0, s, p->dp, p->d_ptile, ps.t0, nt, panel,
-                             (const double *)nullptr);
+                             (const double *)p->d_om);
       }
       if ((rc = check_launch("k_panel")) != Q4C_OK) return rc;
     }

@@ -69,10 +69,11 @@ def gamma(k: int) -> float:
 
 # The stated bound of the split precisions' W elements: FP32 partial sums over
 # 16 points, then FP64.  Per 16 points an element sums at most 48 products
-# (16 points x 3) with its operands rounded to FP32 at most three times
-# (panel, weight, product with the weight): gamma_52 of the magnitudes of its
-# terms for Q4C_PREC_F32; with hi + lo operands every product is three FP32
-# products, 144 per 16 points: gamma_150 for Q4C_PREC_SPLIT_F32.  Values below
+# (16 points x 3) whose two operands (sqrt|w v| times a gradient component,
+# formed in FP64) are each rounded to FP32 once: gamma_52 of the magnitudes of
+# its terms for Q4C_PREC_F32, which also covers operands rounded three times;
+# with hi + lo operands every product is three FP32 products, 144 per 16
+# points: gamma_150 for Q4C_PREC_SPLIT_F32.  Values below
 # FP32's normal range (2^-126) lose their relative precision; the far tails of
 # tight functions reach it, hence an absolute floor, far below any bar.
 # Q4C_PREC_BF16X3 (BF16 MFMA, operands split into three BF16 parts): the

@@ -42,23 +42,23 @@ PREC = {"f64": 0, "split": 1, "f32": 2, "bf16x3": 3, "f64valu": 4}
 # L2; 1: the cost-sorted queue, which does not) and whether the launch is
 # persistent (None for kernels without either).  Any change to those sources
 # makes the figure unknown, and it is then reported as null.
-_KS = "c2e14a824f288f321a362b0e85db26392bea6c045aba82b821db27621919ac84"
+_KS = "d1bcf267ac73ce72878c3d72d7e1c2bf7a5628ffbfac0edc61a4bac88caa57d5"
 TRAFFIC = {
-    ("k_contract", _KS, "f64", "cluster-120", (0, False)): 21.64e9 + 7.44e9,
-    ("k_contract", _KS, "f64", "cluster-120", (0, True)): 23.31e9 + 7.64e9,
-    ("k_contract", _KS, "f64", "cluster-120", (1, False)): 42.80e9 + 7.70e9,
-    ("k_contract", _KS, "f64", "cluster-120", (1, True)): 39.87e9 + 7.96e9,
-    ("k_density_tiles", _KS, "f64", "cluster-120", (0, False)): 19.99e9 + 0.21e9,
-    ("k_density_tiles", _KS, "f64", "cluster-120", (0, True)): 40.31e9 + 0.21e9,
-    ("k_density_tiles", _KS, "f64", "cluster-120", (1, False)): 70.20e9 + 0.21e9,
+    ("k_contract", _KS, "f64", "cluster-120", (0, False)): 21.65e9 + 7.44e9,
+    ("k_contract", _KS, "f64", "cluster-120", (0, True)): 23.30e9 + 7.64e9,
+    ("k_contract", _KS, "f64", "cluster-120", (1, False)): 42.80e9 + 7.69e9,
+    ("k_contract", _KS, "f64", "cluster-120", (1, True)): 39.85e9 + 7.96e9,
+    ("k_density_tiles", _KS, "f64", "cluster-120", (0, False)): 19.95e9 + 0.21e9,
+    ("k_density_tiles", _KS, "f64", "cluster-120", (0, True)): 40.30e9 + 0.21e9,
+    ("k_density_tiles", _KS, "f64", "cluster-120", (1, False)): 70.06e9 + 0.21e9,
     ("k_density_tiles", _KS, "f64", "cluster-120", (1, True)): 69.92e9 + 0.21e9,
-    ("k_panel", _KS, "f64", "cluster-120", None): 0.17e9 + 11.48e9,
+    ("k_panel", _KS, "f64", "cluster-120", None): 0.17e9 + 11.49e9,
     ("k_reduce", _KS, "f64", "cluster-120", None): 7.41e9 + 0.03e9,
     ("k_contract", _KS, "bf16x3", "cluster-120", (0, False)): 9.42e9 + 7.04e9,
-    ("k_contract", _KS, "bf16x3", "cluster-120", (0, True)): 9.79e9 + 7.68e9,
+    ("k_contract", _KS, "bf16x3", "cluster-120", (0, True)): 9.83e9 + 7.68e9,
     ("k_contract", _KS, "bf16x3", "cluster-120", (1, False)): 52.63e9 + 7.84e9,
-    ("k_contract", _KS, "bf16x3", "cluster-120", (1, True)): 47.21e9 + 7.79e9,
-    ("k_panel", _KS, "bf16x3", "cluster-120", None): 0.15e9 + 9.34e9,
+    ("k_contract", _KS, "bf16x3", "cluster-120", (1, True)): 47.29e9 + 7.79e9,
+    ("k_panel", _KS, "bf16x3", "cluster-120", None): 0.16e9 + 9.33e9,
     ("k_reduce", _KS, "bf16x3", "cluster-120", None): 7.41e9 + 0.03e9,
 }
 

@@ -387,6 +387,10 @@ int build_host(q4c_plan *p, const q4c_basis *b, const q4c_grid *g, const std::ve
     p->max_pair_block = std::max<int64_t>(p->max_pair_block, (int64_t)p->pair_na[q] * p->pair_nb[q]);
   }
   p->store_len = p->pair_off[p->n_pairs];
+  // the batch-to-global sum spreads a pair's five blocks over 256-element
+  // workgroups along the grid's second dimension (at most 65535)
+  if ((5 * p->max_pair_block + 255) / 256 > 65535)
+    return fail(Q4C_EUNSUPPORTED, "an atom pair block has more than 3.3M elements");
   p->sys_pair_off.assign(nsys + 1, 0);
   for (int sy = 0; sy < nsys; ++sy) p->sys_pair_off[sy + 1] = p->atom_pair_start[sys_atom_off[sy + 1]];
   auto pair_index = [&](int a, int c) -> int64_t {

@@ -42,32 +42,32 @@ PREC = {"f64": 0, "split": 1, "f32": 2, "bf16x3": 3, "f64valu": 4}
 # L2; 1: the cost-sorted queue, which does not) and whether the launch is
 # persistent (None for kernels without either).  Any change to those sources
 # makes the figure unknown, and it is then reported as null.
-_KS = "d1bcf267ac73ce72878c3d72d7e1c2bf7a5628ffbfac0edc61a4bac88caa57d5"
+_KS = "aa81d82736b822f8aefa511b19cd980116ad21de41c38570d9bde7b4adde63db"
 TRAFFIC = {
     ("k_contract", _KS, "f64", "cluster-120", (0, False)): 21.65e9 + 7.44e9,
     ("k_contract", _KS, "f64", "cluster-120", (0, True)): 23.30e9 + 7.64e9,
     ("k_contract", _KS, "f64", "cluster-120", (1, False)): 42.80e9 + 7.69e9,
-    ("k_contract", _KS, "f64", "cluster-120", (1, True)): 39.85e9 + 7.96e9,
-    ("k_density_tiles", _KS, "f64", "cluster-120", (0, False)): 19.95e9 + 0.21e9,
-    ("k_density_tiles", _KS, "f64", "cluster-120", (0, True)): 40.30e9 + 0.21e9,
-    ("k_density_tiles", _KS, "f64", "cluster-120", (1, False)): 70.06e9 + 0.21e9,
-    ("k_density_tiles", _KS, "f64", "cluster-120", (1, True)): 69.92e9 + 0.21e9,
+    ("k_contract", _KS, "f64", "cluster-120", (1, True)): 39.69e9 + 7.96e9,
+    ("k_density_tiles", _KS, "f64", "cluster-120", (0, False)): 19.93e9 + 0.21e9,
+    ("k_density_tiles", _KS, "f64", "cluster-120", (0, True)): 21.46e9 + 0.21e9,
+    ("k_density_tiles", _KS, "f64", "cluster-120", (1, False)): 70.29e9 + 0.21e9,
+    ("k_density_tiles", _KS, "f64", "cluster-120", (1, True)): 67.54e9 + 0.21e9,
     ("k_panel", _KS, "f64", "cluster-120", None): 0.17e9 + 11.49e9,
     ("k_reduce", _KS, "f64", "cluster-120", None): 7.41e9 + 0.03e9,
     ("k_contract", _KS, "bf16x3", "cluster-120", (0, False)): 9.42e9 + 7.04e9,
-    ("k_contract", _KS, "bf16x3", "cluster-120", (0, True)): 9.83e9 + 7.68e9,
+    ("k_contract", _KS, "bf16x3", "cluster-120", (0, True)): 9.84e9 + 7.68e9,
     ("k_contract", _KS, "bf16x3", "cluster-120", (1, False)): 52.63e9 + 7.84e9,
-    ("k_contract", _KS, "bf16x3", "cluster-120", (1, True)): 47.29e9 + 7.79e9,
+    ("k_contract", _KS, "bf16x3", "cluster-120", (1, True)): 47.39e9 + 7.79e9,
     ("k_panel", _KS, "bf16x3", "cluster-120", None): 0.16e9 + 9.33e9,
     ("k_reduce", _KS, "bf16x3", "cluster-120", None): 7.41e9 + 0.03e9,
 }
 
 # The same for k_contract_hs (q4c_integrate_HS) per component and launch shape,
 # keyed by the SHA-256 of q4c_hs_kernels.hip and q4c_device.h.
-_HS = "cb0aff49a9a25371de0ac031f97c714b4eb5cac134fb2b2f87c77a566f1b5e53"
+_HS = "07c101f6ce1cacc7d5df8cc7267adc142c8576d56c73f0659b9e0b7c9665fe60"
 HS_TRAFFIC = {
-    (_HS, "large", 120, (0, True)): 6.842e9 + 2.994e9,
-    (_HS, "small", 120, (0, True)): 7.154e9 + 7.042e9,
+    (_HS, "large", 120, (0, True)): 6.854e9 + 2.994e9,
+    (_HS, "small", 120, (0, True)): 7.143e9 + 7.043e9,
 }
 
 

@@ -63,13 +63,12 @@ __device__ __forceinline__ int64_t next_item(unsigned *tickets, int64_t nw, bool
   return *s_pos;
 }
 
-// The same queues for a workgroup that draws its next ticket while it still
-// works on the current item: draw_ticket (one thread) adds to its XCD's queue
-// (or the global one) and the result is first needed after the item, so the
-// atomic's round trip hides behind the item's work; ticket_pos turns the
-// ticket into a position and, once the own queue is drained, takes one from
-// the other XCDs' queues as next_item does.  A drained queue's counter may
-// grow past its range; it is never read as a position.
+// The same queues in two steps, for a workgroup that passes the position on
+// through LDS slots of its own: draw_ticket (one thread) adds to its XCD's
+// queue (or the global one), ticket_pos turns the ticket into a position and,
+// once the own queue is drained, takes one from the other XCDs' queues as
+// next_item does.  A drained queue's counter may grow past its range; it is
+// never read as a position.
 __device__ __forceinline__ unsigned draw_ticket(unsigned *tickets, bool global_queue) {
   return atomicAdd(&tickets[global_queue ? 0 : (int)(blockIdx.x & 7) * kTicketStride], 1u);
 }

@@ -1492,8 +1492,9 @@ __device__ __forceinline__ void adj_fill(const DevPlan &d, const AdjPos &D, AdjT
 // double-buffered (the next chunk's loads in flight while this one is
 // multiplied, one barrier per chunk); each lane's 16 column values Z come from
 // the panel straight into registers, two chunks ahead.  Two workgroups fit on a
-// CU.  A persistent workgroup draws its next position's ticket when it starts
-// a position and turns it into a position after the last chunk.
+// CU.  A persistent workgroup draws its next position after the last chunk of
+// a position (drawn when a position starts, the tickets ran one position
+// ahead of need and the launch read twice the bytes, at the same speed).
 // F32W (density_on_grid in FP32): the nine W-term products per K step run on
 // FP32 MFMA with the coefficients and row values rounded to FP32; each
 // chunk's FP32 sums over the wave's 32 rows (at most 96 products per column
@@ -1529,9 +1530,6 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, const AdjPo
   const int ptA = TR ? 4 * (l16 & 3) + (l16 >> 2) : l16;  // the point this lane supplies to the row operand
   int par = 0;
   for (;;) {
-  // the next position's ticket, drawn now and first needed after the position
-  unsigned tk = 0;
-  if (PERSIST && tid == 0) tk = draw_ticket(tickets, gq);
   const int n = D.n, P = D.P;
   const int r0 = D.ti * T, c0 = D.tj * T + 32 * D.half;
   const int Pp = (int)pad16(P), np = (int)pad16(n);
@@ -1781,9 +1779,9 @@ __global__ __launch_bounds__(NTD, 2) void k_density_tiles(DevPlan d, const AdjPo
       out[k0 + tid] = (s_red[bi][0][tid] + s_red[bi][1][tid]) + (s_red[bi][2][tid] + s_red[bi][3][tid]);
   }
   if (!PERSIST) return;
-  // two slots in turn: thread 0 may write the next slot before every thread
-  // has read this one
-  if (tid == 0) s_next[par] = ticket_pos(tickets, npos, gq, tk);
+  // the next position, drawn once this one is done; two slots in turn:
+  // thread 0 may write the next slot before every thread has read this one
+  if (tid == 0) s_next[par] = ticket_pos(tickets, npos, gq, draw_ticket(tickets, gq));
   __syncthreads();
   pos = uniform_i64(s_next[par]);
   par ^= 1;

@@ -473,22 +473,25 @@ __global__ __launch_bounds__(256) void k_panel(DevPlan d, const WorkItem *tiles,
 }
 
 // Modes of the FP64 contraction: all five parts, or V alone (phi only: the
-// V part of the split precisions, and V-only calls).
+// V part of the split precisions, and V-only calls).  V alone does one MFMA
+// per row and column value, too little work per chunk to hide the next
+// chunk's loads at two workgroups per CU: its 16-point chunks (33 KB of LDS)
+// and 110 VGPRs let four share a CU.
 enum { MODE_F64 = 0, MODE_V = 1 };
 
 // Work item positions 0..nw-1 of a pass map to work items w0 + order[w0 + pos]
 // (order != NULL: cost-sorted) or w0 + pos.  tickets == NULL: one workgroup
 // per position; otherwise a persistent loop (next_item).
 template <int MODE, bool PERSIST>
-__global__ __launch_bounds__(NT, 2) void k_contract(DevPlan d, const WorkItem *work, const int32_t *order,
-                                                    int64_t w0, int64_t nw, const double *om, const double *panel,
-                                                    double *staging, unsigned *tickets) {
+__global__ __launch_bounds__(NT, MODE == MODE_V ? 4 : 2) void k_contract(
+    DevPlan d, const WorkItem *work, const int32_t *order, int64_t w0, int64_t nw, const double *om,
+    const double *panel, double *staging, unsigned *tickets) {
   constexpr bool VONLY = MODE == MODE_V;
   constexpr int NQ = VONLY ? 1 : 4;        // panel components multiplied
   constexpr int NP = VONLY ? 1 : 5;        // parts accumulated
   // Chunks of CH points in two LDS buffers, the next chunk's DMA in flight
   // while this one is multiplied (one barrier per chunk)
-  constexpr int CH = VONLY ? 32 : 8;
+  constexpr int CH = VONLY ? 16 : 8;
   constexpr int RPQ = CH / 2;              // LDS rows per component
   constexpr int BUFD = NQ * RPQ * DROW;    // doubles per chunk image
   __shared__ double sa[2 * BUFD], sb[2 * BUFD];
@@ -1981,9 +1984,13 @@ int launch_integrate(const q4c_plan *p, const double *v, int precision, uint32_t
         launch_work(k_contract_b3<true>, k_contract_b3<false>, grid2, pers, s, p->dp, p->d_work, order, ps.w0, nw,
                     p->d_om, panel, p->d_staging, tick_a);
       } else {
-        if (wantV)
-          launch_work(k_contract<MODE_V, true>, k_contract<MODE_V, false>, grid, pers, s, p->dp, p->d_work, order,
+        if (wantV) {
+          // four V-only workgroups fit on a CU, twice the other contraction
+          // kernels' two: twice the persistent workgroups
+          const unsigned grid_v = (unsigned)(pers ? std::min<int64_t>(2 * (int64_t)cfg.persistent, nw) : nw);
+          launch_work(k_contract<MODE_V, true>, k_contract<MODE_V, false>, grid_v, pers, s, p->dp, p->d_work, order,
                       ps.w0, nw, p->d_om, panel, p->d_staging, tick_a);
+        }
         if (wantW && precision == Q4C_PREC_SPLIT_F32)
           launch_work(k_contract_w<true, true>, k_contract_w<true, false>, grid, pers, s, p->dp, p->d_work, order,
                       ps.w0, nw, p->d_om, panel, p->d_staging, tick_w);

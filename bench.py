@@ -42,23 +42,23 @@ PREC = {"f64": 0, "split": 1, "f32": 2, "bf16x3": 3, "f64valu": 4}
 # L2; 1: the cost-sorted queue, which does not) and whether the launch is
 # persistent (None for kernels without either).  Any change to those sources
 # makes the figure unknown, and it is then reported as null.
-_KS = "aa81d82736b822f8aefa511b19cd980116ad21de41c38570d9bde7b4adde63db"
+_KS = "35abda01782c414d04e9480453bea04a41d0afd91997fc328a68a3e9506f141a"
 TRAFFIC = {
-    ("k_contract", _KS, "f64", "cluster-120", (0, False)): 21.65e9 + 7.44e9,
-    ("k_contract", _KS, "f64", "cluster-120", (0, True)): 23.30e9 + 7.64e9,
-    ("k_contract", _KS, "f64", "cluster-120", (1, False)): 42.80e9 + 7.69e9,
-    ("k_contract", _KS, "f64", "cluster-120", (1, True)): 39.69e9 + 7.96e9,
-    ("k_density_tiles", _KS, "f64", "cluster-120", (0, False)): 19.93e9 + 0.21e9,
-    ("k_density_tiles", _KS, "f64", "cluster-120", (0, True)): 21.46e9 + 0.21e9,
-    ("k_density_tiles", _KS, "f64", "cluster-120", (1, False)): 70.29e9 + 0.21e9,
-    ("k_density_tiles", _KS, "f64", "cluster-120", (1, True)): 67.54e9 + 0.21e9,
+    ("k_contract", _KS, "f64", "cluster-120", (0, False)): 21.60e9 + 7.44e9,
+    ("k_contract", _KS, "f64", "cluster-120", (0, True)): 23.26e9 + 7.64e9,
+    ("k_contract", _KS, "f64", "cluster-120", (1, False)): 42.81e9 + 7.69e9,
+    ("k_contract", _KS, "f64", "cluster-120", (1, True)): 39.88e9 + 7.95e9,
+    ("k_density_tiles", _KS, "f64", "cluster-120", (0, False)): 19.94e9 + 0.21e9,
+    ("k_density_tiles", _KS, "f64", "cluster-120", (0, True)): 21.47e9 + 0.21e9,
+    ("k_density_tiles", _KS, "f64", "cluster-120", (1, False)): 70.23e9 + 0.21e9,
+    ("k_density_tiles", _KS, "f64", "cluster-120", (1, True)): 67.87e9 + 0.21e9,
     ("k_panel", _KS, "f64", "cluster-120", None): 0.17e9 + 11.49e9,
     ("k_reduce", _KS, "f64", "cluster-120", None): 7.41e9 + 0.03e9,
     ("k_contract", _KS, "bf16x3", "cluster-120", (0, False)): 9.42e9 + 7.04e9,
-    ("k_contract", _KS, "bf16x3", "cluster-120", (0, True)): 9.84e9 + 7.68e9,
-    ("k_contract", _KS, "bf16x3", "cluster-120", (1, False)): 52.63e9 + 7.84e9,
-    ("k_contract", _KS, "bf16x3", "cluster-120", (1, True)): 47.39e9 + 7.79e9,
-    ("k_panel", _KS, "bf16x3", "cluster-120", None): 0.16e9 + 9.33e9,
+    ("k_contract", _KS, "bf16x3", "cluster-120", (0, True)): 9.80e9 + 7.68e9,
+    ("k_contract", _KS, "bf16x3", "cluster-120", (1, False)): 52.64e9 + 7.84e9,
+    ("k_contract", _KS, "bf16x3", "cluster-120", (1, True)): 47.43e9 + 7.79e9,
+    ("k_panel", _KS, "bf16x3", "cluster-120", None): 0.16e9 + 9.34e9,
     ("k_reduce", _KS, "bf16x3", "cluster-120", None): 7.41e9 + 0.03e9,
 }
 

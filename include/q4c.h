@@ -66,8 +66,9 @@ enum {
  * accumulation can hold to 1e-8 Ha).  The W parts (9 of the 10 P n^2 flops
  * of a batch):
  *   Q4C_PREC_F64        FP64 MFMA, FP64 accumulation.
- *   Q4C_PREC_F32        FP32 MFMA on FP32 operands (gradients tabulated in
- *                       FP32, the weight w v applied in FP64 and rounded);
+ *   Q4C_PREC_F32        FP32 MFMA on FP32 operands (sqrt|w v| times the
+ *                       gradient, formed in FP64 and rounded once; the row
+ *                       operand carries the sign of w v);
  *                       every element's FP32 partial sum covers 16 points (at
  *                       most 48 products) and is then added to an FP64 sum.
  *                       Bound: |error| <= gamma_52 A_ij + (FP32 underflow:
@@ -76,8 +77,10 @@ enum {
  *                       and A_ij the sum over all points of the magnitudes of
  *                       the element's terms (c' sum_g |w_g v_g| sum |d phi_i|
  *                       |d phi_j| over the products entering it).
- *   Q4C_PREC_SPLIT_F32  as F32 with each operand split into hi = fl32(x) and
- *                       lo = fl32(x - hi) and every product taken as
+ *   Q4C_PREC_SPLIT_F32  FP32 MFMA with each operand (the gradient for rows,
+ *                       w v times it, formed in FP64, for columns) split into
+ *                       hi = fl32(x) and lo = fl32(x - hi), FP32 sums over
+ *                       16 points as for F32, and every product taken as
  *                       hi hi + hi lo + lo hi (three FP32 MFMAs): operand
  *                       rounding drops to about 2^-48, and a 16-point partial
  *                       sum has up to 144 products: gamma_150 A_ij.

@@ -42,22 +42,22 @@ PREC = {"f64": 0, "split": 1, "f32": 2, "bf16x3": 3, "f64valu": 4}
 # L2; 1: the cost-sorted queue, which does not) and whether the launch is
 # persistent (None for kernels without either).  Any change to those sources
 # makes the figure unknown, and it is then reported as null.
-_KS = "35abda01782c414d04e9480453bea04a41d0afd91997fc328a68a3e9506f141a"
+_KS = "3988041ce98d2cefbd3169767ac3a161f0c36e4d4c5bb94ed602b3de360c368c"
 TRAFFIC = {
-    ("k_contract", _KS, "f64", "cluster-120", (0, False)): 21.60e9 + 7.44e9,
-    ("k_contract", _KS, "f64", "cluster-120", (0, True)): 23.26e9 + 7.64e9,
-    ("k_contract", _KS, "f64", "cluster-120", (1, False)): 42.81e9 + 7.69e9,
-    ("k_contract", _KS, "f64", "cluster-120", (1, True)): 39.88e9 + 7.95e9,
-    ("k_density_tiles", _KS, "f64", "cluster-120", (0, False)): 19.94e9 + 0.21e9,
-    ("k_density_tiles", _KS, "f64", "cluster-120", (0, True)): 21.47e9 + 0.21e9,
-    ("k_density_tiles", _KS, "f64", "cluster-120", (1, False)): 70.23e9 + 0.21e9,
-    ("k_density_tiles", _KS, "f64", "cluster-120", (1, True)): 67.87e9 + 0.21e9,
+    ("k_contract", _KS, "f64", "cluster-120", (0, False)): 21.63e9 + 7.44e9,
+    ("k_contract", _KS, "f64", "cluster-120", (0, True)): 23.25e9 + 7.64e9,
+    ("k_contract", _KS, "f64", "cluster-120", (1, False)): 42.81e9 + 7.65e9,
+    ("k_contract", _KS, "f64", "cluster-120", (1, True)): 39.92e9 + 7.96e9,
+    ("k_density_tiles", _KS, "f64", "cluster-120", (0, False)): 19.97e9 + 0.21e9,
+    ("k_density_tiles", _KS, "f64", "cluster-120", (0, True)): 21.51e9 + 0.21e9,
+    ("k_density_tiles", _KS, "f64", "cluster-120", (1, False)): 70.18e9 + 0.21e9,
+    ("k_density_tiles", _KS, "f64", "cluster-120", (1, True)): 67.96e9 + 0.21e9,
     ("k_panel", _KS, "f64", "cluster-120", None): 0.17e9 + 11.49e9,
     ("k_reduce", _KS, "f64", "cluster-120", None): 7.41e9 + 0.03e9,
-    ("k_contract", _KS, "bf16x3", "cluster-120", (0, False)): 9.42e9 + 7.04e9,
-    ("k_contract", _KS, "bf16x3", "cluster-120", (0, True)): 9.80e9 + 7.68e9,
-    ("k_contract", _KS, "bf16x3", "cluster-120", (1, False)): 52.64e9 + 7.84e9,
-    ("k_contract", _KS, "bf16x3", "cluster-120", (1, True)): 47.43e9 + 7.79e9,
+    ("k_contract", _KS, "bf16x3", "cluster-120", (0, False)): 9.44e9 + 6.95e9,
+    ("k_contract", _KS, "bf16x3", "cluster-120", (0, True)): 9.69e9 + 7.15e9,
+    ("k_contract", _KS, "bf16x3", "cluster-120", (1, False)): 52.62e9 + 7.84e9,
+    ("k_contract", _KS, "bf16x3", "cluster-120", (1, True)): 47.97e9 + 7.79e9,
     ("k_panel", _KS, "bf16x3", "cluster-120", None): 0.16e9 + 9.34e9,
     ("k_reduce", _KS, "bf16x3", "cluster-120", None): 7.41e9 + 0.03e9,
 }

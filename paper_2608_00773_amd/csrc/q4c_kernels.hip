@@ -1077,19 +1077,25 @@ __global__ __launch_bounds__(NT, 2) void k_contract_b3(DevPlan d, const WorkItem
   // Lanes whose function lies at or beyond np load nothing.
   const __amdgpu_buffer_rsrc_t prs =
       __builtin_amdgcn_make_buffer_rsrc((void *)pb, (short)0, (int)(26 * fplane), 0x00020000);
+  // lanes whose function lies at or beyond np take an offset past the
+  // buffer's range: the load is issued by every lane and reads nothing there
   const bool okr = r0 + lane < np, okc = c0 + (lane & 31) < np;
-  const uint32_t vrow = lane * 16u, vcol = (lane & 31) * 16u + (lane >> 5) * (uint32_t)np * 16u;
-  const uint32_t vprow = lane * 32u, vpcol = (lane & 31) * 32u + (lane >> 5) * 16u;
+  constexpr uint32_t OOB = 0x80000000u;
+  const uint32_t vrow = okr ? lane * 16u : OOB;
+  const uint32_t vcol = okc ? (lane & 31) * 16u + (lane >> 5) * (uint32_t)np * 16u : OOB;
+  const uint32_t vprow = okr ? lane * 32u : OOB, vpcol = okc ? (lane & 31) * 32u + (lane >> 5) * 16u : OOB;
   auto dma = [&](int k0, int bf) {
     const int og = k0 >> 3;
-    for (int k = wave; k < 27; k += 4) {
+#pragma unroll
+    for (int i = 0; i < 7; ++i) {
+      const int k = wave + 4 * i;  // wave-uniform
       if (k < 18) {  // row image row (plane k / 2, octet k % 2), 64 functions
         const uint32_t so = 8u * (uint32_t)fplane + (uint32_t)((((k >> 1) * noct + og + (k & 1)) * np + r0) * 16);
-        if (okr) __builtin_amdgcn_raw_ptr_buffer_load_lds(prs, (lds_void *)(&sr[bf][k * 64]), 16, vrow, so, 0, 0);
-      } else {  // column image rows (plane, octet 0) and (plane, octet 1), 32 functions each
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(prs, (lds_void *)(&sr[bf][k * 64]), 16, vrow, so, 0, 0);
+      } else if (k < 27) {  // column image rows (plane, octet 0) and (plane, octet 1), 32 functions each
         const int pl = k - 18;
         const uint32_t so = 8u * (uint32_t)fplane + (uint32_t)(((pl * noct + og) * np + c0) * 16);
-        if (okc) __builtin_amdgcn_raw_ptr_buffer_load_lds(prs, (lds_void *)(&sc[bf][pl * 64]), 16, vcol, so, 0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(prs, (lds_void *)(&sc[bf][pl * 64]), 16, vcol, so, 0, 0);
       }
     }
     // FP64 phi: image row u = point pair u of the chunk (16 bytes per function)
@@ -1097,12 +1103,11 @@ __global__ __launch_bounds__(NT, 2) void k_contract_b3(DevPlan d, const WorkItem
     for (int h = 0; h < 2; ++h) {  // rows: two point pairs per wave
       const int u = wave + 4 * h;
       const uint32_t so = (uint32_t)(((((k0 >> 2) + (u >> 1)) * np + r0) * 4 + 2 * (u & 1)) * 8);
-      if (okr) __builtin_amdgcn_raw_ptr_buffer_load_lds(prs, (lds_void *)(&dr[bf][u * DROW]), 16, vprow, so, 0, 0);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(prs, (lds_void *)(&dr[bf][u * DROW]), 16, vprow, so, 0, 0);
     }
     {  // columns: point pairs 2 w and 2 w + 1 (one quad) per wave
       const uint32_t so = (uint32_t)(((((k0 >> 2) + wave) * np + c0) * 4) * 8);
-      if (okc)
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(prs, (lds_void *)(&dc[bf][2 * wave * CDW]), 16, vpcol, so, 0, 0);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(prs, (lds_void *)(&dc[bf][2 * wave * CDW]), 16, vpcol, so, 0, 0);
     }
   };
 

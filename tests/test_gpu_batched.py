@@ -43,7 +43,7 @@ def _run(q, torch, plan, v, coef, prec):
 def test_batched_equals_sequential_bitwise(env):
     q, torch, systems, pb, off = env["q"], env["torch"], env["systems"], env["pb"], env["off"]
     print("batched plan:", pb.info, flush=True)
-    for prec in (q.PREC_F64, q.PREC_SPLIT_F32, q.PREC_BF16X3):
+    for prec in (q.PREC_F64, q.PREC_F32, q.PREC_SPLIT_F32, q.PREC_BF16X3):
         st_b, out_b = _run(q, torch, pb, env["v"], env["coef"], prec)
         for s, ws in enumerate(systems):
             p = q.Plan(ws)
@@ -80,7 +80,7 @@ def test_batched_matches_oracle(env):
 def test_launch_shapes_bitwise(env):
     q, torch, pb = env["q"], env["torch"], env["pb"]
     ref = {prec: _run(q, torch, pb, env["v"], env["coef"], prec)
-           for prec in (q.PREC_F64, q.PREC_SPLIT_F32, q.PREC_BF16X3)}
+           for prec in (q.PREC_F64, q.PREC_F32, q.PREC_SPLIT_F32, q.PREC_BF16X3)}
     for order in (0, 1):
         for pers in (0, 256, 512, 3000):
             print("launch shape order=%d persistent=%d" % (order, pers), flush=True)

@@ -361,3 +361,34 @@ def test_periodic_cells_validation_and_layout():
     assert lib.q4c_bloch_density(p.handle, 1, one, 1, one, one, one, None) == q.Q4C_ENODEV
     assert lib.q4c_bloch_density(p.handle, 1, one, -1, one, one, one, None) == q.Q4C_EINVAL
     assert lib.q4c_bloch_density(None, 1, one, 1, one, one, one, None) == q.Q4C_EINVAL
+
+
+def _one_atom_of_g_shells(wl, n_shells):
+    """Atom 0 of wl alone, its basis n_shells copies of its first shell as
+    l = 4 (9 functions each), the grid points it owns."""
+    import dataclasses
+    s0 = int(wl.atom_shell_off[0])
+    rep = np.full(n_shells, s0)
+    pts = np.nonzero(wl.pt_atom == 0)[0][:64]
+    return dataclasses.replace(
+        wl, name="one atom, %d g shells" % n_shells, Z=wl.Z[:1].copy(), R=wl.R[:1].copy(),
+        atom_shell_off=np.array([0, n_shells], dtype=np.int32), shell_l=np.full(n_shells, 4, dtype=np.int32),
+        shell_rcut=wl.shell_rcut[rep].copy(), shell_nint=wl.shell_nint[rep].copy(),
+        shell_coef_off=wl.shell_coef_off[rep].copy(), shell_alpha=wl.shell_alpha[rep].copy(),
+        shell_gcoef=wl.shell_gcoef[rep].copy(), x=wl.x[pts].copy(), y=wl.y[pts].copy(), z=wl.z[pts].copy(),
+        w=wl.w[pts].copy(), pt_atom=np.zeros(pts.size, dtype=np.int32), v=wl.v[pts].copy(),
+        molecule=None, shell_u_off=None, u_coef=None, shell_eps=None)
+
+
+def test_pair_block_limit_of_the_batch_sum():
+    """The batch-to-global sum spreads one atom pair's five blocks over
+    256-element workgroups along the grid's second dimension (at most 65535),
+    so an atom pair block of more than 65535 * 256 / 5 elements is rejected
+    when the plan is built: 1,818 functions on one atom build, 1,836 do not."""
+    q, lib = _lib()
+    wl = W.config_small(nrad=10, nang=26)
+    p = _host_plan(q, _one_atom_of_g_shells(wl, 202))
+    assert p.info["n_fn"] == 1818 and p.info["store_len"] == 1818 * 1818
+    with pytest.raises(q.Q4CError) as e:
+        _host_plan(q, _one_atom_of_g_shells(wl, 204))
+    assert e.value.status == q.Q4C_EUNSUPPORTED

@@ -114,3 +114,18 @@ def per_point_worst(got, ref, scale, floor=0.0):
     assert np.array_equal(got[zero], ref[zero]), "entries with no terms differ"
     nz = ~zero
     return float(np.max(np.abs(got[nz] - ref[nz]) / (scale[nz] + floor))) if np.any(nz) else 0.0
+
+
+def spinor_coef_scale(pairs, D_blocks):
+    """Per stored element and part, the scale of the spinor -> coefficient
+    conversion: f times the sum of the magnitudes of the four spin entries of
+    D for (i, j) (every coefficient is a signed sum of at most two of them, so
+    one rounding leaves it within 2^-53 of this scale), f = 2 for pairs of two
+    atoms, 1 within an atom."""
+    out = []
+    for (a, b), D in zip(pairs, D_blocks):
+        nA, nB = D.shape[0] // 2, D.shape[1] // 2
+        m = np.abs(D).reshape(2, nA, 2, nB).sum(axis=(0, 2))
+        f = 1.0 if a == b else 2.0
+        out.append(np.broadcast_to(f * m, (5, nA, nB)).copy())
+    return out

@@ -15,7 +15,8 @@ import pytest
 
 import oracle
 import workload as W
-from helpers import blocks_to_store, gpu_available, per_point_worst, split_bound_worst, store_to_blocks
+from helpers import (blocks_to_store, gpu_available, per_point_worst, spinor_coef_scale, split_bound_worst,
+                     store_to_blocks)
 
 pytestmark = pytest.mark.gpu
 
@@ -145,11 +146,13 @@ def test_spinor_density_gradient_dot_product(env):
     # the coefficient conversion itself against the oracle on a sample of pairs
     sel = _sample_pairs(pairs, wl)
     ref = oracle.coef_from_spinor_density(pairs[sel], [D[p] for p in sel])
+    scale = spinor_coef_scale(pairs[sel], [D[p] for p in sel])
     c = coef.cpu().numpy()
     nfn = wl.atom_nfn()
     for k, p in enumerate(sel):
         a, b = pairs[p]
-        assert np.max(np.abs(c[:, po[p]:po[p + 1]].reshape(5, nfn[a], nfn[b]) - ref[k])) <= 1e-15 * np.max(np.abs(ref[k]))
+        got = c[:, po[p]:po[p + 1]].reshape(5, nfn[a], nfn[b])
+        assert per_point_worst(got, ref[k], 1e-15 * scale[k]) <= 1.0
 
 
 def test_fullsize_split_error_bar(env):

@@ -341,13 +341,14 @@ def test_coef_from_spinor_matches_oracle(q, small):
     plan = q.Plan(wl)
     _, po = plan.pairs()
     D = W.spinor_density(wl, pairs, 5001)
-    from helpers import blocks_to_store, spinor_from_blocks
+    from helpers import blocks_to_store, spinor_coef_scale, spinor_from_blocks
     spin = torch.from_numpy(spinor_from_blocks(D, po)).cuda()
     out = q.new_store(plan)
     q.q4c_coef_from_spinor(plan, spin, out)
     torch.cuda.synchronize()
     ref = blocks_to_store(oracle.coef_from_spinor_density(pairs, D), po)
-    assert np.max(np.abs(out.cpu().numpy() - ref)) <= 1e-15 * np.max(np.abs(ref))
+    scale = blocks_to_store(spinor_coef_scale(pairs, D), po)
+    assert per_point_worst(out.cpu().numpy(), ref, 1e-15 * scale) <= 1.0
 
 
 # ---------------------------------------------------------------------------

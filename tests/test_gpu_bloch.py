@@ -158,7 +158,13 @@ def test_perovskite_cell_against_oracle_sum(q, hs):
     torch.cuda.synchronize()
     o2 = out.cpu().numpy()
     o2 = o2[..., 0] + 1j * o2[..., 1]
-    assert np.max(np.abs(o2 - o)) <= 1e-11 * np.max(np.abs(o))
+    # per element, against the sum of the magnitudes of its terms: the phases
+    # of k + G differ from those of k by the rounding of arguments of a few
+    # tens of radians
+    got2 = _cell_blocks(o2, cpa, cpo, _ncell(wl))
+    worst = max(float(np.max(np.abs(g - got[key]) / (1e-12 * sc[key][None] + 1e-300))) for key, g in got2.items())
+    print("k -> k + G: worst |d| / bar = %.3g" % worst, flush=True)
+    assert worst <= 1.0
 
 
 # ---------------------------------------------------------------------------

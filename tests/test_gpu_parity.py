@@ -9,7 +9,8 @@ import pytest
 
 import oracle
 import workload as W
-from helpers import gamma, gpu_available, per_point_worst, spinor_to_blocks, split_bound_worst, store_to_blocks
+from helpers import (blocks_to_store, gamma, gpu_available, per_point_worst, spinor_to_blocks, split_bound_worst,
+                     store_to_blocks)
 
 pytestmark = pytest.mark.gpu
 
@@ -480,9 +481,11 @@ def test_parts_mask(q, medium):
     """Selected parts equal the all-parts call bit for bit; parts not selected
     keep what the store held; V-only and W-only calls in every precision."""
     torch = _torch()
-    wl = medium[0]
+    wl, pairs, _, scale = medium
     plan = q.Plan(wl)
     v = torch.from_numpy(wl.v).cuda()
+    # the oracle's per-element scale of V (sum of the magnitudes of its terms)
+    sv = torch.from_numpy(blocks_to_store(scale, plan.pairs()[1])[0]).cuda()
     rows = {"V": [0], "WS": [1], "WSO": [2, 3, 4]}
     bits = {"V": q.PART_V, "WS": q.PART_WS, "WSO": q.PART_WSO}
     for prec in (q.PREC_F64, q.PREC_F32, q.PREC_SPLIT_F32, q.PREC_BF16X3):
@@ -502,8 +505,10 @@ def test_parts_mask(q, medium):
         q.q4c_integrate_H(plan, v, prec, q.ACCUMULATE, acc, parts=q.PART_V)
         torch.cuda.synchronize()
         assert torch.equal(acc[1:], full[1:])
-        # the batch sums are added one by one onto the stored value
-        assert float(torch.max(torch.abs(acc[0] - 2 * full[0]))) <= 1e-13 * float(torch.max(torch.abs(full[0])))
+        # the batch sums are added one by one onto the stored value: within
+        # 1e-13 of each element's scale (twice the scale of one call)
+        d = torch.abs(acc[0] - 2 * full[0])
+        assert bool(torch.all(d[sv == 0] == 0)) and bool(torch.all(d <= 2e-13 * sv)), (prec, float(torch.max(d / (sv + 1e-300))))
     with pytest.raises(q.Q4CError):
         q.q4c_integrate_H(plan, v, q.PREC_F64, q.ASSEMBLE_W, q.new_store(plan), q.new_spinor(plan), parts=q.PART_WS)
 
